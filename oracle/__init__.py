@@ -1,0 +1,395 @@
+"""CPU FP64 oracle for the all-at-once circulant-preconditioned GMRES path.
+
+TEST INFRASTRUCTURE.  Only the test-suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the GPU library (``paper_1810_00615_amd``) and never imports it.
+
+What the oracle computes, and the passage of Goddard & Wathen (arXiv
+1810.00615) each function follows:
+
+* ``apply_A`` / ``solve_seq`` / ``adjoint_seq`` -- the monolithic block
+  lower-triangular Toeplitz system of Sec. 2 (eq. monolithicheat for heat, the
+  system C_BD2 for the wave equation, eq. nonuniformmonolithicheat with variable
+  steps).  ``solve_seq`` is forward block substitution, i.e. the sequential
+  implicit time stepping of eq. timestepproblem1: the exact solution U.
+* ``apply_C`` -- the block circulant preconditioner (eq. standardheatprecon,
+  eq. wavepreconditioner).
+* ``dft`` -- the direct O(ell^2) transform along time (the (U (x) I_n) factor of
+  eq. precon2para in the per-column form of eq. alternativecal).
+* ``pinv_direct`` / ``pinv`` -- C^{-1} r by the Fourier diagonalisation of
+  eq. precon2para: transform, one complex tridiagonal (Thomas) solve per
+  frequency (Sec. 3), inverse transform.  ``pinv`` uses numpy's FFT as the
+  transform step (a library primitive) and is pinned to ``pinv_direct``.
+* ``neumann`` -- the truncated Neumann series of eq. preconapprox1 for the
+  variable-step preconditioner Q = P + sigma (x) K.
+* ``fgmres`` -- textbook restarted right-preconditioned (flexible) GMRES with
+  modified Gram-Schmidt and Givens rotations (Saad & Schultz, cited in Sec. 1).
+* ``grad`` -- adjoint-gradient reductions for d/du_0 and d/dkappa.
+
+Readings of the paper (M + tau K for the printed K + tau M, n = interior nodes,
+L2 projection of the initial data, ...) are the ones listed in the design notes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HEAT = 0
+BD2 = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "aao_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle with gcc (plain -O2, OpenMP for the
+    loops over independent columns / frequencies)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
+             _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        for name in ("or_scheme_coeffs", "or_load_sine", "or_project_sine", "or_build_rhs",
+                     "or_solve_seq", "or_adjoint_seq", "or_apply_A", "or_apply_C", "or_apply_E",
+                     "or_shifted_solve_all", "or_pinv_direct", "or_grad", "or_mk_solve"):
+            getattr(lib, name).restype = ctypes.c_int
+        for name in ("or_dft", "or_mass_apply", "or_stiff_apply", "or_symbol"):
+            getattr(lib, name).restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _chk(st, what):
+    if st != 0:
+        raise RuntimeError(f"oracle {what} failed with status {st}")
+
+
+# ------------------------------------------------------------------ space
+
+def mass(n, x):
+    x = _c(x)
+    y = np.empty(n)
+    _load().or_mass_apply(n, _p(x), _p(y))
+    return y
+
+
+def stiff(n, x):
+    x = _c(x)
+    y = np.empty(n)
+    _load().or_stiff_apply(n, _p(x), _p(y))
+    return y
+
+
+def mk_solve(n, cm, ck, r):
+    """Solve (cm M + ck K) x = r by the Thomas algorithm."""
+    r = _c(r)
+    x = np.empty(n)
+    _chk(_load().or_mk_solve(n, ctypes.c_double(cm), ctypes.c_double(ck), _p(r), _p(x)),
+         "mk_solve")
+    return x
+
+
+def scheme_coeffs(scheme, tau):
+    a = np.zeros(4)
+    b = np.zeros(4)
+    s = _load().or_scheme_coeffs(scheme, ctypes.c_double(tau), _p(a), _p(b))
+    if s < 0:
+        raise ValueError("unknown scheme")
+    return a[: s + 1].copy(), b[: s + 1].copy()
+
+
+def load_sine(n, modes, amps):
+    modes = np.ascontiguousarray(modes, dtype=np.int32)
+    amps = _c(amps)
+    f = np.empty(n)
+    _load().or_load_sine(n, len(modes), modes.ctypes.data_as(_ip), _p(amps), _p(f))
+    return f
+
+
+def project_sine(n, modes, amps):
+    """u_0 = M^{-1} f, the L2 projection of sum_m amps[m] sin(modes[m] pi x)."""
+    modes = np.ascontiguousarray(modes, dtype=np.int32)
+    amps = _c(amps)
+    u0 = np.empty(n)
+    _chk(_load().or_project_sine(n, len(modes), modes.ctypes.data_as(_ip), _p(amps), _p(u0)),
+         "project_sine")
+    return u0
+
+
+# -------------------------------------------------------------- monolithic
+
+def build_rhs(scheme, n, ell, tau, kappa, u0, v0=None):
+    u0 = _c(u0)
+    v0p = _p(_c(v0)) if v0 is not None else None
+    b = np.empty((ell, n))
+    _chk(_load().or_build_rhs(scheme, n, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                              _p(u0), v0p, _p(b)), "build_rhs")
+    return b
+
+
+def _tk(tau_k):
+    return None if tau_k is None else _p(_c(tau_k))
+
+
+def apply_A(scheme, n, ell, tau, kappa, x, transpose=False, tau_k=None):
+    x = _c(x).reshape(ell, n)
+    tk = None if tau_k is None else _c(tau_k)
+    y = np.empty((ell, n))
+    _chk(_load().or_apply_A(scheme, n, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                            _p(tk) if tk is not None else None, _p(x), _p(y), int(transpose)),
+         "apply_A")
+    return y
+
+
+def apply_C(scheme, n, ell, tau, kappa, x, transpose=False):
+    x = _c(x).reshape(ell, n)
+    y = np.empty((ell, n))
+    _chk(_load().or_apply_C(scheme, n, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                            _p(x), _p(y), int(transpose)), "apply_C")
+    return y
+
+
+def apply_E(n, ell, tau, kappa, tau_k, x):
+    x = _c(x).reshape(ell, n)
+    tk = _c(tau_k)
+    y = np.empty((ell, n))
+    _chk(_load().or_apply_E(n, ell, ctypes.c_double(tau), ctypes.c_double(kappa), _p(tk),
+                            _p(x), _p(y)), "apply_E")
+    return y
+
+
+def solve_seq(scheme, n, ell, tau, kappa, b, tau_k=None):
+    """Exact U with A U = b by forward block substitution (time stepping)."""
+    b = _c(b).reshape(ell, n)
+    tk = None if tau_k is None else _c(tau_k)
+    U = np.empty((ell, n))
+    _chk(_load().or_solve_seq(scheme, n, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                              _p(tk) if tk is not None else None, _p(b), _p(U)), "solve_seq")
+    return U
+
+
+def adjoint_seq(scheme, n, ell, tau, kappa, g, tau_k=None):
+    """Exact L with A^T L = g by backward block substitution."""
+    g = _c(g).reshape(ell, n)
+    tk = None if tau_k is None else _c(tau_k)
+    L = np.empty((ell, n))
+    _chk(_load().or_adjoint_seq(scheme, n, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                                _p(tk) if tk is not None else None, _p(g), _p(L)),
+         "adjoint_seq")
+    return L
+
+
+# ----------------------------------------------------------------- Fourier
+
+def dft(x, inverse=False):
+    """Direct DFT along axis 0 of an ell x n (complex) array."""
+    x = np.asarray(x)
+    ell, n = x.shape
+    xr = _c(x.real)
+    xi = _c(x.imag) if np.iscomplexobj(x) else None
+    Xr = np.empty((ell, n))
+    Xi = np.empty((ell, n))
+    _load().or_dft(ell, n, _p(xr), _p(xi) if xi is not None else None, _p(Xr), _p(Xi),
+                   int(inverse))
+    return Xr + 1j * Xi
+
+
+def symbol(scheme, ell, tau, j, transpose=False):
+    """(alpha_j, beta_j) with hatA_j = alpha_j M + beta_j kappa K."""
+    out = np.empty(4)
+    _load().or_symbol(scheme, ell, ctypes.c_double(tau), j, int(transpose), _p(out))
+    return complex(out[0], out[1]), complex(out[2], out[3])
+
+
+def shifted_solve_all(scheme, n, ell, tau, kappa, X, transpose=False):
+    """Y_j = hatA_j^{-1} X_j for every row j of an ell x n complex array."""
+    Xr = _c(np.real(X))
+    Xi = _c(np.imag(X))
+    _chk(_load().or_shifted_solve_all(scheme, n, ell, ctypes.c_double(tau),
+                                      ctypes.c_double(kappa), int(transpose), _p(Xr), _p(Xi)),
+         "shifted_solve_all")
+    return Xr + 1j * Xi
+
+
+def pinv_direct(scheme, n, ell, tau, kappa, r, transpose=False):
+    """C^{-1} r with the direct DFT (O(n ell^2)); returns (z, max|Im|/max|Re|)."""
+    r = _c(r).reshape(ell, n)
+    z = np.empty((ell, n))
+    ratio = ctypes.c_double(0.0)
+    _chk(_load().or_pinv_direct(scheme, n, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                                int(transpose), _p(r), _p(z), ctypes.byref(ratio)),
+         "pinv_direct")
+    return z, ratio.value
+
+
+def pinv(scheme, n, ell, tau, kappa, r, transpose=False):
+    """C^{-1} r with numpy's FFT as the transform step (same definition as
+    ``pinv_direct``; numpy.fft.fft uses the kernel exp(-2 pi i jk/ell))."""
+    r = _c(r).reshape(ell, n)
+    X = np.fft.fft(r, axis=0)
+    Y = shifted_solve_all(scheme, n, ell, tau, kappa, X, transpose)
+    return np.ascontiguousarray(np.fft.ifft(Y, axis=0).real)
+
+
+def neumann(scheme, n, ell, tau, kappa, tau_k, r, order, transpose=False, direct=False):
+    """Truncated Neumann series of eq. preconapprox1,
+    sum_{m=0}^{order} (-C^{-1} E)^m C^{-1} r, E = blockdiag((tau_k - tau) kappa K),
+    evaluated by the recurrence z_0 = C^{-1} r, z_m = C^{-1}(r - E z_{m-1}).
+    (E is block diagonal and symmetric, so the transposed series uses C^{-T}.)"""
+    P = (lambda v: pinv_direct(scheme, n, ell, tau, kappa, v, transpose)[0]) if direct else \
+        (lambda v: pinv(scheme, n, ell, tau, kappa, v, transpose))
+    r = _c(r).reshape(ell, n)
+    z = P(r)
+    for _ in range(order):
+        z = P(r - apply_E(n, ell, tau, kappa, tau_k, z))
+    return z
+
+
+# ------------------------------------------------------------------ GMRES
+
+def fgmres(apply_op, apply_prec, b, restart, tol, maxit, x0=None):
+    """Restarted right-preconditioned flexible GMRES (modified Gram-Schmidt,
+    Givens rotations), stopping when the least-squares residual estimate
+    |g_{j+1}| / ||b|| <= tol and confirming with the true residual
+    ||b - A x|| / ||b|| before returning.  Counts preconditioner applies.
+
+    Returns (x, info) with info = dict(iters, restarts, converged, est, true, hist)."""
+    b = _c(b).ravel()
+    N = b.size
+    x = np.zeros(N) if x0 is None else _c(x0).ravel().copy()
+    bnorm = np.linalg.norm(b)
+    info = dict(iters=0, restarts=0, converged=False, est=np.nan, true=np.nan, hist=[])
+    if bnorm == 0.0:
+        x[:] = 0.0
+        info.update(converged=True, est=0.0, true=0.0)
+        return x, info
+    r = b - apply_op(x)
+    beta = np.linalg.norm(r)
+    info["true"] = beta / bnorm
+    if beta / bnorm <= tol:
+        info.update(converged=True, est=beta / bnorm)
+        return x, info
+    while info["iters"] < maxit:
+        m = restart
+        V = np.zeros((m + 1, N))
+        Z = np.zeros((m, N))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        V[0] = r / beta
+        g[0] = beta
+        k = 0
+        for j in range(m):
+            Z[j] = apply_prec(V[j])
+            w = apply_op(Z[j])
+            info["iters"] += 1
+            for i in range(j + 1):
+                H[i, j] = np.dot(w, V[i])
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            if H[j + 1, j] != 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j] = H[j, j] / den
+            sn[j] = H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            est = abs(g[j + 1]) / bnorm
+            info["hist"].append(est)
+            info["est"] = est
+            if est <= tol or info["iters"] >= maxit:
+                break
+        y = np.zeros(k)
+        for i in range(k - 1, -1, -1):
+            y[i] = (g[i] - np.dot(H[i, i + 1:k], y[i + 1:k])) / H[i, i]
+        x = x + Z[:k].T @ y
+        r = b - apply_op(x)
+        beta = np.linalg.norm(r)
+        info["true"] = beta / bnorm
+        if beta / bnorm <= tol:
+            info["converged"] = True
+            break
+        info["restarts"] += 1
+    return x, info
+
+
+# --------------------------------------------------------------- gradient
+
+def grad(scheme, n, ell, tau, kappa, u0, U, L, v0=None, tau_k=None):
+    """(g_u0, g_v0, g_kappa) of L(U) given the adjoint solution L (A^T L = dL/dU)."""
+    u0 = _c(u0)
+    U = _c(U).reshape(ell, n)
+    L = _c(L).reshape(ell, n)
+    v0c = _c(v0) if v0 is not None else None
+    tk = None if tau_k is None else _c(tau_k)
+    gu = np.empty(n)
+    gv = np.empty(n)
+    gk = ctypes.c_double(0.0)
+    _chk(_load().or_grad(scheme, n, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                         _p(tk) if tk is not None else None, _p(u0),
+                         _p(v0c) if v0c is not None else None, _p(U), _p(L), _p(gu), _p(gv),
+                         ctypes.byref(gk)), "grad")
+    return gu, gv, gk.value
+
+
+# ------------------------------------------------------- dense tiny cases
+
+def dense_MK(n):
+    """Assembled M and K (n x n), for the dense checks on tiny sizes."""
+    h = 1.0 / (n + 1)
+    M = (h / 6.0) * (4.0 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1))
+    K = (1.0 / h) * (2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1))
+    return M, K
+
+
+def dense_A(scheme, n, ell, tau, kappa, circulant=False, tau_k=None):
+    """Assembled monolithic matrix (or its block circulant) for tiny sizes."""
+    a, b = scheme_coeffs(scheme, tau)
+    M, K = dense_MK(n)
+    A = np.zeros((n * ell, n * ell))
+    for k in range(ell):
+        for m in range(len(a)):
+            src = k - m
+            if src < 0:
+                if not circulant:
+                    continue
+                src += ell
+            blk = a[m] * M + b[m] * kappa * K
+            if m == 0 and tau_k is not None and scheme == HEAT:
+                blk = M + tau_k[k] * kappa * K
+            A[k * n:(k + 1) * n, src * n:(src + 1) * n] += blk
+    return A

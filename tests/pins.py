@@ -1,0 +1,125 @@
+"""Independent mathematics used to pin the oracle (closed forms, quadrature,
+dense Kronecker assembly).  Nothing here calls the oracle or the GPU library."""
+import numpy as np
+from scipy import integrate
+
+
+def hat(i, n):
+    """P1 hat function of interior node i (1-based) on the uniform mesh."""
+    h = 1.0 / (n + 1)
+    xi = i * h
+
+    def phi(x):
+        return max(0.0, 1.0 - abs(x - xi) / h)
+    return phi, xi - h, xi + h
+
+
+def quad_MK(n):
+    """M_ij = int phi_i phi_j, K_ij = int phi_i' phi_j' by adaptive quadrature
+    (element by element, so the kinks sit on interval ends)."""
+    h = 1.0 / (n + 1)
+    M = np.zeros((n, n))
+    K = np.zeros((n, n))
+    for i in range(1, n + 1):
+        for j in range(max(1, i - 1), min(n, i + 1) + 1):
+            pi, a, b = hat(i, n)
+            pj, _, _ = hat(j, n)
+            lo = max(a, (j - 1) * h)
+            hi = min(b, (j + 1) * h)
+            if hi <= lo:
+                continue
+            nodes = np.arange(0, n + 2) * h
+            pts = [p for p in nodes if lo < p < hi]
+            edges = [lo] + pts + [hi]
+            mv = 0.0
+            kv = 0.0
+            for e0, e1 in zip(edges[:-1], edges[1:]):
+                mv += integrate.quad(lambda x: pi(x) * pj(x), e0, e1, epsabs=1e-15, epsrel=1e-13)[0]
+                mid = 0.5 * (e0 + e1)
+                di = (1.0 / h) * (1 if mid < i * h else -1)
+                dj = (1.0 / h) * (1 if mid < j * h else -1)
+                kv += di * dj * (e1 - e0)
+            M[i - 1, j - 1] = mv
+            K[i - 1, j - 1] = kv
+    return M, K
+
+
+def sine_vec(n, m):
+    h = 1.0 / (n + 1)
+    return np.sin(m * np.pi * h * np.arange(1, n + 1))
+
+
+def mu(n, m):
+    """Eigenvalue of M on sine mode m."""
+    h = 1.0 / (n + 1)
+    return (h / 3.0) * (2.0 + np.cos(m * np.pi * h))
+
+
+def lam(n, m):
+    """Generalised eigenvalue of (K, M) on sine mode m."""
+    h = 1.0 / (n + 1)
+    c = np.cos(m * np.pi * h)
+    return 6.0 * (1.0 - c) / (h * h * (2.0 + c))
+
+
+def sine_coeffs(u):
+    """Coefficients c_m with u = sum_m c_m s_m (discrete sine transform, DST-I)."""
+    n = u.size
+    h = 1.0 / (n + 1)
+    i = np.arange(1, n + 1)
+    S = np.sin(np.pi * h * np.outer(np.arange(1, n + 1), i))
+    return (2.0 / (n + 1)) * S @ u
+
+
+def sine_synth(c):
+    n = c.size
+    h = 1.0 / (n + 1)
+    i = np.arange(1, n + 1)
+    S = np.sin(np.pi * h * np.outer(np.arange(1, n + 1), i))
+    return S.T @ c
+
+
+def heat_closed_form(u0, ell, tau, kappa):
+    """u_k = sum_m c_m (1 + tau kappa lambda_m)^{-k} s_m, k = 1..ell."""
+    n = u0.size
+    c = sine_coeffs(u0)
+    m = np.arange(1, n + 1)
+    fac = 1.0 / (1.0 + tau * kappa * lam(n, m))
+    U = np.empty((ell, n))
+    ck = c.copy()
+    for k in range(ell):
+        ck = ck * fac
+        U[k] = sine_synth(ck)
+    return U
+
+
+def bd2_closed_form(u0, v0, ell, tau, kappa):
+    """Per sine mode the BD2 recursion (1 + tau^2 kappa lambda) c_k - 2 c_{k-1} + c_{k-2} = 0
+    with c_0 = u_0 mode, c_1 = c_0 + tau d_0 has c_k = rho^k (c_0 cos k phi + B sin k phi),
+    rho = (1 + tau^2 kappa lambda)^{-1/2}, phi = atan(tau sqrt(kappa lambda))."""
+    n = u0.size
+    c0 = sine_coeffs(u0)
+    d0 = sine_coeffs(v0) if v0 is not None else np.zeros(n)
+    m = np.arange(1, n + 1)
+    lm = lam(n, m)
+    rho = 1.0 / np.sqrt(1.0 + tau * tau * kappa * lm)
+    phi = np.arctan(tau * np.sqrt(kappa * lm))
+    c1 = c0 + tau * d0
+    B = (c1 / rho - c0 * np.cos(phi)) / np.sin(phi)
+    U = np.empty((ell, n))
+    for k in range(1, ell + 1):
+        ck = rho ** k * (c0 * np.cos(k * phi) + B * np.sin(k * phi))
+        U[k - 1] = sine_synth(ck)
+    return U
+
+
+def kron_A(blocks, ell, circulant=False):
+    """sum_m Shift^m (x) A_m with Shift the ell x ell down-shift (cyclic if circulant)."""
+    n = blocks[0].shape[0]
+    A = np.zeros((n * ell, n * ell))
+    for m, B in enumerate(blocks):
+        S = np.eye(ell, k=-m)
+        if circulant and m > 0:
+            S = S + np.eye(ell, k=ell - m)
+        A += np.kron(S, B)
+    return A
