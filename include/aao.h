@@ -1,0 +1,194 @@
+/*
+ * aao.h -- C ABI of the all-at-once parallel-in-time solver for gfx950 (MI355X).
+ *
+ * The library solves the monolithic ("all-at-once") time-stepping system
+ *     A U = b,   A block lower-triangular Toeplitz, U = [u_1; ...; u_ell]
+ * of Goddard & Wathen, "A note on parallel preconditioning for all-at-once
+ * evolutionary PDEs" (arXiv 1810.00615), Sec. 2, by GMRES preconditioned with the
+ * block circulant C of McDonald, Pestana & Wathen (eq. standardheatprecon,
+ * eq. wavepreconditioner), applied through its Fourier diagonalisation
+ * (Sec. 3, eq. precon2para).
+ *
+ * Discretisation (Sec. 2): 1D, Omega = [0,1], n interior nodes of a uniform P1
+ * mesh (h = 1/(n+1)), M = (h/6) tridiag(1,4,1), K = (1/h) tridiag(-1,2,-1), a
+ * diffusivity / wave-speed factor kappa multiplying K, ell time steps of size tau.
+ *   AAO_HEAT_IE  implicit Euler, eq. timestepproblem1 / monolithicheat:
+ *                A_0 = M + tau kappa K, A_1 = -M            (s = 1)
+ *   AAO_WAVE_BD2 two-step backward difference, system C_BD2:
+ *                A_0 = M + tau^2 kappa K, A_1 = -2M, A_2 = M (s = 2)
+ * (The paper prints the heat block as K + tau M; implicit Euler on
+ * M u' = -K u gives M + tau K, which is what is built.)
+ *
+ * Conventions for every entry point:
+ *   - Vectors of the monolithic system are caller-owned DEVICE pointers to
+ *     ell*n contiguous doubles, row-major ell x n: row k holds time level k+1,
+ *     the n spatial nodes contiguous.  Per-node vectors (u0, v0, gradients) are
+ *     device pointers to n doubles.  Arrays marked "host" are host memory.
+ *   - Operations are enqueued on the context's stream (aao_set_stream; default:
+ *     the null stream).  apply_* return without synchronising; gmres /
+ *     adjoint_solve / grad synchronise the stream before they return.
+ *   - Input and output vectors must not overlap (AAO_ERR_ARG otherwise).
+ *   - A negative status is an error and leaves outputs unspecified.  The context
+ *     stays usable after every error except AAO_ERR_HIP.  No C++ exception
+ *     crosses this interface.
+ *   - A context is not thread-safe; distinct contexts may be used from distinct
+ *     threads on distinct streams.
+ */
+#ifndef AAO_H
+#define AAO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct aao_ctx_s *aao_ctx;
+
+typedef enum {
+    AAO_OK = 0,
+    AAO_NOT_CONVERGED = 1,  /* maxit reached: x holds the last iterate, info filled */
+    AAO_ERR_ARG = -1,       /* bad size, step, pointer, aliasing or option        */
+    AAO_ERR_ALLOC = -2,     /* device allocation failed                            */
+    AAO_ERR_HIP = -3,       /* HIP runtime error (context unusable afterwards)     */
+    AAO_ERR_NUMERIC = -4,   /* non-finite residual / breakdown of a shifted solve  */
+    AAO_ERR_STATE = -5,     /* call out of order (e.g. steps set for BD2)          */
+    AAO_ERR_UNSUPPORTED = -6
+} aao_status;
+
+enum { AAO_HEAT_IE = 0, AAO_WAVE_BD2 = 1 };
+
+/* Precision of the preconditioner apply inside GMRES (aao_set_precision).
+ *   AAO_PREC_FP64   FFTs, spectra and shifted solves in double.
+ *   AAO_PREC_MIXED  FFTs and spectra in single precision, shifted solves in
+ *                   double arithmetic on single-precision spectra; the outer
+ *                   flexible GMRES (matvec, residual, Arnoldi, update) stays
+ *                   double.
+ *   AAO_PREC_FP32   as MIXED with the shifted solves in single precision too. */
+enum { AAO_PREC_FP64 = 0, AAO_PREC_MIXED = 1, AAO_PREC_FP32 = 2 };
+
+typedef struct {
+    int iters;              /* preconditioner applies (GMRES iterations)          */
+    int restarts;           /* completed restart cycles                            */
+    int converged;          /* 1 if the true relative residual <= tol              */
+    double rel_resid_est;   /* last least-squares estimate |g_{j+1}| / ||b||      */
+    double rel_resid_true;  /* ||b - A x|| / ||b|| recomputed in FP64 at the end   */
+} aao_info;
+
+/* Create a context for n >= 1 interior nodes, ell >= 1 steps of size tau > 0
+ * (tau is the step of the Toeplitz matrix and of the circulant; the mean step
+ * when variable steps are set), scheme AAO_HEAT_IE or AAO_WAVE_BD2.  kappa = 1.
+ * Allocates the device tables on the current HIP device.  Sec. 2. */
+aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *out);
+
+/* Free every device buffer of the context.  NULL is accepted. */
+aao_status aao_destroy(aao_ctx ctx);
+
+/* Stream on which every later call of this context is enqueued (a hipStream_t;
+ * NULL = the null stream). */
+aao_status aao_set_stream(aao_ctx ctx, void *hip_stream);
+
+/* Multiply K by kappa > 0 in every block (heat diffusivity, squared wave speed). */
+aao_status aao_set_kappa(aao_ctx ctx, double kappa);
+
+/* Variable steps tau_1..tau_ell (host array of ell positive doubles), heat only:
+ * the matrix B of eq. nonuniformmonolithicheat with A_0^k = M + tau_k kappa K.
+ * aao_apply_A and aao_gmres then use B, and aao_apply_Pinv with order q >= 1
+ * applies the truncated Neumann series of eq. preconapprox1 for
+ * Q = C + blockdiag((tau_k - tau) kappa K).  NULL restores uniform steps.
+ * AAO_ERR_STATE for the wave scheme. */
+aao_status aao_set_steps(aao_ctx ctx, const double *tau_k);
+
+/* AAO_PREC_FP64 (default), AAO_PREC_MIXED or AAO_PREC_FP32. */
+aao_status aao_set_precision(aao_ctx ctx, int prec);
+
+/* Initial data as a sine series s(x) = sum_m amps[m] sin(modes[m] pi x) (host
+ * arrays of J entries, modes >= 1): writes the L2 projection u0 = M^{-1} f onto
+ * the P1 space (device, n doubles), f_i = int s phi_i.  The initial state
+ * "is a projection of the initial data" (Sec. 2, after eq. timestepproblem1). */
+aao_status aao_project_sine(aao_ctx ctx, int J, const int *modes, const double *amps,
+                            double *u0);
+
+/* Right-hand side b (device, ell x n) from u0 (device, n) and, for BD2, the
+ * initial velocity v0 (device, n, or NULL for v0 = 0):
+ *   heat: b_1 = M u0 (eq. monolithicheat), other rows 0;
+ *   BD2:  b_1 = A_0 (u0 + tau v0), b_2 = -M u0, other rows 0 (system C_BD2,
+ *         with the start-up row u_1 = u0 + tau v0). */
+aao_status aao_build_rhs(aao_ctx ctx, const double *u0, const double *v0, double *b);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1); with variable steps, B
+ * or B^T.  x, y: device, ell x n.  Sec. 2, eq. monolithicheat / C_BD2. */
+aao_status aao_apply_A(aao_ctx ctx, const double *x, double *y, int transpose);
+
+/* z = C^{-1} r (transpose = 0) or C^{-T} r (transpose = 1) through
+ * eq. precon2para: FFT along time, one complex shifted tridiagonal solve per
+ * frequency, inverse FFT.  neumann_order q >= 1 (variable steps set) applies
+ * sum_{m=0}^{q} (-C^{-1} E)^m C^{-1} r (eq. preconapprox1 with i = q + 1 terms),
+ * evaluated as z_0 = C^{-1} r, z_m = C^{-1}(r - E z_{m-1}); with uniform steps
+ * every order equals order 0.  Uses the context precision.  r, z: device,
+ * ell x n, must not overlap. */
+aao_status aao_apply_Pinv(aao_ctx ctx, const double *r, double *z, int neumann_order,
+                          int transpose);
+
+/* Restarted right-preconditioned flexible GMRES(restart) for A x = b (device
+ * vectors; x holds the initial guess on entry -- pass zeros for x0 = 0 -- and
+ * the solution on return), preconditioner aao_apply_Pinv(neumann_order =
+ * aao_set_neumann_order, default 0).  Arnoldi is classical Gram-Schmidt with
+ * one re-orthogonalisation (CGS2) in FP64.  Stops when the least-squares
+ * estimate |g_{j+1}| / ||b|| <= tol, then confirms with the true residual
+ * ||b - A x|| / ||b|| and restarts if it is above tol.  At most maxit
+ * preconditioner applies.  Returns AAO_OK, AAO_NOT_CONVERGED (x = last iterate)
+ * or an error; info (host, may be NULL) is filled in either of the first two
+ * cases.  GMRES: Saad & Schultz, cited in Sec. 1. */
+aao_status aao_gmres(aao_ctx ctx, const double *b, double *x, int restart, double tol,
+                     int maxit, aao_info *info);
+
+/* Neumann order used by aao_gmres and aao_adjoint_solve (default 0). */
+aao_status aao_set_neumann_order(aao_ctx ctx, int q);
+
+/* Adjoint solve A^T lam = g by the same GMRES, preconditioned with C^{-T}
+ * (the conjugated symbol).  g, lam: device, ell x n; lam holds the initial
+ * guess on entry.  Same return convention as aao_gmres. */
+aao_status aao_adjoint_solve(aao_ctx ctx, const double *g, double *lam, int restart,
+                             double tol, int maxit, aao_info *info);
+
+/* Gradient reductions for L(U) with A(kappa) U = b(u0, v0, kappa), given the
+ * forward solution U and the adjoint lam (A^T lam = dL/dU), all device:
+ *   g_u0    (device, n)   = (db/du0)^T lam   heat: M lam_1;
+ *                                            BD2: A_0 lam_1 - M lam_2
+ *   g_v0    (device, n or NULL) = (db/dv0)^T lam  (BD2: tau A_0 lam_1; heat: 0)
+ *   g_kappa (host scalar, may be NULL) = lam^T db/dkappa - lam^T (dA/dkappa) U,
+ *           (dA/dkappa U)_k = sum_m b_m^{(k)} K u_{k-m}.
+ * u0 and v0 are needed only for the BD2 kappa term (NULL allowed otherwise). */
+aao_status aao_grad(aao_ctx ctx, const double *u0, const double *v0, const double *U,
+                    const double *lam, double *g_u0, double *g_v0, double *g_kappa);
+
+/* Per-kernel timing, for measurement.  aao_set_timing(ctx, 1) clears the
+ * accumulators and brackets every later kernel launch of the context with a pair
+ * of HIP events on the context stream; aao_get_timing synchronises the stream and
+ * returns the summed duration (ms) and launch count of one kernel class. */
+enum {
+    AAO_K_FFT_FWD = 0,          /* time-axis transform, real -> half spectrum     */
+    AAO_K_SHIFTED_SOLVE = 1,    /* complex shifted tridiagonal solves             */
+    AAO_K_FFT_INV = 2,          /* half spectrum -> real                          */
+    AAO_K_MATVEC = 3,           /* block-Toeplitz matvec / residual               */
+    AAO_K_CGS_DOT = 4,          /* Gram-Schmidt: projections                      */
+    AAO_K_CGS_UPDATE_DOT = 5,   /* Gram-Schmidt: update + re-projections          */
+    AAO_K_CGS_UPDATE_NORM = 6,  /* Gram-Schmidt: update + norm                    */
+    AAO_K_AXPY = 7,             /* solution update x += Z y                       */
+    AAO_NUM_KERNELS = 8
+};
+aao_status aao_set_timing(aao_ctx ctx, int enable);
+aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count);
+
+/* Text of a status code (static storage). */
+const char *aao_status_string(aao_status st);
+
+/* Last error detail recorded on this context (static per context; "" if none). */
+const char *aao_last_error(aao_ctx ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AAO_H */

@@ -127,7 +127,8 @@ void or_load_sine(int n, int J, const int *modes, const double *amps, double *f)
     for (int i = 0; i < n; ++i) f[i] = 0.0;
     for (int m = 0; m < J; ++m) {
         double q = (double)modes[m];
-        double g = 2.0 * (1.0 - cos(q * M_PI * h)) / (h * q * q * M_PI * M_PI);
+        double sh = sin(0.5 * q * M_PI * h);          /* 1 - cos(q pi h) = 2 sin^2(q pi h/2) */
+        double g = 4.0 * sh * sh / (h * q * q * M_PI * M_PI);
         for (int i = 0; i < n; ++i) f[i] += amps[m] * g * sin(q * M_PI * (i + 1) * h);
     }
 }

@@ -1,0 +1,12 @@
+"""All-at-once parallel-in-time solver for gfx950 (MI355X).
+
+Block-circulant-preconditioned flexible GMRES for the monolithic time-stepping
+systems of Goddard & Wathen (arXiv 1810.00615): heat (implicit Euler) and wave
+(BD2) in 1D, with the preconditioner applied by time-axis FFTs and batched
+complex shifted tridiagonal solves written in HIP.  The C ABI is
+include/aao.h; this package is its Python binding (torch supplies memory and
+streams).
+"""
+from .api import BD2, HEAT, AAOError, Problem  # noqa: F401
+
+__all__ = ["Problem", "AAOError", "HEAT", "BD2"]

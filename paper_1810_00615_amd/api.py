@@ -1,0 +1,215 @@
+"""Python front end of libaao: torch tensors in, torch tensors out.
+
+torch supplies device memory and the stream; every step of the computation runs
+in the library's HIP kernels (see include/aao.h).  All vectors are float64 and
+contiguous on the problem's device; a vector of the monolithic system is an
+(ell, n) tensor whose row k holds time level k+1.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+import torch
+
+from ._lib import KERNELS, AAOError, Info, check, lib
+
+HEAT, BD2 = 0, 1
+SCHEMES = {"heat": HEAT, "heat_ie": HEAT, "bd2": BD2, "wave_bd2": BD2}
+PRECISIONS = {"fp64": 0, "mixed": 1, "fp32": 2}
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One all-at-once system A U = b (arXiv 1810.00615, Sec. 2) on one GPU.
+
+    Parameters follow the paper's statement of the problem: n interior nodes,
+    ell time steps of size tau (default 1/ell, i.e. T = 1), the scheme
+    ("heat" = implicit Euler, "bd2" = two-step backward difference for the wave
+    equation), the coefficient kappa of K, optional variable steps (heat) and
+    the precision of the preconditioner apply ("fp64", "mixed", "fp32")."""
+
+    def __init__(self, n: int, ell: int, tau: Optional[float] = None, scheme="heat",
+                 kappa: float = 1.0, precision: str = "fp64", steps=None, neumann_order: int = 0,
+                 device="cuda"):
+        self.n = int(n)
+        self.ell = int(ell)
+        self.tau = float(tau) if tau is not None else 1.0 / self.ell
+        self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the all-at-once library runs on a GPU device only")
+        self._L = lib()
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self._L.aao_create(self.n, self.ell, self.tau, self.scheme,
+                                    ctypes.byref(self._ctx))
+        check(st, "aao_create")
+        self.kappa = None
+        self.set_kappa(kappa)
+        self.precision = None
+        self.set_precision(precision)
+        self.neumann_order = 0
+        self.set_neumann_order(neumann_order)
+        self.steps = None
+        if steps is not None:
+            self.set_steps(steps)
+
+    # -------------------------------------------------------------- setup
+    def _c(self, st, where):
+        return check(st, where, self._ctx)
+
+    def close(self):
+        if self._ctx:
+            self._L.aao_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_kappa(self, kappa: float):
+        self._c(self._L.aao_set_kappa(self._ctx, float(kappa)), "aao_set_kappa")
+        self.kappa = float(kappa)
+
+    def set_precision(self, precision: str):
+        self._c(self._L.aao_set_precision(self._ctx, PRECISIONS[precision]), "aao_set_precision")
+        self.precision = precision
+
+    def set_neumann_order(self, q: int):
+        self._c(self._L.aao_set_neumann_order(self._ctx, int(q)), "aao_set_neumann_order")
+        self.neumann_order = int(q)
+
+    def set_steps(self, steps):
+        if steps is None:
+            self._c(self._L.aao_set_steps(self._ctx, None), "aao_set_steps")
+            self.steps = None
+            return
+        arr = np.ascontiguousarray(np.asarray(steps, dtype=np.float64))
+        if arr.shape != (self.ell,):
+            raise ValueError(f"steps must have shape ({self.ell},)")
+        self._c(self._L.aao_set_steps(self._ctx, arr.ctypes.data_as(ctypes.c_void_p)),
+                "aao_set_steps")
+        self.steps = arr
+
+    def _stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._c(self._L.aao_set_stream(self._ctx, ctypes.c_void_p(s)), "aao_set_stream")
+
+    def _vec(self, x: torch.Tensor, shape, name):
+        if not isinstance(x, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if x.dtype != torch.float64 or x.device != self.device or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if tuple(x.shape) != tuple(shape) and x.numel() != int(np.prod(shape)):
+            raise ValueError(f"{name} must have shape {shape}")
+        return x
+
+    def empty(self):
+        return torch.empty((self.ell, self.n), dtype=torch.float64, device=self.device)
+
+    def zeros(self):
+        return torch.zeros((self.ell, self.n), dtype=torch.float64, device=self.device)
+
+    # ----------------------------------------------------------- operators
+    def project_sine(self, modes, amps) -> torch.Tensor:
+        """L2 projection onto the P1 space of sum_m amps[m] sin(modes[m] pi x)."""
+        modes = np.ascontiguousarray(np.asarray(modes, dtype=np.int32))
+        amps = np.ascontiguousarray(np.asarray(amps, dtype=np.float64))
+        u0 = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        self._stream()
+        self._c(self._L.aao_project_sine(self._ctx, len(modes), modes.ctypes.data_as(ctypes.c_void_p),
+                                         amps.ctypes.data_as(ctypes.c_void_p), _ptr(u0)),
+                "aao_project_sine")
+        return u0
+
+    def rhs(self, u0: torch.Tensor, v0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._vec(u0, (self.n,), "u0")
+        if v0 is not None:
+            self._vec(v0, (self.n,), "v0")
+        b = self.empty()
+        self._stream()
+        self._c(self._L.aao_build_rhs(self._ctx, _ptr(u0), _ptr(v0), _ptr(b)), "aao_build_rhs")
+        return b
+
+    def A(self, x: torch.Tensor, transpose: bool = False, out=None) -> torch.Tensor:
+        self._vec(x, (self.ell, self.n), "x")
+        y = self.empty() if out is None else self._vec(out, (self.ell, self.n), "out")
+        self._stream()
+        self._c(self._L.aao_apply_A(self._ctx, _ptr(x), _ptr(y), int(transpose)), "aao_apply_A")
+        return y
+
+    def Pinv(self, r: torch.Tensor, order: int = 0, transpose: bool = False, out=None):
+        self._vec(r, (self.ell, self.n), "r")
+        z = self.empty() if out is None else self._vec(out, (self.ell, self.n), "out")
+        self._stream()
+        self._c(self._L.aao_apply_Pinv(self._ctx, _ptr(r), _ptr(z), int(order), int(transpose)),
+                "aao_apply_Pinv")
+        return z
+
+    def solve(self, b: torch.Tensor, restart: int = 30, tol: float = 1e-8, maxit: int = 300,
+              x0: Optional[torch.Tensor] = None, out=None):
+        """FGMRES(restart) with the circulant preconditioner; returns (U, info)."""
+        self._vec(b, (self.ell, self.n), "b")
+        x = out if out is not None else self.empty()
+        if x0 is None:
+            x.zero_()
+        else:
+            x.copy_(x0)
+        info = Info()
+        self._stream()
+        st = self._L.aao_gmres(self._ctx, _ptr(b), _ptr(x), int(restart), float(tol), int(maxit),
+                               ctypes.byref(info))
+        self._c(st, "aao_gmres")
+        d = info.as_dict()
+        d["status"] = st
+        return x, d
+
+    def adjoint(self, g: torch.Tensor, restart: int = 30, tol: float = 1e-8, maxit: int = 300,
+                out=None):
+        """Solve A^T lam = g (preconditioned with C^{-T}); returns (lam, info)."""
+        self._vec(g, (self.ell, self.n), "g")
+        lam = out if out is not None else self.empty()
+        lam.zero_()
+        info = Info()
+        self._stream()
+        st = self._L.aao_adjoint_solve(self._ctx, _ptr(g), _ptr(lam), int(restart), float(tol),
+                                       int(maxit), ctypes.byref(info))
+        self._c(st, "aao_adjoint_solve")
+        d = info.as_dict()
+        d["status"] = st
+        return lam, d
+
+    def set_timing(self, enable: bool = True):
+        """Bracket every kernel launch with HIP events (clears the accumulators)."""
+        self._c(self._L.aao_set_timing(self._ctx, int(enable)), "aao_set_timing")
+
+    def timing(self):
+        """{kernel: (total_ms, launches)} accumulated since set_timing(True)."""
+        out = {}
+        for i, name in enumerate(KERNELS):
+            t = ctypes.c_double(0.0)
+            c = ctypes.c_int64(0)
+            self._c(self._L.aao_get_timing(self._ctx, i, ctypes.byref(t), ctypes.byref(c)),
+                    "aao_get_timing")
+            out[name] = (t.value, c.value)
+        return out
+
+    def grad(self, U, lam, u0=None, v0=None, want_v0=False):
+        """(g_u0, g_v0, g_kappa) of L(U) from the adjoint solution lam."""
+        gu = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        gv = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_v0 else None
+        gk = ctypes.c_double(0.0)
+        self._stream()
+        self._c(self._L.aao_grad(self._ctx, _ptr(u0), _ptr(v0), _ptr(U), _ptr(lam), _ptr(gu),
+                                 _ptr(gv), ctypes.byref(gk)), "aao_grad")
+        return gu, gv, gk.value
+
+
+__all__ = ["Problem", "AAOError", "HEAT", "BD2"]

@@ -1,0 +1,737 @@
+// Host runtime and C ABI of libaao (declared in include/aao.h).
+//
+// The context owns every device buffer: the twiddle table of the time FFT, the
+// half spectrum of the preconditioner apply, the GMRES basis (stored
+// unnormalised, with per-vector scales kept on the device), the search
+// directions Z of flexible GMRES, reduction partials and a few scalars.  Every
+// operation is enqueued on the context stream; GMRES synchronises once per
+// Arnoldi step to read the new Hessenberg column (j+2 doubles) for the Givens
+// update on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/aao.h"
+#include "aao_internal.h"
+
+using namespace aao;
+
+namespace {
+
+constexpr int kMaxRestart = 63;
+constexpr int kSmallStride = 80;   // doubles per small-scalar array
+
+struct Status {
+    aao_status st;
+};
+
+}  // namespace
+
+struct aao_ctx_s {
+    int64_t n = 0, ell = 0;
+    double tau = 0.0;
+    int scheme = 0;
+    double kappa = 1.0;
+    int prec = AAO_PREC_FP64;
+    int neumann = 0;
+    Scheme sc{};
+    hipStream_t st = nullptr;
+    int device = 0;
+    bool broken = false;
+    std::string err;
+
+    double *tw = nullptr;        // ell complex twiddles
+    double *tauk = nullptr;      // variable steps (device, ell) or null
+    double *sigk = nullptr;      // tau_k - tau (device, ell)
+    void *spec = nullptr;        // half spectrum
+    int lds = 0;
+    int *fail = nullptr;         // shifted-solve breakdown flag
+
+    // GMRES workspace
+    int m_alloc = 0;
+    double *V = nullptr, *Z = nullptr, *W = nullptr;
+    double **dV = nullptr, **dZ = nullptr;
+    double *part = nullptr;
+    int nblk = 0, ldp = 0;
+    double *small = nullptr;     // d | h1 | h2 | c | vs | hcol | y
+    double *tmpn = nullptr;      // n-vector scratch
+    int *dmodes = nullptr;
+    double *damps = nullptr;
+    int nmodes_alloc = 0;
+
+    // per-kernel timing (aao_set_timing): event pairs recorded around launches
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    double t_total[AAO_NUM_KERNELS] = {};
+    long long t_count[AAO_NUM_KERNELS] = {};
+
+    size_t N() const { return (size_t)n * (size_t)ell; }
+    double *sd() { return small; }
+    double *sh1() { return small + kSmallStride; }
+    double *sh2() { return small + 2 * kSmallStride; }
+    double *sc_() { return small + 3 * kSmallStride; }
+    double *svs() { return small + 4 * kSmallStride; }
+    double *shcol() { return small + 5 * kSmallStride; }
+    double *sy() { return small + 6 * kSmallStride; }
+};
+
+#define AAO_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
+            ctx->broken = true;                                                         \
+            return AAO_ERR_HIP;                                                         \
+        }                                                                               \
+    } while (0)
+
+static hipEvent_t ev_get(aao_ctx ctx)
+{
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `call` on the context stream; with timing enabled, bracket it with events.
+#define AAO_LAUNCH(id, call)                                                            \
+    do {                                                                                \
+        hipEvent_t e0_ = nullptr, e1_ = nullptr;                                        \
+        if (ctx->timing) {                                                              \
+            e0_ = ev_get(ctx);                                                          \
+            e1_ = ev_get(ctx);                                                          \
+            if (e0_) (void)hipEventRecord(e0_, ctx->st);                                \
+        }                                                                               \
+        AAO_HIP(call);                                                                  \
+        if (ctx->timing && e0_ && e1_) {                                                \
+            (void)hipEventRecord(e1_, ctx->st);                                         \
+            ctx->ev_pending.push_back({(id), {e0_, e1_}});                              \
+        }                                                                               \
+    } while (0)
+
+#define AAO_TRY(expr)                                                                   \
+    do {                                                                                \
+        aao_status s_ = (expr);                                                         \
+        if (s_ < 0) return s_;                                                          \
+    } while (0)
+
+static aao_status arg_err(aao_ctx ctx, const char *msg)
+{
+    if (ctx) ctx->err = msg;
+    return AAO_ERR_ARG;
+}
+
+static bool overlap(const void *a, const void *b, size_t bytes)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+static aao_status dev_alloc(aao_ctx ctx, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        ctx->err = std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e);
+        return AAO_ERR_ALLOC;
+    }
+    return AAO_OK;
+}
+
+static void scheme_of(aao_ctx ctx)
+{
+    Scheme s{};
+    if (ctx->scheme == AAO_HEAT_IE) {
+        s.s = 1;
+        s.a[0] = 1.0;  s.b[0] = ctx->tau;
+        s.a[1] = -1.0; s.b[1] = 0.0;
+    } else {
+        s.s = 2;
+        s.a[0] = 1.0;  s.b[0] = ctx->tau * ctx->tau;
+        s.a[1] = -2.0; s.b[1] = 0.0;
+        s.a[2] = 1.0;  s.b[2] = 0.0;
+    }
+    ctx->sc = s;
+}
+
+static void free_workspace(aao_ctx ctx)
+{
+    (void)hipFree(ctx->V);
+    (void)hipFree(ctx->Z);
+    (void)hipFree(ctx->W);
+    (void)hipFree(ctx->dV);
+    (void)hipFree(ctx->dZ);
+    ctx->V = ctx->Z = ctx->W = nullptr;
+    ctx->dV = ctx->dZ = nullptr;
+    ctx->m_alloc = 0;
+}
+
+static aao_status ensure_workspace(aao_ctx ctx, int m)
+{
+    if (ctx->m_alloc >= m) return AAO_OK;
+    free_workspace(ctx);
+    const size_t N = ctx->N();
+    AAO_TRY(dev_alloc(ctx, (void **)&ctx->V, sizeof(double) * N * (m + 1)));
+    AAO_TRY(dev_alloc(ctx, (void **)&ctx->Z, sizeof(double) * N * m));
+    AAO_TRY(dev_alloc(ctx, (void **)&ctx->W, sizeof(double) * N));
+    AAO_TRY(dev_alloc(ctx, (void **)&ctx->dV, sizeof(double *) * (m + 1)));
+    AAO_TRY(dev_alloc(ctx, (void **)&ctx->dZ, sizeof(double *) * m));
+    std::vector<double *> hv(m + 1), hz(m);
+    for (int i = 0; i <= m; ++i) hv[i] = ctx->V + N * i;
+    for (int i = 0; i < m; ++i) hz[i] = ctx->Z + N * i;
+    AAO_HIP(hipMemcpy(ctx->dV, hv.data(), sizeof(double *) * (m + 1), hipMemcpyHostToDevice));
+    AAO_HIP(hipMemcpy(ctx->dZ, hz.data(), sizeof(double *) * m, hipMemcpyHostToDevice));
+    ctx->m_alloc = m;
+    return AAO_OK;
+}
+
+// ---------------------------------------------------------------- reductions
+
+// sum over all elements of a.b -> host
+static aao_status dot_host(aao_ctx ctx, const double *a, const double *b, double *out)
+{
+    const size_t N = ctx->N();
+    const int nb = dot_blocks(N);
+    AAO_HIP(launch_dot1_parts(a, b, N, ctx->part, ctx->st));
+    AAO_HIP(launch_reduce_parts(ctx->part, nb, 1, 1, ctx->sd(), ctx->st));
+    AAO_HIP(hipMemcpyAsync(out, ctx->sd(), sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    AAO_HIP(hipStreamSynchronize(ctx->st));
+    return AAO_OK;
+}
+
+// --------------------------------------------------------------- operators
+
+static aao_status apply_A_impl(aao_ctx ctx, const double *x, double *y, const double *bsub,
+                               int transpose)
+{
+    AAO_LAUNCH(AAO_K_MATVEC, launch_matvec(x, y, bsub, (int)ctx->n, (int)ctx->ell, ctx->sc,
+                                           ctx->kappa, ctx->tauk, transpose, ctx->st));
+    return AAO_OK;
+}
+
+// z = C^{-1} (s r - E zprev)  (one circulant apply; s from in_scale)
+static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale,
+                            const double *zprev, double *z, int transpose)
+{
+    const bool single = ctx->prec != AAO_PREC_FP64;
+    const bool single_arith = ctx->prec == AAO_PREC_FP32;
+    const int n = (int)ctx->n, ell = (int)ctx->ell;
+    AAO_LAUNCH(AAO_K_FFT_FWD,
+               launch_fft_fwd(r, in_scale, zprev, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
+                              ctx->lds, single, ctx->tw, ctx->st));
+    AAO_LAUNCH(AAO_K_SHIFTED_SOLVE,
+               launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sc,
+                                    ctx->kappa, transpose, ctx->fail, ctx->st));
+    AAO_LAUNCH(AAO_K_FFT_INV,
+               launch_fft_inv(ctx->spec, ctx->lds, single, z, n, ell, ctx->tw, ctx->st));
+    return AAO_OK;
+}
+
+// Neumann recurrence of eq. preconapprox1: z_0 = C^{-1} r, z_m = C^{-1}(r - E z_{m-1}).
+// The forward transform reads z_{m-1} completely before the inverse transform
+// overwrites it, so the recurrence runs in place.
+static aao_status pinv_impl(aao_ctx ctx, const double *r, const double *in_scale, double *z,
+                            int order, int transpose)
+{
+    AAO_TRY(pinv_once(ctx, r, in_scale, nullptr, z, transpose));
+    if (ctx->tauk)
+        for (int m = 0; m < order; ++m) AAO_TRY(pinv_once(ctx, r, in_scale, z, z, transpose));
+    return AAO_OK;
+}
+
+// ------------------------------------------------------------------ GMRES
+
+static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, double tol,
+                             int maxit, aao_info *info, int transpose)
+{
+    if (m < 1 || m > kMaxRestart) return arg_err(ctx, "restart must be in [1, 63]");
+    if (!(tol >= 0.0) || maxit < 0) return arg_err(ctx, "bad tol / maxit");
+    if (!b || !x) return arg_err(ctx, "null vector");
+    const size_t N = ctx->N();
+    if (overlap(b, x, N * sizeof(double))) return arg_err(ctx, "b and x overlap");
+    AAO_TRY(ensure_workspace(ctx, m));
+    hipStream_t st = ctx->st;
+    AAO_HIP(hipMemsetAsync(ctx->fail, 0, sizeof(int), st));
+
+    aao_info inf{};
+    double bb = 0.0;
+    AAO_TRY(dot_host(ctx, b, b, &bb));
+    const double bnorm = std::sqrt(bb);
+    if (!std::isfinite(bnorm)) {
+        ctx->err = "non-finite right-hand side";
+        return AAO_ERR_NUMERIC;
+    }
+    if (bnorm == 0.0) {
+        AAO_HIP(launch_fill(x, 0.0, N, st));
+        AAO_HIP(hipStreamSynchronize(st));
+        inf.converged = 1;
+        if (info) *info = inf;
+        return AAO_OK;
+    }
+    const int nb = dot_blocks(N);
+    double *V0 = ctx->V;
+
+    auto residual = [&](double *beta) -> aao_status {
+        // V_0 = b - A x, scale vs_0 = 1/||V_0||
+        AAO_TRY(apply_A_impl(ctx, x, V0, b, transpose));
+        AAO_HIP(launch_dot1_parts(V0, V0, N, ctx->part, st));
+        AAO_HIP(launch_reduce_parts(ctx->part, nb, 1, 1, ctx->sd(), st));
+        AAO_HIP(launch_arnoldi_small(3, 0, ctx->sd(), ctx->sh1(), ctx->sh2(), ctx->sc_(),
+                                     ctx->svs(), ctx->shcol(), st));
+        AAO_HIP(hipMemcpyAsync(beta, ctx->shcol(), sizeof(double), hipMemcpyDeviceToHost, st));
+        AAO_HIP(hipStreamSynchronize(st));
+        return AAO_OK;
+    };
+
+    double beta = 0.0;
+    AAO_TRY(residual(&beta));
+    inf.rel_resid_true = beta / bnorm;
+    inf.rel_resid_est = inf.rel_resid_true;
+    if (!std::isfinite(beta)) {
+        ctx->err = "non-finite residual";
+        return AAO_ERR_NUMERIC;
+    }
+    if (beta / bnorm <= tol) {
+        inf.converged = 1;
+        if (info) *info = inf;
+        return AAO_OK;
+    }
+
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
+    while (inf.iters < maxit) {
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double *Vj = ctx->V + N * j;
+            double *Zj = ctx->Z + N * j;
+            double *Vn = ctx->V + N * (j + 1);
+            // z_j = P^{-1} v_j ; w = A z_j
+            AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose));
+            AAO_TRY(apply_A_impl(ctx, Zj, ctx->W, nullptr, transpose));
+            const int nv = j + 1;
+            // CGS2: project, re-project, form the new (unnormalised) basis vector
+            AAO_LAUNCH(AAO_K_CGS_DOT,
+                       launch_multidot(ctx->dV, nv, ctx->W, N, ctx->part, ctx->ldp, st));
+            AAO_HIP(launch_reduce_parts(ctx->part, nb, ctx->ldp, nv, ctx->sd(), st));
+            AAO_HIP(launch_arnoldi_small(0, nv, ctx->sd(), ctx->sh1(), ctx->sh2(), ctx->sc_(),
+                                         ctx->svs(), ctx->shcol(), st));
+            AAO_LAUNCH(AAO_K_CGS_UPDATE_DOT, launch_update_dot(ctx->dV, nv, ctx->W, ctx->sc_(), N,
+                                                               ctx->part, ctx->ldp, st));
+            AAO_HIP(launch_reduce_parts(ctx->part, nb, ctx->ldp, nv, ctx->sd(), st));
+            AAO_HIP(launch_arnoldi_small(1, nv, ctx->sd(), ctx->sh1(), ctx->sh2(), ctx->sc_(),
+                                         ctx->svs(), ctx->shcol(), st));
+            AAO_LAUNCH(AAO_K_CGS_UPDATE_NORM, launch_update_norm(ctx->dV, nv, ctx->W, ctx->sc_(),
+                                                                 Vn, N, ctx->part, ctx->ldp, st));
+            AAO_HIP(launch_reduce_parts(ctx->part, nb, ctx->ldp, 1, ctx->sd(), st));
+            AAO_HIP(launch_arnoldi_small(2, nv, ctx->sd(), ctx->sh1(), ctx->sh2(), ctx->sc_(),
+                                         ctx->svs(), ctx->shcol(), st));
+            AAO_HIP(hipMemcpyAsync(hcol.data(), ctx->shcol(), sizeof(double) * (nv + 1),
+                                   hipMemcpyDeviceToHost, st));
+            AAO_HIP(hipStreamSynchronize(st));
+            inf.iters++;
+            for (int i = 0; i <= nv; ++i)
+                if (!std::isfinite(hcol[i])) {
+                    ctx->err = "non-finite Hessenberg entry (preconditioner breakdown?)";
+                    return AAO_ERR_NUMERIC;
+                }
+            // Givens update of the least-squares problem
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+                hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
+                hcol[i] = t;
+            }
+            const double den = std::hypot(hcol[j], hcol[j + 1]);
+            if (den == 0.0) {
+                ctx->err = "GMRES breakdown (zero Hessenberg column)";
+                return AAO_ERR_NUMERIC;
+            }
+            cs[j] = hcol[j] / den;
+            sn[j] = hcol[j + 1] / den;
+            hcol[j] = den;
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            inf.rel_resid_est = std::fabs(g[j + 1]) / bnorm;
+            if (std::getenv("AAO_LOG"))
+                std::fprintf(stderr, "aao gmres it %d est %.3e\n", inf.iters, inf.rel_resid_est);
+            if (inf.rel_resid_est <= tol || inf.iters >= maxit) break;
+        }
+        // x += Z y, y = R^{-1} g
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * m + l] * y[l];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        AAO_HIP(hipMemcpyAsync(ctx->sy(), y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+        AAO_LAUNCH(AAO_K_AXPY, launch_multi_axpy(ctx->dZ, k, ctx->sy(), x, N, st));
+        AAO_TRY(residual(&beta));
+        inf.rel_resid_true = beta / bnorm;
+        if (!std::isfinite(beta)) {
+            ctx->err = "non-finite residual";
+            return AAO_ERR_NUMERIC;
+        }
+        if (inf.rel_resid_true <= tol) {
+            inf.converged = 1;
+            break;
+        }
+        inf.restarts++;
+    }
+    int failed = 0;
+    AAO_HIP(hipMemcpy(&failed, ctx->fail, sizeof(int), hipMemcpyDeviceToHost));
+    if (info) *info = inf;
+    if (failed) {
+        ctx->err = "shifted solve produced non-finite values";
+        return AAO_ERR_NUMERIC;
+    }
+    return inf.converged ? AAO_OK : AAO_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------------------- ABI
+
+extern "C" {
+
+aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *out)
+{
+    if (!out) return AAO_ERR_ARG;
+    *out = nullptr;
+    if (n < 1 || ell < 1 || !(tau > 0.0) || !std::isfinite(tau)) return AAO_ERR_ARG;
+    if (scheme != AAO_HEAT_IE && scheme != AAO_WAVE_BD2) return AAO_ERR_ARG;
+    if (n > 16384 || ell > 65535 || (double)n * (double)ell > 4.0e9) return AAO_ERR_UNSUPPORTED;
+    aao_ctx ctx = nullptr;
+    try {
+        ctx = new aao_ctx_s();
+    } catch (...) {
+        return AAO_ERR_ALLOC;
+    }
+    ctx->n = n;
+    ctx->ell = ell;
+    ctx->tau = tau;
+    ctx->scheme = scheme;
+    scheme_of(ctx);
+    aao_status s = AAO_OK;
+    do {
+        if (hipGetDevice(&ctx->device) != hipSuccess) {
+            s = AAO_ERR_HIP;
+            break;
+        }
+        ctx->lds = (int)((n + 15) / 16 * 16);
+        const size_t H = (size_t)ell / 2 + 1;
+        if ((s = dev_alloc(ctx, (void **)&ctx->tw, sizeof(double) * 2 * ell)) != AAO_OK) break;
+        if ((s = dev_alloc(ctx, &ctx->spec, H * ctx->lds * 2 * sizeof(double))) != AAO_OK) break;
+        if ((s = dev_alloc(ctx, (void **)&ctx->fail, sizeof(int))) != AAO_OK) break;
+        ctx->nblk = dot_blocks(ctx->N());
+        ctx->ldp = kMaxRestart + 2;
+        if ((s = dev_alloc(ctx, (void **)&ctx->part,
+                           sizeof(double) * ctx->nblk * ctx->ldp)) != AAO_OK) break;
+        if ((s = dev_alloc(ctx, (void **)&ctx->small, sizeof(double) * 7 * kSmallStride)) != AAO_OK)
+            break;
+        if ((s = dev_alloc(ctx, (void **)&ctx->tmpn, sizeof(double) * n)) != AAO_OK) break;
+        if (launch_twiddles(ctx->tw, (int)ell, (int)ell, nullptr) != hipSuccess ||
+            hipMemset(ctx->fail, 0, sizeof(int)) != hipSuccess ||
+            hipMemset(ctx->small, 0, sizeof(double) * 7 * kSmallStride) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess) {
+            s = AAO_ERR_HIP;
+            break;
+        }
+    } while (0);
+    if (s != AAO_OK) {
+        aao_destroy(ctx);
+        return s;
+    }
+    *out = ctx;
+    return AAO_OK;
+}
+
+aao_status aao_destroy(aao_ctx ctx)
+{
+    if (!ctx) return AAO_OK;
+    (void)hipStreamSynchronize(ctx->st);
+    for (auto &p : ctx->ev_pending) {
+        ctx->ev_pool.push_back(p.second.first);
+        ctx->ev_pool.push_back(p.second.second);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    free_workspace(ctx);
+    (void)hipFree(ctx->tw);
+    (void)hipFree(ctx->tauk);
+    (void)hipFree(ctx->sigk);
+    (void)hipFree(ctx->spec);
+    (void)hipFree(ctx->fail);
+    (void)hipFree(ctx->part);
+    (void)hipFree(ctx->small);
+    (void)hipFree(ctx->tmpn);
+    (void)hipFree(ctx->dmodes);
+    (void)hipFree(ctx->damps);
+    delete ctx;
+    return AAO_OK;
+}
+
+aao_status aao_set_stream(aao_ctx ctx, void *stream)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    ctx->st = (hipStream_t)stream;
+    return AAO_OK;
+}
+
+aao_status aao_set_kappa(aao_ctx ctx, double kappa)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (!(kappa > 0.0) || !std::isfinite(kappa)) return arg_err(ctx, "kappa must be > 0");
+    ctx->kappa = kappa;
+    return AAO_OK;
+}
+
+aao_status aao_set_steps(aao_ctx ctx, const double *tau_k)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (!tau_k) {
+        (void)hipFree(ctx->tauk);
+        (void)hipFree(ctx->sigk);
+        ctx->tauk = ctx->sigk = nullptr;
+        return AAO_OK;
+    }
+    if (ctx->scheme != AAO_HEAT_IE) {
+        ctx->err = "variable steps are defined for the heat scheme only";
+        return AAO_ERR_STATE;
+    }
+    const size_t ell = (size_t)ctx->ell;
+    std::vector<double> sig(ell);
+    for (size_t k = 0; k < ell; ++k) {
+        if (!(tau_k[k] > 0.0) || !std::isfinite(tau_k[k])) return arg_err(ctx, "steps must be > 0");
+        sig[k] = tau_k[k] - ctx->tau;
+    }
+    if (!ctx->tauk) {
+        AAO_TRY(dev_alloc(ctx, (void **)&ctx->tauk, sizeof(double) * ell));
+        AAO_TRY(dev_alloc(ctx, (void **)&ctx->sigk, sizeof(double) * ell));
+    }
+    AAO_HIP(hipMemcpy(ctx->tauk, tau_k, sizeof(double) * ell, hipMemcpyHostToDevice));
+    AAO_HIP(hipMemcpy(ctx->sigk, sig.data(), sizeof(double) * ell, hipMemcpyHostToDevice));
+    return AAO_OK;
+}
+
+aao_status aao_set_precision(aao_ctx ctx, int prec)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (prec != AAO_PREC_FP64 && prec != AAO_PREC_MIXED && prec != AAO_PREC_FP32)
+        return arg_err(ctx, "unknown precision");
+    ctx->prec = prec;
+    return AAO_OK;
+}
+
+aao_status aao_set_neumann_order(aao_ctx ctx, int q)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (q < 0 || q > 64) return arg_err(ctx, "neumann order must be in [0, 64]");
+    ctx->neumann = q;
+    return AAO_OK;
+}
+
+aao_status aao_project_sine(aao_ctx ctx, int J, const int *modes, const double *amps, double *u0)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (J < 0 || (J > 0 && (!modes || !amps)) || !u0) return arg_err(ctx, "bad sine series");
+    for (int m = 0; m < J; ++m)
+        if (modes[m] < 1) return arg_err(ctx, "modes must be >= 1");
+    if (J > ctx->nmodes_alloc) {
+        (void)hipFree(ctx->dmodes);
+        (void)hipFree(ctx->damps);
+        ctx->dmodes = nullptr;
+        ctx->damps = nullptr;
+        ctx->nmodes_alloc = 0;
+        AAO_TRY(dev_alloc(ctx, (void **)&ctx->dmodes, sizeof(int) * J));
+        AAO_TRY(dev_alloc(ctx, (void **)&ctx->damps, sizeof(double) * J));
+        ctx->nmodes_alloc = J;
+    }
+    if (J > 0) {
+        AAO_HIP(hipMemcpyAsync(ctx->dmodes, modes, sizeof(int) * J, hipMemcpyHostToDevice, ctx->st));
+        AAO_HIP(hipMemcpyAsync(ctx->damps, amps, sizeof(double) * J, hipMemcpyHostToDevice, ctx->st));
+    }
+    AAO_HIP(launch_project_sine(u0, (int)ctx->n, J, ctx->dmodes, ctx->damps, ctx->st));
+    AAO_HIP(hipStreamSynchronize(ctx->st));
+    return AAO_OK;
+}
+
+aao_status aao_build_rhs(aao_ctx ctx, const double *u0, const double *v0, double *b)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (!u0 || !b) return arg_err(ctx, "null vector");
+    AAO_HIP(launch_build_rhs(b, u0, v0, (int)ctx->n, (int)ctx->ell, ctx->sc, ctx->kappa, ctx->tau,
+                             ctx->st));
+    return AAO_OK;
+}
+
+aao_status aao_apply_A(aao_ctx ctx, const double *x, double *y, int transpose)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (!x || !y) return arg_err(ctx, "null vector");
+    if (overlap(x, y, ctx->N() * sizeof(double))) return arg_err(ctx, "x and y overlap");
+    return apply_A_impl(ctx, x, y, nullptr, transpose ? 1 : 0);
+}
+
+aao_status aao_apply_Pinv(aao_ctx ctx, const double *r, double *z, int neumann_order,
+                          int transpose)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (!r || !z) return arg_err(ctx, "null vector");
+    if (neumann_order < 0 || neumann_order > 64) return arg_err(ctx, "bad neumann order");
+    if (overlap(r, z, ctx->N() * sizeof(double))) return arg_err(ctx, "r and z overlap");
+    return pinv_impl(ctx, r, nullptr, z, neumann_order, transpose ? 1 : 0);
+}
+
+aao_status aao_gmres(aao_ctx ctx, const double *b, double *x, int restart, double tol, int maxit,
+                     aao_info *info)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    try {
+        return gmres_impl(ctx, b, x, restart, tol, maxit, info, 0);
+    } catch (const std::bad_alloc &) {
+        return AAO_ERR_ALLOC;
+    } catch (...) {
+        return AAO_ERR_HIP;
+    }
+}
+
+aao_status aao_adjoint_solve(aao_ctx ctx, const double *g, double *lam, int restart, double tol,
+                             int maxit, aao_info *info)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    try {
+        return gmres_impl(ctx, g, lam, restart, tol, maxit, info, 1);
+    } catch (const std::bad_alloc &) {
+        return AAO_ERR_ALLOC;
+    } catch (...) {
+        return AAO_ERR_HIP;
+    }
+}
+
+aao_status aao_grad(aao_ctx ctx, const double *u0, const double *v0, const double *U,
+                    const double *lam, double *g_u0, double *g_v0, double *g_kappa)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (!U || !lam || !g_u0) return arg_err(ctx, "null vector");
+    const int n = (int)ctx->n;
+    const double tau = ctx->tau, kap = ctx->kappa;
+    const bool bd2 = ctx->scheme == AAO_WAVE_BD2;
+    if (bd2 && g_kappa && !u0) return arg_err(ctx, "u0 needed for the BD2 kappa gradient");
+    hipStream_t st = ctx->st;
+    const double *lam1 = lam, *lam2 = ctx->ell > 1 ? lam + n : nullptr;
+    if (!bd2) {
+        AAO_HIP(launch_mk(lam1, 1.0, 0.0, nullptr, 0.0, 0.0, g_u0, n, st));
+        if (g_v0) AAO_HIP(launch_fill(g_v0, 0.0, (size_t)n, st));
+    } else {
+        AAO_HIP(launch_mk(lam1, 1.0, tau * tau * kap, lam2, lam2 ? -1.0 : 0.0, 0.0, g_u0, n, st));
+        if (g_v0) AAO_HIP(launch_mk(lam1, tau, tau * tau * tau * kap, nullptr, 0.0, 0.0, g_v0, n, st));
+    }
+    if (g_kappa) {
+        const int nb = dot_blocks(ctx->N());
+        AAO_HIP(launch_grad_kappa_parts(U, lam, n, (int)ctx->ell, ctx->sc, ctx->tauk, ctx->part, nb,
+                                        st));
+        AAO_HIP(launch_reduce_parts(ctx->part, nb, 1, 1, ctx->sd(), st));
+        double s = 0.0;
+        AAO_HIP(hipMemcpyAsync(&s, ctx->sd(), sizeof(double), hipMemcpyDeviceToHost, st));
+        AAO_HIP(hipStreamSynchronize(st));
+        double gk = -s;
+        if (bd2) {
+            // + lam_1 . tau^2 K (u0 + tau v0)
+            AAO_HIP(launch_mk(u0, 0.0, tau * tau, v0, 0.0, v0 ? tau * tau * tau : 0.0, ctx->tmpn, n,
+                              st));
+            const int nbn = dot_blocks((size_t)n);
+            AAO_HIP(launch_dot1_parts(ctx->tmpn, lam1, (size_t)n, ctx->part, st));
+            AAO_HIP(launch_reduce_parts(ctx->part, nbn, 1, 1, ctx->sd(), st));
+            double t = 0.0;
+            AAO_HIP(hipMemcpyAsync(&t, ctx->sd(), sizeof(double), hipMemcpyDeviceToHost, st));
+            AAO_HIP(hipStreamSynchronize(st));
+            gk += t;
+        }
+        *g_kappa = gk;
+    } else {
+        AAO_HIP(hipStreamSynchronize(st));
+    }
+    return AAO_OK;
+}
+
+aao_status aao_set_timing(aao_ctx ctx, int enable)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    AAO_HIP(hipStreamSynchronize(ctx->st));
+    for (auto &p : ctx->ev_pending) {
+        ctx->ev_pool.push_back(p.second.first);
+        ctx->ev_pool.push_back(p.second.second);
+    }
+    ctx->ev_pending.clear();
+    for (int i = 0; i < AAO_NUM_KERNELS; ++i) {
+        ctx->t_total[i] = 0.0;
+        ctx->t_count[i] = 0;
+    }
+    ctx->timing = enable != 0;
+    return AAO_OK;
+}
+
+aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (kernel < 0 || kernel >= AAO_NUM_KERNELS || !total_ms || !count)
+        return arg_err(ctx, "bad kernel id / output");
+    AAO_HIP(hipStreamSynchronize(ctx->st));
+    for (auto &p : ctx->ev_pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            ctx->t_total[p.first] += ms;
+            ctx->t_count[p.first] += 1;
+        }
+        ctx->ev_pool.push_back(p.second.first);
+        ctx->ev_pool.push_back(p.second.second);
+    }
+    ctx->ev_pending.clear();
+    *total_ms = ctx->t_total[kernel];
+    *count = ctx->t_count[kernel];
+    return AAO_OK;
+}
+
+const char *aao_status_string(aao_status st)
+{
+    switch (st) {
+    case AAO_OK: return "ok";
+    case AAO_NOT_CONVERGED: return "not converged";
+    case AAO_ERR_ARG: return "invalid argument";
+    case AAO_ERR_ALLOC: return "device allocation failed";
+    case AAO_ERR_HIP: return "HIP runtime error";
+    case AAO_ERR_NUMERIC: return "numerical breakdown";
+    case AAO_ERR_STATE: return "invalid state";
+    case AAO_ERR_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+const char *aao_last_error(aao_ctx ctx)
+{
+    if (!ctx) return "";
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

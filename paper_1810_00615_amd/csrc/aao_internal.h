@@ -1,0 +1,109 @@
+// Internal declarations shared by the HIP translation units of libaao.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace aao {
+
+// ----------------------------------------------------------------- complex
+template <typename T> struct cx { T x, y; };
+
+template <typename T> __host__ __device__ inline cx<T> mk(T a, T b) { return cx<T>{a, b}; }
+template <typename T> __host__ __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __host__ __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T> __host__ __device__ inline cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+// i * a
+template <typename T> __host__ __device__ inline cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
+// 1 / a (scaled to avoid overflow of |a|^2 for the magnitudes seen here)
+template <typename T> __host__ __device__ inline cx<T> recip(cx<T> a) {
+    T d = a.x * a.x + a.y * a.y;
+    T inv = T(1) / d;
+    return {a.x * inv, -a.y * inv};
+}
+
+// ------------------------------------------------------------- scheme data
+// Blocks A_m = a_m M + b_m kappa K, m = 0..s (s <= 3).
+struct Scheme {
+    int s;
+    double a[4];
+    double b[4];
+};
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `st` and return hipError_t of the launch.
+
+// Twiddle table w_len^p = exp(-2 pi i p / len), p in [0, count).
+hipError_t launch_twiddles(double *tw, int len, int count, hipStream_t st);
+
+// Forward half-spectrum transform along time of the ell x n real array
+// src = r - E zprev (E term only if zprev != nullptr):
+// spec rows j = 0..ell/2 (complex, leading dimension lds, element type
+// float2/double2 according to `single`).
+// in_scale (device scalar or nullptr) multiplies r.
+hipError_t launch_fft_fwd(const double *r, const double *in_scale, const double *zprev,
+                          const double *sigk, double kappa, int n, int ell, void *spec, int lds,
+                          bool single, const double *tw, hipStream_t st);
+// Inverse of the above: z (ell x n real) from the half spectrum.
+hipError_t launch_fft_inv(const void *spec, int lds, bool single, double *z, int n, int ell,
+                          const double *tw, hipStream_t st);
+// In-place shifted solves (alpha_j M + beta_j kappa K) Y_j = X_j for every
+// half-spectrum row j; `single_arith` selects single-precision arithmetic.
+hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
+                                int n, int ell, Scheme sc, double kappa, int transpose,
+                                int *fail_flag, hipStream_t st);
+bool fft_supported_fast(int ell);
+
+// y = A x (or A^T x); with tau_k != nullptr the variable-step matrix B.
+// If bsub != nullptr computes y = bsub - A x.
+hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
+                         Scheme sc, double kappa, const double *tau_k, int transpose,
+                         hipStream_t st);
+hipError_t launch_project_sine(double *u0, int n, int J, const int *modes, const double *amps,
+                               hipStream_t st);
+hipError_t launch_build_rhs(double *b, const double *u0, const double *v0, int n, int ell,
+                            Scheme sc, double kappa, double tau, hipStream_t st);
+
+// ------------------------------------------------------- Krylov helpers
+// Partial dot products: part[blk * ldp + i] = sum over block slice of V_i . w,
+// i < nv; V given as an array of device pointers (device memory).
+int dot_blocks(size_t N);
+hipError_t launch_multidot(const double *const *V, int nv, const double *w, size_t N,
+                           double *part, int ldp, hipStream_t st);
+// w' = w - sum_i V_i h_i (h device) and partials of V_i . w' (i < nv) and of
+// w'.w' (stored at index nv).  w is not modified.
+hipError_t launch_update_dot(const double *const *V, int nv, const double *w, const double *h,
+                             size_t N, double *part, int ldp, hipStream_t st);
+// out = w - sum_i V_i h_i and the partials of out.out (stored at index 0).
+hipError_t launch_update_norm(const double *const *V, int nv, const double *w, const double *h,
+                              double *out, size_t N, double *part, int ldp, hipStream_t st);
+// sums[i] = sum_blk part[blk * ldp + i] in fixed order, i < cnt
+hipError_t launch_reduce_parts(const double *part, int nblk, int ldp, int cnt, double *sums,
+                               hipStream_t st);
+// x += sum_i Z_i y_i  (y device)
+hipError_t launch_multi_axpy(const double *const *Z, int nz, const double *y, double *x,
+                             size_t N, hipStream_t st);
+// out = w * (*scale)
+hipError_t launch_scale(const double *w, const double *scale, double *out, size_t N,
+                        hipStream_t st);
+// out = a * w (host scalar a)
+hipError_t launch_scale_h(const double *w, double a, double *out, size_t N, hipStream_t st);
+hipError_t launch_fill(double *x, double v, size_t N, hipStream_t st);
+
+// Gradient reduction helpers
+// partial sums of sum_k sum_m c_m^{(k)} lam_k . K u_{k-m} (negated later)
+hipError_t launch_grad_kappa_parts(const double *U, const double *lam, int n, int ell,
+                                   Scheme sc, const double *tau_k, double *part, int nblk,
+                                   hipStream_t st);
+// y = (cm M + ck K) x for one n-vector, plus optional y += (cm2 M + ck2 K) x2
+hipError_t launch_mk(const double *x, double cm, double ck, const double *x2, double cm2,
+                     double ck2, double *y, int n, hipStream_t st);
+hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double *part,
+                             hipStream_t st);
+hipError_t launch_arnoldi_small(int mode, int nv, const double *d, double *h1, double *h2,
+                                double *c, double *vs, double *hcol, hipStream_t st);
+
+}  // namespace aao

@@ -1,0 +1,510 @@
+// Time-axis transforms of the circulant preconditioner apply
+// (arXiv 1810.00615, Sec. 3, eq. precon2para: the (U* (x) I_n) and (U (x) I_n)
+// factors, computed per spatial column as in eq. alternativecal with an FFT).
+//
+// Layout: the real input is ell x n row-major (row k = time level, the n
+// spatial nodes contiguous), so one workgroup owns a tile of W adjacent columns
+// and every global access is a W-wide row segment (coalesced across n).  No
+// transpose is needed -- the paper's vector transpose is replaced by the choice
+// of tile.
+//
+// Real-to-half-spectrum for even ell = 2L: the column is packed as the complex
+// sequence z_k = x_{2k} + i x_{2k+1} of length L, transformed with a radix-16
+// Stockham FFT whose data stay in registers (P points per thread) and are
+// exchanged through LDS between stages (real and imaginary halves in turn, so a
+// tile needs only L*W reals of LDS), then split into the half spectrum
+//   X_j = (Z_j + conj Z_{L-j})/2 - (i/2) w^j (Z_j - conj Z_{L-j}),  j = 0..L,
+// with w = exp(-2 pi i / ell).  The inverse runs the same steps backwards.
+// Lengths that are not powers of two use a direct-DFT kernel.
+#include "aao_internal.h"
+
+namespace aao {
+
+// cos / sin of 2 pi k / 16
+constexpr double kC16[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+constexpr double kS16[16] = {
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+constexpr int bitrev(int v, int bits) {
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+// In-register DFT of length R (1, 2, 4, 8 or 16):
+//   v_s <- sum_r v_r exp(-+ 2 pi i r s / R)   (sign + when INV)
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void dft_reg(cx<T> *v)
+{
+    constexpr int LG = ilog2c(R);
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int j = bitrev(i, LG);
+        if (j > i) {
+            cx<T> t = v[i];
+            v[i] = v[j];
+            v[j] = t;
+        }
+    }
+#pragma unroll
+    for (int m = 2; m <= R; m <<= 1) {
+#pragma unroll
+        for (int k = 0; k < R; k += m) {
+#pragma unroll
+            for (int jj = 0; jj < m / 2; ++jj) {
+                const int ti = jj * (16 / m);
+                cx<T> b = v[k + jj + m / 2];
+                cx<T> t;
+                if (ti == 0) {
+                    t = b;
+                } else if (ti == 4) {               // multiply by -+ i
+                    t = INV ? mul_i(b) : cx<T>{b.y, -b.x};
+                } else {
+                    const cx<T> w = {T(kC16[ti]), T(INV ? kS16[ti] : -kS16[ti])};
+                    t = w * b;
+                }
+                cx<T> a = v[k + jj];
+                v[k + jj] = a + t;
+                v[k + jj + m / 2] = a - t;
+            }
+        }
+    }
+}
+
+// Stage plan of a length-L transform with at most radix 16 per stage.
+template <int L> struct Plan {
+    static constexpr int LG = ilog2c(L);
+    static constexpr int NS = (LG + 3) / 4;                       // number of stages
+    static constexpr int radix(int s) {                           // 16,...,16,rest
+        return (s < NS - 1 || LG % 4 == 0) ? 16 : (1 << (LG % 4));
+    }
+    static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * radix(s - 1); }
+};
+
+// Thread-held values: v[u*R + r] is input r of butterfly q = t + u*TN.
+template <typename T, int L, int P, int S, bool INV>
+__device__ __forceinline__ void stage_compute(cx<T> *v, int t, const cx<double> *tw, int twmul)
+{
+    constexpr int R = Plan<L>::radix(S);
+    constexpr int NS_ = Plan<L>::ns(S);
+    constexpr int TN = L / P;
+#pragma unroll
+    for (int u = 0; u < P / R; ++u) {
+        if (NS_ > 1) {
+            const int q = t + u * TN;
+            const int k = q & (NS_ - 1);
+            const int step = (L / (NS_ * R)) * twmul;   // twiddle w_{NS R}^{r k}
+            // powers w^(2^b) from the table; w^r as the product over the set
+            // bits of r (at most three roundings), so only log2(R) loads are live
+            constexpr int LB = ilog2c(R);
+            cx<T> wp[LB > 0 ? LB : 1];
+#pragma unroll
+            for (int b = 0; b < LB; ++b) {
+                const cx<double> w = tw[(k << b) * step];
+                wp[b] = {T(w.x), T(INV ? -w.y : w.y)};
+            }
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> wt = {T(1), T(0)};
+                bool first = true;
+#pragma unroll
+                for (int b = 0; b < LB; ++b)
+                    if ((r >> b) & 1) {
+                        wt = first ? wp[b] : wt * wp[b];
+                        first = false;
+                    }
+                v[u * R + r] = wt * v[u * R + r];
+            }
+        }
+        dft_reg<R, INV, T>(v + u * R);
+    }
+}
+
+// Output position of value (u, r) after stage S.
+template <int L, int P, int S>
+__device__ __forceinline__ int out_pos(int t, int u, int r)
+{
+    constexpr int R = Plan<L>::radix(S);
+    constexpr int NS_ = Plan<L>::ns(S);
+    const int q = t + u * (L / P);
+    return (q / NS_) * NS_ * R + (q & (NS_ - 1)) + r * NS_;
+}
+
+// Input position of value (u, r) before stage S.
+template <int L, int P, int S>
+__device__ __forceinline__ int in_pos(int t, int u, int r)
+{
+    constexpr int R = Plan<L>::radix(S);
+    return t + u * (L / P) + r * (L / R);
+}
+
+// Exchange the outputs of stage S into the inputs of stage S+1 through LDS,
+// one real plane at a time.
+template <typename T, int L, int P, int S>
+__device__ __forceinline__ void exchange(cx<T> *v, T *sm, int t, int c, int W)
+{
+    constexpr int R1 = Plan<L>::radix(S);
+    constexpr int R2 = Plan<L>::radix(S + 1);
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+        for (int u = 0; u < P / R1; ++u)
+#pragma unroll
+            for (int r = 0; r < R1; ++r)
+                sm[out_pos<L, P, S>(t, u, r) * W + c] = part ? v[u * R1 + r].y : v[u * R1 + r].x;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < P / R2; ++u)
+#pragma unroll
+            for (int r = 0; r < R2; ++r) {
+                const T val = sm[in_pos<L, P, S + 1>(t, u, r) * W + c];
+                if (part) v[u * R2 + r].y = val; else v[u * R2 + r].x = val;
+            }
+        __syncthreads();
+    }
+}
+
+template <typename T, int L, int P, int S, bool INV>
+__device__ __forceinline__ void run_stages(cx<T> *v, T *sm, int t, int c, int W,
+                                           const cx<double> *tw, int twmul)
+{
+    if constexpr (S < Plan<L>::NS) {
+        stage_compute<T, L, P, S, INV>(v, t, tw, twmul);
+        if constexpr (S + 1 < Plan<L>::NS) {
+            exchange<T, L, P, S>(v, sm, t, c, W);
+            run_stages<T, L, P, S + 1, INV>(v, sm, t, c, W, tw, twmul);
+        }
+    }
+}
+
+// Position of held value idx after all stages (natural order).
+template <int L, int P>
+__device__ __forceinline__ int final_pos(int t, int idx)
+{
+    if constexpr (Plan<L>::NS == 0) {
+        return 0;
+    } else {
+        constexpr int RL = Plan<L>::radix(Plan<L>::NS - 1);
+        return out_pos<L, P, Plan<L>::NS - 1>(t, idx / RL, idx % RL);
+    }
+}
+template <int L, int P>
+__device__ __forceinline__ int first_pos(int t, int idx)
+{
+    if constexpr (Plan<L>::NS == 0) {
+        return 0;
+    } else {
+        constexpr int R0 = Plan<L>::radix(0);
+        return in_pos<L, P, 0>(t, idx / R0, idx % R0);
+    }
+}
+
+template <typename T> struct V2;
+template <> struct V2<double> { using type = double2; };
+template <> struct V2<float> { using type = float2; };
+
+// Forward: real ell x n (ell = 2L) -> half spectrum rows 0..L.
+// Input column value at time k is r[k][col] - sigma_k kappa (K zprev_k)[col]
+// when zprev != nullptr (the Neumann residual r - E z, eq. preconapprox1).
+template <typename T, int L, int P, bool NEU>
+__global__ void __launch_bounds__(1024)
+k_fft_fwd(const double *__restrict__ r, const double *__restrict__ in_scale,
+          const double *__restrict__ zprev, const double *__restrict__ sigk, double kap_h, int n,
+          int W,
+          cx<T> *__restrict__ X, int lds, const cx<double> *__restrict__ tw)
+{
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    const int c = threadIdx.x % W;
+    const int t = threadIdx.x / W;
+    const int col = blockIdx.x * W + c;
+    const bool valid = col < n;
+    const double rs = in_scale ? *in_scale : 1.0;
+    cx<T> v[P];
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int pos = first_pos<L, P>(t, idx);
+        double a = 0.0, b = 0.0;
+        if (valid) {
+            const size_t o0 = (size_t)(2 * pos) * n + col;
+            const size_t o1 = o0 + n;
+            a = rs * r[o0];
+            b = rs * r[o1];
+            if (NEU) {
+                const double zl0 = col > 0 ? zprev[o0 - 1] : 0.0;
+                const double zr0 = col < n - 1 ? zprev[o0 + 1] : 0.0;
+                const double zl1 = col > 0 ? zprev[o1 - 1] : 0.0;
+                const double zr1 = col < n - 1 ? zprev[o1 + 1] : 0.0;
+                a -= sigk[2 * pos] * kap_h * (2.0 * zprev[o0] - zl0 - zr0);
+                b -= sigk[2 * pos + 1] * kap_h * (2.0 * zprev[o1] - zl1 - zr1);
+            }
+        }
+        v[idx] = {T(a), T(b)};
+    }
+    run_stages<T, L, P, 0, false>(v, sm, t, c, W, tw, 2);
+    // split Z into the half spectrum: needs Z_{L-p}, held by another thread.
+    // With z = Z_p = (a, b) and Z_{L-p} = (c, d):
+    //   F_e = ((a + c)/2, (b - d)/2),  F_o = (Z_p - conj Z_{L-p}) / 2i = ((b + d)/2, (c - a)/2)
+    // The real plane goes through LDS first; v[idx].x then holds F_e.x and fo_y
+    // holds F_o.y, so only P extra reals are live.
+    T fo_y[P];
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) sm[final_pos<L, P>(t, idx) * W + c] = v[idx].x;
+    __syncthreads();
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int pos = final_pos<L, P>(t, idx);
+        const T cc = sm[((L - pos) & (L - 1)) * W + c];
+        const T a = v[idx].x;
+        v[idx].x = T(0.5) * (a + cc);
+        fo_y[idx] = T(0.5) * (cc - a);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) sm[final_pos<L, P>(t, idx) * W + c] = v[idx].y;
+    __syncthreads();
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int pos = final_pos<L, P>(t, idx);
+        const T dd = sm[((L - pos) & (L - 1)) * W + c];
+        const T b = v[idx].y;
+        const cx<T> fe = {v[idx].x, T(0.5) * (b - dd)};
+        const cx<T> fo = {T(0.5) * (b + dd), fo_y[idx]};
+        if (valid) {
+            const cx<double> wd = tw[pos];                  // w_ell^pos
+            const cx<T> w = {T(wd.x), T(wd.y)};
+            X[(size_t)pos * lds + col] = fe + w * fo;
+            if (pos == 0) X[(size_t)L * lds + col] = fe - fo;
+        }
+    }
+}
+
+// Inverse: half spectrum rows 0..L -> real ell x n, including the 1/ell factor.
+template <typename T, int L, int P>
+__global__ void __launch_bounds__(1024)
+k_fft_inv(const cx<T> *__restrict__ Y, int lds, double *__restrict__ z, int n, int W,
+          const cx<double> *__restrict__ tw)
+{
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    const int c = threadIdx.x % W;
+    const int t = threadIdx.x / W;
+    const int col = blockIdx.x * W + c;
+    const bool valid = col < n;
+    cx<T> v[P];
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int pos = first_pos<L, P>(t, idx);
+        cx<T> q = {T(0), T(0)};
+        if (valid) {
+            const cx<T> a = Y[(size_t)pos * lds + col];
+            const cx<T> b = conj(Y[(size_t)(L - pos) * lds + col]);
+            const cx<double> wd = tw[pos];
+            const cx<T> wc = {T(wd.x), T(-wd.y)};            // w_ell^{-pos}
+            const cx<T> e = a + b;
+            const cx<T> o = wc * (a - b);
+            q = e + mul_i(o);
+        }
+        v[idx] = q;
+    }
+    run_stages<T, L, P, 0, true>(v, sm, t, c, W, tw, 2);
+    if (!valid) return;
+    const double inv = 1.0 / (2.0 * L);
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int pos = final_pos<L, P>(t, idx);
+        const size_t o0 = (size_t)(2 * pos) * n + col;
+        z[o0] = double(v[idx].x) * inv;
+        z[o0 + n] = double(v[idx].y) * inv;
+    }
+}
+
+// ---------------------------------------------------------- direct DFT path
+// Any ell: X_j = sum_k x_k w^{jk}, j = 0..ell/2, one thread per (j, column).
+template <typename T>
+__global__ void k_dft_fwd(const double *__restrict__ r, const double *__restrict__ in_scale,
+                          const double *__restrict__ zprev, const double *__restrict__ sigk,
+                          double kap_h, int n, int ell,
+                          cx<T> *__restrict__ X, int lds, const cx<double> *__restrict__ tw)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (col >= n) return;
+    const double rs = in_scale ? *in_scale : 1.0;
+    double sr = 0.0, si = 0.0;
+    int p = 0;
+    for (int k = 0; k < ell; ++k) {
+        const size_t o = (size_t)k * n + col;
+        double x = rs * r[o];
+        if (zprev) {
+            const double zl = col > 0 ? zprev[o - 1] : 0.0;
+            const double zr = col < n - 1 ? zprev[o + 1] : 0.0;
+            x -= sigk[k] * kap_h * (2.0 * zprev[o] - zl - zr);
+        }
+        const cx<double> w = tw[p];
+        sr += x * w.x;
+        si += x * w.y;
+        p += j;
+        if (p >= ell) p -= ell;
+    }
+    X[(size_t)j * lds + col] = {T(sr), T(si)};
+}
+
+// x_k = (1/ell) sum_{j=0}^{ell-1} Y_j w^{-jk} with Y_{ell-j} = conj(Y_j).
+template <typename T>
+__global__ void k_dft_inv(const cx<T> *__restrict__ Y, int lds, double *__restrict__ z, int n,
+                          int ell, const cx<double> *__restrict__ tw)
+{
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (col >= n) return;
+    const int H = ell / 2;
+    double s = double(Y[col].x);
+    int p = 0;
+    for (int j = 1; j <= H; ++j) {
+        p += k;
+        if (p >= ell) p -= ell;
+        const cx<T> y = Y[(size_t)j * lds + col];
+        const cx<double> w = tw[p];
+        // Re(y * conj(w))
+        const double re = double(y.x) * w.x + double(y.y) * w.y;
+        s += (2 * j == ell) ? re : 2.0 * re;
+    }
+    z[(size_t)k * n + col] = s / ell;
+}
+
+__global__ void k_twiddles(cx<double> *tw, int len, int count)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const long long q = p % len;
+    double s, c;
+    sincospi(-2.0 * (double)q / (double)len, &s, &c);
+    tw[p] = {c, s};
+}
+
+hipError_t launch_twiddles(double *tw, int len, int count, hipStream_t st)
+{
+    k_twiddles<<<(count + 255) / 256, 256, 0, st>>>(reinterpret_cast<cx<double> *>(tw), len,
+                                                     count);
+    return hipGetLastError();
+}
+
+bool fft_supported_fast(int ell) { return ell >= 2 && ell <= 16384 && (ell & (ell - 1)) == 0; }
+
+static int pick_w(int L, int P, int n, size_t realsz)
+{
+    const int tn = L / P;
+    int w = 1;
+    while (w < 64 && 2 * w * tn <= 1024 && (size_t)2 * w * L * realsz <= 160 * 1024 &&
+           (w < 8 || w < n))
+        w *= 2;
+    return w;
+}
+
+template <typename T, int L>
+static hipError_t fwd_L(const double *r, const double *in_scale, const double *zprev,
+                        const double *sigk, double kap_h, int n, void *spec, int lds,
+                        const double *tw, hipStream_t st)
+{
+    constexpr int P = L < 16 ? L : 16;
+    const int W = pick_w(L, P, n, sizeof(T));
+    const size_t smem = (size_t)L * W * sizeof(T);
+    auto kern = zprev ? k_fft_fwd<T, L, P, true> : k_fft_fwd<T, L, P, false>;
+    if (smem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((n + W - 1) / W);
+    kern<<<grid, W * (L / P), smem, st>>>(r, in_scale, zprev, sigk, kap_h, n, W,
+                                          reinterpret_cast<cx<T> *>(spec), lds,
+                                          reinterpret_cast<const cx<double> *>(tw));
+    return hipGetLastError();
+}
+
+template <typename T, int L>
+static hipError_t inv_L(const void *spec, int lds, double *z, int n, const double *tw,
+                        hipStream_t st)
+{
+    constexpr int P = L < 16 ? L : 16;
+    const int W = pick_w(L, P, n, sizeof(T));
+    const size_t smem = (size_t)L * W * sizeof(T);
+    auto kern = k_fft_inv<T, L, P>;
+    if (smem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    dim3 grid((n + W - 1) / W);
+    kern<<<grid, W * (L / P), smem, st>>>(reinterpret_cast<const cx<T> *>(spec), lds, z, n, W,
+                                          reinterpret_cast<const cx<double> *>(tw));
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t fwd_dispatch(const double *r, const double *in_scale, const double *zprev,
+                               const double *sigk, double kap_h, int n, int ell, void *spec,
+                               int lds, const double *tw, hipStream_t st)
+{
+    switch (ell) {
+#define AAO_CASE(E) \
+    case E: return fwd_L<T, E / 2>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st);
+        AAO_CASE(2) AAO_CASE(4) AAO_CASE(8) AAO_CASE(16) AAO_CASE(32) AAO_CASE(64)
+        AAO_CASE(128) AAO_CASE(256) AAO_CASE(512) AAO_CASE(1024) AAO_CASE(2048)
+        AAO_CASE(4096) AAO_CASE(8192) AAO_CASE(16384)
+#undef AAO_CASE
+    default: break;
+    }
+    dim3 grid((n + 127) / 128, ell / 2 + 1);
+    k_dft_fwd<T><<<grid, 128, 0, st>>>(r, in_scale, zprev, sigk, kap_h, n, ell,
+                                       reinterpret_cast<cx<T> *>(spec), lds,
+                                       reinterpret_cast<const cx<double> *>(tw));
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t inv_dispatch(const void *spec, int lds, double *z, int n, int ell,
+                               const double *tw, hipStream_t st)
+{
+    switch (ell) {
+#define AAO_CASE(E) \
+    case E: return inv_L<T, E / 2>(spec, lds, z, n, tw, st);
+        AAO_CASE(2) AAO_CASE(4) AAO_CASE(8) AAO_CASE(16) AAO_CASE(32) AAO_CASE(64)
+        AAO_CASE(128) AAO_CASE(256) AAO_CASE(512) AAO_CASE(1024) AAO_CASE(2048)
+        AAO_CASE(4096) AAO_CASE(8192) AAO_CASE(16384)
+#undef AAO_CASE
+    default: break;
+    }
+    dim3 grid((n + 127) / 128, ell);
+    k_dft_inv<T><<<grid, 128, 0, st>>>(reinterpret_cast<const cx<T> *>(spec), lds, z, n, ell,
+                                       reinterpret_cast<const cx<double> *>(tw));
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_fwd(const double *r, const double *in_scale, const double *zprev,
+                          const double *sigk, double kappa, int n, int ell, void *spec, int lds,
+                          bool single, const double *tw, hipStream_t st)
+{
+    const double kap_h = kappa * (n + 1.0);   // kappa / h
+    return single ? fwd_dispatch<float>(r, in_scale, zprev, sigk, kap_h, n, ell, spec, lds, tw, st)
+                  : fwd_dispatch<double>(r, in_scale, zprev, sigk, kap_h, n, ell, spec, lds, tw,
+                                         st);
+}
+
+hipError_t launch_fft_inv(const void *spec, int lds, bool single, double *z, int n, int ell,
+                          const double *tw, hipStream_t st)
+{
+    return single ? inv_dispatch<float>(spec, lds, z, n, ell, tw, st)
+                  : inv_dispatch<double>(spec, lds, z, n, ell, tw, st);
+}
+
+}  // namespace aao

@@ -1,0 +1,271 @@
+// Shifted complex tridiagonal solves of the circulant preconditioner apply
+// (arXiv 1810.00615, eq. precon2para: the block diagonal middle factor
+// I (x) A_0 + Lambda (x) A_1, one block per frequency; the paper solves each
+// block with the Thomas algorithm, Sec. 3).
+//
+// Frequency row j of the half spectrum is the right-hand side of
+//   hatA_j y = x,  hatA_j = alpha_j M + beta_j kappa K
+//                = tridiag(e_j, d_j, e_j)   (complex symmetric Toeplitz),
+//   alpha_j = sum_m a_m w^{jm},  beta_j = sum_m b_m w^{jm},  w = exp(-2 pi i/ell)
+//   (conjugated for C^T),  d_j = alpha_j 4h/6 + beta_j kappa 2/h,
+//   e_j = alpha_j h/6 - beta_j kappa/h.
+//
+// One workgroup per row.  The row is cut into chunks of CW contiguous unknowns,
+// one chunk per thread; the last unknown of each chunk is a separator.  Each
+// thread eliminates its chunk interior with the Thomas recurrence (no pivoting,
+// as in the paper), which expresses the interior as y + u X_left + v X_right;
+// the separators then satisfy a tridiagonal system with one equation per chunk,
+// solved by parallel cyclic reduction in LDS; a last sweep recovers the
+// interiors.  Because the blocks are Toeplitz, the interior elimination factors
+// are the same for every chunk and are computed once per row.
+#include "aao_internal.h"
+
+namespace aao {
+
+template <typename S> struct Store;
+template <> struct Store<double> { using C = cx<double>; };
+template <> struct Store<float> { using C = cx<float>; };
+
+template <typename A, typename S, int CW, int NTB>
+__global__ void __launch_bounds__(NTB)
+k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, double kappa,
+                int transpose, int *__restrict__ fail)
+{
+    extern __shared__ unsigned char smraw[];
+    const int NT = blockDim.x;
+    cx<A> *s_ip = reinterpret_cast<cx<A> *>(smraw);   // 1/pivot of the interior elimination
+    cx<A> *s_cp = s_ip + CW;                            // e / pivot
+    cx<A> *pa = s_cp + CW;                              // reduced system: lower
+    cx<A> *pb = pa + NT;                                // diagonal
+    cx<A> *pc = pb + NT;                                // upper
+    cx<A> *pd = pc + NT;                                // right-hand side
+    cx<A> *nb = pd + NT;                                // contributions to equation c-1 (3 per chunk)
+
+    const int j = blockIdx.x;
+    const int t = threadIdx.x;
+    cx<S> *row = spec + (size_t)j * lds;
+
+    // symbol of frequency j
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    for (int m = 0; m <= sc.s; ++m) {
+        const long long p = ((long long)j * m) % ell;
+        double sn, cs;
+        sincospi((transpose ? 2.0 : -2.0) * (double)p / (double)ell, &sn, &cs);
+        ar += sc.a[m] * cs;
+        ai += sc.a[m] * sn;
+        br += sc.b[m] * cs;
+        bi += sc.b[m] * sn;
+    }
+    const double h = 1.0 / (n + 1.0);
+    const cx<A> d = {A(ar * (4.0 * h / 6.0) + br * kappa * (2.0 / h)),
+                     A(ai * (4.0 * h / 6.0) + bi * kappa * (2.0 / h))};
+    const cx<A> e = {A(ar * (h / 6.0) - br * kappa / h), A(ai * (h / 6.0) - bi * kappa / h)};
+
+    if (t == 0) {
+        cx<A> cprev = {A(0), A(0)};
+        for (int i = 0; i < CW - 1; ++i) {
+            const cx<A> piv = d - e * cprev;
+            const cx<A> ip = recip(piv);
+            s_ip[i] = ip;
+            cprev = e * ip;
+            s_cp[i] = cprev;
+        }
+    }
+    __syncthreads();
+
+    const int P = (n + CW - 1) / CW;                     // number of chunks / separators
+    const int a0 = t * CW;
+    const int len = (t < P) ? min(CW, n - a0) : 0;
+    const int mi = len - 1;                              // interior length (may be 0)
+
+    cx<A> y[CW], u[CW];
+#pragma unroll
+    for (int i = 0; i < CW; ++i) {
+        if (i < len) {
+            const cx<S> v = row[a0 + i];
+            y[i] = {A(v.x), A(v.y)};
+        } else {
+            y[i] = {A(0), A(0)};
+        }
+        u[i] = {A(0), A(0)};
+    }
+    cx<A> rsep = {A(0), A(0)};
+#pragma unroll
+    for (int i = 0; i < CW; ++i)
+        if (i == mi) rsep = y[i];
+    const cx<A> me = {-e.x, -e.y};
+    const cx<A> zero = {A(0), A(0)};
+
+    // forward elimination of the interior: particular solution y and the
+    // response u to the left separator (right-hand side -e at interior 0)
+    cx<A> gy = {A(0), A(0)}, gu = {A(0), A(0)};
+#pragma unroll
+    for (int i = 0; i < CW - 1; ++i) {
+        if (i < mi) {
+            const cx<A> ip = s_ip[i];
+            gy = (y[i] - e * gy) * ip;
+            gu = (i == 0) ? me * ip : (me * gu) * ip;
+            y[i] = gy;
+            u[i] = gu;
+        }
+    }
+    // back substitution; v (response to the right separator) only at its ends
+    cx<A> vlast = {A(0), A(0)}, vfirst = {A(0), A(0)};
+    if (mi > 0) {
+        vlast = me * s_ip[mi - 1];
+        vfirst = vlast;
+    }
+#pragma unroll
+    for (int i = CW - 3; i >= 0; --i) {
+        if (i < mi - 1) {
+            const cx<A> cp = s_cp[i];
+            y[i] = y[i] - cp * y[i + 1];
+            u[i] = u[i] - cp * u[i + 1];
+            vfirst = zero - cp * vfirst;
+        }
+    }
+
+    // reduced (separator) system, equation c = t
+    if (t < P) {
+        cx<A> lo, di, rh;
+        if (mi > 0) {
+            cx<A> ul = zero, yl = zero;
+#pragma unroll
+            for (int i = 0; i < CW - 1; ++i)
+                if (i == mi - 1) {
+                    ul = u[i];
+                    yl = y[i];
+                }
+            lo = e * ul;
+            di = d + e * vlast;
+            rh = rsep - e * yl;
+        } else {
+            lo = e;
+            di = d;
+            rh = rsep;
+        }
+        if (t == 0) lo = zero;
+        pa[t] = lo;
+        pb[t] = di;
+        pd[t] = rh;
+        // what this chunk adds to equation t-1 (its left neighbour separator)
+        if (mi > 0) {
+            nb[3 * t + 0] = e * u[0];          // to the diagonal
+            nb[3 * t + 1] = e * vfirst;        // upper coefficient (to X_t)
+            nb[3 * t + 2] = e * y[0];          // subtracted from the rhs
+        } else {
+            nb[3 * t + 0] = zero;
+            nb[3 * t + 1] = e;
+            nb[3 * t + 2] = zero;
+        }
+    }
+    __syncthreads();
+    if (t < P) {
+        if (t + 1 < P) {
+            pb[t] = pb[t] + nb[3 * (t + 1) + 0];
+            pc[t] = nb[3 * (t + 1) + 1];
+            pd[t] = pd[t] - nb[3 * (t + 1) + 2];
+        } else {
+            pc[t] = zero;
+        }
+    }
+    __syncthreads();
+
+    // parallel cyclic reduction
+    for (int sd = 1; sd < P; sd <<= 1) {
+        cx<A> na = zero, nbv = zero, nc = zero, nd = zero;
+        if (t < P) {
+            const cx<A> a = pa[t], b = pb[t], c = pc[t], dd = pd[t];
+            nbv = b;
+            nd = dd;
+            if (t - sd >= 0) {
+                const cx<A> k1 = a * recip(pb[t - sd]);
+                na = zero - pa[t - sd] * k1;
+                nbv = nbv - pc[t - sd] * k1;
+                nd = nd - pd[t - sd] * k1;
+            }
+            if (t + sd < P) {
+                const cx<A> k2 = c * recip(pb[t + sd]);
+                nc = zero - pc[t + sd] * k2;
+                nbv = nbv - pa[t + sd] * k2;
+                nd = nd - pd[t + sd] * k2;
+            }
+        }
+        __syncthreads();
+        if (t < P) {
+            pa[t] = na;
+            pb[t] = nbv;
+            pc[t] = nc;
+            pd[t] = nd;
+        }
+        __syncthreads();
+    }
+    if (t < P) pd[t] = pd[t] * recip(pb[t]);            // separator values X_t
+    __syncthreads();
+    if (t >= P) return;
+
+    const cx<A> XL = (t > 0) ? pd[t - 1] : zero;
+    const cx<A> XR = pd[t];
+    // interior: x_i = y_i + u_i XL + v_i XR, v from the back
+    bool bad = false;
+    cx<A> vi = vlast;
+#pragma unroll
+    for (int i = CW - 2; i >= 0; --i) {
+        if (i < mi) {
+            if (i < mi - 1) vi = zero - s_cp[i] * vi;
+            const cx<A> x = y[i] + u[i] * XL + vi * XR;
+            bad |= !(isfinite((double)x.x) && isfinite((double)x.y));
+            row[a0 + i] = {S(x.x), S(x.y)};
+        }
+    }
+    bad |= !(isfinite((double)XR.x) && isfinite((double)XR.y));
+    row[a0 + len - 1] = {S(XR.x), S(XR.y)};
+    if (bad && fail) atomicOr(fail, 1);
+}
+
+template <typename A, typename S>
+static hipError_t solve_disp(void *spec, int lds, int n, int ell, Scheme sc, double kappa,
+                             int transpose, int *fail, hipStream_t st)
+{
+    const int NT = n <= 4096 ? 256 : (n <= 8192 ? 512 : 1024);
+    int cw = 1;
+    while (cw * NT < n) cw *= 2;
+    if (cw > 16) return hipErrorInvalidValue;
+    const int H = ell / 2 + 1;
+    const size_t smem = sizeof(cx<A>) * (2 * 16 + 7 * (size_t)NT);
+    cx<S> *sp = reinterpret_cast<cx<S> *>(spec);
+    auto go = [&](auto kern) -> hipError_t {
+        if (smem > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)smem);
+            if (e != hipSuccess) return e;
+        }
+        kern<<<H, NT, smem, st>>>(sp, lds, n, ell, sc, kappa, transpose, fail);
+        return hipGetLastError();
+    };
+    if (NT == 256) {
+        switch (cw) {
+        case 1: return go(k_shifted_solve<A, S, 1, 256>);
+        case 2: return go(k_shifted_solve<A, S, 2, 256>);
+        case 4: return go(k_shifted_solve<A, S, 4, 256>);
+        case 8: return go(k_shifted_solve<A, S, 8, 256>);
+        default: return go(k_shifted_solve<A, S, 16, 256>);
+        }
+    }
+    if (NT == 512) return go(k_shifted_solve<A, S, 16, 512>);
+    return go(k_shifted_solve<A, S, 16, 1024>);
+}
+
+hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
+                                int n, int ell, Scheme sc, double kappa, int transpose,
+                                int *fail_flag, hipStream_t st)
+{
+    if (!single_store)
+        return solve_disp<double, double>(spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
+    if (!single_arith)
+        return solve_disp<double, float>(spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
+    return solve_disp<float, float>(spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
+}
+
+}  // namespace aao

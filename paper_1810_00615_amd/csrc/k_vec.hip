@@ -1,0 +1,469 @@
+// Stencil and Krylov kernels: the block-Toeplitz matvec (arXiv 1810.00615,
+// Sec. 2, eq. monolithicheat / C_BD2 / eq. nonuniformmonolithicheat), the
+// right-hand side and initial data, and the classical Gram-Schmidt passes of the
+// GMRES Arnoldi process.  All FP64, all memory-bound.
+//
+// Reductions are deterministic: every kernel writes one partial per workgroup
+// (fixed in-block tree), and k_reduce_parts sums the partials in a fixed order.
+// No floating-point atomics.
+#include "aao_internal.h"
+
+namespace aao {
+
+constexpr int kRedThreads = 256;
+
+// ------------------------------------------------------------ block reduce
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&acc)[NV], int nv, double *part,
+                                                   int ldp, double *red)
+{
+    // wave-level butterfly, then one value per wave through LDS
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (i < nv) {
+            double v = acc[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) red[i * 16 + wv] = v;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[i * 16 + w];
+        part[(size_t)blockIdx.x * ldp + i] = s;
+    }
+}
+
+int dot_blocks(size_t N)
+{
+    const size_t nb = (N + kRedThreads * 4 - 1) / (kRedThreads * 4);
+    return (int)(nb < 1024 ? (nb < 1 ? 1 : nb) : 1024);
+}
+
+// ------------------------------------------------------------- CGS passes
+// MODE 0: acc_i = sum_e V_i[e] w[e]
+// MODE 1: w' = w - sum_i V_i c1_i;  acc_i = sum_e V_i[e] w'[e], acc_nv = sum w'^2
+// MODE 2: w'' = w - sum_i V_i c1_i; out = w'' ; acc_0 = sum w''^2
+template <int MODE, int NV>
+__global__ void __launch_bounds__(kRedThreads)
+k_cgs(const double *const *__restrict__ V, int nv, const double *__restrict__ w,
+      const double *__restrict__ c1, size_t N, double *__restrict__ part, int ldp,
+      double *__restrict__ out)
+{
+    __shared__ double red[(NV + 1) * 16];
+    double acc[NV + 1];
+    double cf[NV];
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) cf[i] = (MODE > 0 && i < nv) ? c1[i] : 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        const double we = w[e];
+        if (MODE == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i < nv) acc[i] += V[i][e] * we;
+        } else {
+            double vv[NV];
+            double s = we;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                vv[i] = (i < nv) ? V[i][e] : 0.0;
+                s -= vv[i] * cf[i];
+            }
+            if (MODE == 1) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    if (i < nv) acc[i] += vv[i] * s;
+                acc[NV] += s * s;
+            } else {
+                out[e] = s;
+                acc[0] += s * s;
+            }
+        }
+    }
+    // slots reduced: MODE 0 -> nv dots; MODE 1 -> nv dots + norm (stored at nv);
+    // MODE 2 -> norm only (stored at 0)
+    if (MODE == 2) acc[NV] = acc[0];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) {
+        const bool used = (i < NV) ? (MODE != 2 && i < nv) : (MODE != 0);
+        if (used) {
+            double v = acc[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) red[i * 16 + wv] = v;
+        }
+    }
+    __syncthreads();
+    const int ndots = (MODE == 2) ? 0 : nv;
+    for (int i = threadIdx.x; i <= NV; i += blockDim.x) {
+        const bool used = (i < NV) ? (i < ndots) : (MODE != 0);
+        if (!used) continue;
+        double sum = 0.0;
+        for (int w2 = 0; w2 < nw; ++w2) sum += red[i * 16 + w2];
+        const int slot = (i < NV) ? i : ndots;
+        part[(size_t)blockIdx.x * ldp + slot] = sum;
+    }
+}
+
+template <int MODE>
+static hipError_t cgs_disp(const double *const *V, int nv, const double *w, const double *c1,
+                           size_t N, double *part, int ldp, double *out, hipStream_t st)
+{
+    const int nb = dot_blocks(N);
+#define AAO_NV(K)                                                                        \
+    if (nv <= K) {                                                                       \
+        k_cgs<MODE, K><<<nb, kRedThreads, 0, st>>>(V, nv, w, c1, N, part, ldp, out);     \
+        return hipGetLastError();                                                        \
+    }
+    AAO_NV(4) AAO_NV(8) AAO_NV(16) AAO_NV(32) AAO_NV(64)
+#undef AAO_NV
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_multidot(const double *const *V, int nv, const double *w, size_t N,
+                           double *part, int ldp, hipStream_t st)
+{
+    return cgs_disp<0>(V, nv, w, nullptr, N, part, ldp, nullptr, st);
+}
+
+hipError_t launch_update_dot(const double *const *V, int nv, const double *w, const double *h,
+                             size_t N, double *part, int ldp, hipStream_t st)
+{
+    return cgs_disp<1>(V, nv, w, h, N, part, ldp, nullptr, st);
+}
+
+hipError_t launch_update_norm(const double *const *V, int nv, const double *w, const double *h,
+                              double *out, size_t N, double *part, int ldp, hipStream_t st)
+{
+    return cgs_disp<2>(V, nv, w, h, N, part, ldp, out, st);
+}
+
+// Fixed-order sum of the per-block partials: sums[i] = sum_b part[b*ldp + i].
+__global__ void __launch_bounds__(256)
+k_reduce_parts(const double *__restrict__ part, int nblk, int ldp, double *__restrict__ sums)
+{
+    __shared__ double red[256];
+    const int i = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)b * ldp + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[i] = red[0];
+}
+
+hipError_t launch_reduce_parts(const double *part, int nblk, int ldp, int cnt, double *sums,
+                               hipStream_t st)
+{
+    k_reduce_parts<<<cnt, 256, 0, st>>>(part, nblk, ldp, sums);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- small vector ops
+__global__ void k_multi_axpy(const double *const *__restrict__ Z, int nz,
+                             const double *__restrict__ y, double *__restrict__ x, size_t N)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        double s = x[e];
+        for (int i = 0; i < nz; ++i) s += Z[i][e] * y[i];
+        x[e] = s;
+    }
+}
+
+static int grid_for(size_t N)
+{
+    size_t g = (N + 255) / 256;
+    return (int)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
+}
+
+hipError_t launch_multi_axpy(const double *const *Z, int nz, const double *y, double *x,
+                             size_t N, hipStream_t st)
+{
+    k_multi_axpy<<<grid_for(N), 256, 0, st>>>(Z, nz, y, x, N);
+    return hipGetLastError();
+}
+
+__global__ void k_scale(const double *__restrict__ w, const double *__restrict__ sc, double a,
+                        double *__restrict__ out, size_t N)
+{
+    const double f = sc ? *sc : a;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride)
+        out[e] = w[e] * f;
+}
+
+hipError_t launch_scale(const double *w, const double *scale, double *out, size_t N,
+                        hipStream_t st)
+{
+    k_scale<<<grid_for(N), 256, 0, st>>>(w, scale, 0.0, out, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_h(const double *w, double a, double *out, size_t N, hipStream_t st)
+{
+    k_scale<<<grid_for(N), 256, 0, st>>>(w, nullptr, a, out, N);
+    return hipGetLastError();
+}
+
+__global__ void k_fill(double *x, double v, size_t N)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) x[e] = v;
+}
+
+hipError_t launch_fill(double *x, double v, size_t N, hipStream_t st)
+{
+    k_fill<<<grid_for(N), 256, 0, st>>>(x, v, N);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kRedThreads)
+k_dot1(const double *__restrict__ a, const double *__restrict__ b, size_t N,
+       double *__restrict__ part)
+{
+    __shared__ double red[2 * 16];
+    double acc[1] = {0.0};
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride)
+        acc[0] += a[e] * b[e];
+    block_reduce_store<1>(acc, 1, part, 1, red);
+}
+
+hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double *part,
+                             hipStream_t st)
+{
+    k_dot1<<<dot_blocks(N), kRedThreads, 0, st>>>(a, b, N, part);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------- matvec (Sec. 2)
+// y_k = sum_{m=0}^{s} (a_m M + b_m^{(k)} kappa K) x_{k-m}   (x_{k+m} if transposed)
+// with b_0^{(k)} = tau_k when variable steps are given.  y = bsub - A x if bsub.
+__global__ void __launch_bounds__(256)
+k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
+         int n, int ell, Scheme sc, double kappa, const double *__restrict__ tau_k, int transpose)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= n) return;
+    const double h = 1.0 / (n + 1.0);
+    double al = 0.0, ac = 0.0, ar = 0.0, bl = 0.0, bc = 0.0, br = 0.0;
+    for (int m = 0; m <= sc.s; ++m) {
+        const int src = transpose ? k + m : k - m;
+        if (src < 0 || src >= ell) continue;
+        const double am = sc.a[m];
+        double bm = sc.b[m];
+        if (m == 0 && tau_k) bm = tau_k[k];
+        bm *= kappa;
+        const double *xr = x + (size_t)src * n;
+        const double xc = xr[i];
+        const double xl = i > 0 ? xr[i - 1] : 0.0;
+        const double xrr = i < n - 1 ? xr[i + 1] : 0.0;
+        al += am * xl;
+        ac += am * xc;
+        ar += am * xrr;
+        bl += bm * xl;
+        bc += bm * xc;
+        br += bm * xrr;
+    }
+    const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
+    const size_t o = (size_t)k * n + i;
+    y[o] = bsub ? bsub[o] - v : v;
+}
+
+hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
+                         Scheme sc, double kappa, const double *tau_k, int transpose,
+                         hipStream_t st)
+{
+    dim3 grid((n + 255) / 256, ell);
+    k_matvec<<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, tau_k, transpose);
+    return hipGetLastError();
+}
+
+// y = (cm M + ck K) x (+ (cm2 M + ck2 K) x2), one n-vector
+__global__ void k_mk(const double *__restrict__ x, double cm, double ck,
+                     const double *__restrict__ x2, double cm2, double ck2,
+                     double *__restrict__ y, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = 1.0 / (n + 1.0);
+    const double xl = i > 0 ? x[i - 1] : 0.0, xr = i < n - 1 ? x[i + 1] : 0.0;
+    double v = cm * (h / 6.0) * (xl + 4.0 * x[i] + xr) + ck * (1.0 / h) * (2.0 * x[i] - xl - xr);
+    if (x2) {
+        const double zl = i > 0 ? x2[i - 1] : 0.0, zr = i < n - 1 ? x2[i + 1] : 0.0;
+        v += cm2 * (h / 6.0) * (zl + 4.0 * x2[i] + zr) + ck2 * (1.0 / h) * (2.0 * x2[i] - zl - zr);
+    }
+    y[i] = v;
+}
+
+hipError_t launch_mk(const double *x, double cm, double ck, const double *x2, double cm2,
+                     double ck2, double *y, int n, hipStream_t st)
+{
+    k_mk<<<(n + 255) / 256, 256, 0, st>>>(x, cm, ck, x2, cm2, ck2, y, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------ initial data and rhs
+// u0_i = sum_m amps_m (g_m / mu_m) sin(q_m pi x_i): the L2 projection of a sine
+// series (each sine mode is an eigenvector of M with eigenvalue
+// mu = (h/3)(2 + cos q pi h); its exact load vector is g sin(q pi x_i),
+// g = 4 sin^2(q pi h / 2) / (h q^2 pi^2)).
+__global__ void k_project_sine(double *__restrict__ u0, int n, int J,
+                               const int *__restrict__ modes, const double *__restrict__ amps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double h = 1.0 / (n + 1.0);
+    const long long period = 2LL * (n + 1);
+    double s = 0.0;
+    for (int m = 0; m < J; ++m) {
+        const long long q = modes[m];
+        const double sh = sinpi(0.5 * (double)q / (double)(n + 1));
+        const double g = 4.0 * sh * sh / (h * (double)q * (double)q * M_PI * M_PI);
+        const double mu = (h / 3.0) * (2.0 + cospi((double)q / (double)(n + 1)));
+        const long long arg = (q * (long long)(i + 1)) % period;
+        s += amps[m] * (g / mu) * sinpi((double)arg / (double)(n + 1));
+    }
+    u0[i] = s;
+}
+
+hipError_t launch_project_sine(double *u0, int n, int J, const int *modes, const double *amps,
+                               hipStream_t st)
+{
+    k_project_sine<<<(n + 255) / 256, 256, 0, st>>>(u0, n, J, modes, amps);
+    return hipGetLastError();
+}
+
+// heat: b_1 = M u0; BD2: b_1 = A_0 (u0 + tau v0), b_2 = -M u0; other rows 0.
+__global__ void k_build_rhs(double *__restrict__ b, const double *__restrict__ u0,
+                            const double *__restrict__ v0, int n, int ell, int bd2,
+                            double a0b, double tau)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= n) return;
+    const double h = 1.0 / (n + 1.0);
+    double v = 0.0;
+    if (k == 0) {
+        auto w = [&](int p) {
+            if (p < 0 || p >= n) return 0.0;
+            return u0[p] + (v0 ? tau * v0[p] : 0.0);
+        };
+        const double wl = w(i - 1), wc = w(i), wr = w(i + 1);
+        v = (h / 6.0) * (wl + 4.0 * wc + wr);
+        if (bd2) v += a0b * (1.0 / h) * (2.0 * wc - wl - wr);
+    } else if (k == 1 && bd2) {
+        const double ul = i > 0 ? u0[i - 1] : 0.0, ur = i < n - 1 ? u0[i + 1] : 0.0;
+        v = -(h / 6.0) * (ul + 4.0 * u0[i] + ur);
+    }
+    b[(size_t)k * n + i] = v;
+}
+
+hipError_t launch_build_rhs(double *b, const double *u0, const double *v0, int n, int ell,
+                            Scheme sc, double kappa, double tau, hipStream_t st)
+{
+    const int bd2 = sc.s == 2;
+    dim3 grid((n + 255) / 256, ell);
+    k_build_rhs<<<grid, 256, 0, st>>>(b, u0, bd2 ? v0 : nullptr, n, ell, bd2, sc.b[0] * kappa,
+                                      tau);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------- gradient (kappa)
+// partials of sum_k sum_m c_m^{(k)} lam_k . (K u_{k-m}),  c_m = b_m (tau_k for m = 0)
+__global__ void __launch_bounds__(kRedThreads)
+k_grad_kappa(const double *__restrict__ U, const double *__restrict__ lam, int n, int ell,
+             Scheme sc, const double *__restrict__ tau_k, double *__restrict__ part)
+{
+    __shared__ double red[2 * 16];
+    double acc[1] = {0.0};
+    const double hinv = n + 1.0;
+    const size_t N = (size_t)n * ell;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
+        const int k = (int)(e / n);
+        const int i = (int)(e - (size_t)k * n);
+        double ku = 0.0;
+        for (int m = 0; m <= sc.s; ++m) {
+            double cm = sc.b[m];
+            if (m == 0 && tau_k) cm = tau_k[k];
+            if (cm == 0.0 || k - m < 0) continue;
+            const double *ur = U + (size_t)(k - m) * n;
+            const double ul = i > 0 ? ur[i - 1] : 0.0, urr = i < n - 1 ? ur[i + 1] : 0.0;
+            ku += cm * hinv * (2.0 * ur[i] - ul - urr);
+        }
+        acc[0] += lam[e] * ku;
+    }
+    block_reduce_store<1>(acc, 1, part, 1, red);
+}
+
+hipError_t launch_grad_kappa_parts(const double *U, const double *lam, int n, int ell,
+                                   Scheme sc, const double *tau_k, double *part, int nblk,
+                                   hipStream_t st)
+{
+    k_grad_kappa<<<nblk, kRedThreads, 0, st>>>(U, lam, n, ell, sc, tau_k, part);
+    return hipGetLastError();
+}
+
+}  // namespace aao
+
+namespace aao {
+
+// Scalar bookkeeping of one Arnoldi step, on the device so that no host round
+// trip sits between the Gram-Schmidt passes.  The basis is stored unnormalised
+// with scales vs (v_i = vs_i * V_i); d holds the reduced raw dot products.
+//   mode 0: h1 = vs.d, c = vs.h1                    (first projection)
+//   mode 1: h2 = vs.d, c += vs.h2                   (re-orthogonalisation)
+//   mode 2: nrm = sqrt(d_0), vs_nv = 1/nrm, hcol = [h1 + h2, nrm]
+//   mode 3: nrm = sqrt(d_0), vs_0 = 1/nrm, hcol_0 = nrm   (restart vector)
+__global__ void k_arnoldi_small(int mode, int nv, const double *__restrict__ d, double *h1,
+                                double *h2, double *c, double *vs, double *hcol)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (mode == 0) {
+        for (int i = 0; i < nv; ++i) {
+            h1[i] = vs[i] * d[i];
+            c[i] = vs[i] * h1[i];
+        }
+    } else if (mode == 1) {
+        for (int i = 0; i < nv; ++i) {
+            h2[i] = vs[i] * d[i];
+            c[i] += vs[i] * h2[i];
+        }
+    } else {
+        const double nrm = sqrt(fmax(d[0], 0.0));
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        if (mode == 2) {
+            vs[nv] = inv;
+            for (int i = 0; i < nv; ++i) hcol[i] = h1[i] + h2[i];
+            hcol[nv] = nrm;
+        } else {
+            vs[0] = inv;
+            hcol[0] = nrm;
+        }
+    }
+}
+
+hipError_t launch_arnoldi_small(int mode, int nv, const double *d, double *h1, double *h2,
+                                double *c, double *vs, double *hcol, hipStream_t st)
+{
+    k_arnoldi_small<<<1, 64, 0, st>>>(mode, nv, d, h1, h2, c, vs, hcol);
+    return hipGetLastError();
+}
+
+}  // namespace aao

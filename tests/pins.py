@@ -123,3 +123,39 @@ def kron_A(blocks, ell, circulant=False):
             S = S + np.eye(ell, k=ell - m)
         A += np.kron(S, B)
     return A
+
+
+def eig_C(scheme, n, ell, tau, kappa, transpose=False):
+    """Eigenvalues of the block circulant on the (frequency j, sine mode m) basis:
+    hatA_j = alpha_j M + beta_j kappa K acts on sine mode m as
+    alpha_j mu_m + beta_j kappa lambda_m mu_m (M, K share the sine eigenvectors)."""
+    h = 1.0 / (n + 1)
+    m = np.arange(1, n + 1)
+    c = np.cos(m * np.pi * h)
+    mu_ = (h / 3.0) * (2.0 + c)
+    lam_ = 6.0 * (1.0 - c) / (h * h * (2.0 + c))
+    j = np.arange(ell)
+    w = np.exp((1j if transpose else -1j) * 2 * np.pi * j / ell)
+    if scheme == 0:
+        al, be = 1 - w, np.full(ell, tau)
+    else:
+        al, be = (1 - w) ** 2, np.full(ell, tau * tau)
+    return al[:, None] * mu_[None, :] + be[:, None] * kappa * (lam_ * mu_)[None, :]
+
+
+def cond_C(scheme, n, ell, tau, kappa):
+    e = np.abs(eig_C(scheme, n, ell, tau, kappa))
+    return e.max() / e.min()
+
+
+def pinv_spectral(scheme, n, ell, tau, kappa, r, transpose=False):
+    """C^{-1} r through the full eigen-decomposition of the block circulant: FFT in
+    time, DST-I in space, division by the eigenvalues, inverse transforms.  Its
+    rounding error does not grow with cond(hatA_j) the way an elimination's does,
+    so it is the accuracy reference for ill-conditioned symbols."""
+    from scipy.fft import dst, idst
+    X = np.fft.fft(np.asarray(r, dtype=np.float64).reshape(ell, n), axis=0)
+    Xs = dst(X, type=1, axis=1)
+    Ys = Xs / eig_C(scheme, n, ell, tau, kappa, transpose)
+    Y = idst(Ys, type=1, axis=1)
+    return np.fft.ifft(Y, axis=0).real
