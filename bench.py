@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pinv-reps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one plain device copy of one ell x n FP64 vector "
+                         "(reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -149,6 +152,9 @@ def main():
     b = P.rhs(u0)
     x = P.empty()
     N = w.n * w.ell
+    if args.calibrate_copy:
+        x.copy_(b)
+        torch.cuda.synchronize()
 
     out = {"metric": METRIC, "unit": "solve/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",

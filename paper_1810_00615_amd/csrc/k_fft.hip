@@ -16,21 +16,23 @@
 //   X_j = (Z_j + conj Z_{L-j})/2 - (i/2) w^j (Z_j - conj Z_{L-j}),  j = 0..L,
 // with w = exp(-2 pi i / ell).  The inverse runs the same steps backwards.
 // Lengths that are not powers of two use a direct-DFT kernel.
+#include <cstdlib>
+
 #include "aao_internal.h"
 
 namespace aao {
 
-// cos / sin of 2 pi k / 16
-constexpr double kC16[16] = {
-    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
-    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
-constexpr double kS16[16] = {
-    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
-    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
-    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
-    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+// cos / sin of 2 pi k / 32 (double nearest)
+constexpr double kC32[32] = {1, 0.980785280403230430579, 0.923879532511286738483, 0.831469612302545235671, 0.707106781186547572737, 0.555570233019602177649, 0.382683432365089781779, 0.195090322016128275839, 0.0, -0.195090322016128275839, -0.382683432365089781779, -0.555570233019602177649, -0.707106781186547572737, -0.831469612302545235671, -0.923879532511286738483, -0.980785280403230430579, -1, -0.980785280403230430579, -0.923879532511286738483, -0.831469612302545235671, -0.707106781186547572737, -0.555570233019602177649, -0.382683432365089781779, -0.195090322016128275839, 0.0, 0.195090322016128275839, 0.382683432365089781779, 0.555570233019602177649, 0.707106781186547572737, 0.831469612302545235671, 0.923879532511286738483, 0.980785280403230430579};
+constexpr double kS32[32] = {0.0, 0.195090322016128275839, 0.382683432365089781779, 0.555570233019602177649, 0.707106781186547572737, 0.831469612302545235671, 0.923879532511286738483, 0.980785280403230430579, 1, 0.980785280403230430579, 0.923879532511286738483, 0.831469612302545235671, 0.707106781186547572737, 0.555570233019602177649, 0.382683432365089781779, 0.195090322016128275839, 0.0, -0.195090322016128275839, -0.382683432365089781779, -0.555570233019602177649, -0.707106781186547572737, -0.831469612302545235671, -0.923879532511286738483, -0.980785280403230430579, -1, -0.980785280403230430579, -0.923879532511286738483, -0.831469612302545235671, -0.707106781186547572737, -0.555570233019602177649, -0.382683432365089781779, -0.195090322016128275839};
+
+// exp(-2 pi i k / 32) (conjugated when INV), k a compile-time constant after unrolling
+template <bool INV, typename T>
+__device__ __forceinline__ cx<T> root32(int k)
+{
+    k &= 31;
+    return {T(kC32[k]), T(INV ? kS32[k] : -kS32[k])};
+}
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 constexpr int bitrev(int v, int bits) {
@@ -60,7 +62,7 @@ __device__ __forceinline__ void dft_reg(cx<T> *v)
         for (int k = 0; k < R; k += m) {
 #pragma unroll
             for (int jj = 0; jj < m / 2; ++jj) {
-                const int ti = jj * (16 / m);
+                const int ti = jj * (16 / m);      // index of exp(-2 pi i ti / 16)
                 cx<T> b = v[k + jj + m / 2];
                 cx<T> t;
                 if (ti == 0) {
@@ -68,8 +70,7 @@ __device__ __forceinline__ void dft_reg(cx<T> *v)
                 } else if (ti == 4) {               // multiply by -+ i
                     t = INV ? mul_i(b) : cx<T>{b.y, -b.x};
                 } else {
-                    const cx<T> w = {T(kC16[ti]), T(INV ? kS16[ti] : -kS16[ti])};
-                    t = w * b;
+                    t = root32<INV, T>(2 * ti) * b;
                 }
                 cx<T> a = v[k + jj];
                 v[k + jj] = a + t;
@@ -88,6 +89,23 @@ template <int L> struct Plan {
     }
     static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * radix(s - 1); }
 };
+
+// Workgroups are dealt to the 8 XCDs round-robin (id mod 8).  Tiles that share
+// 128-byte lines with their neighbours should meet in one XCD's L2, so the
+// workgroup id is remapped to give each XCD a contiguous range of tiles.  The
+// grid is padded to a multiple of 8; ids past the last tile map past n and idle.
+__device__ __forceinline__ int xcd_tile(int g, int G)
+{
+    const int per = G / 8;
+    return (g % 8) * per + g / 8;
+}
+__host__ __device__ constexpr int xcd_grid(int tiles) { return (tiles + 7) / 8 * 8; }
+
+// LDS slot of (position, column): one padding row every 16 positions, so that
+// the stride-16 position pattern of the first stage's outputs spreads the
+// W-column groups of a wave over distinct banks.
+__device__ __forceinline__ int lds_idx(int pos, int c, int W) { return (pos + (pos >> 4)) * W + c; }
+__host__ __device__ constexpr int lds_rows(int L) { return L + L / 16 + 1; }
 
 // Thread-held values: v[u*R + r] is input r of butterfly q = t + u*TN.
 template <typename T, int L, int P, int S, bool INV>
@@ -159,13 +177,13 @@ __device__ __forceinline__ void exchange(cx<T> *v, T *sm, int t, int c, int W)
         for (int u = 0; u < P / R1; ++u)
 #pragma unroll
             for (int r = 0; r < R1; ++r)
-                sm[out_pos<L, P, S>(t, u, r) * W + c] = part ? v[u * R1 + r].y : v[u * R1 + r].x;
+                sm[lds_idx(out_pos<L, P, S>(t, u, r), c, W)] = part ? v[u * R1 + r].y : v[u * R1 + r].x;
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < P / R2; ++u)
 #pragma unroll
             for (int r = 0; r < R2; ++r) {
-                const T val = sm[in_pos<L, P, S + 1>(t, u, r) * W + c];
+                const T val = sm[lds_idx(in_pos<L, P, S + 1>(t, u, r), c, W)];
                 if (part) v[u * R2 + r].y = val; else v[u * R2 + r].x = val;
             }
         __syncthreads();
@@ -225,7 +243,7 @@ k_fft_fwd(const double *__restrict__ r, const double *__restrict__ in_scale,
     T *sm = reinterpret_cast<T *>(smraw);
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
-    const int col = blockIdx.x * W + c;
+    const int col = xcd_tile(blockIdx.x, gridDim.x) * W + c;
     const bool valid = col < n;
     const double rs = in_scale ? *in_scale : 1.0;
     cx<T> v[P];
@@ -250,39 +268,50 @@ k_fft_fwd(const double *__restrict__ r, const double *__restrict__ in_scale,
         v[idx] = {T(a), T(b)};
     }
     run_stages<T, L, P, 0, false>(v, sm, t, c, W, tw, 2);
-    // split Z into the half spectrum: needs Z_{L-p}, held by another thread.
-    // With z = Z_p = (a, b) and Z_{L-p} = (c, d):
-    //   F_e = ((a + c)/2, (b - d)/2),  F_o = (Z_p - conj Z_{L-p}) / 2i = ((b + d)/2, (c - a)/2)
-    // The real plane goes through LDS first; v[idx].x then holds F_e.x and fo_y
-    // holds F_o.y, so only P extra reals are live.
-    T fo_y[P];
-#pragma unroll
-    for (int idx = 0; idx < P; ++idx) sm[final_pos<L, P>(t, idx) * W + c] = v[idx].x;
-    __syncthreads();
+    // Split Z into the half spectrum.  With F_e = (Z_p + conj Z_{L-p})/2,
+    // F_o = (Z_p - conj Z_{L-p})/2i and w = w_ell^p:
+    //   X_p = F_e + w F_o,  X_{L-p} = conj(F_e - w F_o),  X_0 = Re Z_0 + Im Z_0,
+    //   X_L = Re Z_0 - Im Z_0,  X_{L/2} = conj Z_{L/2}.
+    // The upper half of Z (positions L/2..L-1) goes to LDS as complex values; the
+    // holders of the lower half then read their partner and write both outputs.
+    constexpr int RL = Plan<L>::NS == 0 ? 1 : Plan<L>::radix(Plan<L>::NS - 1);
+    constexpr int H2 = L / 2;
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
         const int pos = final_pos<L, P>(t, idx);
-        const T cc = sm[((L - pos) & (L - 1)) * W + c];
-        const T a = v[idx].x;
-        v[idx].x = T(0.5) * (a + cc);
-        fo_y[idx] = T(0.5) * (cc - a);
+        if (pos >= H2 && L > 1) {
+            const int k = 2 * lds_idx(pos - H2, c, W);
+            sm[k] = v[idx].x;
+            sm[k + 1] = v[idx].y;
+        }
     }
     __syncthreads();
+    if (!valid) return;
 #pragma unroll
-    for (int idx = 0; idx < P; ++idx) sm[final_pos<L, P>(t, idx) * W + c] = v[idx].y;
-    __syncthreads();
+    for (int u = 0; u < P / RL; ++u) {
+        const int q = t + u * (L / P);
+        const cx<double> wqd = tw[q];
+        const cx<T> wq = {T(wqd.x), T(wqd.y)};
 #pragma unroll
-    for (int idx = 0; idx < P; ++idx) {
-        const int pos = final_pos<L, P>(t, idx);
-        const T dd = sm[((L - pos) & (L - 1)) * W + c];
-        const T b = v[idx].y;
-        const cx<T> fe = {v[idx].x, T(0.5) * (b - dd)};
-        const cx<T> fo = {T(0.5) * (b + dd), fo_y[idx]};
-        if (valid) {
-            const cx<double> wd = tw[pos];                  // w_ell^pos
-            const cx<T> w = {T(wd.x), T(wd.y)};
-            X[(size_t)pos * lds + col] = fe + w * fo;
-            if (pos == 0) X[(size_t)L * lds + col] = fe - fo;
+        for (int r = 0; r < RL; ++r) {
+            const int idx = u * RL + r;
+            const int pos = final_pos<L, P>(t, idx);
+            const cx<T> z = v[idx];
+            if (pos == 0) {
+                X[col] = {z.x + z.y, T(0)};
+                X[(size_t)L * lds + col] = {z.x - z.y, T(0)};
+            } else if (2 * pos == L) {
+                X[(size_t)pos * lds + col] = conj(z);
+            } else if (pos < H2) {
+                const int k = 2 * lds_idx(L - pos - H2, c, W);
+                const cx<T> zp = {sm[k], sm[k + 1]};
+                const cx<T> fe = {T(0.5) * (z.x + zp.x), T(0.5) * (z.y - zp.y)};
+                const cx<T> fo = {T(0.5) * (z.y + zp.y), T(0.5) * (zp.x - z.x)};
+                const cx<T> w = (r == 0) ? wq : wq * root32<false, T>(r * (16 / RL));
+                const cx<T> wf = w * fo;
+                X[(size_t)pos * lds + col] = fe + wf;
+                X[(size_t)(L - pos) * lds + col] = conj(fe - wf);
+            }
         }
     }
 }
@@ -297,23 +326,33 @@ k_fft_inv(const cx<T> *__restrict__ Y, int lds, double *__restrict__ z, int n, i
     T *sm = reinterpret_cast<T *>(smraw);
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
-    const int col = blockIdx.x * W + c;
+    const int col = xcd_tile(blockIdx.x, gridDim.x) * W + c;
     const bool valid = col < n;
     cx<T> v[P];
+    // E_p + i O_p with E_p = Y_p + conj Y_{L-p}, O_p = (Y_p - conj Y_{L-p}) w_ell^{-p};
+    // first-stage positions are p = q + r L/R0, so w_ell^{-p} = conj(w_ell^q) times the
+    // constant conj(w_{2 R0}^r)
+    constexpr int R0 = Plan<L>::NS == 0 ? 1 : Plan<L>::radix(0);
 #pragma unroll
-    for (int idx = 0; idx < P; ++idx) {
-        const int pos = first_pos<L, P>(t, idx);
-        cx<T> q = {T(0), T(0)};
-        if (valid) {
-            const cx<T> a = Y[(size_t)pos * lds + col];
-            const cx<T> b = conj(Y[(size_t)(L - pos) * lds + col]);
-            const cx<double> wd = tw[pos];
-            const cx<T> wc = {T(wd.x), T(-wd.y)};            // w_ell^{-pos}
-            const cx<T> e = a + b;
-            const cx<T> o = wc * (a - b);
-            q = e + mul_i(o);
+    for (int u = 0; u < P / R0; ++u) {
+        const int q0 = t + u * (L / P);
+        const cx<double> wqd = tw[q0];
+        const cx<T> wq = {T(wqd.x), T(-wqd.y)};
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const int idx = u * R0 + r;
+            const int pos = first_pos<L, P>(t, idx);
+            cx<T> q = {T(0), T(0)};
+            if (valid) {
+                const cx<T> a = Y[(size_t)pos * lds + col];
+                const cx<T> b = conj(Y[(size_t)(L - pos) * lds + col]);
+                const cx<T> wc = (r == 0) ? wq : wq * root32<true, T>(r * (16 / R0));
+                const cx<T> e = a + b;
+                const cx<T> o = wc * (a - b);
+                q = e + mul_i(o);
+            }
+            v[idx] = q;
         }
-        v[idx] = q;
     }
     run_stages<T, L, P, 0, true>(v, sm, t, c, W, tw, 2);
     if (!valid) return;
@@ -403,8 +442,14 @@ bool fft_supported_fast(int ell) { return ell >= 2 && ell <= 16384 && (ell & (el
 static int pick_w(int L, int P, int n, size_t realsz)
 {
     const int tn = L / P;
+    if (const char *e = getenv("AAO_FFT_W")) {
+        int w = atoi(e);
+        if (w >= 1 && w <= 64 && (w & (w - 1)) == 0 && w * tn <= 1024 &&
+            (size_t)w * lds_rows(L) * realsz <= 160 * 1024)
+            return w;
+    }
     int w = 1;
-    while (w < 64 && 2 * w * tn <= 1024 && (size_t)2 * w * L * realsz <= 160 * 1024 &&
+    while (w < 64 && 2 * w * tn <= 1024 && (size_t)2 * w * lds_rows(L) * realsz <= 160 * 1024 &&
            (w < 8 || w < n))
         w *= 2;
     return w;
@@ -417,14 +462,14 @@ static hipError_t fwd_L(const double *r, const double *in_scale, const double *z
 {
     constexpr int P = L < 16 ? L : 16;
     const int W = pick_w(L, P, n, sizeof(T));
-    const size_t smem = (size_t)L * W * sizeof(T);
+    const size_t smem = (size_t)lds_rows(L) * W * sizeof(T);
     auto kern = zprev ? k_fft_fwd<T, L, P, true> : k_fft_fwd<T, L, P, false>;
     if (smem > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    dim3 grid((n + W - 1) / W);
+    dim3 grid(xcd_grid((n + W - 1) / W));
     kern<<<grid, W * (L / P), smem, st>>>(r, in_scale, zprev, sigk, kap_h, n, W,
                                           reinterpret_cast<cx<T> *>(spec), lds,
                                           reinterpret_cast<const cx<double> *>(tw));
@@ -437,14 +482,14 @@ static hipError_t inv_L(const void *spec, int lds, double *z, int n, const doubl
 {
     constexpr int P = L < 16 ? L : 16;
     const int W = pick_w(L, P, n, sizeof(T));
-    const size_t smem = (size_t)L * W * sizeof(T);
+    const size_t smem = (size_t)lds_rows(L) * W * sizeof(T);
     auto kern = k_fft_inv<T, L, P>;
     if (smem > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    dim3 grid((n + W - 1) / W);
+    dim3 grid(xcd_grid((n + W - 1) / W));
     kern<<<grid, W * (L / P), smem, st>>>(reinterpret_cast<const cx<T> *>(spec), lds, z, n, W,
                                           reinterpret_cast<const cx<double> *>(tw));
     return hipGetLastError();

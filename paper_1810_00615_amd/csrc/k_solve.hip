@@ -35,7 +35,14 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
     const int NT = blockDim.x;
     cx<A> *s_ip = reinterpret_cast<cx<A> *>(smraw);   // 1/pivot of the interior elimination
     cx<A> *s_cp = s_ip + CW;                            // e / pivot
-    cx<A> *pa = s_cp + CW;                              // reduced system: lower
+    // The row is staged through LDS so that global accesses are coalesced while
+    // each thread works on CW contiguous unknowns.  Element i of chunk t sits in
+    // slot i*(NT+PAD) + t: the chunk reads (consecutive t) and the coalesced writes
+    // (8 consecutive lanes = one chunk) both spread over all banks with PAD = 2
+    // (16-byte elements) or 4 (8-byte elements).  The reduced-system arrays reuse
+    // the same space once the chunks are in registers.
+    cx<S> *stage = reinterpret_cast<cx<S> *>(s_cp + CW);
+    cx<A> *pa = reinterpret_cast<cx<A> *>(s_cp + CW);  // reduced system: lower
     cx<A> *pb = pa + NT;                                // diagonal
     cx<A> *pc = pb + NT;                                // upper
     cx<A> *pd = pc + NT;                                // right-hand side
@@ -78,17 +85,22 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
     const int len = (t < P) ? min(CW, n - a0) : 0;
     const int mi = len - 1;                              // interior length (may be 0)
 
+    constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
+    const int NTP = NT + PAD;
+    for (int e = t; e < n; e += NT) stage[(e % CW) * NTP + e / CW] = row[e];
+    __syncthreads();
     cx<A> y[CW], u[CW];
 #pragma unroll
     for (int i = 0; i < CW; ++i) {
         if (i < len) {
-            const cx<S> v = row[a0 + i];
+            const cx<S> v = stage[i * NTP + t];
             y[i] = {A(v.x), A(v.y)};
         } else {
             y[i] = {A(0), A(0)};
         }
         u[i] = {A(0), A(0)};
     }
+    __syncthreads();   // the staging area is reused for the reduced system
     cx<A> rsep = {A(0), A(0)};
 #pragma unroll
     for (int i = 0; i < CW; ++i)
@@ -202,24 +214,30 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
     }
     if (t < P) pd[t] = pd[t] * recip(pb[t]);            // separator values X_t
     __syncthreads();
-    if (t >= P) return;
-
-    const cx<A> XL = (t > 0) ? pd[t - 1] : zero;
-    const cx<A> XR = pd[t];
+    cx<A> XL = zero, XR = zero;
+    if (t < P) {
+        XL = (t > 0) ? pd[t - 1] : zero;
+        XR = pd[t];
+    }
+    __syncthreads();   // staging area becomes the output buffer again
     // interior: x_i = y_i + u_i XL + v_i XR, v from the back
     bool bad = false;
-    cx<A> vi = vlast;
+    if (t < P) {
+        cx<A> vi = vlast;
 #pragma unroll
-    for (int i = CW - 2; i >= 0; --i) {
-        if (i < mi) {
-            if (i < mi - 1) vi = zero - s_cp[i] * vi;
-            const cx<A> x = y[i] + u[i] * XL + vi * XR;
-            bad |= !(isfinite((double)x.x) && isfinite((double)x.y));
-            row[a0 + i] = {S(x.x), S(x.y)};
+        for (int i = CW - 2; i >= 0; --i) {
+            if (i < mi) {
+                if (i < mi - 1) vi = zero - s_cp[i] * vi;
+                const cx<A> x = y[i] + u[i] * XL + vi * XR;
+                bad |= !(isfinite((double)x.x) && isfinite((double)x.y));
+                stage[i * NTP + t] = {S(x.x), S(x.y)};
+            }
         }
+        bad |= !(isfinite((double)XR.x) && isfinite((double)XR.y));
+        stage[(len - 1) * NTP + t] = {S(XR.x), S(XR.y)};
     }
-    bad |= !(isfinite((double)XR.x) && isfinite((double)XR.y));
-    row[a0 + len - 1] = {S(XR.x), S(XR.y)};
+    __syncthreads();
+    for (int e = t; e < n; e += NT) row[e] = stage[(e % CW) * NTP + e / CW];
     if (bad && fail) atomicOr(fail, 1);
 }
 
@@ -227,12 +245,15 @@ template <typename A, typename S>
 static hipError_t solve_disp(void *spec, int lds, int n, int ell, Scheme sc, double kappa,
                              int transpose, int *fail, hipStream_t st)
 {
-    const int NT = n <= 4096 ? 256 : (n <= 8192 ? 512 : 1024);
+    // chunks of at most 8 unknowns per thread where possible (register budget)
+    const int NT = n <= 2048 ? 256 : (n <= 4096 ? 512 : 1024);
     int cw = 1;
     while (cw * NT < n) cw *= 2;
     if (cw > 16) return hipErrorInvalidValue;
     const int H = ell / 2 + 1;
-    const size_t smem = sizeof(cx<A>) * (2 * 16 + 7 * (size_t)NT);
+    const size_t stage_bytes = sizeof(cx<S>) * (size_t)cw * (NT + 4);
+    const size_t red_bytes = sizeof(cx<A>) * 7 * (size_t)NT;
+    const size_t smem = sizeof(cx<A>) * 2 * (size_t)cw + (stage_bytes > red_bytes ? stage_bytes : red_bytes);
     cx<S> *sp = reinterpret_cast<cx<S> *>(spec);
     auto go = [&](auto kern) -> hipError_t {
         if (smem > 64 * 1024) {
@@ -253,7 +274,11 @@ static hipError_t solve_disp(void *spec, int lds, int n, int ell, Scheme sc, dou
         default: return go(k_shifted_solve<A, S, 16, 256>);
         }
     }
-    if (NT == 512) return go(k_shifted_solve<A, S, 16, 512>);
+    if (NT == 512) {
+        if (cw <= 8) return go(k_shifted_solve<A, S, 8, 512>);
+        return go(k_shifted_solve<A, S, 16, 512>);
+    }
+    if (cw <= 8) return go(k_shifted_solve<A, S, 8, 1024>);
     return go(k_shifted_solve<A, S, 16, 1024>);
 }
 

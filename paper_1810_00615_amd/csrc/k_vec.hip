@@ -41,7 +41,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], int nv, do
 int dot_blocks(size_t N)
 {
     const size_t nb = (N + kRedThreads * 4 - 1) / (kRedThreads * 4);
-    return (int)(nb < 1024 ? (nb < 1 ? 1 : nb) : 1024);
+    return (int)(nb < 4096 ? (nb < 1 ? 1 : nb) : 4096);
 }
 
 // ------------------------------------------------------------- CGS passes
@@ -61,29 +61,38 @@ k_cgs(const double *const *__restrict__ V, int nv, const double *__restrict__ w,
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < NV; ++i) cf[i] = (MODE > 0 && i < nv) ? c1[i] : 0.0;
+    // U consecutive grid-stride elements per iteration, all loads issued first
+    constexpr int U = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
-        const double we = w[e];
-        if (MODE == 0) {
+    for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N; e0 += U * stride) {
+        double we[U];
+        double vv[U][NV];
 #pragma unroll
-            for (int i = 0; i < NV; ++i)
-                if (i < nv) acc[i] += V[i][e] * we;
-        } else {
-            double vv[NV];
-            double s = we;
+        for (int u = 0; u < U; ++u) {
+            const size_t e = e0 + u * stride;
+            const bool in = e < N;
+            we[u] = in ? w[e] : 0.0;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                vv[i] = (i < nv) ? V[i][e] : 0.0;
-                s -= vv[i] * cf[i];
-            }
-            if (MODE == 1) {
+            for (int i = 0; i < NV; ++i) vv[u][i] = (in && i < nv) ? V[i][e] : 0.0;
+        }
 #pragma unroll
-                for (int i = 0; i < NV; ++i)
-                    if (i < nv) acc[i] += vv[i] * s;
-                acc[NV] += s * s;
+        for (int u = 0; u < U; ++u) {
+            const size_t e = e0 + u * stride;
+            if (MODE == 0) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) acc[i] += vv[u][i] * we[u];
             } else {
-                out[e] = s;
-                acc[0] += s * s;
+                double s = we[u];
+#pragma unroll
+                for (int i = 0; i < NV; ++i) s -= vv[u][i] * cf[i];
+                if (MODE == 1) {
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) acc[i] += vv[u][i] * s;
+                    acc[NV] += s * s;
+                } else {
+                    if (e < N) out[e] = s;
+                    acc[0] += s * s;
+                }
             }
         }
     }
@@ -176,11 +185,22 @@ hipError_t launch_reduce_parts(const double *part, int nblk, int ldp, int cnt, d
 __global__ void k_multi_axpy(const double *const *__restrict__ Z, int nz,
                              const double *__restrict__ y, double *__restrict__ x, size_t N)
 {
+    constexpr int U = 4;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride) {
-        double s = x[e];
-        for (int i = 0; i < nz; ++i) s += Z[i][e] * y[i];
-        x[e] = s;
+    for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N; e0 += U * stride) {
+        double s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s[u] = (e0 + u * stride < N) ? x[e0 + u * stride] : 0.0;
+        for (int i = 0; i < nz; ++i) {
+            const double yi = y[i];
+            const double *zi = Z[i];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (e0 + u * stride < N) s[u] += zi[e0 + u * stride] * yi;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * stride < N) x[e0 + u * stride] = s[u];
     }
 }
 
@@ -237,9 +257,19 @@ k_dot1(const double *__restrict__ a, const double *__restrict__ b, size_t N,
 {
     __shared__ double red[2 * 16];
     double acc[1] = {0.0};
+    constexpr int U = 4;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < N; e += stride)
-        acc[0] += a[e] * b[e];
+    for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N; e0 += U * stride) {
+        double av[U], bv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t e = e0 + u * stride;
+            av[u] = e < N ? a[e] : 0.0;
+            bv[u] = e < N ? b[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[0] += av[u] * bv[u];
+    }
     block_reduce_store<1>(acc, 1, part, 1, red);
 }
 
@@ -253,43 +283,68 @@ hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double 
 // -------------------------------------------------------- matvec (Sec. 2)
 // y_k = sum_{m=0}^{s} (a_m M + b_m^{(k)} kappa K) x_{k-m}   (x_{k+m} if transposed)
 // with b_0^{(k)} = tau_k when variable steps are given.  y = bsub - A x if bsub.
+//
+// Each thread owns one spatial column and walks MV_ROWS consecutive time levels,
+// keeping the last s+1 input rows in registers, so every input element is read
+// once from memory (plus s halo rows per block); the i +- 1 neighbours are
+// served by the cache lines the same wave instruction already brings in.
+constexpr int MV_ROWS = 16;
+
 __global__ void __launch_bounds__(256)
 k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
          int n, int ell, Scheme sc, double kappa, const double *__restrict__ tau_k, int transpose)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
     if (i >= n) return;
     const double h = 1.0 / (n + 1.0);
-    double al = 0.0, ac = 0.0, ar = 0.0, bl = 0.0, bc = 0.0, br = 0.0;
-    for (int m = 0; m <= sc.s; ++m) {
-        const int src = transpose ? k + m : k - m;
-        if (src < 0 || src >= ell) continue;
-        const double am = sc.a[m];
-        double bm = sc.b[m];
-        if (m == 0 && tau_k) bm = tau_k[k];
-        bm *= kappa;
-        const double *xr = x + (size_t)src * n;
-        const double xc = xr[i];
-        const double xl = i > 0 ? xr[i - 1] : 0.0;
-        const double xrr = i < n - 1 ? xr[i + 1] : 0.0;
-        al += am * xl;
-        ac += am * xc;
-        ar += am * xrr;
-        bl += bm * xl;
-        bc += bm * xc;
-        br += bm * xrr;
+    const int k0 = blockIdx.y * MV_ROWS;
+    const int k1 = min(k0 + MV_ROWS, ell);          // output rows [k0, k1)
+    const int s = sc.s;
+    const int nin = (k1 - k0) + s;                  // input rows touched by the block
+    // every input row of the block is loaded before any output is formed, so all
+    // loads of a lane are in flight together; the i +- 1 loads hit the same lines
+    constexpr int NR = MV_ROWS + 3;
+    double rl[NR], rc[NR], rr[NR];
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+        const int kk = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
+        const bool in = it < nin && kk >= 0 && kk < ell;
+        const double *row = x + (size_t)(in ? kk : 0) * n;
+        rc[it] = in ? row[i] : 0.0;
+        rl[it] = (in && i > 0) ? row[i - 1] : 0.0;
+        rr[it] = (in && i + 1 < n) ? row[i + 1] : 0.0;
     }
-    const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
-    const size_t o = (size_t)k * n + i;
-    y[o] = bsub ? bsub[o] - v : v;
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+        if (it < s || it >= nin) continue;
+        // output row k; input row k -+ m sits at it - m
+        const int k = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
+        double al = 0.0, ac = 0.0, ar = 0.0, bl = 0.0, bc = 0.0, br = 0.0;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (m > s || it - m < 0) break;
+            const double am = sc.a[m];
+            double bm = sc.b[m];
+            if (m == 0 && tau_k) bm = tau_k[k];
+            bm *= kappa;
+            al += am * rl[it - m];
+            ac += am * rc[it - m];
+            ar += am * rr[it - m];
+            bl += bm * rl[it - m];
+            bc += bm * rc[it - m];
+            br += bm * rr[it - m];
+        }
+        const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
+        const size_t o = (size_t)k * n + i;
+        y[o] = bsub ? bsub[o] - v : v;
+    }
 }
 
 hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
                          Scheme sc, double kappa, const double *tau_k, int transpose,
                          hipStream_t st)
 {
-    dim3 grid((n + 255) / 256, ell);
+    dim3 grid((n + 255) / 256, (ell + MV_ROWS - 1) / MV_ROWS);
     k_matvec<<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, tau_k, transpose);
     return hipGetLastError();
 }
