@@ -163,6 +163,18 @@ aao_status aao_adjoint_solve(aao_ctx ctx, const double *g, double *lam, int rest
 aao_status aao_grad(aao_ctx ctx, const double *u0, const double *v0, const double *U,
                     const double *lam, double *g_u0, double *g_v0, double *g_kappa);
 
+/* Gradient with the forward trajectory checkpointed over time (heat scheme):
+ * Uck (device) holds rows stride-1, 2*stride-1, ... of U (floor(ell/stride) rows
+ * of n doubles; may be NULL when stride >= ell).  The levels in between are
+ * recomputed by sequential implicit Euler steps (eq. timestepproblem1) from the
+ * nearest earlier checkpoint (or u0), one workgroup per segment, while the kappa
+ * reduction of aao_grad runs, so U is never stored whole: memory O(n ell/stride).
+ * g_u0 (device, n) = M lam_1; g_kappa (host, may be NULL); U_out (device ell x n,
+ * may be NULL) receives the recomputed trajectory.  AAO_ERR_UNSUPPORTED for BD2. */
+aao_status aao_grad_checkpointed(aao_ctx ctx, const double *u0, const double *Uck, int stride,
+                                 const double *lam, double *g_u0, double *g_kappa,
+                                 double *U_out);
+
 /* Per-kernel timing, for measurement.  aao_set_timing(ctx, 1) clears the
  * accumulators and brackets every later kernel launch of the context with a pair
  * of HIP events on the context stream; aao_get_timing synchronises the stream and

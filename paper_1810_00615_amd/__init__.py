@@ -8,5 +8,6 @@ include/aao.h; this package is its Python binding (torch supplies memory and
 streams).
 """
 from .api import BD2, HEAT, AAOError, Problem  # noqa: F401
+from .autograd import AllAtOnceSolve, all_at_once_solve  # noqa: F401
 
-__all__ = ["Problem", "AAOError", "HEAT", "BD2"]
+__all__ = ["Problem", "AAOError", "HEAT", "BD2", "AllAtOnceSolve", "all_at_once_solve"]

@@ -45,6 +45,8 @@ SIGNATURES = {
                           ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)],
     "aao_grad": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, _c_double_p],
+    "aao_grad_checkpointed": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                              ctypes.c_void_p, ctypes.c_void_p, _c_double_p, ctypes.c_void_p],
     "aao_set_timing": [ctypes.c_void_p, ctypes.c_int],
     "aao_get_timing": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                        ctypes.POINTER(ctypes.c_int64)],

@@ -186,6 +186,18 @@ class Problem:
         d["status"] = st
         return lam, d
 
+    def grad_checkpointed(self, u0, Uck, stride, lam, want_kappa=True, recompute_out=None):
+        """(g_u0, g_kappa) from checkpoint rows Uck = U[stride-1::stride] (heat); the
+        trajectory between checkpoints is recomputed on the device."""
+        gu = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        gk = ctypes.c_double(0.0)
+        self._stream()
+        self._c(self._L.aao_grad_checkpointed(
+            self._ctx, _ptr(u0), _ptr(Uck) if Uck is not None and Uck.numel() else None,
+            int(stride), _ptr(lam), _ptr(gu), ctypes.byref(gk) if want_kappa else None,
+            _ptr(recompute_out)), "aao_grad_checkpointed")
+        return gu, (gk.value if want_kappa else None)
+
     def set_timing(self, enable: bool = True):
         """Bracket every kernel launch with HIP events (clears the accumulators)."""
         self._c(self._L.aao_set_timing(self._ctx, int(enable)), "aao_set_timing")

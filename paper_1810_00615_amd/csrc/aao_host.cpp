@@ -64,6 +64,8 @@ struct aao_ctx_s {
     int *dmodes = nullptr;
     double *damps = nullptr;
     int nmodes_alloc = 0;
+    double *segpart = nullptr;   // per-segment partials of the checkpointed gradient
+    int nseg_alloc = 0;
 
     // per-kernel timing (aao_set_timing): event pairs recorded around launches
     bool timing = false;
@@ -477,6 +479,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->tmpn);
     (void)hipFree(ctx->dmodes);
     (void)hipFree(ctx->damps);
+    (void)hipFree(ctx->segpart);
     delete ctx;
     return AAO_OK;
 }
@@ -667,6 +670,49 @@ aao_status aao_grad(aao_ctx ctx, const double *u0, const double *v0, const doubl
             gk += t;
         }
         *g_kappa = gk;
+    } else {
+        AAO_HIP(hipStreamSynchronize(st));
+    }
+    return AAO_OK;
+}
+
+aao_status aao_grad_checkpointed(aao_ctx ctx, const double *u0, const double *Uck, int stride,
+                                 const double *lam, double *g_u0, double *g_kappa, double *U_out)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (ctx->scheme != AAO_HEAT_IE) {
+        ctx->err = "checkpointed gradients are implemented for the heat scheme";
+        return AAO_ERR_UNSUPPORTED;
+    }
+    if (stride < 1 || !u0 || !lam || !g_u0) return arg_err(ctx, "bad checkpoint arguments");
+    if (ctx->ell > stride && !Uck) return arg_err(ctx, "checkpoint rows missing");
+    const int n = (int)ctx->n, ell = (int)ctx->ell;
+    hipStream_t st = ctx->st;
+    AAO_HIP(launch_mk(lam, 1.0, 0.0, nullptr, 0.0, 0.0, g_u0, n, st));
+    if (g_kappa || U_out) {
+        const int nseg = (ell + stride - 1) / stride;
+        if (nseg > ctx->nseg_alloc) {
+            (void)hipFree(ctx->segpart);
+            ctx->segpart = nullptr;
+            ctx->nseg_alloc = 0;
+            AAO_TRY(dev_alloc(ctx, (void **)&ctx->segpart, sizeof(double) * nseg));
+            ctx->nseg_alloc = nseg;
+        }
+        AAO_HIP(hipMemsetAsync(ctx->fail, 0, sizeof(int), st));
+        AAO_HIP(launch_heat_segments(u0, Uck, stride, lam, n, ell, ctx->tau, ctx->kappa, ctx->tauk,
+                                     ctx->segpart, U_out, ctx->fail, st));
+        AAO_HIP(launch_reduce_parts(ctx->segpart, nseg, 1, 1, ctx->sd(), st));
+        double s = 0.0;
+        int failed = 0;
+        AAO_HIP(hipMemcpyAsync(&s, ctx->sd(), sizeof(double), hipMemcpyDeviceToHost, st));
+        AAO_HIP(hipMemcpyAsync(&failed, ctx->fail, sizeof(int), hipMemcpyDeviceToHost, st));
+        AAO_HIP(hipStreamSynchronize(st));
+        if (failed) {
+            ctx->err = "non-finite value while recomputing the trajectory";
+            return AAO_ERR_NUMERIC;
+        }
+        if (g_kappa) *g_kappa = -s;
     } else {
         AAO_HIP(hipStreamSynchronize(st));
     }

@@ -56,6 +56,11 @@ hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool sin
                                 int n, int ell, Scheme sc, double kappa, int transpose,
                                 int *fail_flag, hipStream_t st);
 bool fft_supported_fast(int ell);
+// Heat trajectory recomputed from checkpoints (every `stride` rows) while
+// accumulating part[seg] = sum_k tau_k lam_k . K u_k over each segment.
+hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride, const double *lam,
+                                int n, int ell, double tau, double kappa, const double *tau_k,
+                                double *part, double *Uout, int *fail, hipStream_t st);
 
 // y = A x (or A^T x); with tau_k != nullptr the variable-step matrix B.
 // If bsub != nullptr computes y = bsub - A x.

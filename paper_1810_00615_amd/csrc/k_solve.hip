@@ -22,57 +22,25 @@
 
 namespace aao {
 
-template <typename S> struct Store;
-template <> struct Store<double> { using C = cx<double>; };
-template <> struct Store<float> { using C = cx<float>; };
-
-template <typename A, typename S, int CW, int NTB>
-__global__ void __launch_bounds__(NTB)
-k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, double kappa,
-                int transpose, int *__restrict__ fail)
+// Partition solve of tridiag(e, d, e) x = r with n unknowns by one workgroup.
+// Thread t owns unknowns [t*CW, t*CW + len); y[] holds its part of r on entry and
+// of x on exit.  s_ip / s_cp: CW entries of LDS each; red: 7*NT entries of LDS
+// (may alias a staging area the caller has finished reading: the first barrier
+// below precedes every write to it, and the last barrier follows every read).
+// Every thread of the block must call it.  Returns true if a value is not finite.
+template <typename A, int CW>
+__device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *s_ip,
+                                cx<A> *s_cp, cx<A> *red)
 {
-    extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
-    cx<A> *s_ip = reinterpret_cast<cx<A> *>(smraw);   // 1/pivot of the interior elimination
-    cx<A> *s_cp = s_ip + CW;                            // e / pivot
-    // The row is staged through LDS so that global accesses are coalesced while
-    // each thread works on CW contiguous unknowns.  Element i of chunk t sits in
-    // slot i*(NT+PAD) + t: the chunk reads (consecutive t) and the coalesced writes
-    // (8 consecutive lanes = one chunk) both spread over all banks with PAD = 2
-    // (16-byte elements) or 4 (8-byte elements).  The reduced-system arrays reuse
-    // the same space once the chunks are in registers.
-    cx<S> *stage = reinterpret_cast<cx<S> *>(s_cp + CW);
-    cx<A> *pa = reinterpret_cast<cx<A> *>(s_cp + CW);  // reduced system: lower
-    cx<A> *pb = pa + NT;                                // diagonal
-    cx<A> *pc = pb + NT;                                // upper
-    cx<A> *pd = pc + NT;                                // right-hand side
-    cx<A> *nb = pd + NT;                                // contributions to equation c-1 (3 per chunk)
-
-    const int j = blockIdx.x;
     const int t = threadIdx.x;
-    cx<S> *row = spec + (size_t)j * lds;
-
-    // symbol of frequency j
-    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-    for (int m = 0; m <= sc.s; ++m) {
-        const long long p = ((long long)j * m) % ell;
-        double sn, cs;
-        sincospi((transpose ? 2.0 : -2.0) * (double)p / (double)ell, &sn, &cs);
-        ar += sc.a[m] * cs;
-        ai += sc.a[m] * sn;
-        br += sc.b[m] * cs;
-        bi += sc.b[m] * sn;
-    }
-    const double h = 1.0 / (n + 1.0);
-    const cx<A> d = {A(ar * (4.0 * h / 6.0) + br * kappa * (2.0 / h)),
-                     A(ai * (4.0 * h / 6.0) + bi * kappa * (2.0 / h))};
-    const cx<A> e = {A(ar * (h / 6.0) - br * kappa / h), A(ai * (h / 6.0) - bi * kappa / h)};
-
+    cx<A> *pa = red, *pb = red + NT, *pc = red + 2 * NT, *pd = red + 3 * NT, *nb = red + 4 * NT;
+    const cx<A> zero = {A(0), A(0)};
+    const cx<A> me = {-e.x, -e.y};
     if (t == 0) {
-        cx<A> cprev = {A(0), A(0)};
+        cx<A> cprev = zero;
         for (int i = 0; i < CW - 1; ++i) {
-            const cx<A> piv = d - e * cprev;
-            const cx<A> ip = recip(piv);
+            const cx<A> ip = recip(d - e * cprev);
             s_ip[i] = ip;
             cprev = e * ip;
             s_cp[i] = cprev;
@@ -85,32 +53,16 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
     const int len = (t < P) ? min(CW, n - a0) : 0;
     const int mi = len - 1;                              // interior length (may be 0)
 
-    constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
-    const int NTP = NT + PAD;
-    for (int e = t; e < n; e += NT) stage[(e % CW) * NTP + e / CW] = row[e];
-    __syncthreads();
-    cx<A> y[CW], u[CW];
+    cx<A> u[CW];
+    cx<A> rsep = zero;
 #pragma unroll
     for (int i = 0; i < CW; ++i) {
-        if (i < len) {
-            const cx<S> v = stage[i * NTP + t];
-            y[i] = {A(v.x), A(v.y)};
-        } else {
-            y[i] = {A(0), A(0)};
-        }
-        u[i] = {A(0), A(0)};
-    }
-    __syncthreads();   // the staging area is reused for the reduced system
-    cx<A> rsep = {A(0), A(0)};
-#pragma unroll
-    for (int i = 0; i < CW; ++i)
+        u[i] = zero;
         if (i == mi) rsep = y[i];
-    const cx<A> me = {-e.x, -e.y};
-    const cx<A> zero = {A(0), A(0)};
-
+    }
     // forward elimination of the interior: particular solution y and the
     // response u to the left separator (right-hand side -e at interior 0)
-    cx<A> gy = {A(0), A(0)}, gu = {A(0), A(0)};
+    cx<A> gy = zero, gu = zero;
 #pragma unroll
     for (int i = 0; i < CW - 1; ++i) {
         if (i < mi) {
@@ -122,7 +74,7 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
         }
     }
     // back substitution; v (response to the right separator) only at its ends
-    cx<A> vlast = {A(0), A(0)}, vfirst = {A(0), A(0)};
+    cx<A> vlast = zero, vfirst = zero;
     if (mi > 0) {
         vlast = me * s_ip[mi - 1];
         vfirst = vlast;
@@ -219,7 +171,7 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
         XL = (t > 0) ? pd[t - 1] : zero;
         XR = pd[t];
     }
-    __syncthreads();   // staging area becomes the output buffer again
+    __syncthreads();   // the caller may reuse `red` from here on
     // interior: x_i = y_i + u_i XL + v_i XR, v from the back
     bool bad = false;
     if (t < P) {
@@ -228,16 +180,77 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
         for (int i = CW - 2; i >= 0; --i) {
             if (i < mi) {
                 if (i < mi - 1) vi = zero - s_cp[i] * vi;
-                const cx<A> x = y[i] + u[i] * XL + vi * XR;
-                bad |= !(isfinite((double)x.x) && isfinite((double)x.y));
-                stage[i * NTP + t] = {S(x.x), S(x.y)};
+                y[i] = y[i] + u[i] * XL + vi * XR;
+                bad |= !(isfinite((double)y[i].x) && isfinite((double)y[i].y));
             }
         }
+#pragma unroll
+        for (int i = 0; i < CW; ++i)
+            if (i == mi) y[i] = XR;
         bad |= !(isfinite((double)XR.x) && isfinite((double)XR.y));
-        stage[(len - 1) * NTP + t] = {S(XR.x), S(XR.y)};
     }
+    return bad;
+}
+
+template <typename A, typename S, int CW, int NTB>
+__global__ void __launch_bounds__(NTB)
+k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, double kappa,
+                int transpose, int *__restrict__ fail)
+{
+    extern __shared__ unsigned char smraw[];
+    const int NT = blockDim.x;
+    cx<A> *s_ip = reinterpret_cast<cx<A> *>(smraw);   // 1/pivot of the interior elimination
+    cx<A> *s_cp = s_ip + CW;                            // e / pivot
+    // The row is staged through LDS so that global accesses are coalesced while
+    // each thread works on CW contiguous unknowns.  Element i of chunk t sits in
+    // slot i*(NT+PAD) + t: the chunk reads (consecutive t) and the coalesced writes
+    // (CW consecutive lanes = one chunk) both spread over all banks with PAD = 2
+    // (16-byte elements) or 4 (8-byte elements).  The reduced-system arrays reuse
+    // the same space once the chunks are in registers.
+    cx<S> *stage = reinterpret_cast<cx<S> *>(s_cp + CW);
+    cx<A> *red = reinterpret_cast<cx<A> *>(s_cp + CW);
+
+    const int j = blockIdx.x;
+    const int t = threadIdx.x;
+    cx<S> *row = spec + (size_t)j * lds;
+
+    // symbol of frequency j
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    for (int m = 0; m <= sc.s; ++m) {
+        const long long p = ((long long)j * m) % ell;
+        double sn, cs;
+        sincospi((transpose ? 2.0 : -2.0) * (double)p / (double)ell, &sn, &cs);
+        ar += sc.a[m] * cs;
+        ai += sc.a[m] * sn;
+        br += sc.b[m] * cs;
+        bi += sc.b[m] * sn;
+    }
+    const double h = 1.0 / (n + 1.0);
+    const cx<A> d = {A(ar * (4.0 * h / 6.0) + br * kappa * (2.0 / h)),
+                     A(ai * (4.0 * h / 6.0) + bi * kappa * (2.0 / h))};
+    const cx<A> e = {A(ar * (h / 6.0) - br * kappa / h), A(ai * (h / 6.0) - bi * kappa / h)};
+
+    constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
+    const int NTP = NT + PAD;
+    const int P = (n + CW - 1) / CW;
+    const int len = (t < P) ? min(CW, n - t * CW) : 0;
+    for (int q = t; q < n; q += NT) stage[(q % CW) * NTP + q / CW] = row[q];
     __syncthreads();
-    for (int e = t; e < n; e += NT) row[e] = stage[(e % CW) * NTP + e / CW];
+    cx<A> y[CW];
+#pragma unroll
+    for (int i = 0; i < CW; ++i) {
+        y[i] = {A(0), A(0)};
+        if (i < len) {
+            const cx<S> v = stage[i * NTP + t];
+            y[i] = {A(v.x), A(v.y)};
+        }
+    }
+    const bool bad = partition_solve<A, CW>(y, n, d, e, s_ip, s_cp, red);
+#pragma unroll
+    for (int i = 0; i < CW; ++i)
+        if (i < len) stage[i * NTP + t] = {S(y[i].x), S(y[i].y)};
+    __syncthreads();
+    for (int q = t; q < n; q += NT) row[q] = stage[(q % CW) * NTP + q / CW];
     if (bad && fail) atomicOr(fail, 1);
 }
 
@@ -280,6 +293,139 @@ static hipError_t solve_disp(void *spec, int lds, int n, int ell, Scheme sc, dou
     }
     if (cw <= 8) return go(k_shifted_solve<A, S, 8, 1024>);
     return go(k_shifted_solve<A, S, 16, 1024>);
+}
+
+// ------------------------------------------------- checkpoint recomputation
+// Heat trajectory between checkpoints, for the kappa gradient.  Segment s covers
+// time levels [s*stride, min((s+1)*stride, ell)) (0-based rows); it starts from
+// u0 (s = 0) or the stored row s*stride - 1 and takes implicit Euler steps
+// (M + tau_k kappa K) u_k = M u_{k-1} (eq. timestepproblem1 read as M + tau K), each
+// step a partition solve by the whole workgroup.  While stepping it accumulates
+// sum_k tau_k lam_k . (K u_k), the term of dL/dkappa that needs U.
+template <int CW>
+__global__ void __launch_bounds__(256)
+k_heat_segments(const double *__restrict__ u0, const double *__restrict__ Uck, int stride,
+                const double *__restrict__ lam, int n, int ell, double tau, double kappa,
+                const double *__restrict__ tau_k, double *__restrict__ part,
+                double *__restrict__ Uout, int *__restrict__ fail)
+{
+    extern __shared__ unsigned char smraw[];
+    const int NT = blockDim.x;
+    const int t = threadIdx.x;
+    cx<double> *s_ip = reinterpret_cast<cx<double> *>(smraw);
+    cx<double> *s_cp = s_ip + CW;
+    cx<double> *red = s_cp + CW;                            // 7*NT entries
+    double *edge = reinterpret_cast<double *>(red + 7 * NT); // first/last value of every chunk
+    __shared__ double wsum[16];
+
+    const int seg = blockIdx.x;
+    const int kb = seg * stride;
+    const int ke = min(kb + stride, ell);
+    const double *start = seg == 0 ? u0 : Uck + (size_t)(seg - 1) * n;
+    const double h = 1.0 / (n + 1.0);
+    const int a0 = t * CW;
+    const int P = (n + CW - 1) / CW;
+    const int len = (t < P) ? min(CW, n - a0) : 0;
+
+    double u[CW];
+#pragma unroll
+    for (int i = 0; i < CW; ++i) u[i] = (i < len) ? start[a0 + i] : 0.0;
+
+    // neighbours of the chunk ends through LDS: (left of first, right of last)
+    auto halo = [&](double &left, double &right) {
+        double first = 0.0, last = 0.0;
+#pragma unroll
+        for (int i = 0; i < CW; ++i) {
+            if (i == 0) first = u[i];
+            if (i == len - 1) last = u[i];
+        }
+        if (t < P) {
+            edge[2 * t] = first;
+            edge[2 * t + 1] = last;
+        }
+        __syncthreads();
+        left = (t > 0 && t < P) ? edge[2 * (t - 1) + 1] : 0.0;
+        right = (t + 1 < P) ? edge[2 * (t + 1)] : 0.0;
+        __syncthreads();
+    };
+
+    double acc = 0.0;
+    bool bad = false;
+    for (int k = kb; k < ke; ++k) {
+        const double tk = tau_k ? tau_k[k] : tau;
+        // right-hand side M u_{k-1}
+        double left, right;
+        halo(left, right);
+        cx<double> y[CW];
+#pragma unroll
+        for (int i = 0; i < CW; ++i) {
+            const double ul = (i == 0) ? left : u[i > 0 ? i - 1 : 0];
+            const double ur = (i == len - 1) ? right : u[i < CW - 1 ? i + 1 : CW - 1];
+            y[i] = {(i < len) ? (h / 6.0) * (ul + 4.0 * u[i] + ur) : 0.0, 0.0};
+        }
+        const cx<double> d = {4.0 * h / 6.0 + tk * kappa * 2.0 / h, 0.0};
+        const cx<double> e = {h / 6.0 - tk * kappa / h, 0.0};
+        bad |= partition_solve<double, CW>(y, n, d, e, s_ip, s_cp, red);
+#pragma unroll
+        for (int i = 0; i < CW; ++i) u[i] = (i < len) ? y[i].x : 0.0;
+        if (Uout) {
+#pragma unroll
+            for (int i = 0; i < CW; ++i)
+                if (i < len) Uout[(size_t)k * n + a0 + i] = u[i];
+        }
+        // tau_k lam_k . K u_k
+        halo(left, right);
+        const double *lk = lam + (size_t)k * n;
+#pragma unroll
+        for (int i = 0; i < CW; ++i) {
+            if (i < len) {
+                const double ul = (i == 0) ? left : u[i > 0 ? i - 1 : 0];
+                const double ur = (i == len - 1) ? right : u[i < CW - 1 ? i + 1 : CW - 1];
+                acc += tk * lk[a0 + i] * (2.0 * u[i] - ul - ur) / h;
+            }
+        }
+    }
+    // block sum in a fixed order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((t & 63) == 0) wsum[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+        double sacc = 0.0;
+        for (int w = 0; w < NT / 64; ++w) sacc += wsum[w];
+        part[seg] = sacc;
+    }
+    if (bad && fail) atomicOr(fail, 1);
+}
+
+hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride, const double *lam,
+                                int n, int ell, double tau, double kappa, const double *tau_k,
+                                double *part, double *Uout, int *fail, hipStream_t st)
+{
+    const int NT = 256;
+    int cw = 1;
+    while (cw * NT < n) cw *= 2;
+    if (cw > 16) return hipErrorInvalidValue;
+    const int nseg = (ell + stride - 1) / stride;
+    const size_t smem = sizeof(cx<double>) * (2 * (size_t)cw + 7 * NT) + sizeof(double) * 2 * NT;
+    auto go = [&](auto kern) -> hipError_t {
+        if (smem > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)smem);
+            if (e != hipSuccess) return e;
+        }
+        kern<<<nseg, NT, smem, st>>>(u0, Uck, stride, lam, n, ell, tau, kappa, tau_k, part, Uout,
+                                     fail);
+        return hipGetLastError();
+    };
+    switch (cw) {
+    case 1: return go(k_heat_segments<1>);
+    case 2: return go(k_heat_segments<2>);
+    case 4: return go(k_heat_segments<4>);
+    case 8: return go(k_heat_segments<8>);
+    default: return go(k_heat_segments<16>);
+    }
 }
 
 hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
