@@ -193,6 +193,44 @@ enum {
 aao_status aao_set_timing(aao_ctx ctx, int enable);
 aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count);
 
+/* ------------------------------------------------------------------ batch
+ * Many independent problems of uneven size advanced together: every phase of an
+ * Arnoldi step is one launch over a work table spanning all problems, converged
+ * problems are masked out on the device, and the launch sequence of each
+ * Arnoldi step is captured once into a hipGraph and replayed.  Batch vectors
+ * concatenate the ell_p x n_p arrays of the problems at the offsets returned by
+ * aao_batch_offsets (aligned to 64 elements); per-node vectors (u0)
+ * concatenate the n_p-vectors without gaps.  The transform along time uses
+ * Bluestein's chirp-z form for any ell_p (power-of-two convolution length
+ * M_p >= 2 ell_p - 1), so ell_p need not be smooth.  Limits: 1 <= n_p <= 4096,
+ * 2 <= ell_p <= 2048.  The batch owns its own HIP stream. */
+typedef struct aao_batch_s *aao_batch;
+
+/* count problems; n, ell, kappa: host arrays of count entries; tau: host array or
+ * NULL (tau_p = 1/ell_p); scheme as aao_create; prec as aao_set_precision
+ * (AAO_PREC_MIXED: single-precision transforms/spectra, FP64 solves and outer
+ * GMRES). */
+aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, const double *tau,
+                            const double *kappa, int scheme, int prec, aao_batch *out);
+aao_status aao_batch_destroy(aao_batch b);
+/* offsets (host, count entries, may be NULL) and total length of a batch vector */
+aao_status aao_batch_offsets(aao_batch b, int64_t *offsets, int64_t *total);
+/* hipGraph replay of the Arnoldi steps on (1, default) or off (0, eager launches) */
+aao_status aao_batch_set_graph(aao_batch b, int enable);
+/* u0 (device, sum n_p) = L2 projections of sum_q amps[p*J + q] sin(modes[q] pi x) */
+aao_status aao_batch_project_sine(aao_batch b, int J, const int *modes, const double *amps,
+                                  double *u0);
+/* batch right-hand side from the concatenated u0 (heat: b_1 = M u0 per problem) */
+aao_status aao_batch_build_rhs(aao_batch b, const double *u0, double *bvec);
+aao_status aao_batch_apply_A(aao_batch b, const double *x, double *y, int transpose);
+aao_status aao_batch_apply_Pinv(aao_batch b, const double *r, double *z, int transpose);
+/* FGMRES(restart) on every problem to tol (true relative residual per problem);
+ * x: initial guess in, solutions out; infos: host array of count entries or NULL.
+ * AAO_OK when every problem converged, AAO_NOT_CONVERGED otherwise. */
+aao_status aao_batch_gmres(aao_batch b, const double *bvec, double *x, int restart, double tol,
+                           int maxit, aao_info *infos);
+const char *aao_batch_last_error(aao_batch b);
+
 /* Text of a status code (static storage). */
 const char *aao_status_string(aao_status st);
 

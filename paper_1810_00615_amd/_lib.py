@@ -50,10 +50,25 @@ SIGNATURES = {
     "aao_set_timing": [ctypes.c_void_p, ctypes.c_int],
     "aao_get_timing": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                        ctypes.POINTER(ctypes.c_int64)],
+    "aao_batch_create": [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                         ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                         ctypes.POINTER(ctypes.c_void_p)],
+    "aao_batch_destroy": [ctypes.c_void_p],
+    "aao_batch_offsets": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
+    "aao_batch_set_graph": [ctypes.c_void_p, ctypes.c_int],
+    "aao_batch_project_sine": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p],
+    "aao_batch_build_rhs": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+    "aao_batch_apply_A": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "aao_batch_apply_Pinv": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
+    "aao_batch_gmres": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                        ctypes.c_double, ctypes.c_int, ctypes.c_void_p],
+    "aao_batch_last_error": [ctypes.c_void_p],
     "aao_status_string": [ctypes.c_int],
     "aao_last_error": [ctypes.c_void_p],
 }
-_RET = {"aao_status_string": ctypes.c_char_p, "aao_last_error": ctypes.c_char_p}
+_RET = {"aao_status_string": ctypes.c_char_p, "aao_last_error": ctypes.c_char_p,
+        "aao_batch_last_error": ctypes.c_char_p}
 
 _lib = None
 

@@ -225,3 +225,121 @@ class Problem:
 
 
 __all__ = ["Problem", "AAOError", "HEAT", "BD2"]
+
+
+class Batch:
+    """Many independent all-at-once problems of uneven size solved together
+    (one launch per phase over all problems, hipGraph replay per Arnoldi step).
+
+    A batch vector is a 1-D float64 tensor holding problem p's (ell_p, n_p) array at
+    ``offsets[p]``; ``views(vec)`` returns those (ell_p, n_p) views."""
+
+    def __init__(self, ns, ells, kappas, taus=None, scheme="heat", precision="mixed",
+                 device="cuda"):
+        self.ns = np.ascontiguousarray(np.asarray(ns, dtype=np.int64))
+        self.ells = np.ascontiguousarray(np.asarray(ells, dtype=np.int64))
+        self.kappas = np.ascontiguousarray(np.asarray(kappas, dtype=np.float64))
+        self.taus = None if taus is None else np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
+        self.count = len(self.ns)
+        self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        self.device = torch.device(device)
+        self._L = lib()
+        self._b = ctypes.c_void_p()
+        p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        with torch.cuda.device(self.device):
+            st = self._L.aao_batch_create(self.count, p(self.ns), p(self.ells), p(self.taus),
+                                          p(self.kappas), self.scheme, PRECISIONS[precision],
+                                          ctypes.byref(self._b))
+        check(st, "aao_batch_create")
+        self.offsets = np.zeros(self.count, dtype=np.int64)
+        tot = ctypes.c_int64(0)
+        self._c(self._L.aao_batch_offsets(self._b, p(self.offsets), ctypes.byref(tot)),
+                "aao_batch_offsets")
+        self.total = int(tot.value)
+        self.u_offsets = np.concatenate([[0], np.cumsum(self.ns)[:-1]]).astype(np.int64)
+
+    def _c(self, st, where):
+        if st < 0:
+            detail = self._L.aao_batch_last_error(self._b).decode()
+            raise AAOError(st, where, detail)
+        return st
+
+    def close(self):
+        if self._b:
+            self._L.aao_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_in(self):
+        # inputs written on torch's stream must land before the batch stream reads them
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def empty(self):
+        return torch.empty(self.total, dtype=torch.float64, device=self.device)
+
+    def zeros(self):
+        return torch.zeros(self.total, dtype=torch.float64, device=self.device)
+
+    def views(self, vec):
+        return [vec[o:o + int(n) * int(l)].view(int(l), int(n))
+                for o, n, l in zip(self.offsets, self.ns, self.ells)]
+
+    def pack(self, arrays):
+        vec = self.zeros()
+        for v, a in zip(self.views(vec), arrays):
+            v.copy_(torch.as_tensor(a, dtype=torch.float64, device=self.device).view(v.shape))
+        return vec
+
+    def set_graph(self, enable: bool):
+        self._c(self._L.aao_batch_set_graph(self._b, int(enable)), "aao_batch_set_graph")
+
+    def project_sine(self, modes, amps):
+        """u0 for every problem (concatenated n_p-vectors); amps: (count, J)."""
+        modes = np.ascontiguousarray(np.asarray(modes, dtype=np.int32))
+        amps = np.ascontiguousarray(np.asarray(amps, dtype=np.float64))
+        assert amps.shape == (self.count, len(modes))
+        u0 = torch.empty(int(self.ns.sum()), dtype=torch.float64, device=self.device)
+        self._sync_in()
+        self._c(self._L.aao_batch_project_sine(self._b, len(modes),
+                                               modes.ctypes.data_as(ctypes.c_void_p),
+                                               amps.ctypes.data_as(ctypes.c_void_p), _ptr(u0)),
+                "aao_batch_project_sine")
+        return u0
+
+    def rhs(self, u0cat):
+        b = self.empty()
+        self._sync_in()
+        self._c(self._L.aao_batch_build_rhs(self._b, _ptr(u0cat), _ptr(b)), "aao_batch_build_rhs")
+        return b
+
+    def A(self, x, transpose=False):
+        y = self.zeros()
+        self._sync_in()
+        self._c(self._L.aao_batch_apply_A(self._b, _ptr(x), _ptr(y), int(transpose)),
+                "aao_batch_apply_A")
+        return y
+
+    def Pinv(self, r, transpose=False):
+        z = self.zeros()
+        self._sync_in()
+        self._c(self._L.aao_batch_apply_Pinv(self._b, _ptr(r), _ptr(z), int(transpose)),
+                "aao_batch_apply_Pinv")
+        return z
+
+    def solve(self, b, restart=30, tol=1e-8, maxit=300, x0=None, out=None):
+        x = out if out is not None else self.empty()
+        if x0 is None:
+            x.zero_()
+        else:
+            x.copy_(x0)
+        infos = (Info * self.count)()
+        self._sync_in()
+        st = self._L.aao_batch_gmres(self._b, _ptr(b), _ptr(x), int(restart), float(tol),
+                                     int(maxit), ctypes.cast(infos, ctypes.c_void_p))
+        self._c(st, "aao_batch_gmres")
+        return x, [i.as_dict() for i in infos], st

@@ -1,0 +1,574 @@
+// Host side of the batched form (declared in include/aao.h, aao_batch_*).
+//
+// A batch vector concatenates the ell_p x n_p arrays of all problems (offsets
+// aligned to 64 elements, see aao_batch_offsets).  Every phase of an Arnoldi
+// step is one launch over a work table that spans all problems; converged
+// problems are masked out on the device.  The launch sequence of Arnoldi step j
+// does not depend on the data, so it is captured once into a hipGraph and
+// replayed; the host reads one integer (the number of problems still active)
+// after each step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "../../include/aao.h"
+#include "aao_internal.h"
+#include "batch.h"
+
+using namespace aao;
+
+namespace {
+constexpr int kBMaxRestart = 63;
+constexpr int kBSmall = 72;     // doubles per problem in the small per-problem arrays
+}
+
+struct aao_batch_s {
+    int count = 0, scheme = 0, prec = AAO_PREC_MIXED;
+    std::vector<BProb> hp;
+    size_t Ntot = 0, Stot = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    bool use_graph = true;
+    std::string err;
+    bool broken = false;
+
+    BProb *probs = nullptr;
+    int2 *ftiles = nullptr, *rows = nullptr, *pslabs = nullptr;
+    int4 *mtiles = nullptr, *slabs = nullptr;
+    int nftiles = 0, nrows = 0, nmtiles = 0, nslabs = 0;
+    double *chirp = nullptr, *bhat = nullptr, *tw = nullptr;
+    void *spec = nullptr;
+    int *fail = nullptr;
+
+    // GMRES workspace and state
+    int m_alloc = 0;
+    double *V = nullptr, *Z = nullptr, *W = nullptr;
+    double **dV = nullptr, **dZ = nullptr;
+    double *part = nullptr;
+    int ldp = kBMaxRestart + 2;
+    double *sm = nullptr;           // small per-problem arrays
+    double *H = nullptr;
+    int *iv = nullptr;              // iters | ksteps | nact
+    unsigned char *flags = nullptr; // active | done | bad
+    BState bs{};
+    std::vector<hipGraphExec_t> graphs;
+    int graph_m = 0, graph_maxit = -1;
+    double graph_tol = -1.0;
+    double **dB = nullptr;           // one-entry pointer array for norms of the rhs
+
+    BatchLaunch launch(bool masked) const
+    {
+        BatchLaunch L;
+        L.probs = probs;
+        L.count = count;
+        L.ftiles = ftiles;
+        L.nftiles = nftiles;
+        L.rows = rows;
+        L.nrows = nrows;
+        L.mtiles = mtiles;
+        L.nmtiles = nmtiles;
+        L.slabs = slabs;
+        L.nslabs = nslabs;
+        L.pslabs = pslabs;
+        L.active = masked ? flags : nullptr;
+        L.chirp = chirp;
+        L.bhat = bhat;
+        L.tw = tw;
+        return L;
+    }
+};
+
+#define BH(call)                                                                          \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            b->err = std::string(#call) + ": " + hipGetErrorString(e_);                   \
+            b->broken = true;                                                             \
+            return AAO_ERR_HIP;                                                           \
+        }                                                                                 \
+    } while (0)
+
+#define BT(expr)                                                                          \
+    do {                                                                                  \
+        aao_status s_ = (expr);                                                           \
+        if (s_ < 0) return s_;                                                            \
+    } while (0)
+
+static aao_status balloc(aao_batch b, void **p, size_t bytes)
+{
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        b->err = "hipMalloc(" + std::to_string(bytes) + ") failed";
+        return AAO_ERR_ALLOC;
+    }
+    return AAO_OK;
+}
+
+template <typename T>
+static aao_status upload(aao_batch b, T **dst, const std::vector<T> &src)
+{
+    BT(balloc(b, (void **)dst, sizeof(T) * std::max<size_t>(src.size(), 1)));
+    if (!src.empty())
+        BH(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice));
+    return AAO_OK;
+}
+
+static void free_ws(aao_batch b)
+{
+    for (auto g : b->graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+    b->graphs.clear();
+    b->graph_m = 0;
+    (void)hipFree(b->V);
+    (void)hipFree(b->Z);
+    (void)hipFree(b->W);
+    (void)hipFree(b->dV);
+    (void)hipFree(b->dZ);
+    b->V = b->Z = b->W = nullptr;
+    b->dV = b->dZ = nullptr;
+    b->m_alloc = 0;
+}
+
+static aao_status ensure_ws(aao_batch b, int m)
+{
+    if (b->m_alloc >= m) return AAO_OK;
+    free_ws(b);
+    const size_t N = b->Ntot;
+    BT(balloc(b, (void **)&b->V, sizeof(double) * N * (m + 1)));
+    BT(balloc(b, (void **)&b->Z, sizeof(double) * N * m));
+    BT(balloc(b, (void **)&b->W, sizeof(double) * N));
+    std::vector<double *> hv(m + 1), hz(m);
+    for (int i = 0; i <= m; ++i) hv[i] = b->V + N * i;
+    for (int i = 0; i < m; ++i) hz[i] = b->Z + N * i;
+    BT(upload(b, &b->dV, hv));
+    BT(upload(b, &b->dZ, hz));
+    b->m_alloc = m;
+    return AAO_OK;
+}
+
+// ------------------------------------------------------------------ phases
+
+static aao_status b_pinv(aao_batch b, const double *r, const double *scales, int sstride, double *z,
+                         bool masked, int transpose)
+{
+    const bool single = b->prec != AAO_PREC_FP64;
+    const bool single_arith = b->prec == AAO_PREC_FP32;
+    const BatchLaunch L = b->launch(masked);
+    BH(batch_fft_fwd(L, r, scales, sstride, b->spec, single, b->st));
+    BH(batch_solve(L, b->spec, single, single_arith, b->scheme, transpose, b->fail, b->st));
+    BH(batch_fft_inv(L, b->spec, z, single, b->st));
+    return AAO_OK;
+}
+
+// One Arnoldi step j for every active problem (the sequence that is captured).
+static aao_status b_step(aao_batch b, int j, int m, double tol, int transpose)
+{
+    const size_t N = b->Ntot;
+    const BatchLaunch L = b->launch(true);
+    const int nv = j + 1;
+    BState &s = b->bs;
+    double *Vj = b->V + N * j, *Zj = b->Z + N * j, *Vn = b->V + N * (j + 1);
+    BT(b_pinv(b, Vj, s.vs + j, s.sst, Zj, true, transpose));
+    BH(batch_matvec(L, Zj, b->W, nullptr, b->scheme, transpose, true, b->st));
+    BH(batch_cgs(0, L, b->dV, nv, b->W, nullptr, 0, nullptr, b->part, b->ldp, true, b->st));
+    BH(batch_reduce(L, b->part, b->ldp, nv, s.dsum, s.sst, true, b->st));
+    BH(batch_small(0, b->count, j, m, tol, s, b->st));
+    BH(batch_cgs(1, L, b->dV, nv, b->W, s.coef, s.sst, nullptr, b->part, b->ldp, true, b->st));
+    BH(batch_reduce(L, b->part, b->ldp, nv, s.dsum, s.sst, true, b->st));
+    BH(batch_small(1, b->count, j, m, tol, s, b->st));
+    BH(batch_cgs(2, L, b->dV, nv, b->W, s.coef, s.sst, Vn, b->part, b->ldp, true, b->st));
+    BH(batch_reduce(L, b->part, b->ldp, 1, s.dsum, s.sst, true, b->st));
+    BH(batch_small(2, b->count, j, m, tol, s, b->st));
+    BH(batch_count_active(s.active, b->count, b->iv + 2 * b->count, b->st));
+    return AAO_OK;
+}
+
+static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, double tol, int maxit,
+                          aao_info *infos, int transpose)
+{
+    if (m < 1 || m > kBMaxRestart) {
+        b->err = "restart must be in [1, 63]";
+        return AAO_ERR_ARG;
+    }
+    if (!bvec || !x || !(tol >= 0.0) || maxit < 0) {
+        b->err = "bad arguments";
+        return AAO_ERR_ARG;
+    }
+    BT(ensure_ws(b, m));
+    const size_t N = b->Ntot;
+    const int P = b->count;
+    BState &s = b->bs;
+    s.maxit = maxit;
+    const BatchLaunch Lall = b->launch(false);
+    // reset state: iters, flags, fail flag (fill kernels would do for capture; this
+    // part is not captured)
+    BH(hipMemsetAsync(b->iv, 0, sizeof(int) * (2 * P + 1), b->st));
+    BH(hipMemsetAsync(b->flags, 0, 3 * P, b->st));
+    BH(hipMemsetAsync(b->fail, 0, sizeof(int), b->st));
+    // ||b_p||
+    const double *bp[1] = {bvec};
+    BH(hipMemcpyAsync(b->dB, bp, sizeof(double *), hipMemcpyHostToDevice, b->st));
+    BH(batch_cgs(0, Lall, b->dB, 1, bvec, nullptr, 0, nullptr, b->part, b->ldp, false, b->st));
+    BH(batch_reduce(Lall, b->part, b->ldp, 1, s.dsum, s.sst, false, b->st));
+    std::vector<double> hd((size_t)P * s.sst);
+    BH(hipMemcpyAsync(hd.data(), s.dsum, sizeof(double) * hd.size(), hipMemcpyDeviceToHost, b->st));
+    BH(hipStreamSynchronize(b->st));
+    std::vector<double> bn(P);
+    for (int p = 0; p < P; ++p) bn[p] = std::sqrt(hd[(size_t)p * s.sst]);
+    for (int p = 0; p < P; ++p)
+        if (!std::isfinite(bn[p])) {
+            b->err = "non-finite right-hand side";
+            return AAO_ERR_NUMERIC;
+        }
+    // zero right-hand sides: x = 0 and done (bnorm 1 avoids 0/0 in the state)
+    std::vector<double> bn_dev(P);
+    for (int p = 0; p < P; ++p) bn_dev[p] = bn[p] > 0.0 ? bn[p] : 1.0;
+    BH(hipMemcpy(s.bnorm, bn_dev.data(), sizeof(double) * P, hipMemcpyHostToDevice));
+
+    if (b->graph_m != m || b->graph_tol != tol || b->graph_maxit != maxit ||
+        (int)b->graphs.size() != m) {
+        for (auto g : b->graphs)
+            if (g) (void)hipGraphExecDestroy(g);
+        b->graphs.assign(m, nullptr);
+        b->graph_m = m;
+        b->graph_tol = tol;
+        b->graph_maxit = maxit;
+    }
+    int nact = 0;
+    int cycles = 0;
+    while (true) {
+        // r = b - A x -> V_0, beta_p, vs_0, g_0, active/done
+        BH(batch_matvec(Lall, x, b->V, bvec, b->scheme, transpose, false, b->st));
+        BH(batch_cgs(0, Lall, b->dV, 1, b->V, nullptr, 0, nullptr, b->part, b->ldp, false, b->st));
+        BH(batch_reduce(Lall, b->part, b->ldp, 1, s.dsum, s.sst, false, b->st));
+        BH(batch_small(3, P, 0, m, tol, s, b->st));
+        BH(batch_count_active(s.active, P, b->iv + 2 * P, b->st));
+        BH(hipMemcpyAsync(&nact, b->iv + 2 * P, sizeof(int), hipMemcpyDeviceToHost, b->st));
+        BH(hipStreamSynchronize(b->st));
+        if (nact == 0) break;
+        for (int j = 0; j < m; ++j) {
+            if (b->use_graph && b->st) {
+                if (!b->graphs[j]) {
+                    hipGraph_t g = nullptr;
+                    BH(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+                    aao_status cs = b_step(b, j, m, tol, transpose);
+                    hipError_t ce = hipStreamEndCapture(b->st, &g);
+                    if (cs < 0) return cs;
+                    BH(ce);
+                    BH(hipGraphInstantiate(&b->graphs[j], g, nullptr, nullptr, 0));
+                    (void)hipGraphDestroy(g);
+                }
+                BH(hipGraphLaunch(b->graphs[j], b->st));
+            } else {
+                BT(b_step(b, j, m, tol, transpose));
+            }
+            BH(hipMemcpyAsync(&nact, b->iv + 2 * P, sizeof(int), hipMemcpyDeviceToHost, b->st));
+            BH(hipStreamSynchronize(b->st));
+            if (std::getenv("AAO_LOG")) std::fprintf(stderr, "aao batch step %d active %d\n", j, nact);
+            if (nact == 0) break;
+        }
+        BH(batch_backsolve(P, m, s, b->st));
+        BH(batch_axpy(Lall, b->dZ, s, x, b->st));
+        ++cycles;
+    }
+    // report
+    std::vector<int> it(P);
+    std::vector<unsigned char> done(P), bad(P);
+    std::vector<double> est(P), tr(P);
+    BH(hipMemcpy(it.data(), s.iters, sizeof(int) * P, hipMemcpyDeviceToHost));
+    BH(hipMemcpy(done.data(), s.done, P, hipMemcpyDeviceToHost));
+    BH(hipMemcpy(bad.data(), s.bad, P, hipMemcpyDeviceToHost));
+    BH(hipMemcpy(est.data(), s.est, sizeof(double) * P, hipMemcpyDeviceToHost));
+    BH(hipMemcpy(tr.data(), s.truer, sizeof(double) * P, hipMemcpyDeviceToHost));
+    int failed = 0;
+    BH(hipMemcpy(&failed, b->fail, sizeof(int), hipMemcpyDeviceToHost));
+    bool all = true, anybad = failed != 0;
+    for (int p = 0; p < P; ++p) {
+        if (infos) {
+            infos[p].iters = it[p];
+            infos[p].restarts = std::max(0, cycles - 1);
+            infos[p].converged = done[p] ? 1 : 0;
+            infos[p].rel_resid_est = bn[p] > 0.0 ? est[p] : 0.0;
+            infos[p].rel_resid_true = bn[p] > 0.0 ? tr[p] : 0.0;
+        }
+        all = all && done[p];
+        anybad = anybad || bad[p];
+    }
+    if (anybad) {
+        b->err = "numerical breakdown in a batch member";
+        return AAO_ERR_NUMERIC;
+    }
+    return all ? AAO_OK : AAO_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------------------- ABI
+
+extern "C" {
+
+aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, const double *tau,
+                            const double *kappa, int scheme, int prec, aao_batch *out)
+{
+    if (!out) return AAO_ERR_ARG;
+    *out = nullptr;
+    if (count < 1 || !n || !ell || !kappa) return AAO_ERR_ARG;
+    if (scheme != AAO_HEAT_IE && scheme != AAO_WAVE_BD2) return AAO_ERR_ARG;
+    if (prec != AAO_PREC_FP64 && prec != AAO_PREC_MIXED && prec != AAO_PREC_FP32) return AAO_ERR_ARG;
+    for (int p = 0; p < count; ++p) {
+        const double tp = tau ? tau[p] : 1.0 / (double)ell[p];
+        if (n[p] < 1 || ell[p] < 2 || !(tp > 0.0) || !(kappa[p] > 0.0)) return AAO_ERR_ARG;
+        if (n[p] > 4096 || ell[p] > 2048) return AAO_ERR_UNSUPPORTED;
+    }
+    aao_batch b = nullptr;
+    try {
+        b = new aao_batch_s();
+    } catch (...) {
+        return AAO_ERR_ALLOC;
+    }
+    b->count = count;
+    b->scheme = scheme;
+    b->prec = prec;
+    aao_status s = AAO_OK;
+    do {
+        std::vector<int2> ft, rw, ps;
+        std::vector<int4> mt, sl;
+        size_t off = 0, soff = 0, coff = 0, boff = 0;
+        int max_ell = 0, max_M = 0;
+        for (int p = 0; p < count; ++p) {
+            BProb q{};
+            q.n = (int)n[p];
+            q.ell = (int)ell[p];
+            q.lds = (q.n + 15) / 16 * 16;
+            int M = 512;
+            while (M < 2 * q.ell - 1) M *= 2;
+            q.M = M;
+            q.tau = tau ? tau[p] : 1.0 / (double)q.ell;
+            q.kappa = kappa[p];
+            q.off = (long long)off;
+            q.soff = (long long)soff;
+            q.coff = (long long)coff;
+            q.boff = (long long)boff;
+            const size_t Np = (size_t)q.n * q.ell;
+            off += (Np + 63) / 64 * 64;
+            soff += (size_t)(q.ell / 2 + 1) * q.lds;
+            coff += q.ell;
+            boff += 2 * (size_t)M;
+            max_ell = std::max(max_ell, q.ell);
+            max_M = std::max(max_M, M);
+            b->hp.push_back(q);
+            const int Wp = 1024 * 8 / M;                       // column pairs per transform tile
+            const int ntile = (q.n + 2 * Wp - 1) / (2 * Wp);
+            for (int t = 0; t < ntile; ++t) ft.push_back({p, t});
+            for (int j = 0; j <= q.ell / 2; ++j) rw.push_back({p, j});
+            for (int by = 0; by < (q.ell + 15) / 16; ++by)
+                for (int bx = 0; bx < (q.n + 255) / 256; ++bx) mt.push_back({p, bx, by, 0});
+            const int first = (int)sl.size();
+            for (size_t e0 = 0; e0 < Np; e0 += kBatchSlab)
+                sl.push_back({p, (int)e0, (int)std::min<size_t>(kBatchSlab, Np - e0), 0});
+            ps.push_back({first, (int)sl.size()});
+        }
+        b->Ntot = off;
+        b->Stot = soff;
+        b->nftiles = (int)ft.size();
+        b->nrows = (int)rw.size();
+        b->nmtiles = (int)mt.size();
+        b->nslabs = (int)sl.size();
+        if ((s = upload(b, &b->probs, b->hp)) != AAO_OK) break;
+        if ((s = upload(b, &b->ftiles, ft)) != AAO_OK) break;
+        if ((s = upload(b, &b->rows, rw)) != AAO_OK) break;
+        if ((s = upload(b, &b->mtiles, mt)) != AAO_OK) break;
+        if ((s = upload(b, &b->slabs, sl)) != AAO_OK) break;
+        if ((s = upload(b, &b->pslabs, ps)) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->chirp, sizeof(double) * 2 * coff)) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->bhat, sizeof(double) * 2 * boff)) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->tw, sizeof(double) * 2 * 4096)) != AAO_OK) break;
+        if ((s = balloc(b, &b->spec, sizeof(double) * 2 * soff)) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->fail, sizeof(int))) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->part, sizeof(double) * b->ldp * b->nslabs)) != AAO_OK) break;
+        // small per-problem arrays: 10 arrays of kBSmall doubles + 3 scalars per problem
+        const size_t smn = (size_t)count * kBSmall;
+        if ((s = balloc(b, (void **)&b->sm, sizeof(double) * (10 * smn + 3 * (size_t)count))) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->H, sizeof(double) * (size_t)count * (kBMaxRestart + 1) * kBMaxRestart)) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->iv, sizeof(int) * (2 * count + 1))) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->flags, 3 * (size_t)count)) != AAO_OK) break;
+        if ((s = balloc(b, (void **)&b->dB, sizeof(double *))) != AAO_OK) break;
+        BState &bs = b->bs;
+        bs.sst = kBSmall;
+        bs.hst = (long long)(kBMaxRestart + 1) * kBMaxRestart;
+        bs.dsum = b->sm;
+        bs.h1 = b->sm + smn;
+        bs.h2 = b->sm + 2 * smn;
+        bs.coef = b->sm + 3 * smn;
+        bs.vs = b->sm + 4 * smn;
+        bs.cs = b->sm + 5 * smn;
+        bs.sn = b->sm + 6 * smn;
+        bs.g = b->sm + 7 * smn;
+        bs.y = b->sm + 8 * smn;
+        bs.bnorm = b->sm + 10 * smn;
+        bs.est = bs.bnorm + count;
+        bs.truer = bs.est + count;
+        bs.H = b->H;
+        bs.iters = b->iv;
+        bs.ksteps = b->iv + count;
+        bs.active = b->flags;
+        bs.done = b->flags + count;
+        bs.bad = b->flags + 2 * count;
+        if (hipStreamCreate(&b->st) != hipSuccess) {
+            s = AAO_ERR_HIP;
+            break;
+        }
+        b->own_stream = true;
+        if (batch_prepare() != hipSuccess ||
+            hipMemset(b->sm, 0, sizeof(double) * (10 * smn + 3 * (size_t)count)) != hipSuccess ||
+            launch_twiddles(b->tw, 4096, 4096, b->st) != hipSuccess ||
+            batch_setup_tables(b->probs, count, max_ell, max_M, b->chirp, b->bhat, b->st) != hipSuccess ||
+            hipStreamSynchronize(b->st) != hipSuccess) {
+            s = AAO_ERR_HIP;
+            break;
+        }
+        if (const char *g = std::getenv("AAO_BATCH_GRAPH")) b->use_graph = std::atoi(g) != 0;
+    } while (0);
+    if (s != AAO_OK) {
+        aao_batch_destroy(b);
+        return s;
+    }
+    *out = b;
+    return AAO_OK;
+}
+
+aao_status aao_batch_destroy(aao_batch b)
+{
+    if (!b) return AAO_OK;
+    if (b->st) (void)hipStreamSynchronize(b->st);
+    free_ws(b);
+    (void)hipFree(b->probs);
+    (void)hipFree(b->ftiles);
+    (void)hipFree(b->rows);
+    (void)hipFree(b->mtiles);
+    (void)hipFree(b->slabs);
+    (void)hipFree(b->pslabs);
+    (void)hipFree(b->chirp);
+    (void)hipFree(b->bhat);
+    (void)hipFree(b->tw);
+    (void)hipFree(b->spec);
+    (void)hipFree(b->fail);
+    (void)hipFree(b->part);
+    (void)hipFree(b->sm);
+    (void)hipFree(b->H);
+    (void)hipFree(b->iv);
+    (void)hipFree(b->flags);
+    (void)hipFree(b->dB);
+    if (b->own_stream && b->st) (void)hipStreamDestroy(b->st);
+    delete b;
+    return AAO_OK;
+}
+
+aao_status aao_batch_offsets(aao_batch b, int64_t *offsets, int64_t *total)
+{
+    if (!b) return AAO_ERR_ARG;
+    if (offsets)
+        for (int p = 0; p < b->count; ++p) offsets[p] = b->hp[p].off;
+    if (total) *total = (int64_t)b->Ntot;
+    return AAO_OK;
+}
+
+aao_status aao_batch_set_graph(aao_batch b, int enable)
+{
+    if (!b) return AAO_ERR_ARG;
+    b->use_graph = enable != 0;
+    return AAO_OK;
+}
+
+aao_status aao_batch_apply_A(aao_batch b, const double *x, double *y, int transpose)
+{
+    if (!b) return AAO_ERR_ARG;
+    if (b->broken) return AAO_ERR_HIP;
+    if (!x || !y) return AAO_ERR_ARG;
+    BH(batch_matvec(b->launch(false), x, y, nullptr, b->scheme, transpose ? 1 : 0, false, b->st));
+    BH(hipStreamSynchronize(b->st));
+    return AAO_OK;
+}
+
+aao_status aao_batch_apply_Pinv(aao_batch b, const double *r, double *z, int transpose)
+{
+    if (!b) return AAO_ERR_ARG;
+    if (b->broken) return AAO_ERR_HIP;
+    if (!r || !z) return AAO_ERR_ARG;
+    BT(b_pinv(b, r, nullptr, 0, z, false, transpose ? 1 : 0));
+    BH(hipStreamSynchronize(b->st));
+    return AAO_OK;
+}
+
+aao_status aao_batch_gmres(aao_batch b, const double *bvec, double *x, int restart, double tol,
+                           int maxit, aao_info *infos)
+{
+    if (!b) return AAO_ERR_ARG;
+    if (b->broken) return AAO_ERR_HIP;
+    try {
+        return b_gmres(b, bvec, x, restart, tol, maxit, infos, 0);
+    } catch (...) {
+        return AAO_ERR_ALLOC;
+    }
+}
+
+aao_status aao_batch_project_sine(aao_batch b, int J, const int *modes, const double *amps,
+                                  double *u0)
+{
+    if (!b) return AAO_ERR_ARG;
+    if (b->broken) return AAO_ERR_HIP;
+    if (J < 1 || !modes || !amps || !u0) return AAO_ERR_ARG;
+    for (int q = 0; q < J; ++q)
+        if (modes[q] < 1) return AAO_ERR_ARG;
+    int *dm = nullptr;
+    double *da = nullptr;
+    BT(balloc(b, (void **)&dm, sizeof(int) * J));
+    aao_status s = balloc(b, (void **)&da, sizeof(double) * (size_t)J * b->count);
+    if (s != AAO_OK) {
+        (void)hipFree(dm);
+        return s;
+    }
+    hipError_t e = hipMemcpy(dm, modes, sizeof(int) * J, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(da, amps, sizeof(double) * (size_t)J * b->count, hipMemcpyHostToDevice);
+    size_t uoff = 0;
+    for (int p = 0; p < b->count && e == hipSuccess; ++p) {
+        e = launch_project_sine(u0 + uoff, b->hp[p].n, J, dm, da + (size_t)p * J, b->st);
+        uoff += b->hp[p].n;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    (void)hipFree(dm);
+    (void)hipFree(da);
+    BH(e);
+    return AAO_OK;
+}
+
+aao_status aao_batch_build_rhs(aao_batch b, const double *u0, double *bvec)
+{
+    if (!b) return AAO_ERR_ARG;
+    if (b->broken) return AAO_ERR_HIP;
+    if (!u0 || !bvec) return AAO_ERR_ARG;
+    BH(launch_fill(bvec, 0.0, b->Ntot, b->st));
+    size_t uoff = 0;
+    for (int p = 0; p < b->count; ++p) {
+        const BProb &q = b->hp[p];
+        Scheme sc{};
+        if (b->scheme == AAO_HEAT_IE) {
+            sc.s = 1; sc.a[0] = 1.0; sc.a[1] = -1.0; sc.b[0] = q.tau;
+        } else {
+            sc.s = 2; sc.a[0] = 1.0; sc.a[1] = -2.0; sc.a[2] = 1.0; sc.b[0] = q.tau * q.tau;
+        }
+        BH(launch_build_rhs(bvec + q.off, u0 + uoff, nullptr, q.n, q.ell, sc, q.kappa, q.tau, b->st));
+        uoff += q.n;
+    }
+    BH(hipStreamSynchronize(b->st));
+    return AAO_OK;
+}
+
+const char *aao_batch_last_error(aao_batch b) { return b ? b->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// Device-side description of a batch of independent all-at-once problems and
+// the launchers of the batched kernels (k_batch.hip).
+#pragma once
+#include "aao_internal.h"
+
+namespace aao {
+
+struct BProb {
+    int n, ell, lds, M;          // M: Bluestein convolution length, power of two >= 2 ell - 1
+    double tau, kappa;
+    long long off;               // first element of the problem in a batch vector
+    long long soff;              // first complex element of its half spectrum
+    long long coff;              // first entry of its chirp table (ell entries)
+    long long boff;              // first entry of its filter spectra (2 M entries)
+};
+
+// Per-problem GMRES state (device arrays; `sst` doubles per problem for the
+// small vectors, `hst` for the Hessenberg matrix, column-major (m+1) x m).
+struct BState {
+    int sst;
+    long long hst;
+    int maxit;
+    double *dsum, *h1, *h2, *coef, *vs, *H, *cs, *sn, *g, *y, *bnorm, *est, *truer;
+    int *iters, *ksteps;
+    unsigned char *active, *done, *bad;
+};
+
+// Work tables of one batch (device pointers).
+struct BatchLaunch {
+    const BProb *probs;
+    int count;
+    const int2 *ftiles;  int nftiles;   // transform tiles (problem, tile)
+    const int2 *rows;    int nrows;     // spectrum rows (problem, frequency)
+    const int4 *mtiles;  int nmtiles;   // matvec tiles (problem, column block, row block, -)
+    const int4 *slabs;   int nslabs;    // element slabs (problem, first, count, -)
+    const int2 *pslabs;                 // slab range [x, y) of every problem
+    const unsigned char *active;        // per-problem mask
+    const double *chirp, *bhat, *tw;    // Bluestein tables, 4096-point twiddles
+};
+
+constexpr int kBatchSlab = 65536;       // elements per Gram-Schmidt / update slab
+
+hipError_t batch_prepare();
+hipError_t batch_setup_tables(const BProb *probs, int count, int max_ell, int max_M,
+                              double *chirp, double *bhat, hipStream_t st);
+hipError_t batch_fft_fwd(const BatchLaunch &L, const double *r, const double *scales, int sstride,
+                         void *spec, bool single, hipStream_t st);
+hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool single,
+                         hipStream_t st);
+hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool single_arith,
+                       int scheme, int transpose, int *fail, hipStream_t st);
+hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const double *bsub,
+                        int scheme, int transpose, bool masked, hipStream_t st);
+hipError_t batch_cgs(int mode, const BatchLaunch &L, const double *const *V, int nv,
+                     const double *w, const double *coef, int cst, double *out, double *part,
+                     int ldp, bool masked, hipStream_t st);
+hipError_t batch_reduce(const BatchLaunch &L, const double *part, int ldp, int cnt, double *sums,
+                        int sst, bool masked, hipStream_t st);
+hipError_t batch_small(int mode, int count, int j, int m, double tol, const BState &s,
+                       hipStream_t st);
+hipError_t batch_backsolve(int count, int m, const BState &s, hipStream_t st);
+hipError_t batch_axpy(const BatchLaunch &L, const double *const *Z, const BState &s, double *x,
+                      hipStream_t st);
+hipError_t batch_count_active(const unsigned char *a, int count, int *nact, hipStream_t st);
+
+}  // namespace aao

@@ -1,0 +1,792 @@
+// Batched form: many independent all-at-once problems of uneven size (n_p, ell_p,
+// kappa_p) advanced together, every phase of the preconditioned GMRES step as
+// ONE launch over a table of work items that spans all problems (problem id and
+// tile / row / slab).  Problems that have converged are masked out through a
+// device flag, so the launch sequence of one Arnoldi step is fixed and can be
+// captured in a hipGraph and replayed.
+//
+// The time-axis transform of a batch member uses Bluestein's chirp-z identity
+// (jk = (j^2 + k^2 - (j-k)^2)/2), which turns a DFT of any length ell into a
+// circular convolution of power-of-two length M >= 2 ell - 1, evaluated with
+// the same register/LDS Stockham FFT as the single-problem path.  Two real
+// columns travel as one complex sequence and are separated with the Hermitian
+// symmetry of their spectra.
+#include <cstdlib>
+
+#include "batch.h"
+#include "fft_core.h"
+#include "solve_core.h"
+
+namespace aao {
+
+// Move values from the natural-order positions of a finished transform to the
+// input positions of the first stage of the next one (both planes in turn).
+template <typename T, int L, int P>
+__device__ __forceinline__ void regroup(cx<T> *v, T *sm, int t, int c, int W)
+{
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+        for (int idx = 0; idx < P; ++idx)
+            sm[lds_idx(final_pos<L, P>(t, idx), c, W)] = part ? v[idx].y : v[idx].x;
+        __syncthreads();
+#pragma unroll
+        for (int idx = 0; idx < P; ++idx) {
+            const T val = sm[lds_idx(first_pos<L, P>(t, idx), c, W)];
+            if (part) v[idx].y = val; else v[idx].x = val;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T> __device__ __forceinline__ cx<T> cvt(cx<double> a) { return {T(a.x), T(a.y)}; }
+
+// Keep at most a few table loads in flight inside the fully unrolled per-point
+// loops (the scheduler would otherwise hoist all of them and spill).
+#define AAO_GROUP_FENCE(idx)                                     \
+    do {                                                         \
+        if (((idx) & 3) == 3) __builtin_amdgcn_sched_barrier(0); \
+    } while (0)
+
+// ---------------------------------------------------------- forward (Bluestein)
+// X_j = c_j sum_k (x_k c_k) conj(c_{j-k}),  c_m = exp(-i pi m^2 / ell): the input
+// a_k = x_k c_k is zero-padded to M, convolved with the filter through its
+// precomputed spectrum, and the result multiplied by c_j.
+template <typename T, int M>
+__device__ void bl_fwd_tile(const BProb &pb, int tile, const double *__restrict__ r, double rs,
+                            cx<T> *__restrict__ spec,
+                            const cx<double> *__restrict__ chirp,
+                            const cx<double> *__restrict__ bhat,
+                            const cx<double> *__restrict__ twM, T *sm)
+{
+    constexpr int P = 8;                              // points per thread (register budget)
+    constexpr int TN = M / P;
+    constexpr int W = 1024 / TN;                      // column pairs per tile
+    const int c = threadIdx.x % W;
+    const int t = threadIdx.x / W;
+    const int n = pb.n, ell = pb.ell;
+    const int col0 = (tile * W + c) * 2;
+    const bool v0 = col0 < n, v1 = col0 + 1 < n;
+    const double *rp = r + pb.off;
+    const cx<double> *ch = chirp + pb.coff;
+    cx<T> v[P];
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int k = first_pos<M, P>(t, idx);
+        cx<T> a = {T(0), T(0)};
+        if (k < ell) {
+            double x0 = 0.0, x1 = 0.0;
+            const size_t o = (size_t)k * n + col0;
+            if (v0) x0 = rs * rp[o];
+            if (v1) x1 = rs * rp[o + 1];
+            const cx<double> ck = ch[k];
+            a = cvt<T>(cx<double>{x0 * ck.x - x1 * ck.y, x0 * ck.y + x1 * ck.x});
+        }
+        v[idx] = a;
+        AAO_GROUP_FENCE(idx);
+    }
+    run_stages<T, M, P, 0, false>(v, sm, t, c, W, twM, 4096 / M);
+    const cx<double> *bh = bhat + pb.boff;           // spectrum of the forward filter
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        v[idx] = v[idx] * cvt<T>(bh[final_pos<M, P>(t, idx)]);
+        AAO_GROUP_FENCE(idx);
+    }
+    regroup<T, M, P>(v, sm, t, c, W);
+    run_stages<T, M, P, 0, true>(v, sm, t, c, W, twM, 4096 / M);
+    // Z_j = c_j conv_j / M for j < ell; stage Z in LDS (complex) to pair j with ell-j
+    const T invM = T(1.0 / M);
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int j = final_pos<M, P>(t, idx);
+        if (j < ell) {
+            const cx<T> z = cvt<T>(ch[j]) * v[idx];
+            sm[2 * (j * W + c)] = z.x * invM;
+            sm[2 * (j * W + c) + 1] = z.y * invM;
+        }
+        AAO_GROUP_FENCE(idx);
+    }
+    __syncthreads();
+    // X1_j = (Z_j + conj Z_{ell-j}) / 2,  X2_j = (Z_j - conj Z_{ell-j}) / 2i,  j <= ell/2
+    cx<T> *sp = spec + pb.soff;
+    const int H = ell / 2;
+    for (int j = t; j <= H; j += TN) {
+        const int jm = (ell - j) % ell;
+        const cx<T> z = {sm[2 * (j * W + c)], sm[2 * (j * W + c) + 1]};
+        const cx<T> zm = {sm[2 * (jm * W + c)], sm[2 * (jm * W + c) + 1]};
+        const cx<T> x1 = {T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+        const cx<T> x2 = {T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
+        if (v0) sp[(size_t)j * pb.lds + col0] = x1;
+        if (v1) sp[(size_t)j * pb.lds + col0 + 1] = x2;
+    }
+}
+
+// ---------------------------------------------------------- inverse (Bluestein)
+// x_k = (1/ell) conj(c_k) sum_j (Z_j conj(c_j)) c_{k-j}, Z = Y1 + i Y2 over the
+// full spectrum (Y_{ell-j} = conj Y_j); Re x and Im x are the two real columns.
+template <typename T, int M>
+__device__ void bl_inv_tile(const BProb &pb, int tile, const cx<T> *__restrict__ spec,
+                            double *__restrict__ z, const cx<double> *__restrict__ chirp,
+                            const cx<double> *__restrict__ bhat,
+                            const cx<double> *__restrict__ twM, T *sm)
+{
+    constexpr int P = 8;
+    constexpr int TN = M / P;
+    constexpr int W = 1024 / TN;
+    const int c = threadIdx.x % W;
+    const int t = threadIdx.x / W;
+    const int n = pb.n, ell = pb.ell;
+    const int col0 = (tile * W + c) * 2;
+    const bool v0 = col0 < n, v1 = col0 + 1 < n;
+    const cx<double> *ch = chirp + pb.coff;
+    const cx<T> *sp = spec + pb.soff;
+    const int H = ell / 2;
+    cx<T> v[P];
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int j = first_pos<M, P>(t, idx);
+        cx<T> a = {T(0), T(0)};
+        if (j < ell) {
+            const bool up = j > H;
+            const int jr = up ? ell - j : j;
+            cx<T> y1 = {T(0), T(0)}, y2 = {T(0), T(0)};
+            if (v0) y1 = sp[(size_t)jr * pb.lds + col0];
+            if (v1) y2 = sp[(size_t)jr * pb.lds + col0 + 1];
+            if (up) {
+                y1 = conj(y1);
+                y2 = conj(y2);
+            }
+            const cx<T> zz = y1 + mul_i(y2);
+            a = zz * conj(cvt<T>(ch[j]));
+        }
+        v[idx] = a;
+        AAO_GROUP_FENCE(idx);
+    }
+    run_stages<T, M, P, 0, false>(v, sm, t, c, W, twM, 4096 / M);
+    const cx<double> *bh = bhat + pb.boff + M;       // spectrum of the inverse filter
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        v[idx] = v[idx] * cvt<T>(bh[final_pos<M, P>(t, idx)]);
+        AAO_GROUP_FENCE(idx);
+    }
+    regroup<T, M, P>(v, sm, t, c, W);
+    run_stages<T, M, P, 0, true>(v, sm, t, c, W, twM, 4096 / M);
+    const double scale = 1.0 / ((double)M * (double)ell);
+    double *zp = z + pb.off;
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int k = final_pos<M, P>(t, idx);
+        if (k < ell) {
+            const cx<T> x = conj(cvt<T>(ch[k])) * v[idx];
+            const size_t o = (size_t)k * n + col0;
+            if (v0) zp[o] = double(x.x) * scale;
+            if (v1) zp[o + 1] = double(x.y) * scale;
+        }
+        AAO_GROUP_FENCE(idx);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_batch_fft_fwd(const BProb *__restrict__ probs, const int2 *__restrict__ tiles, int ntiles,
+                const unsigned char *__restrict__ active, const double *__restrict__ r,
+                const double *__restrict__ scales, int sstride, cx<T> *__restrict__ spec, const cx<double> *__restrict__ chirp,
+                const cx<double> *__restrict__ bhat, const cx<double> *__restrict__ twM)
+{
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    if (g >= ntiles) return;
+    const int2 e = tiles[g];
+    if (active && !active[e.x]) return;
+    const BProb pb = probs[e.x];
+    const double rs = scales ? scales[(size_t)e.x * sstride] : 1.0;
+    switch (pb.M) {
+    case 512: bl_fwd_tile<T, 512>(pb, e.y, r, rs, spec, chirp, bhat, twM, sm); break;
+    case 1024: bl_fwd_tile<T, 1024>(pb, e.y, r, rs, spec, chirp, bhat, twM, sm); break;
+    case 2048: bl_fwd_tile<T, 2048>(pb, e.y, r, rs, spec, chirp, bhat, twM, sm); break;
+    default: bl_fwd_tile<T, 4096>(pb, e.y, r, rs, spec, chirp, bhat, twM, sm); break;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_batch_fft_inv(const BProb *__restrict__ probs, const int2 *__restrict__ tiles, int ntiles,
+                const unsigned char *__restrict__ active, const cx<T> *__restrict__ spec,
+                double *__restrict__ z, const cx<double> *__restrict__ chirp,
+                const cx<double> *__restrict__ bhat, const cx<double> *__restrict__ twM)
+{
+    extern __shared__ unsigned char smraw[];
+    T *sm = reinterpret_cast<T *>(smraw);
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    if (g >= ntiles) return;
+    const int2 e = tiles[g];
+    if (active && !active[e.x]) return;
+    const BProb pb = probs[e.x];
+    switch (pb.M) {
+    case 512: bl_inv_tile<T, 512>(pb, e.y, spec, z, chirp, bhat, twM, sm); break;
+    case 1024: bl_inv_tile<T, 1024>(pb, e.y, spec, z, chirp, bhat, twM, sm); break;
+    case 2048: bl_inv_tile<T, 2048>(pb, e.y, spec, z, chirp, bhat, twM, sm); break;
+    default: bl_inv_tile<T, 4096>(pb, e.y, spec, z, chirp, bhat, twM, sm); break;
+    }
+}
+
+// ------------------------------------------------------------ shifted solves
+template <typename A, typename S>
+__global__ void __launch_bounds__(512)
+k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, int nrows,
+              const unsigned char *__restrict__ active, cx<S> *__restrict__ spec, int scheme,
+              int transpose, int *__restrict__ fail)
+{
+    constexpr int CW = 8;
+    extern __shared__ unsigned char smraw[];
+    const int NT = blockDim.x;
+    cx<A> *s_ip = reinterpret_cast<cx<A> *>(smraw);
+    cx<A> *s_cp = s_ip + CW;
+    cx<S> *stage = reinterpret_cast<cx<S> *>(s_cp + CW);
+    cx<A> *red = reinterpret_cast<cx<A> *>(s_cp + CW);
+    const int g = blockIdx.x;
+    if (g >= nrows) return;
+    const int2 e = rows[g];
+    if (active && !active[e.x]) return;
+    const BProb pb = probs[e.x];
+    const int j = e.y, n = pb.n, ell = pb.ell, t = threadIdx.x;
+    cx<S> *row = spec + pb.soff + (size_t)j * pb.lds;
+    // heat: alpha = 1 - w^j, beta = tau;  BD2: alpha = (1 - w^j)^2, beta = tau^2
+    double sn, cs;
+    sincospi((transpose ? 2.0 : -2.0) * (double)j / (double)ell, &sn, &cs);
+    double ar = 1.0 - cs, ai = -sn, br = pb.tau, bi = 0.0;
+    if (scheme == 1) {
+        const double r2 = ar * ar - ai * ai, i2 = 2.0 * ar * ai;
+        ar = r2;
+        ai = i2;
+        br = pb.tau * pb.tau;
+    }
+    const double h = 1.0 / (n + 1.0), kap = pb.kappa;
+    const cx<A> d = {A(ar * (4.0 * h / 6.0) + br * kap * (2.0 / h)), A(ai * (4.0 * h / 6.0) + bi * kap * (2.0 / h))};
+    const cx<A> ee = {A(ar * (h / 6.0) - br * kap / h), A(ai * (h / 6.0) - bi * kap / h)};
+    constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
+    const int NTP = NT + PAD;
+    const int P = (n + CW - 1) / CW;
+    const int len = (t < P) ? min(CW, n - t * CW) : 0;
+    for (int q = t; q < n; q += NT) stage[(q % CW) * NTP + q / CW] = row[q];
+    __syncthreads();
+    cx<A> y[CW];
+#pragma unroll
+    for (int i = 0; i < CW; ++i) {
+        y[i] = {A(0), A(0)};
+        if (i < len) {
+            const cx<S> v = stage[i * NTP + t];
+            y[i] = {A(v.x), A(v.y)};
+        }
+    }
+    const bool bad = partition_solve<A, CW>(y, n, d, ee, s_ip, s_cp, red);
+#pragma unroll
+    for (int i = 0; i < CW; ++i)
+        if (i < len) stage[i * NTP + t] = {S(y[i].x), S(y[i].y)};
+    __syncthreads();
+    for (int q = t; q < n; q += NT) row[q] = stage[(q % CW) * NTP + q / CW];
+    if (bad && fail) atomicOr(fail, 1);
+}
+
+// ------------------------------------------------------------------ matvec
+// y = A x (or bsub - A x) per problem, tiles of 256 columns x 16 time levels.
+__global__ void __launch_bounds__(256)
+k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, int ntiles,
+               const unsigned char *__restrict__ active, const double *__restrict__ x,
+               double *__restrict__ y, const double *__restrict__ bsub, int scheme, int transpose)
+{
+    constexpr int RB = 16;
+    const int g = blockIdx.x;
+    if (g >= ntiles) return;
+    const int4 e = tiles[g];
+    if (active && !active[e.x]) return;
+    const BProb pb = probs[e.x];
+    const int n = pb.n, ell = pb.ell;
+    const int i = e.y * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int s = scheme == 1 ? 2 : 1;
+    double am[3], bm[3];
+    if (scheme == 1) {
+        am[0] = 1.0; am[1] = -2.0; am[2] = 1.0;
+        bm[0] = pb.tau * pb.tau * pb.kappa; bm[1] = 0.0; bm[2] = 0.0;
+    } else {
+        am[0] = 1.0; am[1] = -1.0; am[2] = 0.0;
+        bm[0] = pb.tau * pb.kappa; bm[1] = 0.0; bm[2] = 0.0;
+    }
+    const double h = 1.0 / (n + 1.0);
+    const int k0 = e.z * RB, k1 = min(k0 + RB, ell);
+    const int nin = (k1 - k0) + s;
+    const double *xp = x + pb.off;
+    constexpr int NR = RB + 2;
+    double rl[NR], rc[NR], rr[NR];
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+        const int kk = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
+        const bool in = it < nin && kk >= 0 && kk < ell;
+        const double *row = xp + (size_t)(in ? kk : 0) * n;
+        rc[it] = in ? row[i] : 0.0;
+        rl[it] = (in && i > 0) ? row[i - 1] : 0.0;
+        rr[it] = (in && i + 1 < n) ? row[i + 1] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+        if (it < s || it >= nin) continue;
+        const int k = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
+        double al = 0, ac = 0, ar = 0, bl = 0, bc = 0, br = 0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if (m > s || it - m < 0) break;
+            al += am[m] * rl[it - m];
+            ac += am[m] * rc[it - m];
+            ar += am[m] * rr[it - m];
+            bl += bm[m] * rl[it - m];
+            bc += bm[m] * rc[it - m];
+            br += bm[m] * rr[it - m];
+        }
+        const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
+        const size_t o = pb.off + (size_t)k * n + i;
+        y[o] = bsub ? bsub[o] - v : v;
+    }
+}
+
+// ------------------------------------------------- Gram-Schmidt (per problem)
+// Each block owns one slab of one problem.  MODE 0: dots of the nv basis
+// vectors with w; MODE 1: w' = w - sum V_i c_i, dots with w'; MODE 2:
+// w'' = w - sum V_i c_i written to out, and ||w''||^2.  Coefficients c are per
+// problem (c[p * cst + i]).  Partials: part[slab * ldp + slot].
+template <int MODE, int NV>
+__global__ void __launch_bounds__(256)
+k_batch_cgs(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int nslabs,
+            const unsigned char *__restrict__ active, const double *const *__restrict__ V, int nv,
+            const double *__restrict__ w, const double *__restrict__ coef, int cst,
+            double *__restrict__ out, double *__restrict__ part, int ldp)
+{
+    __shared__ double red[(NV + 1) * 4];
+    const int g = blockIdx.x;
+    if (g >= nslabs) return;
+    const int4 e = slabs[g];                      // (problem, first, count, -)
+    const bool act = !active || active[e.x];
+    double acc[NV + 1];
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    if (act) {
+        const size_t base = probs[e.x].off + (size_t)e.y;
+        double cf[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) cf[i] = (MODE > 0 && i < nv) ? coef[(size_t)e.x * cst + i] : 0.0;
+        for (int q = threadIdx.x; q < e.z; q += blockDim.x) {
+            const size_t o = base + q;
+            double s = w[o];
+            double vv[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) vv[i] = (i < nv) ? V[i][o] : 0.0;
+            if (MODE == 0) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) acc[i] += vv[i] * s;
+            } else {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) s -= vv[i] * cf[i];
+                if (MODE == 1) {
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) acc[i] += vv[i] * s;
+                } else {
+                    out[o] = s;
+                    acc[NV] += s * s;
+                }
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) {
+        const bool used = (i < NV) ? (MODE != 2 && i < nv) : (MODE == 2);
+        if (used) {
+            double v = acc[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) red[i * 4 + wv] = v;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= NV; i += blockDim.x) {
+        const bool used = (i < NV) ? (MODE != 2 && i < nv) : (MODE == 2);
+        if (!used) continue;
+        const double sum = red[i * 4] + red[i * 4 + 1] + red[i * 4 + 2] + red[i * 4 + 3];
+        part[(size_t)g * ldp + (i < NV ? i : 0)] = sum;
+    }
+}
+
+// sums[p * sst + i] = sum over the slabs of problem p of part[slab * ldp + i]
+__global__ void k_batch_reduce(const int2 *__restrict__ pslabs, int count,
+                               const unsigned char *__restrict__ active,
+                               const double *__restrict__ part, int ldp, int cnt,
+                               double *__restrict__ sums, int sst)
+{
+    const int p = blockIdx.x;
+    if (p >= count || (active && !active[p])) return;
+    const int2 rg = pslabs[p];                     // slab range [x, y)
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        double s = 0.0;
+        for (int b = rg.x; b < rg.y; ++b) s += part[(size_t)b * ldp + i];
+        sums[(size_t)p * sst + i] = s;
+    }
+}
+
+// Per-problem Arnoldi bookkeeping and Givens update, one thread per problem.
+//   mode 0: h1 = vs.d, c = vs.h1
+//   mode 1: h2 = vs.d, c += vs.h2
+//   mode 2: nrm = sqrt(d0); vs[j+1] = 1/nrm; H column = [h1 + h2, nrm]; apply the
+//           previous rotations, form rotation j, update g, test convergence
+//   mode 3: restart vector: nrm = sqrt(d0) = beta; vs[0] = 1/beta; g = [beta, 0..];
+//           active = (beta / bnorm > tol) && !done
+template <int dummy>
+__global__ void k_batch_small(int mode, int count, int j, int m, double tol, BState st)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    if (mode != 3 && !st.active[p]) return;
+    const int nv = j + 1;
+    double *d = st.dsum + (size_t)p * st.sst;
+    double *h1 = st.h1 + (size_t)p * st.sst;
+    double *h2 = st.h2 + (size_t)p * st.sst;
+    double *c = st.coef + (size_t)p * st.sst;
+    double *vs = st.vs + (size_t)p * st.sst;
+    if (mode == 0) {
+        for (int i = 0; i < nv; ++i) {
+            h1[i] = vs[i] * d[i];
+            c[i] = vs[i] * h1[i];
+        }
+    } else if (mode == 1) {
+        for (int i = 0; i < nv; ++i) {
+            h2[i] = vs[i] * d[i];
+            c[i] += vs[i] * h2[i];
+        }
+    } else if (mode == 2) {
+        const double nrm = sqrt(fmax(d[0], 0.0));
+        vs[nv] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        double *H = st.H + (size_t)p * st.hst;          // column-major (m+1) x m
+        double *hc = H + (size_t)j * (m + 1);
+        for (int i = 0; i < nv; ++i) hc[i] = h1[i] + h2[i];
+        hc[nv] = nrm;
+        double *cs = st.cs + (size_t)p * st.sst, *sn = st.sn + (size_t)p * st.sst;
+        double *gg = st.g + (size_t)p * st.sst;
+        for (int i = 0; i < j; ++i) {
+            const double a = cs[i] * hc[i] + sn[i] * hc[i + 1];
+            hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+            hc[i] = a;
+        }
+        const double den = hypot(hc[j], hc[j + 1]);
+        const bool ok = den > 0.0 && isfinite(den);
+        cs[j] = ok ? hc[j] / den : 1.0;
+        sn[j] = ok ? hc[j + 1] / den : 0.0;
+        hc[j] = ok ? den : hc[j];
+        hc[j + 1] = 0.0;
+        gg[j + 1] = -sn[j] * gg[j];
+        gg[j] = cs[j] * gg[j];
+        st.iters[p] += 1;
+        st.ksteps[p] = nv;
+        const double est = fabs(gg[j + 1]) / st.bnorm[p];
+        st.est[p] = est;
+        if (!ok || !(est > tol) || st.iters[p] >= st.maxit) st.active[p] = 0;
+        if (!ok || !isfinite(est)) st.bad[p] = 1;
+    } else {
+        const double beta = sqrt(fmax(d[0], 0.0));
+        vs[0] = beta > 0.0 ? 1.0 / beta : 0.0;
+        double *gg = st.g + (size_t)p * st.sst;
+        gg[0] = beta;
+        st.ksteps[p] = 0;
+        const double rel = beta / st.bnorm[p];
+        st.truer[p] = rel;
+        if (!isfinite(rel)) st.bad[p] = 1;
+        const bool conv = !(rel > tol);
+        st.done[p] = conv ? 1 : st.done[p];
+        st.active[p] = (!conv && st.iters[p] < st.maxit && !st.bad[p]) ? 1 : 0;
+    }
+}
+
+// y = R^{-1} g per problem (k steps), one thread per problem
+__global__ void k_batch_backsolve(int count, int m, BState st)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= count) return;
+    const int k = st.ksteps[p];
+    const double *H = st.H + (size_t)p * st.hst;
+    const double *gg = st.g + (size_t)p * st.sst;
+    double *y = st.y + (size_t)p * st.sst;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = gg[i];
+        for (int l = i + 1; l < k; ++l) s -= H[(size_t)l * (m + 1) + i] * y[l];
+        y[i] = s / H[(size_t)i * (m + 1) + i];
+    }
+}
+
+// x += sum_{i < k_p} Z_i y_i per problem, over slabs
+__global__ void __launch_bounds__(256)
+k_batch_axpy(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int nslabs,
+             const double *const *__restrict__ Z, BState st, double *__restrict__ x)
+{
+    const int g = blockIdx.x;
+    if (g >= nslabs) return;
+    const int4 e = slabs[g];
+    const int k = st.ksteps[e.x];
+    if (k == 0) return;
+    const double *y = st.y + (size_t)e.x * st.sst;
+    const size_t base = probs[e.x].off + (size_t)e.y;
+    for (int q = threadIdx.x; q < e.z; q += blockDim.x) {
+        const size_t o = base + q;
+        double s = x[o];
+        for (int i = 0; i < k; ++i) s += Z[i][o] * y[i];
+        x[o] = s;
+    }
+}
+
+__global__ void k_batch_copy_active(const unsigned char *__restrict__ a, int count,
+                                    int *__restrict__ nact)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int s = 0;
+    for (int p = 0; p < count; ++p) s += a[p] ? 1 : 0;
+    *nact = s;
+}
+
+// ----------------------------------------------------------------- setup
+// chirp c_m = exp(-i pi m^2 / ell) with m^2 reduced mod 2 ell in integers
+__global__ void k_batch_chirp(const BProb *__restrict__ probs, int count,
+                              cx<double> *__restrict__ chirp)
+{
+    const int p = blockIdx.y;
+    if (p >= count) return;
+    const BProb pb = probs[p];
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < pb.ell; m += gridDim.x * blockDim.x) {
+        const long long q = ((long long)m * m) % (2LL * pb.ell);
+        double s, c;
+        sincospi(-(double)q / (double)pb.ell, &s, &c);
+        chirp[pb.coff + m] = {c, s};
+    }
+}
+
+// Filter spectra by a direct DFT of length M (setup only):
+//   forward filter  b_m = conj(c_m), |m| < ell (wrapped), inverse filter c_m.
+__global__ void k_batch_bhat(const BProb *__restrict__ probs, int count,
+                             const cx<double> *__restrict__ chirp, cx<double> *__restrict__ bhat)
+{
+    const int p = blockIdx.y;
+    if (p >= count) return;
+    const BProb pb = probs[p];
+    const int M = pb.M, ell = pb.ell;
+    const cx<double> *ch = chirp + pb.coff;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < M; q += gridDim.x * blockDim.x) {
+        double fr = 0.0, fi = 0.0, ir = 0.0, ii = 0.0;
+        for (int m = 0; m < M; ++m) {
+            int src = -1;
+            if (m < ell) src = m;
+            else if (m > M - ell) src = M - m;
+            if (src < 0) continue;
+            const cx<double> cm = ch[src];
+            const long long ph = ((long long)q * m) % M;
+            double s, c;
+            sincospi(-2.0 * (double)ph / (double)M, &s, &c);
+            // forward filter conj(c): (cm.x - i cm.y) (c + i s)
+            fr += cm.x * c + cm.y * s;
+            fi += cm.x * s - cm.y * c;
+            // inverse filter c: (cm.x + i cm.y) (c + i s)
+            ir += cm.x * c - cm.y * s;
+            ii += cm.x * s + cm.y * c;
+        }
+        bhat[pb.boff + q] = {fr, fi};
+        bhat[pb.boff + M + q] = {ir, ii};
+    }
+}
+
+// ------------------------------------------------------------- launchers
+hipError_t bl_twiddles(double *tw, hipStream_t st) { return launch_twiddles(tw, 4096, 4096, st); }
+
+hipError_t batch_setup_tables(const BProb *probs, int count, int max_ell, int max_M,
+                              double *chirp, double *bhat, hipStream_t st)
+{
+    dim3 g1((max_ell + 255) / 256, count);
+    k_batch_chirp<<<g1, 256, 0, st>>>(probs, count, reinterpret_cast<cx<double> *>(chirp));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g2((max_M + 255) / 256, count);
+    k_batch_bhat<<<g2, 256, 0, st>>>(probs, count, reinterpret_cast<const cx<double> *>(chirp),
+                                     reinterpret_cast<cx<double> *>(bhat));
+    return hipGetLastError();
+}
+
+static size_t bl_smem(size_t realsz)
+{
+    // largest tile plane over M in {512..4096}: lds_rows(M) * W reals, W = 1024 P / M
+    const int P = 8;
+    size_t best = 0;
+    for (int M = 512; M <= 4096; M *= 2) {
+        const size_t s = (size_t)lds_rows(M) * (1024 * P / M) * realsz;
+        if (s > best) best = s;
+    }
+    return best;
+}
+
+static size_t solve_smem(size_t es, size_t as)
+{
+    const int NT = 512, CW = 8;
+    const size_t stage = es * CW * (NT + 4), redb = as * 7 * NT;
+    return as * 2 * CW + (stage > redb ? stage : redb);
+}
+
+// Dynamic-LDS limits of the batched kernels, set once before any graph capture.
+hipError_t batch_prepare()
+{
+    hipError_t e;
+#define AAO_ATTR(k, bytes)                                                                     \
+    e = hipFuncSetAttribute((const void *)(k), hipFuncAttributeMaxDynamicSharedMemorySize,      \
+                            (int)(bytes));                                                    \
+    if (e != hipSuccess) return e;
+    AAO_ATTR(k_batch_fft_fwd<float>, bl_smem(sizeof(float)))
+    AAO_ATTR(k_batch_fft_fwd<double>, bl_smem(sizeof(double)))
+    AAO_ATTR(k_batch_fft_inv<float>, bl_smem(sizeof(float)))
+    AAO_ATTR(k_batch_fft_inv<double>, bl_smem(sizeof(double)))
+    AAO_ATTR((k_batch_solve<double, double>), solve_smem(16, 16))
+    AAO_ATTR((k_batch_solve<double, float>), solve_smem(8, 16))
+    AAO_ATTR((k_batch_solve<float, float>), solve_smem(8, 8))
+#undef AAO_ATTR
+    return hipSuccess;
+}
+
+hipError_t batch_fft_fwd(const BatchLaunch &L, const double *r, const double *scales, int sstride,
+                         void *spec, bool single, hipStream_t st)
+{
+    const int G = xcd_grid(L.nftiles);
+    if (single) {
+        const size_t smem = bl_smem(sizeof(float));
+        auto k = k_batch_fft_fwd<float>;
+        k<<<G, 1024, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active, r, scales, sstride,
+                                 reinterpret_cast<cx<float> *>(spec),
+                                 reinterpret_cast<const cx<double> *>(L.chirp),
+                                 reinterpret_cast<const cx<double> *>(L.bhat),
+                                 reinterpret_cast<const cx<double> *>(L.tw));
+    } else {
+        const size_t smem = bl_smem(sizeof(double));
+        auto k = k_batch_fft_fwd<double>;
+        k<<<G, 1024, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active, r, scales, sstride,
+                                 reinterpret_cast<cx<double> *>(spec),
+                                 reinterpret_cast<const cx<double> *>(L.chirp),
+                                 reinterpret_cast<const cx<double> *>(L.bhat),
+                                 reinterpret_cast<const cx<double> *>(L.tw));
+    }
+    return hipGetLastError();
+}
+
+hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool single,
+                         hipStream_t st)
+{
+    const int G = xcd_grid(L.nftiles);
+    if (single) {
+        const size_t smem = bl_smem(sizeof(float));
+        auto k = k_batch_fft_inv<float>;
+        k<<<G, 1024, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active,
+                                 reinterpret_cast<const cx<float> *>(spec), z,
+                                 reinterpret_cast<const cx<double> *>(L.chirp),
+                                 reinterpret_cast<const cx<double> *>(L.bhat),
+                                 reinterpret_cast<const cx<double> *>(L.tw));
+    } else {
+        const size_t smem = bl_smem(sizeof(double));
+        auto k = k_batch_fft_inv<double>;
+        k<<<G, 1024, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active,
+                                 reinterpret_cast<const cx<double> *>(spec), z,
+                                 reinterpret_cast<const cx<double> *>(L.chirp),
+                                 reinterpret_cast<const cx<double> *>(L.bhat),
+                                 reinterpret_cast<const cx<double> *>(L.tw));
+    }
+    return hipGetLastError();
+}
+
+hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool single_arith,
+                       int scheme, int transpose, int *fail, hipStream_t st)
+{
+    const int NT = 512;
+    if (!single) {
+        k_batch_solve<double, double><<<L.nrows, NT, solve_smem(16, 16), st>>>(
+            L.probs, L.rows, L.nrows, L.active, reinterpret_cast<cx<double> *>(spec), scheme,
+            transpose, fail);
+    } else if (!single_arith) {
+        k_batch_solve<double, float><<<L.nrows, NT, solve_smem(8, 16), st>>>(
+            L.probs, L.rows, L.nrows, L.active, reinterpret_cast<cx<float> *>(spec), scheme,
+            transpose, fail);
+    } else {
+        k_batch_solve<float, float><<<L.nrows, NT, solve_smem(8, 8), st>>>(
+            L.probs, L.rows, L.nrows, L.active, reinterpret_cast<cx<float> *>(spec), scheme,
+            transpose, fail);
+    }
+    return hipGetLastError();
+}
+
+hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const double *bsub,
+                        int scheme, int transpose, bool masked, hipStream_t st)
+{
+    k_batch_matvec<<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, masked ? L.active : nullptr,
+                                              x, y, bsub, scheme, transpose);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t cgs_b(const BatchLaunch &L, const double *const *V, int nv, const double *w,
+                        const double *coef, int cst, double *out, double *part, int ldp,
+                        bool masked, hipStream_t st)
+{
+    const unsigned char *act = masked ? L.active : nullptr;
+#define AAO_BNV(K)                                                                          \
+    if (nv <= K) {                                                                          \
+        k_batch_cgs<MODE, K><<<L.nslabs, 256, 0, st>>>(L.probs, L.slabs, L.nslabs, act, V, nv, w, \
+                                                      coef, cst, out, part, ldp);           \
+        return hipGetLastError();                                                           \
+    }
+    AAO_BNV(1) AAO_BNV(4) AAO_BNV(8) AAO_BNV(16) AAO_BNV(32) AAO_BNV(64)
+#undef AAO_BNV
+    return hipErrorInvalidValue;
+}
+
+hipError_t batch_cgs(int mode, const BatchLaunch &L, const double *const *V, int nv, const double *w,
+                     const double *coef, int cst, double *out, double *part, int ldp, bool masked,
+                     hipStream_t st)
+{
+    if (mode == 0) return cgs_b<0>(L, V, nv, w, coef, cst, out, part, ldp, masked, st);
+    if (mode == 1) return cgs_b<1>(L, V, nv, w, coef, cst, out, part, ldp, masked, st);
+    return cgs_b<2>(L, V, nv, w, coef, cst, out, part, ldp, masked, st);
+}
+
+hipError_t batch_reduce(const BatchLaunch &L, const double *part, int ldp, int cnt, double *sums,
+                        int sst, bool masked, hipStream_t st)
+{
+    k_batch_reduce<<<L.count, 64, 0, st>>>(L.pslabs, L.count, masked ? L.active : nullptr, part, ldp,
+                                           cnt, sums, sst);
+    return hipGetLastError();
+}
+
+hipError_t batch_small(int mode, int count, int j, int m, double tol, const BState &s,
+                       hipStream_t st)
+{
+    k_batch_small<0><<<(count + 63) / 64, 64, 0, st>>>(mode, count, j, m, tol, s);
+    return hipGetLastError();
+}
+
+hipError_t batch_backsolve(int count, int m, const BState &s, hipStream_t st)
+{
+    k_batch_backsolve<<<(count + 63) / 64, 64, 0, st>>>(count, m, s);
+    return hipGetLastError();
+}
+
+hipError_t batch_axpy(const BatchLaunch &L, const double *const *Z, const BState &s, double *x,
+                      hipStream_t st)
+{
+    k_batch_axpy<<<L.nslabs, 256, 0, st>>>(L.probs, L.slabs, L.nslabs, Z, s, x);
+    return hipGetLastError();
+}
+
+hipError_t batch_count_active(const unsigned char *a, int count, int *nact, hipStream_t st)
+{
+    k_batch_copy_active<<<1, 64, 0, st>>>(a, count, nact);
+    return hipGetLastError();
+}
+
+}  // namespace aao

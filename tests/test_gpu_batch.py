@@ -1,0 +1,111 @@
+"""Batched form on the GPU: problems of uneven n and ell (including lengths with
+large prime factors, ell = 2 and 3, n = 1) in one launch per phase, against the
+oracle problem by problem; hipGraph replay against eager launches; the 64-problem
+batch workload to 1e-8."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HEAT = 0
+SMALL = [(63, 100), (255, 256), (17, 97), (400, 513), (31, 1000), (5, 2), (1, 3), (130, 1021)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def normrel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def make(dev, prec, sizes=SMALL, kap_seed=0):
+    from paper_1810_00615_amd import Batch
+    rng = np.random.default_rng(kap_seed)
+    ns = [s[0] for s in sizes]
+    ells = [s[1] for s in sizes]
+    kappas = rng.uniform(0.5, 2.0, len(sizes))
+    return Batch(ns, ells, kappas, precision=prec, device=dev), ns, ells, kappas
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 2e-6)])
+def test_batch_pinv(dev, orc, prec, tol):
+    import torch
+    B, ns, ells, kappas = make(dev, prec)
+    rs = [np.random.default_rng([i, 1]).standard_normal((l, n)) for i, (n, l) in enumerate(zip(ns, ells))]
+    z = B.Pinv(B.pack(rs))
+    for i, (zv, r) in enumerate(zip(B.views(z), rs)):
+        ref = orc.pinv(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i], r)
+        e = normrel(zv.cpu().numpy(), ref)
+        print(f"batch pinv {prec} n={ns[i]} ell={ells[i]}: {e:.2e}")
+        assert e < tol
+
+
+def test_batch_matvec(dev, orc):
+    B, ns, ells, kappas = make(dev, "mixed")
+    xs = [np.random.default_rng([i, 2]).standard_normal((l, n)) for i, (n, l) in enumerate(zip(ns, ells))]
+    y = B.A(B.pack(xs))
+    for i, (yv, x) in enumerate(zip(B.views(y), xs)):
+        ref = orc.apply_A(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i], x)
+        assert float(np.max(np.abs(yv.cpu().numpy() - ref)) / np.max(np.abs(ref))) < 1e-14
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_gmres_small(dev, orc, prec):
+    """Every member reaches the 1e-8 true residual (oracle FP64 matvec) and the exact
+    sequential solution; graph replay gives bitwise the same result as eager launches."""
+    B, ns, ells, kappas = make(dev, prec)
+    J = 20
+    modes = np.arange(1, J + 1)
+    amps = np.random.default_rng(3).normal(0, 0.1, (len(ns), J))
+    u0 = B.project_sine(modes, amps)
+    b = B.rhs(u0)
+    B.set_graph(True)
+    x_g, infos, st = B.solve(b, restart=30, tol=1e-8, maxit=300)
+    B.set_graph(False)
+    x_e, infos_e, st_e = B.solve(b, restart=30, tol=1e-8, maxit=300)
+    assert st == 0 and st_e == 0
+    assert bool((x_g == x_e).all())
+    bcpu = [v.cpu().numpy() for v in B.views(b)]
+    for i, (xv, bv) in enumerate(zip(B.views(x_g), bcpu)):
+        n, ell, kap = ns[i], ells[i], kappas[i]
+        u0r = orc.project_sine(n, modes.astype(np.int32), amps[i])
+        br = orc.build_rhs(HEAT, n, ell, 1.0 / ell, kap, u0r)
+        assert float(np.max(np.abs(bv - br)) / np.max(np.abs(br))) < 1e-12
+        X = xv.cpu().numpy()
+        res = np.linalg.norm(br - orc.apply_A(HEAT, n, ell, 1.0 / ell, kap, X)) / np.linalg.norm(br)
+        U = orc.solve_seq(HEAT, n, ell, 1.0 / ell, kap, br)
+        print(f"batch gmres {prec} n={n} ell={ell}: iters {infos[i]['iters']} res {res:.2e} "
+              f"err {normrel(X, U):.2e}")
+        assert infos[i]["converged"] and res <= 1e-8
+        assert normrel(X, U) < 1e-6
+
+
+def test_batch_workload_64(dev, orc):
+    """The 64-problem batch (n in U{255..4095}, ell in U{256..2048}, kappa in U[0.5, 2],
+    20-mode u0): single-precision transforms, FP64 outer FGMRES(30) to 1e-8, every member
+    checked by the oracle's FP64 matvec and exact time stepping."""
+    from paper_1810_00615_amd import Batch
+    from paper_1810_00615_amd.inputs import heat_batch
+    ws = heat_batch()
+    B = Batch([w.n for w in ws], [w.ell for w in ws], [w.kappa for w in ws], precision="mixed",
+              device=dev)
+    modes = ws[0].modes
+    amps = np.stack([w.amps for w in ws])
+    u0 = B.project_sine(modes, amps)
+    b = B.rhs(u0)
+    x, infos, st = B.solve(b, restart=30, tol=1e-8, maxit=300)
+    assert st == 0
+    worst = 0.0
+    for i, (xv, w) in enumerate(zip(B.views(x), ws)):
+        u0r = orc.project_sine(w.n, w.modes, w.amps)
+        br = orc.build_rhs(HEAT, w.n, w.ell, w.tau, w.kappa, u0r)
+        X = xv.cpu().numpy()
+        res = np.linalg.norm(br - orc.apply_A(HEAT, w.n, w.ell, w.tau, w.kappa, X)) / np.linalg.norm(br)
+        worst = max(worst, res)
+        assert infos[i]["converged"] and res <= 1e-8, (i, w.n, w.ell, res)
+    print(f"batch 64: max true residual {worst:.2e}, iterations "
+          f"{sorted(set(i['iters'] for i in infos))}")
