@@ -124,6 +124,128 @@ def cpu_baseline(w, seconds_cap=60.0):
     }
 
 
+def _time(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for _ in range(reps):
+        res = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, res
+
+
+def bench_wave(args):
+    """Wave BD2, n = 2047, ell = 8192: FGMRES(30) to 1e-8, FP64 and mixed."""
+    import torch
+
+    from paper_1810_00615_amd import Problem
+    from paper_1810_00615_amd.inputs import wave_bd2
+    w = wave_bd2()
+    P = Problem(w.n, w.ell, w.tau, "bd2", kappa=w.kappa)
+    b = P.rhs(P.project_sine(w.modes, w.amps), P.project_sine(w.v_modes, w.v_amps))
+    x = P.empty()
+    out = {"workload": w.name, "unknowns": w.n * w.ell}
+    for prec in ("fp64", "mixed"):
+        P.set_precision(prec)
+        solve = lambda: P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit, out=x)[1]
+        solve()
+        t, info = _time(solve, 2)
+        out[prec] = {"solve_ms": t * 1e3, "iters": info["iters"],
+                     "true_rel_resid": info["rel_resid_true"], "converged": bool(info["converged"])}
+    out["mixed_speedup_vs_fp64"] = out["fp64"]["solve_ms"] / out["mixed"]["solve_ms"]
+    P.set_precision("fp64")
+    z = P.empty()
+    P.Pinv(b, out=z)
+    t, _ = _time(lambda: P.Pinv(b, out=z), 10)
+    N, S = w.n * w.ell, (w.ell // 2 + 1) * w.n
+    out["pinv_fp64_us"] = t * 1e6
+    out["pinv_fp64_GBps"] = (16 * N + 64 * S) / t / 1e9
+    return out
+
+
+def bench_batch(args):
+    """64 heat problems of uneven n, ell, kappa: batched mixed-precision FGMRES(30) to
+    1e-8 (hipGraph replay), against the same 64 problems solved one after the other
+    with plain FP64 single-problem solves."""
+    import numpy as np
+    import torch
+
+    from paper_1810_00615_amd import Batch, Problem
+    from paper_1810_00615_amd.inputs import heat_batch
+    ws = heat_batch()
+    out = {"workload": "heat_batch64", "problems": len(ws),
+           "unknowns": int(sum(w.n * w.ell for w in ws))}
+    modes = ws[0].modes
+    amps = np.stack([w.amps for w in ws])
+    for prec in ("mixed", "fp64"):
+        B = Batch([w.n for w in ws], [w.ell for w in ws], [w.kappa for w in ws], precision=prec)
+        b = B.rhs(B.project_sine(modes, amps))
+        x = B.empty()
+        solve = lambda: B.solve(b, restart=30, tol=1e-8, maxit=300, out=x)
+        solve()
+        t, (_, infos, st) = _time(solve, 2)
+        out[prec] = {"solve_ms": t * 1e3, "all_converged": st == 0,
+                     "max_true_rel_resid": max(i["rel_resid_true"] for i in infos),
+                     "iters": sorted(set(i["iters"] for i in infos))}
+        B.close()
+        del B, b, x
+        torch.cuda.empty_cache()
+    seq = 0.0
+    worst = 0.0
+    for w in ws:
+        P = Problem(w.n, w.ell, w.tau, "heat", kappa=w.kappa)
+        b = P.rhs(P.project_sine(w.modes, w.amps))
+        x = P.empty()
+        P.solve(b, restart=30, tol=1e-8, maxit=300, out=x)
+        t, (_, info) = _time(lambda: P.solve(b, restart=30, tol=1e-8, maxit=300, out=x), 1)
+        seq += t
+        worst = max(worst, info["rel_resid_true"])
+        P.close()
+        del P, b, x
+    torch.cuda.empty_cache()
+    out["sequential_fp64_ms"] = seq * 1e3
+    out["sequential_fp64_max_true_rel_resid"] = worst
+    out["batched_mixed_speedup_vs_sequential_fp64"] = seq * 1e3 / out["mixed"]["solve_ms"]
+    return out
+
+
+def bench_adjoint(args):
+    """Adjoint heat, n = 2047, ell = 2048: forward solve + adjoint solve + gradient
+    reductions (tol 1e-10), FP64 and mixed, and the backward pass with U
+    checkpointed every 64 levels."""
+    import torch
+
+    from paper_1810_00615_amd import Problem, all_at_once_solve
+    from paper_1810_00615_amd.inputs import heat_adjoint
+    w = heat_adjoint()
+    P = Problem(w.n, w.ell, w.tau, "heat", kappa=w.extra["target_kappa"])
+    Ut = P.solve(P.rhs(P.project_sine(w.modes, w.extra["target_amps"])), restart=30, tol=1e-12,
+                 maxit=300)[0].clone()
+    P.set_kappa(w.kappa)
+    u0 = P.project_sine(w.modes, w.amps)
+    out = {"workload": w.name, "unknowns": w.n * w.ell}
+    for prec in ("fp64", "mixed"):
+        P.set_precision(prec)
+
+        def step(stride=1):
+            uu = u0.clone().requires_grad_(True)
+            kk = torch.tensor(w.kappa, dtype=torch.float64, device=u0.device, requires_grad=True)
+            U = all_at_once_solve(uu, kk, P, restart=w.restart, tol=w.tol, maxit=w.maxit,
+                                  checkpoint_stride=stride)
+            (0.5 * ((U - Ut) ** 2).sum()).backward()
+            return float(kk.grad)
+        step()
+        t, gk = _time(step, 2)
+        out[prec] = {"forward_backward_ms": t * 1e3, "g_kappa": gk}
+        if prec == "fp64":
+            step(64)
+            t64, gk64 = _time(lambda: step(64), 2)
+            out["fp64_checkpoint64"] = {"forward_backward_ms": t64 * 1e3, "g_kappa": gk64}
+    P.set_precision("fp64")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +253,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pinv-reps", type=int, default=20)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the wave / batch / adjoint measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of one ell x n FP64 vector "
                          "(reference kernel for the HBM byte counters)")
@@ -236,6 +360,17 @@ def main():
                     "converged": bool(infos_m[-1]["converged"]),
                     "speedup_vs_fp64": t_step / (gpu_m / args.steps)}
     P.set_precision("fp64")
+
+    del P, x, b, u0
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        for key, fn in (("wave_bd2", bench_wave), ("batch", bench_batch),
+                        ("adjoint", bench_adjoint)):
+            try:
+                out[key] = fn(args)
+            except Exception as e:          # the headline line is printed regardless
+                out[key] = {"error": repr(e)}
+            torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

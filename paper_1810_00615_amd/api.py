@@ -24,6 +24,13 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _device(device):
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
 class Problem:
     """One all-at-once system A U = b (arXiv 1810.00615, Sec. 2) on one GPU.
 
@@ -40,7 +47,7 @@ class Problem:
         self.ell = int(ell)
         self.tau = float(tau) if tau is not None else 1.0 / self.ell
         self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-        self.device = torch.device(device)
+        self.device = _device(device)
         if self.device.type != "cuda":
             raise ValueError("the all-at-once library runs on a GPU device only")
         self._L = lib()
@@ -242,7 +249,7 @@ class Batch:
         self.taus = None if taus is None else np.ascontiguousarray(np.asarray(taus, dtype=np.float64))
         self.count = len(self.ns)
         self.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-        self.device = torch.device(device)
+        self.device = _device(device)
         self._L = lib()
         self._b = ctypes.c_void_p()
         p = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)

@@ -19,6 +19,7 @@
 
 #include "../../include/aao.h"
 #include "aao_internal.h"
+#include "batch.h"
 
 using namespace aao;
 
@@ -66,6 +67,14 @@ struct aao_ctx_s {
     int nmodes_alloc = 0;
     double *segpart = nullptr;   // per-segment partials of the checkpointed gradient
     int nseg_alloc = 0;
+
+    // lengths that are not powers of two: Bluestein transforms (the batched
+    // kernels with a batch of one)
+    bool bluestein = false;
+    BProb *bl_prob = nullptr;
+    int2 *bl_tiles = nullptr;
+    int bl_ntiles = 0;
+    double *bl_chirp = nullptr, *bl_bhat = nullptr, *bl_tw = nullptr;
 
     // per-kernel timing (aao_set_timing): event pairs recorded around launches
     bool timing = false;
@@ -223,6 +232,19 @@ static aao_status apply_A_impl(aao_ctx ctx, const double *x, double *y, const do
     return AAO_OK;
 }
 
+static BatchLaunch bl_launch(aao_ctx ctx)
+{
+    BatchLaunch L{};
+    L.probs = ctx->bl_prob;
+    L.count = 1;
+    L.ftiles = ctx->bl_tiles;
+    L.nftiles = ctx->bl_ntiles;
+    L.chirp = ctx->bl_chirp;
+    L.bhat = ctx->bl_bhat;
+    L.tw = ctx->bl_tw;
+    return L;
+}
+
 // z = C^{-1} (s r - E zprev)  (one circulant apply; s from in_scale)
 static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale,
                             const double *zprev, double *z, int transpose)
@@ -230,6 +252,15 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     const bool single = ctx->prec != AAO_PREC_FP64;
     const bool single_arith = ctx->prec == AAO_PREC_FP32;
     const int n = (int)ctx->n, ell = (int)ctx->ell;
+    if (ctx->bluestein && !zprev) {
+        const BatchLaunch L = bl_launch(ctx);
+        AAO_LAUNCH(AAO_K_FFT_FWD, batch_fft_fwd(L, r, in_scale, 0, ctx->spec, single, ctx->st));
+        AAO_LAUNCH(AAO_K_SHIFTED_SOLVE,
+                   launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sc,
+                                        ctx->kappa, transpose, ctx->fail, ctx->st));
+        AAO_LAUNCH(AAO_K_FFT_INV, batch_fft_inv(L, ctx->spec, z, single, ctx->st));
+        return AAO_OK;
+    }
     AAO_LAUNCH(AAO_K_FFT_FWD,
                launch_fft_fwd(r, in_scale, zprev, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
                               ctx->lds, single, ctx->tw, ctx->st));
@@ -443,6 +474,38 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
         if ((s = dev_alloc(ctx, (void **)&ctx->small, sizeof(double) * 7 * kSmallStride)) != AAO_OK)
             break;
         if ((s = dev_alloc(ctx, (void **)&ctx->tmpn, sizeof(double) * n)) != AAO_OK) break;
+        if (!fft_supported_fast((int)ell) && ell >= 17 && ell <= 2048 && n <= 16384) {
+            // Bluestein transforms through the batched kernels (batch of one)
+            BProb q{};
+            q.n = (int)n;
+            q.ell = (int)ell;
+            q.lds = ctx->lds;
+            int M = 512;
+            while (M < 2 * q.ell - 1) M *= 2;
+            q.M = M;
+            q.tau = tau;
+            q.kappa = 1.0;
+            std::vector<int2> tiles;
+            const int Wp = 1024 * 8 / M;
+            for (int t = 0; t < (q.n + 2 * Wp - 1) / (2 * Wp); ++t) tiles.push_back({0, t});
+            ctx->bl_ntiles = (int)tiles.size();
+            if ((s = dev_alloc(ctx, (void **)&ctx->bl_prob, sizeof(BProb))) != AAO_OK) break;
+            if ((s = dev_alloc(ctx, (void **)&ctx->bl_tiles, sizeof(int2) * tiles.size())) != AAO_OK) break;
+            if ((s = dev_alloc(ctx, (void **)&ctx->bl_chirp, sizeof(double) * 2 * ell)) != AAO_OK) break;
+            if ((s = dev_alloc(ctx, (void **)&ctx->bl_bhat, sizeof(double) * 4 * M)) != AAO_OK) break;
+            if ((s = dev_alloc(ctx, (void **)&ctx->bl_tw, sizeof(double) * 2 * 4096)) != AAO_OK) break;
+            if (hipMemcpy(ctx->bl_prob, &q, sizeof(BProb), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(ctx->bl_tiles, tiles.data(), sizeof(int2) * tiles.size(),
+                          hipMemcpyHostToDevice) != hipSuccess ||
+                batch_prepare() != hipSuccess ||
+                launch_twiddles(ctx->bl_tw, 4096, 4096, nullptr) != hipSuccess ||
+                batch_setup_tables(ctx->bl_prob, 1, (int)ell, M, ctx->bl_chirp, ctx->bl_bhat,
+                                   nullptr) != hipSuccess) {
+                s = AAO_ERR_HIP;
+                break;
+            }
+            ctx->bluestein = true;
+        }
         if (launch_twiddles(ctx->tw, (int)ell, (int)ell, nullptr) != hipSuccess ||
             hipMemset(ctx->fail, 0, sizeof(int)) != hipSuccess ||
             hipMemset(ctx->small, 0, sizeof(double) * 7 * kSmallStride) != hipSuccess ||
@@ -480,6 +543,11 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->dmodes);
     (void)hipFree(ctx->damps);
     (void)hipFree(ctx->segpart);
+    (void)hipFree(ctx->bl_prob);
+    (void)hipFree(ctx->bl_tiles);
+    (void)hipFree(ctx->bl_chirp);
+    (void)hipFree(ctx->bl_bhat);
+    (void)hipFree(ctx->bl_tw);
     delete ctx;
     return AAO_OK;
 }
