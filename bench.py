@@ -148,6 +148,8 @@ def bench_wave(args):
     out = {"workload": w.name, "unknowns": w.n * w.ell}
     for prec in ("fp64", "mixed"):
         P.set_precision(prec)
+        if not args.no_tune:
+            P.tune(reps=3)
         solve = lambda: P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit, out=x)[1]
         solve()
         t, info = _time(solve, 2)
@@ -255,6 +257,8 @@ def main():
     ap.add_argument("--pinv-reps", type=int, default=20)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the wave / batch / adjoint measurements")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the built-in launch shapes instead of autotuning them")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of one ell x n FP64 vector "
                          "(reference kernel for the HBM byte counters)")
@@ -288,6 +292,12 @@ def main():
                       "x0": "zero", "parallelism": "single GPU"}}
 
     # ---------------------------------------------------------------- FP64
+    shapes = {}
+    if not args.no_tune:
+        shapes["fp64"] = P.tune(reps=5)
+        P.set_precision("mixed")
+        shapes["mixed"] = P.tune(reps=5)
+        P.set_precision("fp64")
     for _ in range(args.warmup):
         P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit, out=x)
     P.set_timing(True)
@@ -311,6 +321,7 @@ def main():
             rec["GBps"] = kb / (avg_us * 1e-6) / 1e9
         kernels[name] = rec
     out["fp64"]["kernels"] = kernels
+    out["launch_shapes"] = shapes or "built-in defaults"
 
     # roofline of the dominant kernel (largest total time with a byte count)
     dom = max((k for k in kernels if kernel_bytes(k, w.n, w.ell, 16)),

@@ -193,6 +193,38 @@ enum {
 aao_status aao_set_timing(aao_ctx ctx, int enable);
 aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count);
 
+/* Launch shapes of the three kernels of the preconditioner apply (Sec. 3: forward
+ * time transform, shifted solves, inverse transform) and of the block-Toeplitz
+ * matvec (Sec. 2), and their autotuner.
+ * Shape codes:
+ *   AAO_CFG_FFT_FWD / AAO_CFG_FFT_INV: 16 v + log2 W, W = columns per workgroup,
+ *     v = 0: min(ell/2, 16) points per thread (radix-16 stages), v = 1: 8 points per
+ *     thread (radix-8 stages, ell = 1024..8192);
+ *   AAO_CFG_SHIFTED_SOLVE: index of a (chunk CW, threads NT, LDS staging) triple;
+ *   AAO_CFG_MATVEC: 3 v + r, R = 4 << r time levels per thread, v = 1 for DPP
+ *     cross-lane moves, v = 0 for ds_bpermute.
+ * -1 means the built-in default.  Shapes are kept per precision mode.
+ * aao_tune times every admissible shape of each kernel `reps` times on the context
+ * stream with HIP events (on scratch data; the context's vectors are untouched) and
+ * keeps the fastest for the current precision mode; it synchronises the stream.
+ * Results are cached per process by (device, kernel, precision, n, ell); if the
+ * environment variable AAO_TUNE_CACHE names a file, results are also read from and
+ * appended to it, one line "kernel precision n ell code microseconds".
+ * aao_set_config rejects a code that does not fit (n, ell) with AAO_ERR_ARG.
+ * aao_config_shape decodes a code: FFT -> {points per thread, W, 0}; solve -> {CW,
+ * NT, staged}; matvec -> {R, DPP, 0}. */
+typedef enum {
+    AAO_CFG_FFT_FWD = 0,
+    AAO_CFG_SHIFTED_SOLVE = 1,
+    AAO_CFG_FFT_INV = 2,
+    AAO_CFG_MATVEC = 3,
+    AAO_NUM_CFG = 4
+} aao_cfg_kind;
+aao_status aao_tune(aao_ctx ctx, int reps);
+aao_status aao_get_config(aao_ctx ctx, int kind, int *code);
+aao_status aao_set_config(aao_ctx ctx, int kind, int code);
+aao_status aao_config_shape(aao_ctx ctx, int kind, int code, int shape[3]);
+
 /* ------------------------------------------------------------------ batch
  * Many independent problems of uneven size advanced together: every phase of an
  * Arnoldi step is one launch over a work table spanning all problems, converged

@@ -50,6 +50,10 @@ SIGNATURES = {
     "aao_set_timing": [ctypes.c_void_p, ctypes.c_int],
     "aao_get_timing": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                        ctypes.POINTER(ctypes.c_int64)],
+    "aao_tune": [ctypes.c_void_p, ctypes.c_int],
+    "aao_get_config": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "aao_set_config": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "aao_config_shape": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "aao_batch_create": [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                          ctypes.POINTER(ctypes.c_void_p)],
@@ -104,5 +108,6 @@ def check(status, where, ctx=None):
         raise AAOError(status, where, detail)
     return status
 
+CONFIG_KINDS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec"]
 KERNELS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec", "cgs_dot", "cgs_update_dot",
            "cgs_update_norm", "axpy"]

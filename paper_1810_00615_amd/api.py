@@ -13,7 +13,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import KERNELS, AAOError, Info, check, lib
+from ._lib import CONFIG_KINDS, KERNELS, AAOError, Info, check, lib
 
 HEAT, BD2 = 0, 1
 SCHEMES = {"heat": HEAT, "heat_ie": HEAT, "bd2": BD2, "wave_bd2": BD2}
@@ -204,6 +204,36 @@ class Problem:
             int(stride), _ptr(lam), _ptr(gu), ctypes.byref(gk) if want_kappa else None,
             _ptr(recompute_out)), "aao_grad_checkpointed")
         return gu, (gk.value if want_kappa else None)
+
+    def tune(self, reps: int = 10):
+        """Time every admissible launch shape of the forward transform, the shifted
+        solves, the inverse transform and the matvec for the current precision mode
+        and keep the fastest (aao_tune); returns configs()."""
+        self._stream()
+        with torch.cuda.device(self.device):
+            self._c(self._L.aao_tune(self._ctx, int(reps)), "aao_tune")
+        return self.configs()
+
+    def configs(self):
+        """{kernel: None (default) or (code, shape)}; shape is (points per thread, W, 0)
+        for the transforms, (chunk, threads, staged) for the shifted solves and
+        (rows per thread, DPP lane moves, 0) for the matvec."""
+        out = {}
+        for kind, name in enumerate(CONFIG_KINDS):
+            code = ctypes.c_int(0)
+            self._c(self._L.aao_get_config(self._ctx, kind, ctypes.byref(code)), "aao_get_config")
+            if code.value < 0:
+                out[name] = None
+                continue
+            shape = (ctypes.c_int * 3)()
+            self._c(self._L.aao_config_shape(self._ctx, kind, code.value, shape), "aao_config_shape")
+            out[name] = (code.value, tuple(shape))
+        return out
+
+    def set_config(self, kernel: str, code: int):
+        """Pin one kernel's launch shape (code as in configs(); -1 = default)."""
+        self._c(self._L.aao_set_config(self._ctx, CONFIG_KINDS.index(kernel), int(code)),
+                "aao_set_config")
 
     def set_timing(self, enable: bool = True):
         """Bracket every kernel launch with HIP events (clears the accumulators)."""

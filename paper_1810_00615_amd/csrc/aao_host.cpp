@@ -12,9 +12,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/aao.h"
@@ -82,6 +86,10 @@ struct aao_ctx_s {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
     double t_total[AAO_NUM_KERNELS] = {};
     long long t_count[AAO_NUM_KERNELS] = {};
+
+    // launch shapes per precision mode (aao_set_config / aao_tune); -1 = default
+    int cfg[3][AAO_NUM_CFG] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
+    int cf(int kind) const { return cfg[prec][kind]; }
 
     size_t N() const { return (size_t)n * (size_t)ell; }
     double *sd() { return small; }
@@ -228,7 +236,8 @@ static aao_status apply_A_impl(aao_ctx ctx, const double *x, double *y, const do
                                int transpose)
 {
     AAO_LAUNCH(AAO_K_MATVEC, launch_matvec(x, y, bsub, (int)ctx->n, (int)ctx->ell, ctx->sc,
-                                           ctx->kappa, ctx->tauk, transpose, ctx->st));
+                                           ctx->kappa, ctx->tauk, transpose, ctx->st,
+                                           ctx->cf(AAO_CFG_MATVEC)));
     return AAO_OK;
 }
 
@@ -257,19 +266,166 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
         AAO_LAUNCH(AAO_K_FFT_FWD, batch_fft_fwd(L, r, in_scale, 0, ctx->spec, single, ctx->st));
         AAO_LAUNCH(AAO_K_SHIFTED_SOLVE,
                    launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sc,
-                                        ctx->kappa, transpose, ctx->fail, ctx->st));
+                                        ctx->kappa, transpose, ctx->fail, ctx->st,
+                                        ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
         AAO_LAUNCH(AAO_K_FFT_INV, batch_fft_inv(L, ctx->spec, z, single, ctx->st));
         return AAO_OK;
     }
     AAO_LAUNCH(AAO_K_FFT_FWD,
                launch_fft_fwd(r, in_scale, zprev, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
-                              ctx->lds, single, ctx->tw, ctx->st));
+                              ctx->lds, single, ctx->tw, ctx->st, ctx->cf(AAO_CFG_FFT_FWD)));
     AAO_LAUNCH(AAO_K_SHIFTED_SOLVE,
                launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sc,
-                                    ctx->kappa, transpose, ctx->fail, ctx->st));
+                                    ctx->kappa, transpose, ctx->fail, ctx->st,
+                                    ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
     AAO_LAUNCH(AAO_K_FFT_INV,
-               launch_fft_inv(ctx->spec, ctx->lds, single, z, n, ell, ctx->tw, ctx->st));
+               launch_fft_inv(ctx->spec, ctx->lds, single, z, n, ell, ctx->tw, ctx->st,
+                              ctx->cf(AAO_CFG_FFT_INV)));
     return AAO_OK;
+}
+
+
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+
+using TuneKey = std::tuple<int, int, int, int64_t, int64_t>;   // device, kind, prec, n, ell
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_file_read = false;
+
+const char *tune_file() { return std::getenv("AAO_TUNE_CACHE"); }
+
+// caller holds g_tune_mu
+void tune_read_file(int device)
+{
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char *path = tune_file();
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    int kind, prec, code;
+    long long n, ell;
+    double us;
+    while (std::fscanf(f, "%d %d %lld %lld %d %lf", &kind, &prec, &n, &ell, &code, &us) == 6)
+        g_tune[TuneKey(device, kind, prec, n, ell)] = code;
+    std::fclose(f);
+}
+
+void tune_append_file(int kind, int prec, int64_t n, int64_t ell, int code, double us)
+{
+    const char *path = tune_file();
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %lld %lld %d %.3f\n", kind, prec, (long long)n, (long long)ell, code, us);
+    std::fclose(f);
+}
+
+// admissible codes of one kernel for the context's sizes and precision mode
+std::vector<int> tune_candidates(aao_ctx ctx, int kind)
+{
+    std::vector<int> out;
+    const bool single = ctx->prec != AAO_PREC_FP64;
+    if (kind == AAO_CFG_SHIFTED_SOLVE) {
+        for (int c = 0; c < solve_num_configs(); ++c)
+            if (solve_config_ok(c, (int)ctx->n)) out.push_back(c);
+    } else if (kind == AAO_CFG_MATVEC) {
+        for (int c = 0; c < matvec_num_configs(); ++c) out.push_back(c);
+    } else if (!ctx->bluestein) {
+        int buf[32];
+        const int k = fft_configs((int)ctx->ell, (int)ctx->n, single, buf, 32);
+        for (int i = 0; i < k && i < 32; ++i) out.push_back(buf[i]);
+    }
+    return out;
+}
+
+bool config_valid(aao_ctx ctx, int kind, int code)
+{
+    if (code == -1) return true;
+    for (int c : tune_candidates(ctx, kind))
+        if (c == code) return true;
+    return false;
+}
+
+}  // namespace
+
+static aao_status launch_kind(aao_ctx ctx, int kind, int code, double *buf)
+{
+    if (kind == AAO_CFG_MATVEC) {
+        AAO_HIP(launch_matvec(buf, buf + ctx->N(), nullptr, (int)ctx->n, (int)ctx->ell, ctx->sc,
+                              ctx->kappa, ctx->tauk, 0, ctx->st, code));
+        return AAO_OK;
+    }
+    const bool single = ctx->prec != AAO_PREC_FP64;
+    const bool single_arith = ctx->prec == AAO_PREC_FP32;
+    const int n = (int)ctx->n, ell = (int)ctx->ell;
+    if (kind == AAO_CFG_FFT_FWD)
+        AAO_HIP(launch_fft_fwd(buf, nullptr, nullptr, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
+                               ctx->lds, single, ctx->tw, ctx->st, code));
+    else if (kind == AAO_CFG_SHIFTED_SOLVE)
+        AAO_HIP(launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sc,
+                                     ctx->kappa, 0, nullptr, ctx->st, code));
+    else
+        AAO_HIP(launch_fft_inv(ctx->spec, ctx->lds, single, buf, n, ell, ctx->tw, ctx->st, code));
+    return AAO_OK;
+}
+
+static aao_status tune_impl(aao_ctx ctx, int reps, double *buf)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    AAO_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return arg_err(ctx, "hipEventCreate failed");
+    }
+    aao_status s = AAO_OK;
+    for (int kind = 0; kind < AAO_NUM_CFG && s == AAO_OK; ++kind) {
+        const TuneKey key(ctx->device, kind, ctx->prec, ctx->n, ctx->ell);
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            tune_read_file(ctx->device);
+            auto it = g_tune.find(key);
+            if (it != g_tune.end() && config_valid(ctx, kind, it->second)) {
+                ctx->cfg[ctx->prec][kind] = it->second;
+                continue;
+            }
+        }
+        const std::vector<int> cand = tune_candidates(ctx, kind);
+        if (cand.empty()) continue;
+        int best = -1;
+        double best_ms = 0.0;
+        for (int code : cand) {
+            if ((s = launch_kind(ctx, kind, code, buf)) != AAO_OK) break;   // warm-up
+            if (hipEventRecord(e0, ctx->st) != hipSuccess) { s = AAO_ERR_HIP; break; }
+            for (int r = 0; r < reps && s == AAO_OK; ++r) s = launch_kind(ctx, kind, code, buf);
+            if (s != AAO_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, ctx->st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                s = AAO_ERR_HIP;
+                break;
+            }
+            if (best < 0 || ms < best_ms) {
+                best = code;
+                best_ms = ms;
+            }
+        }
+        if (s != AAO_OK) break;
+        ctx->cfg[ctx->prec][kind] = best;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[key] = best;
+        tune_append_file(kind, ctx->prec, ctx->n, ctx->ell, best, 1e3 * best_ms / reps);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s == AAO_ERR_HIP) {
+        ctx->broken = true;
+        if (ctx->err.empty()) ctx->err = "HIP error while tuning";
+    }
+    return s;
 }
 
 // Neumann recurrence of eq. preconapprox1: z_0 = C^{-1} r, z_m = C^{-1}(r - E z_{m-1}).
@@ -824,6 +980,69 @@ aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *co
     ctx->ev_pending.clear();
     *total_ms = ctx->t_total[kernel];
     *count = ctx->t_count[kernel];
+    return AAO_OK;
+}
+
+aao_status aao_tune(aao_ctx ctx, int reps)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (ctx->broken) return AAO_ERR_HIP;
+    if (reps < 1 || reps > 1000) return arg_err(ctx, "reps must be in [1, 1000]");
+    // scratch: two real ell x n arrays (zeros) for the transforms and the matvec; the
+    // half spectrum is workspace and is rewritten by every apply
+    double *buf = nullptr;
+    AAO_TRY(dev_alloc(ctx, (void **)&buf, 2 * sizeof(double) * ctx->N()));
+    aao_status s = AAO_OK;
+    const size_t H = (size_t)ctx->ell / 2 + 1;
+    if (launch_fill(buf, 0.0, 2 * ctx->N(), ctx->st) != hipSuccess ||
+        launch_fill((double *)ctx->spec, 0.0, H * ctx->lds * 2, ctx->st) != hipSuccess)
+        s = AAO_ERR_HIP;
+    if (s == AAO_OK) s = tune_impl(ctx, reps, buf);
+    (void)hipStreamSynchronize(ctx->st);
+    (void)hipFree(buf);
+    if (s == AAO_ERR_HIP) {
+        ctx->broken = true;
+        if (ctx->err.empty()) ctx->err = "HIP error while tuning";
+    }
+    return s;
+}
+
+aao_status aao_get_config(aao_ctx ctx, int kind, int *code)
+{
+    if (!ctx || !code) return AAO_ERR_ARG;
+    if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
+    *code = ctx->cfg[ctx->prec][kind];
+    return AAO_OK;
+}
+
+aao_status aao_set_config(aao_ctx ctx, int kind, int code)
+{
+    if (!ctx) return AAO_ERR_ARG;
+    if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
+    if (!config_valid(ctx, kind, code)) return arg_err(ctx, "launch shape does not fit n, ell");
+    ctx->cfg[ctx->prec][kind] = code;
+    return AAO_OK;
+}
+
+aao_status aao_config_shape(aao_ctx ctx, int kind, int code, int shape[3])
+{
+    if (!ctx || !shape) return AAO_ERR_ARG;
+    if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
+    if (code < 0) return arg_err(ctx, "default shapes have no code");
+    if (kind == AAO_CFG_SHIFTED_SOLVE) {
+        if (code >= solve_num_configs()) return arg_err(ctx, "bad code");
+        solve_config_shape(code, &shape[0], &shape[1], &shape[2]);
+    } else if (kind == AAO_CFG_MATVEC) {
+        if (code >= matvec_num_configs()) return arg_err(ctx, "bad code");
+        shape[0] = 4 << (code % 3);
+        shape[1] = code / 3;
+        shape[2] = 0;
+    } else {
+        const int L = (int)ctx->ell / 2;
+        shape[0] = code >= 16 ? 8 : (L < 16 ? L : 16);
+        shape[1] = 1 << (code & 15);
+        shape[2] = 0;
+    }
     return AAO_OK;
 }
 

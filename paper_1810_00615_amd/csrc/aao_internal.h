@@ -44,17 +44,30 @@ hipError_t launch_twiddles(double *tw, int len, int count, hipStream_t st);
 // spec rows j = 0..ell/2 (complex, leading dimension lds, element type
 // float2/double2 according to `single`).
 // in_scale (device scalar or nullptr) multiplies r.
+// cfg: launch shape (16 v + log2 W, see fft_configs), negative = default.
 hipError_t launch_fft_fwd(const double *r, const double *in_scale, const double *zprev,
                           const double *sigk, double kappa, int n, int ell, void *spec, int lds,
-                          bool single, const double *tw, hipStream_t st);
+                          bool single, const double *tw, hipStream_t st, int cfg = -1);
 // Inverse of the above: z (ell x n real) from the half spectrum.
 hipError_t launch_fft_inv(const void *spec, int lds, bool single, double *z, int n, int ell,
-                          const double *tw, hipStream_t st);
+                          const double *tw, hipStream_t st, int cfg = -1);
+// Admissible launch shapes of the power-of-two transforms for (ell, n, element
+// type): writes up to cap of them to out, returns how many there are (0 when ell
+// is not a supported power of two).
+int fft_configs(int ell, int n, bool single, int *out, int cap);
+bool fft_config_ok(int cfg, int ell, int n, bool single);
 // In-place shifted solves (alpha_j M + beta_j kappa K) Y_j = X_j for every
 // half-spectrum row j; `single_arith` selects single-precision arithmetic.
+// cfg selects the launch shape (chunk, threads, LDS staging) among
+// solve_num_configs(); a value that is out of range or does not cover n selects
+// solve_default_config(n).
 hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
                                 int n, int ell, Scheme sc, double kappa, int transpose,
-                                int *fail_flag, hipStream_t st);
+                                int *fail_flag, hipStream_t st, int cfg = -1);
+int solve_num_configs();
+bool solve_config_ok(int cfg, int n);
+void solve_config_shape(int cfg, int *cw, int *nt, int *stage);
+int solve_default_config(int n);
 bool fft_supported_fast(int ell);
 // Heat trajectory recomputed from checkpoints (every `stride` rows) while
 // accumulating part[seg] = sum_k tau_k lam_k . K u_k over each segment.
@@ -66,7 +79,10 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
 // If bsub != nullptr computes y = bsub - A x.
 hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
                          Scheme sc, double kappa, const double *tau_k, int transpose,
-                         hipStream_t st);
+                         hipStream_t st, int cfg = -1);
+// matvec launch shapes: code = 3 v + r (R = 4 << r rows per thread, v = 1: DPP lane moves)
+int matvec_num_configs();
+int matvec_default_config();
 hipError_t launch_project_sine(double *u0, int n, int J, const int *modes, const double *amps,
                                hipStream_t st);
 hipError_t launch_build_rhs(double *b, const double *u0, const double *v0, int n, int ell,

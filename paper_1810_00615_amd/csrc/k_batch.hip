@@ -241,10 +241,9 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
     constexpr int CW = 8;
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
-    cx<A> *s_ip = reinterpret_cast<cx<A> *>(smraw);
-    cx<A> *s_cp = s_ip + CW;
-    cx<S> *stage = reinterpret_cast<cx<S> *>(s_cp + CW);
-    cx<A> *red = reinterpret_cast<cx<A> *>(s_cp + CW);
+    cx<A> *tab = reinterpret_cast<cx<A> *>(smraw);
+    cx<A> *red = tab + 3 * CW;
+    cx<S> *stage = reinterpret_cast<cx<S> *>(red);
     const int g = blockIdx.x;
     if (g >= nrows) return;
     const int2 e = rows[g];
@@ -280,7 +279,7 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
             y[i] = {A(v.x), A(v.y)};
         }
     }
-    const bool bad = partition_solve<A, CW>(y, n, d, ee, s_ip, s_cp, red);
+    const bool bad = partition_solve<A, CW>(y, n, d, ee, tab, red);
 #pragma unroll
     for (int i = 0; i < CW; ++i)
         if (i < len) stage[i * NTP + t] = {S(y[i].x), S(y[i].y)};
@@ -630,8 +629,8 @@ static size_t bl_smem(size_t realsz)
 static size_t solve_smem(size_t es, size_t as)
 {
     const int NT = 512, CW = 8;
-    const size_t stage = es * CW * (NT + 4), redb = as * 7 * NT;
-    return as * 2 * CW + (stage > redb ? stage : redb);
+    const size_t stage = es * CW * (NT + 4), redb = as * 6 * NT;
+    return as * 3 * CW + (stage > redb ? stage : redb);
 }
 
 // Dynamic-LDS limits of the batched kernels, set once before any graph capture.

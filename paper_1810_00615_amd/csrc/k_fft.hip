@@ -16,8 +16,6 @@
 //   X_j = (Z_j + conj Z_{L-j})/2 - (i/2) w^j (Z_j - conj Z_{L-j}),  j = 0..L,
 // with w = exp(-2 pi i / ell).  The inverse runs the same steps backwards.
 // Lengths that are not powers of two use a direct-DFT kernel.
-#include <cstdlib>
-
 #include "fft_core.h"
 
 namespace aao {
@@ -232,29 +230,57 @@ hipError_t launch_twiddles(double *tw, int len, int count, hipStream_t st)
 
 bool fft_supported_fast(int ell) { return ell >= 2 && ell <= 16384 && (ell & (ell - 1)) == 0; }
 
-static int pick_w(int L, int P, int n, size_t realsz)
+// Launch shape of the power-of-two transforms: cfg = 16 v + log2 W, where W is the
+// tile width (columns per workgroup) and v selects the points per thread P
+// (v = 0: P = min(L, 16), radix-16 stages; v = 1: P = 8, radix-8 stages, offered
+// for L = 512..4096).  A negative cfg selects the default.
+static bool w_ok(int L, int P, int w, size_t realsz)
 {
-    const int tn = L / P;
-    if (const char *e = getenv("AAO_FFT_W")) {
-        int w = atoi(e);
-        if (w >= 1 && w <= 64 && (w & (w - 1)) == 0 && w * tn <= 1024 &&
-            (size_t)w * lds_rows(L) * realsz <= 160 * 1024)
-            return w;
-    }
+    return w >= 1 && w <= 64 && w * (L / P) <= 1024 && (size_t)w * lds_rows(L) * realsz <= 160 * 1024;
+}
+
+static int default_w(int L, int P, int n, size_t realsz)
+{
     int w = 1;
-    while (w < 64 && 2 * w * tn <= 1024 && (size_t)2 * w * lds_rows(L) * realsz <= 160 * 1024 &&
-           (w < 8 || w < n))
-        w *= 2;
+    while (w < 64 && w_ok(L, P, 2 * w, realsz) && (w < 8 || w < n)) w *= 2;
     return w;
 }
 
-template <typename T, int L>
-static hipError_t fwd_L(const double *r, const double *in_scale, const double *zprev,
-                        const double *sigk, double kap_h, int n, void *spec, int lds,
-                        const double *tw, hipStream_t st)
+static bool has_p8(int L) { return L >= 512 && L <= 4096; }
+
+int fft_configs(int ell, int n, bool single, int *out, int cap)
 {
-    constexpr int P = L < 16 ? L : 16;
-    const int W = pick_w(L, P, n, sizeof(T));
+    if (!fft_supported_fast(ell)) return 0;
+    const int L = ell / 2;
+    const size_t rs = single ? sizeof(float) : sizeof(double);
+    int k = 0;
+    for (int v = 0; v < 2; ++v) {
+        if (v == 1 && !has_p8(L)) break;
+        const int P = v ? 8 : (L < 16 ? L : 16);
+        for (int lw = 0; lw <= 6; ++lw) {
+            const int w = 1 << lw;
+            if (!w_ok(L, P, w, rs) || (w > 1 && (w / 2) >= n)) continue;
+            if (out && k < cap) out[k] = 16 * v + lw;
+            ++k;
+        }
+    }
+    return k;
+}
+
+bool fft_config_ok(int cfg, int ell, int n, bool single)
+{
+    int list[16];
+    const int k = fft_configs(ell, n, single, list, 16);
+    for (int i = 0; i < k && i < 16; ++i)
+        if (list[i] == cfg) return true;
+    return false;
+}
+
+template <typename T, int L, int P>
+static hipError_t fwd_LP(const double *r, const double *in_scale, const double *zprev,
+                         const double *sigk, double kap_h, int n, void *spec, int lds,
+                         const double *tw, hipStream_t st, int W)
+{
     const size_t smem = (size_t)lds_rows(L) * W * sizeof(T);
     auto kern = zprev ? k_fft_fwd<T, L, P, true> : k_fft_fwd<T, L, P, false>;
     if (smem > 64 * 1024) {
@@ -270,11 +296,25 @@ static hipError_t fwd_L(const double *r, const double *in_scale, const double *z
 }
 
 template <typename T, int L>
-static hipError_t inv_L(const void *spec, int lds, double *z, int n, const double *tw,
-                        hipStream_t st)
+static hipError_t fwd_L(const double *r, const double *in_scale, const double *zprev,
+                        const double *sigk, double kap_h, int n, void *spec, int lds,
+                        const double *tw, hipStream_t st, int cfg)
 {
-    constexpr int P = L < 16 ? L : 16;
-    const int W = pick_w(L, P, n, sizeof(T));
+    constexpr int P16 = L < 16 ? L : 16;
+    if (cfg >= 16) {
+        if constexpr (L >= 512 && L <= 4096)
+            return fwd_LP<T, L, 8>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st,
+                                   1 << (cfg & 15));
+        return hipErrorInvalidValue;
+    }
+    const int W = cfg >= 0 ? 1 << cfg : default_w(L, P16, n, sizeof(T));
+    return fwd_LP<T, L, P16>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st, W);
+}
+
+template <typename T, int L, int P>
+static hipError_t inv_LP(const void *spec, int lds, double *z, int n, const double *tw,
+                         hipStream_t st, int W)
+{
     const size_t smem = (size_t)lds_rows(L) * W * sizeof(T);
     auto kern = k_fft_inv<T, L, P>;
     if (smem > 64 * 1024) {
@@ -288,14 +328,28 @@ static hipError_t inv_L(const void *spec, int lds, double *z, int n, const doubl
     return hipGetLastError();
 }
 
+template <typename T, int L>
+static hipError_t inv_L(const void *spec, int lds, double *z, int n, const double *tw,
+                        hipStream_t st, int cfg)
+{
+    constexpr int P16 = L < 16 ? L : 16;
+    if (cfg >= 16) {
+        if constexpr (L >= 512 && L <= 4096)
+            return inv_LP<T, L, 8>(spec, lds, z, n, tw, st, 1 << (cfg & 15));
+        return hipErrorInvalidValue;
+    }
+    const int W = cfg >= 0 ? 1 << cfg : default_w(L, P16, n, sizeof(T));
+    return inv_LP<T, L, P16>(spec, lds, z, n, tw, st, W);
+}
+
 template <typename T>
 static hipError_t fwd_dispatch(const double *r, const double *in_scale, const double *zprev,
                                const double *sigk, double kap_h, int n, int ell, void *spec,
-                               int lds, const double *tw, hipStream_t st)
+                               int lds, const double *tw, hipStream_t st, int cfg)
 {
     switch (ell) {
 #define AAO_CASE(E) \
-    case E: return fwd_L<T, E / 2>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st);
+    case E: return fwd_L<T, E / 2>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st, cfg);
         AAO_CASE(2) AAO_CASE(4) AAO_CASE(8) AAO_CASE(16) AAO_CASE(32) AAO_CASE(64)
         AAO_CASE(128) AAO_CASE(256) AAO_CASE(512) AAO_CASE(1024) AAO_CASE(2048)
         AAO_CASE(4096) AAO_CASE(8192) AAO_CASE(16384)
@@ -311,11 +365,11 @@ static hipError_t fwd_dispatch(const double *r, const double *in_scale, const do
 
 template <typename T>
 static hipError_t inv_dispatch(const void *spec, int lds, double *z, int n, int ell,
-                               const double *tw, hipStream_t st)
+                               const double *tw, hipStream_t st, int cfg)
 {
     switch (ell) {
 #define AAO_CASE(E) \
-    case E: return inv_L<T, E / 2>(spec, lds, z, n, tw, st);
+    case E: return inv_L<T, E / 2>(spec, lds, z, n, tw, st, cfg);
         AAO_CASE(2) AAO_CASE(4) AAO_CASE(8) AAO_CASE(16) AAO_CASE(32) AAO_CASE(64)
         AAO_CASE(128) AAO_CASE(256) AAO_CASE(512) AAO_CASE(1024) AAO_CASE(2048)
         AAO_CASE(4096) AAO_CASE(8192) AAO_CASE(16384)
@@ -330,19 +384,22 @@ static hipError_t inv_dispatch(const void *spec, int lds, double *z, int n, int 
 
 hipError_t launch_fft_fwd(const double *r, const double *in_scale, const double *zprev,
                           const double *sigk, double kappa, int n, int ell, void *spec, int lds,
-                          bool single, const double *tw, hipStream_t st)
+                          bool single, const double *tw, hipStream_t st, int cfg)
 {
+    if (cfg >= 0 && !fft_config_ok(cfg, ell, n, single)) cfg = -1;
     const double kap_h = kappa * (n + 1.0);   // kappa / h
-    return single ? fwd_dispatch<float>(r, in_scale, zprev, sigk, kap_h, n, ell, spec, lds, tw, st)
+    return single ? fwd_dispatch<float>(r, in_scale, zprev, sigk, kap_h, n, ell, spec, lds, tw, st,
+                                        cfg)
                   : fwd_dispatch<double>(r, in_scale, zprev, sigk, kap_h, n, ell, spec, lds, tw,
-                                         st);
+                                         st, cfg);
 }
 
 hipError_t launch_fft_inv(const void *spec, int lds, bool single, double *z, int n, int ell,
-                          const double *tw, hipStream_t st)
+                          const double *tw, hipStream_t st, int cfg)
 {
-    return single ? inv_dispatch<float>(spec, lds, z, n, ell, tw, st)
-                  : inv_dispatch<double>(spec, lds, z, n, ell, tw, st);
+    if (cfg >= 0 && !fft_config_ok(cfg, ell, n, single)) cfg = -1;
+    return single ? inv_dispatch<float>(spec, lds, z, n, ell, tw, st, cfg)
+                  : inv_dispatch<double>(spec, lds, z, n, ell, tw, st, cfg);
 }
 
 }  // namespace aao

@@ -22,27 +22,44 @@
 
 namespace aao {
 
-template <typename A, typename S, int CW, int NTB>
+// One workgroup per frequency row.  STAGE: the row passes through LDS so that the
+// global accesses are coalesced (element i of chunk t in slot i*(NT+PAD) + t, PAD
+// = 2 for 16-byte and 4 for 8-byte elements, which spreads both the chunk-wise and
+// the coalesced accesses over all banks); otherwise every thread reads and writes
+// its own chunk directly.
+template <typename A, typename S, int CW, int NTB, bool STAGE>
 __global__ void __launch_bounds__(NTB)
 k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, double kappa,
                 int transpose, int *__restrict__ fail)
 {
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
-    cx<A> *s_ip = reinterpret_cast<cx<A> *>(smraw);   // 1/pivot of the interior elimination
-    cx<A> *s_cp = s_ip + CW;                            // e / pivot
-    // The row is staged through LDS so that global accesses are coalesced while
-    // each thread works on CW contiguous unknowns.  Element i of chunk t sits in
-    // slot i*(NT+PAD) + t: the chunk reads (consecutive t) and the coalesced writes
-    // (CW consecutive lanes = one chunk) both spread over all banks with PAD = 2
-    // (16-byte elements) or 4 (8-byte elements).  The reduced-system arrays reuse
-    // the same space once the chunks are in registers.
-    cx<S> *stage = reinterpret_cast<cx<S> *>(s_cp + CW);
-    cx<A> *red = reinterpret_cast<cx<A> *>(s_cp + CW);
+    cx<A> *tab = reinterpret_cast<cx<A> *>(smraw);
+    cx<A> *red = tab + 3 * CW;
+    cx<S> *stage = reinterpret_cast<cx<S> *>(red);
 
     const int j = blockIdx.x;
     const int t = threadIdx.x;
     cx<S> *row = spec + (size_t)j * lds;
+
+    const int P = (n + CW - 1) / CW;
+    const int a0 = t * CW;
+    const int len = (t < P) ? min(CW, n - a0) : 0;
+    constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
+    const int NTP = NT + PAD;
+    if (STAGE) {
+        for (int q = t; q < n; q += NT) stage[(q % CW) * NTP + q / CW] = row[q];
+        __syncthreads();
+    }
+    cx<A> y[CW];
+#pragma unroll
+    for (int i = 0; i < CW; ++i) {
+        y[i] = {A(0), A(0)};
+        if (i < len) {
+            const cx<S> v = STAGE ? stage[i * NTP + t] : row[a0 + i];
+            y[i] = {A(v.x), A(v.y)};
+        }
+    }
 
     // symbol of frequency j
     double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
@@ -60,69 +77,122 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
                      A(ai * (4.0 * h / 6.0) + bi * kappa * (2.0 / h))};
     const cx<A> e = {A(ar * (h / 6.0) - br * kappa / h), A(ai * (h / 6.0) - bi * kappa / h)};
 
-    constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
-    const int NTP = NT + PAD;
-    const int P = (n + CW - 1) / CW;
-    const int len = (t < P) ? min(CW, n - t * CW) : 0;
-    for (int q = t; q < n; q += NT) stage[(q % CW) * NTP + q / CW] = row[q];
-    __syncthreads();
-    cx<A> y[CW];
+    const bool bad = partition_solve<A, CW>(y, n, d, e, tab, red);
+    if (STAGE) {
 #pragma unroll
-    for (int i = 0; i < CW; ++i) {
-        y[i] = {A(0), A(0)};
-        if (i < len) {
-            const cx<S> v = stage[i * NTP + t];
-            y[i] = {A(v.x), A(v.y)};
-        }
+        for (int i = 0; i < CW; ++i)
+            if (i < len) stage[i * NTP + t] = {S(y[i].x), S(y[i].y)};
+        __syncthreads();
+        for (int q = t; q < n; q += NT) row[q] = stage[(q % CW) * NTP + q / CW];
+    } else {
+#pragma unroll
+        for (int i = 0; i < CW; ++i)
+            if (i < len) row[a0 + i] = {S(y[i].x), S(y[i].y)};
     }
-    const bool bad = partition_solve<A, CW>(y, n, d, e, s_ip, s_cp, red);
-#pragma unroll
-    for (int i = 0; i < CW; ++i)
-        if (i < len) stage[i * NTP + t] = {S(y[i].x), S(y[i].y)};
-    __syncthreads();
-    for (int q = t; q < n; q += NT) row[q] = stage[(q % CW) * NTP + q / CW];
     if (bad && fail) atomicOr(fail, 1);
 }
 
-template <typename A, typename S>
-static hipError_t solve_disp(void *spec, int lds, int n, int ell, Scheme sc, double kappa,
-                             int transpose, int *fail, hipStream_t st)
+// Launch configurations {chunk CW, threads NT}; configuration k < kNumSolveCfg
+// reads chunks directly, k + kNumSolveCfg stages the row through LDS.  A row of n
+// unknowns needs n <= CW * NT.
+static const int kSolveCfg[][2] = {{1, 256}, {2, 256}, {4, 256}, {8, 256}, {8, 512},
+                                   {8, 1024}, {16, 128}, {16, 256}, {16, 512}, {16, 1024},
+                                   {32, 128}, {32, 256}};
+constexpr int kNumSolveCfg = sizeof(kSolveCfg) / sizeof(kSolveCfg[0]);
+
+int solve_num_configs() { return 2 * kNumSolveCfg; }
+
+// LDS bytes of a configuration, for 16-byte complex elements (the largest case)
+static size_t solve_lds_bytes(int cw, int nt, bool stage)
 {
-    // chunks of at most 8 unknowns per thread where possible (register budget)
-    const int NT = n <= 2048 ? 256 : (n <= 4096 ? 512 : 1024);
-    int cw = 1;
-    while (cw * NT < n) cw *= 2;
-    if (cw > 16) return hipErrorInvalidValue;
-    const int H = ell / 2 + 1;
-    const size_t stage_bytes = sizeof(cx<S>) * (size_t)cw * (NT + 4);
-    const size_t red_bytes = sizeof(cx<A>) * 7 * (size_t)NT;
-    const size_t smem = sizeof(cx<A>) * 2 * (size_t)cw + (stage_bytes > red_bytes ? stage_bytes : red_bytes);
-    cx<S> *sp = reinterpret_cast<cx<S> *>(spec);
-    auto go = [&](auto kern) -> hipError_t {
-        if (smem > 64 * 1024) {
-            hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)smem);
-            if (e != hipSuccess) return e;
-        }
-        kern<<<H, NT, smem, st>>>(sp, lds, n, ell, sc, kappa, transpose, fail);
-        return hipGetLastError();
-    };
-    if (NT == 256) {
-        switch (cw) {
-        case 1: return go(k_shifted_solve<A, S, 1, 256>);
-        case 2: return go(k_shifted_solve<A, S, 2, 256>);
-        case 4: return go(k_shifted_solve<A, S, 4, 256>);
-        case 8: return go(k_shifted_solve<A, S, 8, 256>);
-        default: return go(k_shifted_solve<A, S, 16, 256>);
-        }
+    const size_t red = 16 * (size_t)psolve_lds_entries(cw, nt);
+    const size_t stg = 16 * (3 * (size_t)cw + (size_t)cw * (nt + 2));
+    return stage && stg > red ? stg : red;
+}
+
+bool solve_config_ok(int cfg, int n)
+{
+    if (cfg < 0 || cfg >= 2 * kNumSolveCfg) return false;
+    const int k = cfg % kNumSolveCfg;
+    return n <= kSolveCfg[k][0] * kSolveCfg[k][1] &&
+           solve_lds_bytes(kSolveCfg[k][0], kSolveCfg[k][1], cfg >= kNumSolveCfg) <= 160 * 1024;
+}
+
+void solve_config_shape(int cfg, int *cw, int *nt, int *stage)
+{
+    const int k = cfg % kNumSolveCfg;
+    *cw = kSolveCfg[k][0];
+    *nt = kSolveCfg[k][1];
+    *stage = cfg >= kNumSolveCfg;
+}
+
+// default: the staged configuration with the smallest chunk (then the fewest
+// threads) that covers n with at most 512 threads; beyond that the widest
+// configuration that fits
+int solve_default_config(int n)
+{
+    int best = -1;
+    for (int k = 0; k < kNumSolveCfg; ++k) {
+        const int cw = kSolveCfg[k][0], nt = kSolveCfg[k][1];
+        if (nt > 512 || !solve_config_ok(k + kNumSolveCfg, n)) continue;
+        if (best < 0 || cw < kSolveCfg[best][0] ||
+            (cw == kSolveCfg[best][0] && nt < kSolveCfg[best][1]))
+            best = k;
     }
-    if (NT == 512) {
-        if (cw <= 8) return go(k_shifted_solve<A, S, 8, 512>);
-        return go(k_shifted_solve<A, S, 16, 512>);
+    if (best >= 0) return best + kNumSolveCfg;
+    for (int c = 2 * kNumSolveCfg - 1; c >= 0; --c)
+        if (solve_config_ok(c, n)) return c;
+    return -1;
+}
+
+template <typename A, typename S, int CW, int NT, bool STAGE>
+static hipError_t solve_go(void *spec, int lds, int n, int ell, Scheme sc, double kappa,
+                           int transpose, int *fail, hipStream_t st)
+{
+    size_t smem = sizeof(cx<A>) * psolve_lds_entries(CW, NT);
+    if (STAGE) {
+        constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
+        const size_t stg = sizeof(cx<A>) * 3 * CW + sizeof(cx<S>) * CW * (NT + PAD);
+        if (stg > smem) smem = stg;
     }
-    if (cw <= 8) return go(k_shifted_solve<A, S, 8, 1024>);
-    return go(k_shifted_solve<A, S, 16, 1024>);
+    auto kern = k_shifted_solve<A, S, CW, NT, STAGE>;
+    if (smem > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    kern<<<ell / 2 + 1, NT, smem, st>>>(reinterpret_cast<cx<S> *>(spec), lds, n, ell, sc, kappa,
+                                        transpose, fail);
+    return hipGetLastError();
+}
+
+template <typename A, typename S>
+static hipError_t solve_disp(int cfg, void *spec, int lds, int n, int ell, Scheme sc,
+                             double kappa, int transpose, int *fail, hipStream_t st)
+{
+    const bool stage = cfg >= kNumSolveCfg;
+#define AAO_SCFG(I, CW, NT)                                                                    \
+    case I:                                                                                    \
+        return stage ? solve_go<A, S, CW, NT, true>(spec, lds, n, ell, sc, kappa, transpose,   \
+                                                    fail, st)                                  \
+                     : solve_go<A, S, CW, NT, false>(spec, lds, n, ell, sc, kappa, transpose,  \
+                                                     fail, st);
+    switch (cfg % kNumSolveCfg) {
+        AAO_SCFG(0, 1, 256)
+        AAO_SCFG(1, 2, 256)
+        AAO_SCFG(2, 4, 256)
+        AAO_SCFG(3, 8, 256)
+        AAO_SCFG(4, 8, 512)
+        AAO_SCFG(5, 8, 1024)
+        AAO_SCFG(6, 16, 128)
+        AAO_SCFG(7, 16, 256)
+        AAO_SCFG(8, 16, 512)
+        AAO_SCFG(9, 16, 1024)
+        AAO_SCFG(10, 32, 128)
+        AAO_SCFG(11, 32, 256)
+    default: return hipErrorInvalidValue;
+    }
+#undef AAO_SCFG
 }
 
 // ------------------------------------------------- checkpoint recomputation
@@ -142,10 +212,9 @@ k_heat_segments(const double *__restrict__ u0, const double *__restrict__ Uck, i
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
     const int t = threadIdx.x;
-    cx<double> *s_ip = reinterpret_cast<cx<double> *>(smraw);
-    cx<double> *s_cp = s_ip + CW;
-    cx<double> *red = s_cp + CW;                            // 7*NT entries
-    double *edge = reinterpret_cast<double *>(red + 7 * NT); // first/last value of every chunk
+    cx<double> *tab = reinterpret_cast<cx<double> *>(smraw);
+    cx<double> *red = tab + 3 * CW;                         // 6*NT entries
+    double *edge = reinterpret_cast<double *>(red + 6 * NT); // first/last value of every chunk
     __shared__ double wsum[16];
 
     const int seg = blockIdx.x;
@@ -195,7 +264,7 @@ k_heat_segments(const double *__restrict__ u0, const double *__restrict__ Uck, i
         }
         const cx<double> d = {4.0 * h / 6.0 + tk * kappa * 2.0 / h, 0.0};
         const cx<double> e = {h / 6.0 - tk * kappa / h, 0.0};
-        bad |= partition_solve<double, CW>(y, n, d, e, s_ip, s_cp, red);
+        bad |= partition_solve<double, CW>(y, n, d, e, tab, red);
 #pragma unroll
         for (int i = 0; i < CW; ++i) u[i] = (i < len) ? y[i].x : 0.0;
         if (Uout) {
@@ -237,7 +306,7 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
     while (cw * NT < n) cw *= 2;
     if (cw > 16) return hipErrorInvalidValue;
     const int nseg = (ell + stride - 1) / stride;
-    const size_t smem = sizeof(cx<double>) * (2 * (size_t)cw + 7 * NT) + sizeof(double) * 2 * NT;
+    const size_t smem = sizeof(cx<double>) * psolve_lds_entries(cw, NT) + sizeof(double) * 2 * NT;
     auto go = [&](auto kern) -> hipError_t {
         if (smem > 64 * 1024) {
             hipError_t e = hipFuncSetAttribute((const void *)kern,
@@ -260,13 +329,15 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
 
 hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
                                 int n, int ell, Scheme sc, double kappa, int transpose,
-                                int *fail_flag, hipStream_t st)
+                                int *fail_flag, hipStream_t st, int cfg)
 {
+    if (!solve_config_ok(cfg, n)) cfg = solve_default_config(n);
+    if (!solve_config_ok(cfg, n)) return hipErrorInvalidValue;
     if (!single_store)
-        return solve_disp<double, double>(spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
+        return solve_disp<double, double>(cfg, spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
     if (!single_arith)
-        return solve_disp<double, float>(spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
-    return solve_disp<float, float>(spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
+        return solve_disp<double, float>(cfg, spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
+    return solve_disp<float, float>(cfg, spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
 }
 
 }  // namespace aao

@@ -284,69 +284,146 @@ hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double 
 // y_k = sum_{m=0}^{s} (a_m M + b_m^{(k)} kappa K) x_{k-m}   (x_{k+m} if transposed)
 // with b_0^{(k)} = tau_k when variable steps are given.  y = bsub - A x if bsub.
 //
-// Each thread owns one spatial column and walks MV_ROWS consecutive time levels,
-// keeping the last s+1 input rows in registers, so every input element is read
-// once from memory (plus s halo rows per block); the i +- 1 neighbours are
-// served by the cache lines the same wave instruction already brings in.
-constexpr int MV_ROWS = 16;
+// Each thread owns one spatial column and R consecutive output time levels; the
+// R + S input rows it needs (S = scheme order) are all loaded before any output
+// is formed, one aligned load per row, so the loads of a lane are in flight
+// together.  The i -+ 1 neighbours come from the adjacent lanes by a cross-lane
+// move (DPP wave shift when DPP is set, else ds_bpermute); lanes 0 and 63 fetch
+// the neighbour outside their wave with a second, two-lane load.
+template <bool DPP>
+__device__ __forceinline__ double lane_from_left(double v)
+{
+    if constexpr (DPP) {
+        // wave_shr:1 -- lane j receives lane j-1
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+        return __hiloint2double(hi, lo);
+    } else {
+        return __shfl_up(v, 1, 64);
+    }
+}
+template <bool DPP>
+__device__ __forceinline__ double lane_from_right(double v)
+{
+    if constexpr (DPP) {
+        // wave_shl:1 -- lane j receives lane j+1
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+        return __hiloint2double(hi, lo);
+    } else {
+        return __shfl_down(v, 1, 64);
+    }
+}
 
+template <int S, int R, bool DPP>
 __global__ void __launch_bounds__(256)
 k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
          int n, int ell, Scheme sc, double kappa, const double *__restrict__ tau_k, int transpose)
 {
+    const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const bool col = i < n;          // lanes past n still take part in the lane moves
     const double h = 1.0 / (n + 1.0);
-    const int k0 = blockIdx.y * MV_ROWS;
-    const int k1 = min(k0 + MV_ROWS, ell);          // output rows [k0, k1)
-    const int s = sc.s;
-    const int nin = (k1 - k0) + s;                  // input rows touched by the block
-    // every input row of the block is loaded before any output is formed, so all
-    // loads of a lane are in flight together; the i +- 1 loads hit the same lines
-    constexpr int NR = MV_ROWS + 3;
-    double rl[NR], rc[NR], rr[NR];
+    const int k0 = blockIdx.y * R;
+    const int k1 = min(k0 + R, ell);                // output rows [k0, k1)
+    const int nin = (k1 - k0) + S;                  // input rows touched by the block
+    constexpr int NR = R + S;
+    const int je = lane == 0 ? i - 1 : i + 1;       // outside neighbour of lanes 0 / 63
+    const bool edge = (lane == 0 || lane == 63) && je >= 0 && je < n;
+    double c[NR], e[NR];
 #pragma unroll
     for (int it = 0; it < NR; ++it) {
-        const int kk = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
+        const int kk = transpose ? (k1 - 1 + S - it) : (k0 - S + it);
         const bool in = it < nin && kk >= 0 && kk < ell;
         const double *row = x + (size_t)(in ? kk : 0) * n;
-        rc[it] = in ? row[i] : 0.0;
-        rl[it] = (in && i > 0) ? row[i - 1] : 0.0;
-        rr[it] = (in && i + 1 < n) ? row[i + 1] : 0.0;
+        c[it] = (in && col) ? row[i] : 0.0;
+        e[it] = (in && edge) ? row[je] : 0.0;
     }
+    // l, c, r of the last S+1 input rows; the time combination is formed before
+    // the space stencil, so that cancelling time differences (BD2: x_k - 2 x_{k-1}
+    // + x_{k-2}) are taken on the raw values
+    double wl[S + 1] = {}, wc[S + 1] = {}, wr[S + 1] = {};
 #pragma unroll
     for (int it = 0; it < NR; ++it) {
-        if (it < s || it >= nin) continue;
-        // output row k; input row k -+ m sits at it - m
-        const int k = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
+        double l = lane_from_left<DPP>(c[it]);
+        double r = lane_from_right<DPP>(c[it]);
+        if (lane == 0) l = e[it];
+        if (lane == 63) r = e[it];
+#pragma unroll
+        for (int m = S; m > 0; --m) {
+            wl[m] = wl[m - 1];
+            wc[m] = wc[m - 1];
+            wr[m] = wr[m - 1];
+        }
+        wl[0] = l;
+        wc[0] = c[it];
+        wr[0] = r;
+        if (it < S || it >= nin) continue;
+        // output row k uses input rows k -+ m, m = 0..S
+        const int k = transpose ? (k1 - 1 + S - it) : (k0 - S + it);
         double al = 0.0, ac = 0.0, ar = 0.0, bl = 0.0, bc = 0.0, br = 0.0;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m > s || it - m < 0) break;
+        for (int m = 0; m <= S; ++m) {
             const double am = sc.a[m];
             double bm = sc.b[m];
             if (m == 0 && tau_k) bm = tau_k[k];
             bm *= kappa;
-            al += am * rl[it - m];
-            ac += am * rc[it - m];
-            ar += am * rr[it - m];
-            bl += bm * rl[it - m];
-            bc += bm * rc[it - m];
-            br += bm * rr[it - m];
+            al += am * wl[m];
+            ac += am * wc[m];
+            ar += am * wr[m];
+            bl += bm * wl[m];
+            bc += bm * wc[m];
+            br += bm * wr[m];
         }
         const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
-        const size_t o = (size_t)k * n + i;
-        y[o] = bsub ? bsub[o] - v : v;
+        if (col) {
+            const size_t o = (size_t)k * n + i;
+            y[o] = bsub ? bsub[o] - v : v;
+        }
     }
+}
+
+// Launch shapes: code = 3 v + r, R = 4 << r rows per thread, v = 1 for DPP lane
+// moves, v = 0 for ds_bpermute.
+int matvec_num_configs() { return 6; }
+int matvec_default_config() { return 3 + 2; }
+
+template <int S>
+static hipError_t matvec_disp(int cfg, const double *x, double *y, const double *bsub, int n,
+                              int ell, Scheme sc, double kappa, const double *tau_k,
+                              int transpose, hipStream_t st)
+{
+    const int R = 4 << (cfg % 3);
+    dim3 grid((n + 255) / 256, (ell + R - 1) / R);
+#define AAO_MV(C, RR, D)                                                                    \
+    case C:                                                                                 \
+        k_matvec<S, RR, D><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, tau_k,      \
+                                                 transpose);                                \
+        break;
+    switch (cfg) {
+        AAO_MV(0, 4, false)
+        AAO_MV(1, 8, false)
+        AAO_MV(2, 16, false)
+        AAO_MV(3, 4, true)
+        AAO_MV(4, 8, true)
+        AAO_MV(5, 16, true)
+    default: return hipErrorInvalidValue;
+    }
+#undef AAO_MV
+    return hipGetLastError();
 }
 
 hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
                          Scheme sc, double kappa, const double *tau_k, int transpose,
-                         hipStream_t st)
+                         hipStream_t st, int cfg)
 {
-    dim3 grid((n + 255) / 256, (ell + MV_ROWS - 1) / MV_ROWS);
-    k_matvec<<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, tau_k, transpose);
-    return hipGetLastError();
+    if (cfg < 0 || cfg >= matvec_num_configs()) cfg = matvec_default_config();
+    switch (sc.s) {
+    case 1: return matvec_disp<1>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, st);
+    case 2: return matvec_disp<2>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, st);
+    case 3: return matvec_disp<3>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // y = (cm M + ck K) x (+ (cm2 M + ck2 K) x2), one n-vector

@@ -7,28 +7,47 @@
 
 namespace aao {
 
-// Partition solve of tridiag(e, d, e) x = r with n unknowns by one workgroup.
-// Thread t owns unknowns [t*CW, t*CW + len); y[] holds its part of r on entry and
-// of x on exit.  s_ip / s_cp: CW entries of LDS each; red: 7*NT entries of LDS
-// (may alias a staging area the caller has finished reading: the first barrier
-// below precedes every write to it, and the last barrier follows every read).
-// Every thread of the block must call it.  Returns true if a value is not finite.
+// LDS needed by partition_solve: tables (3 CW) + reduced system (6 NT) entries.
+__host__ __device__ constexpr int psolve_lds_entries(int CW, int NT) { return 3 * CW + 6 * NT; }
+
+// Solve tridiag(e, d, e) x = r with n unknowns.  Thread t owns unknowns
+// [t*CW, t*CW + len); y[] holds its part of r on entry and of x on exit.
+//
+// Chunk t is split into an interior (its first len-1 unknowns) and a separator
+// (its last unknown).  With the interior eliminated, x_i = y_i + u_i X_{t-1} +
+// v_i X_t, where y is the interior solution with zero neighbours and u, v its
+// responses to the left / right separator.  Because the matrix is Toeplitz, the
+// elimination factors (1/pivot, e/pivot) and the forward part of u are the same
+// for every chunk: one thread tabulates them per row in LDS and every thread
+// regenerates u and v backwards from the table, so a thread keeps only y in
+// registers.  The separators satisfy a tridiagonal system (one equation per
+// chunk), solved by parallel cyclic reduction with every equation normalised to
+// a unit diagonal (one complex reciprocal per equation and step).
+//
+// tab: 3*CW entries of LDS; red: 6*NT entries (may alias a staging area the caller
+// has finished reading: the first barrier below precedes every write to it, and
+// the last barrier follows every read).  Every thread of the block must call it.
+// Returns true if a value is not finite.
 template <typename A, int CW>
-__device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *s_ip,
-                                cx<A> *s_cp, cx<A> *red)
+__device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *tab, cx<A> *red)
 {
     const int NT = blockDim.x;
     const int t = threadIdx.x;
-    cx<A> *pa = red, *pb = red + NT, *pc = red + 2 * NT, *pd = red + 3 * NT, *nb = red + 4 * NT;
+    cx<A> *s_ip = tab, *s_cp = tab + CW, *s_gu = tab + 2 * CW;
+    cx<A> *pa = red, *pc = red + NT, *pd = red + 2 * NT, *nb = red + 3 * NT;
     const cx<A> zero = {A(0), A(0)};
     const cx<A> me = {-e.x, -e.y};
     if (t == 0) {
-        cx<A> cprev = zero;
+        // pivots of the interior elimination and the forward part of u (the
+        // response to -e in the first interior equation)
+        cx<A> cprev = zero, g = zero;
         for (int i = 0; i < CW - 1; ++i) {
             const cx<A> ip = recip(d - e * cprev);
             s_ip[i] = ip;
             cprev = e * ip;
             s_cp[i] = cprev;
+            g = (i == 0) ? me * ip : (me * g) * ip;
+            s_gu[i] = g;
         }
     }
     __syncthreads();
@@ -38,56 +57,48 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
     const int len = (t < P) ? min(CW, n - a0) : 0;
     const int mi = len - 1;                              // interior length (may be 0)
 
-    cx<A> u[CW];
     cx<A> rsep = zero;
 #pragma unroll
-    for (int i = 0; i < CW; ++i) {
-        u[i] = zero;
+    for (int i = 0; i < CW; ++i)
         if (i == mi) rsep = y[i];
-    }
-    // forward elimination of the interior: particular solution y and the
-    // response u to the left separator (right-hand side -e at interior 0)
-    cx<A> gy = zero, gu = zero;
+    // interior: forward elimination and back substitution in place
+    cx<A> gy = zero;
 #pragma unroll
     for (int i = 0; i < CW - 1; ++i) {
         if (i < mi) {
-            const cx<A> ip = s_ip[i];
-            gy = (y[i] - e * gy) * ip;
-            gu = (i == 0) ? me * ip : (me * gu) * ip;
+            gy = (y[i] - e * gy) * s_ip[i];
             y[i] = gy;
-            u[i] = gu;
         }
     }
-    // back substitution; v (response to the right separator) only at its ends
-    cx<A> vlast = zero, vfirst = zero;
-    if (mi > 0) {
-        vlast = me * s_ip[mi - 1];
-        vfirst = vlast;
-    }
 #pragma unroll
-    for (int i = CW - 3; i >= 0; --i) {
-        if (i < mi - 1) {
+    for (int i = CW - 3; i >= 0; --i)
+        if (i < mi - 1) y[i] = y[i] - s_cp[i] * y[i + 1];
+
+    // ends of u and v for this chunk's interior length
+    cx<A> ulast = zero, ufirst = zero, vlast = zero, vfirst = zero;
+    if (mi > 0) {
+        ulast = s_gu[mi - 1];
+        vlast = me * s_ip[mi - 1];
+        ufirst = ulast;
+        vfirst = vlast;
+        for (int i = mi - 2; i >= 0; --i) {
             const cx<A> cp = s_cp[i];
-            y[i] = y[i] - cp * y[i + 1];
-            u[i] = u[i] - cp * u[i + 1];
+            ufirst = s_gu[i] - cp * ufirst;
             vfirst = zero - cp * vfirst;
         }
     }
+    cx<A> ylast = zero, yfirst = y[0];
+#pragma unroll
+    for (int i = 0; i < CW - 1; ++i)
+        if (i == mi - 1) ylast = y[i];
 
-    // reduced (separator) system, equation c = t
+    // reduced (separator) system, equation t:  lo X_{t-1} + di X_t + up X_{t+1} = rh
     if (t < P) {
         cx<A> lo, di, rh;
         if (mi > 0) {
-            cx<A> ul = zero, yl = zero;
-#pragma unroll
-            for (int i = 0; i < CW - 1; ++i)
-                if (i == mi - 1) {
-                    ul = u[i];
-                    yl = y[i];
-                }
-            lo = e * ul;
+            lo = e * ulast;
             di = d + e * vlast;
-            rh = rsep - e * yl;
+            rh = rsep - e * ylast;
         } else {
             lo = e;
             di = d;
@@ -95,13 +106,13 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
         }
         if (t == 0) lo = zero;
         pa[t] = lo;
-        pb[t] = di;
+        pc[t] = di;        // diagonal kept in pc until the neighbour terms are added
         pd[t] = rh;
         // what this chunk adds to equation t-1 (its left neighbour separator)
         if (mi > 0) {
-            nb[3 * t + 0] = e * u[0];          // to the diagonal
+            nb[3 * t + 0] = e * ufirst;        // to the diagonal
             nb[3 * t + 1] = e * vfirst;        // upper coefficient (to X_t)
-            nb[3 * t + 2] = e * y[0];          // subtracted from the rhs
+            nb[3 * t + 2] = e * yfirst;        // subtracted from the rhs
         } else {
             nb[3 * t + 0] = zero;
             nb[3 * t + 1] = e;
@@ -109,63 +120,78 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
         }
     }
     __syncthreads();
+    cx<A> a = zero, c = zero, dd = zero;
     if (t < P) {
+        cx<A> di = pc[t];
+        dd = pd[t];
+        a = pa[t];
         if (t + 1 < P) {
-            pb[t] = pb[t] + nb[3 * (t + 1) + 0];
-            pc[t] = nb[3 * (t + 1) + 1];
-            pd[t] = pd[t] - nb[3 * (t + 1) + 2];
-        } else {
-            pc[t] = zero;
+            di = di + nb[3 * (t + 1) + 0];
+            c = nb[3 * (t + 1) + 1];
+            dd = dd - nb[3 * (t + 1) + 2];
         }
+        const cx<A> r = recip(di);                       // unit diagonal
+        a = a * r;
+        c = c * r;
+        dd = dd * r;
+    }
+    __syncthreads();
+    if (t < P) {
+        pa[t] = a;
+        pc[t] = c;
+        pd[t] = dd;
     }
     __syncthreads();
 
-    // parallel cyclic reduction
+    // parallel cyclic reduction on unit-diagonal equations
     for (int sd = 1; sd < P; sd <<= 1) {
-        cx<A> na = zero, nbv = zero, nc = zero, nd = zero;
+        cx<A> na = zero, nc = zero, nd = dd, nbd = {A(1), A(0)};
         if (t < P) {
-            const cx<A> a = pa[t], b = pb[t], c = pc[t], dd = pd[t];
-            nbv = b;
-            nd = dd;
             if (t - sd >= 0) {
-                const cx<A> k1 = a * recip(pb[t - sd]);
-                na = zero - pa[t - sd] * k1;
-                nbv = nbv - pc[t - sd] * k1;
-                nd = nd - pd[t - sd] * k1;
+                const cx<A> al = pa[t - sd], cl = pc[t - sd], dl = pd[t - sd];
+                na = zero - a * al;
+                nbd = nbd - a * cl;
+                nd = nd - a * dl;
             }
             if (t + sd < P) {
-                const cx<A> k2 = c * recip(pb[t + sd]);
-                nc = zero - pc[t + sd] * k2;
-                nbv = nbv - pa[t + sd] * k2;
-                nd = nd - pd[t + sd] * k2;
+                const cx<A> ar = pa[t + sd], cr = pc[t + sd], dr = pd[t + sd];
+                nc = zero - c * cr;
+                nbd = nbd - c * ar;
+                nd = nd - c * dr;
             }
+            const cx<A> r = recip(nbd);
+            a = na * r;
+            c = nc * r;
+            dd = nd * r;
         }
         __syncthreads();
         if (t < P) {
-            pa[t] = na;
-            pb[t] = nbv;
-            pc[t] = nc;
-            pd[t] = nd;
+            pa[t] = a;
+            pc[t] = c;
+            pd[t] = dd;
         }
         __syncthreads();
     }
-    if (t < P) pd[t] = pd[t] * recip(pb[t]);            // separator values X_t
-    __syncthreads();
+    // pd[t] now holds the separator value X_t
     cx<A> XL = zero, XR = zero;
     if (t < P) {
         XL = (t > 0) ? pd[t - 1] : zero;
-        XR = pd[t];
+        XR = dd;
     }
     __syncthreads();   // the caller may reuse `red` from here on
-    // interior: x_i = y_i + u_i XL + v_i XR, v from the back
+    // interior: x_i = y_i + u_i XL + v_i XR, u and v regenerated from the back
     bool bad = false;
     if (t < P) {
-        cx<A> vi = vlast;
+        cx<A> ui = ulast, vi = vlast;
 #pragma unroll
         for (int i = CW - 2; i >= 0; --i) {
             if (i < mi) {
-                if (i < mi - 1) vi = zero - s_cp[i] * vi;
-                y[i] = y[i] + u[i] * XL + vi * XR;
+                if (i < mi - 1) {
+                    const cx<A> cp = s_cp[i];
+                    ui = s_gu[i] - cp * ui;
+                    vi = zero - cp * vi;
+                }
+                y[i] = y[i] + ui * XL + vi * XR;
                 bad |= !(isfinite((double)y[i].x) && isfinite((double)y[i].y));
             }
         }
