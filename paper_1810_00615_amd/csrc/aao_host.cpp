@@ -57,6 +57,8 @@ struct aao_ctx_s {
     void *spec = nullptr;        // half spectrum
     int lds = 0;
     int *fail = nullptr;         // shifted-solve breakdown flag
+    double *sym = nullptr;       // per-row d_j, e_j of the shifted solves
+    double sym_kappa = NAN;      // kappa the table was built for
 
     // GMRES workspace
     int m_alloc = 0;
@@ -254,6 +256,17 @@ static BatchLaunch bl_launch(aao_ctx ctx)
     return L;
 }
 
+// rebuild the per-row symbol table after a change of kappa; the stream is
+// synchronised so that later work on any stream sees the table
+static aao_status refresh_symbols(aao_ctx ctx)
+{
+    if (ctx->sym_kappa == ctx->kappa) return AAO_OK;
+    AAO_HIP(launch_symbols(ctx->sym, (int)ctx->n, (int)ctx->ell, ctx->sc, ctx->kappa, ctx->st));
+    AAO_HIP(hipStreamSynchronize(ctx->st));
+    ctx->sym_kappa = ctx->kappa;
+    return AAO_OK;
+}
+
 // z = C^{-1} (s r - E zprev)  (one circulant apply; s from in_scale)
 static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale,
                             const double *zprev, double *z, int transpose)
@@ -261,12 +274,13 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     const bool single = ctx->prec != AAO_PREC_FP64;
     const bool single_arith = ctx->prec == AAO_PREC_FP32;
     const int n = (int)ctx->n, ell = (int)ctx->ell;
+    AAO_TRY(refresh_symbols(ctx));
     if (ctx->bluestein && !zprev) {
         const BatchLaunch L = bl_launch(ctx);
         AAO_LAUNCH(AAO_K_FFT_FWD, batch_fft_fwd(L, r, in_scale, 0, ctx->spec, single, ctx->st));
         AAO_LAUNCH(AAO_K_SHIFTED_SOLVE,
-                   launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sc,
-                                        ctx->kappa, transpose, ctx->fail, ctx->st,
+                   launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
+                                        transpose, ctx->fail, ctx->st,
                                         ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
         AAO_LAUNCH(AAO_K_FFT_INV, batch_fft_inv(L, ctx->spec, z, single, ctx->st));
         return AAO_OK;
@@ -275,8 +289,8 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
                launch_fft_fwd(r, in_scale, zprev, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
                               ctx->lds, single, ctx->tw, ctx->st, ctx->cf(AAO_CFG_FFT_FWD)));
     AAO_LAUNCH(AAO_K_SHIFTED_SOLVE,
-               launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sc,
-                                    ctx->kappa, transpose, ctx->fail, ctx->st,
+               launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
+                                    transpose, ctx->fail, ctx->st,
                                     ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
     AAO_LAUNCH(AAO_K_FFT_INV,
                launch_fft_inv(ctx->spec, ctx->lds, single, z, n, ell, ctx->tw, ctx->st,
@@ -366,8 +380,8 @@ static aao_status launch_kind(aao_ctx ctx, int kind, int code, double *buf)
         AAO_HIP(launch_fft_fwd(buf, nullptr, nullptr, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
                                ctx->lds, single, ctx->tw, ctx->st, code));
     else if (kind == AAO_CFG_SHIFTED_SOLVE)
-        AAO_HIP(launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sc,
-                                     ctx->kappa, 0, nullptr, ctx->st, code));
+        AAO_HIP(launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
+                                     0, nullptr, ctx->st, code));
     else
         AAO_HIP(launch_fft_inv(ctx->spec, ctx->lds, single, buf, n, ell, ctx->tw, ctx->st, code));
     return AAO_OK;
@@ -375,6 +389,7 @@ static aao_status launch_kind(aao_ctx ctx, int kind, int code, double *buf)
 
 static aao_status tune_impl(aao_ctx ctx, int reps, double *buf)
 {
+    AAO_TRY(refresh_symbols(ctx));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     AAO_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -623,6 +638,7 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
         if ((s = dev_alloc(ctx, (void **)&ctx->tw, sizeof(double) * 2 * ell)) != AAO_OK) break;
         if ((s = dev_alloc(ctx, &ctx->spec, H * ctx->lds * 2 * sizeof(double))) != AAO_OK) break;
         if ((s = dev_alloc(ctx, (void **)&ctx->fail, sizeof(int))) != AAO_OK) break;
+        if ((s = dev_alloc(ctx, (void **)&ctx->sym, sizeof(double) * 8 * H)) != AAO_OK) break;
         ctx->nblk = dot_blocks(ctx->N());
         ctx->ldp = kMaxRestart + 2;
         if ((s = dev_alloc(ctx, (void **)&ctx->part,
@@ -693,6 +709,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->sigk);
     (void)hipFree(ctx->spec);
     (void)hipFree(ctx->fail);
+    (void)hipFree(ctx->sym);
     (void)hipFree(ctx->part);
     (void)hipFree(ctx->small);
     (void)hipFree(ctx->tmpn);

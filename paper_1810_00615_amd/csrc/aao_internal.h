@@ -15,7 +15,17 @@ template <typename T> __host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> 
     return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 template <typename T> __host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T> __host__ __device__ inline cx<T> operator-(cx<T> a) { return {-a.x, -a.y}; }
 template <typename T> __host__ __device__ inline cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+__host__ __device__ inline double ffma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__host__ __device__ inline float ffma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+// a + b c and a - b c, each component two fused multiply-adds
+template <typename T> __host__ __device__ inline cx<T> cfma(cx<T> a, cx<T> b, cx<T> c) {
+    return {ffma(b.x, c.x, ffma(-b.y, c.y, a.x)), ffma(b.x, c.y, ffma(b.y, c.x, a.y))};
+}
+template <typename T> __host__ __device__ inline cx<T> cfms(cx<T> a, cx<T> b, cx<T> c) {
+    return {ffma(-b.x, c.x, ffma(b.y, c.y, a.x)), ffma(-b.x, c.y, ffma(-b.y, c.x, a.y))};
+}
 // i * a
 template <typename T> __host__ __device__ inline cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
 // 1 / a (scaled to avoid overflow of |a|^2 for the magnitudes seen here)
@@ -57,13 +67,16 @@ hipError_t launch_fft_inv(const void *spec, int lds, bool single, double *z, int
 int fft_configs(int ell, int n, bool single, int *out, int cap);
 bool fft_config_ok(int cfg, int ell, int n, bool single);
 // In-place shifted solves (alpha_j M + beta_j kappa K) Y_j = X_j for every
-// half-spectrum row j; `single_arith` selects single-precision arithmetic.
+// half-spectrum row j; `single_arith` selects single-precision arithmetic.  sym:
+// the per-row table of launch_symbols.
 // cfg selects the launch shape (chunk, threads, LDS staging) among
 // solve_num_configs(); a value that is out of range or does not cover n selects
 // solve_default_config(n).
 hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
-                                int n, int ell, Scheme sc, double kappa, int transpose,
+                                int n, int ell, const double *sym, int transpose,
                                 int *fail_flag, hipStream_t st, int cfg = -1);
+// Per-row symbol table, (ell/2 + 1) x 2 orientations x (d, e) complex = 8 doubles a row.
+hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, hipStream_t st);
 int solve_num_configs();
 bool solve_config_ok(int cfg, int n);
 void solve_config_shape(int cfg, int *cw, int *nt, int *stage);

@@ -242,7 +242,7 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
     cx<A> *tab = reinterpret_cast<cx<A> *>(smraw);
-    cx<A> *red = tab + 3 * CW;
+    cx<A> *red = tab + psolve_tab_entries(CW);
     cx<S> *stage = reinterpret_cast<cx<S> *>(red);
     const int g = blockIdx.x;
     if (g >= nrows) return;
@@ -630,7 +630,7 @@ static size_t solve_smem(size_t es, size_t as)
 {
     const int NT = 512, CW = 8;
     const size_t stage = es * CW * (NT + 4), redb = as * 6 * NT;
-    return as * 3 * CW + (stage > redb ? stage : redb);
+    return as * psolve_tab_entries(CW) + (stage > redb ? stage : redb);
 }
 
 // Dynamic-LDS limits of the batched kernels, set once before any graph capture.

@@ -29,13 +29,13 @@ namespace aao {
 // its own chunk directly.
 template <typename A, typename S, int CW, int NTB, bool STAGE>
 __global__ void __launch_bounds__(NTB)
-k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, double kappa,
+k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restrict__ sym,
                 int transpose, int *__restrict__ fail)
 {
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
     cx<A> *tab = reinterpret_cast<cx<A> *>(smraw);
-    cx<A> *red = tab + 3 * CW;
+    cx<A> *red = tab + psolve_tab_entries(CW);
     cx<S> *stage = reinterpret_cast<cx<S> *>(red);
 
     const int j = blockIdx.x;
@@ -61,21 +61,10 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, int ell, Scheme sc, do
         }
     }
 
-    // symbol of frequency j
-    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-    for (int m = 0; m <= sc.s; ++m) {
-        const long long p = ((long long)j * m) % ell;
-        double sn, cs;
-        sincospi((transpose ? 2.0 : -2.0) * (double)p / (double)ell, &sn, &cs);
-        ar += sc.a[m] * cs;
-        ai += sc.a[m] * sn;
-        br += sc.b[m] * cs;
-        bi += sc.b[m] * sn;
-    }
-    const double h = 1.0 / (n + 1.0);
-    const cx<A> d = {A(ar * (4.0 * h / 6.0) + br * kappa * (2.0 / h)),
-                     A(ai * (4.0 * h / 6.0) + bi * kappa * (2.0 / h))};
-    const cx<A> e = {A(ar * (h / 6.0) - br * kappa / h), A(ai * (h / 6.0) - bi * kappa / h)};
+    // symbol of frequency j (tabulated per row and orientation)
+    const double *sj = sym + ((size_t)j * 2 + (transpose ? 1 : 0)) * 4;
+    const cx<A> d = {A(sj[0]), A(sj[1])};
+    const cx<A> e = {A(sj[2]), A(sj[3])};
 
     const bool bad = partition_solve<A, CW>(y, n, d, e, tab, red);
     if (STAGE) {
@@ -106,7 +95,7 @@ int solve_num_configs() { return 2 * kNumSolveCfg; }
 static size_t solve_lds_bytes(int cw, int nt, bool stage)
 {
     const size_t red = 16 * (size_t)psolve_lds_entries(cw, nt);
-    const size_t stg = 16 * (3 * (size_t)cw + (size_t)cw * (nt + 2));
+    const size_t stg = 16 * ((size_t)psolve_tab_entries(cw) + (size_t)cw * (nt + 2));
     return stage && stg > red ? stg : red;
 }
 
@@ -146,13 +135,13 @@ int solve_default_config(int n)
 }
 
 template <typename A, typename S, int CW, int NT, bool STAGE>
-static hipError_t solve_go(void *spec, int lds, int n, int ell, Scheme sc, double kappa,
+static hipError_t solve_go(void *spec, int lds, int n, int ell, const double *sym,
                            int transpose, int *fail, hipStream_t st)
 {
     size_t smem = sizeof(cx<A>) * psolve_lds_entries(CW, NT);
     if (STAGE) {
         constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
-        const size_t stg = sizeof(cx<A>) * 3 * CW + sizeof(cx<S>) * CW * (NT + PAD);
+        const size_t stg = sizeof(cx<A>) * psolve_tab_entries(CW) + sizeof(cx<S>) * CW * (NT + PAD);
         if (stg > smem) smem = stg;
     }
     auto kern = k_shifted_solve<A, S, CW, NT, STAGE>;
@@ -161,22 +150,20 @@ static hipError_t solve_go(void *spec, int lds, int n, int ell, Scheme sc, doubl
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    kern<<<ell / 2 + 1, NT, smem, st>>>(reinterpret_cast<cx<S> *>(spec), lds, n, ell, sc, kappa,
-                                        transpose, fail);
+    kern<<<ell / 2 + 1, NT, smem, st>>>(reinterpret_cast<cx<S> *>(spec), lds, n, sym, transpose,
+                                        fail);
     return hipGetLastError();
 }
 
 template <typename A, typename S>
-static hipError_t solve_disp(int cfg, void *spec, int lds, int n, int ell, Scheme sc,
-                             double kappa, int transpose, int *fail, hipStream_t st)
+static hipError_t solve_disp(int cfg, void *spec, int lds, int n, int ell, const double *sym,
+                             int transpose, int *fail, hipStream_t st)
 {
     const bool stage = cfg >= kNumSolveCfg;
 #define AAO_SCFG(I, CW, NT)                                                                    \
     case I:                                                                                    \
-        return stage ? solve_go<A, S, CW, NT, true>(spec, lds, n, ell, sc, kappa, transpose,   \
-                                                    fail, st)                                  \
-                     : solve_go<A, S, CW, NT, false>(spec, lds, n, ell, sc, kappa, transpose,  \
-                                                     fail, st);
+        return stage ? solve_go<A, S, CW, NT, true>(spec, lds, n, ell, sym, transpose, fail, st) \
+                     : solve_go<A, S, CW, NT, false>(spec, lds, n, ell, sym, transpose, fail, st);
     switch (cfg % kNumSolveCfg) {
         AAO_SCFG(0, 1, 256)
         AAO_SCFG(1, 2, 256)
@@ -213,7 +200,7 @@ k_heat_segments(const double *__restrict__ u0, const double *__restrict__ Uck, i
     const int NT = blockDim.x;
     const int t = threadIdx.x;
     cx<double> *tab = reinterpret_cast<cx<double> *>(smraw);
-    cx<double> *red = tab + 3 * CW;                         // 6*NT entries
+    cx<double> *red = tab + psolve_tab_entries(CW);                         // 6*NT entries
     double *edge = reinterpret_cast<double *>(red + 6 * NT); // first/last value of every chunk
     __shared__ double wsum[16];
 
@@ -327,17 +314,52 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
     }
 }
 
+// d_j, e_j of every half-spectrum row, for the symbol (tr = 0) and its conjugate
+// (tr = 1): sym[(2 j + tr) * 4 + {0, 1, 2, 3}] = Re d, Im d, Re e, Im e with
+//   alpha_j = sum_m a_m w^{jm},  beta_j = sum_m b_m w^{jm},  w = exp(-+2 pi i/ell),
+//   d_j = alpha_j 4h/6 + beta_j kappa 2/h,  e_j = alpha_j h/6 - beta_j kappa/h.
+__global__ void k_symbols(double *__restrict__ sym, int n, int ell, Scheme sc, double kappa)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > ell / 2) return;
+    const double h = 1.0 / (n + 1.0);
+    for (int tr = 0; tr < 2; ++tr) {
+        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+        for (int m = 0; m <= sc.s; ++m) {
+            const long long p = ((long long)j * m) % ell;
+            double sn, cs;
+            sincospi((tr ? 2.0 : -2.0) * (double)p / (double)ell, &sn, &cs);
+            ar += sc.a[m] * cs;
+            ai += sc.a[m] * sn;
+            br += sc.b[m] * cs;
+            bi += sc.b[m] * sn;
+        }
+        double *o = sym + ((size_t)j * 2 + tr) * 4;
+        o[0] = ar * (4.0 * h / 6.0) + br * kappa * (2.0 / h);
+        o[1] = ai * (4.0 * h / 6.0) + bi * kappa * (2.0 / h);
+        o[2] = ar * (h / 6.0) - br * kappa / h;
+        o[3] = ai * (h / 6.0) - bi * kappa / h;
+    }
+}
+
+hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, hipStream_t st)
+{
+    const int rows = ell / 2 + 1;
+    k_symbols<<<(rows + 255) / 256, 256, 0, st>>>(sym, n, ell, sc, kappa);
+    return hipGetLastError();
+}
+
 hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
-                                int n, int ell, Scheme sc, double kappa, int transpose,
+                                int n, int ell, const double *sym, int transpose,
                                 int *fail_flag, hipStream_t st, int cfg)
 {
     if (!solve_config_ok(cfg, n)) cfg = solve_default_config(n);
     if (!solve_config_ok(cfg, n)) return hipErrorInvalidValue;
     if (!single_store)
-        return solve_disp<double, double>(cfg, spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
+        return solve_disp<double, double>(cfg, spec, lds, n, ell, sym, transpose, fail_flag, st);
     if (!single_arith)
-        return solve_disp<double, float>(cfg, spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
-    return solve_disp<float, float>(cfg, spec, lds, n, ell, sc, kappa, transpose, fail_flag, st);
+        return solve_disp<double, float>(cfg, spec, lds, n, ell, sym, transpose, fail_flag, st);
+    return solve_disp<float, float>(cfg, spec, lds, n, ell, sym, transpose, fail_flag, st);
 }
 
 }  // namespace aao

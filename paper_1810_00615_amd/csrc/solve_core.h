@@ -1,14 +1,47 @@
 // Partition solve of a constant-coefficient (Toeplitz) tridiagonal system by one
-// workgroup: Thomas elimination of per-thread chunks, parallel cyclic reduction
-// of the separator system in LDS, back substitution.  Shared by the shifted
-// solves (single problem and batched) and the trajectory recomputation.
+// workgroup: Thomas elimination of per-thread chunks, cyclic reduction of the
+// separator system in LDS down to one wave, parallel cyclic reduction of the last
+// (at most 64) equations with cross-lane moves, back substitution.  Shared by the
+// shifted solves (single problem and batched) and the trajectory recomputation.
 #pragma once
 #include "aao_internal.h"
 
 namespace aao {
 
-// LDS needed by partition_solve: tables (3 CW) + reduced system (6 NT) entries.
-__host__ __device__ constexpr int psolve_lds_entries(int CW, int NT) { return 3 * CW + 6 * NT; }
+// LDS needed by partition_solve: the table (3 CW + 8 entries) followed by the
+// reduced-system area (6 NT entries).
+__host__ __device__ constexpr int psolve_tab_entries(int CW) { return 3 * CW + 8; }
+__host__ __device__ constexpr int psolve_lds_entries(int CW, int NT)
+{
+    return psolve_tab_entries(CW) + 6 * NT;
+}
+
+// Normalised tridiagonal equation a X_{k-1} + X_k + c X_{k+1} = d.
+template <typename A> struct TriEq {
+    cx<A> a, c, d;
+};
+
+// Eliminate the neighbours k -+ s from equation k (both normalised); missing
+// neighbours pass zeros.  Returns the new equation, normalised.
+template <typename A>
+__device__ __forceinline__ TriEq<A> reduce_eq(TriEq<A> m, TriEq<A> l, TriEq<A> r)
+{
+    const cx<A> one = {A(1), A(0)};
+    TriEq<A> o;
+    const cx<A> dg = cfms(cfms(one, m.a, l.c), m.c, r.a);   // 1 - a cl - c ar
+    const cx<A> nd = cfms(cfms(m.d, m.a, l.d), m.c, r.d);   // d - a dl - c dr
+    const cx<A> q = recip(dg);
+    o.a = -((m.a * l.a) * q);
+    o.c = -((m.c * r.c) * q);
+    o.d = nd * q;
+    return o;
+}
+
+template <typename A>
+__device__ __forceinline__ cx<A> shfl_cx(cx<A> v, int src)
+{
+    return {__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
+}
 
 // Solve tridiag(e, d, e) x = r with n unknowns.  Thread t owns unknowns
 // [t*CW, t*CW + len); y[] holds its part of r on entry and of x on exit.
@@ -16,46 +49,73 @@ __host__ __device__ constexpr int psolve_lds_entries(int CW, int NT) { return 3 
 // Chunk t is split into an interior (its first len-1 unknowns) and a separator
 // (its last unknown).  With the interior eliminated, x_i = y_i + u_i X_{t-1} +
 // v_i X_t, where y is the interior solution with zero neighbours and u, v its
-// responses to the left / right separator.  Because the matrix is Toeplitz, the
-// elimination factors (1/pivot, e/pivot) and the forward part of u are the same
-// for every chunk: one thread tabulates them per row in LDS and every thread
-// regenerates u and v backwards from the table, so a thread keeps only y in
-// registers.  The separators satisfy a tridiagonal system (one equation per
-// chunk), solved by parallel cyclic reduction with every equation normalised to
-// a unit diagonal (one complex reciprocal per equation and step).
+// responses to the left / right separator.  The matrix being Toeplitz, the
+// elimination factors (1/pivot, e/pivot), the forward part of u and the end values
+// of u and v are the same for every full chunk: one thread tabulates them (and the
+// end values for the shorter last chunk) in LDS, every thread regenerates u and v
+// backwards from the table, so a thread keeps only y in registers.
 //
-// tab: 3*CW entries of LDS; red: 6*NT entries (may alias a staging area the caller
-// has finished reading: the first barrier below precedes every write to it, and
-// the last barrier follows every read).  Every thread of the block must call it.
-// Returns true if a value is not finite.
+// The separators satisfy a tridiagonal system with one equation per chunk.  Its
+// equations are normalised to a unit diagonal and reduced by cyclic reduction
+// (even-numbered unknowns survive each level, compacted) until at most 64 remain;
+// one wave solves those by parallel cyclic reduction with lane shuffles, and the
+// eliminated unknowns are recovered level by level.  No pivoting, as in the
+// Thomas algorithm the method prescribes per block.
+//
+// tab: psolve_tab_entries(CW) entries of LDS; red: 6*NT entries (may alias a
+// staging area the caller has finished reading: the first barrier below precedes
+// every write to it, and the last barrier follows every read).  Every thread of
+// the block must call it.  Returns true if a value is not finite.
 template <typename A, int CW>
 __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *tab, cx<A> *red)
 {
     const int NT = blockDim.x;
     const int t = threadIdx.x;
-    cx<A> *s_ip = tab, *s_cp = tab + CW, *s_gu = tab + 2 * CW;
-    cx<A> *pa = red, *pc = red + NT, *pd = red + 2 * NT, *nb = red + 3 * NT;
+    cx<A> *s_ip = tab, *s_cp = tab + CW, *s_gu = tab + 2 * CW, *s_end = tab + 3 * CW;
     const cx<A> zero = {A(0), A(0)};
-    const cx<A> me = {-e.x, -e.y};
+    const int P = (n + CW - 1) / CW;                     // number of chunks / separators
+    const int mlast = n - (P - 1) * CW - 1;              // interior length of the last chunk
     if (t == 0) {
         // pivots of the interior elimination and the forward part of u (the
         // response to -e in the first interior equation)
         cx<A> cprev = zero, g = zero;
         for (int i = 0; i < CW - 1; ++i) {
-            const cx<A> ip = recip(d - e * cprev);
+            const cx<A> ip = recip(cfms(d, e, cprev));
             s_ip[i] = ip;
             cprev = e * ip;
             s_cp[i] = cprev;
-            g = (i == 0) ? me * ip : (me * g) * ip;
+            g = (i == 0) ? -(e * ip) : -((e * g) * ip);
             s_gu[i] = g;
         }
+        // first / last values of u and v: full chunks (slots 0-3), last chunk (4-7)
+        for (int k = 0; k < 2; ++k) {
+            const int mi = k == 0 ? CW - 1 : mlast;
+            cx<A> uf = zero, ul = zero, vf = zero, vl = zero;
+            if (mi > 0) {
+                ul = s_gu[mi - 1];
+                vl = -(e * s_ip[mi - 1]);
+                uf = ul;
+                vf = vl;
+                for (int i = mi - 2; i >= 0; --i) {
+                    uf = cfms(s_gu[i], s_cp[i], uf);
+                    vf = -(s_cp[i] * vf);
+                }
+            }
+            s_end[4 * k + 0] = uf;
+            s_end[4 * k + 1] = ul;
+            s_end[4 * k + 2] = vf;
+            s_end[4 * k + 3] = vl;
+        }
     }
+    // level-0 reduced system (a | c | d, NT each), then the neighbour terms and the
+    // compacted deeper levels in the second half
+    cx<A> *a0 = red, *c0 = red + NT, *d0 = red + 2 * NT, *ny = red + 3 * NT;
     __syncthreads();
 
-    const int P = (n + CW - 1) / CW;                     // number of chunks / separators
-    const int a0 = t * CW;
-    const int len = (t < P) ? min(CW, n - a0) : 0;
+    const int a0i = t * CW;
+    const int len = (t < P) ? min(CW, n - a0i) : 0;
     const int mi = len - 1;                              // interior length (may be 0)
+    const bool last = (t == P - 1);
 
     cx<A> rsep = zero;
 #pragma unroll
@@ -66,117 +126,125 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
 #pragma unroll
     for (int i = 0; i < CW - 1; ++i) {
         if (i < mi) {
-            gy = (y[i] - e * gy) * s_ip[i];
+            gy = cfms(y[i], e, gy) * s_ip[i];
             y[i] = gy;
         }
     }
 #pragma unroll
     for (int i = CW - 3; i >= 0; --i)
-        if (i < mi - 1) y[i] = y[i] - s_cp[i] * y[i + 1];
+        if (i < mi - 1) y[i] = cfms(y[i], s_cp[i], y[i + 1]);
 
-    // ends of u and v for this chunk's interior length
-    cx<A> ulast = zero, ufirst = zero, vlast = zero, vfirst = zero;
-    if (mi > 0) {
-        ulast = s_gu[mi - 1];
-        vlast = me * s_ip[mi - 1];
-        ufirst = ulast;
-        vfirst = vlast;
-        for (int i = mi - 2; i >= 0; --i) {
-            const cx<A> cp = s_cp[i];
-            ufirst = s_gu[i] - cp * ufirst;
-            vfirst = zero - cp * vfirst;
-        }
-    }
-    cx<A> ylast = zero, yfirst = y[0];
+    const int eo = last ? 4 : 0;
+    const cx<A> ulast = mi > 0 ? s_end[eo + 1] : zero;
+    const cx<A> vlast = mi > 0 ? s_end[eo + 3] : zero;
+    cx<A> ylast = zero;
 #pragma unroll
     for (int i = 0; i < CW - 1; ++i)
         if (i == mi - 1) ylast = y[i];
 
-    // reduced (separator) system, equation t:  lo X_{t-1} + di X_t + up X_{t+1} = rh
+    // equation t:  lo X_{t-1} + di X_t + up X_{t+1} = rh, where the next chunk's
+    // first unknown (interior or separator) has been eliminated
+    if (t < P) ny[t] = (mi > 0) ? e * y[0] : zero;
+    __syncthreads();
     if (t < P) {
-        cx<A> lo, di, rh;
-        if (mi > 0) {
-            lo = e * ulast;
-            di = d + e * vlast;
-            rh = rsep - e * ylast;
-        } else {
-            lo = e;
-            di = d;
-            rh = rsep;
-        }
+        cx<A> lo = (mi > 0) ? e * ulast : e;
+        cx<A> di = (mi > 0) ? cfma(d, e, vlast) : d;
+        cx<A> rh = (mi > 0) ? cfms(rsep, e, ylast) : rsep;
         if (t == 0) lo = zero;
-        pa[t] = lo;
-        pc[t] = di;        // diagonal kept in pc until the neighbour terms are added
-        pd[t] = rh;
-        // what this chunk adds to equation t-1 (its left neighbour separator)
-        if (mi > 0) {
-            nb[3 * t + 0] = e * ufirst;        // to the diagonal
-            nb[3 * t + 1] = e * vfirst;        // upper coefficient (to X_t)
-            nb[3 * t + 2] = e * yfirst;        // subtracted from the rhs
-        } else {
-            nb[3 * t + 0] = zero;
-            nb[3 * t + 1] = e;
-            nb[3 * t + 2] = zero;
-        }
-    }
-    __syncthreads();
-    cx<A> a = zero, c = zero, dd = zero;
-    if (t < P) {
-        cx<A> di = pc[t];
-        dd = pd[t];
-        a = pa[t];
+        cx<A> up = zero;
         if (t + 1 < P) {
-            di = di + nb[3 * (t + 1) + 0];
-            c = nb[3 * (t + 1) + 1];
-            dd = dd - nb[3 * (t + 1) + 2];
+            const int mn = (t + 1 == P - 1) ? mlast : CW - 1;
+            const int no = (t + 1 == P - 1) ? 4 : 0;
+            if (mn > 0) {
+                di = cfma(di, e, s_end[no + 0]);
+                up = e * s_end[no + 2];
+                rh = rh - ny[t + 1];
+            } else {
+                up = e;
+            }
         }
-        const cx<A> r = recip(di);                       // unit diagonal
-        a = a * r;
-        c = c * r;
-        dd = dd * r;
-    }
-    __syncthreads();
-    if (t < P) {
-        pa[t] = a;
-        pc[t] = c;
-        pd[t] = dd;
+        const cx<A> q = recip(di);
+        a0[t] = lo * q;
+        c0[t] = up * q;
+        d0[t] = rh * q;
     }
     __syncthreads();
 
-    // parallel cyclic reduction on unit-diagonal equations
-    for (int sd = 1; sd < P; sd <<= 1) {
-        cx<A> na = zero, nc = zero, nd = dd, nbd = {A(1), A(0)};
-        if (t < P) {
-            if (t - sd >= 0) {
-                const cx<A> al = pa[t - sd], cl = pc[t - sd], dl = pd[t - sd];
-                na = zero - a * al;
-                nbd = nbd - a * cl;
-                nd = nd - a * dl;
-            }
-            if (t + sd < P) {
-                const cx<A> ar = pa[t + sd], cr = pc[t + sd], dr = pd[t + sd];
-                nc = zero - c * cr;
-                nbd = nbd - c * ar;
-                nd = nd - c * dr;
-            }
-            const cx<A> r = recip(nbd);
-            a = na * r;
-            c = nc * r;
-            dd = nd * r;
+    // cyclic reduction down to at most 64 equations; level s arrays (a, c, d) of
+    // length Ps; level s+1 keeps the even unknowns of level s
+    int Ps = P;
+    cx<A> *as = a0, *cs = c0, *ds = d0;
+    cx<A> *next = red + 3 * NT;
+    int levels = 0;
+    while (Ps > 64) {
+        const int Pn = (Ps + 1) / 2;
+        cx<A> *an = next, *cn = next + Pn, *dn = next + 2 * Pn;
+        for (int u = t; u < Pn; u += NT) {
+            const int k = 2 * u;
+            TriEq<A> m{as[k], cs[k], ds[k]}, l{zero, zero, zero}, r{zero, zero, zero};
+            if (k >= 1) l = {as[k - 1], cs[k - 1], ds[k - 1]};
+            if (k + 1 < Ps) r = {as[k + 1], cs[k + 1], ds[k + 1]};
+            const TriEq<A> o = reduce_eq(m, l, r);
+            an[u] = o.a;
+            cn[u] = o.c;
+            dn[u] = o.d;
         }
         __syncthreads();
-        if (t < P) {
-            pa[t] = a;
-            pc[t] = c;
-            pd[t] = dd;
+        as = an;
+        cs = cn;
+        ds = dn;
+        next = dn + Pn;
+        Ps = Pn;
+        ++levels;
+    }
+    // one wave: parallel cyclic reduction of the remaining Ps <= 64 equations
+    if (t < 64) {
+        TriEq<A> m{zero, zero, zero};
+        if (t < Ps) m = {as[t], cs[t], ds[t]};
+        for (int sd = 1; sd < Ps; sd <<= 1) {
+            TriEq<A> l{shfl_cx(m.a, t - sd), shfl_cx(m.c, t - sd), shfl_cx(m.d, t - sd)};
+            TriEq<A> r{shfl_cx(m.a, t + sd), shfl_cx(m.c, t + sd), shfl_cx(m.d, t + sd)};
+            if (t - sd < 0) l = {zero, zero, zero};
+            if (t + sd >= Ps) r = {zero, zero, zero};
+            const TriEq<A> o = reduce_eq(m, l, r);
+            m = (t < Ps) ? o : m;
+        }
+        if (t < Ps) ds[t] = m.d;                         // X at the deepest level
+    }
+    __syncthreads();
+    // back substitution, level by level: level s recovers its odd unknowns from
+    // the even ones (level s+1); the d arrays are overwritten with X
+    for (int lv = levels; lv > 0; --lv) {
+        // arrays of level lv-1: recompute their position
+        int P0 = P;
+        cx<A> *ap = a0, *cp = c0, *dp = d0;
+        cx<A> *nx = red + 3 * NT;
+        for (int q = 0; q < lv - 1; ++q) {
+            const int Pn = (P0 + 1) / 2;
+            ap = nx;
+            cp = nx + Pn;
+            dp = nx + 2 * Pn;
+            nx = dp + Pn;
+            P0 = Pn;
+        }
+        const int Pn = (P0 + 1) / 2;
+        const cx<A> *dn = nx + 2 * Pn;                  // X of level lv
+        for (int u = t; u < Pn; u += NT) {
+            const int k = 2 * u;
+            const cx<A> xk = dn[u];
+            if (k + 1 < P0) {
+                const cx<A> xr = (k + 2 < P0) ? dn[u + 1] : zero;
+                dp[k + 1] = cfms(cfms(dp[k + 1], ap[k + 1], xk), cp[k + 1], xr);
+            }
+            dp[k] = xk;
         }
         __syncthreads();
     }
-    // pd[t] now holds the separator value X_t
+    // d0[t] now holds the separator value X_t
     cx<A> XL = zero, XR = zero;
     if (t < P) {
-        XL = (t > 0) ? pd[t - 1] : zero;
-        XR = dd;
+        XL = (t > 0) ? d0[t - 1] : zero;
+        XR = d0[t];
     }
     __syncthreads();   // the caller may reuse `red` from here on
     // interior: x_i = y_i + u_i XL + v_i XR, u and v regenerated from the back
@@ -187,11 +255,11 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
         for (int i = CW - 2; i >= 0; --i) {
             if (i < mi) {
                 if (i < mi - 1) {
-                    const cx<A> cp = s_cp[i];
-                    ui = s_gu[i] - cp * ui;
-                    vi = zero - cp * vi;
+                    const cx<A> cpi = s_cp[i];
+                    ui = cfms(s_gu[i], cpi, ui);
+                    vi = -(cpi * vi);
                 }
-                y[i] = y[i] + ui * XL + vi * XR;
+                y[i] = cfma(cfma(y[i], ui, XL), vi, XR);
                 bad |= !(isfinite((double)y[i].x) && isfinite((double)y[i].y));
             }
         }

@@ -46,14 +46,21 @@ SHAPES = [(1000, 256), (63, 64), (2047, 1024), (4500, 128), (130, 2048)]
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("n,ell", SHAPES)
 def test_every_shape_matches_oracle(dev, orc, n, ell, prec):
+    """FP64: 1e-10 relative up to n = 4096; beyond, the forward-error bound
+    4 eps kappa_2(C) of an elimination without pivoting (the zero-frequency block is
+    kappa tau K, whose condition number grows like n^2: about 8e6 at n = 4500)."""
     import torch
+    import pins
     from paper_1810_00615_amd import Problem
     tau, kappa = 1.0 / ell, 1.1
     r = np.random.default_rng([n, ell, 11]).standard_normal((ell, n))
     ref = orc.pinv(HEAT, n, ell, tau, kappa, r)
     P = Problem(n, ell, tau, "heat", kappa=kappa, precision=prec, device=dev)
     rd = torch.from_numpy(r).to(dev)
-    tol = 1e-10 if prec == "fp64" else 2e-6
+    if prec == "fp64":
+        tol = 1e-10 if n <= 4096 else max(1e-10, 4 * EPS * pins.cond_C(HEAT, n, ell, tau, kappa))
+    else:
+        tol = 2e-6
     solve_codes = admissible(P, "shifted_solve", range(64))
     assert solve_codes, "no solve shape admitted"
     fft_codes = admissible(P, "fft_fwd", FFT_CODES)
