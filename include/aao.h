@@ -143,6 +143,14 @@ aao_status aao_apply_Pinv(aao_ctx ctx, const double *r, double *z, int neumann_o
 aao_status aao_gmres(aao_ctx ctx, const double *b, double *x, int restart, double tol,
                      int maxit, aao_info *info);
 
+/* aao_gmres with flags: AAO_GMRES_ZERO_GUESS -- x0 = 0 whatever x holds on entry
+ * (x is only written; the first basis vector is b itself, so the initial
+ * residual costs no matvec); AAO_GMRES_TRANSPOSE -- solve A^T x = b with C^{-T}
+ * (as aao_adjoint_solve).  Unknown bits: AAO_ERR_ARG. */
+enum { AAO_GMRES_ZERO_GUESS = 1, AAO_GMRES_TRANSPOSE = 2 };
+aao_status aao_gmres_ex(aao_ctx ctx, const double *b, double *x, int restart, double tol,
+                        int maxit, int flags, aao_info *info);
+
 /* Neumann order used by aao_gmres and aao_adjoint_solve (default 0). */
 aao_status aao_set_neumann_order(aao_ctx ctx, int q);
 

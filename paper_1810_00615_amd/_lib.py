@@ -41,6 +41,8 @@ SIGNATURES = {
                        ctypes.c_int],
     "aao_gmres": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                   ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)],
+    "aao_gmres_ex": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                     ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Info)],
     "aao_adjoint_solve": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                           ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)],
     "aao_grad": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -108,6 +110,7 @@ def check(status, where, ctx=None):
         raise AAOError(status, where, detail)
     return status
 
+GMRES_ZERO_GUESS, GMRES_TRANSPOSE = 1, 2
 CONFIG_KINDS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec"]
 KERNELS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec", "cgs_dot", "cgs_update_dot",
            "cgs_update_norm", "axpy"]

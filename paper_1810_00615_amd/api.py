@@ -13,7 +13,8 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import CONFIG_KINDS, KERNELS, AAOError, Info, check, lib
+from ._lib import (CONFIG_KINDS, GMRES_TRANSPOSE, GMRES_ZERO_GUESS, KERNELS, AAOError, Info,
+                   check, lib)
 
 HEAT, BD2 = 0, 1
 SCHEMES = {"heat": HEAT, "heat_ie": HEAT, "bd2": BD2, "wave_bd2": BD2}
@@ -165,15 +166,16 @@ class Problem:
         """FGMRES(restart) with the circulant preconditioner; returns (U, info)."""
         self._vec(b, (self.ell, self.n), "b")
         x = out if out is not None else self.empty()
+        flags = 0
         if x0 is None:
-            x.zero_()
+            flags = GMRES_ZERO_GUESS
         else:
             x.copy_(x0)
         info = Info()
         self._stream()
-        st = self._L.aao_gmres(self._ctx, _ptr(b), _ptr(x), int(restart), float(tol), int(maxit),
-                               ctypes.byref(info))
-        self._c(st, "aao_gmres")
+        st = self._L.aao_gmres_ex(self._ctx, _ptr(b), _ptr(x), int(restart), float(tol),
+                                  int(maxit), flags, ctypes.byref(info))
+        self._c(st, "aao_gmres_ex")
         d = info.as_dict()
         d["status"] = st
         return x, d
@@ -183,12 +185,12 @@ class Problem:
         """Solve A^T lam = g (preconditioned with C^{-T}); returns (lam, info)."""
         self._vec(g, (self.ell, self.n), "g")
         lam = out if out is not None else self.empty()
-        lam.zero_()
         info = Info()
         self._stream()
-        st = self._L.aao_adjoint_solve(self._ctx, _ptr(g), _ptr(lam), int(restart), float(tol),
-                                       int(maxit), ctypes.byref(info))
-        self._c(st, "aao_adjoint_solve")
+        st = self._L.aao_gmres_ex(self._ctx, _ptr(g), _ptr(lam), int(restart), float(tol),
+                                  int(maxit), GMRES_ZERO_GUESS | GMRES_TRANSPOSE,
+                                  ctypes.byref(info))
+        self._c(st, "aao_gmres_ex")
         d = info.as_dict()
         d["status"] = st
         return lam, d

@@ -30,6 +30,7 @@ using namespace aao;
 namespace {
 
 constexpr int kMaxRestart = 63;
+constexpr int kPartStride = 16384;   // partials per value (dot and fused-matvec blocks)
 constexpr int kSmallStride = 80;   // doubles per small-scalar array
 
 struct Status {
@@ -63,9 +64,10 @@ struct aao_ctx_s {
     // GMRES workspace
     int m_alloc = 0;
     double *V = nullptr, *Z = nullptr, *W = nullptr;
-    double **dV = nullptr, **dZ = nullptr;
-    double *part = nullptr;
+    double *part = nullptr;      // value-major block partials, ldp per value
     int nblk = 0, ldp = 0;
+    double *hbuf = nullptr;      // mapped pinned host buffer (k_reduce_small results)
+    double *hdev = nullptr;      // its device view
     double *small = nullptr;     // d | h1 | h2 | c | vs | hcol | y
     double *tmpn = nullptr;      // n-vector scratch
     int *dmodes = nullptr;
@@ -192,10 +194,7 @@ static void free_workspace(aao_ctx ctx)
     (void)hipFree(ctx->V);
     (void)hipFree(ctx->Z);
     (void)hipFree(ctx->W);
-    (void)hipFree(ctx->dV);
-    (void)hipFree(ctx->dZ);
     ctx->V = ctx->Z = ctx->W = nullptr;
-    ctx->dV = ctx->dZ = nullptr;
     ctx->m_alloc = 0;
 }
 
@@ -207,13 +206,6 @@ static aao_status ensure_workspace(aao_ctx ctx, int m)
     AAO_TRY(dev_alloc(ctx, (void **)&ctx->V, sizeof(double) * N * (m + 1)));
     AAO_TRY(dev_alloc(ctx, (void **)&ctx->Z, sizeof(double) * N * m));
     AAO_TRY(dev_alloc(ctx, (void **)&ctx->W, sizeof(double) * N));
-    AAO_TRY(dev_alloc(ctx, (void **)&ctx->dV, sizeof(double *) * (m + 1)));
-    AAO_TRY(dev_alloc(ctx, (void **)&ctx->dZ, sizeof(double *) * m));
-    std::vector<double *> hv(m + 1), hz(m);
-    for (int i = 0; i <= m; ++i) hv[i] = ctx->V + N * i;
-    for (int i = 0; i < m; ++i) hz[i] = ctx->Z + N * i;
-    AAO_HIP(hipMemcpy(ctx->dV, hv.data(), sizeof(double *) * (m + 1), hipMemcpyHostToDevice));
-    AAO_HIP(hipMemcpy(ctx->dZ, hz.data(), sizeof(double *) * m, hipMemcpyHostToDevice));
     ctx->m_alloc = m;
     return AAO_OK;
 }
@@ -458,7 +450,7 @@ static aao_status pinv_impl(aao_ctx ctx, const double *r, const double *in_scale
 // ------------------------------------------------------------------ GMRES
 
 static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, double tol,
-                             int maxit, aao_info *info, int transpose)
+                             int maxit, aao_info *info, int transpose, bool zero_guess)
 {
     if (m < 1 || m > kMaxRestart) return arg_err(ctx, "restart must be in [1, 63]");
     if (!(tol >= 0.0) || maxit < 0) return arg_err(ctx, "bad tol / maxit");
@@ -467,12 +459,41 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     if (overlap(b, x, N * sizeof(double))) return arg_err(ctx, "b and x overlap");
     AAO_TRY(ensure_workspace(ctx, m));
     hipStream_t st = ctx->st;
+    const int n = (int)ctx->n, ell = (int)ctx->ell;
+    const int nb = dot_blocks(N), ldp = ctx->ldp;
+    volatile double *hb = ctx->hbuf;
     AAO_HIP(hipMemsetAsync(ctx->fail, 0, sizeof(int), st));
+    SmallArgs sa{0, 0, ctx->sh1(), ctx->sh2(), ctx->sc_(), ctx->svs(), ctx->hdev, ctx->fail};
+    auto small = [&](int mode, int nv, int nblk) -> aao_status {
+        sa.mode = mode;
+        sa.nv = nv;
+        AAO_HIP(launch_reduce_small(ctx->part, nblk, ldp, sa, st));
+        return AAO_OK;
+    };
 
+    // basis V_j (V_0 = b for a zero initial guess) and search directions Z_j
+    VecList Vl{}, Zl{};
+    for (int j = 0; j <= m; ++j) Vl.p[j] = ctx->V + N * j;
+    for (int j = 0; j < m; ++j) Zl.p[j] = ctx->Z + N * j;
+    double *V0 = ctx->V;
+    auto residual = [&]() -> aao_status {
+        // V_0 = b - A x, vs_0 = 1/||V_0||
+        AAO_TRY(apply_A_impl(ctx, x, V0, b, transpose));
+        AAO_HIP(launch_dot1_parts(V0, V0, N, ctx->part, st));
+        return small(3, 0, nb);
+    };
+
+    // ||b|| and the first residual, one synchronisation
     aao_info inf{};
-    double bb = 0.0;
-    AAO_TRY(dot_host(ctx, b, b, &bb));
-    const double bnorm = std::sqrt(bb);
+    AAO_HIP(launch_dot1_parts(b, b, N, ctx->part, st));
+    AAO_TRY(small(4, zero_guess ? 1 : 0, nb));
+    if (zero_guess)
+        Vl.p[0] = b;
+    else
+        AAO_TRY(residual());
+    AAO_HIP(hipStreamSynchronize(st));
+    const double bnorm = std::sqrt(hb[kHostBB]);
+    double beta = hb[kHostBeta];
     if (!std::isfinite(bnorm)) {
         ctx->err = "non-finite right-hand side";
         return AAO_ERR_NUMERIC;
@@ -484,68 +505,63 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
         if (info) *info = inf;
         return AAO_OK;
     }
-    const int nb = dot_blocks(N);
-    double *V0 = ctx->V;
-
-    auto residual = [&](double *beta) -> aao_status {
-        // V_0 = b - A x, scale vs_0 = 1/||V_0||
-        AAO_TRY(apply_A_impl(ctx, x, V0, b, transpose));
-        AAO_HIP(launch_dot1_parts(V0, V0, N, ctx->part, st));
-        AAO_HIP(launch_reduce_parts(ctx->part, nb, 1, 1, ctx->sd(), st));
-        AAO_HIP(launch_arnoldi_small(3, 0, ctx->sd(), ctx->sh1(), ctx->sh2(), ctx->sc_(),
-                                     ctx->svs(), ctx->shcol(), st));
-        AAO_HIP(hipMemcpyAsync(beta, ctx->shcol(), sizeof(double), hipMemcpyDeviceToHost, st));
-        AAO_HIP(hipStreamSynchronize(st));
-        return AAO_OK;
-    };
-
-    double beta = 0.0;
-    AAO_TRY(residual(&beta));
     inf.rel_resid_true = beta / bnorm;
     inf.rel_resid_est = inf.rel_resid_true;
     if (!std::isfinite(beta)) {
         ctx->err = "non-finite residual";
         return AAO_ERR_NUMERIC;
     }
-    if (beta / bnorm <= tol) {
-        inf.converged = 1;
-        if (info) *info = inf;
+    bool x_zero = zero_guess;   // x not yet written
+    auto finish_zero = [&]() -> aao_status {
+        if (x_zero) {
+            AAO_HIP(launch_fill(x, 0.0, N, st));
+            AAO_HIP(hipStreamSynchronize(st));
+        }
         return AAO_OK;
+    };
+    if (beta / bnorm <= tol || maxit == 0) {
+        AAO_TRY(finish_zero());
+        inf.converged = beta / bnorm <= tol;
+        if (info) *info = inf;
+        return inf.converged ? AAO_OK : AAO_NOT_CONVERGED;
     }
 
+    const int mcfg = ctx->cf(AAO_CFG_MATVEC);
+    const bool fused = matvec_blocks(n, ell, mcfg) <= ldp;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
+    bool failed = false;
     while (inf.iters < maxit) {
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int k = 0;
         for (int j = 0; j < m; ++j) {
-            double *Vj = ctx->V + N * j;
+            const double *Vj = Vl.p[j];
             double *Zj = ctx->Z + N * j;
             double *Vn = ctx->V + N * (j + 1);
-            // z_j = P^{-1} v_j ; w = A z_j
-            AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose));
-            AAO_TRY(apply_A_impl(ctx, Zj, ctx->W, nullptr, transpose));
             const int nv = j + 1;
-            // CGS2: project, re-project, form the new (unnormalised) basis vector
-            AAO_LAUNCH(AAO_K_CGS_DOT,
-                       launch_multidot(ctx->dV, nv, ctx->W, N, ctx->part, ctx->ldp, st));
-            AAO_HIP(launch_reduce_parts(ctx->part, nb, ctx->ldp, nv, ctx->sd(), st));
-            AAO_HIP(launch_arnoldi_small(0, nv, ctx->sd(), ctx->sh1(), ctx->sh2(), ctx->sc_(),
-                                         ctx->svs(), ctx->shcol(), st));
-            AAO_LAUNCH(AAO_K_CGS_UPDATE_DOT, launch_update_dot(ctx->dV, nv, ctx->W, ctx->sc_(), N,
-                                                               ctx->part, ctx->ldp, st));
-            AAO_HIP(launch_reduce_parts(ctx->part, nb, ctx->ldp, nv, ctx->sd(), st));
-            AAO_HIP(launch_arnoldi_small(1, nv, ctx->sd(), ctx->sh1(), ctx->sh2(), ctx->sc_(),
-                                         ctx->svs(), ctx->shcol(), st));
-            AAO_LAUNCH(AAO_K_CGS_UPDATE_NORM, launch_update_norm(ctx->dV, nv, ctx->W, ctx->sc_(),
-                                                                 Vn, N, ctx->part, ctx->ldp, st));
-            AAO_HIP(launch_reduce_parts(ctx->part, nb, ctx->ldp, 1, ctx->sd(), st));
-            AAO_HIP(launch_arnoldi_small(2, nv, ctx->sd(), ctx->sh1(), ctx->sh2(), ctx->sc_(),
-                                         ctx->svs(), ctx->shcol(), st));
-            AAO_HIP(hipMemcpyAsync(hcol.data(), ctx->shcol(), sizeof(double) * (nv + 1),
-                                   hipMemcpyDeviceToHost, st));
+            // z_j = P^{-1} v_j ; w = A z_j with the first projection V^T w
+            AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose));
+            if (fused) {
+                AAO_LAUNCH(AAO_K_MATVEC,
+                           launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc, ctx->kappa,
+                                         ctx->tauk, transpose, st, mcfg, &Vl, nv, ctx->part, ldp));
+                AAO_TRY(small(0, nv, matvec_blocks(n, ell, mcfg)));
+            } else {
+                AAO_TRY(apply_A_impl(ctx, Zj, ctx->W, nullptr, transpose));
+                AAO_LAUNCH(AAO_K_CGS_DOT, launch_multidot(Vl, nv, ctx->W, N, ctx->part, ldp, st));
+                AAO_TRY(small(0, nv, nb));
+            }
+            // CGS2: re-project, form the new (unnormalised) basis vector and its norm
+            AAO_LAUNCH(AAO_K_CGS_UPDATE_DOT,
+                       launch_update_dot(Vl, nv, ctx->W, ctx->sc_(), N, ctx->part, ldp, st));
+            AAO_TRY(small(1, nv, nb));
+            AAO_LAUNCH(AAO_K_CGS_UPDATE_NORM, launch_update_norm(Vl, nv, ctx->W, ctx->sc_(), Vn,
+                                                                 N, ctx->part, ldp, st));
+            AAO_TRY(small(2, nv, nb));
             AAO_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i <= nv; ++i) hcol[i] = hb[i];
+            failed = failed || hb[kHostFail] != 0.0;
             inf.iters++;
             for (int i = 0; i <= nv; ++i)
                 if (!std::isfinite(hcol[i])) {
@@ -575,15 +591,21 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 std::fprintf(stderr, "aao gmres it %d est %.3e\n", inf.iters, inf.rel_resid_est);
             if (inf.rel_resid_est <= tol || inf.iters >= maxit) break;
         }
-        // x += Z y, y = R^{-1} g
+        // x (+)= Z y, y = R^{-1} g
+        CoefList yc{};
         for (int i = k - 1; i >= 0; --i) {
             double s = g[i];
             for (int l = i + 1; l < k; ++l) s -= H[(size_t)i * m + l] * y[l];
             y[i] = s / H[(size_t)i * m + i];
+            yc.v[i] = y[i];
         }
-        AAO_HIP(hipMemcpyAsync(ctx->sy(), y.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
-        AAO_LAUNCH(AAO_K_AXPY, launch_multi_axpy(ctx->dZ, k, ctx->sy(), x, N, st));
-        AAO_TRY(residual(&beta));
+        AAO_LAUNCH(AAO_K_AXPY, launch_multi_axpy(Zl, k, yc, x, N, !x_zero, st));
+        x_zero = false;
+        Vl.p[0] = V0;
+        AAO_TRY(residual());
+        AAO_HIP(hipStreamSynchronize(st));
+        beta = hb[kHostBeta];
+        failed = failed || hb[kHostFail] != 0.0;
         inf.rel_resid_true = beta / bnorm;
         if (!std::isfinite(beta)) {
             ctx->err = "non-finite residual";
@@ -595,8 +617,6 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
         }
         inf.restarts++;
     }
-    int failed = 0;
-    AAO_HIP(hipMemcpy(&failed, ctx->fail, sizeof(int), hipMemcpyDeviceToHost));
     if (info) *info = inf;
     if (failed) {
         ctx->err = "shifted solve produced non-finite values";
@@ -640,9 +660,17 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
         if ((s = dev_alloc(ctx, (void **)&ctx->fail, sizeof(int))) != AAO_OK) break;
         if ((s = dev_alloc(ctx, (void **)&ctx->sym, sizeof(double) * 8 * H)) != AAO_OK) break;
         ctx->nblk = dot_blocks(ctx->N());
-        ctx->ldp = kMaxRestart + 2;
+        ctx->ldp = kPartStride;
         if ((s = dev_alloc(ctx, (void **)&ctx->part,
-                           sizeof(double) * ctx->nblk * ctx->ldp)) != AAO_OK) break;
+                           sizeof(double) * (kMaxVecs + 2) * ctx->ldp)) != AAO_OK) break;
+        if (hipHostMalloc((void **)&ctx->hbuf, sizeof(double) * kHostSlots, hipHostMallocMapped) !=
+                hipSuccess ||
+            hipHostGetDevicePointer((void **)&ctx->hdev, ctx->hbuf, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            s = AAO_ERR_ALLOC;
+            break;
+        }
+        std::memset(ctx->hbuf, 0, sizeof(double) * kHostSlots);
         if ((s = dev_alloc(ctx, (void **)&ctx->small, sizeof(double) * 7 * kSmallStride)) != AAO_OK)
             break;
         if ((s = dev_alloc(ctx, (void **)&ctx->tmpn, sizeof(double) * n)) != AAO_OK) break;
@@ -711,6 +739,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->fail);
     (void)hipFree(ctx->sym);
     (void)hipFree(ctx->part);
+    if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
     (void)hipFree(ctx->small);
     (void)hipFree(ctx->tmpn);
     (void)hipFree(ctx->dmodes);
@@ -845,10 +874,18 @@ aao_status aao_apply_Pinv(aao_ctx ctx, const double *r, double *z, int neumann_o
 aao_status aao_gmres(aao_ctx ctx, const double *b, double *x, int restart, double tol, int maxit,
                      aao_info *info)
 {
+    return aao_gmres_ex(ctx, b, x, restart, tol, maxit, 0, info);
+}
+
+aao_status aao_gmres_ex(aao_ctx ctx, const double *b, double *x, int restart, double tol,
+                        int maxit, int flags, aao_info *info)
+{
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
+    if (flags & ~(AAO_GMRES_ZERO_GUESS | AAO_GMRES_TRANSPOSE)) return arg_err(ctx, "bad flags");
     try {
-        return gmres_impl(ctx, b, x, restart, tol, maxit, info, 0);
+        return gmres_impl(ctx, b, x, restart, tol, maxit, info,
+                          (flags & AAO_GMRES_TRANSPOSE) ? 1 : 0, (flags & AAO_GMRES_ZERO_GUESS) != 0);
     } catch (const std::bad_alloc &) {
         return AAO_ERR_ALLOC;
     } catch (...) {
@@ -862,7 +899,7 @@ aao_status aao_adjoint_solve(aao_ctx ctx, const double *g, double *lam, int rest
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
     try {
-        return gmres_impl(ctx, g, lam, restart, tol, maxit, info, 1);
+        return gmres_impl(ctx, g, lam, restart, tol, maxit, info, 1, false);
     } catch (const std::bad_alloc &) {
         return AAO_ERR_ALLOC;
     } catch (...) {

@@ -90,36 +90,63 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
 
 // y = A x (or A^T x); with tau_k != nullptr the variable-step matrix B.
 // If bsub != nullptr computes y = bsub - A x.
+struct VecList;
 hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
                          Scheme sc, double kappa, const double *tau_k, int transpose,
-                         hipStream_t st, int cfg = -1);
+                         hipStream_t st, int cfg = -1, const VecList *V = nullptr, int nv = 0,
+                         double *part = nullptr, int ldp = 0);
 // matvec launch shapes: code = 3 v + r (R = 4 << r rows per thread, v = 1: DPP lane moves)
 int matvec_num_configs();
 int matvec_default_config();
+// number of workgroups (= partials per dot value) of a matvec launch
+int matvec_blocks(int n, int ell, int cfg);
 hipError_t launch_project_sine(double *u0, int n, int J, const int *modes, const double *amps,
                                hipStream_t st);
 hipError_t launch_build_rhs(double *b, const double *u0, const double *v0, int n, int ell,
                             Scheme sc, double kappa, double tau, hipStream_t st);
 
 // ------------------------------------------------------- Krylov helpers
-// Partial dot products: part[blk * ldp + i] = sum over block slice of V_i . w,
-// i < nv; V given as an array of device pointers (device memory).
+// Up to kMaxVecs device vectors / coefficients, passed to kernels by value.
+constexpr int kMaxVecs = 64;
+struct VecList {
+    const double *p[kMaxVecs];
+};
+struct CoefList {
+    double v[kMaxVecs];
+};
+// Partial dot products, value-major: part[i * ldp + blk] = sum over block blk's
+// slice of V_i . w, i < nv (dot_blocks(N) blocks, ldp >= that count).
 int dot_blocks(size_t N);
-hipError_t launch_multidot(const double *const *V, int nv, const double *w, size_t N,
-                           double *part, int ldp, hipStream_t st);
-// w' = w - sum_i V_i h_i (h device) and partials of V_i . w' (i < nv) and of
-// w'.w' (stored at index nv).  w is not modified.
-hipError_t launch_update_dot(const double *const *V, int nv, const double *w, const double *h,
+hipError_t launch_multidot(const VecList &V, int nv, const double *w, size_t N, double *part,
+                           int ldp, hipStream_t st);
+// w' = w - sum_i V_i h_i (h device) and the partials of V_i . w' (i < nv).  w is
+// not modified.
+hipError_t launch_update_dot(const VecList &V, int nv, const double *w, const double *h,
                              size_t N, double *part, int ldp, hipStream_t st);
-// out = w - sum_i V_i h_i and the partials of out.out (stored at index 0).
-hipError_t launch_update_norm(const double *const *V, int nv, const double *w, const double *h,
+// out = w - sum_i V_i h_i and the partials of out.out (value 0).
+hipError_t launch_update_norm(const VecList &V, int nv, const double *w, const double *h,
                               double *out, size_t N, double *part, int ldp, hipStream_t st);
-// sums[i] = sum_blk part[blk * ldp + i] in fixed order, i < cnt
+// sums[i] = sum_blk part[i * ldp + blk] in fixed order, i < cnt
 hipError_t launch_reduce_parts(const double *part, int nblk, int ldp, int cnt, double *sums,
                                hipStream_t st);
-// x += sum_i Z_i y_i  (y device)
-hipError_t launch_multi_axpy(const double *const *Z, int nz, const double *y, double *x,
-                             size_t N, hipStream_t st);
+// x = (accumulate ? x : 0) + sum_i Z_i y_i
+hipError_t launch_multi_axpy(const VecList &Z, int nz, const CoefList &y, double *x, size_t N,
+                             bool accumulate, hipStream_t st);
+// Slots of the mapped host buffer written by k_reduce_small.
+constexpr int kHostBeta = kMaxVecs;       // residual norm
+constexpr int kHostBB = kMaxVecs + 1;     // b.b
+constexpr int kHostFail = kMaxVecs + 2;   // shifted-solve breakdown flag (0 / 1)
+constexpr int kHostSlots = kMaxVecs + 4;
+struct SmallArgs {
+    int mode, nv;
+    double *h1, *h2, *c, *vs;   // device scalars (kMaxVecs + 1 each)
+    double *host;               // device view of the mapped host buffer
+    const int *fail;
+};
+// Fused fixed-order reduction of one Krylov step's partials and its scalar update
+// (modes documented at the kernel).
+hipError_t launch_reduce_small(const double *part, int nblk, int ldp, const SmallArgs &a,
+                               hipStream_t st);
 // out = w * (*scale)
 hipError_t launch_scale(const double *w, const double *scale, double *out, size_t N,
                         hipStream_t st);
@@ -137,7 +164,6 @@ hipError_t launch_mk(const double *x, double cm, double ck, const double *x2, do
                      double ck2, double *y, int n, hipStream_t st);
 hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double *part,
                              hipStream_t st);
-hipError_t launch_arnoldi_small(int mode, int nv, const double *d, double *h1, double *h2,
-                                double *c, double *vs, double *hcol, hipStream_t st);
+
 
 }  // namespace aao

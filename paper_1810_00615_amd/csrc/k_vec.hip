@@ -4,8 +4,9 @@
 // GMRES Arnoldi process.  All FP64, all memory-bound.
 //
 // Reductions are deterministic: every kernel writes one partial per workgroup
-// (fixed in-block tree), and k_reduce_parts sums the partials in a fixed order.
-// No floating-point atomics.
+// (fixed in-block tree) into a value-major array part[i * ldp + block], and the
+// partials are summed in a fixed order (k_reduce_parts, k_reduce_small).  No
+// floating-point atomics.
 #include "aao_internal.h"
 
 namespace aao {
@@ -34,7 +35,7 @@ __device__ __forceinline__ void block_reduce_store(double (&acc)[NV], int nv, do
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
         double s = 0.0;
         for (int w = 0; w < nw; ++w) s += red[i * 16 + w];
-        part[(size_t)blockIdx.x * ldp + i] = s;
+        part[(size_t)i * ldp + blockIdx.x] = s;
     }
 }
 
@@ -46,19 +47,18 @@ int dot_blocks(size_t N)
 
 // ------------------------------------------------------------- CGS passes
 // MODE 0: acc_i = sum_e V_i[e] w[e]
-// MODE 1: w' = w - sum_i V_i c1_i;  acc_i = sum_e V_i[e] w'[e], acc_nv = sum w'^2
+// MODE 1: w' = w - sum_i V_i c1_i;  acc_i = sum_e V_i[e] w'[e]
 // MODE 2: w'' = w - sum_i V_i c1_i; out = w'' ; acc_0 = sum w''^2
 template <int MODE, int NV>
 __global__ void __launch_bounds__(kRedThreads)
-k_cgs(const double *const *__restrict__ V, int nv, const double *__restrict__ w,
-      const double *__restrict__ c1, size_t N, double *__restrict__ part, int ldp,
-      double *__restrict__ out)
+k_cgs(VecList V, int nv, const double *__restrict__ w, const double *__restrict__ c1, size_t N,
+      double *__restrict__ part, int ldp, double *__restrict__ out)
 {
-    __shared__ double red[(NV + 1) * 16];
-    double acc[NV + 1];
+    __shared__ double red[NV * 16];
+    double acc[NV];
     double cf[NV];
 #pragma unroll
-    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < NV; ++i) cf[i] = (MODE > 0 && i < nv) ? c1[i] : 0.0;
     // U consecutive grid-stride elements per iteration, all loads issued first
@@ -73,7 +73,7 @@ k_cgs(const double *const *__restrict__ V, int nv, const double *__restrict__ w,
             const bool in = e < N;
             we[u] = in ? w[e] : 0.0;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) vv[u][i] = (in && i < nv) ? V[i][e] : 0.0;
+            for (int i = 0; i < NV; ++i) vv[u][i] = (in && i < nv) ? V.p[i][e] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -88,7 +88,6 @@ k_cgs(const double *const *__restrict__ V, int nv, const double *__restrict__ w,
                 if (MODE == 1) {
 #pragma unroll
                     for (int i = 0; i < NV; ++i) acc[i] += vv[u][i] * s;
-                    acc[NV] += s * s;
                 } else {
                     if (e < N) out[e] = s;
                     acc[0] += s * s;
@@ -96,36 +95,11 @@ k_cgs(const double *const *__restrict__ V, int nv, const double *__restrict__ w,
             }
         }
     }
-    // slots reduced: MODE 0 -> nv dots; MODE 1 -> nv dots + norm (stored at nv);
-    // MODE 2 -> norm only (stored at 0)
-    if (MODE == 2) acc[NV] = acc[0];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-#pragma unroll
-    for (int i = 0; i <= NV; ++i) {
-        const bool used = (i < NV) ? (MODE != 2 && i < nv) : (MODE != 0);
-        if (used) {
-            double v = acc[i];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-            if (lane == 0) red[i * 16 + wv] = v;
-        }
-    }
-    __syncthreads();
-    const int ndots = (MODE == 2) ? 0 : nv;
-    for (int i = threadIdx.x; i <= NV; i += blockDim.x) {
-        const bool used = (i < NV) ? (i < ndots) : (MODE != 0);
-        if (!used) continue;
-        double sum = 0.0;
-        for (int w2 = 0; w2 < nw; ++w2) sum += red[i * 16 + w2];
-        const int slot = (i < NV) ? i : ndots;
-        part[(size_t)blockIdx.x * ldp + slot] = sum;
-    }
+    block_reduce_store<NV>(acc, MODE == 2 ? 1 : nv, part, ldp, red);
 }
 
 template <int MODE>
-static hipError_t cgs_disp(const double *const *V, int nv, const double *w, const double *c1,
+static hipError_t cgs_disp(const VecList &V, int nv, const double *w, const double *c1,
                            size_t N, double *part, int ldp, double *out, hipStream_t st)
 {
     const int nb = dot_blocks(N);
@@ -139,32 +113,32 @@ static hipError_t cgs_disp(const double *const *V, int nv, const double *w, cons
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_multidot(const double *const *V, int nv, const double *w, size_t N,
-                           double *part, int ldp, hipStream_t st)
+hipError_t launch_multidot(const VecList &V, int nv, const double *w, size_t N, double *part,
+                           int ldp, hipStream_t st)
 {
     return cgs_disp<0>(V, nv, w, nullptr, N, part, ldp, nullptr, st);
 }
 
-hipError_t launch_update_dot(const double *const *V, int nv, const double *w, const double *h,
+hipError_t launch_update_dot(const VecList &V, int nv, const double *w, const double *h,
                              size_t N, double *part, int ldp, hipStream_t st)
 {
     return cgs_disp<1>(V, nv, w, h, N, part, ldp, nullptr, st);
 }
 
-hipError_t launch_update_norm(const double *const *V, int nv, const double *w, const double *h,
+hipError_t launch_update_norm(const VecList &V, int nv, const double *w, const double *h,
                               double *out, size_t N, double *part, int ldp, hipStream_t st)
 {
     return cgs_disp<2>(V, nv, w, h, N, part, ldp, out, st);
 }
 
-// Fixed-order sum of the per-block partials: sums[i] = sum_b part[b*ldp + i].
+// Fixed-order sum of the per-block partials: sums[i] = sum_b part[i*ldp + b].
 __global__ void __launch_bounds__(256)
 k_reduce_parts(const double *__restrict__ part, int nblk, int ldp, double *__restrict__ sums)
 {
     __shared__ double red[256];
     const int i = blockIdx.x;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)b * ldp + i];
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)i * ldp + b];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
@@ -182,18 +156,19 @@ hipError_t launch_reduce_parts(const double *part, int nblk, int ldp, int cnt, d
 }
 
 // ------------------------------------------------------- small vector ops
-__global__ void k_multi_axpy(const double *const *__restrict__ Z, int nz,
-                             const double *__restrict__ y, double *__restrict__ x, size_t N)
+__global__ void k_multi_axpy(VecList Z, int nz, CoefList y, double *__restrict__ x, size_t N,
+                             int accumulate)
 {
     constexpr int U = 4;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N; e0 += U * stride) {
         double s[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) s[u] = (e0 + u * stride < N) ? x[e0 + u * stride] : 0.0;
+        for (int u = 0; u < U; ++u)
+            s[u] = (accumulate && e0 + u * stride < N) ? x[e0 + u * stride] : 0.0;
         for (int i = 0; i < nz; ++i) {
-            const double yi = y[i];
-            const double *zi = Z[i];
+            const double yi = y.v[i];
+            const double *zi = Z.p[i];
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (e0 + u * stride < N) s[u] += zi[e0 + u * stride] * yi;
@@ -210,10 +185,10 @@ static int grid_for(size_t N)
     return (int)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
 }
 
-hipError_t launch_multi_axpy(const double *const *Z, int nz, const double *y, double *x,
-                             size_t N, hipStream_t st)
+hipError_t launch_multi_axpy(const VecList &Z, int nz, const CoefList &y, double *x, size_t N,
+                             bool accumulate, hipStream_t st)
 {
-    k_multi_axpy<<<grid_for(N), 256, 0, st>>>(Z, nz, y, x, N);
+    k_multi_axpy<<<grid_for(N), 256, 0, st>>>(Z, nz, y, x, N, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -289,7 +264,9 @@ hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double 
 // is formed, one aligned load per row, so the loads of a lane are in flight
 // together.  The i -+ 1 neighbours come from the adjacent lanes by a cross-lane
 // move (DPP wave shift when DPP is set, else ds_bpermute); lanes 0 and 63 fetch
-// the neighbour outside their wave with a second, two-lane load.
+// the neighbour outside their wave with a second, two-lane load.  With nv > 0 the
+// kernel also leaves the block partials of V_q . y, q < nv (value-major, block id
+// y * gridDim.x + x), for the first Gram-Schmidt pass.
 template <bool DPP>
 __device__ __forceinline__ double lane_from_left(double v)
 {
@@ -315,10 +292,11 @@ __device__ __forceinline__ double lane_from_right(double v)
     }
 }
 
-template <int S, int R, bool DPP>
+template <int S, int R, bool DPP, bool DOTS>
 __global__ void __launch_bounds__(256)
 k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
-         int n, int ell, Scheme sc, double kappa, const double *__restrict__ tau_k, int transpose)
+         int n, int ell, Scheme sc, double kappa, const double *__restrict__ tau_k, int transpose,
+         VecList V, int nv, double *__restrict__ part, int ldp)
 {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -343,6 +321,9 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
     // the space stencil, so that cancelling time differences (BD2: x_k - 2 x_{k-1}
     // + x_{k-2}) are taken on the raw values
     double wl[S + 1] = {}, wc[S + 1] = {}, wr[S + 1] = {};
+    double yv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) yv[r] = 0.0;
 #pragma unroll
     for (int it = 0; it < NR; ++it) {
         double l = lane_from_left<DPP>(c[it]);
@@ -376,11 +357,39 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
             br += bm * wr[m];
         }
         const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
-        if (col) {
-            const size_t o = (size_t)k * n + i;
-            y[o] = bsub ? bsub[o] - v : v;
+        const double out = bsub ? (col ? bsub[(size_t)k * n + i] : 0.0) - v : v;
+        yv[it - S] = out;
+        if (col) y[(size_t)k * n + i] = out;
+    }
+    if (!DOTS) return;
+    // partial dot products V_q . y over this block's tile (first Gram-Schmidt pass)
+    __shared__ double red[kMaxVecs * 4];
+    const int wv = threadIdx.x >> 6;
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    // four basis vectors at a time, all their loads issued before the sums
+    for (int q0 = 0; q0 < nv; q0 += 4) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        double vq[4][R];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int k = transpose ? (k1 - 1 - r) : (k0 + r);
+                vq[u][r] = (q0 + u < nv && col && r < nin - S) ? V.p[q0 + u][(size_t)k * n + i]
+                                                                : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[u] += vq[u][r] * yv[r];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) acc[u] += __shfl_down(acc[u], off, 64);
+            if (lane == 0 && q0 + u < nv) red[(q0 + u) * 4 + wv] = acc[u];
         }
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nv; q += blockDim.x)
+        part[(size_t)q * ldp + blk] = ((red[q * 4] + red[q * 4 + 1]) + red[q * 4 + 2]) + red[q * 4 + 3];
 }
 
 // Launch shapes: code = 3 v + r, R = 4 << r rows per thread, v = 1 for DPP lane
@@ -391,14 +400,19 @@ int matvec_default_config() { return 3 + 2; }
 template <int S>
 static hipError_t matvec_disp(int cfg, const double *x, double *y, const double *bsub, int n,
                               int ell, Scheme sc, double kappa, const double *tau_k,
-                              int transpose, hipStream_t st)
+                              int transpose, const VecList &V, int nv, double *part, int ldp,
+                              hipStream_t st)
 {
     const int R = 4 << (cfg % 3);
     dim3 grid((n + 255) / 256, (ell + R - 1) / R);
 #define AAO_MV(C, RR, D)                                                                    \
     case C:                                                                                 \
-        k_matvec<S, RR, D><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, tau_k,      \
-                                                 transpose);                                \
+        if (nv > 0)                                                                         \
+            k_matvec<S, RR, D, true><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa,   \
+                                                           tau_k, transpose, V, nv, part, ldp); \
+        else                                                                                \
+            k_matvec<S, RR, D, false><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa,  \
+                                                            tau_k, transpose, V, 0, part, ldp); \
         break;
     switch (cfg) {
         AAO_MV(0, 4, false)
@@ -413,15 +427,32 @@ static hipError_t matvec_disp(int cfg, const double *x, double *y, const double 
     return hipGetLastError();
 }
 
-hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
-                         Scheme sc, double kappa, const double *tau_k, int transpose,
-                         hipStream_t st, int cfg)
+int matvec_blocks(int n, int ell, int cfg)
 {
     if (cfg < 0 || cfg >= matvec_num_configs()) cfg = matvec_default_config();
+    const int R = 4 << (cfg % 3);
+    return ((n + 255) / 256) * ((ell + R - 1) / R);
+}
+
+hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
+                         Scheme sc, double kappa, const double *tau_k, int transpose,
+                         hipStream_t st, int cfg, const VecList *V, int nv, double *part, int ldp)
+{
+    if (cfg < 0 || cfg >= matvec_num_configs()) cfg = matvec_default_config();
+    if (nv > 0 && (!V || !part || nv > kMaxVecs || matvec_blocks(n, ell, cfg) > ldp))
+        return hipErrorInvalidValue;
+    static const VecList none{};
+    const VecList &L = V ? *V : none;
     switch (sc.s) {
-    case 1: return matvec_disp<1>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, st);
-    case 2: return matvec_disp<2>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, st);
-    case 3: return matvec_disp<3>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, st);
+    case 1:
+        return matvec_disp<1>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, L, nv, part,
+                              ldp, st);
+    case 2:
+        return matvec_disp<2>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, L, nv, part,
+                              ldp, st);
+    case 3:
+        return matvec_disp<3>(cfg, x, y, bsub, n, ell, sc, kappa, tau_k, transpose, L, nv, part,
+                              ldp, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -556,45 +587,79 @@ hipError_t launch_grad_kappa_parts(const double *U, const double *lam, int n, in
 
 namespace aao {
 
-// Scalar bookkeeping of one Arnoldi step, on the device so that no host round
-// trip sits between the Gram-Schmidt passes.  The basis is stored unnormalised
-// with scales vs (v_i = vs_i * V_i); d holds the reduced raw dot products.
-//   mode 0: h1 = vs.d, c = vs.h1                    (first projection)
-//   mode 1: h2 = vs.d, c += vs.h2                   (re-orthogonalisation)
-//   mode 2: nrm = sqrt(d_0), vs_nv = 1/nrm, hcol = [h1 + h2, nrm]
-//   mode 3: nrm = sqrt(d_0), vs_0 = 1/nrm, hcol_0 = nrm   (restart vector)
-__global__ void k_arnoldi_small(int mode, int nv, const double *__restrict__ d, double *h1,
-                                double *h2, double *c, double *vs, double *hcol)
+// Fixed-order reduction of the partials of one Krylov step followed by its scalar
+// update, in one block (16 waves; wave w sums a fixed sixteenth of the partials of
+// every value, then thread 0 adds the 16 wave sums in order).  The basis
+// is stored unnormalised with scales vs (v_i = vs_i V_i), so that no host round
+// trip sits between the Gram-Schmidt passes; d are the reduced raw dot products.
+//   mode 0: h1_i = vs_i d_i, c_i = vs_i h1_i             (first projection, i < nv)
+//   mode 1: h2_i = vs_i d_i, c_i += vs_i h2_i            (re-orthogonalisation)
+//   mode 2: nrm = sqrt(d_0), vs_nv = 1/nrm, host[0..nv] = (h1 + h2, nrm)
+//   mode 3: nrm = sqrt(d_0), vs_0 = 1/nrm, host[kHostBeta] = nrm    (restart vector)
+//   mode 4: host[kHostBB] = d_0 (= b.b); with nv == 1 also vs_0 = 1/sqrt(d_0)
+//           and host[kHostBeta] = sqrt(d_0)       (zero initial guess: V_0 = b)
+// host: mapped pinned memory; host[kHostFail] receives the breakdown flag.
+__global__ void __launch_bounds__(1024)
+k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (mode == 0) {
+    __shared__ double wsum[16][kMaxVecs];
+    double sums[kMaxVecs];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int cnt = (a.mode <= 1) ? a.nv : 1;
+    // wave wv sums the partials [b0, b1) of every value
+    const int per = (nblk + 15) / 16;
+    const int b0 = wv * per, b1 = min(nblk, b0 + per);
+    for (int i = 0; i < cnt; ++i) {
+        double s = 0.0;
+        for (int b = b0 + lane; b < b1; b += 64) s += part[(size_t)i * ldp + b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) wsum[wv][i] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < cnt; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < 16; ++w) s += wsum[w][i];
+        sums[i] = s;
+    }
+    const int nv = a.nv;
+    if (a.mode == 0) {
         for (int i = 0; i < nv; ++i) {
-            h1[i] = vs[i] * d[i];
-            c[i] = vs[i] * h1[i];
+            a.h1[i] = a.vs[i] * sums[i];
+            a.c[i] = a.vs[i] * a.h1[i];
         }
-    } else if (mode == 1) {
+    } else if (a.mode == 1) {
         for (int i = 0; i < nv; ++i) {
-            h2[i] = vs[i] * d[i];
-            c[i] += vs[i] * h2[i];
+            a.h2[i] = a.vs[i] * sums[i];
+            a.c[i] += a.vs[i] * a.h2[i];
+        }
+    } else if (a.mode == 2 || a.mode == 3) {
+        const double nrm = sqrt(fmax(sums[0], 0.0));
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        if (a.mode == 2) {
+            a.vs[nv] = inv;
+            for (int i = 0; i < nv; ++i) a.host[i] = a.h1[i] + a.h2[i];
+            a.host[nv] = nrm;
+        } else {
+            a.vs[0] = inv;
+            a.host[kHostBeta] = nrm;
         }
     } else {
-        const double nrm = sqrt(fmax(d[0], 0.0));
-        const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        if (mode == 2) {
-            vs[nv] = inv;
-            for (int i = 0; i < nv; ++i) hcol[i] = h1[i] + h2[i];
-            hcol[nv] = nrm;
-        } else {
-            vs[0] = inv;
-            hcol[0] = nrm;
+        a.host[kHostBB] = sums[0];
+        if (nv == 1) {
+            const double nrm = sqrt(fmax(sums[0], 0.0));
+            a.vs[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+            a.host[kHostBeta] = nrm;
         }
     }
+    a.host[kHostFail] = (a.fail && *a.fail) ? 1.0 : 0.0;
 }
 
-hipError_t launch_arnoldi_small(int mode, int nv, const double *d, double *h1, double *h2,
-                                double *c, double *vs, double *hcol, hipStream_t st)
+hipError_t launch_reduce_small(const double *part, int nblk, int ldp, const SmallArgs &a,
+                               hipStream_t st)
 {
-    k_arnoldi_small<<<1, 64, 0, st>>>(mode, nv, d, h1, h2, c, vs, hcol);
+    k_reduce_small<<<1, 1024, 0, st>>>(part, nblk, ldp, a);
     return hipGetLastError();
 }
 

@@ -262,3 +262,49 @@ def test_adjoint_and_gradient_small(aao, orc, torch_dev):
     assert normrel(lam.cpu().numpy(), lr) < 1e-9
     assert normrel(gu.cpu().numpy(), gur) < 1e-9
     assert abs(gk - gkr) < 1e-9 * abs(gkr)
+
+
+@pytest.mark.parametrize("scheme", [HEAT, BD2])
+def test_gmres_initial_guess_paths(aao, orc, torch_dev, scheme):
+    """The zero-guess entry (first basis vector = b, x only written) and an explicit
+    initial guess reach the same solution; garbage in x is ignored with the zero
+    guess; maxit = 0 returns x = 0 unconverged; restarts (restart = 2) go through
+    the accumulate path of the solution update (restart 1 for the heat scheme, whose
+    preconditioned system converges in two steps, 3 for BD2); the transposed flag
+    solves A^T."""
+    import ctypes
+    import torch
+    from paper_1810_00615_amd._lib import GMRES_TRANSPOSE, GMRES_ZERO_GUESS, Info, lib
+    n, ell = 127, 64
+    tau, kappa = 1.0 / ell, 0.9
+    P = aao.Problem(n, ell, tau, sched(scheme), kappa=kappa, device=torch_dev[1])
+    u0 = rand_vec(n, 31) * 0.1
+    b = P.rhs(to_dev(torch_dev, u0), to_dev(torch_dev, u0) if scheme == BD2 else None)
+    bn = b.cpu().numpy()
+    U_ref = orc.solve_seq(scheme, n, ell, tau, kappa, bn)
+    x = torch.full_like(b, 7.0)                      # ignored with the zero guess
+    L = lib()
+    info = Info()
+    P._stream()
+    rs = 1 if scheme == HEAT else 3
+    st = L.aao_gmres_ex(P._ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), rs,
+                        1e-12, 400, GMRES_ZERO_GUESS, ctypes.byref(info))
+    assert st == 0 and info.converged and info.restarts >= 1
+    assert normrel(x.cpu().numpy(), U_ref) < 1e-9
+    x0 = to_dev(torch_dev, 0.5 * U_ref)
+    U2, info2 = P.solve(b, restart=rs, tol=1e-12, maxit=400, x0=x0)
+    assert info2["converged"] and normrel(U2.cpu().numpy(), U_ref) < 1e-9
+    x.fill_(3.0)
+    st = L.aao_gmres_ex(P._ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), 10,
+                        1e-12, 0, GMRES_ZERO_GUESS, ctypes.byref(info))
+    torch.cuda.synchronize()
+    assert st == 1 and not info.converged and float(x.abs().max()) == 0.0
+    # transposed system through the flag
+    lam = torch.full_like(b, -1.0)
+    st = L.aao_gmres_ex(P._ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                        30, 1e-12, 400, GMRES_ZERO_GUESS | GMRES_TRANSPOSE, ctypes.byref(info))
+    assert st == 0
+    lr = orc.adjoint_seq(scheme, n, ell, tau, kappa, bn)
+    assert normrel(lam.cpu().numpy(), lr) < 1e-9
+    assert L.aao_gmres_ex(P._ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                          10, 1e-12, 10, 8, ctypes.byref(info)) == -1
