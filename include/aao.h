@@ -183,10 +183,14 @@ aao_status aao_grad_checkpointed(aao_ctx ctx, const double *u0, const double *Uc
                                  const double *lam, double *g_u0, double *g_kappa,
                                  double *U_out);
 
-/* Per-kernel timing, for measurement.  aao_set_timing(ctx, 1) clears the
- * accumulators and brackets every later kernel launch of the context with a pair
- * of HIP events on the context stream; aao_get_timing synchronises the stream and
- * returns the summed duration (ms) and launch count of one kernel class. */
+/* Per-kernel timing, for measurement.  aao_set_timing_mask(ctx, mask) clears the
+ * accumulators and brackets every later launch of the kernel classes whose bit
+ * (1 << AAO_K_...) is set with a pair of HIP events on the context stream;
+ * aao_set_timing(ctx, e) sets all bits (e != 0) or none.  aao_get_timing[_ex]
+ * synchronises the stream and returns the summed duration (ms), the launch count
+ * and (bytes may be NULL) the summed algorithmic bytes of one class: every operand
+ * counted once per launch (ell x n FP64 vectors 8 n ell bytes, half spectra
+ * (ell/2 + 1) n complex entries of 16 or 8 bytes). */
 enum {
     AAO_K_FFT_FWD = 0,          /* time-axis transform, real -> half spectrum     */
     AAO_K_SHIFTED_SOLVE = 1,    /* complex shifted tridiagonal solves             */
@@ -200,6 +204,9 @@ enum {
 };
 aao_status aao_set_timing(aao_ctx ctx, int enable);
 aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count);
+aao_status aao_set_timing_mask(aao_ctx ctx, unsigned mask);
+aao_status aao_get_timing_ex(aao_ctx ctx, int kernel, double *total_ms, int64_t *count,
+                             double *bytes);
 
 /* Launch shapes of the three kernels of the preconditioner apply (Sec. 3: forward
  * time transform, shifted solves, inverse transform) and of the block-Toeplitz

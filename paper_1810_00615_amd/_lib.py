@@ -52,6 +52,9 @@ SIGNATURES = {
     "aao_set_timing": [ctypes.c_void_p, ctypes.c_int],
     "aao_get_timing": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                        ctypes.POINTER(ctypes.c_int64)],
+    "aao_set_timing_mask": [ctypes.c_void_p, ctypes.c_uint],
+    "aao_get_timing_ex": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
     "aao_tune": [ctypes.c_void_p, ctypes.c_int],
     "aao_get_config": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "aao_set_config": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],

@@ -237,19 +237,27 @@ class Problem:
         self._c(self._L.aao_set_config(self._ctx, CONFIG_KINDS.index(kernel), int(code)),
                 "aao_set_config")
 
-    def set_timing(self, enable: bool = True):
-        """Bracket every kernel launch with HIP events (clears the accumulators)."""
-        self._c(self._L.aao_set_timing(self._ctx, int(enable)), "aao_set_timing")
+    def set_timing(self, enable=True):
+        """Bracket kernel launches with HIP events (clears the accumulators).  enable:
+        True / False for every kernel or none, or an iterable of kernel names."""
+        if isinstance(enable, bool) or enable is None:
+            mask = (1 << len(KERNELS)) - 1 if enable else 0
+        else:
+            mask = 0
+            for name in enable:
+                mask |= 1 << KERNELS.index(name)
+        self._c(self._L.aao_set_timing_mask(self._ctx, mask), "aao_set_timing_mask")
 
     def timing(self):
-        """{kernel: (total_ms, launches)} accumulated since set_timing(True)."""
+        """{kernel: (total_ms, launches, algorithmic_bytes)} accumulated since set_timing."""
         out = {}
         for i, name in enumerate(KERNELS):
             t = ctypes.c_double(0.0)
             c = ctypes.c_int64(0)
-            self._c(self._L.aao_get_timing(self._ctx, i, ctypes.byref(t), ctypes.byref(c)),
-                    "aao_get_timing")
-            out[name] = (t.value, c.value)
+            b = ctypes.c_double(0.0)
+            self._c(self._L.aao_get_timing_ex(self._ctx, i, ctypes.byref(t), ctypes.byref(c),
+                                              ctypes.byref(b)), "aao_get_timing_ex")
+            out[name] = (t.value, c.value, b.value)
         return out
 
     def grad(self, U, lam, u0=None, v0=None, want_v0=False):

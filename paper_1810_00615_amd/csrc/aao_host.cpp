@@ -85,11 +85,17 @@ struct aao_ctx_s {
     double *bl_chirp = nullptr, *bl_bhat = nullptr, *bl_tw = nullptr;
 
     // per-kernel timing (aao_set_timing): event pairs recorded around launches
-    bool timing = false;
+    unsigned timing = 0;         // bit k: kernel id k is timed
+    struct Pending {
+        int id;
+        double bytes;
+        hipEvent_t e0, e1;
+    };
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
+    std::vector<Pending> ev_pending;
     double t_total[AAO_NUM_KERNELS] = {};
     long long t_count[AAO_NUM_KERNELS] = {};
+    double t_bytes[AAO_NUM_KERNELS] = {};
 
     // launch shapes per precision mode (aao_set_config / aao_tune); -1 = default
     int cfg[3][AAO_NUM_CFG] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
@@ -127,19 +133,21 @@ static hipEvent_t ev_get(aao_ctx ctx)
     return e;
 }
 
-// Launch `call` on the context stream; with timing enabled, bracket it with events.
-#define AAO_LAUNCH(id, call)                                                            \
+// Launch `call` on the context stream; if kernel `id` is timed, bracket it with
+// events and record its algorithmic bytes (each operand read or written once).
+#define AAO_LAUNCH_B(id, bytes, call)                                                   \
     do {                                                                                \
         hipEvent_t e0_ = nullptr, e1_ = nullptr;                                        \
-        if (ctx->timing) {                                                              \
+        const bool tm_ = (ctx->timing >> (id)) & 1u;                                    \
+        if (tm_) {                                                                      \
             e0_ = ev_get(ctx);                                                          \
             e1_ = ev_get(ctx);                                                          \
             if (e0_) (void)hipEventRecord(e0_, ctx->st);                                \
         }                                                                               \
         AAO_HIP(call);                                                                  \
-        if (ctx->timing && e0_ && e1_) {                                                \
+        if (tm_ && e0_ && e1_) {                                                        \
             (void)hipEventRecord(e1_, ctx->st);                                         \
-            ctx->ev_pending.push_back({(id), {e0_, e1_}});                              \
+            ctx->ev_pending.push_back({(id), (double)(bytes), e0_, e1_});               \
         }                                                                               \
     } while (0)
 
@@ -224,12 +232,21 @@ static aao_status dot_host(aao_ctx ctx, const double *a, const double *b, double
     return AAO_OK;
 }
 
+// algorithmic bytes: one ell x n FP64 vector, and the half spectrum at the current
+// storage precision
+static double vec_bytes(aao_ctx ctx) { return 8.0 * (double)ctx->N(); }
+static double spec_bytes(aao_ctx ctx)
+{
+    return (ctx->prec != AAO_PREC_FP64 ? 8.0 : 16.0) * (double)(ctx->ell / 2 + 1) * (double)ctx->n;
+}
+
 // --------------------------------------------------------------- operators
 
 static aao_status apply_A_impl(aao_ctx ctx, const double *x, double *y, const double *bsub,
                                int transpose)
 {
-    AAO_LAUNCH(AAO_K_MATVEC, launch_matvec(x, y, bsub, (int)ctx->n, (int)ctx->ell, ctx->sc,
+    AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (bsub ? 3 : 2),
+                 launch_matvec(x, y, bsub, (int)ctx->n, (int)ctx->ell, ctx->sc,
                                            ctx->kappa, ctx->tauk, transpose, ctx->st,
                                            ctx->cf(AAO_CFG_MATVEC)));
     return AAO_OK;
@@ -269,22 +286,24 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     AAO_TRY(refresh_symbols(ctx));
     if (ctx->bluestein && !zprev) {
         const BatchLaunch L = bl_launch(ctx);
-        AAO_LAUNCH(AAO_K_FFT_FWD, batch_fft_fwd(L, r, in_scale, 0, ctx->spec, single, ctx->st));
-        AAO_LAUNCH(AAO_K_SHIFTED_SOLVE,
+        AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) + spec_bytes(ctx),
+                     batch_fft_fwd(L, r, in_scale, 0, ctx->spec, single, ctx->st));
+        AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, 2 * spec_bytes(ctx),
                    launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
                                         transpose, ctx->fail, ctx->st,
                                         ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
-        AAO_LAUNCH(AAO_K_FFT_INV, batch_fft_inv(L, ctx->spec, z, single, ctx->st));
+        AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_bytes(ctx),
+                     batch_fft_inv(L, ctx->spec, z, single, ctx->st));
         return AAO_OK;
     }
-    AAO_LAUNCH(AAO_K_FFT_FWD,
+    AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) * (zprev ? 2 : 1) + spec_bytes(ctx),
                launch_fft_fwd(r, in_scale, zprev, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
                               ctx->lds, single, ctx->tw, ctx->st, ctx->cf(AAO_CFG_FFT_FWD)));
-    AAO_LAUNCH(AAO_K_SHIFTED_SOLVE,
+    AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, 2 * spec_bytes(ctx),
                launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
                                     transpose, ctx->fail, ctx->st,
                                     ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
-    AAO_LAUNCH(AAO_K_FFT_INV,
+    AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_bytes(ctx),
                launch_fft_inv(ctx->spec, ctx->lds, single, z, n, ell, ctx->tw, ctx->st,
                               ctx->cf(AAO_CFG_FFT_INV)));
     return AAO_OK;
@@ -543,20 +562,21 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             // z_j = P^{-1} v_j ; w = A z_j with the first projection V^T w
             AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose));
             if (fused) {
-                AAO_LAUNCH(AAO_K_MATVEC,
-                           launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc, ctx->kappa,
+                AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (2 + nv),
+                             launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc, ctx->kappa,
                                          ctx->tauk, transpose, st, mcfg, &Vl, nv, ctx->part, ldp));
                 AAO_TRY(small(0, nv, matvec_blocks(n, ell, mcfg)));
             } else {
                 AAO_TRY(apply_A_impl(ctx, Zj, ctx->W, nullptr, transpose));
-                AAO_LAUNCH(AAO_K_CGS_DOT, launch_multidot(Vl, nv, ctx->W, N, ctx->part, ldp, st));
+                AAO_LAUNCH_B(AAO_K_CGS_DOT, vec_bytes(ctx) * (nv + 1),
+                             launch_multidot(Vl, nv, ctx->W, N, ctx->part, ldp, st));
                 AAO_TRY(small(0, nv, nb));
             }
             // CGS2: re-project, form the new (unnormalised) basis vector and its norm
-            AAO_LAUNCH(AAO_K_CGS_UPDATE_DOT,
-                       launch_update_dot(Vl, nv, ctx->W, ctx->sc_(), N, ctx->part, ldp, st));
+            AAO_LAUNCH_B(AAO_K_CGS_UPDATE_DOT, vec_bytes(ctx) * (nv + 1),
+                         launch_update_dot(Vl, nv, ctx->W, ctx->sc_(), N, ctx->part, ldp, st));
             AAO_TRY(small(1, nv, nb));
-            AAO_LAUNCH(AAO_K_CGS_UPDATE_NORM, launch_update_norm(Vl, nv, ctx->W, ctx->sc_(), Vn,
+            AAO_LAUNCH_B(AAO_K_CGS_UPDATE_NORM, vec_bytes(ctx) * (nv + 2), launch_update_norm(Vl, nv, ctx->W, ctx->sc_(), Vn,
                                                                  N, ctx->part, ldp, st));
             AAO_TRY(small(2, nv, nb));
             AAO_HIP(hipStreamSynchronize(st));
@@ -599,7 +619,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             y[i] = s / H[(size_t)i * m + i];
             yc.v[i] = y[i];
         }
-        AAO_LAUNCH(AAO_K_AXPY, launch_multi_axpy(Zl, k, yc, x, N, !x_zero, st));
+        AAO_LAUNCH_B(AAO_K_AXPY, vec_bytes(ctx) * (k + (x_zero ? 1 : 2)),
+                     launch_multi_axpy(Zl, k, yc, x, N, !x_zero, st));
         x_zero = false;
         Vl.p[0] = V0;
         AAO_TRY(residual());
@@ -727,8 +748,8 @@ aao_status aao_destroy(aao_ctx ctx)
     if (!ctx) return AAO_OK;
     (void)hipStreamSynchronize(ctx->st);
     for (auto &p : ctx->ev_pending) {
-        ctx->ev_pool.push_back(p.second.first);
-        ctx->ev_pool.push_back(p.second.second);
+        ctx->ev_pool.push_back(p.e0);
+        ctx->ev_pool.push_back(p.e1);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     free_workspace(ctx);
@@ -997,25 +1018,32 @@ aao_status aao_grad_checkpointed(aao_ctx ctx, const double *u0, const double *Uc
     return AAO_OK;
 }
 
-aao_status aao_set_timing(aao_ctx ctx, int enable)
+aao_status aao_set_timing_mask(aao_ctx ctx, unsigned mask)
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
     AAO_HIP(hipStreamSynchronize(ctx->st));
     for (auto &p : ctx->ev_pending) {
-        ctx->ev_pool.push_back(p.second.first);
-        ctx->ev_pool.push_back(p.second.second);
+        ctx->ev_pool.push_back(p.e0);
+        ctx->ev_pool.push_back(p.e1);
     }
     ctx->ev_pending.clear();
     for (int i = 0; i < AAO_NUM_KERNELS; ++i) {
         ctx->t_total[i] = 0.0;
         ctx->t_count[i] = 0;
+        ctx->t_bytes[i] = 0.0;
     }
-    ctx->timing = enable != 0;
+    ctx->timing = mask & ((1u << AAO_NUM_KERNELS) - 1u);
     return AAO_OK;
 }
 
-aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count)
+aao_status aao_set_timing(aao_ctx ctx, int enable)
+{
+    return aao_set_timing_mask(ctx, enable ? ~0u : 0u);
+}
+
+aao_status aao_get_timing_ex(aao_ctx ctx, int kernel, double *total_ms, int64_t *count,
+                             double *bytes)
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
@@ -1024,17 +1052,24 @@ aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *co
     AAO_HIP(hipStreamSynchronize(ctx->st));
     for (auto &p : ctx->ev_pending) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
-            ctx->t_total[p.first] += ms;
-            ctx->t_count[p.first] += 1;
+        if (hipEventElapsedTime(&ms, p.e0, p.e1) == hipSuccess) {
+            ctx->t_total[p.id] += ms;
+            ctx->t_count[p.id] += 1;
+            ctx->t_bytes[p.id] += p.bytes;
         }
-        ctx->ev_pool.push_back(p.second.first);
-        ctx->ev_pool.push_back(p.second.second);
+        ctx->ev_pool.push_back(p.e0);
+        ctx->ev_pool.push_back(p.e1);
     }
     ctx->ev_pending.clear();
     *total_ms = ctx->t_total[kernel];
     *count = ctx->t_count[kernel];
+    if (bytes) *bytes = ctx->t_bytes[kernel];
     return AAO_OK;
+}
+
+aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count)
+{
+    return aao_get_timing_ex(ctx, kernel, total_ms, count, nullptr);
 }
 
 aao_status aao_tune(aao_ctx ctx, int reps)
