@@ -60,6 +60,10 @@ struct aao_ctx_s {
     int *fail = nullptr;         // shifted-solve breakdown flag
     double *sym = nullptr;       // per-row d_j, e_j of the shifted solves
     double sym_kappa = NAN;      // kappa the table was built for
+    void *ptab = nullptr;        // partition tables of the shifted solves
+    double ptab_kappa = NAN;     // ... built for this kappa,
+    int ptab_cw = -1;            // chunk width
+    int ptab_single = -1;        // and arithmetic
 
     // GMRES workspace
     int m_alloc = 0;
@@ -276,6 +280,26 @@ static aao_status refresh_symbols(aao_ctx ctx)
     return AAO_OK;
 }
 
+// rebuild the partition tables of the shifted solves for launch shape `cfg` after a
+// change of kappa, chunk width or arithmetic (synchronised like the symbols)
+static aao_status refresh_tables(aao_ctx ctx, int cfg, bool sync)
+{
+    const int n = (int)ctx->n;
+    cfg = solve_effective_config(cfg, n);
+    int cw = 0, nt = 0, stg = 0;
+    solve_config_shape(cfg, &cw, &nt, &stg);
+    const int single = ctx->prec == AAO_PREC_FP32 ? 1 : 0;
+    if (ctx->ptab_kappa == ctx->kappa && ctx->ptab_cw == cw && ctx->ptab_single == single)
+        return AAO_OK;
+    AAO_TRY(refresh_symbols(ctx));
+    AAO_HIP(launch_solve_tables(ctx->sym, n, (int)ctx->ell, cfg, single != 0, ctx->ptab, ctx->st));
+    if (sync) AAO_HIP(hipStreamSynchronize(ctx->st));
+    ctx->ptab_kappa = ctx->kappa;
+    ctx->ptab_cw = cw;
+    ctx->ptab_single = single;
+    return AAO_OK;
+}
+
 // z = C^{-1} (s r - E zprev)  (one circulant apply; s from in_scale)
 static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale,
                             const double *zprev, double *z, int transpose)
@@ -284,13 +308,14 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     const bool single_arith = ctx->prec == AAO_PREC_FP32;
     const int n = (int)ctx->n, ell = (int)ctx->ell;
     AAO_TRY(refresh_symbols(ctx));
+    AAO_TRY(refresh_tables(ctx, ctx->cf(AAO_CFG_SHIFTED_SOLVE), true));
     if (ctx->bluestein && !zprev) {
         const BatchLaunch L = bl_launch(ctx);
         AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) + spec_bytes(ctx),
                      batch_fft_fwd(L, r, in_scale, 0, ctx->spec, single, ctx->st));
         AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, 2 * spec_bytes(ctx),
                    launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
-                                        transpose, ctx->fail, ctx->st,
+                                        ctx->ptab, transpose, ctx->fail, ctx->st,
                                         ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
         AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_bytes(ctx),
                      batch_fft_inv(L, ctx->spec, z, single, ctx->st));
@@ -301,7 +326,7 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
                               ctx->lds, single, ctx->tw, ctx->st, ctx->cf(AAO_CFG_FFT_FWD)));
     AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, 2 * spec_bytes(ctx),
                launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
-                                    transpose, ctx->fail, ctx->st,
+                                    ctx->ptab, transpose, ctx->fail, ctx->st,
                                     ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
     AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_bytes(ctx),
                launch_fft_inv(ctx->spec, ctx->lds, single, z, n, ell, ctx->tw, ctx->st,
@@ -390,9 +415,11 @@ static aao_status launch_kind(aao_ctx ctx, int kind, int code, double *buf)
     if (kind == AAO_CFG_FFT_FWD)
         AAO_HIP(launch_fft_fwd(buf, nullptr, nullptr, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
                                ctx->lds, single, ctx->tw, ctx->st, code));
-    else if (kind == AAO_CFG_SHIFTED_SOLVE)
+    else if (kind == AAO_CFG_SHIFTED_SOLVE) {
+        AAO_TRY(refresh_tables(ctx, code, false));
         AAO_HIP(launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
-                                     0, nullptr, ctx->st, code));
+                                     ctx->ptab, 0, nullptr, ctx->st, code));
+    }
     else
         AAO_HIP(launch_fft_inv(ctx->spec, ctx->lds, single, buf, n, ell, ctx->tw, ctx->st, code));
     return AAO_OK;
@@ -680,6 +707,7 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
         if ((s = dev_alloc(ctx, &ctx->spec, H * ctx->lds * 2 * sizeof(double))) != AAO_OK) break;
         if ((s = dev_alloc(ctx, (void **)&ctx->fail, sizeof(int))) != AAO_OK) break;
         if ((s = dev_alloc(ctx, (void **)&ctx->sym, sizeof(double) * 8 * H)) != AAO_OK) break;
+        if ((s = dev_alloc(ctx, &ctx->ptab, solve_table_bytes((int)ell))) != AAO_OK) break;
         ctx->nblk = dot_blocks(ctx->N());
         ctx->ldp = kPartStride;
         if ((s = dev_alloc(ctx, (void **)&ctx->part,
@@ -759,6 +787,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->spec);
     (void)hipFree(ctx->fail);
     (void)hipFree(ctx->sym);
+    (void)hipFree(ctx->ptab);
     (void)hipFree(ctx->part);
     if (ctx->hbuf) (void)hipHostFree(ctx->hbuf);
     (void)hipFree(ctx->small);

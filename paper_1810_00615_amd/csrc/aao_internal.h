@@ -68,15 +68,23 @@ int fft_configs(int ell, int n, bool single, int *out, int cap);
 bool fft_config_ok(int cfg, int ell, int n, bool single);
 // In-place shifted solves (alpha_j M + beta_j kappa K) Y_j = X_j for every
 // half-spectrum row j; `single_arith` selects single-precision arithmetic.  sym:
-// the per-row table of launch_symbols.
+// the per-row table of launch_symbols; ptab: the partition tables of
+// launch_solve_tables for the same configuration and arithmetic.
 // cfg selects the launch shape (chunk, threads, LDS staging) among
 // solve_num_configs(); a value that is out of range or does not cover n selects
 // solve_default_config(n).
 hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
-                                int n, int ell, const double *sym, int transpose,
-                                int *fail_flag, hipStream_t st, int cfg = -1);
+                                int n, int ell, const double *sym, const void *ptab,
+                                int transpose, int *fail_flag, hipStream_t st, int cfg = -1);
 // Per-row symbol table, (ell/2 + 1) x 2 orientations x (d, e) complex = 8 doubles a row.
 hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, hipStream_t st);
+// Partition tables (interior elimination factors and response end values) of every
+// row and orientation for the chunk width of configuration cfg, in the solve's
+// arithmetic; out holds solve_table_bytes(ell).
+hipError_t launch_solve_tables(const double *sym, int n, int ell, int cfg, bool single_arith,
+                               void *out, hipStream_t st);
+size_t solve_table_bytes(int ell);
+int solve_effective_config(int cfg, int n);
 int solve_num_configs();
 bool solve_config_ok(int cfg, int n);
 void solve_config_shape(int cfg, int *cw, int *nt, int *stage);

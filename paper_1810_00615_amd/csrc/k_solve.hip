@@ -30,7 +30,7 @@ namespace aao {
 template <typename A, typename S, int CW, int NTB, bool STAGE>
 __global__ void __launch_bounds__(NTB)
 k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restrict__ sym,
-                int transpose, int *__restrict__ fail)
+                const cx<A> *__restrict__ ptab, int transpose, int *__restrict__ fail)
 {
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
@@ -66,7 +66,8 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
     const cx<A> d = {A(sj[0]), A(sj[1])};
     const cx<A> e = {A(sj[2]), A(sj[3])};
 
-    const bool bad = partition_solve<A, CW>(y, n, d, e, tab, red);
+    const cx<A> *rtab = ptab + ((size_t)j * 2 + (transpose ? 1 : 0)) * psolve_tab_entries(CW);
+    const bool bad = partition_solve<A, CW, true>(y, n, d, e, tab, red, rtab);
     if (STAGE) {
 #pragma unroll
         for (int i = 0; i < CW; ++i)
@@ -136,7 +137,7 @@ int solve_default_config(int n)
 
 template <typename A, typename S, int CW, int NT, bool STAGE>
 static hipError_t solve_go(void *spec, int lds, int n, int ell, const double *sym,
-                           int transpose, int *fail, hipStream_t st)
+                           const void *ptab, int transpose, int *fail, hipStream_t st)
 {
     size_t smem = sizeof(cx<A>) * psolve_lds_entries(CW, NT);
     if (STAGE) {
@@ -150,20 +151,22 @@ static hipError_t solve_go(void *spec, int lds, int n, int ell, const double *sy
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    kern<<<ell / 2 + 1, NT, smem, st>>>(reinterpret_cast<cx<S> *>(spec), lds, n, sym, transpose,
-                                        fail);
+    kern<<<ell / 2 + 1, NT, smem, st>>>(reinterpret_cast<cx<S> *>(spec), lds, n, sym,
+                                        reinterpret_cast<const cx<A> *>(ptab), transpose, fail);
     return hipGetLastError();
 }
 
 template <typename A, typename S>
 static hipError_t solve_disp(int cfg, void *spec, int lds, int n, int ell, const double *sym,
-                             int transpose, int *fail, hipStream_t st)
+                             const void *ptab, int transpose, int *fail, hipStream_t st)
 {
     const bool stage = cfg >= kNumSolveCfg;
 #define AAO_SCFG(I, CW, NT)                                                                    \
     case I:                                                                                    \
-        return stage ? solve_go<A, S, CW, NT, true>(spec, lds, n, ell, sym, transpose, fail, st) \
-                     : solve_go<A, S, CW, NT, false>(spec, lds, n, ell, sym, transpose, fail, st);
+        return stage ? solve_go<A, S, CW, NT, true>(spec, lds, n, ell, sym, ptab, transpose,     \
+                                                    fail, st)                                  \
+                     : solve_go<A, S, CW, NT, false>(spec, lds, n, ell, sym, ptab, transpose,    \
+                                                     fail, st);
     switch (cfg % kNumSolveCfg) {
         AAO_SCFG(0, 1, 256)
         AAO_SCFG(1, 2, 256)
@@ -349,17 +352,72 @@ hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, 
     return hipGetLastError();
 }
 
-hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
-                                int n, int ell, const double *sym, int transpose,
-                                int *fail_flag, hipStream_t st, int cfg)
+// Partition tables of every row and orientation for chunk width CW (build_tab):
+// out[((2 j + tr) * psolve_tab_entries(CW) + i], one thread per (row, orientation).
+template <typename A, int CW>
+__global__ void k_ptab(const double *__restrict__ sym, int rows, int n, cx<A> *__restrict__ out)
 {
-    if (!solve_config_ok(cfg, n)) cfg = solve_default_config(n);
-    if (!solve_config_ok(cfg, n)) return hipErrorInvalidValue;
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= 2 * rows) return;
+    const double *sj = sym + (size_t)id * 4;
+    const cx<A> d = {A(sj[0]), A(sj[1])};
+    const cx<A> e = {A(sj[2]), A(sj[3])};
+    const int P = (n + CW - 1) / CW;
+    build_tab<A, CW>(d, e, n - (P - 1) * CW - 1, out + (size_t)id * psolve_tab_entries(CW));
+}
+
+size_t solve_table_bytes(int ell)
+{
+    return sizeof(cx<double>) * 2 * (size_t)(ell / 2 + 1) * psolve_tab_entries(32);
+}
+
+int solve_effective_config(int cfg, int n)
+{
+    return solve_config_ok(cfg, n) ? cfg : solve_default_config(n);
+}
+
+template <typename A>
+static hipError_t ptab_disp(int cw, const double *sym, int n, int ell, void *out, hipStream_t st)
+{
+    const int rows = ell / 2 + 1;
+    const int grid = (2 * rows + 255) / 256;
+    cx<A> *o = reinterpret_cast<cx<A> *>(out);
+    switch (cw) {
+    case 1: k_ptab<A, 1><<<grid, 256, 0, st>>>(sym, rows, n, o); break;
+    case 2: k_ptab<A, 2><<<grid, 256, 0, st>>>(sym, rows, n, o); break;
+    case 4: k_ptab<A, 4><<<grid, 256, 0, st>>>(sym, rows, n, o); break;
+    case 8: k_ptab<A, 8><<<grid, 256, 0, st>>>(sym, rows, n, o); break;
+    case 16: k_ptab<A, 16><<<grid, 256, 0, st>>>(sym, rows, n, o); break;
+    case 32: k_ptab<A, 32><<<grid, 256, 0, st>>>(sym, rows, n, o); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_tables(const double *sym, int n, int ell, int cfg, bool single_arith,
+                               void *out, hipStream_t st)
+{
+    cfg = solve_effective_config(cfg, n);
+    if (cfg < 0) return hipErrorInvalidValue;
+    int cw, nt, stage;
+    solve_config_shape(cfg, &cw, &nt, &stage);
+    return single_arith ? ptab_disp<float>(cw, sym, n, ell, out, st)
+                        : ptab_disp<double>(cw, sym, n, ell, out, st);
+}
+
+hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
+                                int n, int ell, const double *sym, const void *ptab,
+                                int transpose, int *fail_flag, hipStream_t st, int cfg)
+{
+    cfg = solve_effective_config(cfg, n);
+    if (cfg < 0 || !ptab) return hipErrorInvalidValue;
     if (!single_store)
-        return solve_disp<double, double>(cfg, spec, lds, n, ell, sym, transpose, fail_flag, st);
+        return solve_disp<double, double>(cfg, spec, lds, n, ell, sym, ptab, transpose,
+                                          fail_flag, st);
     if (!single_arith)
-        return solve_disp<double, float>(cfg, spec, lds, n, ell, sym, transpose, fail_flag, st);
-    return solve_disp<float, float>(cfg, spec, lds, n, ell, sym, transpose, fail_flag, st);
+        return solve_disp<double, float>(cfg, spec, lds, n, ell, sym, ptab, transpose,
+                                         fail_flag, st);
+    return solve_disp<float, float>(cfg, spec, lds, n, ell, sym, ptab, transpose, fail_flag, st);
 }
 
 }  // namespace aao

@@ -66,47 +66,86 @@ __device__ __forceinline__ cx<A> shfl_cx(cx<A> v, int src)
 // staging area the caller has finished reading: the first barrier below precedes
 // every write to it, and the last barrier follows every read).  Every thread of
 // the block must call it.  Returns true if a value is not finite.
-template <typename A, int CW>
-__device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *tab, cx<A> *red)
+// Table of the interior elimination of a chunk of CW unknowns (one thread):
+// tab[0..CW-2] 1/pivot, tab[CW..2CW-2] e/pivot, tab[2CW..3CW-2] the forward part of
+// the response to the left separator, tab[3CW..3CW+7] the first / last values of
+// both responses for full chunks (slots 0-3) and for the last chunk, whose interior
+// has mlast unknowns (slots 4-7).
+template <typename A, int CW, typename P>
+__device__ __forceinline__ void build_tab(cx<A> d, cx<A> e, int mlast, P tab)
+{
+    const cx<A> zero = {A(0), A(0)};
+    // pivots of the interior elimination and the forward part of u (the response to
+    // -e in the first interior equation)
+    cx<A> cprev = zero, g = zero;
+    for (int i = 0; i < CW - 1; ++i) {
+        const cx<A> ip = recip(cfms(d, e, cprev));
+        tab[i] = ip;
+        cprev = e * ip;
+        tab[CW + i] = cprev;
+        g = (i == 0) ? -(e * ip) : -((e * g) * ip);
+        tab[2 * CW + i] = g;
+    }
+    for (int k = 0; k < 2; ++k) {
+        const int mi = k == 0 ? CW - 1 : mlast;
+        cx<A> uf = zero, ul = zero, vf = zero, vl = zero;
+        if (mi > 0) {
+            ul = tab[2 * CW + mi - 1];
+            vl = -(e * tab[mi - 1]);
+            uf = ul;
+            vf = vl;
+            for (int i = mi - 2; i >= 0; --i) {
+                uf = cfms(tab[2 * CW + i], tab[CW + i], uf);
+                vf = -(tab[CW + i] * vf);
+            }
+        }
+        tab[3 * CW + 4 * k + 0] = uf;
+        tab[3 * CW + 4 * k + 1] = ul;
+        tab[3 * CW + 4 * k + 2] = vf;
+        tab[3 * CW + 4 * k + 3] = vl;
+    }
+}
+
+// Solve tridiag(e, d, e) x = r with n unknowns.  Thread t owns unknowns
+// [t*CW, t*CW + len); y[] holds its part of r on entry and of x on exit.
+//
+// Chunk t is split into an interior (its first len-1 unknowns) and a separator
+// (its last unknown).  With the interior eliminated, x_i = y_i + u_i X_{t-1} +
+// v_i X_t, where y is the interior solution with zero neighbours and u, v its
+// responses to the left / right separator.  The matrix being Toeplitz, the
+// elimination factors (1/pivot, e/pivot), the forward part of u and the end values
+// of u and v are the same for every full chunk: they form one table per row
+// (build_tab) in LDS, built by one thread or (GTAB) copied from a table precomputed
+// per row, and every thread regenerates u and v backwards from it, so a thread
+// keeps only y in registers.
+//
+// The separators satisfy a tridiagonal system with one equation per chunk.  Its
+// equations are normalised to a unit diagonal and reduced by cyclic reduction
+// (even-numbered unknowns survive each level, compacted) until at most 64 remain;
+// one wave solves those by parallel cyclic reduction with lane shuffles, and the
+// eliminated unknowns are recovered level by level.  No pivoting, as in the
+// Thomas algorithm the method prescribes per block.
+//
+// tab: psolve_tab_entries(CW) entries of LDS (NT >= that count with GTAB); red: 6*NT entries
+// (may alias a staging area the caller has finished reading: the first barrier
+// below precedes every write to it, and the last barrier follows every read).
+// Every thread of the block must call it.  Returns true if a value is not finite.
+template <typename A, int CW, bool GTAB = false>
+__device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *tab, cx<A> *red,
+                                const cx<A> *__restrict__ gtab = nullptr)
 {
     const int NT = blockDim.x;
     const int t = threadIdx.x;
-    cx<A> *s_ip = tab, *s_cp = tab + CW, *s_gu = tab + 2 * CW, *s_end = tab + 3 * CW;
     const cx<A> zero = {A(0), A(0)};
     const int P = (n + CW - 1) / CW;                     // number of chunks / separators
     const int mlast = n - (P - 1) * CW - 1;              // interior length of the last chunk
-    if (t == 0) {
-        // pivots of the interior elimination and the forward part of u (the
-        // response to -e in the first interior equation)
-        cx<A> cprev = zero, g = zero;
-        for (int i = 0; i < CW - 1; ++i) {
-            const cx<A> ip = recip(cfms(d, e, cprev));
-            s_ip[i] = ip;
-            cprev = e * ip;
-            s_cp[i] = cprev;
-            g = (i == 0) ? -(e * ip) : -((e * g) * ip);
-            s_gu[i] = g;
-        }
-        // first / last values of u and v: full chunks (slots 0-3), last chunk (4-7)
-        for (int k = 0; k < 2; ++k) {
-            const int mi = k == 0 ? CW - 1 : mlast;
-            cx<A> uf = zero, ul = zero, vf = zero, vl = zero;
-            if (mi > 0) {
-                ul = s_gu[mi - 1];
-                vl = -(e * s_ip[mi - 1]);
-                uf = ul;
-                vf = vl;
-                for (int i = mi - 2; i >= 0; --i) {
-                    uf = cfms(s_gu[i], s_cp[i], uf);
-                    vf = -(s_cp[i] * vf);
-                }
-            }
-            s_end[4 * k + 0] = uf;
-            s_end[4 * k + 1] = ul;
-            s_end[4 * k + 2] = vf;
-            s_end[4 * k + 3] = vl;
-        }
+    if (GTAB) {
+        // copy the precomputed table into LDS (read there as broadcasts)
+        if (t < psolve_tab_entries(CW)) tab[t] = gtab[t];
+    } else if (t == 0) {
+        build_tab<A, CW>(d, e, mlast, tab);
     }
+    const cx<A> *s_ip = tab, *s_cp = tab + CW, *s_gu = tab + 2 * CW, *s_end = tab + 3 * CW;
     // level-0 reduced system (a | c | d, NT each), then the neighbour terms and the
     // compacted deeper levels in the second half
     cx<A> *a0 = red, *c0 = red + NT, *d0 = red + 2 * NT, *ny = red + 3 * NT;
