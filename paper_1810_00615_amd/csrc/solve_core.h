@@ -160,7 +160,9 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
 #pragma unroll
     for (int i = 0; i < CW; ++i)
         if (i == mi) rsep = y[i];
-    // interior: forward elimination and back substitution in place
+    // interior: forward elimination in place (y becomes the forward sweep g); the
+    // back substitution is deferred until the separators are known, only its
+    // first value y_0 = g_0 - cp_0 (g_1 - cp_1 (...)) is formed now
     cx<A> gy = zero;
 #pragma unroll
     for (int i = 0; i < CW - 1; ++i) {
@@ -169,21 +171,22 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
             y[i] = gy;
         }
     }
-#pragma unroll
-    for (int i = CW - 3; i >= 0; --i)
-        if (i < mi - 1) y[i] = cfms(y[i], s_cp[i], y[i + 1]);
-
-    const int eo = last ? 4 : 0;
-    const cx<A> ulast = mi > 0 ? s_end[eo + 1] : zero;
-    const cx<A> vlast = mi > 0 ? s_end[eo + 3] : zero;
     cx<A> ylast = zero;
 #pragma unroll
     for (int i = 0; i < CW - 1; ++i)
         if (i == mi - 1) ylast = y[i];
+    cx<A> yfirst = ylast;
+#pragma unroll
+    for (int i = CW - 3; i >= 0; --i)
+        if (i < mi - 1) yfirst = cfms(y[i], s_cp[i], yfirst);
+
+    const int eo = last ? 4 : 0;
+    const cx<A> ulast = mi > 0 ? s_end[eo + 1] : zero;
+    const cx<A> vlast = mi > 0 ? s_end[eo + 3] : zero;
 
     // equation t:  lo X_{t-1} + di X_t + up X_{t+1} = rh, where the next chunk's
     // first unknown (interior or separator) has been eliminated
-    if (t < P) ny[t] = (mi > 0) ? e * y[0] : zero;
+    if (t < P) ny[t] = (mi > 0) ? e * yfirst : zero;
     __syncthreads();
     if (t < P) {
         cx<A> lo = (mi > 0) ? e * ulast : e;
@@ -286,20 +289,23 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
         XR = d0[t];
     }
     __syncthreads();   // the caller may reuse `red` from here on
-    // interior: x_i = y_i + u_i XL + v_i XR, u and v regenerated from the back
+    // interior: the forward sweep of the full right-hand side r - e XL e_0 - e XR
+    // e_last is g + XL gu (+ vlast XR in the last entry); back substitution
     bool bad = false;
     if (t < P) {
-        cx<A> ui = ulast, vi = vlast;
+        cx<A> xn = XR;   // x_{i+1}; the separator for i = mi - 1
 #pragma unroll
         for (int i = CW - 2; i >= 0; --i) {
             if (i < mi) {
-                if (i < mi - 1) {
-                    const cx<A> cpi = s_cp[i];
-                    ui = cfms(s_gu[i], cpi, ui);
-                    vi = -(cpi * vi);
+                cx<A> g = cfma(y[i], s_gu[i], XL);
+                if (i == mi - 1) {
+                    g = cfma(g, vlast, XR);
+                    xn = g;
+                } else {
+                    xn = cfms(g, s_cp[i], xn);
                 }
-                y[i] = cfma(cfma(y[i], ui, XL), vi, XR);
-                bad |= !(isfinite((double)y[i].x) && isfinite((double)y[i].y));
+                y[i] = xn;
+                bad |= !(isfinite((double)xn.x) && isfinite((double)xn.y));
             }
         }
 #pragma unroll
