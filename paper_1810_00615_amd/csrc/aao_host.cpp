@@ -300,9 +300,15 @@ static aao_status refresh_tables(aao_ctx ctx, int cfg, bool sync)
     return AAO_OK;
 }
 
-// z = C^{-1} (s r - E zprev)  (one circulant apply; s from in_scale)
+static aao_status launch_small(aao_ctx ctx, int mode, int nv, int nblk);
+
+// z = C^{-1} (s r - E zprev)  (one circulant apply; s from in_scale).  With
+// first_norm (power-of-two ell, no zprev, in_scale unused): the forward transform
+// also forms ||r||^2, the fused reduction sets s = 1/||r|| on the device (mode 4 of
+// k_reduce_small) and the inverse transform applies s to its output -- the first
+// basis vector of a zero-initial-guess solve, whose norm costs no separate pass.
 static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale,
-                            const double *zprev, double *z, int transpose)
+                            const double *zprev, double *z, int transpose, bool first_norm = false)
 {
     const bool single = ctx->prec != AAO_PREC_FP64;
     const bool single_arith = ctx->prec == AAO_PREC_FP32;
@@ -322,15 +328,18 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
         return AAO_OK;
     }
     AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) * (zprev ? 2 : 1) + spec_bytes(ctx),
-               launch_fft_fwd(r, in_scale, zprev, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
-                              ctx->lds, single, ctx->tw, ctx->st, ctx->cf(AAO_CFG_FFT_FWD)));
+               launch_fft_fwd(r, first_norm ? nullptr : in_scale, zprev, ctx->sigk, ctx->kappa,
+                              n, ell, ctx->spec, ctx->lds, single, ctx->tw, ctx->st,
+                              ctx->cf(AAO_CFG_FFT_FWD), first_norm ? ctx->part : nullptr));
+    if (first_norm)
+        AAO_TRY(launch_small(ctx, 4, 1, fft_fwd_blocks(ell, n, single, ctx->cf(AAO_CFG_FFT_FWD))));
     AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, 2 * spec_bytes(ctx),
                launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
                                     ctx->ptab, transpose, ctx->fail, ctx->st,
                                     ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
     AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_bytes(ctx),
                launch_fft_inv(ctx->spec, ctx->lds, single, z, n, ell, ctx->tw, ctx->st,
-                              ctx->cf(AAO_CFG_FFT_INV)));
+                              ctx->cf(AAO_CFG_FFT_INV), first_norm ? in_scale : nullptr));
     return AAO_OK;
 }
 
@@ -485,11 +494,20 @@ static aao_status tune_impl(aao_ctx ctx, int reps, double *buf)
 // The forward transform reads z_{m-1} completely before the inverse transform
 // overwrites it, so the recurrence runs in place.
 static aao_status pinv_impl(aao_ctx ctx, const double *r, const double *in_scale, double *z,
-                            int order, int transpose)
+                            int order, int transpose, bool first_norm = false)
 {
-    AAO_TRY(pinv_once(ctx, r, in_scale, nullptr, z, transpose));
+    AAO_TRY(pinv_once(ctx, r, in_scale, nullptr, z, transpose, first_norm));
     if (ctx->tauk)
         for (int m = 0; m < order; ++m) AAO_TRY(pinv_once(ctx, r, in_scale, z, z, transpose));
+    return AAO_OK;
+}
+
+// fused fixed-order reduction of ctx->part + Krylov scalar update (k_reduce_small)
+static aao_status launch_small(aao_ctx ctx, int mode, int nv, int nblk)
+{
+    const SmallArgs sa{mode, nv, ctx->sh1(), ctx->sh2(), ctx->sc_(), ctx->svs(), ctx->hdev,
+                       ctx->fail};
+    AAO_HIP(launch_reduce_small(ctx->part, nblk, ctx->ldp, sa, ctx->st));
     return AAO_OK;
 }
 
@@ -509,53 +527,68 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     const int nb = dot_blocks(N), ldp = ctx->ldp;
     volatile double *hb = ctx->hbuf;
     AAO_HIP(hipMemsetAsync(ctx->fail, 0, sizeof(int), st));
-    SmallArgs sa{0, 0, ctx->sh1(), ctx->sh2(), ctx->sc_(), ctx->svs(), ctx->hdev, ctx->fail};
-    auto small = [&](int mode, int nv, int nblk) -> aao_status {
-        sa.mode = mode;
-        sa.nv = nv;
-        AAO_HIP(launch_reduce_small(ctx->part, nblk, ldp, sa, st));
-        return AAO_OK;
-    };
+    auto small = [&](int mode, int nv, int nblk) { return launch_small(ctx, mode, nv, nblk); };
 
     // basis V_j (V_0 = b for a zero initial guess) and search directions Z_j
     VecList Vl{}, Zl{};
     for (int j = 0; j <= m; ++j) Vl.p[j] = ctx->V + N * j;
     for (int j = 0; j < m; ++j) Zl.p[j] = ctx->Z + N * j;
     double *V0 = ctx->V;
+    const int mcfg = ctx->cf(AAO_CFG_MATVEC);
+    const bool fused = matvec_blocks(n, ell, mcfg) <= ldp;
     auto residual = [&]() -> aao_status {
-        // V_0 = b - A x, vs_0 = 1/||V_0||
+        // V_0 = b - A x, vs_0 = 1/||V_0|| (the norm formed by the same launch)
+        if (fused) {
+            VecList self{};
+            self.p[0] = V0;
+            AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * 3,
+                         launch_matvec(x, V0, b, n, ell, ctx->sc, ctx->kappa, ctx->tauk,
+                                       transpose, st, mcfg, &self, 1, ctx->part, ldp));
+            return small(3, 0, matvec_blocks(n, ell, mcfg));
+        }
         AAO_TRY(apply_A_impl(ctx, x, V0, b, transpose));
         AAO_HIP(launch_dot1_parts(V0, V0, N, ctx->part, st));
         return small(3, 0, nb);
     };
 
-    // ||b|| and the first residual, one synchronisation
+    // ||b|| and the first residual.  With a zero initial guess on a power-of-two
+    // length the norm of b is formed inside the first preconditioner apply
+    // (pinv_once, first_norm) and read with the first Hessenberg column; otherwise
+    // one synchronisation here.
     aao_info inf{};
-    AAO_HIP(launch_dot1_parts(b, b, N, ctx->part, st));
-    AAO_TRY(small(4, zero_guess ? 1 : 0, nb));
-    if (zero_guess)
-        Vl.p[0] = b;
-    else
-        AAO_TRY(residual());
-    AAO_HIP(hipStreamSynchronize(st));
-    const double bnorm = std::sqrt(hb[kHostBB]);
-    double beta = hb[kHostBeta];
-    if (!std::isfinite(bnorm)) {
-        ctx->err = "non-finite right-hand side";
-        return AAO_ERR_NUMERIC;
-    }
-    if (bnorm == 0.0) {
-        AAO_HIP(launch_fill(x, 0.0, N, st));
-        AAO_HIP(hipStreamSynchronize(st));
-        inf.converged = 1;
-        if (info) *info = inf;
+    const bool defer_b = zero_guess && !ctx->bluestein && fft_supported_fast(ell) && maxit > 0;
+    double bnorm = 0.0, beta = 0.0;
+    if (zero_guess) Vl.p[0] = b;
+    auto check_b = [&]() -> aao_status {
+        bnorm = std::sqrt(hb[kHostBB]);
+        if (!std::isfinite(bnorm)) {
+            ctx->err = "non-finite right-hand side";
+            return AAO_ERR_NUMERIC;
+        }
         return AAO_OK;
-    }
-    inf.rel_resid_true = beta / bnorm;
-    inf.rel_resid_est = inf.rel_resid_true;
-    if (!std::isfinite(beta)) {
-        ctx->err = "non-finite residual";
-        return AAO_ERR_NUMERIC;
+    };
+    if (!defer_b) {
+        AAO_HIP(launch_dot1_parts(b, b, N, ctx->part, st));
+        AAO_TRY(small(4, zero_guess ? 1 : 0, nb));
+        if (!zero_guess) AAO_TRY(residual());
+        AAO_HIP(hipStreamSynchronize(st));
+        AAO_TRY(check_b());
+        beta = hb[kHostBeta];
+        if (bnorm == 0.0) {
+            AAO_HIP(launch_fill(x, 0.0, N, st));
+            AAO_HIP(hipStreamSynchronize(st));
+            inf.converged = 1;
+            if (info) *info = inf;
+            return AAO_OK;
+        }
+        inf.rel_resid_true = beta / bnorm;
+        inf.rel_resid_est = inf.rel_resid_true;
+        if (!std::isfinite(beta)) {
+            ctx->err = "non-finite residual";
+            return AAO_ERR_NUMERIC;
+        }
+    } else {
+        inf.rel_resid_true = inf.rel_resid_est = 1.0;   // x0 = 0: r0 = b
     }
     bool x_zero = zero_guess;   // x not yet written
     auto finish_zero = [&]() -> aao_status {
@@ -565,15 +598,13 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
         }
         return AAO_OK;
     };
-    if (beta / bnorm <= tol || maxit == 0) {
+    if (!defer_b && (beta / bnorm <= tol || maxit == 0)) {
         AAO_TRY(finish_zero());
         inf.converged = beta / bnorm <= tol;
         if (info) *info = inf;
         return inf.converged ? AAO_OK : AAO_NOT_CONVERGED;
     }
 
-    const int mcfg = ctx->cf(AAO_CFG_MATVEC);
-    const bool fused = matvec_blocks(n, ell, mcfg) <= ldp;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
     bool failed = false;
     while (inf.iters < maxit) {
@@ -587,7 +618,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             double *Vn = ctx->V + N * (j + 1);
             const int nv = j + 1;
             // z_j = P^{-1} v_j ; w = A z_j with the first projection V^T w
-            AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose));
+            const bool first = defer_b && inf.iters == 0;
+            AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose, first));
             if (fused) {
                 AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (2 + nv),
                              launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc, ctx->kappa,
@@ -607,6 +639,19 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                                                                  N, ctx->part, ldp, st));
             AAO_TRY(small(2, nv, nb));
             AAO_HIP(hipStreamSynchronize(st));
+            if (first) {
+                AAO_TRY(check_b());
+                if (bnorm == 0.0) {
+                    AAO_HIP(launch_fill(x, 0.0, N, st));
+                    AAO_HIP(hipStreamSynchronize(st));
+                    inf.rel_resid_true = inf.rel_resid_est = 0.0;
+                    inf.converged = 1;
+                    if (info) *info = inf;
+                    return AAO_OK;
+                }
+                beta = bnorm;
+                g[0] = beta;
+            }
             for (int i = 0; i <= nv; ++i) hcol[i] = hb[i];
             failed = failed || hb[kHostFail] != 0.0;
             inf.iters++;

@@ -55,12 +55,18 @@ hipError_t launch_twiddles(double *tw, int len, int count, hipStream_t st);
 // float2/double2 according to `single`).
 // in_scale (device scalar or nullptr) multiplies r.
 // cfg: launch shape (16 v + log2 W, see fft_configs), negative = default.
+// norm_part (power-of-two ell, no zprev): one partial of ||r||^2 (r unscaled) per
+// workgroup, fft_fwd_blocks() of them.
 hipError_t launch_fft_fwd(const double *r, const double *in_scale, const double *zprev,
                           const double *sigk, double kappa, int n, int ell, void *spec, int lds,
-                          bool single, const double *tw, hipStream_t st, int cfg = -1);
-// Inverse of the above: z (ell x n real) from the half spectrum.
+                          bool single, const double *tw, hipStream_t st, int cfg = -1,
+                          double *norm_part = nullptr);
+int fft_fwd_blocks(int ell, int n, bool single, int cfg);
+// Inverse of the above: z (ell x n real) from the half spectrum, times *out_scale
+// (device scalar, power-of-two ell) if given.
 hipError_t launch_fft_inv(const void *spec, int lds, bool single, double *z, int n, int ell,
-                          const double *tw, hipStream_t st, int cfg = -1);
+                          const double *tw, hipStream_t st, int cfg = -1,
+                          const double *out_scale = nullptr);
 // Admissible launch shapes of the power-of-two transforms for (ell, n, element
 // type): writes up to cap of them to out, returns how many there are (0 when ell
 // is not a supported power of two).

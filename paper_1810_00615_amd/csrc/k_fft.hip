@@ -28,15 +28,18 @@ __global__ void __launch_bounds__(1024)
 k_fft_fwd(const double *__restrict__ r, const double *__restrict__ in_scale,
           const double *__restrict__ zprev, const double *__restrict__ sigk, double kap_h, int n,
           int W,
-          cx<T> *__restrict__ X, int lds, const cx<double> *__restrict__ tw)
+          cx<T> *__restrict__ X, int lds, const cx<double> *__restrict__ tw,
+          double *__restrict__ norm_part)
 {
     extern __shared__ unsigned char smraw[];
+    __shared__ double nsum[16];
     T *sm = reinterpret_cast<T *>(smraw);
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int col = xcd_tile(blockIdx.x, gridDim.x) * W + c;
     const bool valid = col < n;
     const double rs = in_scale ? *in_scale : 1.0;
+    double nrm = 0.0;   // sum of the squared inputs (norm_part)
     cx<T> v[P];
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
@@ -45,8 +48,11 @@ k_fft_fwd(const double *__restrict__ r, const double *__restrict__ in_scale,
         if (valid) {
             const size_t o0 = (size_t)(2 * pos) * n + col;
             const size_t o1 = o0 + n;
-            a = rs * r[o0];
-            b = rs * r[o1];
+            a = r[o0];
+            b = r[o1];
+            nrm += a * a + b * b;
+            a *= rs;
+            b *= rs;
             if (NEU) {
                 const double zl0 = col > 0 ? zprev[o0 - 1] : 0.0;
                 const double zr0 = col < n - 1 ? zprev[o0 + 1] : 0.0;
@@ -59,6 +65,24 @@ k_fft_fwd(const double *__restrict__ r, const double *__restrict__ in_scale,
         v[idx] = {T(a), T(b)};
     }
     run_stages<T, L, P, 0, false>(v, sm, t, c, W, tw, 2);
+    if (norm_part) {
+        // block partial of ||r||^2 (unscaled input), fixed order; blocks of fewer
+        // than 64 threads (short transforms) fill only part of their wave
+        const int lane = threadIdx.x & 63;
+        const int wl = blockDim.x < 64 ? (int)blockDim.x : 64;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_down(nrm, off, 64);
+            if (lane + off < wl) nrm += o;
+        }
+        if (lane == 0) nsum[threadIdx.x >> 6] = nrm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w2 = 0; w2 < (int)((blockDim.x + 63) >> 6); ++w2) s += nsum[w2];
+            norm_part[blockIdx.x] = s;
+        }
+    }
     // Split Z into the half spectrum.  With F_e = (Z_p + conj Z_{L-p})/2,
     // F_o = (Z_p - conj Z_{L-p})/2i and w = w_ell^p:
     //   X_p = F_e + w F_o,  X_{L-p} = conj(F_e - w F_o),  X_0 = Re Z_0 + Im Z_0,
@@ -111,7 +135,7 @@ k_fft_fwd(const double *__restrict__ r, const double *__restrict__ in_scale,
 template <typename T, int L, int P>
 __global__ void __launch_bounds__(1024)
 k_fft_inv(const cx<T> *__restrict__ Y, int lds, double *__restrict__ z, int n, int W,
-          const cx<double> *__restrict__ tw)
+          const cx<double> *__restrict__ tw, const double *__restrict__ out_scale)
 {
     extern __shared__ unsigned char smraw[];
     T *sm = reinterpret_cast<T *>(smraw);
@@ -147,7 +171,7 @@ k_fft_inv(const cx<T> *__restrict__ Y, int lds, double *__restrict__ z, int n, i
     }
     run_stages<T, L, P, 0, true>(v, sm, t, c, W, tw, 2);
     if (!valid) return;
-    const double inv = 1.0 / (2.0 * L);
+    const double inv = (1.0 / (2.0 * L)) * (out_scale ? *out_scale : 1.0);
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
         const int pos = final_pos<L, P>(t, idx);
@@ -279,7 +303,7 @@ bool fft_config_ok(int cfg, int ell, int n, bool single)
 template <typename T, int L, int P>
 static hipError_t fwd_LP(const double *r, const double *in_scale, const double *zprev,
                          const double *sigk, double kap_h, int n, void *spec, int lds,
-                         const double *tw, hipStream_t st, int W)
+                         const double *tw, hipStream_t st, int W, double *norm_part)
 {
     const size_t smem = (size_t)lds_rows(L) * W * sizeof(T);
     auto kern = zprev ? k_fft_fwd<T, L, P, true> : k_fft_fwd<T, L, P, false>;
@@ -291,29 +315,30 @@ static hipError_t fwd_LP(const double *r, const double *in_scale, const double *
     dim3 grid(xcd_grid((n + W - 1) / W));
     kern<<<grid, W * (L / P), smem, st>>>(r, in_scale, zprev, sigk, kap_h, n, W,
                                           reinterpret_cast<cx<T> *>(spec), lds,
-                                          reinterpret_cast<const cx<double> *>(tw));
+                                          reinterpret_cast<const cx<double> *>(tw), norm_part);
     return hipGetLastError();
 }
 
 template <typename T, int L>
 static hipError_t fwd_L(const double *r, const double *in_scale, const double *zprev,
                         const double *sigk, double kap_h, int n, void *spec, int lds,
-                        const double *tw, hipStream_t st, int cfg)
+                        const double *tw, hipStream_t st, int cfg, double *norm_part)
 {
     constexpr int P16 = L < 16 ? L : 16;
     if (cfg >= 16) {
         if constexpr (L >= 512 && L <= 4096)
             return fwd_LP<T, L, 8>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st,
-                                   1 << (cfg & 15));
+                                   1 << (cfg & 15), norm_part);
         return hipErrorInvalidValue;
     }
     const int W = cfg >= 0 ? 1 << cfg : default_w(L, P16, n, sizeof(T));
-    return fwd_LP<T, L, P16>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st, W);
+    return fwd_LP<T, L, P16>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st, W,
+                             norm_part);
 }
 
 template <typename T, int L, int P>
 static hipError_t inv_LP(const void *spec, int lds, double *z, int n, const double *tw,
-                         hipStream_t st, int W)
+                         hipStream_t st, int W, const double *out_scale)
 {
     const size_t smem = (size_t)lds_rows(L) * W * sizeof(T);
     auto kern = k_fft_inv<T, L, P>;
@@ -324,32 +349,35 @@ static hipError_t inv_LP(const void *spec, int lds, double *z, int n, const doub
     }
     dim3 grid(xcd_grid((n + W - 1) / W));
     kern<<<grid, W * (L / P), smem, st>>>(reinterpret_cast<const cx<T> *>(spec), lds, z, n, W,
-                                          reinterpret_cast<const cx<double> *>(tw));
+                                          reinterpret_cast<const cx<double> *>(tw), out_scale);
     return hipGetLastError();
 }
 
 template <typename T, int L>
 static hipError_t inv_L(const void *spec, int lds, double *z, int n, const double *tw,
-                        hipStream_t st, int cfg)
+                        hipStream_t st, int cfg, const double *out_scale)
 {
     constexpr int P16 = L < 16 ? L : 16;
     if (cfg >= 16) {
         if constexpr (L >= 512 && L <= 4096)
-            return inv_LP<T, L, 8>(spec, lds, z, n, tw, st, 1 << (cfg & 15));
+            return inv_LP<T, L, 8>(spec, lds, z, n, tw, st, 1 << (cfg & 15), out_scale);
         return hipErrorInvalidValue;
     }
     const int W = cfg >= 0 ? 1 << cfg : default_w(L, P16, n, sizeof(T));
-    return inv_LP<T, L, P16>(spec, lds, z, n, tw, st, W);
+    return inv_LP<T, L, P16>(spec, lds, z, n, tw, st, W, out_scale);
 }
 
 template <typename T>
 static hipError_t fwd_dispatch(const double *r, const double *in_scale, const double *zprev,
                                const double *sigk, double kap_h, int n, int ell, void *spec,
-                               int lds, const double *tw, hipStream_t st, int cfg)
+                               int lds, const double *tw, hipStream_t st, int cfg,
+                               double *norm_part)
 {
     switch (ell) {
 #define AAO_CASE(E) \
-    case E: return fwd_L<T, E / 2>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st, cfg);
+    case E:                                                                                  \
+        return fwd_L<T, E / 2>(r, in_scale, zprev, sigk, kap_h, n, spec, lds, tw, st, cfg,  \
+                               norm_part);
         AAO_CASE(2) AAO_CASE(4) AAO_CASE(8) AAO_CASE(16) AAO_CASE(32) AAO_CASE(64)
         AAO_CASE(128) AAO_CASE(256) AAO_CASE(512) AAO_CASE(1024) AAO_CASE(2048)
         AAO_CASE(4096) AAO_CASE(8192) AAO_CASE(16384)
@@ -365,11 +393,11 @@ static hipError_t fwd_dispatch(const double *r, const double *in_scale, const do
 
 template <typename T>
 static hipError_t inv_dispatch(const void *spec, int lds, double *z, int n, int ell,
-                               const double *tw, hipStream_t st, int cfg)
+                               const double *tw, hipStream_t st, int cfg, const double *out_scale)
 {
     switch (ell) {
 #define AAO_CASE(E) \
-    case E: return inv_L<T, E / 2>(spec, lds, z, n, tw, st, cfg);
+    case E: return inv_L<T, E / 2>(spec, lds, z, n, tw, st, cfg, out_scale);
         AAO_CASE(2) AAO_CASE(4) AAO_CASE(8) AAO_CASE(16) AAO_CASE(32) AAO_CASE(64)
         AAO_CASE(128) AAO_CASE(256) AAO_CASE(512) AAO_CASE(1024) AAO_CASE(2048)
         AAO_CASE(4096) AAO_CASE(8192) AAO_CASE(16384)
@@ -382,24 +410,37 @@ static hipError_t inv_dispatch(const void *spec, int lds, double *z, int n, int 
     return hipGetLastError();
 }
 
+int fft_fwd_blocks(int ell, int n, bool single, int cfg)
+{
+    if (!fft_supported_fast(ell)) return 0;
+    if (cfg >= 0 && !fft_config_ok(cfg, ell, n, single)) cfg = -1;
+    const int L = ell / 2;
+    const int P = cfg >= 16 ? 8 : (L < 16 ? L : 16);
+    const int W = cfg >= 0 ? 1 << (cfg & 15) : default_w(L, P, n, single ? 4 : 8);
+    return xcd_grid((n + W - 1) / W);
+}
+
 hipError_t launch_fft_fwd(const double *r, const double *in_scale, const double *zprev,
                           const double *sigk, double kappa, int n, int ell, void *spec, int lds,
-                          bool single, const double *tw, hipStream_t st, int cfg)
+                          bool single, const double *tw, hipStream_t st, int cfg,
+                          double *norm_part)
 {
     if (cfg >= 0 && !fft_config_ok(cfg, ell, n, single)) cfg = -1;
+    if (norm_part && (zprev || !fft_supported_fast(ell))) return hipErrorInvalidValue;
     const double kap_h = kappa * (n + 1.0);   // kappa / h
     return single ? fwd_dispatch<float>(r, in_scale, zprev, sigk, kap_h, n, ell, spec, lds, tw, st,
-                                        cfg)
+                                        cfg, norm_part)
                   : fwd_dispatch<double>(r, in_scale, zprev, sigk, kap_h, n, ell, spec, lds, tw,
-                                         st, cfg);
+                                         st, cfg, norm_part);
 }
 
 hipError_t launch_fft_inv(const void *spec, int lds, bool single, double *z, int n, int ell,
-                          const double *tw, hipStream_t st, int cfg)
+                          const double *tw, hipStream_t st, int cfg, const double *out_scale)
 {
     if (cfg >= 0 && !fft_config_ok(cfg, ell, n, single)) cfg = -1;
-    return single ? inv_dispatch<float>(spec, lds, z, n, ell, tw, st, cfg)
-                  : inv_dispatch<double>(spec, lds, z, n, ell, tw, st, cfg);
+    if (out_scale && !fft_supported_fast(ell)) return hipErrorInvalidValue;
+    return single ? inv_dispatch<float>(spec, lds, z, n, ell, tw, st, cfg, out_scale)
+                  : inv_dispatch<double>(spec, lds, z, n, ell, tw, st, cfg, out_scale);
 }
 
 }  // namespace aao

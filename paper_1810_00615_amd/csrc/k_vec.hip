@@ -279,7 +279,8 @@ hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double 
 // move (DPP wave shift when DPP is set, else ds_bpermute); lanes 0 and 63 fetch
 // the neighbour outside their wave with a second, two-lane load.  With nv > 0 the
 // kernel also leaves the block partials of V_q . y, q < nv (value-major, block id
-// y * gridDim.x + x), for the first Gram-Schmidt pass.
+// y * gridDim.x + x): the first Gram-Schmidt pass, or with nv = 1 and V_0 = y the
+// squared norm of a residual (from registers).
 template <bool DPP>
 __device__ __forceinline__ double lane_from_left(double v)
 {
@@ -305,7 +306,8 @@ __device__ __forceinline__ double lane_from_right(double v)
     }
 }
 
-template <int S, int R, bool DPP, bool DOTS>
+// DOTS: 0 none, 1 partials of V_q . y (q < nv), 2 the partial of y . y only
+template <int S, int R, bool DPP, int DOTS>
 __global__ void __launch_bounds__(256)
 k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
          int n, int ell, Scheme sc, double kappa, const double *__restrict__ tau_k, int transpose,
@@ -374,11 +376,22 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
         yv[it - S] = out;
         if (col) y[(size_t)k * n + i] = out;
     }
-    if (!DOTS) return;
-    // partial dot products V_q . y over this block's tile (first Gram-Schmidt pass)
+    if (DOTS == 0) return;
     __shared__ double red[kMaxVecs * 4];
     const int wv = threadIdx.x >> 6;
     const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    if (DOTS == 2) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc += (col && r < nin - S) ? yv[r] * yv[r] : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) red[wv] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) part[blk] = ((red[0] + red[1]) + red[2]) + red[3];
+        return;
+    }
+    // partial dot products V_q . y over this block's tile (first Gram-Schmidt pass)
     // four basis vectors at a time, all their loads issued before the sums
     for (int q0 = 0; q0 < nv; q0 += 4) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -420,12 +433,15 @@ static hipError_t matvec_disp(int cfg, const double *x, double *y, const double 
     dim3 grid((n + 255) / 256, (ell + R - 1) / R);
 #define AAO_MV(C, RR, D)                                                                    \
     case C:                                                                                 \
-        if (nv > 0)                                                                         \
-            k_matvec<S, RR, D, true><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa,   \
-                                                           tau_k, transpose, V, nv, part, ldp); \
+        if (nv > 0 && V.p[0] == y)                                                         \
+            k_matvec<S, RR, D, 2><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, tau_k, \
+                                                        transpose, V, 1, part, ldp);          \
+        else if (nv > 0)                                                                    \
+            k_matvec<S, RR, D, 1><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, tau_k, \
+                                                        transpose, V, nv, part, ldp);         \
         else                                                                                \
-            k_matvec<S, RR, D, false><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa,  \
-                                                            tau_k, transpose, V, 0, part, ldp); \
+            k_matvec<S, RR, D, 0><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, tau_k, \
+                                                        transpose, V, 0, part, ldp);          \
         break;
     switch (cfg) {
         AAO_MV(0, 4, false)
