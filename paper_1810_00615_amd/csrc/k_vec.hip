@@ -392,20 +392,23 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
         return;
     }
     // partial dot products V_q . y over this block's tile (first Gram-Schmidt pass)
-    // four basis vectors at a time, all their loads issued before the sums
-    for (int q0 = 0; q0 < nv; q0 += 4) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        double vq[4][R];
+    // two basis vectors at a time, all their loads issued before the sums
+    constexpr int G = 2;
+    for (int q0 = 0; q0 < nv; q0 += G) {
+        double acc[G];
+        double vq[G][R];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < G; ++u) {
+            acc[u] = 0.0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int k = transpose ? (k1 - 1 - r) : (k0 + r);
                 vq[u][r] = (q0 + u < nv && col && r < nin - S) ? V.p[q0 + u][(size_t)k * n + i]
                                                                 : 0.0;
             }
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < G; ++u) {
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[u] += vq[u][r] * yv[r];
 #pragma unroll

@@ -84,6 +84,16 @@ def trace_table(d, cmd=None):
     lines += ["", "| family | calls | avg us | total us |", "|---|---|---|---|"]
     for f, (c, t) in sorted(fams.items(), key=lambda kv: -kv[1][1]):
         lines.append(f"| {f} | {c} | {t / c:.1f} | {t:.1f} |")
+    stats = glob.glob(os.path.join(d, "**", "*_kernel_stats.csv"), recursive=True)
+    if stats:
+        lines += ["", "rocprofv3 --stats summary (`*_kernel_stats.csv`):", "",
+                  "| kernel | calls | avg us | min us | max us | percent |",
+                  "|---|---|---|---|---|---|"]
+        for f in stats:
+            for r in csv.DictReader(open(f)):
+                lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | "
+                             f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                             f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
     return "\n".join(lines)
 
 
