@@ -216,6 +216,7 @@ aao_status aao_get_timing_ex(aao_ctx ctx, int kernel, double *total_ms, int64_t 
  *     v = 0: min(ell/2, 16) points per thread (radix-16 stages), v = 1: 8 points per
  *     thread (radix-8 stages, ell = 1024..8192);
  *   AAO_CFG_SHIFTED_SOLVE: index of a (chunk CW, threads NT, LDS staging) triple;
+ *     a staged shape passes the row through LDS half a row at a time;
  *   AAO_CFG_MATVEC: 3 v + r, R = 4 << r time levels per thread, v = 1 for DPP
  *     cross-lane moves, v = 0 for ds_bpermute.
  * -1 means the built-in default.  Shapes are kept per precision mode.

@@ -23,10 +23,12 @@
 namespace aao {
 
 // One workgroup per frequency row.  STAGE: the row passes through LDS so that the
-// global accesses are coalesced (element i of chunk t in slot i*(NT+PAD) + t, PAD
-// = 2 for 16-byte and 4 for 8-byte elements, which spreads both the chunk-wise and
-// the coalesced accesses over all banks); otherwise every thread reads and writes
-// its own chunk directly.
+// global accesses are coalesced, half a row at a time (the chunks of the first
+// NT/2 threads, then the rest), so that the staging area is no larger than the
+// reduced-system area it aliases.  Element i of chunk t of a half sits in slot
+// i*(NT/2+PAD) + t, PAD = 2 for 16-byte and 4 for 8-byte elements, which spreads
+// both the chunk-wise and the coalesced accesses over all banks.  Otherwise every
+// thread reads and writes its own chunk directly.
 template <typename A, typename S, int CW, int NTB, bool STAGE>
 __global__ void __launch_bounds__(NTB)
 k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restrict__ sym,
@@ -46,19 +48,41 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
     const int a0 = t * CW;
     const int len = (t < P) ? min(CW, n - a0) : 0;
     constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
-    const int NTP = NT + PAD;
-    if (STAGE) {
-        for (int q = t; q < n; q += NT) stage[(q % CW) * NTP + q / CW] = row[q];
-        __syncthreads();
-    }
+    const int NH = NT / 2;                       // threads per staged half
+    const int NTP = NH + PAD;
+    const int H = NH * CW;                       // unknowns per staged half
+    const int mine = t / NH;                     // the half holding this thread's chunk
+    const int tl = t - mine * NH;
     cx<A> y[CW];
 #pragma unroll
-    for (int i = 0; i < CW; ++i) {
-        y[i] = {A(0), A(0)};
-        if (i < len) {
-            const cx<S> v = STAGE ? stage[i * NTP + t] : row[a0 + i];
-            y[i] = {A(v.x), A(v.y)};
+    for (int i = 0; i < CW; ++i) y[i] = {A(0), A(0)};
+    if (STAGE) {
+        for (int half = 0; half < 2; ++half) {
+            const int q0 = half * H;
+            const int q1 = min(n, q0 + H);
+            if (half == 1) __syncthreads();      // the first half has been read
+            for (int q = q0 + t; q < q1; q += NT) {
+                const int ql = q - q0;
+                stage[(ql % CW) * NTP + ql / CW] = row[q];
+            }
+            __syncthreads();
+            if (mine == half) {
+#pragma unroll
+                for (int i = 0; i < CW; ++i)
+                    if (i < len) {
+                        const cx<S> v = stage[i * NTP + tl];
+                        y[i] = {A(v.x), A(v.y)};
+                    }
+            }
         }
+        // partition_solve's first barrier precedes its first write to the area
+    } else {
+#pragma unroll
+        for (int i = 0; i < CW; ++i)
+            if (i < len) {
+                const cx<S> v = row[a0 + i];
+                y[i] = {A(v.x), A(v.y)};
+            }
     }
 
     // symbol of frequency j (tabulated per row and orientation)
@@ -67,13 +91,23 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
     const cx<A> e = {A(sj[2]), A(sj[3])};
 
     const cx<A> *rtab = ptab + ((size_t)j * 2 + (transpose ? 1 : 0)) * psolve_tab_entries(CW);
-    const bool bad = partition_solve<A, CW, true>(y, n, d, e, tab, red, rtab);
+    const bool bad = partition_solve<A, CW, kTabGlobal>(y, n, d, e, tab, red, rtab);
     if (STAGE) {
+        for (int half = 0; half < 2; ++half) {
+            const int q0 = half * H;
+            const int q1 = min(n, q0 + H);
+            if (half == 1) __syncthreads();      // the first half has been stored
+            if (mine == half) {
 #pragma unroll
-        for (int i = 0; i < CW; ++i)
-            if (i < len) stage[i * NTP + t] = {S(y[i].x), S(y[i].y)};
-        __syncthreads();
-        for (int q = t; q < n; q += NT) row[q] = stage[(q % CW) * NTP + q / CW];
+                for (int i = 0; i < CW; ++i)
+                    if (i < len) stage[i * NTP + tl] = {S(y[i].x), S(y[i].y)};
+            }
+            __syncthreads();
+            for (int q = q0 + t; q < q1; q += NT) {
+                const int ql = q - q0;
+                row[q] = stage[(ql % CW) * NTP + ql / CW];
+            }
+        }
     } else {
 #pragma unroll
         for (int i = 0; i < CW; ++i)
@@ -83,8 +117,8 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
 }
 
 // Launch configurations {chunk CW, threads NT}; configuration k < kNumSolveCfg
-// reads chunks directly, k + kNumSolveCfg stages the row through LDS.  A row of n
-// unknowns needs n <= CW * NT.
+// reads chunks directly, k + kNumSolveCfg stages the row through LDS half a row at
+// a time.  A row of n unknowns needs n <= CW * NT.
 static const int kSolveCfg[][2] = {{1, 256}, {2, 256}, {4, 256}, {8, 256}, {8, 512},
                                    {8, 1024}, {16, 128}, {16, 256}, {16, 512}, {16, 1024},
                                    {32, 128}, {32, 256}};
@@ -96,7 +130,7 @@ int solve_num_configs() { return 2 * kNumSolveCfg; }
 static size_t solve_lds_bytes(int cw, int nt, bool stage)
 {
     const size_t red = 16 * (size_t)psolve_lds_entries(cw, nt);
-    const size_t stg = 16 * ((size_t)psolve_tab_entries(cw) + (size_t)cw * (nt + 2));
+    const size_t stg = 16 * ((size_t)psolve_tab_entries(cw) + (size_t)cw * (nt / 2 + 2));
     return stage && stg > red ? stg : red;
 }
 
@@ -116,7 +150,7 @@ void solve_config_shape(int cfg, int *cw, int *nt, int *stage)
     *stage = cfg >= kNumSolveCfg;
 }
 
-// default: the staged configuration with the smallest chunk (then the fewest
+// default: the half-staged configuration with the smallest chunk (then the fewest
 // threads) that covers n with at most 512 threads; beyond that the widest
 // configuration that fits
 int solve_default_config(int n)
@@ -142,7 +176,8 @@ static hipError_t solve_go(void *spec, int lds, int n, int ell, const double *sy
     size_t smem = sizeof(cx<A>) * psolve_lds_entries(CW, NT);
     if (STAGE) {
         constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
-        const size_t stg = sizeof(cx<A>) * psolve_tab_entries(CW) + sizeof(cx<S>) * CW * (NT + PAD);
+        const size_t stg =
+            sizeof(cx<A>) * psolve_tab_entries(CW) + sizeof(cx<S>) * CW * (NT / 2 + PAD);
         if (stg > smem) smem = stg;
     }
     auto kern = k_shifted_solve<A, S, CW, NT, STAGE>;

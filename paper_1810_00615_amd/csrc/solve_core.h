@@ -38,6 +38,12 @@ __device__ __forceinline__ TriEq<A> reduce_eq(TriEq<A> m, TriEq<A> l, TriEq<A> r
 }
 
 template <typename A>
+__device__ __forceinline__ cx<A> csel(bool b, cx<A> x, cx<A> y)
+{
+    return {b ? x.x : y.x, b ? x.y : y.y};
+}
+
+template <typename A>
 __device__ __forceinline__ cx<A> shfl_cx(cx<A> v, int src)
 {
     return {__shfl(v.x, src, 64), __shfl(v.y, src, 64)};
@@ -115,8 +121,8 @@ __device__ __forceinline__ void build_tab(cx<A> d, cx<A> e, int mlast, P tab)
 // responses to the left / right separator.  The matrix being Toeplitz, the
 // elimination factors (1/pivot, e/pivot), the forward part of u and the end values
 // of u and v are the same for every full chunk: they form one table per row
-// (build_tab) in LDS, built by one thread or (GTAB) copied from a table precomputed
-// per row, and every thread regenerates u and v backwards from it, so a thread
+// (build_tab) in LDS, built by one thread or copied from a table precomputed per
+// row, and every thread regenerates u and v backwards from it, so a thread
 // keeps only y in registers.
 //
 // The separators satisfy a tridiagonal system with one equation per chunk.  Its
@@ -126,11 +132,16 @@ __device__ __forceinline__ void build_tab(cx<A> d, cx<A> e, int mlast, P tab)
 // eliminated unknowns are recovered level by level.  No pivoting, as in the
 // Thomas algorithm the method prescribes per block.
 //
-// tab: psolve_tab_entries(CW) entries of LDS (NT >= that count with GTAB); red: 6*NT entries
-// (may alias a staging area the caller has finished reading: the first barrier
-// below precedes every write to it, and the last barrier follows every read).
+// Where partition_solve finds the table: built by thread 0, copied from a table
+// precomputed per row in global memory, or already written to LDS by the caller.
+enum TabSource { kTabBuild = 0, kTabGlobal = 1, kTabReady = 2 };
+
+// tab: psolve_tab_entries(CW) entries of LDS (NT >= that count with kTabGlobal); red:
+// 6*NT entries (may alias a staging area the caller has finished reading: the first
+// barrier below precedes every write to it, and the last barrier follows every read).
+// With kTabReady the caller's writes to tab must precede the call's first barrier.
 // Every thread of the block must call it.  Returns true if a value is not finite.
-template <typename A, int CW, bool GTAB = false>
+template <typename A, int CW, int TABSRC = kTabBuild>
 __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *tab, cx<A> *red,
                                 const cx<A> *__restrict__ gtab = nullptr)
 {
@@ -139,10 +150,10 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
     const cx<A> zero = {A(0), A(0)};
     const int P = (n + CW - 1) / CW;                     // number of chunks / separators
     const int mlast = n - (P - 1) * CW - 1;              // interior length of the last chunk
-    if (GTAB) {
+    if (TABSRC == kTabGlobal) {
         // copy the precomputed table into LDS (read there as broadcasts)
         if (t < psolve_tab_entries(CW)) tab[t] = gtab[t];
-    } else if (t == 0) {
+    } else if (TABSRC == kTabBuild && t == 0) {
         build_tab<A, CW>(d, e, mlast, tab);
     }
     const cx<A> *s_ip = tab, *s_cp = tab + CW, *s_gu = tab + 2 * CW, *s_end = tab + 3 * CW;
@@ -239,19 +250,23 @@ __device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *
         Ps = Pn;
         ++levels;
     }
-    // one wave: parallel cyclic reduction of the remaining Ps <= 64 equations
+    // one wave: parallel cyclic reduction of the remaining Ps <= 64 equations.  Lanes
+    // t >= Ps hold zero equations and are never a neighbour of a live lane (a right
+    // neighbour t + sd >= Ps is replaced by zeros), so every lane updates
+    // unconditionally; the selects are per component, which keeps them in registers.
     if (t < 64) {
-        TriEq<A> m{zero, zero, zero};
-        if (t < Ps) m = {as[t], cs[t], ds[t]};
+        const bool live = t < Ps;
+        TriEq<A> m{csel(live, as[min(t, Ps - 1)], zero), csel(live, cs[min(t, Ps - 1)], zero),
+                   csel(live, ds[min(t, Ps - 1)], zero)};
         for (int sd = 1; sd < Ps; sd <<= 1) {
-            TriEq<A> l{shfl_cx(m.a, t - sd), shfl_cx(m.c, t - sd), shfl_cx(m.d, t - sd)};
-            TriEq<A> r{shfl_cx(m.a, t + sd), shfl_cx(m.c, t + sd), shfl_cx(m.d, t + sd)};
-            if (t - sd < 0) l = {zero, zero, zero};
-            if (t + sd >= Ps) r = {zero, zero, zero};
-            const TriEq<A> o = reduce_eq(m, l, r);
-            m = (t < Ps) ? o : m;
+            const bool hl = t - sd >= 0, hr = t + sd < Ps;
+            const TriEq<A> l{csel(hl, shfl_cx(m.a, t - sd), zero), csel(hl, shfl_cx(m.c, t - sd), zero),
+                             csel(hl, shfl_cx(m.d, t - sd), zero)};
+            const TriEq<A> r{csel(hr, shfl_cx(m.a, t + sd), zero), csel(hr, shfl_cx(m.c, t + sd), zero),
+                             csel(hr, shfl_cx(m.d, t + sd), zero)};
+            m = reduce_eq(m, l, r);
         }
-        if (t < Ps) ds[t] = m.d;                         // X at the deepest level
+        if (live) ds[t] = m.d;                           // X at the deepest level
     }
     __syncthreads();
     // back substitution, level by level: level s recovers its odd unknowns from
