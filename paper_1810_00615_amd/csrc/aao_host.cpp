@@ -132,8 +132,9 @@ static hipEvent_t ev_get(aao_ctx ctx)
         ctx->ev_pool.pop_back();
         return e;
     }
+    // timing-only events: no system-scope fence (cache writeback) when recorded
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

@@ -620,8 +620,9 @@ hipError_t launch_grad_kappa_parts(const double *U, const double *lam, int n, in
 namespace aao {
 
 // Fixed-order reduction of the partials of one Krylov step followed by its scalar
-// update, in one block (16 waves; wave w sums a fixed sixteenth of the partials of
-// every value, then thread 0 adds the 16 wave sums in order).  The basis
+// update, in one block (16 waves; every thread sums a fixed strided subset of the
+// partials of every value, each wave adds its threads' sums, then thread 0 adds the
+// 16 wave sums in order).  The basis
 // is stored unnormalised with scales vs (v_i = vs_i V_i), so that no host round
 // trip sits between the Gram-Schmidt passes; d are the reduced raw dot products.
 //   mode 0: h1_i = vs_i d_i, c_i = vs_i h1_i             (first projection, i < nv)
@@ -638,12 +639,21 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
     double sums[kMaxVecs];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int cnt = (a.mode <= 1) ? a.nv : 1;
-    // wave wv sums the partials [b0, b1) of every value
-    const int per = (nblk + 15) / 16;
-    const int b0 = wv * per, b1 = min(nblk, b0 + per);
+    // thread t sums the partials t, t + 1024, ... of every value, 16 loads in flight
+    // at a time; then each wave and finally thread 0 add in a fixed order
     for (int i = 0; i < cnt; ++i) {
+        const double *p = part + (size_t)i * ldp;
         double s = 0.0;
-        for (int b = b0 + lane; b < b1; b += 64) s += part[(size_t)i * ldp + b];
+        for (int base = 0; base < nblk; base += 16 * 1024) {
+            double v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int b = base + k * 1024 + (int)threadIdx.x;
+                v[k] = b < nblk ? p[b] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) s += v[k];
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
         if (lane == 0) wsum[wv][i] = s;
