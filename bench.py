@@ -39,6 +39,7 @@ KERNEL_SOURCES = {
     "cgs_update_dot": ["paper_1810_00615_amd/csrc/k_vec.hip"],
     "cgs_update_norm": ["paper_1810_00615_amd/csrc/k_vec.hip"],
     "axpy": ["paper_1810_00615_amd/csrc/k_vec.hip"],
+    "arnoldi_update": ["paper_1810_00615_amd/csrc/k_vec.hip"],
 }
 
 

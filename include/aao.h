@@ -200,7 +200,8 @@ enum {
     AAO_K_CGS_UPDATE_DOT = 5,   /* Gram-Schmidt: update + re-projections          */
     AAO_K_CGS_UPDATE_NORM = 6,  /* Gram-Schmidt: update + norm                    */
     AAO_K_AXPY = 7,             /* solution update x += Z y                       */
-    AAO_NUM_KERNELS = 8
+    AAO_K_ARNOLDI_UPDATE = 8,   /* Arnoldi update, delayed re-orthogonalisation   */
+    AAO_NUM_KERNELS = 9
 };
 aao_status aao_set_timing(aao_ctx ctx, int enable);
 aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count);

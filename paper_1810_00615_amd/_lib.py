@@ -116,4 +116,4 @@ def check(status, where, ctx=None):
 GMRES_ZERO_GUESS, GMRES_TRANSPOSE = 1, 2
 CONFIG_KINDS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec"]
 KERNELS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec", "cgs_dot", "cgs_update_dot",
-           "cgs_update_norm", "axpy"]
+           "cgs_update_norm", "axpy", "arnoldi_update"]

@@ -32,6 +32,7 @@ namespace {
 constexpr int kMaxRestart = 63;
 constexpr int kPartStride = 16384;   // partials per value (dot and fused-matvec blocks)
 constexpr int kSmallStride = 80;   // doubles per small-scalar array
+constexpr int kSmallArrays = 10;
 
 struct Status {
     aao_status st;
@@ -113,6 +114,9 @@ struct aao_ctx_s {
     double *svs() { return small + 4 * kSmallStride; }
     double *shcol() { return small + 5 * kSmallStride; }
     double *sy() { return small + 6 * kSmallStride; }
+    double *sa() { return small + 7 * kSmallStride; }    // re-orthogonalisation coefficients
+    double *scv() { return small + 8 * kSmallStride; }   // update-pass coefficients (v_j)
+    double *scw() { return small + 9 * kSmallStride; }   // update-pass coefficients (w1)
 };
 
 #define AAO_HIP(call)                                                                   \
@@ -506,8 +510,9 @@ static aao_status pinv_impl(aao_ctx ctx, const double *r, const double *in_scale
 // fused fixed-order reduction of ctx->part + Krylov scalar update (k_reduce_small)
 static aao_status launch_small(aao_ctx ctx, int mode, int nv, int nblk)
 {
-    const SmallArgs sa{mode, nv, ctx->sh1(), ctx->sh2(), ctx->sc_(), ctx->svs(), ctx->hdev,
-                       ctx->fail};
+    const SmallArgs sa{mode,       nv,        ctx->sh1(), ctx->sh2(), ctx->sc_(),
+                       ctx->svs(), ctx->hdev, ctx->fail,  ctx->sa(),  ctx->scv(),
+                       ctx->scw()};
     AAO_HIP(launch_reduce_small(ctx->part, nblk, ctx->ldp, sa, ctx->st));
     return AAO_OK;
 }
@@ -606,6 +611,9 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
         return inf.converged ? AAO_OK : AAO_NOT_CONVERGED;
     }
 
+    // Arnoldi: CGS2 with delayed re-orthogonalisation (two passes over the basis per
+    // step) unless AAO_CGS2_CLASSIC is set (three passes: project, re-project, update)
+    const bool delayed = std::getenv("AAO_CGS2_CLASSIC") == nullptr;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
     bool failed = false;
     while (inf.iters < maxit) {
@@ -625,20 +633,34 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (2 + nv),
                              launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc, ctx->kappa,
                                          ctx->tauk, transpose, st, mcfg, &Vl, nv, ctx->part, ldp));
-                AAO_TRY(small(0, nv, matvec_blocks(n, ell, mcfg)));
             } else {
                 AAO_TRY(apply_A_impl(ctx, Zj, ctx->W, nullptr, transpose));
                 AAO_LAUNCH_B(AAO_K_CGS_DOT, vec_bytes(ctx) * (nv + 1),
                              launch_multidot(Vl, nv, ctx->W, N, ctx->part, ldp, st));
-                AAO_TRY(small(0, nv, nb));
             }
-            // CGS2: re-project, form the new (unnormalised) basis vector and its norm
-            AAO_LAUNCH_B(AAO_K_CGS_UPDATE_DOT, vec_bytes(ctx) * (nv + 1),
-                         launch_update_dot(Vl, nv, ctx->W, ctx->sc_(), N, ctx->part, ldp, st));
-            AAO_TRY(small(1, nv, nb));
-            AAO_LAUNCH_B(AAO_K_CGS_UPDATE_NORM, vec_bytes(ctx) * (nv + 2), launch_update_norm(Vl, nv, ctx->W, ctx->sc_(), Vn,
-                                                                 N, ctx->part, ldp, st));
-            AAO_TRY(small(2, nv, nb));
+            if (delayed) {
+                // CGS2 with the re-orthogonalisation of v_j deferred to this step: one
+                // pass writes the final v_j and the once-projected w1 (the next pending
+                // vector) and forms the dots that re-orthogonalise w1 in the next step
+                AAO_TRY(small(5, nv, fused ? matvec_blocks(n, ell, mcfg) : nb));
+                AAO_LAUNCH_B(AAO_K_ARNOLDI_UPDATE, vec_bytes(ctx) * (nv + (j > 0 ? 3 : 2)),
+                             launch_arnoldi_update(Vl, nv, ctx->W, ctx->scv(), ctx->scw(),
+                                                   j > 0 ? ctx->V + N * j : nullptr, Vn, N,
+                                                   ctx->part,
+                                                   ldp, st));
+                AAO_TRY(small(6, nv, nb));
+            } else {
+                AAO_TRY(small(0, nv, fused ? matvec_blocks(n, ell, mcfg) : nb));
+                // CGS2: re-project, form the new (unnormalised) basis vector and its norm
+                AAO_LAUNCH_B(AAO_K_CGS_UPDATE_DOT, vec_bytes(ctx) * (nv + 1),
+                             launch_update_dot(Vl, nv, ctx->W, ctx->sc_(), N, ctx->part, ldp,
+                                               st));
+                AAO_TRY(small(1, nv, nb));
+                AAO_LAUNCH_B(AAO_K_CGS_UPDATE_NORM, vec_bytes(ctx) * (nv + 2),
+                             launch_update_norm(Vl, nv, ctx->W, ctx->sc_(), Vn, N, ctx->part,
+                                                ldp, st));
+                AAO_TRY(small(2, nv, nb));
+            }
             AAO_HIP(hipStreamSynchronize(st));
             if (first) {
                 AAO_TRY(check_b());
@@ -654,6 +676,19 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 g[0] = beta;
             }
             for (int i = 0; i <= nv; ++i) hcol[i] = hb[i];
+            if (delayed) {
+                // A z_j = sum_{i<=j} h_i v_i + beta p_{j+1}, and p_{j+1} = sum a_i v_i +
+                // alpha v_{j+1} with |p_{j+1}| = 1: the column of the fully
+                // re-orthogonalised basis
+                const double beta = hcol[nv];
+                double aa = 0.0;
+                for (int i = 0; i <= j; ++i) {
+                    const double ai = hb[kHostA + i];
+                    hcol[i] += beta * ai;
+                    aa += ai * ai;
+                }
+                hcol[nv] = beta * std::sqrt(std::max(1.0 - aa, 0.0));
+            }
             failed = failed || hb[kHostFail] != 0.0;
             inf.iters++;
             for (int i = 0; i <= nv; ++i)
@@ -766,7 +801,7 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
             break;
         }
         std::memset(ctx->hbuf, 0, sizeof(double) * kHostSlots);
-        if ((s = dev_alloc(ctx, (void **)&ctx->small, sizeof(double) * 7 * kSmallStride)) != AAO_OK)
+        if ((s = dev_alloc(ctx, (void **)&ctx->small, sizeof(double) * kSmallArrays * kSmallStride)) != AAO_OK)
             break;
         if ((s = dev_alloc(ctx, (void **)&ctx->tmpn, sizeof(double) * n)) != AAO_OK) break;
         if (!fft_supported_fast((int)ell) && ell >= 17 && ell <= 2048 && n <= 16384) {
@@ -803,7 +838,7 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
         }
         if (launch_twiddles(ctx->tw, (int)ell, (int)ell, nullptr) != hipSuccess ||
             hipMemset(ctx->fail, 0, sizeof(int)) != hipSuccess ||
-            hipMemset(ctx->small, 0, sizeof(double) * 7 * kSmallStride) != hipSuccess ||
+            hipMemset(ctx->small, 0, sizeof(double) * kSmallArrays * kSmallStride) != hipSuccess ||
             hipDeviceSynchronize() != hipSuccess) {
             s = AAO_ERR_HIP;
             break;

@@ -146,16 +146,26 @@ hipError_t launch_reduce_parts(const double *part, int nblk, int ldp, int cnt, d
 // x = (accumulate ? x : 0) + sum_i Z_i y_i
 hipError_t launch_multi_axpy(const VecList &Z, int nz, const CoefList &y, double *x, size_t N,
                              bool accumulate, hipStream_t st);
+// Arnoldi update with delayed re-orthogonalisation, step j (nv = j + 1 basis vectors
+// S_0..S_j, S_j the pending vector p):
+//   v_j = sum_i cv_i S_i  (written to vout unless vout is null),
+//   w1  = w - sum_i cw_i S_i  (written to wout),
+// and the partials of S_i . w1 (i < j), v_j . w1 (value j) and w1 . w1 (value nv).
+hipError_t launch_arnoldi_update(const VecList &S, int nv, const double *w, const double *cv,
+                                 const double *cw, double *vout, double *wout, size_t N,
+                                 double *part, int ldp, hipStream_t st);
 // Slots of the mapped host buffer written by k_reduce_small.
 constexpr int kHostBeta = kMaxVecs;       // residual norm
 constexpr int kHostBB = kMaxVecs + 1;     // b.b
 constexpr int kHostFail = kMaxVecs + 2;   // shifted-solve breakdown flag (0 / 1)
-constexpr int kHostSlots = kMaxVecs + 4;
+constexpr int kHostA = kMaxVecs + 4;      // re-orthogonalisation coefficients (kMaxVecs)
+constexpr int kHostSlots = 2 * kMaxVecs + 8;
 struct SmallArgs {
     int mode, nv;
     double *h1, *h2, *c, *vs;   // device scalars (kMaxVecs + 1 each)
     double *host;               // device view of the mapped host buffer
     const int *fail;
+    double *a, *cv, *cw;        // delayed re-orthogonalisation scalars (kMaxVecs + 1 each)
 };
 // Fused fixed-order reduction of one Krylov step's partials and its scalar update
 // (modes documented at the kernel).

@@ -144,6 +144,85 @@ hipError_t launch_update_norm(const VecList &V, int nv, const double *w, const d
     return cgs_disp<2>(V, nv, w, h, N, part, ldp, out, st);
 }
 
+// ------------------------------------ Arnoldi update, delayed re-orthogonalisation
+// One pass over the basis of step j (S_0..S_j, S_j the pending vector p_j whose
+// re-orthogonalisation was deferred to this step) and w = A z_j: forms the final
+// v_j = sum_i cv_i S_i and the once-projected w1 = w - sum_i cw_i S_i, and the
+// partials of S_i . w1 (i < j), v_j . w1 (value j) and w1 . w1 (value nv), from
+// which the next step takes its re-orthogonalisation coefficients and w1's norm.
+// vout may be S_j itself (each element is read before it is written, by the same
+// thread); vout == nullptr when v_j = S_j needs no rewrite (j = 0).
+template <int NV>
+__global__ void __launch_bounds__(kRedThreads)
+k_arnoldi_update(VecList S, int nv, const double *__restrict__ w, const double *__restrict__ cv,
+                 const double *__restrict__ cw, double *vout, double *__restrict__ wout,
+                 size_t N, double *__restrict__ part, int ldp)
+{
+    __shared__ double red[(NV + 1) * 16];
+    double acc[NV + 1];
+    double fv[NV], fw[NV];
+    const int j = nv - 1;
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        fv[i] = i < nv ? cv[i] : 0.0;
+        fw[i] = i < nv ? cw[i] : 0.0;
+    }
+    double nrm = 0.0;
+    constexpr int U = NV <= 4 ? 4 : (NV <= 8 ? 2 : 1);
+    const Walk g = grid_walk(N);
+    for (size_t e0 = g.first; e0 < g.end; e0 += (size_t)U * g.stride) {
+        double we[U];
+        double vv[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t e = e0 + (size_t)u * g.stride;
+            const bool in = e < g.end;
+            we[u] = in ? w[e] : 0.0;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) vv[u][i] = (in && i < nv) ? S.p[i][e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t e = e0 + (size_t)u * g.stride;
+            double vj = 0.0, s = we[u];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                vj += fv[i] * vv[u][i];
+                s -= fw[i] * vv[u][i];
+            }
+            if (e < g.end) {
+                if (vout) vout[e] = vj;
+                wout[e] = s;
+            }
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] += (i == j ? vj : vv[u][i]) * s;
+            nrm += s * s;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i <= NV; ++i)
+        if (i == nv) acc[i] = nrm;
+    block_reduce_store<NV + 1>(acc, nv + 1, part, ldp, red);
+}
+
+hipError_t launch_arnoldi_update(const VecList &S, int nv, const double *w, const double *cv,
+                                 const double *cw, double *vout, double *wout, size_t N,
+                                 double *part, int ldp, hipStream_t st)
+{
+    const int nb = dot_blocks(N);
+#define AAO_NV(K)                                                                          \
+    if (nv <= K) {                                                                         \
+        k_arnoldi_update<K><<<nb, kRedThreads, 0, st>>>(S, nv, w, cv, cw, vout, wout, N,   \
+                                                          part, ldp);                      \
+        return hipGetLastError();                                                          \
+    }
+    AAO_NV(1) AAO_NV(2) AAO_NV(3) AAO_NV(4) AAO_NV(8) AAO_NV(16) AAO_NV(32) AAO_NV(63)
+#undef AAO_NV
+    return hipErrorInvalidValue;
+}
+
 // Fixed-order sum of the per-block partials: sums[i] = sum_b part[i*ldp + b].
 __global__ void __launch_bounds__(256)
 k_reduce_parts(const double *__restrict__ part, int nblk, int ldp, double *__restrict__ sums)
@@ -631,6 +710,10 @@ namespace aao {
 //   mode 3: nrm = sqrt(d_0), vs_0 = 1/nrm, host[kHostBeta] = nrm    (restart vector)
 //   mode 4: host[kHostBB] = d_0 (= b.b); with nv == 1 also vs_0 = 1/sqrt(d_0)
 //           and host[kHostBeta] = sqrt(d_0)       (zero initial guess: V_0 = b)
+//   mode 5: delayed re-orthogonalisation after the matvec of step j = nv - 1:
+//           coefficients cv, cw of the update pass, host[0..j] = first projections
+//   mode 6: after the update pass: vs_nv = 1/|w1|, a_i (next step's coefficients),
+//           host[nv] = |w1|, host[kHostA + i] = a_i
 // host: mapped pinned memory; host[kHostFail] receives the breakdown flag.
 __global__ void __launch_bounds__(1024)
 k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
@@ -638,7 +721,7 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
     __shared__ double wsum[16][kMaxVecs];
     double sums[kMaxVecs];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int cnt = (a.mode <= 1) ? a.nv : 1;
+    const int cnt = (a.mode <= 1 || a.mode == 5) ? a.nv : (a.mode == 6 ? a.nv + 1 : 1);
     // thread t sums the partials t, t + 1024, ... of every value, 16 loads in flight
     // at a time; then each wave and finally thread 0 add in a fixed order
     for (int i = 0; i < cnt; ++i) {
@@ -666,7 +749,44 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
         sums[i] = s;
     }
     const int nv = a.nv;
-    if (a.mode == 0) {
+    if (a.mode == 5) {
+        // delayed re-orthogonalisation, after w = A z_j (sums: S_i . w, i <= j):
+        // p_j = sum_{i<j} a_i v_i + alpha v_j with |p_j| = 1, so
+        //   alpha = sqrt(1 - |a|^2),  v_j = (p_j - sum a_i v_i) / alpha,
+        //   h_i = v_i . w = b_i (i < j),  h_j = v_j . w = (p_j . w - a . b) / alpha,
+        //   w1 = w - sum_{i<j} h_i v_i - h_j v_j.
+        const int j = nv - 1;
+        double aa = 0.0, ab = 0.0;
+        for (int i = 0; i < j; ++i) {
+            const double bi = a.vs[i] * sums[i];
+            aa += a.a[i] * a.a[i];
+            ab += a.a[i] * bi;
+        }
+        const double alpha = j > 0 ? sqrt(fmax(1.0 - aa, 1e-300)) : 1.0;
+        const double hj = (a.vs[j] * sums[j] - ab) / alpha;
+        for (int i = 0; i < j; ++i) {
+            const double bi = a.vs[i] * sums[i];
+            a.cv[i] = -a.a[i] * a.vs[i] / alpha;
+            a.cw[i] = (bi - a.a[i] * hj / alpha) * a.vs[i];
+            a.host[i] = bi;
+        }
+        a.cv[j] = a.vs[j] / alpha;
+        a.cw[j] = hj / alpha * a.vs[j];
+        a.host[j] = hj;
+        if (j > 0) a.vs[j] = 1.0;   // S_j is rewritten as the unit vector v_j
+    } else if (a.mode == 6) {
+        // after the update (sums: S_i . w1 for i < j, v_j . w1, w1 . w1):
+        // beta = |w1|, p_{j+1} = w1 / beta, a_i = v_i . p_{j+1} (i <= j)
+        const int j = nv - 1;
+        const double beta = sqrt(fmax(sums[nv], 0.0));
+        const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+        a.vs[nv] = inv;
+        for (int i = 0; i <= j; ++i) {
+            a.a[i] = (i < j ? a.vs[i] : 1.0) * sums[i] * inv;
+            a.host[kHostA + i] = a.a[i];
+        }
+        a.host[nv] = beta;
+    } else if (a.mode == 0) {
         for (int i = 0; i < nv; ++i) {
             a.h1[i] = a.vs[i] * sums[i];
             a.c[i] = a.vs[i] * a.h1[i];

@@ -33,6 +33,7 @@ FAMILIES = [
     ("cgs", r"k_cgs|k_batch_cgs"),
     ("reduce", r"k_reduce_small|k_reduce_parts|k_batch_reduce|k_batch_small"),
     ("axpy", r"k_multi_axpy|k_batch_axpy"),
+    ("arnoldi_update", r"k_arnoldi_update"),
     ("dot", r"k_dot1"),
     ("copy", r"copyBuffer|elementwise_kernel.*copy|direct_copy"),
 ]

@@ -221,6 +221,43 @@ def test_gmres_bd2_small(aao, orc, torch_dev, prec):
     assert normrel(U.cpu().numpy(), Ur) < 1e-4
 
 
+@pytest.mark.parametrize("scheme,restart", [(HEAT, 50), (BD2, 8), (BD2, 60)])
+def test_arnoldi_delayed_matches_classic(aao, orc, torch_dev, scheme, restart, monkeypatch):
+    """The Arnoldi process with the re-orthogonalisation deferred to the next step
+    (default) against the three-pass CGS2 (AAO_CGS2_CLASSIC): both reach the
+    requested true residual, their iteration counts differ by at most 2, and their
+    solutions agree to the accuracy the tolerance allows.  Restart 60 with BD2 runs
+    bases past 32 vectors; restart 8 exercises several restarts."""
+    n, ell = 127, 256
+    tau = 1.0 / ell
+    from paper_1810_00615_amd.inputs import sine_amps
+    m, a = sine_amps([5, 0], 30)
+    mv, av = sine_amps([5, 1], 30)
+    name = "heat" if scheme == HEAT else "bd2"
+    P = aao.Problem(n, ell, tau, name, device=torch_dev[1])
+    u0 = P.project_sine(m, a)
+    b = P.rhs(u0, P.project_sine(mv, av) if scheme == BD2 else None)
+    tol = 1e-10
+    out = {}
+    for variant in ("delayed", "classic"):
+        if variant == "classic":
+            monkeypatch.setenv("AAO_CGS2_CLASSIC", "1")
+        else:
+            monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
+        U, info = P.solve(b, restart=restart, tol=tol, maxit=600)
+        assert info["converged"], (variant, info)
+        Un = U.cpu().numpy()
+        br = b.cpu().numpy()
+        r = br - orc.apply_A(scheme, n, ell, tau, 1.0, Un)
+        assert np.linalg.norm(r) / np.linalg.norm(br) <= 1.0001 * tol, variant
+        out[variant] = (Un, info["iters"])
+    monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
+    (Ud, itd), (Uc, itc) = out["delayed"], out["classic"]
+    print(f"{name} restart {restart}: iterations delayed {itd}, classic {itc}")
+    assert abs(itd - itc) <= 2
+    assert normrel(Ud, Uc) < 1e-6
+
+
 def test_gmres_errors_and_edges(aao, torch_dev):
     import torch
     P = aao.Problem(15, 16, scheme="heat", device=torch_dev[1])
