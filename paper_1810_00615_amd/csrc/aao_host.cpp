@@ -542,14 +542,19 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     double *V0 = ctx->V;
     const int mcfg = ctx->cf(AAO_CFG_MATVEC);
     const bool fused = matvec_blocks(n, ell, mcfg) <= ldp;
-    auto residual = [&]() -> aao_status {
-        // V_0 = b - A x, vs_0 = 1/||V_0|| (the norm formed by the same launch)
+    auto residual = [&](bool store) -> aao_status {
+        // V_0 = b - A x, vs_0 = 1/||V_0|| (the norm formed by the same launch); with
+        // store false only the norm (the check after a cycle, before a restart is
+        // known to be needed)
         if (fused) {
+            // a one-entry list equal to the output selects the self-norm (|b - A x|^2)
+            double *out = store ? V0 : nullptr;
             VecList self{};
-            self.p[0] = V0;
-            AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * 3,
-                         launch_matvec(x, V0, b, n, ell, ctx->sc, ctx->kappa, ctx->tauk,
-                                       transpose, st, mcfg, &self, 1, ctx->part, ldp));
+            self.p[0] = out;
+            AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (store ? 3 : 2),
+                         launch_matvec(x, out, b, n, ell, ctx->sc, ctx->kappa,
+                                       ctx->tauk, transpose, st, mcfg, &self, 1, ctx->part,
+                                       ldp));
             return small(3, 0, matvec_blocks(n, ell, mcfg));
         }
         AAO_TRY(apply_A_impl(ctx, x, V0, b, transpose));
@@ -576,7 +581,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     if (!defer_b) {
         AAO_HIP(launch_dot1_parts(b, b, N, ctx->part, st));
         AAO_TRY(small(4, zero_guess ? 1 : 0, nb));
-        if (!zero_guess) AAO_TRY(residual());
+        if (!zero_guess) AAO_TRY(residual(true));
         AAO_HIP(hipStreamSynchronize(st));
         AAO_TRY(check_b());
         beta = hb[kHostBeta];
@@ -731,7 +736,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                      launch_multi_axpy(Zl, k, yc, x, N, !x_zero, st));
         x_zero = false;
         Vl.p[0] = V0;
-        AAO_TRY(residual());
+        AAO_TRY(residual(false));
         AAO_HIP(hipStreamSynchronize(st));
         beta = hb[kHostBeta];
         failed = failed || hb[kHostFail] != 0.0;
@@ -744,6 +749,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             inf.converged = 1;
             break;
         }
+        if (inf.iters >= maxit) break;
+        AAO_TRY(residual(true));   // the restart vector (same launch, now stored)
         inf.restarts++;
     }
     if (info) *info = inf;

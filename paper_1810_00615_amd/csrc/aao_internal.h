@@ -103,7 +103,9 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
                                 double *part, double *Uout, int *fail, hipStream_t st);
 
 // y = A x (or A^T x); with tau_k != nullptr the variable-step matrix B.
-// If bsub != nullptr computes y = bsub - A x.
+// If bsub != nullptr computes y = bsub - A x.  With nv > 0 the launch also writes the
+// block partials of V_q . y (q < nv); nv == 1 with V->p[0] == y selects the partials
+// of y . y instead.  y may be null (nothing stored; only with the self-norm).
 struct VecList;
 hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
                          Scheme sc, double kappa, const double *tau_k, int transpose,

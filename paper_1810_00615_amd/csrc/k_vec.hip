@@ -453,7 +453,7 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
         const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
         const double out = bsub ? (col ? bsub[(size_t)k * n + i] : 0.0) - v : v;
         yv[it - S] = out;
-        if (col) y[(size_t)k * n + i] = out;
+        if (col && y) y[(size_t)k * n + i] = out;
     }
     if (DOTS == 0) return;
     __shared__ double red[kMaxVecs * 4];
