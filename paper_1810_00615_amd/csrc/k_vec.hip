@@ -248,26 +248,35 @@ hipError_t launch_reduce_parts(const double *part, int nblk, int ldp, int cnt, d
 }
 
 // ------------------------------------------------------- small vector ops
-__global__ void k_multi_axpy(VecList Z, int nz, CoefList y, double *__restrict__ x, size_t N,
-                             int accumulate)
+// x = (accumulate ? x : 0) + sum_i Z_i y_i; NZ >= nz, all loads of an iteration
+// issued before the sums
+template <int NZ>
+__global__ void __launch_bounds__(kRedThreads)
+k_multi_axpy(VecList Z, int nz, CoefList y, double *__restrict__ x, size_t N, int accumulate)
 {
-    constexpr int U = 4;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t e0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e0 < N; e0 += U * stride) {
+    constexpr int U = NZ <= 2 ? 4 : (NZ <= 8 ? 2 : 1);
+    double yc[NZ];
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) yc[i] = i < nz ? y.v[i] : 0.0;
+    const Walk g = grid_walk(N);
+    for (size_t e0 = g.first; e0 < g.end; e0 += (size_t)U * g.stride) {
         double s[U];
+        double zz[U][NZ];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            s[u] = (accumulate && e0 + u * stride < N) ? x[e0 + u * stride] : 0.0;
-        for (int i = 0; i < nz; ++i) {
-            const double yi = y.v[i];
-            const double *zi = Z.p[i];
+        for (int u = 0; u < U; ++u) {
+            const size_t e = e0 + (size_t)u * g.stride;
+            const bool in = e < g.end;
+            s[u] = (accumulate && in) ? x[e] : 0.0;
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (e0 + u * stride < N) s[u] += zi[e0 + u * stride] * yi;
+            for (int i = 0; i < NZ; ++i) zz[u][i] = (in && i < nz) ? Z.p[i][e] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (e0 + u * stride < N) x[e0 + u * stride] = s[u];
+        for (int u = 0; u < U; ++u) {
+            const size_t e = e0 + (size_t)u * g.stride;
+#pragma unroll
+            for (int i = 0; i < NZ; ++i) s[u] += zz[u][i] * yc[i];
+            if (e < g.end) x[e] = s[u];
+        }
     }
 }
 
@@ -280,8 +289,15 @@ static int grid_for(size_t N)
 hipError_t launch_multi_axpy(const VecList &Z, int nz, const CoefList &y, double *x, size_t N,
                              bool accumulate, hipStream_t st)
 {
-    k_multi_axpy<<<grid_for(N), 256, 0, st>>>(Z, nz, y, x, N, accumulate ? 1 : 0);
-    return hipGetLastError();
+    const int nb = dot_blocks(N);
+#define AAO_NZ(K)                                                                          \
+    if (nz <= K) {                                                                         \
+        k_multi_axpy<K><<<nb, kRedThreads, 0, st>>>(Z, nz, y, x, N, accumulate ? 1 : 0);   \
+        return hipGetLastError();                                                          \
+    }
+    AAO_NZ(1) AAO_NZ(2) AAO_NZ(3) AAO_NZ(4) AAO_NZ(8) AAO_NZ(16) AAO_NZ(32) AAO_NZ(64)
+#undef AAO_NZ
+    return hipErrorInvalidValue;
 }
 
 __global__ void k_scale(const double *__restrict__ w, const double *__restrict__ sc, double a,
