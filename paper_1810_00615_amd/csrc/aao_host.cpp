@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -101,6 +103,7 @@ struct aao_ctx_s {
     double t_total[AAO_NUM_KERNELS] = {};
     long long t_count[AAO_NUM_KERNELS] = {};
     double t_bytes[AAO_NUM_KERNELS] = {};
+    double seq = 0.0;   // sequence number of the last k_reduce_small launch
 
     // launch shapes per precision mode (aao_set_config / aao_tune); -1 = default
     int cfg[3][AAO_NUM_CFG] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
@@ -510,10 +513,29 @@ static aao_status pinv_impl(aao_ctx ctx, const double *r, const double *in_scale
 // fused fixed-order reduction of ctx->part + Krylov scalar update (k_reduce_small)
 static aao_status launch_small(aao_ctx ctx, int mode, int nv, int nblk)
 {
+    ctx->seq += 1.0;
     const SmallArgs sa{mode,       nv,        ctx->sh1(), ctx->sh2(), ctx->sc_(),
                        ctx->svs(), ctx->hdev, ctx->fail,  ctx->sa(),  ctx->scv(),
-                       ctx->scw()};
+                       ctx->scw(), ctx->seq};
     AAO_HIP(launch_reduce_small(ctx->part, nblk, ctx->ldp, sa, ctx->st));
+    return AAO_OK;
+}
+
+// Wait until the last launch_small's results are in the host buffer: poll its
+// sequence number (it is written after every other result, behind a system-scope
+// fence) for up to about a millisecond, then fall back to synchronising the stream
+// (long steps, and the path that reports launch failures).
+static aao_status wait_small(aao_ctx ctx)
+{
+    volatile double *hb = ctx->hbuf;
+    const auto t0 = std::chrono::steady_clock::now();
+    while (hb[kHostSeq] != ctx->seq) {
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(1000)) {
+            AAO_HIP(hipStreamSynchronize(ctx->st));
+            break;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     return AAO_OK;
 }
 
@@ -666,7 +688,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                                                 ldp, st));
                 AAO_TRY(small(2, nv, nb));
             }
-            AAO_HIP(hipStreamSynchronize(st));
+            AAO_TRY(wait_small(ctx));
             if (first) {
                 AAO_TRY(check_b());
                 if (bnorm == 0.0) {
@@ -737,7 +759,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
         x_zero = false;
         Vl.p[0] = V0;
         AAO_TRY(residual(false));
-        AAO_HIP(hipStreamSynchronize(st));
+        AAO_TRY(wait_small(ctx));
         beta = hb[kHostBeta];
         failed = failed || hb[kHostFail] != 0.0;
         inf.rel_resid_true = beta / bnorm;

@@ -160,6 +160,7 @@ hipError_t launch_arnoldi_update(const VecList &S, int nv, const double *w, cons
 constexpr int kHostBeta = kMaxVecs;       // residual norm
 constexpr int kHostBB = kMaxVecs + 1;     // b.b
 constexpr int kHostFail = kMaxVecs + 2;   // shifted-solve breakdown flag (0 / 1)
+constexpr int kHostSeq = kMaxVecs + 3;    // sequence number of the last reduction
 constexpr int kHostA = kMaxVecs + 4;      // re-orthogonalisation coefficients (kMaxVecs)
 constexpr int kHostSlots = 2 * kMaxVecs + 8;
 struct SmallArgs {
@@ -168,6 +169,7 @@ struct SmallArgs {
     double *host;               // device view of the mapped host buffer
     const int *fail;
     double *a, *cv, *cw;        // delayed re-orthogonalisation scalars (kMaxVecs + 1 each)
+    double seq;                 // written to host[kHostSeq] after every other result
 };
 // Fused fixed-order reduction of one Krylov step's partials and its scalar update
 // (modes documented at the kernel).

@@ -730,7 +730,8 @@ namespace aao {
 //           coefficients cv, cw of the update pass, host[0..j] = first projections
 //   mode 6: after the update pass: vs_nv = 1/|w1|, a_i (next step's coefficients),
 //           host[nv] = |w1|, host[kHostA + i] = a_i
-// host: mapped pinned memory; host[kHostFail] receives the breakdown flag.
+// host: mapped pinned memory; host[kHostFail] receives the breakdown flag, and
+// host[kHostSeq] the launch's sequence number once everything else is visible.
 __global__ void __launch_bounds__(1024)
 k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
 {
@@ -832,6 +833,9 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
         }
     }
     a.host[kHostFail] = (a.fail && *a.fail) ? 1.0 : 0.0;
+    // the host may poll the sequence number instead of synchronising the stream
+    __threadfence_system();
+    a.host[kHostSeq] = a.seq;
 }
 
 hipError_t launch_reduce_small(const double *part, int nblk, int ldp, const SmallArgs &a,
