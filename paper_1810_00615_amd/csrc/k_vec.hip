@@ -736,27 +736,36 @@ __global__ void __launch_bounds__(1024)
 k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
 {
     __shared__ double wsum[16][kMaxVecs];
-    double sums[kMaxVecs];
+    __shared__ double sums[kMaxVecs + 1];   // final sums (LDS: indexed at run time)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int cnt = (a.mode <= 1 || a.mode == 5) ? a.nv : (a.mode == 6 ? a.nv + 1 : 1);
-    // thread t sums the partials t, t + 1024, ... of every value, 16 loads in flight
-    // at a time; then each wave and finally thread 0 add in a fixed order
-    for (int i = 0; i < cnt; ++i) {
-        const double *p = part + (size_t)i * ldp;
-        double s = 0.0;
+    // thread t sums the partials t, t + 1024, ... of every value, the loads of two
+    // values (32 per thread) in flight at a time; then each wave and finally thread 0
+    // add in a fixed order
+    for (int i0 = 0; i0 < cnt; i0 += 2) {
+        double s[2] = {0.0, 0.0};
         for (int base = 0; base < nblk; base += 16 * 1024) {
-            double v[16];
+            double v[2][16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int b = base + k * 1024 + (int)threadIdx.x;
-                v[k] = b < nblk ? p[b] : 0.0;
+            for (int q = 0; q < 2; ++q) {
+                const double *p = part + (size_t)min(i0 + q, cnt - 1) * ldp;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int b = base + k * 1024 + (int)threadIdx.x;
+                    v[q][k] = (i0 + q < cnt && b < nblk) ? p[b] : 0.0;
+                }
             }
 #pragma unroll
-            for (int k = 0; k < 16; ++k) s += v[k];
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) s[q] += v[q][k];
         }
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) wsum[wv][i] = s;
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_down(s[q], off, 64);
+            if (lane == 0 && i0 + q < cnt) wsum[wv][i0 + q] = s[q];
+        }
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
