@@ -361,7 +361,7 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             max_ell = std::max(max_ell, q.ell);
             max_M = std::max(max_M, M);
             b->hp.push_back(q);
-            const int Wp = 1024 * 8 / M;                       // column pairs per transform tile
+            const int Wp = bluestein_pairs(M);                 // column pairs per transform tile
             const int ntile = (q.n + 2 * Wp - 1) / (2 * Wp);
             for (int t = 0; t < ntile; ++t) ft.push_back({p, t});
             for (int j = 0; j <= q.ell / 2; ++j) rw.push_back({p, j});

@@ -845,7 +845,7 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
             q.tau = tau;
             q.kappa = 1.0;
             std::vector<int2> tiles;
-            const int Wp = 1024 * 8 / M;
+            const int Wp = bluestein_pairs(M);
             for (int t = 0; t < (q.n + 2 * Wp - 1) / (2 * Wp); ++t) tiles.push_back({0, t});
             ctx->bl_ntiles = (int)tiles.size();
             if ((s = dev_alloc(ctx, (void **)&ctx->bl_prob, sizeof(BProb))) != AAO_OK) break;

@@ -39,6 +39,10 @@ struct BatchLaunch {
 };
 
 constexpr int kBatchSlab = 65536;       // elements per Gram-Schmidt / update slab
+// Bluestein transforms: points per thread of the length-M FFTs; a 1024-thread
+// workgroup transforms 1024 P / M column pairs
+constexpr int kBluesteinP = 8;   // (16 spills registers in the two-transform tiles)
+constexpr int bluestein_pairs(int M) { return 1024 * kBluesteinP / M; }
 
 hipError_t batch_prepare();
 hipError_t batch_setup_tables(const BProb *probs, int count, int max_ell, int max_M,

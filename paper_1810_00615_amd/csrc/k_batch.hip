@@ -59,7 +59,7 @@ __device__ void bl_fwd_tile(const BProb &pb, int tile, const double *__restrict_
                             const cx<double> *__restrict__ bhat,
                             const cx<double> *__restrict__ twM, T *sm)
 {
-    constexpr int P = 8;                              // points per thread (register budget)
+    constexpr int P = kBluesteinP;                    // points per thread
     constexpr int TN = M / P;
     constexpr int W = 1024 / TN;                      // column pairs per tile
     const int c = threadIdx.x % W;
@@ -130,7 +130,7 @@ __device__ void bl_inv_tile(const BProb &pb, int tile, const cx<T> *__restrict__
                             const cx<double> *__restrict__ bhat,
                             const cx<double> *__restrict__ twM, T *sm)
 {
-    constexpr int P = 8;
+    constexpr int P = kBluesteinP;
     constexpr int TN = M / P;
     constexpr int W = 1024 / TN;
     const int c = threadIdx.x % W;
@@ -617,10 +617,9 @@ hipError_t batch_setup_tables(const BProb *probs, int count, int max_ell, int ma
 static size_t bl_smem(size_t realsz)
 {
     // largest tile plane over M in {512..4096}: lds_rows(M) * W reals, W = 1024 P / M
-    const int P = 8;
     size_t best = 0;
     for (int M = 512; M <= 4096; M *= 2) {
-        const size_t s = (size_t)lds_rows(M) * (1024 * P / M) * realsz;
+        const size_t s = (size_t)lds_rows(M) * bluestein_pairs(M) * realsz;
         if (s > best) best = s;
     }
     return best;
