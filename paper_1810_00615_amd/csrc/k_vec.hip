@@ -427,6 +427,24 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
         c[it] = (in && col) ? row[i] : 0.0;
         e[it] = (in && edge) ? row[je] : 0.0;
     }
+    // the rows of bsub and of the first two basis vectors are loaded with x, so that
+    // their latency overlaps the x loads instead of following the stencil
+    double bs[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int k = transpose ? (k1 - 1 - r) : (k0 + r);
+        bs[r] = (bsub && col && r < nin - S) ? bsub[(size_t)k * n + i] : 0.0;
+    }
+    constexpr int G = 2;
+    double vq0[G][R];
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = transpose ? (k1 - 1 - r) : (k0 + r);
+            vq0[u][r] = (DOTS == 1 && u < nv && col && r < nin - S) ? V.p[u][(size_t)k * n + i]
+                                                                     : 0.0;
+        }
     // l, c, r of the last S+1 input rows; the time combination is formed before
     // the space stencil, so that cancelling time differences (BD2: x_k - 2 x_{k-1}
     // + x_{k-2}) are taken on the raw values
@@ -467,7 +485,7 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
             br += bm * wr[m];
         }
         const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
-        const double out = bsub ? (col ? bsub[(size_t)k * n + i] : 0.0) - v : v;
+        const double out = bsub ? bs[it - S] - v : v;
         yv[it - S] = out;
         if (col && y) y[(size_t)k * n + i] = out;
     }
@@ -487,8 +505,8 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
         return;
     }
     // partial dot products V_q . y over this block's tile (first Gram-Schmidt pass)
-    // two basis vectors at a time, all their loads issued before the sums
-    constexpr int G = 2;
+    // two basis vectors at a time, all their loads issued before the sums (the first
+    // two with x)
     for (int q0 = 0; q0 < nv; q0 += G) {
         double acc[G];
         double vq[G][R];
@@ -498,8 +516,10 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int k = transpose ? (k1 - 1 - r) : (k0 + r);
-                vq[u][r] = (q0 + u < nv && col && r < nin - S) ? V.p[q0 + u][(size_t)k * n + i]
-                                                                : 0.0;
+                vq[u][r] = q0 == 0 ? vq0[u][r]
+                                   : (q0 + u < nv && col && r < nin - S)
+                                         ? V.p[q0 + u][(size_t)k * n + i]
+                                         : 0.0;
             }
         }
 #pragma unroll
