@@ -57,13 +57,27 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
 #pragma unroll
     for (int i = 0; i < CW; ++i) y[i] = {A(0), A(0)};
     if (STAGE) {
+        // H / NT = CW / 2 elements per thread and half, loaded together (unconditional
+        // at a clamped index; a guarded load per element would be waited for in turn)
+        constexpr int KH = CW >= 2 ? CW / 2 : 1;
         for (int half = 0; half < 2; ++half) {
             const int q0 = half * H;
             const int q1 = min(n, q0 + H);
+            S lx[KH], ly[KH];   // separate parts: a whole-struct array would live in scratch
+#pragma unroll
+            for (int k = 0; k < KH; ++k) {
+                const cx<S> v = row[min(q0 + t + k * NT, n - 1)];
+                lx[k] = v.x;
+                ly[k] = v.y;
+            }
             if (half == 1) __syncthreads();      // the first half has been read
-            for (int q = q0 + t; q < q1; q += NT) {
-                const int ql = q - q0;
-                stage[(ql % CW) * NTP + ql / CW] = row[q];
+#pragma unroll
+            for (int k = 0; k < KH; ++k) {
+                const int q = q0 + t + k * NT;
+                if (q < q1) {
+                    const int ql = q - q0;
+                    stage[(ql % CW) * NTP + ql / CW] = {lx[k], ly[k]};
+                }
             }
             __syncthreads();
             if (mine == half) {
@@ -78,11 +92,10 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
         // partition_solve's first barrier precedes its first write to the area
     } else {
 #pragma unroll
-        for (int i = 0; i < CW; ++i)
-            if (i < len) {
-                const cx<S> v = row[a0 + i];
-                y[i] = {A(v.x), A(v.y)};
-            }
+        for (int i = 0; i < CW; ++i) {
+            const cx<S> v = row[min(a0 + i, n - 1)];   // unconditional: all in flight
+            if (i < len) y[i] = {A(v.x), A(v.y)};
+        }
     }
 
     // symbol of frequency j (tabulated per row and orientation)
