@@ -268,7 +268,22 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
     const int NTP = NT + PAD;
     const int P = (n + CW - 1) / CW;
     const int len = (t < P) ? min(CW, n - t * CW) : 0;
-    for (int q = t; q < n; q += NT) stage[(q % CW) * NTP + q / CW] = row[q];
+    {
+        // CW elements per thread (n <= CW NT), loaded together: unconditional at a
+        // clamped index, parts kept apart (a whole-struct array would live in scratch)
+        S lx[CW], ly[CW];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            const cx<S> v = row[min(t + k * NT, n - 1)];
+            lx[k] = v.x;
+            ly[k] = v.y;
+        }
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            const int q = t + k * NT;
+            if (q < n) stage[(q % CW) * NTP + q / CW] = {lx[k], ly[k]};
+        }
+    }
     __syncthreads();
     cx<A> y[CW];
 #pragma unroll
