@@ -754,11 +754,26 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             y[i] = s / H[(size_t)i * m + i];
             yc.v[i] = y[i];
         }
-        AAO_LAUNCH_B(AAO_K_AXPY, vec_bytes(ctx) * (k + (x_zero ? 1 : 2)),
-                     launch_multi_axpy(Zl, k, yc, x, N, !x_zero, st));
+        if (x_zero && fused && matvec_comb_ok(mcfg, k)) {
+            // x = Z y formed inside the residual-check launch (x is not read, so no
+            // block reads rows another one writes): one pass over Z, b and x
+            MatvecComb cb{};
+            for (int i = 0; i < k; ++i) {
+                cb.z[i] = Zl.p[i];
+                cb.c[i] = yc.v[i];
+            }
+            cb.xout = x;
+            AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (k + 2),
+                         launch_matvec_comb(cb, k, b, n, ell, ctx->sc, ctx->kappa, ctx->tauk,
+                                            transpose, st, mcfg, ctx->part, ldp));
+            AAO_TRY(small(3, 0, matvec_blocks(n, ell, mcfg)));
+        } else {
+            AAO_LAUNCH_B(AAO_K_AXPY, vec_bytes(ctx) * (k + (x_zero ? 1 : 2)),
+                         launch_multi_axpy(Zl, k, yc, x, N, !x_zero, st));
+            AAO_TRY(residual(false));
+        }
         x_zero = false;
         Vl.p[0] = V0;
-        AAO_TRY(residual(false));
         AAO_TRY(wait_small(ctx));
         beta = hb[kHostBeta];
         failed = failed || hb[kHostFail] != 0.0;

@@ -111,6 +111,19 @@ hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, 
                          Scheme sc, double kappa, const double *tau_k, int transpose,
                          hipStream_t st, int cfg = -1, const VecList *V = nullptr, int nv = 0,
                          double *part = nullptr, int ldp = 0);
+// x given as a combination sum_q c[q] z[q] (q < 4) and written to xout by the matvec
+struct MatvecComb {
+    const double *z[4];
+    double c[4];
+    double *xout;
+};
+// The residual check of a solution update in one launch: x = sum_{q<nz} c_q z_q is
+// formed on the fly, written to cb.xout, and the block partials of |bsub - A x|^2 go to
+// part (one value).  Only for DPP launch shapes and nz <= 4 (matvec_comb_ok).
+bool matvec_comb_ok(int cfg, int nz);
+hipError_t launch_matvec_comb(const MatvecComb &cb, int nz, const double *bsub, int n, int ell,
+                              Scheme sc, double kappa, const double *tau_k, int transpose,
+                              hipStream_t st, int cfg, double *part, int ldp);
 // matvec launch shapes: code = 3 v + r (R = 4 << r rows per thread, v = 1: DPP lane moves)
 int matvec_num_configs();
 int matvec_default_config();

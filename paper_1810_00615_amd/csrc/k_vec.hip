@@ -402,11 +402,11 @@ __device__ __forceinline__ double lane_from_right(double v)
 }
 
 // DOTS: 0 none, 1 partials of V_q . y (q < nv), 2 the partial of y . y only
-template <int S, int R, bool DPP, int DOTS>
+template <int S, int R, bool DPP, int DOTS, int NZ = 0>
 __global__ void __launch_bounds__(256)
 k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
          int n, int ell, Scheme sc, double kappa, const double *__restrict__ tau_k, int transpose,
-         VecList V, int nv, double *__restrict__ part, int ldp)
+         VecList V, int nv, double *__restrict__ part, int ldp, MatvecComb cb = {})
 {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -423,9 +423,22 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
     for (int it = 0; it < NR; ++it) {
         const int kk = transpose ? (k1 - 1 + S - it) : (k0 - S + it);
         const bool in = it < nin && kk >= 0 && kk < ell;
-        const double *row = x + (size_t)(in ? kk : 0) * n;
-        c[it] = (in && col) ? row[i] : 0.0;
-        e[it] = (in && edge) ? row[je] : 0.0;
+        if (NZ == 0) {
+            const double *row = x + (size_t)(in ? kk : 0) * n;
+            c[it] = (in && col) ? row[i] : 0.0;
+            e[it] = (in && edge) ? row[je] : 0.0;
+        } else {
+            // x = sum_q c_q Z_q formed on the fly (and stored for the owned rows below)
+            double cc = 0.0, ee = 0.0;
+#pragma unroll
+            for (int q = 0; q < NZ; ++q) {
+                const double *row = cb.z[q] + (size_t)(in ? kk : 0) * n;
+                cc += cb.c[q] * ((in && col) ? row[i] : 0.0);
+                ee += cb.c[q] * ((in && edge) ? row[je] : 0.0);
+            }
+            c[it] = cc;
+            e[it] = ee;
+        }
     }
     // the rows of bsub and of the first two basis vectors are loaded with x, so that
     // their latency overlaps the x loads instead of following the stencil
@@ -488,6 +501,7 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
         const double out = bsub ? bs[it - S] - v : v;
         yv[it - S] = out;
         if (col && y) y[(size_t)k * n + i] = out;
+        if (NZ > 0 && col) cb.xout[(size_t)k * n + i] = c[it];   // the owned rows of x
     }
     if (DOTS == 0) return;
     __shared__ double red[kMaxVecs * 4];
@@ -572,6 +586,54 @@ static hipError_t matvec_disp(int cfg, const double *x, double *y, const double 
     }
 #undef AAO_MV
     return hipGetLastError();
+}
+
+// Residual check of x = sum_q c_q Z_q (nz <= 4, DPP launch shapes only): x is formed
+// on the fly, stored, and the launch writes the partials of |bsub - A x|^2.
+template <int S>
+static hipError_t matvec_comb_disp(int cfg, const MatvecComb &cb, int nz, const double *bsub,
+                                   int n, int ell, Scheme sc, double kappa, const double *tau_k,
+                                   int transpose, double *part, hipStream_t st)
+{
+    const int R = 4 << (cfg % 3);
+    dim3 grid((n + 255) / 256, (ell + R - 1) / R);
+    const VecList none{};
+#define AAO_MC(RR, K)                                                                           \
+    if (R == RR && nz == K) {                                                                   \
+        k_matvec<S, RR, true, 2, K><<<grid, 256, 0, st>>>(nullptr, nullptr, bsub, n, ell, sc,   \
+                                                          kappa, tau_k, transpose, none, 1,     \
+                                                          part, 0, cb);                         \
+        return hipGetLastError();                                                               \
+    }
+    AAO_MC(4, 1) AAO_MC(4, 2) AAO_MC(4, 3) AAO_MC(4, 4)
+    AAO_MC(8, 1) AAO_MC(8, 2) AAO_MC(8, 3) AAO_MC(8, 4)
+    AAO_MC(16, 1) AAO_MC(16, 2) AAO_MC(16, 3) AAO_MC(16, 4)
+#undef AAO_MC
+    return hipErrorInvalidValue;
+}
+
+bool matvec_comb_ok(int cfg, int nz)
+{
+    if (cfg < 0 || cfg >= matvec_num_configs()) cfg = matvec_default_config();
+    return cfg >= 3 && nz >= 1 && nz <= 4;
+}
+
+hipError_t launch_matvec_comb(const MatvecComb &cb, int nz, const double *bsub, int n, int ell,
+                              Scheme sc, double kappa, const double *tau_k, int transpose,
+                              hipStream_t st, int cfg, double *part, int ldp)
+{
+    if (cfg < 0 || cfg >= matvec_num_configs()) cfg = matvec_default_config();
+    if (!matvec_comb_ok(cfg, nz) || !part || !cb.xout || matvec_blocks(n, ell, cfg) > ldp)
+        return hipErrorInvalidValue;
+    switch (sc.s) {
+    case 1:
+        return matvec_comb_disp<1>(cfg, cb, nz, bsub, n, ell, sc, kappa, tau_k, transpose, part, st);
+    case 2:
+        return matvec_comb_disp<2>(cfg, cb, nz, bsub, n, ell, sc, kappa, tau_k, transpose, part, st);
+    case 3:
+        return matvec_comb_disp<3>(cfg, cb, nz, bsub, n, ell, sc, kappa, tau_k, transpose, part, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 int matvec_blocks(int n, int ell, int cfg)

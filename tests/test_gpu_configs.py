@@ -167,3 +167,28 @@ def test_matvec_shapes_variable_steps(dev, orc):
             P.set_config("matvec", code)
             y = P.A(xd, transpose=tr).cpu().numpy()
             assert float(np.max(np.abs(y - ref)) / np.max(np.abs(ref))) < 1e-14, (code, tr)
+
+
+@pytest.mark.parametrize("code", [1, 4])
+@pytest.mark.parametrize("scheme,restart", [(HEAT, 3), (BD2, 8)])
+def test_solution_update_paths(dev, orc, code, scheme, restart):
+    """The solution update and residual check in one launch (DPP launch shapes, at
+    most four directions, zero initial guess) and as a separate update plus check
+    (other shapes, more directions, restart cycles): both reach the requested true
+    residual, and the reported residual is the oracle's."""
+    import torch
+    from paper_1810_00615_amd import Problem
+    n, ell = 255, 128
+    tau, kappa = 1.0 / ell, 1.0
+    P = Problem(n, ell, tau, "heat" if scheme == HEAT else "bd2", kappa=kappa, device=dev)
+    P.set_config("matvec", code)
+    rng = np.random.default_rng([code, restart])
+    br = np.zeros((ell, n))
+    br[:2] = rng.standard_normal((2, n))
+    b = torch.from_numpy(br).to(dev)
+    U, info = P.solve(b, restart=restart, tol=1e-10, maxit=600)
+    assert info["converged"], info
+    Un = U.cpu().numpy()
+    rel = np.linalg.norm(br - orc.apply_A(scheme, n, ell, tau, kappa, Un)) / np.linalg.norm(br)
+    assert rel <= 1.0001e-10
+    assert abs(info["rel_resid_true"] - rel) < 1e-12
