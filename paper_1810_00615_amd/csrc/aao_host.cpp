@@ -641,13 +641,17 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     // Arnoldi: CGS2 with delayed re-orthogonalisation (two passes over the basis per
     // step) unless AAO_CGS2_CLASSIC is set (three passes: project, re-project, update)
     const bool delayed = std::getenv("AAO_CGS2_CLASSIC") == nullptr;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m),
+        hprov(m + 2);
     bool failed = false;
     while (inf.iters < maxit) {
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int k = 0;
+        // relative residual estimates of the last two steps (the cycle start counts
+        // as step -1; x0 = 0 with the deferred norm of b starts from 1)
+        double est_prev = bnorm > 0.0 ? beta / bnorm : 1.0, est_prev2 = 1.0;
         for (int j = 0; j < m; ++j) {
             const double *Vj = Vl.p[j];
             double *Zj = ctx->Z + N * j;
@@ -665,17 +669,42 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 AAO_LAUNCH_B(AAO_K_CGS_DOT, vec_bytes(ctx) * (nv + 1),
                              launch_multidot(Vl, nv, ctx->W, N, ctx->part, ldp, st));
             }
+            bool provisional = false;   // column from the Pythagorean norm, no update pass
             if (delayed) {
                 // CGS2 with the re-orthogonalisation of v_j deferred to this step: one
                 // pass writes the final v_j and the once-projected w1 (the next pending
                 // vector) and forms the dots that re-orthogonalise w1 in the next step
                 AAO_TRY(small(5, nv, fused ? matvec_blocks(n, ell, mcfg) : nb));
-                AAO_LAUNCH_B(AAO_K_ARNOLDI_UPDATE, vec_bytes(ctx) * (nv + (j > 0 ? 3 : 2)),
-                             launch_arnoldi_update(Vl, nv, ctx->W, ctx->scv(), ctx->scw(),
-                                                   j > 0 ? ctx->V + N * j : nullptr, Vn, N,
-                                                   ctx->part,
-                                                   ldp, st));
-                AAO_TRY(small(6, nv, nb));
+                // When the estimates so far predict convergence at this step, look
+                // first: with |w1|^2 = |w|^2 - |h|^2 the column is known without the
+                // update pass, and if its estimate meets tol the update (whose vectors
+                // would go unused) is skipped.  The true residual decides convergence.
+                if (fused && j > 0 && est_prev * (est_prev / est_prev2) <= 10.0 * tol) {
+                    AAO_TRY(wait_small(ctx));
+                    double hh = 0.0;
+                    for (int i = 0; i <= j; ++i) {
+                        hprov[i] = hb[i];
+                        hh += hprov[i] * hprov[i];
+                    }
+                    const double b2 = hb[kHostWW] - hh;
+                    hprov[nv] = b2 > 0.0 ? std::sqrt(b2) : 0.0;
+                    std::vector<double> tcol(hprov.begin(), hprov.begin() + nv + 1);
+                    for (int i = 0; i < j; ++i) {
+                        const double t = cs[i] * tcol[i] + sn[i] * tcol[i + 1];
+                        tcol[i + 1] = -sn[i] * tcol[i] + cs[i] * tcol[i + 1];
+                        tcol[i] = t;
+                    }
+                    const double den = std::hypot(tcol[j], tcol[j + 1]);
+                    const double est = den > 0.0 ? std::fabs(g[j]) * tcol[j + 1] / den / bnorm : 1.0;
+                    provisional = std::isfinite(est) && est <= 0.5 * tol;
+                }
+                if (!provisional) {
+                    AAO_LAUNCH_B(AAO_K_ARNOLDI_UPDATE, vec_bytes(ctx) * (nv + (j > 0 ? 3 : 2)),
+                                 launch_arnoldi_update(Vl, nv, ctx->W, ctx->scv(), ctx->scw(),
+                                                       j > 0 ? ctx->V + N * j : nullptr, Vn, N,
+                                                       ctx->part, ldp, st));
+                    AAO_TRY(small(6, nv, nb));
+                }
             } else {
                 AAO_TRY(small(0, nv, fused ? matvec_blocks(n, ell, mcfg) : nb));
                 // CGS2: re-project, form the new (unnormalised) basis vector and its norm
@@ -688,7 +717,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                                                 ldp, st));
                 AAO_TRY(small(2, nv, nb));
             }
-            AAO_TRY(wait_small(ctx));
+            if (!provisional) AAO_TRY(wait_small(ctx));
             if (first) {
                 AAO_TRY(check_b());
                 if (bnorm == 0.0) {
@@ -702,8 +731,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 beta = bnorm;
                 g[0] = beta;
             }
-            for (int i = 0; i <= nv; ++i) hcol[i] = hb[i];
-            if (delayed) {
+            for (int i = 0; i <= nv; ++i) hcol[i] = provisional ? hprov[i] : hb[i];
+            if (delayed && !provisional) {
                 // A z_j = sum_{i<=j} h_i v_i + beta p_{j+1}, and p_{j+1} = sum a_i v_i +
                 // alpha v_{j+1} with |p_{j+1}| = 1: the column of the fully
                 // re-orthogonalised basis
@@ -742,6 +771,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             g[j] = cs[j] * g[j];
             k = j + 1;
             inf.rel_resid_est = std::fabs(g[j + 1]) / bnorm;
+            est_prev2 = est_prev;
+            est_prev = inf.rel_resid_est;
             if (std::getenv("AAO_LOG"))
                 std::fprintf(stderr, "aao gmres it %d est %.3e\n", inf.iters, inf.rel_resid_est);
             if (inf.rel_resid_est <= tol || inf.iters >= maxit) break;

@@ -104,8 +104,9 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
 
 // y = A x (or A^T x); with tau_k != nullptr the variable-step matrix B.
 // If bsub != nullptr computes y = bsub - A x.  With nv > 0 the launch also writes the
-// block partials of V_q . y (q < nv); nv == 1 with V->p[0] == y selects the partials
-// of y . y instead.  y may be null (nothing stored; only with the self-norm).
+// block partials of V_q . y (q < nv) and of y . y (value nv); nv == 1 with
+// V->p[0] == y selects only the partials of y . y (value 0).  y may be null (nothing
+// stored; only with the self-norm).
 struct VecList;
 hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
                          Scheme sc, double kappa, const double *tau_k, int transpose,
@@ -174,6 +175,7 @@ constexpr int kHostBeta = kMaxVecs;       // residual norm
 constexpr int kHostBB = kMaxVecs + 1;     // b.b
 constexpr int kHostFail = kMaxVecs + 2;   // shifted-solve breakdown flag (0 / 1)
 constexpr int kHostSeq = kMaxVecs + 3;    // sequence number of the last reduction
+constexpr int kHostWW = 2 * kMaxVecs + 4; // w . w of the step's matvec
 constexpr int kHostA = kMaxVecs + 4;      // re-orthogonalisation coefficients (kMaxVecs)
 constexpr int kHostSlots = 2 * kMaxVecs + 8;
 struct SmallArgs {

@@ -545,8 +545,17 @@ k_matvec(const double *__restrict__ x, double *__restrict__ y, const double *__r
             if (lane == 0 && q0 + u < nv) red[(q0 + u) * 4 + wv] = acc[u];
         }
     }
+    {
+        // y . y as value nv (the Pythagorean estimate of the projected norm)
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc += (col && r < nin - S) ? yv[r] * yv[r] : 0.0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if (lane == 0) red[nv * 4 + wv] = acc;
+    }
     __syncthreads();
-    for (int q = threadIdx.x; q < nv; q += blockDim.x)
+    for (int q = threadIdx.x; q <= nv; q += blockDim.x)
         part[(size_t)q * ldp + blk] = ((red[q * 4] + red[q * 4 + 1]) + red[q * 4 + 2]) + red[q * 4 + 3];
 }
 
@@ -648,7 +657,7 @@ hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, 
                          hipStream_t st, int cfg, const VecList *V, int nv, double *part, int ldp)
 {
     if (cfg < 0 || cfg >= matvec_num_configs()) cfg = matvec_default_config();
-    if (nv > 0 && (!V || !part || nv > kMaxVecs || matvec_blocks(n, ell, cfg) > ldp))
+    if (nv > 0 && (!V || !part || nv >= kMaxVecs || matvec_blocks(n, ell, cfg) > ldp))
         return hipErrorInvalidValue;
     static const VecList none{};
     const VecList &L = V ? *V : none;
@@ -809,7 +818,8 @@ namespace aao {
 //   mode 4: host[kHostBB] = d_0 (= b.b); with nv == 1 also vs_0 = 1/sqrt(d_0)
 //           and host[kHostBeta] = sqrt(d_0)       (zero initial guess: V_0 = b)
 //   mode 5: delayed re-orthogonalisation after the matvec of step j = nv - 1:
-//           coefficients cv, cw of the update pass, host[0..j] = first projections
+//           coefficients cv, cw of the update pass, host[0..j] = first projections,
+//           host[kHostWW] = w . w (partials: S_i . w for i < nv, then w . w)
 //   mode 6: after the update pass: vs_nv = 1/|w1|, a_i (next step's coefficients),
 //           host[nv] = |w1|, host[kHostA + i] = a_i
 // host: mapped pinned memory; host[kHostFail] receives the breakdown flag, and
@@ -820,7 +830,7 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
     __shared__ double wsum[16][kMaxVecs];
     __shared__ double sums[kMaxVecs + 1];   // final sums (LDS: indexed at run time)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int cnt = (a.mode <= 1 || a.mode == 5) ? a.nv : (a.mode == 6 ? a.nv + 1 : 1);
+    const int cnt = (a.mode <= 1) ? a.nv : (a.mode >= 5 ? a.nv + 1 : 1);
     // thread t sums the partials t, t + 1024, ... of every value, the loads of two
     // values (32 per thread) in flight at a time; then each wave and finally thread 0
     // add in a fixed order
@@ -881,6 +891,7 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
         a.cv[j] = a.vs[j] / alpha;
         a.cw[j] = hj / alpha * a.vs[j];
         a.host[j] = hj;
+        a.host[kHostWW] = sums[nv];   // w . w
         if (j > 0) a.vs[j] = 1.0;   // S_j is rewritten as the unit vector v_j
     } else if (a.mode == 6) {
         // after the update (sums: S_i . w1 for i < j, v_j . w1, w1 . w1):
