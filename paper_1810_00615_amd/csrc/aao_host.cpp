@@ -652,14 +652,17 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
         // relative residual estimates of the last two steps (the cycle start counts
         // as step -1; x0 = 0 with the deferred norm of b starts from 1)
         double est_prev = bnorm > 0.0 ? beta / bnorm : 1.0, est_prev2 = 1.0;
+        int ahead = -1;   // step whose preconditioner apply is already enqueued
         for (int j = 0; j < m; ++j) {
             const double *Vj = Vl.p[j];
             double *Zj = ctx->Z + N * j;
             double *Vn = ctx->V + N * (j + 1);
             const int nv = j + 1;
-            // z_j = P^{-1} v_j ; w = A z_j with the first projection V^T w
+            // z_j = P^{-1} v_j (unless already enqueued ahead of the previous step's wait);
+            // w = A z_j with the first projection V^T w
             const bool first = defer_b && inf.iters == 0;
-            AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose, first));
+            if (ahead != j)
+                AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose, first));
             if (fused) {
                 AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (2 + nv),
                              launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc, ctx->kappa,
@@ -679,7 +682,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 // first: with |w1|^2 = |w|^2 - |h|^2 the column is known without the
                 // update pass, and if its estimate meets tol the update (whose vectors
                 // would go unused) is skipped.  The true residual decides convergence.
-                if (fused && j > 0 && est_prev * (est_prev / est_prev2) <= 10.0 * tol) {
+                const bool expect = j > 0 && est_prev * (est_prev / est_prev2) <= 10.0 * tol;
+                if (fused && expect) {
                     AAO_TRY(wait_small(ctx));
                     double hh = 0.0;
                     for (int i = 0; i <= j; ++i) {
@@ -704,6 +708,15 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                                                        j > 0 ? ctx->V + N * j : nullptr, Vn, N,
                                                        ctx->part, ldp, st));
                     AAO_TRY(small(6, nv, nb));
+                    // convergence is not expected at this step: the next step's
+                    // preconditioner apply (which needs only the pending vector and its
+                    // scale, both on the device) is enqueued before the wait, so the GPU
+                    // does not idle through the host's Givens update
+                    if (!expect && j + 1 < m && inf.iters + 1 < maxit) {
+                        AAO_TRY(pinv_impl(ctx, Vl.p[j + 1], ctx->svs() + j + 1,
+                                          ctx->Z + N * (j + 1), ctx->neumann, transpose, false));
+                        ahead = j + 1;
+                    }
                 }
             } else {
                 AAO_TRY(small(0, nv, fused ? matvec_blocks(n, ell, mcfg) : nb));
