@@ -153,8 +153,12 @@ k_fft_inv(const cx<T> *__restrict__ Y, int lds, double *__restrict__ z, int n, i
         const int q0 = t + u * (L / P);
         const cx<double> wqd = tw[q0];
         const cx<T> wq = {T(wqd.x), T(-wqd.y)};
+        // points in the order r = 0, R0-1, 1, R0-2, ...: the partner L - p of the
+        // point taken in a slot is taken by its own holder in an adjacent slot, so the
+        // second read of each spectrum entry comes soon after the first (from L2)
 #pragma unroll
-        for (int r = 0; r < R0; ++r) {
+        for (int sl = 0; sl < R0; ++sl) {
+            const int r = (sl & 1) ? R0 - 1 - (sl >> 1) : (sl >> 1);
             const int idx = u * R0 + r;
             const int pos = first_pos<L, P>(t, idx);
             cx<T> q = {T(0), T(0)};
