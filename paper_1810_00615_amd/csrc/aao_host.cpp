@@ -641,6 +641,9 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     // Arnoldi: CGS2 with delayed re-orthogonalisation (two passes over the basis per
     // step) unless AAO_CGS2_CLASSIC is set (three passes: project, re-project, update)
     const bool delayed = std::getenv("AAO_CGS2_CLASSIC") == nullptr;
+    // AAO_EARLY_CHECK set: the early column check at every step after the first (a
+    // test of the path where the check fails and the step completes normally)
+    const bool early_always = std::getenv("AAO_EARLY_CHECK") != nullptr;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m),
         hprov(m + 2);
     bool failed = false;
@@ -663,10 +666,16 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             const bool first = defer_b && inf.iters == 0;
             if (ahead != j)
                 AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose, first));
+            // convergence expected at this step (from the estimates of the last two):
+            // the step's column is then checked before the update pass, and w is not
+            // stored unless that check fails
+            const bool expect = delayed && fused && j > 0 &&
+                                (early_always || est_prev * (est_prev / est_prev2) <= 10.0 * tol);
             if (fused) {
-                AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (2 + nv),
-                             launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc, ctx->kappa,
-                                         ctx->tauk, transpose, st, mcfg, &Vl, nv, ctx->part, ldp));
+                AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (expect ? 1 + nv : 2 + nv),
+                             launch_matvec(Zj, expect ? nullptr : ctx->W, nullptr, n, ell,
+                                           ctx->sc, ctx->kappa, ctx->tauk, transpose, st, mcfg,
+                                           &Vl, nv, ctx->part, ldp));
             } else {
                 AAO_TRY(apply_A_impl(ctx, Zj, ctx->W, nullptr, transpose));
                 AAO_LAUNCH_B(AAO_K_CGS_DOT, vec_bytes(ctx) * (nv + 1),
@@ -682,8 +691,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 // first: with |w1|^2 = |w|^2 - |h|^2 the column is known without the
                 // update pass, and if its estimate meets tol the update (whose vectors
                 // would go unused) is skipped.  The true residual decides convergence.
-                const bool expect = j > 0 && est_prev * (est_prev / est_prev2) <= 10.0 * tol;
-                if (fused && expect) {
+                if (expect) {
                     AAO_TRY(wait_small(ctx));
                     double hh = 0.0;
                     for (int i = 0; i <= j; ++i) {
@@ -703,6 +711,10 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                     provisional = std::isfinite(est) && est <= 0.5 * tol;
                 }
                 if (!provisional) {
+                    if (expect)   // w was not stored by the first pass
+                        AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * 2,
+                                     launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc,
+                                                   ctx->kappa, ctx->tauk, transpose, st, mcfg));
                     AAO_LAUNCH_B(AAO_K_ARNOLDI_UPDATE, vec_bytes(ctx) * (nv + (j > 0 ? 3 : 2)),
                                  launch_arnoldi_update(Vl, nv, ctx->W, ctx->scv(), ctx->scw(),
                                                        j > 0 ? ctx->V + N * j : nullptr, Vn, N,

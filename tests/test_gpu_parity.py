@@ -258,6 +258,37 @@ def test_arnoldi_delayed_matches_classic(aao, orc, torch_dev, scheme, restart, m
     assert normrel(Ud, Uc) < 1e-6
 
 
+@pytest.mark.parametrize("scheme,restart", [(HEAT, 30), (BD2, 12)])
+def test_early_column_check_every_step(aao, orc, torch_dev, scheme, restart, monkeypatch):
+    """The early column check (formed from the matvec's dots before the update pass)
+    forced at every step: where it fails, w is recomputed and the step completes
+    normally; the solve matches the default one (same iterations up to 1) and reaches
+    the requested true residual."""
+    n, ell = 127, 256
+    tau = 1.0 / ell
+    from paper_1810_00615_amd.inputs import sine_amps
+    m, a = sine_amps([6, 0], 30)
+    mv, av = sine_amps([6, 1], 30)
+    name = "heat" if scheme == HEAT else "bd2"
+    P = aao.Problem(n, ell, tau, name, device=torch_dev[1])
+    b = P.rhs(P.project_sine(m, a), P.project_sine(mv, av) if scheme == BD2 else None)
+    br = b.cpu().numpy()
+    out = {}
+    for forced in (False, True):
+        if forced:
+            monkeypatch.setenv("AAO_EARLY_CHECK", "1")
+        else:
+            monkeypatch.delenv("AAO_EARLY_CHECK", raising=False)
+        U, info = P.solve(b, restart=restart, tol=1e-10, maxit=600)
+        assert info["converged"], (forced, info)
+        r = br - orc.apply_A(scheme, n, ell, tau, 1.0, U.cpu().numpy())
+        assert np.linalg.norm(r) / np.linalg.norm(br) <= 1.0001e-10, forced
+        out[forced] = (U.cpu().numpy(), info["iters"])
+    monkeypatch.delenv("AAO_EARLY_CHECK", raising=False)
+    assert abs(out[True][1] - out[False][1]) <= 1
+    assert normrel(out[True][0], out[False][0]) < 1e-6
+
+
 def test_gmres_errors_and_edges(aao, torch_dev):
     import torch
     P = aao.Problem(15, 16, scheme="heat", device=torch_dev[1])
