@@ -3,6 +3,10 @@
 #pragma once
 #include "aao_internal.h"
 
+#ifndef BL_THREADS_DEFAULT
+#define BL_THREADS_DEFAULT 512
+#endif
+
 namespace aao {
 
 struct BProb {
@@ -39,10 +43,11 @@ struct BatchLaunch {
 };
 
 constexpr int kBatchSlab = 65536;       // elements per Gram-Schmidt / update slab
-// Bluestein transforms: points per thread of the length-M FFTs; a 1024-thread
-// workgroup transforms 1024 P / M column pairs
-constexpr int kBluesteinP = 8;   // (16 spills registers in the two-transform tiles)
-constexpr int bluestein_pairs(int M) { return 1024 * kBluesteinP / M; }
+// Bluestein transforms: points per thread of the length-M FFTs and threads per
+// workgroup; a workgroup transforms kBluesteinThreads P / M column pairs
+constexpr int kBluesteinP = 8;
+constexpr int kBluesteinThreads = BL_THREADS_DEFAULT;
+constexpr int bluestein_pairs(int M) { return kBluesteinThreads * kBluesteinP / M; }
 
 hipError_t batch_prepare();
 hipError_t batch_setup_tables(const BProb *probs, int count, int max_ell, int max_M,

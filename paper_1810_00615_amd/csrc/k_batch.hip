@@ -11,6 +11,7 @@
 // the same register/LDS Stockham FFT as the single-problem path.  Two real
 // columns travel as one complex sequence and are separated with the Hermitian
 // symmetry of their spectra.
+#include <algorithm>
 #include <cstdlib>
 
 #include "batch.h"
@@ -41,6 +42,55 @@ __device__ __forceinline__ void regroup(cx<T> *v, T *sm, int t, int c, int W)
 
 template <typename T> __device__ __forceinline__ cx<T> cvt(cx<double> a) { return {T(a.x), T(a.y)}; }
 
+// The second transform of a Bluestein tile reads the same twiddle and chirp
+// entries as the first; left visible, the compiler keeps the first loads live
+// across both transforms instead of loading again, and spills.  An empty asm
+// makes the pointer opaque so the loads are repeated.
+template <typename P>
+__device__ __forceinline__ P *fresh(P *p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Copy rows 0..ell-1, columns [cbase, cbase + C2) of a row-major ell x n array
+// to LDS (row k at xs[k * C2], columns past n read as 0), and back.  ell <= M/2
+// and C2 M = 2 NTB P, so both loops take exactly P passes of the NTB threads;
+// the addresses are clamped so that every pass issues its load unconditionally.
+template <int C2>
+__device__ __forceinline__ void stage_rows(const double *__restrict__ rp, int n, int ell, int cbase,
+                                           double *xs)
+{
+    constexpr int NQ = kBluesteinP, NTB = kBluesteinThreads;
+    double val[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = threadIdx.x + u * NTB;
+        const int k = min(q / C2, ell - 1), col = min(cbase + q % C2, n - 1);
+        val[u] = rp[(size_t)k * n + col];
+    }
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+        const int q = threadIdx.x + u * NTB;
+        const bool ok = q / C2 < ell && cbase + q % C2 < n;
+        xs[q] = ok ? val[u] : 0.0;
+    }
+    __syncthreads();
+}
+
+template <int C2>
+__device__ __forceinline__ void unstage_rows(const double *xs, int n, int ell, int cbase,
+                                             double *__restrict__ zp)
+{
+    constexpr int NQ = kBluesteinP, NTB = kBluesteinThreads;
+#pragma unroll 4   // (fully unrolled, the addresses of all eight stores spill)
+    for (int u = 0; u < NQ; ++u) {
+        const int q = threadIdx.x + u * NTB;
+        const int k = q / C2, col = cbase + q % C2;
+        if (k < ell && col < n) zp[(size_t)k * n + col] = xs[q];
+    }
+}
+
 // Keep at most a few table loads in flight inside the fully unrolled per-point
 // loops (the scheduler would otherwise hoist all of them and spill).
 #define AAO_GROUP_FENCE(idx)                                     \
@@ -61,30 +111,34 @@ __device__ void bl_fwd_tile(const BProb &pb, int tile, const double *__restrict_
 {
     constexpr int P = kBluesteinP;                    // points per thread
     constexpr int TN = M / P;
-    constexpr int W = 1024 / TN;                      // column pairs per tile
+    constexpr int NTB = kBluesteinThreads;
+    constexpr int W = NTB / TN;                       // column pairs per tile
+    constexpr int C2 = 2 * W;                         // real columns per tile
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int n = pb.n, ell = pb.ell;
-    const int col0 = (tile * W + c) * 2;
-    const bool v0 = col0 < n, v1 = col0 + 1 < n;
+    const int cbase = tile * C2;
     const double *rp = r + pb.off;
     const cx<double> *ch = chirp + pb.coff;
+    // The tile's rows are staged in LDS first, C2 consecutive lanes reading one
+    // row segment, so that every segment is one contiguous request (per-point
+    // loads would touch each segment with several scattered requests).
+    stage_rows<C2>(rp, n, ell, cbase, reinterpret_cast<double *>(sm));
+    const double *xs = reinterpret_cast<const double *>(sm);
     cx<T> v[P];
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
         const int k = first_pos<M, P>(t, idx);
         cx<T> a = {T(0), T(0)};
         if (k < ell) {
-            double x0 = 0.0, x1 = 0.0;
-            const size_t o = (size_t)k * n + col0;
-            if (v0) x0 = rs * rp[o];
-            if (v1) x1 = rs * rp[o + 1];
+            const double x0 = rs * xs[k * C2 + 2 * c], x1 = rs * xs[k * C2 + 2 * c + 1];
             const cx<double> ck = ch[k];
             a = cvt<T>(cx<double>{x0 * ck.x - x1 * ck.y, x0 * ck.y + x1 * ck.x});
         }
         v[idx] = a;
         AAO_GROUP_FENCE(idx);
     }
+    __syncthreads();                                  // staging read before the first exchange
     run_stages<T, M, P, 0, false>(v, sm, t, c, W, twM, 4096 / M);
     const cx<double> *bh = bhat + pb.boff;           // spectrum of the forward filter
 #pragma unroll
@@ -93,31 +147,35 @@ __device__ void bl_fwd_tile(const BProb &pb, int tile, const double *__restrict_
         AAO_GROUP_FENCE(idx);
     }
     regroup<T, M, P>(v, sm, t, c, W);
-    run_stages<T, M, P, 0, true>(v, sm, t, c, W, twM, 4096 / M);
+    run_stages<T, M, P, 0, true>(v, sm, t, c, W, fresh(twM), 4096 / M);
     // Z_j = c_j conv_j / M for j < ell; stage Z in LDS (complex) to pair j with ell-j
     const T invM = T(1.0 / M);
+    const cx<double> *ch2 = fresh(ch);
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
         const int j = final_pos<M, P>(t, idx);
         if (j < ell) {
-            const cx<T> z = cvt<T>(ch[j]) * v[idx];
+            const cx<T> z = cvt<T>(ch2[j]) * v[idx];
             sm[2 * (j * W + c)] = z.x * invM;
             sm[2 * (j * W + c) + 1] = z.y * invM;
         }
         AAO_GROUP_FENCE(idx);
     }
     __syncthreads();
-    // X1_j = (Z_j + conj Z_{ell-j}) / 2,  X2_j = (Z_j - conj Z_{ell-j}) / 2i,  j <= ell/2
+    // X1_j = (Z_j + conj Z_{ell-j}) / 2,  X2_j = (Z_j - conj Z_{ell-j}) / 2i,  j <= ell/2;
+    // consecutive lanes take consecutive columns of a spectrum row
     cx<T> *sp = spec + pb.soff;
     const int H = ell / 2;
-    for (int j = t; j <= H; j += TN) {
+    for (int q = threadIdx.x; q < (H + 1) * C2; q += NTB) {
+        const int j = q / C2, cc = q % C2, pc = cc >> 1;
         const int jm = (ell - j) % ell;
-        const cx<T> z = {sm[2 * (j * W + c)], sm[2 * (j * W + c) + 1]};
-        const cx<T> zm = {sm[2 * (jm * W + c)], sm[2 * (jm * W + c) + 1]};
-        const cx<T> x1 = {T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
-        const cx<T> x2 = {T(0.5) * (z.y + zm.y), T(0.5) * (zm.x - z.x)};
-        if (v0) sp[(size_t)j * pb.lds + col0] = x1;
-        if (v1) sp[(size_t)j * pb.lds + col0 + 1] = x2;
+        const cx<T> z = {sm[2 * (j * W + pc)], sm[2 * (j * W + pc) + 1]};
+        const cx<T> zm = {sm[2 * (jm * W + pc)], sm[2 * (jm * W + pc) + 1]};
+        // component-wise selects (a selected aggregate would be built in scratch)
+        const bool second = cc & 1;
+        const T ox = T(0.5) * (second ? z.y + zm.y : z.x + zm.x);
+        const T oy = T(0.5) * (second ? zm.x - z.x : z.y - zm.y);
+        if (cbase + cc < n) sp[(size_t)j * pb.lds + cbase + cc] = cx<T>{ox, oy};
     }
 }
 
@@ -132,15 +190,39 @@ __device__ void bl_inv_tile(const BProb &pb, int tile, const cx<T> *__restrict__
 {
     constexpr int P = kBluesteinP;
     constexpr int TN = M / P;
-    constexpr int W = 1024 / TN;
+    constexpr int NTB = kBluesteinThreads;
+    constexpr int W = NTB / TN;
+    constexpr int C2 = 2 * W;                         // real columns per tile
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int n = pb.n, ell = pb.ell;
-    const int col0 = (tile * W + c) * 2;
-    const bool v0 = col0 < n, v1 = col0 + 1 < n;
+    const int cbase = tile * C2;
     const cx<double> *ch = chirp + pb.coff;
     const cx<T> *sp = spec + pb.soff;
     const int H = ell / 2;
+    // spectrum rows 0..H of the tile's columns staged in LDS, one contiguous
+    // request per row segment
+    // (H + 1) C2 <= (M/4 + 1) C2 = NTB P / 2 + C2 entries: P/2 + 1 passes, loads clamped
+    cx<T> *ys = reinterpret_cast<cx<T> *>(sm);
+    {
+        constexpr int NQ = P / 2 + 1;
+        T vx[NQ], vy[NQ];
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int q = threadIdx.x + u * NTB;
+            const int j = min(q / C2, H), col = min(cbase + q % C2, n - 1);
+            const cx<T> y = sp[(size_t)j * pb.lds + col];
+            vx[u] = y.x;
+            vy[u] = y.y;
+        }
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int q = threadIdx.x + u * NTB;
+            const bool in = cbase + q % C2 < n;
+            if (q < (H + 1) * C2) ys[q] = cx<T>{in ? vx[u] : T(0), in ? vy[u] : T(0)};
+        }
+    }
+    __syncthreads();
     cx<T> v[P];
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
@@ -149,9 +231,7 @@ __device__ void bl_inv_tile(const BProb &pb, int tile, const cx<T> *__restrict__
         if (j < ell) {
             const bool up = j > H;
             const int jr = up ? ell - j : j;
-            cx<T> y1 = {T(0), T(0)}, y2 = {T(0), T(0)};
-            if (v0) y1 = sp[(size_t)jr * pb.lds + col0];
-            if (v1) y2 = sp[(size_t)jr * pb.lds + col0 + 1];
+            cx<T> y1 = ys[jr * C2 + 2 * c], y2 = ys[jr * C2 + 2 * c + 1];
             if (up) {
                 y1 = conj(y1);
                 y2 = conj(y2);
@@ -162,6 +242,7 @@ __device__ void bl_inv_tile(const BProb &pb, int tile, const cx<T> *__restrict__
         v[idx] = a;
         AAO_GROUP_FENCE(idx);
     }
+    __syncthreads();                                  // staging read before the first exchange
     run_stages<T, M, P, 0, false>(v, sm, t, c, W, twM, 4096 / M);
     const cx<double> *bh = bhat + pb.boff + M;       // spectrum of the inverse filter
 #pragma unroll
@@ -170,24 +251,29 @@ __device__ void bl_inv_tile(const BProb &pb, int tile, const cx<T> *__restrict__
         AAO_GROUP_FENCE(idx);
     }
     regroup<T, M, P>(v, sm, t, c, W);
-    run_stages<T, M, P, 0, true>(v, sm, t, c, W, twM, 4096 / M);
+    run_stages<T, M, P, 0, true>(v, sm, t, c, W, fresh(twM), 4096 / M);
+    // rows of the result staged in LDS and written one contiguous segment per row
     const double scale = 1.0 / ((double)M * (double)ell);
-    double *zp = z + pb.off;
+    double *xs = reinterpret_cast<double *>(sm);
+    const cx<double> *ch2 = fresh(ch);
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
         const int k = final_pos<M, P>(t, idx);
         if (k < ell) {
-            const cx<T> x = conj(cvt<T>(ch[k])) * v[idx];
-            const size_t o = (size_t)k * n + col0;
-            if (v0) zp[o] = double(x.x) * scale;
-            if (v1) zp[o + 1] = double(x.y) * scale;
+            const cx<T> x = conj(cvt<T>(ch2[k])) * v[idx];
+            xs[k * C2 + 2 * c] = double(x.x) * scale;
+            xs[k * C2 + 2 * c + 1] = double(x.y) * scale;
         }
         AAO_GROUP_FENCE(idx);
     }
+    __syncthreads();
+    unstage_rows<C2>(xs, n, ell, cbase, z + pb.off);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024)
+// two workgroups per CU (at most 128 VGPRs), so that one can load or store
+// while the other transforms
+__global__ void __launch_bounds__(kBluesteinThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_batch_fft_fwd(const BProb *__restrict__ probs, const int2 *__restrict__ tiles, int ntiles,
                 const unsigned char *__restrict__ active, const double *__restrict__ r,
                 const double *__restrict__ scales, int sstride, cx<T> *__restrict__ spec, const cx<double> *__restrict__ chirp,
@@ -210,7 +296,9 @@ k_batch_fft_fwd(const BProb *__restrict__ probs, const int2 *__restrict__ tiles,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024)
+// two workgroups per CU (at most 128 VGPRs), so that one can load or store
+// while the other transforms
+__global__ void __launch_bounds__(kBluesteinThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_batch_fft_inv(const BProb *__restrict__ probs, const int2 *__restrict__ tiles, int ntiles,
                 const unsigned char *__restrict__ active, const cx<T> *__restrict__ spec,
                 double *__restrict__ z, const cx<double> *__restrict__ chirp,
@@ -631,11 +719,16 @@ hipError_t batch_setup_tables(const BProb *probs, int count, int max_ell, int ma
 
 static size_t bl_smem(size_t realsz)
 {
-    // largest tile plane over M in {512..4096}: lds_rows(M) * W reals, W = 1024 P / M
+    // largest of, over M in {512..4096} (W = NTB P / M pairs, C2 = 2 W columns,
+    // ell <= M/2): the tile plane lds_rows(M) W reals; the staged real rows
+    // ell C2 doubles; the staged spectrum rows (M/4 + 1) C2 complex values
     size_t best = 0;
     for (int M = 512; M <= 4096; M *= 2) {
-        const size_t s = (size_t)lds_rows(M) * bluestein_pairs(M) * realsz;
-        if (s > best) best = s;
+        const size_t W = bluestein_pairs(M), C2 = 2 * W;
+        const size_t plane = (size_t)lds_rows(M) * W * realsz;
+        const size_t rows = (size_t)(M / 2) * C2 * sizeof(double);
+        const size_t spec = (size_t)(M / 4 + 1) * C2 * 2 * realsz;
+        best = std::max(best, std::max(plane, std::max(rows, spec)));
     }
     return best;
 }
@@ -673,7 +766,7 @@ hipError_t batch_fft_fwd(const BatchLaunch &L, const double *r, const double *sc
     if (single) {
         const size_t smem = bl_smem(sizeof(float));
         auto k = k_batch_fft_fwd<float>;
-        k<<<G, 1024, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active, r, scales, sstride,
+        k<<<G, kBluesteinThreads, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active, r, scales, sstride,
                                  reinterpret_cast<cx<float> *>(spec),
                                  reinterpret_cast<const cx<double> *>(L.chirp),
                                  reinterpret_cast<const cx<double> *>(L.bhat),
@@ -681,7 +774,7 @@ hipError_t batch_fft_fwd(const BatchLaunch &L, const double *r, const double *sc
     } else {
         const size_t smem = bl_smem(sizeof(double));
         auto k = k_batch_fft_fwd<double>;
-        k<<<G, 1024, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active, r, scales, sstride,
+        k<<<G, kBluesteinThreads, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active, r, scales, sstride,
                                  reinterpret_cast<cx<double> *>(spec),
                                  reinterpret_cast<const cx<double> *>(L.chirp),
                                  reinterpret_cast<const cx<double> *>(L.bhat),
@@ -697,7 +790,7 @@ hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool
     if (single) {
         const size_t smem = bl_smem(sizeof(float));
         auto k = k_batch_fft_inv<float>;
-        k<<<G, 1024, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active,
+        k<<<G, kBluesteinThreads, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active,
                                  reinterpret_cast<const cx<float> *>(spec), z,
                                  reinterpret_cast<const cx<double> *>(L.chirp),
                                  reinterpret_cast<const cx<double> *>(L.bhat),
@@ -705,7 +798,7 @@ hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool
     } else {
         const size_t smem = bl_smem(sizeof(double));
         auto k = k_batch_fft_inv<double>;
-        k<<<G, 1024, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active,
+        k<<<G, kBluesteinThreads, smem, st>>>(L.probs, L.ftiles, L.nftiles, L.active,
                                  reinterpret_cast<const cx<double> *>(spec), z,
                                  reinterpret_cast<const cx<double> *>(L.chirp),
                                  reinterpret_cast<const cx<double> *>(L.bhat),
