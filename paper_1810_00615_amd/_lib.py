@@ -72,6 +72,8 @@ SIGNATURES = {
     "aao_batch_apply_Pinv": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "aao_batch_gmres": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                         ctypes.c_double, ctypes.c_int, ctypes.c_void_p],
+    "aao_batch_gmres_ex": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                           ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_void_p],
     "aao_batch_last_error": [ctypes.c_void_p],
     "aao_status_string": [ctypes.c_int],
     "aao_last_error": [ctypes.c_void_p],

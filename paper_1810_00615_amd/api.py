@@ -378,15 +378,18 @@ class Batch:
                 "aao_batch_apply_Pinv")
         return z
 
-    def solve(self, b, restart=30, tol=1e-8, maxit=300, x0=None, out=None):
+    def solve(self, b, restart=30, tol=1e-8, maxit=300, x0=None, out=None, transpose=False):
+        """FGMRES on every problem; x0=None starts from zero (no residual matvec in
+        the first cycle); transpose=True solves A_p^T x_p = b_p."""
         x = out if out is not None else self.empty()
+        flags = GMRES_TRANSPOSE if transpose else 0
         if x0 is None:
-            x.zero_()
+            flags |= GMRES_ZERO_GUESS
         else:
             x.copy_(x0)
         infos = (Info * self.count)()
         self._sync_in()
-        st = self._L.aao_batch_gmres(self._b, _ptr(b), _ptr(x), int(restart), float(tol),
-                                     int(maxit), ctypes.cast(infos, ctypes.c_void_p))
-        self._c(st, "aao_batch_gmres")
+        st = self._L.aao_batch_gmres_ex(self._b, _ptr(b), _ptr(x), int(restart), float(tol),
+                                        int(maxit), flags, ctypes.cast(infos, ctypes.c_void_p))
+        self._c(st, "aao_batch_gmres_ex")
         return x, [i.as_dict() for i in infos], st

@@ -167,13 +167,17 @@ static aao_status b_pinv(aao_batch b, const double *r, const double *scales, int
 }
 
 // One Arnoldi step j for every active problem (the sequence that is captured).
-static aao_status b_step(aao_batch b, int j, int m, double tol, int transpose)
+// v0 (step 0 only, may be null): the first basis vector's storage when it is not
+// the workspace's own (the right-hand side itself, for a zero initial guess).
+static aao_status b_step(aao_batch b, int j, int m, double tol, int transpose,
+                         const double *v0 = nullptr)
 {
     const size_t N = b->Ntot;
     const BatchLaunch L = b->launch(true);
     const int nv = j + 1;
     BState &s = b->bs;
-    double *Vj = b->V + N * j, *Zj = b->Z + N * j, *Vn = b->V + N * (j + 1);
+    const double *Vj = (j == 0 && v0) ? v0 : b->V + N * j;
+    double *Zj = b->Z + N * j, *Vn = b->V + N * (j + 1);
     BT(b_pinv(b, Vj, s.vs + j, s.sst, Zj, true, transpose));
     BH(batch_matvec(L, Zj, b->W, nullptr, b->scheme, transpose, true, b->st));
     BH(batch_cgs(0, L, b->dV, nv, b->W, nullptr, 0, nullptr, b->part, b->ldp, true, b->st));
@@ -189,8 +193,11 @@ static aao_status b_step(aao_batch b, int j, int m, double tol, int transpose)
     return AAO_OK;
 }
 
+// zero: x0 = 0 whatever x holds (x is only written).  The first cycle then takes
+// b itself as its first basis vector: no residual matvec and no norm pass (||b||
+// is already known), and the solution update overwrites x.
 static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, double tol, int maxit,
-                          aao_info *infos, int transpose)
+                          aao_info *infos, int transpose, bool zero = false)
 {
     if (m < 1 || m > kBMaxRestart) {
         b->err = "restart must be in [1, 63]";
@@ -244,16 +251,36 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
     int cycles = 0;
     while (true) {
         // r = b - A x -> V_0, beta_p, vs_0, g_0, active/done
-        BH(batch_matvec(Lall, x, b->V, bvec, b->scheme, transpose, false, b->st));
-        BH(batch_cgs(0, Lall, b->dV, 1, b->V, nullptr, 0, nullptr, b->part, b->ldp, false, b->st));
-        BH(batch_reduce(Lall, b->part, b->ldp, 1, s.dsum, s.sst, false, b->st));
+        const bool from_b = zero && cycles == 0;
+        if (from_b) {
+            // V_0 = b: the pointer table's first entry names b for this cycle (the
+            // steps read V_0 through it); dsum still holds ||b_p||^2
+            const double *bp0[1] = {bvec};
+            BH(hipMemcpyAsync(b->dV, bp0, sizeof(double *), hipMemcpyHostToDevice, b->st));
+        } else {
+            BH(batch_matvec(Lall, x, b->V, bvec, b->scheme, transpose, false, b->st));
+            BH(batch_cgs(0, Lall, b->dV, 1, b->V, nullptr, 0, nullptr, b->part, b->ldp, false,
+                         b->st));
+            BH(batch_reduce(Lall, b->part, b->ldp, 1, s.dsum, s.sst, false, b->st));
+        }
         BH(batch_small(3, P, 0, m, tol, s, b->st));
         BH(batch_count_active(s.active, P, b->iv + 2 * P, b->st));
         BH(hipMemcpyAsync(&nact, b->iv + 2 * P, sizeof(int), hipMemcpyDeviceToHost, b->st));
         BH(hipStreamSynchronize(b->st));
-        if (nact == 0) break;
+        if (nact == 0) {
+            if (from_b) {
+                // every b_p already meets tol (or is zero): x = 0
+                BH(hipMemsetAsync(x, 0, sizeof(double) * N, b->st));
+                const double *vp0[1] = {b->V};
+                BH(hipMemcpyAsync(b->dV, vp0, sizeof(double *), hipMemcpyHostToDevice, b->st));
+            }
+            break;
+        }
         for (int j = 0; j < m; ++j) {
-            if (b->use_graph && b->st) {
+            if (from_b && j == 0) {
+                // the captured step 0 reads V_0 from the workspace: launch eagerly
+                BT(b_step(b, 0, m, tol, transpose, bvec));
+            } else if (b->use_graph && b->st) {
                 if (!b->graphs[j]) {
                     hipGraph_t g = nullptr;
                     BH(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
@@ -274,7 +301,11 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
             if (nact == 0) break;
         }
         BH(batch_backsolve(P, m, s, b->st));
-        BH(batch_axpy(Lall, b->dZ, s, x, b->st));
+        BH(batch_axpy(Lall, b->dZ, s, x, from_b, b->st));
+        if (from_b) {
+            const double *vp0[1] = {b->V};
+            BH(hipMemcpyAsync(b->dV, vp0, sizeof(double *), hipMemcpyHostToDevice, b->st));
+        }
         ++cycles;
     }
     // report
@@ -511,6 +542,23 @@ aao_status aao_batch_gmres(aao_batch b, const double *bvec, double *x, int resta
     if (b->broken) return AAO_ERR_HIP;
     try {
         return b_gmres(b, bvec, x, restart, tol, maxit, infos, 0);
+    } catch (...) {
+        return AAO_ERR_ALLOC;
+    }
+}
+
+aao_status aao_batch_gmres_ex(aao_batch b, const double *bvec, double *x, int restart, double tol,
+                              int maxit, int flags, aao_info *infos)
+{
+    if (!b) return AAO_ERR_ARG;
+    if (b->broken) return AAO_ERR_HIP;
+    if (flags & ~(AAO_GMRES_ZERO_GUESS | AAO_GMRES_TRANSPOSE)) {
+        b->err = "unknown flag bits";
+        return AAO_ERR_ARG;
+    }
+    try {
+        return b_gmres(b, bvec, x, restart, tol, maxit, infos,
+                       (flags & AAO_GMRES_TRANSPOSE) ? 1 : 0, (flags & AAO_GMRES_ZERO_GUESS) != 0);
     } catch (...) {
         return AAO_ERR_ALLOC;
     }

@@ -69,7 +69,7 @@ hipError_t batch_small(int mode, int count, int j, int m, double tol, const BSta
                        hipStream_t st);
 hipError_t batch_backsolve(int count, int m, const BState &s, hipStream_t st);
 hipError_t batch_axpy(const BatchLaunch &L, const double *const *Z, const BState &s, double *x,
-                      hipStream_t st);
+                      bool overwrite, hipStream_t st);
 hipError_t batch_count_active(const unsigned char *a, int count, int *nact, hipStream_t st);
 
 }  // namespace aao

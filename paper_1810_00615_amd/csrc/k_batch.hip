@@ -623,21 +623,21 @@ __global__ void k_batch_backsolve(int count, int m, BState st)
     }
 }
 
-// x += sum_{i < k_p} Z_i y_i per problem, over slabs
+// x += sum_{i < k_p} Z_i y_i per problem, over slabs (x = sum ... when overwrite)
 __global__ void __launch_bounds__(256)
 k_batch_axpy(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int nslabs,
-             const double *const *__restrict__ Z, BState st, double *__restrict__ x)
+             const double *const *__restrict__ Z, BState st, double *__restrict__ x, int overwrite)
 {
     const int g = blockIdx.x;
     if (g >= nslabs) return;
     const int4 e = slabs[g];
     const int k = st.ksteps[e.x];
-    if (k == 0) return;
+    if (k == 0 && !overwrite) return;
     const double *y = st.y + (size_t)e.x * st.sst;
     const size_t base = probs[e.x].off + (size_t)e.y;
     for (int q = threadIdx.x; q < e.z; q += blockDim.x) {
         const size_t o = base + q;
-        double s = x[o];
+        double s = overwrite ? 0.0 : x[o];
         for (int i = 0; i < k; ++i) s += Z[i][o] * y[i];
         x[o] = s;
     }
@@ -883,9 +883,9 @@ hipError_t batch_backsolve(int count, int m, const BState &s, hipStream_t st)
 }
 
 hipError_t batch_axpy(const BatchLaunch &L, const double *const *Z, const BState &s, double *x,
-                      hipStream_t st)
+                      bool overwrite, hipStream_t st)
 {
-    k_batch_axpy<<<L.nslabs, 256, 0, st>>>(L.probs, L.slabs, L.nslabs, Z, s, x);
+    k_batch_axpy<<<L.nslabs, 256, 0, st>>>(L.probs, L.slabs, L.nslabs, Z, s, x, overwrite ? 1 : 0);
     return hipGetLastError();
 }
 

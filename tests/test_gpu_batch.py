@@ -84,6 +84,49 @@ def test_batch_gmres_small(dev, orc, prec):
         assert normrel(X, U) < 1e-6
 
 
+@pytest.mark.parametrize("restart", [30, 2])
+def test_batch_zero_guess(dev, orc, restart):
+    """The zero-guess entry (first cycle starts from b itself, x only written: the
+    output buffer starts as NaN) gives bitwise the result of an explicit zero initial
+    guess, also when the problems restart; an all-zero right-hand side returns x = 0."""
+    import torch
+    B, ns, ells, kappas = make(dev, "fp64")
+    J = 20
+    modes = np.arange(1, J + 1)
+    amps = np.random.default_rng(5).normal(0, 0.1, (len(ns), J))
+    b = B.rhs(B.project_sine(modes, amps))
+    out = torch.full((B.total,), float("nan"), dtype=torch.float64, device=dev)
+    x_z, inf_z, st_z = B.solve(b, restart=restart, tol=1e-8, maxit=300, out=out)
+    x_e, inf_e, st_e = B.solve(b, restart=restart, tol=1e-8, maxit=300, x0=B.zeros())
+    torch.cuda.synchronize()
+    print(f"zero guess restart {restart}: iterations {[i['iters'] for i in inf_z]} status {st_z}")
+    assert st_z == st_e
+    if restart == 30:
+        assert st_z == 0
+    # (the alignment padding between members belongs to no problem: compare the views)
+    for vz, ve in zip(B.views(x_z), B.views(x_e)):
+        assert bool((vz == ve).all())
+    assert [i["iters"] for i in inf_z] == [i["iters"] for i in inf_e]
+    out.fill_(float("nan"))
+    x0, inf0, st0 = B.solve(B.zeros(), restart=restart, tol=1e-8, maxit=300, out=out)
+    assert st0 == 0 and all(bool((v == 0).all()) for v in B.views(x0))
+
+
+def test_batch_transpose_solve(dev, orc):
+    """transpose=True solves A_p^T x_p = b_p to the 1e-8 true residual (oracle FP64
+    transposed matvec) for every member."""
+    B, ns, ells, kappas = make(dev, "fp64")
+    gs = [np.random.default_rng([i, 7]).standard_normal((l, n)) for i, (n, l) in enumerate(zip(ns, ells))]
+    x, infos, st = B.solve(B.pack(gs), restart=30, tol=1e-8, maxit=300, transpose=True)
+    assert st == 0
+    for i, (xv, g) in enumerate(zip(B.views(x), gs)):
+        X = xv.cpu().numpy()
+        res = np.linalg.norm(g - orc.apply_A(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i], X,
+                                             transpose=True)) / np.linalg.norm(g)
+        print(f"batch transpose n={ns[i]} ell={ells[i]}: iters {infos[i]['iters']} res {res:.2e}")
+        assert infos[i]["converged"] and res <= 1e-8
+
+
 def test_batch_workload_64(dev, orc):
     """The 64-problem batch (n in U{255..4095}, ell in U{256..2048}, kappa in U[0.5, 2],
     20-mode u0): single-precision transforms, FP64 outer FGMRES(30) to 1e-8, every member
