@@ -279,8 +279,9 @@ aao_status aao_batch_apply_Pinv(aao_batch b, const double *r, double *z, int tra
 aao_status aao_batch_gmres(aao_batch b, const double *bvec, double *x, int restart, double tol,
                            int maxit, aao_info *infos);
 /* aao_batch_gmres with flags (the AAO_GMRES_* bits of aao_gmres_ex):
- * AAO_GMRES_ZERO_GUESS -- x0 = 0 for every problem whatever x holds (x is only
- * written; the first cycle starts from b itself, with no residual matvec);
+ * AAO_GMRES_ZERO_GUESS -- x0 = 0 for every problem whatever x holds (the members'
+ * ranges of x are only written, the alignment padding between them not at all; the
+ * first cycle starts from b itself, with no residual matvec);
  * AAO_GMRES_TRANSPOSE -- solve A_p^T x_p = b_p with C_p^{-T}.  Unknown bits:
  * AAO_ERR_ARG. */
 aao_status aao_batch_gmres_ex(aao_batch b, const double *bvec, double *x, int restart,

@@ -380,7 +380,8 @@ class Batch:
 
     def solve(self, b, restart=30, tol=1e-8, maxit=300, x0=None, out=None, transpose=False):
         """FGMRES on every problem; x0=None starts from zero (no residual matvec in
-        the first cycle); transpose=True solves A_p^T x_p = b_p."""
+        the first cycle; the alignment padding between members of the result is then
+        left unwritten); transpose=True solves A_p^T x_p = b_p."""
         x = out if out is not None else self.empty()
         flags = GMRES_TRANSPOSE if transpose else 0
         if x0 is None:

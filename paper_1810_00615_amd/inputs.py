@@ -62,6 +62,20 @@ def perturbed_steps(ell, delta, seed):
     return np.diff(t)
 
 
+def paper_initial_data(name, n):
+    """Nodal values at x_i = i/(n+1), i = 1..n, of the paper's initial functions
+    (Sec. 4): "x(1-x)" (u_0^{s1}), "sin2pix" (u_0^{s2}) and "bump", the non-smooth
+    u_0^{ns} = cos^2(4 pi (x - 1/2)) on (3/8, 5/8) and 0 elsewhere."""
+    x = np.arange(1, n + 1) / (n + 1)
+    if name == "x(1-x)":
+        return x * (1 - x)
+    if name == "sin2pix":
+        return np.sin(2 * np.pi * x)
+    if name == "bump":
+        return np.where((x > 3 / 8) & (x < 5 / 8), np.cos(4 * np.pi * (x - 0.5)) ** 2, 0.0)
+    raise ValueError(name)
+
+
 def heat_small(n=63, ell=64):
     """Heat, n = 63, ell = 64, tau = 1/64: sin(pi x) plus a 10-mode N(0, 0.1^2)
     series; GMRES(50), tol 1e-10."""

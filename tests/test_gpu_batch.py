@@ -68,7 +68,10 @@ def test_batch_gmres_small(dev, orc, prec):
     B.set_graph(False)
     x_e, infos_e, st_e = B.solve(b, restart=30, tol=1e-8, maxit=300)
     assert st == 0 and st_e == 0
-    assert bool((x_g == x_e).all())
+    # (x0 = 0 by the zero-guess entry: the alignment padding between members is
+    # never written, so compare the members' views)
+    for vg, ve in zip(B.views(x_g), B.views(x_e)):
+        assert bool((vg == ve).all())
     bcpu = [v.cpu().numpy() for v in B.views(b)]
     for i, (xv, bv) in enumerate(zip(B.views(x_g), bcpu)):
         n, ell, kap = ns[i], ells[i], kappas[i]
