@@ -709,6 +709,9 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                     const double den = std::hypot(tcol[j], tcol[j + 1]);
                     const double est = den > 0.0 ? std::fabs(g[j]) * tcol[j + 1] / den / bnorm : 1.0;
                     provisional = std::isfinite(est) && est <= 0.5 * tol;
+                    if (std::getenv("AAO_LOG"))
+                        std::fprintf(stderr, "aao gmres step %d expected, column estimate %.3e%s\n",
+                                     inf.iters + 1, est, provisional ? " (update skipped)" : "");
                 }
                 if (!provisional) {
                     if (expect)   // w was not stored by the first pass
