@@ -666,11 +666,13 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             const bool first = defer_b && inf.iters == 0;
             if (ahead != j)
                 AAO_TRY(pinv_impl(ctx, Vj, ctx->svs() + j, Zj, ctx->neumann, transpose, first));
-            // convergence expected at this step (from the estimates of the last two):
-            // the step's column is then checked before the update pass, and w is not
-            // stored unless that check fails
+            // convergence expected at this step (the last two estimates extrapolated
+            // geometrically reach tol): the step's column is then checked before the
+            // update pass, and w is not stored unless that check fails.  (A looser
+            // margin fires at every step of a slowly converging tail, each false
+            // expectation costing a second matvec and a host round trip.)
             const bool expect = delayed && fused && j > 0 &&
-                                (early_always || est_prev * (est_prev / est_prev2) <= 10.0 * tol);
+                                (early_always || est_prev * (est_prev / est_prev2) <= tol);
             if (fused) {
                 AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (expect ? 1 + nv : 2 + nv),
                              launch_matvec(Zj, expect ? nullptr : ctx->W, nullptr, n, ell,
