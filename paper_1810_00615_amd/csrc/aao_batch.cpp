@@ -49,6 +49,9 @@ struct aao_batch_s {
     int m_alloc = 0;
     double *V = nullptr, *Z = nullptr, *W = nullptr;
     double **dV = nullptr, **dZ = nullptr;
+    // host sources of the pointer-table updates of a zero-guess cycle (members, so
+    // that they outlive the asynchronous copies that read them)
+    const double *first_b = nullptr, *first_v = nullptr;
     double *part = nullptr;
     int ldp = kBMaxRestart + 2;
     double *sm = nullptr;           // small per-problem arrays
@@ -255,8 +258,9 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
         if (from_b) {
             // V_0 = b: the pointer table's first entry names b for this cycle (the
             // steps read V_0 through it); dsum still holds ||b_p||^2
-            const double *bp0[1] = {bvec};
-            BH(hipMemcpyAsync(b->dV, bp0, sizeof(double *), hipMemcpyHostToDevice, b->st));
+            b->first_b = bvec;
+            BH(hipMemcpyAsync(b->dV, &b->first_b, sizeof(double *), hipMemcpyHostToDevice,
+                              b->st));
         } else {
             BH(batch_matvec(Lall, x, b->V, bvec, b->scheme, transpose, false, b->st));
             BH(batch_cgs(0, Lall, b->dV, 1, b->V, nullptr, 0, nullptr, b->part, b->ldp, false,
@@ -271,8 +275,9 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
             if (from_b) {
                 // every b_p already meets tol (or is zero): x = 0
                 BH(hipMemsetAsync(x, 0, sizeof(double) * N, b->st));
-                const double *vp0[1] = {b->V};
-                BH(hipMemcpyAsync(b->dV, vp0, sizeof(double *), hipMemcpyHostToDevice, b->st));
+                b->first_v = b->V;
+                BH(hipMemcpyAsync(b->dV, &b->first_v, sizeof(double *), hipMemcpyHostToDevice,
+                                  b->st));
             }
             break;
         }
@@ -303,8 +308,8 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
         BH(batch_backsolve(P, m, s, b->st));
         BH(batch_axpy(Lall, b->dZ, s, x, from_b, b->st));
         if (from_b) {
-            const double *vp0[1] = {b->V};
-            BH(hipMemcpyAsync(b->dV, vp0, sizeof(double *), hipMemcpyHostToDevice, b->st));
+            b->first_v = b->V;
+            BH(hipMemcpyAsync(b->dV, &b->first_v, sizeof(double *), hipMemcpyHostToDevice, b->st));
         }
         ++cycles;
     }

@@ -477,12 +477,15 @@ k_batch_cgs(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int
         double cf[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) cf[i] = (MODE > 0 && i < nv) ? coef[(size_t)e.x * cst + i] : 0.0;
+        // a norm (the only vector is w itself) reads w once
+        const bool self = MODE == 0 && nv == 1 && V[0] == w;
         for (int q = threadIdx.x; q < e.z; q += blockDim.x) {
             const size_t o = base + q;
             double s = w[o];
             double vv[NV];
 #pragma unroll
-            for (int i = 0; i < NV; ++i) vv[i] = (i < nv) ? V[i][o] : 0.0;
+            for (int i = 0; i < NV; ++i) vv[i] = (i < nv && !(i == 0 && self)) ? V[i][o] : 0.0;
+            if (self) vv[0] = s;
             if (MODE == 0) {
 #pragma unroll
                 for (int i = 0; i < NV; ++i) acc[i] += vv[i] * s;
