@@ -16,6 +16,7 @@
 
 #include "batch.h"
 #include "fft_core.h"
+#include "lanes.h"
 #include "solve_core.h"
 
 namespace aao {
@@ -392,7 +393,10 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
 }
 
 // ------------------------------------------------------------------ matvec
-// y = A x (or bsub - A x) per problem, tiles of 256 columns x 16 time levels.
+// y = A x (or bsub - A x) per problem, tiles of 256 columns x 16 time levels.  A
+// thread loads its own column of each input row once; the i -+ 1 neighbours come
+// from the adjacent lanes (DPP wave shift), and lanes 0 and 63 load the one
+// neighbour outside their wave.  Threads past n stay for the lane moves (with 0).
 __global__ void __launch_bounds__(256)
 k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, int ntiles,
                const unsigned char *__restrict__ active, const double *__restrict__ x,
@@ -405,8 +409,11 @@ k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, 
     if (active && !active[e.x]) return;
     const BProb pb = probs[e.x];
     const int n = pb.n, ell = pb.ell;
+    const int lane = threadIdx.x & 63;
     const int i = e.y * 256 + threadIdx.x;
-    if (i >= n) return;
+    const bool col = i < n;
+    const int je = lane == 0 ? i - 1 : i + 1;        // outside neighbour of lanes 0 / 63
+    const bool edge = (lane == 0 || lane == 63) && je >= 0 && je < n;
     const int s = scheme == 1 ? 2 : 1;
     double am[3], bm[3];
     if (scheme == 1) {
@@ -427,10 +434,18 @@ k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, 
         const int kk = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
         const bool in = it < nin && kk >= 0 && kk < ell;
         const double *row = xp + (size_t)(in ? kk : 0) * n;
-        rc[it] = in ? row[i] : 0.0;
-        rl[it] = (in && i > 0) ? row[i - 1] : 0.0;
-        rr[it] = (in && i + 1 < n) ? row[i + 1] : 0.0;
+        rc[it] = (in && col) ? row[i] : 0.0;
+        rr[it] = (in && edge) ? row[je] : 0.0;      // edge value, replaced below
     }
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+        const double l = lane_from_left<true>(rc[it]);
+        const double r = lane_from_right<true>(rc[it]);
+        const double ev = rr[it];
+        rl[it] = lane == 0 ? ev : l;
+        rr[it] = lane == 63 ? ev : r;
+    }
+    if (!col) return;
 #pragma unroll
     for (int it = 0; it < NR; ++it) {
         if (it < s || it >= nin) continue;

@@ -8,6 +8,7 @@
 // partials are summed in a fixed order (k_reduce_parts, k_reduce_small).  No
 // floating-point atomics.
 #include "aao_internal.h"
+#include "lanes.h"
 
 namespace aao {
 
@@ -376,31 +377,6 @@ hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double 
 // kernel also leaves the block partials of V_q . y, q < nv (value-major, block id
 // y * gridDim.x + x): the first Gram-Schmidt pass, or with nv = 1 and V_0 = y the
 // squared norm of a residual (from registers).
-template <bool DPP>
-__device__ __forceinline__ double lane_from_left(double v)
-{
-    if constexpr (DPP) {
-        // wave_shr:1 -- lane j receives lane j-1
-        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
-        return __hiloint2double(hi, lo);
-    } else {
-        return __shfl_up(v, 1, 64);
-    }
-}
-template <bool DPP>
-__device__ __forceinline__ double lane_from_right(double v)
-{
-    if constexpr (DPP) {
-        // wave_shl:1 -- lane j receives lane j+1
-        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
-        return __hiloint2double(hi, lo);
-    } else {
-        return __shfl_down(v, 1, 64);
-    }
-}
-
 // DOTS: 0 none, 1 partials of V_q . y (q < nv), 2 the partial of y . y only
 template <int S, int R, bool DPP, int DOTS, int NZ = 0>
 __global__ void __launch_bounds__(256)
