@@ -45,13 +45,16 @@ template <typename T> __device__ __forceinline__ cx<T> cvt(cx<double> a) { retur
 
 // The second transform of a Bluestein tile reads the same twiddle and chirp
 // entries as the first; left visible, the compiler keeps the first loads live
-// across both transforms instead of loading again, and spills.  An empty asm
-// makes the pointer opaque so the loads are repeated.
+// across both transforms instead of loading again, and spills.  Offsetting the
+// pointer by a zero the compiler cannot see through makes the loads repeat (an
+// opaque offset rather than an opaque pointer, so that the global address space of
+// the pointer is still known and the loads stay global loads, not flat ones).
 template <typename P>
 __device__ __forceinline__ P *fresh(P *p)
 {
-    asm volatile("" : "+s"(p));
-    return p;
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return p + z;
 }
 
 // Copy rows 0..ell-1, columns [cbase, cbase + C2) of a row-major ell x n array
