@@ -44,6 +44,23 @@ def test_batch_pinv(dev, orc, prec, tol):
         assert e < tol
 
 
+LARGE = [(4095, 2048), (33, 1025), (700, 1531), (1, 1100)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 2e-6)])
+def test_batch_pinv_long(dev, orc, prec, tol):
+    """Bluestein lengths M = 4096 (ell 1025..2048): one column pair per workgroup,
+    ragged last tiles (odd n, n = 1), the largest n."""
+    B, ns, ells, kappas = make(dev, prec, sizes=LARGE, kap_seed=4)
+    rs = [np.random.default_rng([i, 9]).standard_normal((l, n)) for i, (n, l) in enumerate(zip(ns, ells))]
+    z = B.Pinv(B.pack(rs))
+    for i, (zv, r) in enumerate(zip(B.views(z), rs)):
+        ref = orc.pinv(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i], r)
+        e = normrel(zv.cpu().numpy(), ref)
+        print(f"batch pinv {prec} n={ns[i]} ell={ells[i]}: {e:.2e}")
+        assert e < tol
+
+
 def test_batch_matvec(dev, orc):
     B, ns, ells, kappas = make(dev, "mixed")
     xs = [np.random.default_rng([i, 2]).standard_normal((l, n)) for i, (n, l) in enumerate(zip(ns, ells))]
