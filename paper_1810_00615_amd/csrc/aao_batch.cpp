@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -18,6 +19,7 @@
 
 #include "../../include/aao.h"
 #include "aao_internal.h"
+
 #include "batch.h"
 
 using namespace aao;
@@ -196,6 +198,14 @@ static aao_status b_step(aao_batch b, int j, int m, double tol, int transpose,
     return AAO_OK;
 }
 
+// true if two batch vectors (Ntot doubles each) share memory
+static bool b_overlap(const aao_batch b, const void *p, const void *q)
+{
+    const auto a = reinterpret_cast<uintptr_t>(p), c = reinterpret_cast<uintptr_t>(q);
+    const uintptr_t bytes = sizeof(double) * b->Ntot;
+    return a < c + bytes && c < a + bytes;
+}
+
 // zero: x0 = 0 whatever x holds (x is only written).  The first cycle then takes
 // b itself as its first basis vector: no residual matvec and no norm pass (||b||
 // is already known), and the solution update overwrites x.
@@ -208,6 +218,10 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
     }
     if (!bvec || !x || !(tol >= 0.0) || maxit < 0) {
         b->err = "bad arguments";
+        return AAO_ERR_ARG;
+    }
+    if (b_overlap(b, bvec, x)) {
+        b->err = "b and x overlap";
         return AAO_ERR_ARG;
     }
     BT(ensure_ws(b, m));
@@ -525,6 +539,10 @@ aao_status aao_batch_apply_A(aao_batch b, const double *x, double *y, int transp
     if (!b) return AAO_ERR_ARG;
     if (b->broken) return AAO_ERR_HIP;
     if (!x || !y) return AAO_ERR_ARG;
+    if (b_overlap(b, x, y)) {
+        b->err = "x and y overlap";
+        return AAO_ERR_ARG;
+    }
     BH(batch_matvec(b->launch(false), x, y, nullptr, b->scheme, transpose ? 1 : 0, false, b->st));
     BH(hipStreamSynchronize(b->st));
     return AAO_OK;
@@ -535,6 +553,10 @@ aao_status aao_batch_apply_Pinv(aao_batch b, const double *r, double *z, int tra
     if (!b) return AAO_ERR_ARG;
     if (b->broken) return AAO_ERR_HIP;
     if (!r || !z) return AAO_ERR_ARG;
+    if (b_overlap(b, r, z)) {
+        b->err = "r and z overlap";
+        return AAO_ERR_ARG;
+    }
     BT(b_pinv(b, r, nullptr, 0, z, false, transpose ? 1 : 0));
     BH(hipStreamSynchronize(b->st));
     return AAO_OK;

@@ -132,6 +132,17 @@ def test_batch_zero_guess(dev, orc, restart):
     assert st0 == 0 and all(bool((v == 0).all()) for v in B.views(x0))
 
 
+def test_batch_rejects_overlap(dev):
+    """b and x sharing memory is an argument error (x is written while b is read)."""
+    from paper_1810_00615_amd._lib import AAOError
+    B, ns, ells, kappas = make(dev, "fp64")
+    b = B.rhs(B.project_sine(np.arange(1, 4), np.ones((len(ns), 3))))
+    with pytest.raises(AAOError):
+        B.solve(b, out=b)
+    with pytest.raises(AAOError):
+        B.solve(b, x0=b, out=b)
+
+
 def test_batch_transpose_solve(dev, orc):
     """transpose=True solves A_p^T x_p = b_p to the 1e-8 true residual (oracle FP64
     transposed matvec) for every member."""
