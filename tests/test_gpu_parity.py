@@ -105,7 +105,8 @@ def test_apply_A_variable_steps(aao, orc, torch_dev, transpose):
 # ------------------------------------------------- preconditioner C^{-1}
 
 PINV_SHAPES = [(1, 1), (1, 2), (3, 4), (5, 3), (7, 5), (2, 16), (31, 8), (63, 64), (17, 97),
-               (255, 256), (257, 128), (31, 1024), (4095, 16), (100, 2048), (33, 4096)]
+               (255, 256), (257, 128), (31, 1024), (4095, 16), (100, 2048), (33, 4096),
+               (33, 1531), (1000, 1100)]
 EPS = 2.0 ** -52
 
 
