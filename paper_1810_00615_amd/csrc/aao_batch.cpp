@@ -26,7 +26,6 @@ using namespace aao;
 
 namespace {
 constexpr int kBMaxRestart = 63;
-constexpr int kBSmall = 72;     // doubles per problem in the small per-problem arrays
 }
 
 struct aao_batch_s {
@@ -36,6 +35,9 @@ struct aao_batch_s {
     hipStream_t st = nullptr;
     bool own_stream = false;
     bool use_graph = true;
+    // CGS2 with deferred re-orthogonalisation (two passes per Arnoldi step) unless
+    // AAO_CGS2_CLASSIC is set (three passes)
+    bool delayed = true;
     std::string err;
     bool broken = false;
 
@@ -187,6 +189,17 @@ static aao_status b_step(aao_batch b, int j, int m, double tol, int transpose,
     BH(batch_matvec(L, Zj, b->W, nullptr, b->scheme, transpose, true, b->st));
     BH(batch_cgs(0, L, b->dV, nv, b->W, nullptr, 0, nullptr, b->part, b->ldp, true, b->st));
     BH(batch_reduce(L, b->part, b->ldp, nv, s.dsum, s.sst, true, b->st));
+    if (b->delayed) {
+        // CGS2 with the re-orthogonalisation deferred by one step: the dots above
+        // (with the pending V_j), then one pass that writes the final v_j and the
+        // once-projected next vector and forms the dots of its re-orthogonalisation
+        BH(batch_small(4, b->count, j, m, tol, s, b->st));
+        BH(batch_cgs_delayed(L, b->dV, nv, b->W, s, Vn, b->part, b->ldp, b->st));
+        BH(batch_reduce(L, b->part, b->ldp, nv + 1, s.dsum, s.sst, true, b->st));
+        BH(batch_small(5, b->count, j, m, tol, s, b->st));
+        BH(batch_count_active(s.active, b->count, b->iv + 2 * b->count, b->st));
+        return AAO_OK;
+    }
     BH(batch_small(0, b->count, j, m, tol, s, b->st));
     BH(batch_cgs(1, L, b->dV, nv, b->W, s.coef, s.sst, nullptr, b->part, b->ldp, true, b->st));
     BH(batch_reduce(L, b->part, b->ldp, nv, s.dsum, s.sst, true, b->st));
@@ -482,6 +495,7 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             break;
         }
         if (const char *g = std::getenv("AAO_BATCH_GRAPH")) b->use_graph = std::atoi(g) != 0;
+        b->delayed = std::getenv("AAO_CGS2_CLASSIC") == nullptr;
     } while (0);
     if (s != AAO_OK) {
         aao_batch_destroy(b);

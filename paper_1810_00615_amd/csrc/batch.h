@@ -43,6 +43,7 @@ struct BatchLaunch {
 };
 
 constexpr int kBatchSlab = 65536;       // elements per Gram-Schmidt / update slab
+constexpr int kBSmall = 72;             // doubles per problem in the small per-problem arrays
 // Bluestein transforms: points per thread of the length-M FFTs and threads per
 // workgroup; a workgroup transforms kBluesteinThreads P / M column pairs
 constexpr int kBluesteinP = 8;
@@ -63,6 +64,12 @@ hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const 
 hipError_t batch_cgs(int mode, const BatchLaunch &L, const double *const *V, int nv,
                      const double *w, const double *coef, int cst, double *out, double *part,
                      int ldp, bool masked, hipStream_t st);
+// The deferred-re-orthogonalisation update of step nv - 1 (coefficients from
+// batch_small mode 4): v_j written over the pending vector (j > 0), w1 to out,
+// partials V_i . w1, v_j . w1, w1 . w1 (nv + 1 slots)
+hipError_t batch_cgs_delayed(const BatchLaunch &L, const double *const *V, int nv,
+                             const double *w, const BState &s, double *out, double *part, int ldp,
+                             hipStream_t st);
 hipError_t batch_reduce(const BatchLaunch &L, const double *part, int ldp, int cnt, double *sums,
                         int sst, bool masked, hipStream_t st);
 hipError_t batch_small(int mode, int count, int j, int m, double tol, const BState &s,

@@ -475,12 +475,22 @@ k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, 
 // vectors with w; MODE 1: w' = w - sum V_i c_i, dots with w'; MODE 2:
 // w'' = w - sum V_i c_i written to out, and ||w''||^2.  Coefficients c are per
 // problem (c[p * cst + i]).  Partials: part[slab * ldp + slot].
+//
+// MODE 3 (CGS2 with the re-orthogonalisation deferred by one step): V_0..V_{j-1}
+// hold the final basis (V_0 with its scale folded into the coefficients), V_j the
+// pending vector p_j (j = nv - 1).  Per element, v_j = s p_j - sum_{i<j} a_i V_i
+// (s = coef[kBC - 2], a_i = coef2[i]) is written over p_j when j > 0, and
+// w1 = w - sum_{i<j} c_i V_i - h_j v_j (c_i = coef[i], h_j = coef[kBC - 1]) to out;
+// the partials are V_i . w1 (slots i < j), v_j . w1 (slot j) and w1 . w1 (slot nv).
+constexpr int kBC = kBSmall;   // coefficients per problem (the small arrays' stride)
+
 template <int MODE, int NV>
 __global__ void __launch_bounds__(256)
 k_batch_cgs(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int nslabs,
             const unsigned char *__restrict__ active, const double *const *__restrict__ V, int nv,
             const double *__restrict__ w, const double *__restrict__ coef, int cst,
-            double *__restrict__ out, double *__restrict__ part, int ldp)
+            double *__restrict__ out, double *__restrict__ part, int ldp,
+            const double *__restrict__ coef2 = nullptr)
 {
     __shared__ double red[(NV + 1) * 4];
     const int g = blockIdx.x;
@@ -492,9 +502,18 @@ k_batch_cgs(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int
     for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
     if (act) {
         const size_t base = probs[e.x].off + (size_t)e.y;
-        double cf[NV];
+        const int j = nv - 1;
+        double cf[NV], ca[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) cf[i] = (MODE > 0 && i < nv) ? coef[(size_t)e.x * cst + i] : 0.0;
+        for (int i = 0; i < NV; ++i) {
+            const bool use = MODE == 3 ? i < j : (MODE > 0 && i < nv);
+            cf[i] = use ? coef[(size_t)e.x * cst + i] : 0.0;
+            ca[i] = (MODE == 3 && i < j) ? coef2[(size_t)e.x * cst + i] : 0.0;
+        }
+        const double sp = MODE == 3 ? coef[(size_t)e.x * cst + kBC - 2] : 0.0;
+        const double hj = MODE == 3 ? coef[(size_t)e.x * cst + kBC - 1] : 0.0;
+        // the pending vector is workspace storage when j > 0 (V_0 may be the caller's b)
+        double *pj = (MODE == 3 && j > 0) ? const_cast<double *>(V[j]) : nullptr;
         // a norm (the only vector is w itself) reads w once
         const bool self = MODE == 0 && nv == 1 && V[0] == w;
         for (int q = threadIdx.x; q < e.z; q += blockDim.x) {
@@ -504,7 +523,22 @@ k_batch_cgs(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int
 #pragma unroll
             for (int i = 0; i < NV; ++i) vv[i] = (i < nv && !(i == 0 && self)) ? V[i][o] : 0.0;
             if (self) vv[0] = s;
-            if (MODE == 0) {
+            if (MODE == 3) {
+                double vj = 0.0;
+#pragma unroll
+                for (int i = 0; i < NV; ++i)
+                    if (i == j) vj = sp * vv[i];
+#pragma unroll
+                for (int i = 0; i < NV; ++i) vj -= ca[i] * vv[i];
+#pragma unroll
+                for (int i = 0; i < NV; ++i) s -= cf[i] * vv[i];
+                s -= hj * vj;
+                if (pj) pj[o] = vj;
+                out[o] = s;
+#pragma unroll
+                for (int i = 0; i < NV; ++i) acc[i] += (i < j ? vv[i] : (i == j ? vj : 0.0)) * s;
+                acc[NV] += s * s;
+            } else if (MODE == 0) {
 #pragma unroll
                 for (int i = 0; i < NV; ++i) acc[i] += vv[i] * s;
             } else {
@@ -523,7 +557,7 @@ k_batch_cgs(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i <= NV; ++i) {
-        const bool used = (i < NV) ? (MODE != 2 && i < nv) : (MODE == 2);
+        const bool used = (i < NV) ? (MODE != 2 && i < nv) : (MODE >= 2);
         if (used) {
             double v = acc[i];
 #pragma unroll
@@ -533,10 +567,10 @@ k_batch_cgs(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= NV; i += blockDim.x) {
-        const bool used = (i < NV) ? (MODE != 2 && i < nv) : (MODE == 2);
+        const bool used = (i < NV) ? (MODE != 2 && i < nv) : (MODE >= 2);
         if (!used) continue;
         const double sum = red[i * 4] + red[i * 4 + 1] + red[i * 4 + 2] + red[i * 4 + 3];
-        part[(size_t)g * ldp + (i < NV ? i : 0)] = sum;
+        part[(size_t)g * ldp + (i < NV ? i : (MODE == 3 ? nv : 0))] = sum;
     }
 }
 
@@ -613,6 +647,65 @@ __global__ void k_batch_small(int mode, int count, int j, int m, double tol, BSt
         st.est[p] = est;
         if (!ok || !(est > tol) || st.iters[p] >= st.maxit) st.active[p] = 0;
         if (!ok || !isfinite(est)) st.bad[p] = 1;
+    } else if (mode == 4 || mode == 5) {
+        // CGS2 with the re-orthogonalisation deferred by one step.  h2[0..j-1] and
+        // h2[kBC-1] hold the coefficients a_i and alpha of the pending p_j (unit after
+        // the scale vs[j]): p_j vs_j = sum_{i<j} a_i v_i + alpha v_j.
+        double *H = st.H + (size_t)p * st.hst;          // column-major (m+1) x m
+        double *hc = H + (size_t)j * (m + 1);
+        double *a = h2;
+        if (mode == 4) {
+            // d_i = V_i . w (i < j: final basis, v_i = vs_i V_i), d_j = p_j . w
+            const double alpha = j > 0 ? a[kBC - 1] : 1.0;
+            double hj = vs[j] * d[j];
+            for (int i = 0; i < j; ++i) {
+                hc[i] = vs[i] * d[i];
+                hj -= a[i] * hc[i];
+                c[i] = hc[i] * vs[i];                    // w1 coefficients on V_i
+                h1[i] = a[i] * vs[i] / alpha;            // v_j = (vs_j p_j - sum a_i v_i) / alpha
+            }
+            hj /= alpha;
+            hc[j] = hj;
+            c[kBC - 2] = vs[j] / alpha;
+            c[kBC - 1] = hj;
+        } else {
+            // d_i = V_i . w1 (i < j), d_j = v_j . w1, d_nv = w1 . w1
+            const double nrm = sqrt(fmax(d[nv], 0.0));
+            const double sn1 = nrm > 0.0 ? 1.0 / nrm : 0.0;
+            double aa = 0.0;
+            for (int i = 0; i <= j; ++i) {
+                const double ai = (i < j ? vs[i] : 1.0) * d[i] * sn1;
+                a[i] = ai;
+                aa += ai * ai;
+                hc[i] += nrm * ai;
+            }
+            const double alpha = sqrt(fmax(1.0 - aa, 0.0));
+            a[kBC - 1] = alpha;
+            hc[nv] = nrm * alpha;
+            if (j > 0) vs[j] = 1.0;                      // v_j now stored normalised
+            vs[nv] = sn1;                                // scale of the pending p_{j+1}
+            double *cs = st.cs + (size_t)p * st.sst, *sn = st.sn + (size_t)p * st.sst;
+            double *gg = st.g + (size_t)p * st.sst;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * hc[i] + sn[i] * hc[i + 1];
+                hc[i + 1] = -sn[i] * hc[i] + cs[i] * hc[i + 1];
+                hc[i] = t;
+            }
+            const double den = hypot(hc[j], hc[j + 1]);
+            const bool ok = den > 0.0 && isfinite(den);
+            cs[j] = ok ? hc[j] / den : 1.0;
+            sn[j] = ok ? hc[j + 1] / den : 0.0;
+            hc[j] = ok ? den : hc[j];
+            hc[j + 1] = 0.0;
+            gg[j + 1] = -sn[j] * gg[j];
+            gg[j] = cs[j] * gg[j];
+            st.iters[p] += 1;
+            st.ksteps[p] = nv;
+            const double est = fabs(gg[j + 1]) / st.bnorm[p];
+            st.est[p] = est;
+            if (!ok || !(est > tol) || st.iters[p] >= st.maxit) st.active[p] = 0;
+            if (!ok || !isfinite(est)) st.bad[p] = 1;
+        }
     } else {
         const double beta = sqrt(fmax(d[0], 0.0));
         vs[0] = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -859,13 +952,13 @@ hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const 
 template <int MODE>
 static hipError_t cgs_b(const BatchLaunch &L, const double *const *V, int nv, const double *w,
                         const double *coef, int cst, double *out, double *part, int ldp,
-                        bool masked, hipStream_t st)
+                        bool masked, hipStream_t st, const double *coef2 = nullptr)
 {
     const unsigned char *act = masked ? L.active : nullptr;
 #define AAO_BNV(K)                                                                          \
     if (nv <= K) {                                                                          \
         k_batch_cgs<MODE, K><<<L.nslabs, 256, 0, st>>>(L.probs, L.slabs, L.nslabs, act, V, nv, w, \
-                                                      coef, cst, out, part, ldp);           \
+                                                      coef, cst, out, part, ldp, coef2);    \
         return hipGetLastError();                                                           \
     }
     AAO_BNV(1) AAO_BNV(4) AAO_BNV(8) AAO_BNV(16) AAO_BNV(32) AAO_BNV(64)
@@ -880,6 +973,13 @@ hipError_t batch_cgs(int mode, const BatchLaunch &L, const double *const *V, int
     if (mode == 0) return cgs_b<0>(L, V, nv, w, coef, cst, out, part, ldp, masked, st);
     if (mode == 1) return cgs_b<1>(L, V, nv, w, coef, cst, out, part, ldp, masked, st);
     return cgs_b<2>(L, V, nv, w, coef, cst, out, part, ldp, masked, st);
+}
+
+hipError_t batch_cgs_delayed(const BatchLaunch &L, const double *const *V, int nv,
+                             const double *w, const BState &s, double *out, double *part, int ldp,
+                             hipStream_t st)
+{
+    return cgs_b<3>(L, V, nv, w, s.coef, s.sst, out, part, ldp, true, st, s.h1);
 }
 
 hipError_t batch_reduce(const BatchLaunch &L, const double *part, int ldp, int cnt, double *sums,

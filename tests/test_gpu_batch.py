@@ -132,6 +132,83 @@ def test_batch_zero_guess(dev, orc, restart):
     assert st0 == 0 and all(bool((v == 0).all()) for v in B.views(x0))
 
 
+@pytest.mark.parametrize("restart", [30, 2])
+def test_batch_delayed_matches_classic(dev, orc, restart, monkeypatch):
+    """CGS2 with the re-orthogonalisation deferred by one step (two passes per step)
+    against the three-pass form (AAO_CGS2_CLASSIC): the same iteration counts and the
+    same solutions to rounding, with and without restarts; both meet the 1e-8 true
+    residual (oracle FP64 matvec)."""
+    import torch
+    J = 20
+    modes = np.arange(1, J + 1)
+    amps = np.random.default_rng(6).normal(0, 0.1, (len(SMALL), J))
+    out = {}
+    for name, classic in (("delayed", False), ("classic", True)):
+        if classic:
+            monkeypatch.setenv("AAO_CGS2_CLASSIC", "1")
+        else:
+            monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
+        B, ns, ells, kappas = make(dev, "fp64")
+        b = B.rhs(B.project_sine(modes, amps))
+        x, infos, st = B.solve(b, restart=restart, tol=1e-8, maxit=300)
+        torch.cuda.synchronize()
+        assert st == 0
+        out[name] = ([v.cpu().numpy() for v in B.views(x)], [i["iters"] for i in infos],
+                     [v.cpu().numpy() for v in B.views(b)])
+        B.close()
+    monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
+    xd, itd, bd = out["delayed"]
+    xc, itc, _ = out["classic"]
+    print(f"restart {restart}: iterations delayed {itd} classic {itc}")
+    for i, (a, c, bv) in enumerate(zip(xd, xc, bd)):
+        res = np.linalg.norm(bv - orc.apply_A(HEAT, SMALL[i][0], SMALL[i][1], 1.0 / SMALL[i][1],
+                                              make_kappas()[i], a)) / np.linalg.norm(bv)
+        assert res <= 1e-8, (i, res)
+        assert abs(itd[i] - itc[i]) <= 1
+        if itd[i] == itc[i]:
+            assert normrel(a, c) < 1e-10
+
+
+@pytest.mark.parametrize("restart", [8, 30])
+def test_batch_delayed_bd2_long(dev, orc, restart, monkeypatch):
+    """Many Arnoldi steps and restarts (wave BD2, 20-mode data): the deferred and the
+    three-pass CGS2 both reach the 1e-8 true residual (oracle FP64 BD2 matvec) with
+    iteration counts within two of each other."""
+    import torch
+    from paper_1810_00615_amd import Batch
+    sizes = [(63, 64), (127, 256), (31, 100)]
+    ns = [a for a, _ in sizes]
+    ells = [c for _, c in sizes]
+    modes = np.arange(1, 21)
+    amps = np.random.default_rng(8).normal(0, 0.1, (len(sizes), 20))
+    its = {}
+    for name, classic in (("delayed", False), ("classic", True)):
+        if classic:
+            monkeypatch.setenv("AAO_CGS2_CLASSIC", "1")
+        else:
+            monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
+        B = Batch(ns, ells, [1.0] * len(sizes), scheme="bd2", precision="fp64", device=dev)
+        b = B.rhs(B.project_sine(modes, amps))
+        x, infos, st = B.solve(b, restart=restart, tol=1e-8, maxit=400)
+        torch.cuda.synchronize()
+        assert st == 0
+        for i, (xv, bv) in enumerate(zip(B.views(x), B.views(b))):
+            X, bb = xv.cpu().numpy(), bv.cpu().numpy()
+            res = np.linalg.norm(bb - orc.apply_A(1, ns[i], ells[i], 1.0 / ells[i], 1.0, X)) \
+                / np.linalg.norm(bb)
+            assert res <= 1e-8, (name, i, res)
+        its[name] = [i["iters"] for i in infos]
+        B.close()
+    monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
+    print(f"BD2 restart {restart}: iterations delayed {its['delayed']} classic {its['classic']}")
+    for a, c in zip(its["delayed"], its["classic"]):
+        assert abs(a - c) <= 2
+
+
+def make_kappas(kap_seed=0):
+    return np.random.default_rng(kap_seed).uniform(0.5, 2.0, len(SMALL))
+
+
 def test_batch_rejects_overlap(dev):
     """b and x sharing memory is an argument error (x is written while b is read)."""
     from paper_1810_00615_amd._lib import AAOError
