@@ -34,12 +34,12 @@ KERNEL_SOURCES = {
     "fft_inv": ["paper_1810_00615_amd/csrc/k_fft.hip", "paper_1810_00615_amd/csrc/fft_core.h"],
     "shifted_solve": ["paper_1810_00615_amd/csrc/k_solve.hip",
                       "paper_1810_00615_amd/csrc/solve_core.h"],
-    "matvec": ["paper_1810_00615_amd/csrc/k_vec.hip"],
-    "cgs_dot": ["paper_1810_00615_amd/csrc/k_vec.hip"],
-    "cgs_update_dot": ["paper_1810_00615_amd/csrc/k_vec.hip"],
-    "cgs_update_norm": ["paper_1810_00615_amd/csrc/k_vec.hip"],
-    "axpy": ["paper_1810_00615_amd/csrc/k_vec.hip"],
-    "arnoldi_update": ["paper_1810_00615_amd/csrc/k_vec.hip"],
+    "matvec": ["paper_1810_00615_amd/csrc/k_vec.hip", "paper_1810_00615_amd/csrc/lanes.h"],
+    "cgs_dot": ["paper_1810_00615_amd/csrc/k_vec.hip", "paper_1810_00615_amd/csrc/lanes.h"],
+    "cgs_update_dot": ["paper_1810_00615_amd/csrc/k_vec.hip", "paper_1810_00615_amd/csrc/lanes.h"],
+    "cgs_update_norm": ["paper_1810_00615_amd/csrc/k_vec.hip", "paper_1810_00615_amd/csrc/lanes.h"],
+    "axpy": ["paper_1810_00615_amd/csrc/k_vec.hip", "paper_1810_00615_amd/csrc/lanes.h"],
+    "arnoldi_update": ["paper_1810_00615_amd/csrc/k_vec.hip", "paper_1810_00615_amd/csrc/lanes.h"],
 }
 
 
