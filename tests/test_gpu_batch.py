@@ -132,7 +132,7 @@ def test_batch_zero_guess(dev, orc, restart):
     assert st0 == 0 and all(bool((v == 0).all()) for v in B.views(x0))
 
 
-@pytest.mark.parametrize("restart", [30, 2])
+@pytest.mark.parametrize("restart", [30, 2, 1])
 def test_batch_delayed_matches_classic(dev, orc, restart, monkeypatch):
     """CGS2 with the re-orthogonalisation deferred by one step (two passes per step)
     against the three-pass form (AAO_CGS2_CLASSIC): the same iteration counts and the
