@@ -45,6 +45,7 @@ struct aao_batch_s {
     int2 *ftiles = nullptr, *rows = nullptr, *pslabs = nullptr;
     int4 *mtiles = nullptr, *slabs = nullptr;
     int nftiles = 0, nrows = 0, nmtiles = 0, nslabs = 0;
+    int row_start[5] = {};
     double *chirp = nullptr, *bhat = nullptr, *tw = nullptr;
     void *spec = nullptr;
     int *fail = nullptr;
@@ -77,6 +78,7 @@ struct aao_batch_s {
         L.nftiles = nftiles;
         L.rows = rows;
         L.nrows = nrows;
+        for (int c = 0; c < 5; ++c) L.row_start[c] = row_start[c];
         L.mtiles = mtiles;
         L.nmtiles = nmtiles;
         L.slabs = slabs;
@@ -399,6 +401,7 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
     aao_status s = AAO_OK;
     do {
         std::vector<int2> ft, rw, ps;
+        std::vector<int2> rwc[kSolveClasses];   // spectrum rows by class of n
         std::vector<int4> mt, sl;
         size_t off = 0, soff = 0, coff = 0, boff = 0;
         int max_ell = 0, max_M = 0;
@@ -427,7 +430,7 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             const int Wp = bluestein_pairs(M);                 // column pairs per transform tile
             const int ntile = (q.n + 2 * Wp - 1) / (2 * Wp);
             for (int t = 0; t < ntile; ++t) ft.push_back({p, t});
-            for (int j = 0; j <= q.ell / 2; ++j) rw.push_back({p, j});
+            for (int j = 0; j <= q.ell / 2; ++j) rwc[solve_class(q.n)].push_back({p, j});
             for (int by = 0; by < (q.ell + 15) / 16; ++by)
                 for (int bx = 0; bx < (q.n + 255) / 256; ++bx) mt.push_back({p, bx, by, 0});
             const int first = (int)sl.size();
@@ -438,6 +441,11 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
         b->Ntot = off;
         b->Stot = soff;
         b->nftiles = (int)ft.size();
+        b->row_start[0] = 0;
+        for (int c = 0; c < kSolveClasses; ++c) {
+            rw.insert(rw.end(), rwc[c].begin(), rwc[c].end());
+            b->row_start[c + 1] = (int)rw.size();
+        }
         b->nrows = (int)rw.size();
         b->nmtiles = (int)mt.size();
         b->nslabs = (int)sl.size();

@@ -34,7 +34,8 @@ struct BatchLaunch {
     const BProb *probs;
     int count;
     const int2 *ftiles;  int nftiles;   // transform tiles (problem, tile)
-    const int2 *rows;    int nrows;     // spectrum rows (problem, frequency)
+    const int2 *rows;    int nrows;     // spectrum rows (problem, frequency), by class of n
+    int row_start[5];                   // rows of class c: [row_start[c], row_start[c + 1])
     const int4 *mtiles;  int nmtiles;   // matvec tiles (problem, column block, row block, -)
     const int4 *slabs;   int nslabs;    // element slabs (problem, first, count, -)
     const int2 *pslabs;                 // slab range [x, y) of every problem
@@ -44,6 +45,10 @@ struct BatchLaunch {
 
 constexpr int kBatchSlab = 65536;       // elements per Gram-Schmidt / update slab
 constexpr int kBSmall = 72;             // doubles per problem in the small per-problem arrays
+// shifted solves: class c = 0..3 of a problem holds n <= 8 * (64 << c) (workgroups of
+// 64 << c threads, 8 unknowns per thread)
+constexpr int kSolveClasses = 4;
+constexpr int solve_class(int n) { return n <= 512 ? 0 : n <= 1024 ? 1 : n <= 2048 ? 2 : 3; }
 // Bluestein transforms: points per thread of the length-M FFTs and threads per
 // workgroup; a workgroup transforms kBluesteinThreads P / M column pairs
 constexpr int kBluesteinP = 8;

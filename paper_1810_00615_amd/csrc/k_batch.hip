@@ -847,9 +847,9 @@ static size_t bl_smem(size_t realsz)
     return best;
 }
 
-static size_t solve_smem(size_t es, size_t as)
+static size_t solve_smem(size_t es, size_t as, int NT = 512)
 {
-    const int NT = 512, CW = 8;
+    const int CW = 8;
     const size_t stage = es * CW * (NT + 4), redb = as * 6 * NT;
     return as * psolve_tab_entries(CW) + (stage > redb ? stage : redb);
 }
@@ -924,21 +924,29 @@ hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool
 hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool single_arith,
                        int scheme, int transpose, int *fail, hipStream_t st)
 {
-    const int NT = 512;
-    if (!single) {
-        k_batch_solve<double, double><<<L.nrows, NT, solve_smem(16, 16), st>>>(
-            L.probs, L.rows, L.nrows, L.active, reinterpret_cast<cx<double> *>(spec), scheme,
-            transpose, fail);
-    } else if (!single_arith) {
-        k_batch_solve<double, float><<<L.nrows, NT, solve_smem(8, 16), st>>>(
-            L.probs, L.rows, L.nrows, L.active, reinterpret_cast<cx<float> *>(spec), scheme,
-            transpose, fail);
-    } else {
-        k_batch_solve<float, float><<<L.nrows, NT, solve_smem(8, 8), st>>>(
-            L.probs, L.rows, L.nrows, L.active, reinterpret_cast<cx<float> *>(spec), scheme,
-            transpose, fail);
+    // one launch per class of n: NT = 64 << c threads cover n <= 8 NT unknowns
+    for (int c = 0; c < kSolveClasses; ++c) {
+        const int first = L.row_start[c], count = L.row_start[c + 1] - first;
+        if (count <= 0) continue;
+        const int NT = 64 << c;
+        const int2 *rows = L.rows + first;
+        if (!single) {
+            k_batch_solve<double, double><<<count, NT, solve_smem(16, 16, NT), st>>>(
+                L.probs, rows, count, L.active, reinterpret_cast<cx<double> *>(spec), scheme,
+                transpose, fail);
+        } else if (!single_arith) {
+            k_batch_solve<double, float><<<count, NT, solve_smem(8, 16, NT), st>>>(
+                L.probs, rows, count, L.active, reinterpret_cast<cx<float> *>(spec), scheme,
+                transpose, fail);
+        } else {
+            k_batch_solve<float, float><<<count, NT, solve_smem(8, 8, NT), st>>>(
+                L.probs, rows, count, L.active, reinterpret_cast<cx<float> *>(spec), scheme,
+                transpose, fail);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const double *bsub,
