@@ -57,6 +57,16 @@ __device__ __forceinline__ P *fresh(P *p)
     return p + z;
 }
 
+// ell <= M/2 always (M >= 2 ell - 1): the points of the first transform at positions
+// >= M/2 are zero padding and the outputs of the second one there are never used.
+// The position offset of a held value (its position at t = 0) is a compile-time
+// constant after unrolling, so these tests let the compiler drop the zero inputs
+// from the first stage and the unused outputs from the last one.
+template <int M, int P>
+__device__ __forceinline__ bool first_is_pad(int idx) { return first_pos<M, P>(0, idx) >= M / 2; }
+template <int M, int P>
+__device__ __forceinline__ bool final_is_unused(int idx) { return final_pos<M, P>(0, idx) >= M / 2; }
+
 // Copy rows 0..ell-1, columns [cbase, cbase + C2) of a row-major ell x n array
 // to LDS (row k at xs[k * C2], columns past n read as 0), and back.  ell <= M/2
 // and C2 M = 2 NTB P, so both loops take exactly P passes of the NTB threads;
@@ -134,7 +144,7 @@ __device__ void bl_fwd_tile(const BProb &pb, int tile, const double *__restrict_
     for (int idx = 0; idx < P; ++idx) {
         const int k = first_pos<M, P>(t, idx);
         cx<T> a = {T(0), T(0)};
-        if (k < ell) {
+        if (!first_is_pad<M, P>(idx) && k < ell) {
             const double x0 = rs * xs[k * C2 + 2 * c], x1 = rs * xs[k * C2 + 2 * c + 1];
             const cx<double> ck = ch[k];
             a = cvt<T>(cx<double>{x0 * ck.x - x1 * ck.y, x0 * ck.y + x1 * ck.x});
@@ -158,7 +168,7 @@ __device__ void bl_fwd_tile(const BProb &pb, int tile, const double *__restrict_
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
         const int j = final_pos<M, P>(t, idx);
-        if (j < ell) {
+        if (!final_is_unused<M, P>(idx) && j < ell) {
             const cx<T> z = cvt<T>(ch2[j]) * v[idx];
             sm[2 * (j * W + c)] = z.x * invM;
             sm[2 * (j * W + c) + 1] = z.y * invM;
@@ -232,7 +242,7 @@ __device__ void bl_inv_tile(const BProb &pb, int tile, const cx<T> *__restrict__
     for (int idx = 0; idx < P; ++idx) {
         const int j = first_pos<M, P>(t, idx);
         cx<T> a = {T(0), T(0)};
-        if (j < ell) {
+        if (!first_is_pad<M, P>(idx) && j < ell) {
             const bool up = j > H;
             const int jr = up ? ell - j : j;
             cx<T> y1 = ys[jr * C2 + 2 * c], y2 = ys[jr * C2 + 2 * c + 1];
@@ -263,7 +273,7 @@ __device__ void bl_inv_tile(const BProb &pb, int tile, const cx<T> *__restrict__
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
         const int k = final_pos<M, P>(t, idx);
-        if (k < ell) {
+        if (!final_is_unused<M, P>(idx) && k < ell) {
             const cx<T> x = conj(cvt<T>(ch2[k])) * v[idx];
             xs[k * C2 + 2 * c] = double(x.x) * scale;
             xs[k * C2 + 2 * c + 1] = double(x.y) * scale;
