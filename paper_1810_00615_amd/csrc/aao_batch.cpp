@@ -42,7 +42,7 @@ struct aao_batch_s {
     bool broken = false;
 
     BProb *probs = nullptr;
-    int2 *ftiles = nullptr, *rows = nullptr, *pslabs = nullptr;
+    int2 *ftiles = nullptr, *rows = nullptr, *pslabs = nullptr, *mranges = nullptr;
     int4 *mtiles = nullptr, *slabs = nullptr;
     int nftiles = 0, nrows = 0, nmtiles = 0, nslabs = 0;
     int row_start[5] = {};
@@ -84,6 +84,7 @@ struct aao_batch_s {
         L.slabs = slabs;
         L.nslabs = nslabs;
         L.pslabs = pslabs;
+        L.mranges = mranges;
         L.active = masked ? flags : nullptr;
         L.chirp = chirp;
         L.bhat = bhat;
@@ -188,9 +189,17 @@ static aao_status b_step(aao_batch b, int j, int m, double tol, int transpose,
     const double *Vj = (j == 0 && v0) ? v0 : b->V + N * j;
     double *Zj = b->Z + N * j, *Vn = b->V + N * (j + 1);
     BT(b_pinv(b, Vj, s.vs + j, s.sst, Zj, true, transpose));
-    BH(batch_matvec(L, Zj, b->W, nullptr, b->scheme, transpose, true, b->st));
-    BH(batch_cgs(0, L, b->dV, nv, b->W, nullptr, 0, nullptr, b->part, b->ldp, true, b->st));
-    BH(batch_reduce(L, b->part, b->ldp, nv, s.dsum, s.sst, true, b->st));
+    if (b->delayed && nv <= 2) {
+        // the first Gram-Schmidt pass (dots of w with the basis and the pending
+        // vector) formed by the matvec itself
+        BH(batch_matvec(L, Zj, b->W, nullptr, b->scheme, transpose, true, b->st, b->dV, nv,
+                        b->part, b->ldp));
+        BH(batch_reduce(L, b->part, b->ldp, nv, s.dsum, s.sst, true, b->st, L.mranges));
+    } else {
+        BH(batch_matvec(L, Zj, b->W, nullptr, b->scheme, transpose, true, b->st));
+        BH(batch_cgs(0, L, b->dV, nv, b->W, nullptr, 0, nullptr, b->part, b->ldp, true, b->st));
+        BH(batch_reduce(L, b->part, b->ldp, nv, s.dsum, s.sst, true, b->st));
+    }
     if (b->delayed) {
         // CGS2 with the re-orthogonalisation deferred by one step: the dots above
         // (with the pending V_j), then one pass that writes the final v_j and the
@@ -400,7 +409,7 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
     b->prec = prec;
     aao_status s = AAO_OK;
     do {
-        std::vector<int2> ft, rw, ps;
+        std::vector<int2> ft, rw, ps, mr;
         std::vector<int2> rwc[kSolveClasses];   // spectrum rows by class of n
         std::vector<int4> mt, sl;
         size_t off = 0, soff = 0, coff = 0, boff = 0;
@@ -431,8 +440,10 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             const int ntile = (q.n + 2 * Wp - 1) / (2 * Wp);
             for (int t = 0; t < ntile; ++t) ft.push_back({p, t});
             for (int j = 0; j <= q.ell / 2; ++j) rwc[solve_class(q.n)].push_back({p, j});
+            const int mfirst = (int)mt.size();
             for (int by = 0; by < (q.ell + 15) / 16; ++by)
                 for (int bx = 0; bx < (q.n + 255) / 256; ++bx) mt.push_back({p, bx, by, 0});
+            mr.push_back({mfirst, (int)mt.size()});
             const int first = (int)sl.size();
             for (size_t e0 = 0; e0 < Np; e0 += kBatchSlab)
                 sl.push_back({p, (int)e0, (int)std::min<size_t>(kBatchSlab, Np - e0), 0});
@@ -455,12 +466,16 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
         if ((s = upload(b, &b->mtiles, mt)) != AAO_OK) break;
         if ((s = upload(b, &b->slabs, sl)) != AAO_OK) break;
         if ((s = upload(b, &b->pslabs, ps)) != AAO_OK) break;
+        if ((s = upload(b, &b->mranges, mr)) != AAO_OK) break;
         if ((s = balloc(b, (void **)&b->chirp, sizeof(double) * 2 * coff)) != AAO_OK) break;
         if ((s = balloc(b, (void **)&b->bhat, sizeof(double) * 2 * boff)) != AAO_OK) break;
         if ((s = balloc(b, (void **)&b->tw, sizeof(double) * 2 * 4096)) != AAO_OK) break;
         if ((s = balloc(b, &b->spec, sizeof(double) * 2 * soff)) != AAO_OK) break;
         if ((s = balloc(b, (void **)&b->fail, sizeof(int))) != AAO_OK) break;
-        if ((s = balloc(b, (void **)&b->part, sizeof(double) * b->ldp * b->nslabs)) != AAO_OK) break;
+        // block partials of the Gram-Schmidt slabs and of the matvec tiles
+        if ((s = balloc(b, (void **)&b->part,
+                        sizeof(double) * b->ldp * std::max(b->nslabs, b->nmtiles))) != AAO_OK)
+            break;
         // small per-problem arrays: 10 arrays of kBSmall doubles + 3 scalars per problem
         const size_t smn = (size_t)count * kBSmall;
         if ((s = balloc(b, (void **)&b->sm, sizeof(double) * (10 * smn + 3 * (size_t)count))) != AAO_OK) break;
@@ -524,6 +539,7 @@ aao_status aao_batch_destroy(aao_batch b)
     (void)hipFree(b->mtiles);
     (void)hipFree(b->slabs);
     (void)hipFree(b->pslabs);
+    (void)hipFree(b->mranges);
     (void)hipFree(b->chirp);
     (void)hipFree(b->bhat);
     (void)hipFree(b->tw);

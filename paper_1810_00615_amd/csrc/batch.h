@@ -39,6 +39,7 @@ struct BatchLaunch {
     const int4 *mtiles;  int nmtiles;   // matvec tiles (problem, column block, row block, -)
     const int4 *slabs;   int nslabs;    // element slabs (problem, first, count, -)
     const int2 *pslabs;                 // slab range [x, y) of every problem
+    const int2 *mranges;                // matvec tile range [x, y) of every problem
     const unsigned char *active;        // per-problem mask
     const double *chirp, *bhat, *tw;    // Bluestein tables, 4096-point twiddles
 };
@@ -64,8 +65,12 @@ hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool
                          hipStream_t st);
 hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool single_arith,
                        int scheme, int transpose, int *fail, hipStream_t st);
+// nd = 1 or 2: the tiles also leave the partials of Vd[q] . y (q < nd) at
+// part[tile * ldp + q] (reduced per problem over L.mranges)
 hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const double *bsub,
-                        int scheme, int transpose, bool masked, hipStream_t st);
+                        int scheme, int transpose, bool masked, hipStream_t st,
+                        const double *const *Vd = nullptr, int nd = 0, double *part = nullptr,
+                        int ldp = 0);
 hipError_t batch_cgs(int mode, const BatchLaunch &L, const double *const *V, int nv,
                      const double *w, const double *coef, int cst, double *out, double *part,
                      int ldp, bool masked, hipStream_t st);
@@ -75,8 +80,9 @@ hipError_t batch_cgs(int mode, const BatchLaunch &L, const double *const *V, int
 hipError_t batch_cgs_delayed(const BatchLaunch &L, const double *const *V, int nv,
                              const double *w, const BState &s, double *out, double *part, int ldp,
                              hipStream_t st);
+// ranges: per-problem block ranges of part (L.pslabs when null)
 hipError_t batch_reduce(const BatchLaunch &L, const double *part, int ldp, int cnt, double *sums,
-                        int sst, bool masked, hipStream_t st);
+                        int sst, bool masked, hipStream_t st, const int2 *ranges = nullptr);
 hipError_t batch_small(int mode, int count, int j, int m, double tol, const BState &s,
                        hipStream_t st);
 hipError_t batch_backsolve(int count, int m, const BState &s, hipStream_t st);

@@ -410,12 +410,18 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
 // thread loads its own column of each input row once; the i -+ 1 neighbours come
 // from the adjacent lanes (DPP wave shift), and lanes 0 and 63 load the one
 // neighbour outside their wave.  Threads past n stay for the lane moves (with 0).
+//
+// DOTS > 0: the tile also leaves the partials of V_q . y, q < DOTS (the first
+// Gram-Schmidt pass of an early Arnoldi step), at part[tile * ldp + q].
+template <int DOTS>
 __global__ void __launch_bounds__(256)
 k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, int ntiles,
                const unsigned char *__restrict__ active, const double *__restrict__ x,
-               double *__restrict__ y, const double *__restrict__ bsub, int scheme, int transpose)
+               double *__restrict__ y, const double *__restrict__ bsub, int scheme, int transpose,
+               const double *const *__restrict__ Vd, double *__restrict__ part, int ldp)
 {
     constexpr int RB = 16;
+    __shared__ double red[(DOTS > 0 ? DOTS : 1) * 4];
     const int g = blockIdx.x;
     if (g >= ntiles) return;
     const int4 e = tiles[g];
@@ -458,25 +464,44 @@ k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, 
         rl[it] = lane == 0 ? ev : l;
         rr[it] = lane == 63 ? ev : r;
     }
-    if (!col) return;
+    if (DOTS == 0 && !col) return;
+    double acc[DOTS > 0 ? DOTS : 1] = {};
+    if (col) {
 #pragma unroll
-    for (int it = 0; it < NR; ++it) {
-        if (it < s || it >= nin) continue;
-        const int k = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
-        double al = 0, ac = 0, ar = 0, bl = 0, bc = 0, br = 0;
+        for (int it = 0; it < NR; ++it) {
+            if (it < s || it >= nin) continue;
+            const int k = transpose ? (k1 - 1 + s - it) : (k0 - s + it);
+            double al = 0, ac = 0, ar = 0, bl = 0, bc = 0, br = 0;
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            if (m > s || it - m < 0) break;
-            al += am[m] * rl[it - m];
-            ac += am[m] * rc[it - m];
-            ar += am[m] * rr[it - m];
-            bl += bm[m] * rl[it - m];
-            bc += bm[m] * rc[it - m];
-            br += bm[m] * rr[it - m];
+            for (int m = 0; m < 3; ++m) {
+                if (m > s || it - m < 0) break;
+                al += am[m] * rl[it - m];
+                ac += am[m] * rc[it - m];
+                ar += am[m] * rr[it - m];
+                bl += bm[m] * rl[it - m];
+                bc += bm[m] * rc[it - m];
+                br += bm[m] * rr[it - m];
+            }
+            const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
+            const size_t o = pb.off + (size_t)k * n + i;
+            const double out = bsub ? bsub[o] - v : v;
+            y[o] = out;
+#pragma unroll
+            for (int q = 0; q < DOTS; ++q) acc[q] += Vd[q][o] * out;
         }
-        const double v = (h / 6.0) * (al + 4.0 * ac + ar) + (1.0 / h) * (2.0 * bc - bl - br);
-        const size_t o = pb.off + (size_t)k * n + i;
-        y[o] = bsub ? bsub[o] - v : v;
+    }
+    if constexpr (DOTS > 0) {
+#pragma unroll
+        for (int q = 0; q < DOTS; ++q) {
+            double v = acc[q];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) red[q * 4 + (threadIdx.x >> 6)] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < DOTS)
+            part[(size_t)g * ldp + threadIdx.x] = red[threadIdx.x * 4] + red[threadIdx.x * 4 + 1] +
+                                                  red[threadIdx.x * 4 + 2] + red[threadIdx.x * 4 + 3];
     }
 }
 
@@ -590,13 +615,18 @@ __global__ void k_batch_reduce(const int2 *__restrict__ pslabs, int count,
                                const double *__restrict__ part, int ldp, int cnt,
                                double *__restrict__ sums, int sst)
 {
+    // one wave per problem: lane l sums blocks l, l + 64, ... of each slot, then a
+    // fixed shuffle tree (the order is the same on every run)
     const int p = blockIdx.x;
     if (p >= count || (active && !active[p])) return;
-    const int2 rg = pslabs[p];                     // slab range [x, y)
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const int2 rg = pslabs[p];                     // block range [x, y)
+    const int lane = threadIdx.x;
+    for (int i = 0; i < cnt; ++i) {
         double s = 0.0;
-        for (int b = rg.x; b < rg.y; ++b) s += part[(size_t)b * ldp + i];
-        sums[(size_t)p * sst + i] = s;
+        for (int b = rg.x + lane; b < rg.y; b += 64) s += part[(size_t)b * ldp + i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) sums[(size_t)p * sst + i] = s;
     }
 }
 
@@ -960,10 +990,21 @@ hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool singl
 }
 
 hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const double *bsub,
-                        int scheme, int transpose, bool masked, hipStream_t st)
+                        int scheme, int transpose, bool masked, hipStream_t st,
+                        const double *const *Vd, int nd, double *part, int ldp)
 {
-    k_batch_matvec<<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, masked ? L.active : nullptr,
-                                              x, y, bsub, scheme, transpose);
+    const unsigned char *act = masked ? L.active : nullptr;
+    if (nd == 1)
+        k_batch_matvec<1><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
+                                                     scheme, transpose, Vd, part, ldp);
+    else if (nd == 2)
+        k_batch_matvec<2><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
+                                                     scheme, transpose, Vd, part, ldp);
+    else if (nd == 0)
+        k_batch_matvec<0><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
+                                                     scheme, transpose, nullptr, nullptr, 0);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -1001,10 +1042,10 @@ hipError_t batch_cgs_delayed(const BatchLaunch &L, const double *const *V, int n
 }
 
 hipError_t batch_reduce(const BatchLaunch &L, const double *part, int ldp, int cnt, double *sums,
-                        int sst, bool masked, hipStream_t st)
+                        int sst, bool masked, hipStream_t st, const int2 *ranges)
 {
-    k_batch_reduce<<<L.count, 64, 0, st>>>(L.pslabs, L.count, masked ? L.active : nullptr, part, ldp,
-                                           cnt, sums, sst);
+    k_batch_reduce<<<L.count, 64, 0, st>>>(ranges ? ranges : L.pslabs, L.count,
+                                           masked ? L.active : nullptr, part, ldp, cnt, sums, sst);
     return hipGetLastError();
 }
 
