@@ -189,7 +189,7 @@ static aao_status b_step(aao_batch b, int j, int m, double tol, int transpose,
     const double *Vj = (j == 0 && v0) ? v0 : b->V + N * j;
     double *Zj = b->Z + N * j, *Vn = b->V + N * (j + 1);
     BT(b_pinv(b, Vj, s.vs + j, s.sst, Zj, true, transpose));
-    if (b->delayed && nv <= 2) {
+    if (b->delayed && nv <= 4) {
         // the first Gram-Schmidt pass (dots of w with the basis and the pending
         // vector) formed by the matvec itself
         BH(batch_matvec(L, Zj, b->W, nullptr, b->scheme, transpose, true, b->st, b->dV, nv,

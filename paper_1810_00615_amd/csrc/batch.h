@@ -65,7 +65,7 @@ hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool
                          hipStream_t st);
 hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool single_arith,
                        int scheme, int transpose, int *fail, hipStream_t st);
-// nd = 1 or 2: the tiles also leave the partials of Vd[q] . y (q < nd) at
+// nd = 1..4: the tiles also leave the partials of Vd[q] . y (q < nd) at
 // part[tile * ldp + q] (reduced per problem over L.mranges)
 hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const double *bsub,
                         int scheme, int transpose, bool masked, hipStream_t st,

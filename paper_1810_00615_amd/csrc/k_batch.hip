@@ -1000,6 +1000,12 @@ hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const 
     else if (nd == 2)
         k_batch_matvec<2><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
                                                      scheme, transpose, Vd, part, ldp);
+    else if (nd == 3)
+        k_batch_matvec<3><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
+                                                     scheme, transpose, Vd, part, ldp);
+    else if (nd == 4)
+        k_batch_matvec<4><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
+                                                     scheme, transpose, Vd, part, ldp);
     else if (nd == 0)
         k_batch_matvec<0><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
                                                      scheme, transpose, nullptr, nullptr, 0);
