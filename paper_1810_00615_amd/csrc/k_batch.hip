@@ -637,6 +637,10 @@ __global__ void k_batch_reduce(const int2 *__restrict__ pslabs, int count,
 //           previous rotations, form rotation j, update g, test convergence
 //   mode 3: restart vector: nrm = sqrt(d0) = beta; vs[0] = 1/beta; g = [beta, 0..];
 //           active = (beta / bnorm > tol) && !done
+//   mode 4: (deferred CGS2, after the dots of w with V_0..V_j) the column's h_i and
+//           the coefficients of the update pass
+//   mode 5: (after the update pass) the re-orthogonalisation coefficients of the new
+//           pending vector, the completed column, scales, Givens and convergence
 template <int dummy>
 __global__ void k_batch_small(int mode, int count, int j, int m, double tol, BState st)
 {
