@@ -319,7 +319,9 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
             }
             break;
         }
+        int steps_run = 0;
         for (int j = 0; j < m; ++j) {
+            ++steps_run;
             if (from_b && j == 0) {
                 // the captured step 0 reads V_0 from the workspace: launch eagerly
                 BT(b_step(b, 0, m, tol, transpose, bvec));
@@ -344,7 +346,7 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
             if (nact == 0) break;
         }
         BH(batch_backsolve(P, m, s, b->st));
-        BH(batch_axpy(Lall, b->dZ, s, x, from_b, b->st));
+        BH(batch_axpy(Lall, b->dZ, s, x, from_b, b->st, steps_run));
         if (from_b) {
             b->first_v = b->V;
             BH(hipMemcpyAsync(b->dV, &b->first_v, sizeof(double *), hipMemcpyHostToDevice, b->st));

@@ -86,8 +86,9 @@ hipError_t batch_reduce(const BatchLaunch &L, const double *part, int ldp, int c
 hipError_t batch_small(int mode, int count, int j, int m, double tol, const BState &s,
                        hipStream_t st);
 hipError_t batch_backsolve(int count, int m, const BState &s, hipStream_t st);
+// kmax: an upper bound of every problem's step count in the cycle (<= 64)
 hipError_t batch_axpy(const BatchLaunch &L, const double *const *Z, const BState &s, double *x,
-                      bool overwrite, hipStream_t st);
+                      bool overwrite, hipStream_t st, int kmax);
 hipError_t batch_count_active(const unsigned char *a, int count, int *nact, hipStream_t st);
 
 }  // namespace aao

@@ -781,7 +781,10 @@ __global__ void k_batch_backsolve(int count, int m, BState st)
     }
 }
 
-// x += sum_{i < k_p} Z_i y_i per problem, over slabs (x = sum ... when overwrite)
+// x += sum_{i < k_p} Z_i y_i per problem, over slabs (x = sum ... when overwrite).
+// KM >= every k_p: the direction loop is unrolled, so the loads of one element are
+// all in flight together.
+template <int KM>
 __global__ void __launch_bounds__(256)
 k_batch_axpy(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, int nslabs,
              const double *const *__restrict__ Z, BState st, double *__restrict__ x, int overwrite)
@@ -792,11 +795,24 @@ k_batch_axpy(const BProb *__restrict__ probs, const int4 *__restrict__ slabs, in
     const int k = st.ksteps[e.x];
     if (k == 0 && !overwrite) return;
     const double *y = st.y + (size_t)e.x * st.sst;
+    double yc[KM];
+    const double *zp[KM];
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {
+        yc[i] = i < k ? y[i] : 0.0;
+        zp[i] = Z[i < k ? i : 0];
+    }
     const size_t base = probs[e.x].off + (size_t)e.y;
     for (int q = threadIdx.x; q < e.z; q += blockDim.x) {
         const size_t o = base + q;
         double s = overwrite ? 0.0 : x[o];
-        for (int i = 0; i < k; ++i) s += Z[i][o] * y[i];
+        // unconditional loads (directions past k_p read Z_0, valid workspace) and
+        // a select, so that no branch separates the loads
+        double zv[KM];
+#pragma unroll
+        for (int i = 0; i < KM; ++i) zv[i] = zp[i][o];
+#pragma unroll
+        for (int i = 0; i < KM; ++i) s += i < k ? zv[i] * yc[i] : 0.0;
         x[o] = s;
     }
 }
@@ -1073,10 +1089,17 @@ hipError_t batch_backsolve(int count, int m, const BState &s, hipStream_t st)
 }
 
 hipError_t batch_axpy(const BatchLaunch &L, const double *const *Z, const BState &s, double *x,
-                      bool overwrite, hipStream_t st)
+                      bool overwrite, hipStream_t st, int kmax)
 {
-    k_batch_axpy<<<L.nslabs, 256, 0, st>>>(L.probs, L.slabs, L.nslabs, Z, s, x, overwrite ? 1 : 0);
-    return hipGetLastError();
+#define AAO_BAXPY(K)                                                                          \
+    if (kmax <= K) {                                                                          \
+        k_batch_axpy<K><<<L.nslabs, 256, 0, st>>>(L.probs, L.slabs, L.nslabs, Z, s, x,        \
+                                                  overwrite ? 1 : 0);                         \
+        return hipGetLastError();                                                             \
+    }
+    AAO_BAXPY(1) AAO_BAXPY(2) AAO_BAXPY(4) AAO_BAXPY(8) AAO_BAXPY(16) AAO_BAXPY(32) AAO_BAXPY(64)
+#undef AAO_BAXPY
+    return hipErrorInvalidValue;
 }
 
 hipError_t batch_count_active(const unsigned char *a, int count, int *nact, hipStream_t st)
