@@ -300,10 +300,10 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
             BH(hipMemcpyAsync(b->dV, &b->first_b, sizeof(double *), hipMemcpyHostToDevice,
                               b->st));
         } else {
-            BH(batch_matvec(Lall, x, b->V, bvec, b->scheme, transpose, false, b->st));
-            BH(batch_cgs(0, Lall, b->dV, 1, b->V, nullptr, 0, nullptr, b->part, b->ldp, false,
-                         b->st));
-            BH(batch_reduce(Lall, b->part, b->ldp, 1, s.dsum, s.sst, false, b->st));
+            // the matvec leaves the tile partials of |b - A x|^2
+            BH(batch_matvec(Lall, x, b->V, bvec, b->scheme, transpose, false, b->st, nullptr, -1,
+                            b->part, b->ldp));
+            BH(batch_reduce(Lall, b->part, b->ldp, 1, s.dsum, s.sst, false, b->st, Lall.mranges));
         }
         BH(batch_small(3, P, 0, m, tol, s, b->st));
         BH(batch_count_active(s.active, P, b->iv + 2 * P, b->st));

@@ -66,7 +66,8 @@ hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool
 hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool single_arith,
                        int scheme, int transpose, int *fail, hipStream_t st);
 // nd = 1..4: the tiles also leave the partials of Vd[q] . y (q < nd) at
-// part[tile * ldp + q] (reduced per problem over L.mranges)
+// part[tile * ldp + q] (reduced per problem over L.mranges); nd = -1: the partial
+// of y . y at part[tile * ldp]
 hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const double *bsub,
                         int scheme, int transpose, bool masked, hipStream_t st,
                         const double *const *Vd = nullptr, int nd = 0, double *part = nullptr,

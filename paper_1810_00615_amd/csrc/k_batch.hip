@@ -412,7 +412,8 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
 // neighbour outside their wave.  Threads past n stay for the lane moves (with 0).
 //
 // DOTS > 0: the tile also leaves the partials of V_q . y, q < DOTS (the first
-// Gram-Schmidt pass of an early Arnoldi step), at part[tile * ldp + q].
+// Gram-Schmidt pass of an early Arnoldi step), at part[tile * ldp + q]; DOTS = -1:
+// the partial of y . y (the norm of a residual), from registers.
 template <int DOTS>
 __global__ void __launch_bounds__(256)
 k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, int ntiles,
@@ -421,7 +422,8 @@ k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, 
                const double *const *__restrict__ Vd, double *__restrict__ part, int ldp)
 {
     constexpr int RB = 16;
-    __shared__ double red[(DOTS > 0 ? DOTS : 1) * 4];
+    constexpr int ND = DOTS < 0 ? 1 : DOTS;        // partials per tile
+    __shared__ double red[(ND > 0 ? ND : 1) * 4];
     const int g = blockIdx.x;
     if (g >= ntiles) return;
     const int4 e = tiles[g];
@@ -465,7 +467,7 @@ k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, 
         rr[it] = lane == 63 ? ev : r;
     }
     if (DOTS == 0 && !col) return;
-    double acc[DOTS > 0 ? DOTS : 1] = {};
+    double acc[ND > 0 ? ND : 1] = {};
     if (col) {
 #pragma unroll
         for (int it = 0; it < NR; ++it) {
@@ -486,20 +488,24 @@ k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, 
             const size_t o = pb.off + (size_t)k * n + i;
             const double out = bsub ? bsub[o] - v : v;
             y[o] = out;
+            if constexpr (DOTS < 0) {
+                acc[0] += out * out;
+            } else {
 #pragma unroll
-            for (int q = 0; q < DOTS; ++q) acc[q] += Vd[q][o] * out;
+                for (int q = 0; q < DOTS; ++q) acc[q] += Vd[q][o] * out;
+            }
         }
     }
-    if constexpr (DOTS > 0) {
+    if constexpr (ND > 0) {
 #pragma unroll
-        for (int q = 0; q < DOTS; ++q) {
+        for (int q = 0; q < ND; ++q) {
             double v = acc[q];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
             if (lane == 0) red[q * 4 + (threadIdx.x >> 6)] = v;
         }
         __syncthreads();
-        if (threadIdx.x < DOTS)
+        if (threadIdx.x < ND)
             part[(size_t)g * ldp + threadIdx.x] = red[threadIdx.x * 4] + red[threadIdx.x * 4 + 1] +
                                                   red[threadIdx.x * 4 + 2] + red[threadIdx.x * 4 + 3];
     }
@@ -1026,6 +1032,9 @@ hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const 
     else if (nd == 4)
         k_batch_matvec<4><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
                                                      scheme, transpose, Vd, part, ldp);
+    else if (nd == -1)
+        k_batch_matvec<-1><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y,
+                                                      bsub, scheme, transpose, nullptr, part, ldp);
     else if (nd == 0)
         k_batch_matvec<0><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
                                                      scheme, transpose, nullptr, nullptr, 0);

@@ -107,8 +107,10 @@ def test_batch_gmres_small(dev, orc, prec):
 @pytest.mark.parametrize("restart", [30, 2])
 def test_batch_zero_guess(dev, orc, restart):
     """The zero-guess entry (first cycle starts from b itself, x only written: the
-    output buffer starts as NaN) gives bitwise the result of an explicit zero initial
-    guess, also when the problems restart; an all-zero right-hand side returns x = 0."""
+    output buffer starts as NaN) matches an explicit zero initial guess, also when
+    the problems restart, and every member meets the 1e-8 true residual (oracle FP64
+    matvec); an all-zero right-hand side returns x = 0.  (The two entries sum |b|^2
+    in different orders, so they agree to rounding, not bitwise.)"""
     import torch
     B, ns, ells, kappas = make(dev, "fp64")
     J = 20
@@ -119,14 +121,21 @@ def test_batch_zero_guess(dev, orc, restart):
     x_z, inf_z, st_z = B.solve(b, restart=restart, tol=1e-8, maxit=300, out=out)
     x_e, inf_e, st_e = B.solve(b, restart=restart, tol=1e-8, maxit=300, x0=B.zeros())
     torch.cuda.synchronize()
-    print(f"zero guess restart {restart}: iterations {[i['iters'] for i in inf_z]} status {st_z}")
-    assert st_z == st_e
-    if restart == 30:
-        assert st_z == 0
+    print(f"zero guess restart {restart}: iterations {[i['iters'] for i in inf_z]} "
+          f"(explicit {[i['iters'] for i in inf_e]}) status {st_z}")
+    assert st_z == 0 and st_e == 0
+    bcpu = [v.cpu().numpy() for v in B.views(b)]
     # (the alignment padding between members belongs to no problem: compare the views)
-    for vz, ve in zip(B.views(x_z), B.views(x_e)):
-        assert bool((vz == ve).all())
-    assert [i["iters"] for i in inf_z] == [i["iters"] for i in inf_e]
+    for i, (vz, ve, bv) in enumerate(zip(B.views(x_z), B.views(x_e), bcpu)):
+        X = vz.cpu().numpy()
+        res = np.linalg.norm(bv - orc.apply_A(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i], X)) \
+            / np.linalg.norm(bv)
+        assert res <= 1e-8, (i, res)
+        if inf_z[i]["iters"] == inf_e[i]["iters"]:
+            assert normrel(X, ve.cpu().numpy()) < 1e-12
+        else:
+            assert abs(inf_z[i]["iters"] - inf_e[i]["iters"]) <= 1
+            assert normrel(X, ve.cpu().numpy()) < 1e-6
     out.fill_(float("nan"))
     x0, inf0, st0 = B.solve(B.zeros(), restart=restart, tol=1e-8, maxit=300, out=out)
     assert st0 == 0 and all(bool((v == 0).all()) for v in B.views(x0))
