@@ -33,6 +33,17 @@
  *     crosses this interface.
  *   - A context is not thread-safe; distinct contexts may be used from distinct
  *     threads on distinct streams.
+ *
+ * Environment variables (diagnostics and comparisons; none is needed for normal use):
+ *   AAO_CGS2_CLASSIC  set: three-pass CGS2 instead of the re-orthogonalisation
+ *                     deferred by one step (read at each aao_gmres* call; by a
+ *                     batch at aao_batch_create)
+ *   AAO_EARLY_CHECK   set: the single-problem GMRES checks the column before the
+ *                     update pass at every step, not only where convergence is
+ *                     expected
+ *   AAO_BATCH_GRAPH   0: batched Arnoldi steps launched eagerly, no hipGraph replay
+ *   AAO_TUNE_CACHE    file of autotuned launch shapes (see aao_tune)
+ *   AAO_LOG           set: per-step residual estimates on stderr
  */
 #ifndef AAO_H
 #define AAO_H
