@@ -31,7 +31,7 @@ def make(dev, prec, sizes=SMALL, kap_seed=0):
     return Batch(ns, ells, kappas, precision=prec, device=dev), ns, ells, kappas
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 2e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 2e-6), ("fp32", 1e-3)])
 def test_batch_pinv(dev, orc, prec, tol):
     import torch
     B, ns, ells, kappas = make(dev, prec)
@@ -70,7 +70,7 @@ def test_batch_matvec(dev, orc):
         assert float(np.max(np.abs(yv.cpu().numpy() - ref)) / np.max(np.abs(ref))) < 1e-14
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "fp32"])
 def test_batch_gmres_small(dev, orc, prec):
     """Every member reaches the 1e-8 true residual (oracle FP64 matvec) and the exact
     sequential solution; graph replay gives bitwise the same result as eager launches."""
