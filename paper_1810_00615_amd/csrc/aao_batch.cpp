@@ -443,7 +443,7 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             for (int t = 0; t < ntile; ++t) ft.push_back({p, t});
             for (int j = 0; j <= q.ell / 2; ++j) rwc[solve_class(q.n)].push_back({p, j});
             const int mfirst = (int)mt.size();
-            for (int by = 0; by < (q.ell + 15) / 16; ++by)
+            for (int by = 0; by < (q.ell + kMatvecRows - 1) / kMatvecRows; ++by)
                 for (int bx = 0; bx < (q.n + 255) / 256; ++bx) mt.push_back({p, bx, by, 0});
             mr.push_back({mfirst, (int)mt.size()});
             const int first = (int)sl.size();

@@ -406,7 +406,7 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
 }
 
 // ------------------------------------------------------------------ matvec
-// y = A x (or bsub - A x) per problem, tiles of 256 columns x 16 time levels.  A
+// y = A x (or bsub - A x) per problem, tiles of 256 columns x kMatvecRows time levels.  A
 // thread loads its own column of each input row once; the i -+ 1 neighbours come
 // from the adjacent lanes (DPP wave shift), and lanes 0 and 63 load the one
 // neighbour outside their wave.  Threads past n stay for the lane moves (with 0).
@@ -421,7 +421,7 @@ k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, 
                double *__restrict__ y, const double *__restrict__ bsub, int scheme, int transpose,
                const double *const *__restrict__ Vd, double *__restrict__ part, int ldp)
 {
-    constexpr int RB = 16;
+    constexpr int RB = kMatvecRows;
     constexpr int ND = DOTS < 0 ? 1 : DOTS;        // partials per tile
     __shared__ double red[(ND > 0 ? ND : 1) * 4];
     const int g = blockIdx.x;
