@@ -45,7 +45,7 @@ struct BatchLaunch {
 };
 
 constexpr int kBatchSlab = 65536;       // elements per Gram-Schmidt / update slab
-constexpr int kMatvecRows = 8;          // time levels per batched matvec tile
+constexpr int kMatvecRows = 4;          // time levels per batched matvec tile
 constexpr int kBSmall = 72;             // doubles per problem in the small per-problem arrays
 // shifted solves: class c = 0..3 of a problem holds n <= 8 * (64 << c) (workgroups of
 // 64 << c threads, 8 unknowns per thread)
