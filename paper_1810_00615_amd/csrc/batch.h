@@ -44,7 +44,7 @@ struct BatchLaunch {
     const double *chirp, *bhat, *tw;    // Bluestein tables, 4096-point twiddles
 };
 
-constexpr int kBatchSlab = 16384;       // elements per Gram-Schmidt / update slab
+constexpr int kBatchSlab = 4096;        // elements per Gram-Schmidt / update slab
 constexpr int kMatvecRows = 4;          // time levels per batched matvec tile
 constexpr int kBSmall = 72;             // doubles per problem in the small per-problem arrays
 // shifted solves: class c = 0..3 of a problem holds n <= 8 * (64 << c) (workgroups of
