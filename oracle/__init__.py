@@ -364,32 +364,3 @@ def grad(scheme, n, ell, tau, kappa, u0, U, L, v0=None, tau_k=None):
                          _p(v0c) if v0c is not None else None, _p(U), _p(L), _p(gu), _p(gv),
                          ctypes.byref(gk)), "grad")
     return gu, gv, gk.value
-
-
-# ------------------------------------------------------- dense tiny cases
-
-def dense_MK(n):
-    """Assembled M and K (n x n), for the dense checks on tiny sizes."""
-    h = 1.0 / (n + 1)
-    M = (h / 6.0) * (4.0 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1))
-    K = (1.0 / h) * (2.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1))
-    return M, K
-
-
-def dense_A(scheme, n, ell, tau, kappa, circulant=False, tau_k=None):
-    """Assembled monolithic matrix (or its block circulant) for tiny sizes."""
-    a, b = scheme_coeffs(scheme, tau)
-    M, K = dense_MK(n)
-    A = np.zeros((n * ell, n * ell))
-    for k in range(ell):
-        for m in range(len(a)):
-            src = k - m
-            if src < 0:
-                if not circulant:
-                    continue
-                src += ell
-            blk = a[m] * M + b[m] * kappa * K
-            if m == 0 and tau_k is not None and scheme == HEAT:
-                blk = M + tau_k[k] * kappa * K
-            A[k * n:(k + 1) * n, src * n:(src + 1) * n] += blk
-    return A

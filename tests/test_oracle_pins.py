@@ -309,3 +309,75 @@ def test_adjoint_gradient_fd_and_sine_basis(orc):
         y[k] = (G[k] / ((n + 1) / 2.0) + mu_m * y[k + 1]) / (mu_m * (1 + tau * kappa * lm))
     gu_sine = pins.sine_synth(mu_m * y[0])
     assert rel(gu, gu_sine) < 1e-12
+
+
+def test_bd2_adjoint_gradient_fd_and_sine_basis(orc):
+    """BD2 gradients (system C_BD2 with the start-up row u_1 = u_0 + tau v_0):
+    g_u0 = A_0 l_1 - M l_2, g_v0 = tau A_0 l_1 and
+    g_kappa = l_1 . tau^2 K (u_0 + tau v_0) - tau^2 sum_k l_k . K u_k, against central
+    finite differences on exact solves and, for g_u0 and g_v0, against the scalar
+    per-mode adjoint recursion in the discrete sine basis."""
+    n, ell = 11, 16
+    tau = 1.0 / ell
+    kappa = 1.3
+    rng = np.random.default_rng(11)
+    u0 = rng.standard_normal(n)
+    v0 = rng.standard_normal(n)
+    U_t = orc.solve_seq(BD2, n, ell, tau, 1.0,
+                        orc.build_rhs(BD2, n, ell, tau, 1.0, rng.standard_normal(n),
+                                      rng.standard_normal(n)))
+
+    def loss(u, v, k):
+        U = orc.solve_seq(BD2, n, ell, tau, k, orc.build_rhs(BD2, n, ell, tau, k, u, v))
+        return 0.5 * np.sum((U - U_t) ** 2), U
+    _, U = loss(u0, v0, kappa)
+    lam_ = orc.adjoint_seq(BD2, n, ell, tau, kappa, U - U_t)
+    gu, gv, gk = orc.grad(BD2, n, ell, tau, kappa, u0, U, lam_, v0=v0)
+    hh = 1e-6
+    fd_k = (loss(u0, v0, kappa + hh)[0] - loss(u0, v0, kappa - hh)[0]) / (2 * hh)
+    assert abs(gk - fd_k) < 1e-7 * max(1.0, abs(fd_k))
+    d = rng.standard_normal(n)
+    fd_u = (loss(u0 + hh * d, v0, kappa)[0] - loss(u0 - hh * d, v0, kappa)[0]) / (2 * hh)
+    assert abs(gu @ d - fd_u) < 1e-7 * max(1.0, abs(fd_u))
+    fd_v = (loss(u0, v0 + hh * d, kappa)[0] - loss(u0, v0 - hh * d, kappa)[0]) / (2 * hh)
+    assert abs(gv @ d - fd_v) < 1e-7 * max(1.0, abs(fd_v))
+    # sine basis: on mode m the blocks act as mu (1 + tau^2 kappa lam), -2 mu, mu; with
+    # l_k = sum_m y_{m,k} s_m and ||s_m||^2 = (n+1)/2 the adjoint rows read
+    # mu (1 + tau^2 kappa lam) y_k - 2 mu y_{k+1} + mu y_{k+2} = G_k / ((n+1)/2)
+    m = np.arange(1, n + 1)
+    nrm = (n + 1) / 2.0
+    G = np.array([pins.sine_coeffs(row) for row in (U - U_t)]) * nrm
+    mu_m, lm = pins.mu(n, m), pins.lam(n, m)
+    a0 = mu_m * (1 + tau * tau * kappa * lm)
+    y = np.zeros((ell + 2, n))
+    for k in range(ell - 1, -1, -1):
+        y[k] = (G[k] / nrm + 2 * mu_m * y[k + 1] - mu_m * y[k + 2]) / a0
+    assert rel(gu, pins.sine_synth(a0 * y[0] - mu_m * y[1])) < 1e-11
+    assert rel(gv, pins.sine_synth(tau * a0 * y[0])) < 1e-11
+
+
+def test_variable_step_gradient_fd(orc):
+    """Heat with variable steps (eq. nonuniformmonolithicheat, A_0^k = M + tau_k kappa K):
+    g_kappa = -sum_k tau_k l_k . K u_k and g_u0 = M l_1, against central finite
+    differences on exact solves."""
+    n, ell = 10, 12
+    tau = 1.0 / ell
+    tk = tau * (1 + 0.4 * np.sin(1.7 * np.arange(ell)))
+    kappa = 0.9
+    rng = np.random.default_rng(12)
+    u0 = rng.standard_normal(n)
+    U_t = rng.standard_normal((ell, n)) * 0.1
+
+    def loss(u, k):
+        U = orc.solve_seq(HEAT, n, ell, tau, k, orc.build_rhs(HEAT, n, ell, tau, k, u), tau_k=tk)
+        return 0.5 * np.sum((U - U_t) ** 2), U
+    _, U = loss(u0, kappa)
+    lam_ = orc.adjoint_seq(HEAT, n, ell, tau, kappa, U - U_t, tau_k=tk)
+    gu, gv, gk = orc.grad(HEAT, n, ell, tau, kappa, u0, U, lam_, tau_k=tk)
+    hh = 1e-6
+    fd_k = (loss(u0, kappa + hh)[0] - loss(u0, kappa - hh)[0]) / (2 * hh)
+    assert abs(gk - fd_k) < 1e-7 * max(1.0, abs(fd_k))
+    d = rng.standard_normal(n)
+    fd_u = (loss(u0 + hh * d, kappa)[0] - loss(u0 - hh * d, kappa)[0]) / (2 * hh)
+    assert abs(gu @ d - fd_u) < 1e-7 * max(1.0, abs(fd_u))
+    assert np.all(gv == 0.0)
