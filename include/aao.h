@@ -34,16 +34,8 @@
  *   - A context is not thread-safe; distinct contexts may be used from distinct
  *     threads on distinct streams.
  *
- * Environment variables (diagnostics and comparisons; none is needed for normal use):
- *   AAO_CGS2_CLASSIC  set: three-pass CGS2 instead of the re-orthogonalisation
- *                     deferred by one step (read at each aao_gmres* call; by a
- *                     batch at aao_batch_create)
- *   AAO_EARLY_CHECK   set: the single-problem GMRES checks the column before the
- *                     update pass at every step, not only where convergence is
- *                     expected
- *   AAO_BATCH_GRAPH   0: batched Arnoldi steps launched eagerly, no hipGraph replay
- *   AAO_TUNE_CACHE    file of autotuned launch shapes (see aao_tune)
- *   AAO_LOG           set: per-step residual estimates on stderr
+ * The library reads no environment variables: every option is an argument or a
+ * flag of this interface.
  */
 #ifndef AAO_H
 #define AAO_H
@@ -154,11 +146,27 @@ aao_status aao_apply_Pinv(aao_ctx ctx, const double *r, double *z, int neumann_o
 aao_status aao_gmres(aao_ctx ctx, const double *b, double *x, int restart, double tol,
                      int maxit, aao_info *info);
 
-/* aao_gmres with flags: AAO_GMRES_ZERO_GUESS -- x0 = 0 whatever x holds on entry
- * (x is only written; the first basis vector is b itself, so the initial
- * residual costs no matvec); AAO_GMRES_TRANSPOSE -- solve A^T x = b with C^{-T}
- * (as aao_adjoint_solve).  Unknown bits: AAO_ERR_ARG. */
-enum { AAO_GMRES_ZERO_GUESS = 1, AAO_GMRES_TRANSPOSE = 2 };
+/* aao_gmres with flags:
+ *   AAO_GMRES_ZERO_GUESS   x0 = 0 whatever x holds on entry (x is only written; the
+ *                          first basis vector is b itself, so the initial residual
+ *                          costs no matvec);
+ *   AAO_GMRES_TRANSPOSE    solve A^T x = b with C^{-T} (as aao_adjoint_solve);
+ *   AAO_GMRES_CGS2_CLASSIC three-pass CGS2 (project, re-project, update + norm) instead
+ *                          of the re-orthogonalisation deferred by one step (the same
+ *                          Hessenberg columns up to rounding; a comparison path);
+ *   AAO_GMRES_EARLY_CHECK  check the Hessenberg column before the update pass at every
+ *                          step, not only where the residual history predicts
+ *                          convergence (exercises the path where that check fails).
+ * The early check forms the last column entry from |w|^2 - |h|^2, which loses relative
+ * accuracy once that difference falls below about 1e-8 |w|^2; when it skips the update
+ * pass, rel_resid_est comes from that column.  Convergence is always decided by the
+ * true residual (rel_resid_true).  Unknown bits: AAO_ERR_ARG. */
+enum {
+    AAO_GMRES_ZERO_GUESS = 1,
+    AAO_GMRES_TRANSPOSE = 2,
+    AAO_GMRES_CGS2_CLASSIC = 4,
+    AAO_GMRES_EARLY_CHECK = 8
+};
 aao_status aao_gmres_ex(aao_ctx ctx, const double *b, double *x, int restart, double tol,
                         int maxit, int flags, aao_info *info);
 
@@ -235,9 +243,9 @@ aao_status aao_get_timing_ex(aao_ctx ctx, int kernel, double *total_ms, int64_t 
  * aao_tune times every admissible shape of each kernel `reps` times on the context
  * stream with HIP events (on scratch data; the context's vectors are untouched) and
  * keeps the fastest for the current precision mode; it synchronises the stream.
- * Results are cached per process by (device, kernel, precision, n, ell); if the
- * environment variable AAO_TUNE_CACHE names a file, results are also read from and
- * appended to it, one line "kernel precision n ell code microseconds".
+ * Results are cached per process by (device, kernel, precision, n, ell); once
+ * aao_set_tune_cache has named a file, results are also read from and appended to it,
+ * one line "kernel precision n ell code microseconds".
  * aao_set_config rejects a code that does not fit (n, ell) with AAO_ERR_ARG.
  * aao_config_shape decodes a code: FFT -> {points per thread, W, 0}; solve -> {CW,
  * NT, staged}; matvec -> {R, DPP, 0}. */
@@ -249,6 +257,8 @@ typedef enum {
     AAO_NUM_CFG = 4
 } aao_cfg_kind;
 aao_status aao_tune(aao_ctx ctx, int reps);
+/* Process-wide file of tuned launch shapes (host string, copied; NULL or "" = none). */
+aao_status aao_set_tune_cache(const char *path);
 aao_status aao_get_config(aao_ctx ctx, int kind, int *code);
 aao_status aao_set_config(aao_ctx ctx, int kind, int code);
 aao_status aao_config_shape(aao_ctx ctx, int kind, int code, int shape[3]);
@@ -293,7 +303,9 @@ aao_status aao_batch_gmres(aao_batch b, const double *bvec, double *x, int resta
  * AAO_GMRES_ZERO_GUESS -- x0 = 0 for every problem whatever x holds (the members'
  * ranges of x are only written, the alignment padding between them not at all; the
  * first cycle starts from b itself, with no residual matvec);
- * AAO_GMRES_TRANSPOSE -- solve A_p^T x_p = b_p with C_p^{-T}.  Unknown bits:
+ * AAO_GMRES_TRANSPOSE -- solve A_p^T x_p = b_p with C_p^{-T};
+ * AAO_GMRES_CGS2_CLASSIC -- three-pass CGS2.  Captured step graphs are rebuilt when
+ * the orientation, the CGS2 form, restart, tol or maxit change.  Other bits:
  * AAO_ERR_ARG. */
 aao_status aao_batch_gmres_ex(aao_batch b, const double *bvec, double *x, int restart,
                               double tol, int maxit, int flags, aao_info *infos);

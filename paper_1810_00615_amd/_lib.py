@@ -56,6 +56,7 @@ SIGNATURES = {
     "aao_get_timing_ex": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
     "aao_tune": [ctypes.c_void_p, ctypes.c_int],
+    "aao_set_tune_cache": [ctypes.c_char_p],
     "aao_get_config": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
     "aao_set_config": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
     "aao_config_shape": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
@@ -115,7 +116,7 @@ def check(status, where, ctx=None):
         raise AAOError(status, where, detail)
     return status
 
-GMRES_ZERO_GUESS, GMRES_TRANSPOSE = 1, 2
+GMRES_ZERO_GUESS, GMRES_TRANSPOSE, GMRES_CGS2_CLASSIC, GMRES_EARLY_CHECK = 1, 2, 4, 8
 CONFIG_KINDS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec"]
 KERNELS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec", "cgs_dot", "cgs_update_dot",
            "cgs_update_norm", "axpy", "arnoldi_update"]

@@ -13,8 +13,8 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import (CONFIG_KINDS, GMRES_TRANSPOSE, GMRES_ZERO_GUESS, KERNELS, AAOError, Info,
-                   check, lib)
+from ._lib import (CONFIG_KINDS, GMRES_CGS2_CLASSIC, GMRES_EARLY_CHECK, GMRES_TRANSPOSE,
+                   GMRES_ZERO_GUESS, KERNELS, AAOError, Info, check, lib)
 
 HEAT, BD2 = 0, 1
 SCHEMES = {"heat": HEAT, "heat_ie": HEAT, "bd2": BD2, "wave_bd2": BD2}
@@ -23,6 +23,18 @@ PRECISIONS = {"fp64": 0, "mixed": 1, "fp32": 2}
 
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _cgs2_flag(cgs2):
+    if cgs2 not in ("delayed", "classic"):
+        raise ValueError("cgs2 must be 'delayed' or 'classic'")
+    return GMRES_CGS2_CLASSIC if cgs2 == "classic" else 0
+
+
+def set_tune_cache(path: Optional[str]):
+    """Process-wide file of tuned launch shapes (aao_set_tune_cache); None = none."""
+    st = lib().aao_set_tune_cache(None if path is None else str(path).encode())
+    check(st, "aao_set_tune_cache")
 
 
 def _device(device):
@@ -162,13 +174,17 @@ class Problem:
         return z
 
     def solve(self, b: torch.Tensor, restart: int = 30, tol: float = 1e-8, maxit: int = 300,
-              x0: Optional[torch.Tensor] = None, out=None):
-        """FGMRES(restart) with the circulant preconditioner; returns (U, info)."""
+              x0: Optional[torch.Tensor] = None, out=None, cgs2: str = "delayed",
+              early_check: bool = False):
+        """FGMRES(restart) with the circulant preconditioner; returns (U, info).
+        cgs2: "delayed" (re-orthogonalisation deferred by one step) or "classic"
+        (three passes); early_check: check the column before the update pass at every
+        step (AAO_GMRES_EARLY_CHECK)."""
         self._vec(b, (self.ell, self.n), "b")
         x = out if out is not None else self.empty()
-        flags = 0
+        flags = _cgs2_flag(cgs2) | (GMRES_EARLY_CHECK if early_check else 0)
         if x0 is None:
-            flags = GMRES_ZERO_GUESS
+            flags |= GMRES_ZERO_GUESS
         else:
             x.copy_(x0)
         info = Info()
@@ -271,7 +287,7 @@ class Problem:
         return gu, gv, gk.value
 
 
-__all__ = ["Problem", "AAOError", "HEAT", "BD2"]
+__all__ = ["Problem", "AAOError", "HEAT", "BD2", "set_tune_cache"]
 
 
 class Batch:
@@ -378,12 +394,14 @@ class Batch:
                 "aao_batch_apply_Pinv")
         return z
 
-    def solve(self, b, restart=30, tol=1e-8, maxit=300, x0=None, out=None, transpose=False):
+    def solve(self, b, restart=30, tol=1e-8, maxit=300, x0=None, out=None, transpose=False,
+              cgs2="delayed"):
         """FGMRES on every problem; x0=None starts from zero (no residual matvec in
         the first cycle; the alignment padding between members of the result is then
-        left unwritten); transpose=True solves A_p^T x_p = b_p."""
+        left unwritten); transpose=True solves A_p^T x_p = b_p; cgs2 as in
+        Problem.solve."""
         x = out if out is not None else self.empty()
-        flags = GMRES_TRANSPOSE if transpose else 0
+        flags = (GMRES_TRANSPOSE if transpose else 0) | _cgs2_flag(cgs2)
         if x0 is None:
             flags |= GMRES_ZERO_GUESS
         else:

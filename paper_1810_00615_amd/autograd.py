@@ -22,6 +22,8 @@ class AllAtOnceSolve(torch.autograd.Function):
             raise RuntimeError(f"forward all-at-once solve did not converge: {info}")
         c = int(checkpoint_stride)
         ctx.problem = problem
+        # the Problem is shared: backward re-selects the kappa of this forward pass
+        ctx.kappa = float(kappa)
         ctx.opts = (restart, tol, maxit, c)
         ctx.has_v0 = v0 is not None
         if c > 1:
@@ -36,6 +38,7 @@ class AllAtOnceSolve(torch.autograd.Function):
         problem = ctx.problem
         restart, tol, maxit, c = ctx.opts
         u0, Usaved, v0 = ctx.saved_tensors
+        problem.set_kappa(ctx.kappa)
         lam, info = problem.adjoint(gU.contiguous(), restart=restart, tol=tol, maxit=maxit)
         if not info["converged"]:
             raise RuntimeError(f"adjoint solve did not converge: {info}")

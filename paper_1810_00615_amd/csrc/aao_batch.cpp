@@ -35,8 +35,8 @@ struct aao_batch_s {
     hipStream_t st = nullptr;
     bool own_stream = false;
     bool use_graph = true;
-    // CGS2 with deferred re-orthogonalisation (two passes per Arnoldi step) unless
-    // AAO_CGS2_CLASSIC is set (three passes)
+    // CGS2 with deferred re-orthogonalisation (two passes per Arnoldi step) unless the
+    // solve asks for the three-pass form (AAO_GMRES_CGS2_CLASSIC)
     bool delayed = true;
     std::string err;
     bool broken = false;
@@ -65,7 +65,8 @@ struct aao_batch_s {
     unsigned char *flags = nullptr; // active | done | bad
     BState bs{};
     std::vector<hipGraphExec_t> graphs;
-    int graph_m = 0, graph_maxit = -1;
+    // the captured steps depend on these: a solve with other values recaptures
+    int graph_m = 0, graph_maxit = -1, graph_transpose = -1, graph_delayed = -1;
     double graph_tol = -1.0;
     double **dB = nullptr;           // one-entry pointer array for norms of the rhs
 
@@ -280,6 +281,7 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
     BH(hipMemcpy(s.bnorm, bn_dev.data(), sizeof(double) * P, hipMemcpyHostToDevice));
 
     if (b->graph_m != m || b->graph_tol != tol || b->graph_maxit != maxit ||
+        b->graph_transpose != transpose || b->graph_delayed != (int)b->delayed ||
         (int)b->graphs.size() != m) {
         for (auto g : b->graphs)
             if (g) (void)hipGraphExecDestroy(g);
@@ -287,6 +289,8 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
         b->graph_m = m;
         b->graph_tol = tol;
         b->graph_maxit = maxit;
+        b->graph_transpose = transpose;
+        b->graph_delayed = (int)b->delayed;
     }
     int nact = 0;
     int cycles = 0;
@@ -342,7 +346,6 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
             }
             BH(hipMemcpyAsync(&nact, b->iv + 2 * P, sizeof(int), hipMemcpyDeviceToHost, b->st));
             BH(hipStreamSynchronize(b->st));
-            if (std::getenv("AAO_LOG")) std::fprintf(stderr, "aao batch step %d active %d\n", j, nact);
             if (nact == 0) break;
         }
         BH(batch_backsolve(P, m, s, b->st));
@@ -519,8 +522,6 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             s = AAO_ERR_HIP;
             break;
         }
-        if (const char *g = std::getenv("AAO_BATCH_GRAPH")) b->use_graph = std::atoi(g) != 0;
-        b->delayed = std::getenv("AAO_CGS2_CLASSIC") == nullptr;
     } while (0);
     if (s != AAO_OK) {
         aao_batch_destroy(b);
@@ -619,10 +620,11 @@ aao_status aao_batch_gmres_ex(aao_batch b, const double *bvec, double *x, int re
 {
     if (!b) return AAO_ERR_ARG;
     if (b->broken) return AAO_ERR_HIP;
-    if (flags & ~(AAO_GMRES_ZERO_GUESS | AAO_GMRES_TRANSPOSE)) {
+    if (flags & ~(AAO_GMRES_ZERO_GUESS | AAO_GMRES_TRANSPOSE | AAO_GMRES_CGS2_CLASSIC)) {
         b->err = "unknown flag bits";
         return AAO_ERR_ARG;
     }
+    b->delayed = (flags & AAO_GMRES_CGS2_CLASSIC) == 0;
     try {
         return b_gmres(b, bvec, x, restart, tol, maxit, infos,
                        (flags & AAO_GMRES_TRANSPOSE) ? 1 : 0, (flags & AAO_GMRES_ZERO_GUESS) != 0);

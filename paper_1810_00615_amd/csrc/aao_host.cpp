@@ -361,8 +361,9 @@ using TuneKey = std::tuple<int, int, int, int64_t, int64_t>;   // device, kind, 
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;
 bool g_tune_file_read = false;
+std::string g_tune_path;   // aao_set_tune_cache; empty: per-process cache only
 
-const char *tune_file() { return std::getenv("AAO_TUNE_CACHE"); }
+const char *tune_file() { return g_tune_path.empty() ? nullptr : g_tune_path.c_str(); }
 
 // caller holds g_tune_mu
 void tune_read_file(int device)
@@ -542,7 +543,8 @@ static aao_status wait_small(aao_ctx ctx)
 // ------------------------------------------------------------------ GMRES
 
 static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, double tol,
-                             int maxit, aao_info *info, int transpose, bool zero_guess)
+                             int maxit, aao_info *info, int transpose, bool zero_guess,
+                             bool classic = false, bool early_always = false)
 {
     if (m < 1 || m > kMaxRestart) return arg_err(ctx, "restart must be in [1, 63]");
     if (!(tol >= 0.0) || maxit < 0) return arg_err(ctx, "bad tol / maxit");
@@ -639,11 +641,10 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     }
 
     // Arnoldi: CGS2 with delayed re-orthogonalisation (two passes over the basis per
-    // step) unless AAO_CGS2_CLASSIC is set (three passes: project, re-project, update)
-    const bool delayed = std::getenv("AAO_CGS2_CLASSIC") == nullptr;
-    // AAO_EARLY_CHECK set: the early column check at every step after the first (a
-    // test of the path where the check fails and the step completes normally)
-    const bool early_always = std::getenv("AAO_EARLY_CHECK") != nullptr;
+    // step) unless `classic` (three passes: project, re-project, update).
+    // early_always: the early column check at every step after the first (exercises
+    // the path where the check fails and the step completes normally)
+    const bool delayed = !classic;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hcol(m + 2), y(m),
         hprov(m + 2);
     bool failed = false;
@@ -711,9 +712,6 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                     const double den = std::hypot(tcol[j], tcol[j + 1]);
                     const double est = den > 0.0 ? std::fabs(g[j]) * tcol[j + 1] / den / bnorm : 1.0;
                     provisional = std::isfinite(est) && est <= 0.5 * tol;
-                    if (std::getenv("AAO_LOG"))
-                        std::fprintf(stderr, "aao gmres step %d expected, column estimate %.3e%s\n",
-                                     inf.iters + 1, est, provisional ? " (update skipped)" : "");
                 }
                 if (!provisional) {
                     if (expect)   // w was not stored by the first pass
@@ -803,8 +801,6 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             inf.rel_resid_est = std::fabs(g[j + 1]) / bnorm;
             est_prev2 = est_prev;
             est_prev = inf.rel_resid_est;
-            if (std::getenv("AAO_LOG"))
-                std::fprintf(stderr, "aao gmres it %d est %.3e\n", inf.iters, inf.rel_resid_est);
             if (inf.rel_resid_est <= tol || inf.iters >= maxit) break;
         }
         // x (+)= Z y, y = R^{-1} g
@@ -1118,10 +1114,14 @@ aao_status aao_gmres_ex(aao_ctx ctx, const double *b, double *x, int restart, do
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
-    if (flags & ~(AAO_GMRES_ZERO_GUESS | AAO_GMRES_TRANSPOSE)) return arg_err(ctx, "bad flags");
+    if (flags & ~(AAO_GMRES_ZERO_GUESS | AAO_GMRES_TRANSPOSE | AAO_GMRES_CGS2_CLASSIC |
+                  AAO_GMRES_EARLY_CHECK))
+        return arg_err(ctx, "bad flags");
     try {
         return gmres_impl(ctx, b, x, restart, tol, maxit, info,
-                          (flags & AAO_GMRES_TRANSPOSE) ? 1 : 0, (flags & AAO_GMRES_ZERO_GUESS) != 0);
+                          (flags & AAO_GMRES_TRANSPOSE) ? 1 : 0, (flags & AAO_GMRES_ZERO_GUESS) != 0,
+                          (flags & AAO_GMRES_CGS2_CLASSIC) != 0,
+                          (flags & AAO_GMRES_EARLY_CHECK) != 0);
     } catch (const std::bad_alloc &) {
         return AAO_ERR_ALLOC;
     } catch (...) {
@@ -1309,6 +1309,14 @@ aao_status aao_tune(aao_ctx ctx, int reps)
         if (ctx->err.empty()) ctx->err = "HIP error while tuning";
     }
     return s;
+}
+
+aao_status aao_set_tune_cache(const char *path)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_path = path ? path : "";
+    g_tune_file_read = false;   // read the (new) file at the next aao_tune
+    return AAO_OK;
 }
 
 aao_status aao_get_config(aao_ctx ctx, int kind, int *code)

@@ -104,3 +104,30 @@ def test_bd2_autograd_gradients(dev, orc):
     assert normrel(u0.grad.cpu().numpy(), gur) < 1e-7
     assert normrel(v0.grad.cpu().numpy(), gvr) < 1e-7
     assert abs(float(k.grad) - gkr) < 1e-7 * abs(gkr)
+
+
+def test_two_forwards_backward_uses_own_kappa(dev, orc):
+    """Two forward passes with different kappa on one shared Problem, then a backward
+    through the first only: its gradients are the oracle's at the first kappa (the
+    backward re-selects the kappa its forward used)."""
+    import torch
+    from paper_1810_00615_amd import Problem, all_at_once_solve
+    n, ell = 63, 64
+    tau = 1.0 / ell
+    rng = np.random.default_rng(21)
+    u0r = rng.standard_normal(n) * 0.1
+    Ut = rng.standard_normal((ell, n)) * 0.01
+    P = Problem(n, ell, tau, "heat", device=dev)
+    u0 = torch.from_numpy(u0r).to(dev).requires_grad_(True)
+    k1 = torch.tensor(0.7, dtype=torch.float64, device=dev, requires_grad=True)
+    k2 = torch.tensor(1.9, dtype=torch.float64, device=dev, requires_grad=True)
+    U1 = all_at_once_solve(u0, k1, P, restart=50, tol=1e-13, maxit=200)
+    U2 = all_at_once_solve(u0, k2, P, restart=50, tol=1e-13, maxit=200)
+    (0.5 * ((U1 - torch.from_numpy(Ut).to(dev)) ** 2).sum()).backward()
+    assert k2.grad is None
+    Ur = orc.solve_seq(HEAT, n, ell, tau, 0.7, orc.build_rhs(HEAT, n, ell, tau, 0.7, u0r))
+    lr = orc.adjoint_seq(HEAT, n, ell, tau, 0.7, Ur - Ut)
+    gur, _, gkr = orc.grad(HEAT, n, ell, tau, 0.7, u0r, Ur, lr)
+    assert normrel(u0.grad.cpu().numpy(), gur) < 1e-9
+    assert abs(float(k1.grad) - gkr) < 1e-9 * abs(gkr)
+    del U2

@@ -142,9 +142,9 @@ def test_batch_zero_guess(dev, orc, restart):
 
 
 @pytest.mark.parametrize("restart", [30, 2, 1])
-def test_batch_delayed_matches_classic(dev, orc, restart, monkeypatch):
+def test_batch_delayed_matches_classic(dev, orc, restart):
     """CGS2 with the re-orthogonalisation deferred by one step (two passes per step)
-    against the three-pass form (AAO_CGS2_CLASSIC): the same iteration counts and the
+    against the three-pass form (AAO_GMRES_CGS2_CLASSIC): the same iteration counts and the
     same solutions to rounding, with and without restarts; both meet the 1e-8 true
     residual (oracle FP64 matvec)."""
     import torch
@@ -152,20 +152,15 @@ def test_batch_delayed_matches_classic(dev, orc, restart, monkeypatch):
     modes = np.arange(1, J + 1)
     amps = np.random.default_rng(6).normal(0, 0.1, (len(SMALL), J))
     out = {}
-    for name, classic in (("delayed", False), ("classic", True)):
-        if classic:
-            monkeypatch.setenv("AAO_CGS2_CLASSIC", "1")
-        else:
-            monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
+    for name in ("delayed", "classic"):
         B, ns, ells, kappas = make(dev, "fp64")
         b = B.rhs(B.project_sine(modes, amps))
-        x, infos, st = B.solve(b, restart=restart, tol=1e-8, maxit=300)
+        x, infos, st = B.solve(b, restart=restart, tol=1e-8, maxit=300, cgs2=name)
         torch.cuda.synchronize()
         assert st == 0
         out[name] = ([v.cpu().numpy() for v in B.views(x)], [i["iters"] for i in infos],
                      [v.cpu().numpy() for v in B.views(b)])
         B.close()
-    monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
     xd, itd, bd = out["delayed"]
     xc, itc, _ = out["classic"]
     print(f"restart {restart}: iterations delayed {itd} classic {itc}")
@@ -179,7 +174,7 @@ def test_batch_delayed_matches_classic(dev, orc, restart, monkeypatch):
 
 
 @pytest.mark.parametrize("restart", [8, 30])
-def test_batch_delayed_bd2_long(dev, orc, restart, monkeypatch):
+def test_batch_delayed_bd2_long(dev, orc, restart):
     """Many Arnoldi steps and restarts (wave BD2, 20-mode data): the deferred and the
     three-pass CGS2 both reach the 1e-8 true residual (oracle FP64 BD2 matvec) with
     iteration counts within two of each other."""
@@ -191,14 +186,10 @@ def test_batch_delayed_bd2_long(dev, orc, restart, monkeypatch):
     modes = np.arange(1, 21)
     amps = np.random.default_rng(8).normal(0, 0.1, (len(sizes), 20))
     its = {}
-    for name, classic in (("delayed", False), ("classic", True)):
-        if classic:
-            monkeypatch.setenv("AAO_CGS2_CLASSIC", "1")
-        else:
-            monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
+    for name in ("delayed", "classic"):
         B = Batch(ns, ells, [1.0] * len(sizes), scheme="bd2", precision="fp64", device=dev)
         b = B.rhs(B.project_sine(modes, amps))
-        x, infos, st = B.solve(b, restart=restart, tol=1e-8, maxit=400)
+        x, infos, st = B.solve(b, restart=restart, tol=1e-8, maxit=400, cgs2=name)
         torch.cuda.synchronize()
         assert st == 0
         for i, (xv, bv) in enumerate(zip(B.views(x), B.views(b))):
@@ -208,7 +199,6 @@ def test_batch_delayed_bd2_long(dev, orc, restart, monkeypatch):
             assert res <= 1e-8, (name, i, res)
         its[name] = [i["iters"] for i in infos]
         B.close()
-    monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
     print(f"BD2 restart {restart}: iterations delayed {its['delayed']} classic {its['classic']}")
     for a, c in zip(its["delayed"], its["classic"]):
         assert abs(a - c) <= 2
@@ -242,6 +232,23 @@ def test_batch_transpose_solve(dev, orc):
                                              transpose=True)) / np.linalg.norm(g)
         print(f"batch transpose n={ns[i]} ell={ells[i]}: iters {infos[i]['iters']} res {res:.2e}")
         assert infos[i]["converged"] and res <= 1e-8
+
+
+def test_batch_forward_then_transpose_same_batch(dev, orc):
+    """A forward solve and then a transposed solve on the same Batch with graph replay
+    on (the captured steps depend on the orientation and must be recaptured), then a
+    forward solve again: each meets the 1e-8 true residual of its own operator."""
+    B, ns, ells, kappas = make(dev, "fp64")
+    B.set_graph(True)
+    gs = [np.random.default_rng([i, 8]).standard_normal((l, n)) for i, (n, l) in enumerate(zip(ns, ells))]
+    g = B.pack(gs)
+    for tr in (False, True, False):
+        x, infos, st = B.solve(g, restart=30, tol=1e-8, maxit=300, transpose=tr)
+        assert st == 0, tr
+        for i, (xv, gv) in enumerate(zip(B.views(x), gs)):
+            res = np.linalg.norm(gv - orc.apply_A(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i],
+                                                  xv.cpu().numpy(), transpose=tr)) / np.linalg.norm(gv)
+            assert infos[i]["converged"] and res <= 1e-8, (tr, i, res)
 
 
 def test_batch_workload_64(dev, orc):

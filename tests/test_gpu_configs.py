@@ -2,7 +2,7 @@
 transform, the shifted solves and the inverse transform gives the oracle's C^{-1} r
 (Sec. 3, eq. precon2para) to the same tolerance as the default shapes, and every
 matvec shape the oracle's block-Toeplitz product (Sec. 2); aao_tune picks admissible
-shapes, caches them per process and in AAO_TUNE_CACHE, and the tuned apply still
+shapes, caches them per process and in the aao_set_tune_cache file, and the tuned apply still
 matches the oracle."""
 import numpy as np
 import pytest
@@ -97,11 +97,12 @@ def test_solve_shapes_bd2_transpose(dev, orc):
         assert e < tol, (c, e, tol)
 
 
-def test_tune_picks_admissible_shapes(dev, orc, tmp_path, monkeypatch):
+def test_tune_picks_admissible_shapes(dev, orc, tmp_path):
     import torch
     from paper_1810_00615_amd import Problem
+    from paper_1810_00615_amd.api import set_tune_cache
     cache = tmp_path / "tune.txt"
-    monkeypatch.setenv("AAO_TUNE_CACHE", str(cache))
+    set_tune_cache(str(cache))
     n, ell = 1023, 512
     tau, kappa = 1.0 / ell, 0.9
     P = Problem(n, ell, tau, "heat", kappa=kappa, device=dev)
@@ -126,6 +127,7 @@ def test_tune_picks_admissible_shapes(dev, orc, tmp_path, monkeypatch):
     assert info["converged"]
     ref = orc.solve_seq(HEAT, n, ell, tau, kappa, b.cpu().numpy())
     assert normrel(U.cpu().numpy(), ref) < 1e-8
+    set_tune_cache(None)
 
 
 MV_SHAPES = [(1, 1), (2, 3), (63, 5), (64, 17), (65, 16), (130, 33), (257, 100), (4095, 9)]

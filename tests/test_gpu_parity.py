@@ -223,9 +223,9 @@ def test_gmres_bd2_small(aao, orc, torch_dev, prec):
 
 
 @pytest.mark.parametrize("scheme,restart", [(HEAT, 50), (BD2, 8), (BD2, 60)])
-def test_arnoldi_delayed_matches_classic(aao, orc, torch_dev, scheme, restart, monkeypatch):
+def test_arnoldi_delayed_matches_classic(aao, orc, torch_dev, scheme, restart):
     """The Arnoldi process with the re-orthogonalisation deferred to the next step
-    (default) against the three-pass CGS2 (AAO_CGS2_CLASSIC): both reach the
+    (default) against the three-pass CGS2 (AAO_GMRES_CGS2_CLASSIC): both reach the
     requested true residual, their iteration counts differ by at most 2, and their
     solutions agree to the accuracy the tolerance allows.  Restart 60 with BD2 runs
     bases past 32 vectors; restart 8 exercises several restarts."""
@@ -241,18 +241,13 @@ def test_arnoldi_delayed_matches_classic(aao, orc, torch_dev, scheme, restart, m
     tol = 1e-10
     out = {}
     for variant in ("delayed", "classic"):
-        if variant == "classic":
-            monkeypatch.setenv("AAO_CGS2_CLASSIC", "1")
-        else:
-            monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
-        U, info = P.solve(b, restart=restart, tol=tol, maxit=600)
+        U, info = P.solve(b, restart=restart, tol=tol, maxit=600, cgs2=variant)
         assert info["converged"], (variant, info)
         Un = U.cpu().numpy()
         br = b.cpu().numpy()
         r = br - orc.apply_A(scheme, n, ell, tau, 1.0, Un)
         assert np.linalg.norm(r) / np.linalg.norm(br) <= 1.0001 * tol, variant
         out[variant] = (Un, info["iters"])
-    monkeypatch.delenv("AAO_CGS2_CLASSIC", raising=False)
     (Ud, itd), (Uc, itc) = out["delayed"], out["classic"]
     print(f"{name} restart {restart}: iterations delayed {itd}, classic {itc}")
     assert abs(itd - itc) <= 2
@@ -260,7 +255,7 @@ def test_arnoldi_delayed_matches_classic(aao, orc, torch_dev, scheme, restart, m
 
 
 @pytest.mark.parametrize("scheme,restart", [(HEAT, 30), (BD2, 12)])
-def test_early_column_check_every_step(aao, orc, torch_dev, scheme, restart, monkeypatch):
+def test_early_column_check_every_step(aao, orc, torch_dev, scheme, restart):
     """The early column check (formed from the matvec's dots before the update pass)
     forced at every step: where it fails, w is recomputed and the step completes
     normally; the solve matches the default one (same iterations up to 1) and reaches
@@ -276,16 +271,11 @@ def test_early_column_check_every_step(aao, orc, torch_dev, scheme, restart, mon
     br = b.cpu().numpy()
     out = {}
     for forced in (False, True):
-        if forced:
-            monkeypatch.setenv("AAO_EARLY_CHECK", "1")
-        else:
-            monkeypatch.delenv("AAO_EARLY_CHECK", raising=False)
-        U, info = P.solve(b, restart=restart, tol=1e-10, maxit=600)
+        U, info = P.solve(b, restart=restart, tol=1e-10, maxit=600, early_check=forced)
         assert info["converged"], (forced, info)
         r = br - orc.apply_A(scheme, n, ell, tau, 1.0, U.cpu().numpy())
         assert np.linalg.norm(r) / np.linalg.norm(br) <= 1.0001e-10, forced
         out[forced] = (U.cpu().numpy(), info["iters"])
-    monkeypatch.delenv("AAO_EARLY_CHECK", raising=False)
     assert abs(out[True][1] - out[False][1]) <= 1
     assert normrel(out[True][0], out[False][0]) < 1e-6
 
