@@ -173,14 +173,20 @@ aao_status aao_gmres_ex(aao_ctx ctx, const double *b, double *x, int restart, do
 /* Neumann order used by aao_gmres and aao_adjoint_solve (default 0). */
 aao_status aao_set_neumann_order(aao_ctx ctx, int q);
 
-/* Adjoint solve A^T lam = g by the same GMRES, preconditioned with C^{-T}
- * (the conjugated symbol).  g, lam: device, ell x n; lam holds the initial
- * guess on entry.  Same return convention as aao_gmres. */
+/* Adjoint solve A^T lam = g: the transpose of the monolithic matrix of Sec. 2
+ * (eq. monolithicheat, system C_BD2; block upper-triangular, A^T = J A J with J the
+ * reversal of the time levels, every block being symmetric), by the same GMRES
+ * preconditioned with C^{-T}.  C^T is the block circulant of the same blocks wrapped
+ * the other way; its Fourier diagonalisation (eq. precon2para) has the conjugated
+ * symbol, so C^{-T} costs what C^{-1} costs.  g, lam: device, ell x n; lam holds the
+ * initial guess on entry.  Same return convention as aao_gmres. */
 aao_status aao_adjoint_solve(aao_ctx ctx, const double *g, double *lam, int restart,
                              double tol, int maxit, aao_info *info);
 
-/* Gradient reductions for L(U) with A(kappa) U = b(u0, v0, kappa), given the
- * forward solution U and the adjoint lam (A^T lam = dL/dU), all device:
+/* Gradient reductions for L(U) with A(kappa) U = b(u0, v0, kappa) (the monolithic
+ * system and right-hand side of Sec. 2, eq. monolithicheat / system C_BD2, whose
+ * blocks are linear in kappa), given the forward solution U and the adjoint lam
+ * (A^T lam = dL/dU), all device:
  *   g_u0    (device, n)   = (db/du0)^T lam   heat: M lam_1;
  *                                            BD2: A_0 lam_1 - M lam_2
  *   g_v0    (device, n or NULL) = (db/dv0)^T lam  (BD2: tau A_0 lam_1; heat: 0)
@@ -190,7 +196,9 @@ aao_status aao_adjoint_solve(aao_ctx ctx, const double *g, double *lam, int rest
 aao_status aao_grad(aao_ctx ctx, const double *u0, const double *v0, const double *U,
                     const double *lam, double *g_u0, double *g_v0, double *g_kappa);
 
-/* Gradient with the forward trajectory checkpointed over time (heat scheme):
+/* Gradient with the forward trajectory checkpointed over time (heat scheme; the
+ * trajectory is the sequential solution of eq. timestepproblem1 that the monolithic
+ * system of eq. monolithicheat packages):
  * Uck (device) holds rows stride-1, 2*stride-1, ... of U (floor(ell/stride) rows
  * of n doubles; may be NULL when stride >= ell).  The levels in between are
  * recomputed by sequential implicit Euler steps (eq. timestepproblem1) from the
@@ -273,7 +281,10 @@ aao_status aao_config_shape(aao_ctx ctx, int kind, int code, int shape[3]);
  * concatenate the n_p-vectors without gaps.  The transform along time uses
  * Bluestein's chirp-z form for any ell_p (power-of-two convolution length
  * M_p >= 2 ell_p - 1), so ell_p need not be smooth.  Limits: 1 <= n_p <= 4096,
- * 2 <= ell_p <= 2048.  The batch owns its own HIP stream. */
+ * 2 <= ell_p <= 2048.  The batch owns its own HIP stream.
+ * Member p is the system A_p U_p = b_p of Sec. 2 (eq. monolithicheat, or system
+ * C_BD2) with its own n_p, ell_p, tau_p and kappa_p, preconditioned by its circulant
+ * C_p applied as in Sec. 3 (eq. precon2para); the members share no data. */
 typedef struct aao_batch_s *aao_batch;
 
 /* count problems; n, ell, kappa: host arrays of count entries; tau: host array or
@@ -290,13 +301,20 @@ aao_status aao_batch_set_graph(aao_batch b, int enable);
 /* u0 (device, sum n_p) = L2 projections of sum_q amps[p*J + q] sin(modes[q] pi x) */
 aao_status aao_batch_project_sine(aao_batch b, int J, const int *modes, const double *amps,
                                   double *u0);
-/* batch right-hand side from the concatenated u0 (heat: b_1 = M u0 per problem) */
+/* batch right-hand side from the concatenated u0 (heat: b_1 = M u0 per problem,
+ * eq. monolithicheat) */
 aao_status aao_batch_build_rhs(aao_batch b, const double *u0, double *bvec);
+/* y_p = A_p x_p (A_p^T x_p if transpose) for every member (Sec. 2); x, y device batch
+ * vectors, must not overlap */
 aao_status aao_batch_apply_A(aao_batch b, const double *x, double *y, int transpose);
+/* z_p = C_p^{-1} r_p (C_p^{-T} r_p if transpose) for every member through
+ * eq. precon2para: transform along time, shifted tridiagonal solves per frequency,
+ * inverse transform, in the batch precision */
 aao_status aao_batch_apply_Pinv(aao_batch b, const double *r, double *z, int transpose);
-/* FGMRES(restart) on every problem to tol (true relative residual per problem);
- * x: initial guess in, solutions out; infos: host array of count entries or NULL.
- * AAO_OK when every problem converged, AAO_NOT_CONVERGED otherwise. */
+/* FGMRES(restart) on every problem to tol (true relative residual per problem), the
+ * preconditioned GMRES of Sec. 4 in its right-preconditioned flexible form, CGS2
+ * Arnoldi; x: initial guess in, solutions out; infos: host array of count entries or
+ * NULL.  AAO_OK when every problem converged, AAO_NOT_CONVERGED otherwise. */
 aao_status aao_batch_gmres(aao_batch b, const double *bvec, double *x, int restart, double tol,
                            int maxit, aao_info *infos);
 /* aao_batch_gmres with flags (the AAO_GMRES_* bits of aao_gmres_ex):
