@@ -193,21 +193,30 @@ static aao_status dev_alloc(aao_ctx ctx, void **p, size_t bytes)
     return AAO_OK;
 }
 
-static void scheme_of(aao_ctx ctx)
+namespace aao {
+// Block coefficients (a_m, b_m) of A_m = a_m M + b_m kappa K for a scheme constant
+// (Sec. 2: eq. monolithicheat read as A_0 = M + tau K, A_1 = -M; system C_BD2).
+bool make_scheme(int scheme, double tau, Scheme *out)
 {
     Scheme s{};
-    if (ctx->scheme == AAO_HEAT_IE) {
+    if (scheme == AAO_HEAT_IE) {
         s.s = 1;
-        s.a[0] = 1.0;  s.b[0] = ctx->tau;
+        s.a[0] = 1.0;  s.b[0] = tau;
         s.a[1] = -1.0; s.b[1] = 0.0;
-    } else {
+    } else if (scheme == AAO_WAVE_BD2) {
         s.s = 2;
-        s.a[0] = 1.0;  s.b[0] = ctx->tau * ctx->tau;
+        s.a[0] = 1.0;  s.b[0] = tau * tau;
         s.a[1] = -2.0; s.b[1] = 0.0;
         s.a[2] = 1.0;  s.b[2] = 0.0;
+    } else {
+        return false;
     }
-    ctx->sc = s;
+    *out = s;
+    return true;
 }
+}  // namespace aao
+
+static void scheme_of(aao_ctx ctx) { make_scheme(ctx->scheme, ctx->tau, &ctx->sc); }
 
 static void free_workspace(aao_ctx ctx)
 {

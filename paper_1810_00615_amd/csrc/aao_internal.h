@@ -43,6 +43,10 @@ struct Scheme {
     double b[4];
 };
 
+// Coefficients of a scheme constant of aao.h (AAO_HEAT_IE, ...) for step tau; false
+// for an unknown scheme.
+bool make_scheme(int scheme, double tau, Scheme *out);
+
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `st` and return hipError_t of the launch.
 

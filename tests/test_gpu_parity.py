@@ -366,4 +366,4 @@ def test_gmres_initial_guess_paths(aao, orc, torch_dev, scheme):
     lr = orc.adjoint_seq(scheme, n, ell, tau, kappa, bn)
     assert normrel(lam.cpu().numpy(), lr) < 1e-9
     assert L.aao_gmres_ex(P._ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                          10, 1e-12, 10, 8, ctypes.byref(info)) == -1
+                          10, 1e-12, 10, 1 << 6, ctypes.byref(info)) == -1
