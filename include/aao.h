@@ -133,6 +133,27 @@ aao_status aao_apply_A(aao_ctx ctx, const double *x, double *y, int transpose);
 aao_status aao_apply_Pinv(aao_ctx ctx, const double *r, double *z, int neumann_order,
                           int transpose);
 
+/* z = C^{-1} r (transpose = 0) or C^{-T} r as aao_apply_Pinv with neumann_order 0,
+ * for callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc): no context, and no allocation by
+ * this call.  The twiddles, the symbol and partition tables and the half spectrum
+ * live in one static device array of 64 MiB per GPU, held until the process ends:
+ * 16 ell + 64 H + 2 H (3 CW + 8) w_a + H lds w_s bytes, each term rounded up to 256,
+ * with H = ell/2 + 1, lds = n rounded up to 16, CW the chunk width of the default
+ * shifted-solve shape for n (at most 8 up to n = 4096), w_a = 16 (8 for
+ * AAO_PREC_FP32) and w_s = 16 (8 for the reduced precisions); e.g. n = 2047,
+ * ell = 2048 needs at most 34.8 MB in FP64.  Sizes beyond it, ell not a power of two in [2, 16384] or n > 16384:
+ * AAO_ERR_UNSUPPORTED; bad values or overlapping r, z: AAO_ERR_ARG.  kappa > 0 as in
+ * aao_set_kappa; scheme and prec as in aao_create / aao_set_precision; r, z device,
+ * ell x n; stream a hipStream_t (NULL = null stream).  The call is asynchronous and
+ * leaves its result in z only; every call on one GPU shares that GPU's array, so
+ * calls that overlap in time on one GPU (other streams, other threads) race, and
+ * must be ordered by the caller.  The first call on a GPU looks the array up
+ * (hipGetSymbolAddress); make that call outside any stream capture. */
+aao_status aao_apply_Pinv_noalloc(int64_t n, int64_t ell, double tau, double kappa, int scheme,
+                                  int prec, const double *r, double *z, int transpose,
+                                  void *stream);
+
 /* Restarted right-preconditioned flexible GMRES(restart) for A x = b (device
  * vectors; x holds the initial guess on entry -- pass zeros for x0 = 0 -- and
  * the solution on return), preconditioner aao_apply_Pinv(neumann_order =

@@ -39,6 +39,9 @@ SIGNATURES = {
     "aao_apply_A": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int],
     "aao_apply_Pinv": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                        ctypes.c_int],
+    "aao_apply_Pinv_noalloc": [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_int, ctypes.c_void_p],
     "aao_gmres": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                   ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)],
     "aao_gmres_ex": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,

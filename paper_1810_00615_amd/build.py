@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaao.so")
 BUILD = os.path.join(ROOT, "_build")
 SOURCES = ["k_fft.hip", "k_solve.hip", "k_vec.hip", "k_batch.hip", "aao_host.cpp",
-           "aao_batch.cpp"]
+           "aao_batch.cpp", "aao_noalloc.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
