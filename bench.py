@@ -153,7 +153,7 @@ def bench_wave(args):
     b = P.rhs(P.project_sine(w.modes, w.amps), P.project_sine(w.v_modes, w.v_amps))
     x = P.empty()
     out = {"workload": w.name, "unknowns": w.n * w.ell}
-    for prec in ("fp64", "mixed"):
+    for prec in ("fp64", "mixed", "mixed_in"):
         P.set_precision(prec)
         if not args.no_tune:
             P.tune(reps=3)
@@ -163,6 +163,7 @@ def bench_wave(args):
         out[prec] = {"solve_ms": t * 1e3, "iters": info["iters"],
                      "true_rel_resid": info["rel_resid_true"], "converged": bool(info["converged"])}
     out["mixed_speedup_vs_fp64"] = out["fp64"]["solve_ms"] / out["mixed"]["solve_ms"]
+    out["mixed_in_speedup_vs_fp64"] = out["fp64"]["solve_ms"] / out["mixed_in"]["solve_ms"]
     P.set_precision("fp64")
     z = P.empty()
     P.Pinv(b, out=z)
@@ -187,7 +188,7 @@ def bench_batch(args):
            "unknowns": int(sum(w.n * w.ell for w in ws))}
     modes = ws[0].modes
     amps = np.stack([w.amps for w in ws])
-    for prec in ("mixed", "fp64"):
+    for prec in ("mixed", "mixed_in", "fp64"):
         B = Batch([w.n for w in ws], [w.ell for w in ws], [w.kappa for w in ws], precision=prec)
         b = B.rhs(B.project_sine(modes, amps))
         x = B.empty()
@@ -218,6 +219,7 @@ def bench_batch(args):
     out["sequential_fp64_ms"] = seq * 1e3
     out["sequential_fp64_max_true_rel_resid"] = worst
     out["batched_mixed_speedup_vs_sequential_fp64"] = seq * 1e3 / out["mixed"]["solve_ms"]
+    out["batched_mixed_in_speedup_vs_sequential_fp64"] = seq * 1e3 / out["mixed_in"]["solve_ms"]
     out["batched_fp64_speedup_vs_sequential_fp64"] = seq * 1e3 / out["fp64"]["solve_ms"]
     return out
 
@@ -315,8 +317,9 @@ def main():
     shapes = {}
     if not args.no_tune:
         shapes["fp64"] = P.tune(reps=5)
-        P.set_precision("mixed")
-        shapes["mixed"] = P.tune(reps=5)
+        for prec in ("mixed", "mixed_in"):
+            P.set_precision(prec)
+            shapes[prec] = P.tune(reps=5)
         P.set_precision("fp64")
     for _ in range(args.warmup):
         P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit, out=x)
@@ -381,8 +384,11 @@ def main():
         kt2 = P.timing()
         P.set_timing(False)
         t = e0.elapsed_time(e1) / 1e3 / args.pinv_reps
-        wspec = 16 if prec == "fp64" else 8
-        alg = 2 * 8 * N + 4 * wspec * (w.ell // 2 + 1) * w.n
+        # bytes per spectrum pass: input side (forward write, solve read) and output side
+        # (solve write, inverse read)
+        w_in = 16 if prec == "fp64" else 8
+        w_out = 8 if prec == "mixed" else 16
+        alg = 2 * 8 * N + 2 * (w_in + w_out) * (w.ell // 2 + 1) * w.n
         per = {k: kt2[k][0] / max(kt2[k][1], 1) * 1e3 for k in ("fft_fwd", "shifted_solve", "fft_inv")}
         per_gbps = {k: kt2[k][2] / max(kt2[k][0], 1e-12) / 1e6
                     for k in ("fft_fwd", "shifted_solve", "fft_inv")}
@@ -392,16 +398,21 @@ def main():
 
     out["pinv_fp64"] = time_pinv("fp64")
     out["pinv_mixed"] = time_pinv("mixed")
+    out["pinv_mixed_in"] = time_pinv("mixed_in")
 
     # --------------------------------------------------------------- mixed
-    P.set_precision("mixed")
-    for _ in range(max(1, args.warmup)):
-        P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit, out=x)
-    infos_m, wall_m, gpu_m = run_solves(P, b, x, w, args.steps)
-    out["mixed"] = {"solve_ms": gpu_m / args.steps * 1e3, "iters": infos_m[-1]["iters"],
-                    "true_rel_resid": infos_m[-1]["rel_resid_true"],
-                    "converged": bool(infos_m[-1]["converged"]),
-                    "speedup_vs_fp64": t_step / (gpu_m / args.steps)}
+    # "mixed": single-precision transforms and spectra on both sides of the solves;
+    # "mixed_in": single precision on the input side only (forward transform and its
+    # spectrum), FP64 solves, output spectrum and inverse transform
+    for prec in ("mixed", "mixed_in"):
+        P.set_precision(prec)
+        for _ in range(max(1, args.warmup)):
+            P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit, out=x)
+        infos_m, wall_m, gpu_m = run_solves(P, b, x, w, args.steps)
+        out[prec] = {"solve_ms": gpu_m / args.steps * 1e3, "iters": infos_m[-1]["iters"],
+                     "true_rel_resid": infos_m[-1]["rel_resid_true"],
+                     "converged": bool(infos_m[-1]["converged"]),
+                     "speedup_vs_fp64": t_step / (gpu_m / args.steps)}
     P.set_precision("fp64")
 
     del P, x, b, u0

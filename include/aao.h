@@ -61,14 +61,21 @@ typedef enum {
 
 enum { AAO_HEAT_IE = 0, AAO_WAVE_BD2 = 1 };
 
-/* Precision of the preconditioner apply inside GMRES (aao_set_precision).
- *   AAO_PREC_FP64   FFTs, spectra and shifted solves in double.
- *   AAO_PREC_MIXED  FFTs and spectra in single precision, shifted solves in
- *                   double arithmetic on single-precision spectra; the outer
- *                   flexible GMRES (matvec, residual, Arnoldi, update) stays
- *                   double.
- *   AAO_PREC_FP32   as MIXED with the shifted solves in single precision too. */
-enum { AAO_PREC_FP64 = 0, AAO_PREC_MIXED = 1, AAO_PREC_FP32 = 2 };
+/* Precision of the preconditioner apply inside GMRES (aao_set_precision).  In every
+ * mode the outer flexible GMRES (matvec, residual, Arnoldi, update) stays double.
+ *   AAO_PREC_FP64      FFTs, spectra and shifted solves in double.
+ *   AAO_PREC_MIXED     FFTs and spectra in single precision, shifted solves in
+ *                      double arithmetic on single-precision spectra.
+ *   AAO_PREC_FP32      as MIXED with the shifted solves in single precision too.
+ *   AAO_PREC_MIXED_IN  single precision on the input side only: the forward FFT and
+ *                      the spectrum it writes; the shifted solves (double arithmetic),
+ *                      their output spectrum and the inverse FFT in double.  A
+ *                      rounding error d of the input side reaches the preconditioned
+ *                      residual as A C^{-1} d ~ d (C^{-1} A is the identity plus a
+ *                      low-rank term), so it costs no accuracy; one of the output side
+ *                      is multiplied by ||A|| ||C^{-1} r|| / ||r||, which is what makes
+ *                      AAO_PREC_MIXED need more GMRES iterations. */
+enum { AAO_PREC_FP64 = 0, AAO_PREC_MIXED = 1, AAO_PREC_FP32 = 2, AAO_PREC_MIXED_IN = 3 };
 
 typedef struct {
     int iters;              /* preconditioner applies (GMRES iterations)          */
@@ -102,7 +109,8 @@ aao_status aao_set_kappa(aao_ctx ctx, double kappa);
  * AAO_ERR_STATE for the wave scheme. */
 aao_status aao_set_steps(aao_ctx ctx, const double *tau_k);
 
-/* AAO_PREC_FP64 (default), AAO_PREC_MIXED or AAO_PREC_FP32. */
+/* AAO_PREC_FP64 (default), AAO_PREC_MIXED, AAO_PREC_FP32 or AAO_PREC_MIXED_IN (which
+ * allocates its single-precision input spectrum on first selection). */
 aao_status aao_set_precision(aao_ctx ctx, int prec);
 
 /* Initial data as a sine series s(x) = sum_m amps[m] sin(modes[m] pi x) (host
@@ -138,11 +146,11 @@ aao_status aao_apply_Pinv(aao_ctx ctx, const double *r, double *z, int neumann_o
  * serving loops, harnesses that forbid hipMalloc): no context, and no allocation by
  * this call.  The twiddles, the symbol and partition tables and the half spectrum
  * live in one static device array of 64 MiB per GPU, held until the process ends:
- * 16 ell + 64 H + 2 H (3 CW + 8) w_a + H lds w_s bytes, each term rounded up to 256,
- * with H = ell/2 + 1, lds = n rounded up to 16, CW the chunk width of the default
- * shifted-solve shape for n (at most 8 up to n = 4096), w_a = 16 (8 for
- * AAO_PREC_FP32) and w_s = 16 (8 for the reduced precisions); e.g. n = 2047,
- * ell = 2048 needs at most 34.8 MB in FP64.  Sizes beyond it, ell not a power of two in [2, 16384] or n > 16384:
+ * 16 ell + 64 H + 2 H (3 CW + 8) w_a + H lds w_s (+ 8 H lds for AAO_PREC_MIXED_IN)
+ * bytes, each term rounded up to 256, with H = ell/2 + 1, lds = n rounded up to 16,
+ * CW the chunk width of the default shifted-solve shape for n (at most 8 up to
+ * n = 4096), w_a = 16 (8 for AAO_PREC_FP32) and w_s = 8 for AAO_PREC_MIXED and
+ * AAO_PREC_FP32, else 16; e.g. n = 2047, ell = 2048 needs at most 34.8 MB in FP64.  Sizes beyond it, ell not a power of two in [2, 16384] or n > 16384:
  * AAO_ERR_UNSUPPORTED; bad values or overlapping r, z: AAO_ERR_ARG.  kappa > 0 as in
  * aao_set_kappa; scheme and prec as in aao_create / aao_set_precision; r, z device,
  * ell x n; stream a hipStream_t (NULL = null stream).  The call is asynchronous and

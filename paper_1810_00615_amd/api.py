@@ -18,7 +18,7 @@ from ._lib import (CONFIG_KINDS, GMRES_CGS2_CLASSIC, GMRES_EARLY_CHECK, GMRES_TR
 
 HEAT, BD2 = 0, 1
 SCHEMES = {"heat": HEAT, "heat_ie": HEAT, "bd2": BD2, "wave_bd2": BD2}
-PRECISIONS = {"fp64": 0, "mixed": 1, "fp32": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1, "fp32": 2, "mixed_in": 3}
 
 
 def _ptr(t: Optional[torch.Tensor]):

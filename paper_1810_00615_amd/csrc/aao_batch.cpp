@@ -47,7 +47,8 @@ struct aao_batch_s {
     int nftiles = 0, nrows = 0, nmtiles = 0, nslabs = 0;
     int row_start[5] = {};
     double *chirp = nullptr, *bhat = nullptr, *tw = nullptr;
-    void *spec = nullptr;
+    void *spec = nullptr;           // half spectra (the solves' output side)
+    void *spec_in = nullptr;        // single-precision input spectra (AAO_PREC_MIXED_IN)
     int *fail = nullptr;
 
     // GMRES workspace and state
@@ -168,12 +169,14 @@ static aao_status ensure_ws(aao_batch b, int m)
 static aao_status b_pinv(aao_batch b, const double *r, const double *scales, int sstride, double *z,
                          bool masked, int transpose)
 {
-    const bool single = b->prec != AAO_PREC_FP64;
-    const bool single_arith = b->prec == AAO_PREC_FP32;
+    const bool sin = b->prec != AAO_PREC_FP64;
+    const bool sout = b->prec == AAO_PREC_MIXED || b->prec == AAO_PREC_FP32;
+    const bool sar = b->prec == AAO_PREC_FP32;
+    void *ispec = sin && !sout ? b->spec_in : b->spec;
     const BatchLaunch L = b->launch(masked);
-    BH(batch_fft_fwd(L, r, scales, sstride, b->spec, single, b->st));
-    BH(batch_solve(L, b->spec, single, single_arith, b->scheme, transpose, b->fail, b->st));
-    BH(batch_fft_inv(L, b->spec, z, single, b->st));
+    BH(batch_fft_fwd(L, r, scales, sstride, ispec, sin, b->st));
+    BH(batch_solve(L, ispec, b->spec, sin, sout, sar, b->scheme, transpose, b->fail, b->st));
+    BH(batch_fft_inv(L, b->spec, z, sout, b->st));
     return AAO_OK;
 }
 
@@ -397,7 +400,9 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
     *out = nullptr;
     if (count < 1 || !n || !ell || !kappa) return AAO_ERR_ARG;
     if (scheme != AAO_HEAT_IE && scheme != AAO_WAVE_BD2) return AAO_ERR_ARG;
-    if (prec != AAO_PREC_FP64 && prec != AAO_PREC_MIXED && prec != AAO_PREC_FP32) return AAO_ERR_ARG;
+    if (prec != AAO_PREC_FP64 && prec != AAO_PREC_MIXED && prec != AAO_PREC_FP32 &&
+        prec != AAO_PREC_MIXED_IN)
+        return AAO_ERR_ARG;
     for (int p = 0; p < count; ++p) {
         const double tp = tau ? tau[p] : 1.0 / (double)ell[p];
         if (n[p] < 1 || ell[p] < 2 || !(tp > 0.0) || !(kappa[p] > 0.0)) return AAO_ERR_ARG;
@@ -476,6 +481,9 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
         if ((s = balloc(b, (void **)&b->bhat, sizeof(double) * 2 * boff)) != AAO_OK) break;
         if ((s = balloc(b, (void **)&b->tw, sizeof(double) * 2 * 4096)) != AAO_OK) break;
         if ((s = balloc(b, &b->spec, sizeof(double) * 2 * soff)) != AAO_OK) break;
+        if (prec == AAO_PREC_MIXED_IN &&
+            (s = balloc(b, &b->spec_in, sizeof(float) * 2 * soff)) != AAO_OK)
+            break;
         if ((s = balloc(b, (void **)&b->fail, sizeof(int))) != AAO_OK) break;
         // block partials of the Gram-Schmidt slabs and of the matvec tiles
         if ((s = balloc(b, (void **)&b->part,
@@ -547,6 +555,7 @@ aao_status aao_batch_destroy(aao_batch b)
     (void)hipFree(b->bhat);
     (void)hipFree(b->tw);
     (void)hipFree(b->spec);
+    (void)hipFree(b->spec_in);
     (void)hipFree(b->fail);
     (void)hipFree(b->part);
     (void)hipFree(b->sm);

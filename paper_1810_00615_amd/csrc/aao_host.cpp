@@ -58,7 +58,8 @@ struct aao_ctx_s {
     double *tw = nullptr;        // ell complex twiddles
     double *tauk = nullptr;      // variable steps (device, ell) or null
     double *sigk = nullptr;      // tau_k - tau (device, ell)
-    void *spec = nullptr;        // half spectrum
+    void *spec = nullptr;        // half spectrum (the solves' output side)
+    void *spec_in = nullptr;     // single-precision input spectrum (AAO_PREC_MIXED_IN)
     int lds = 0;
     int *fail = nullptr;         // shifted-solve breakdown flag
     double *sym = nullptr;       // per-row d_j, e_j of the shifted solves
@@ -106,7 +107,8 @@ struct aao_ctx_s {
     double seq = 0.0;   // sequence number of the last k_reduce_small launch
 
     // launch shapes per precision mode (aao_set_config / aao_tune); -1 = default
-    int cfg[3][AAO_NUM_CFG] = {{-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
+    int cfg[4][AAO_NUM_CFG] = {
+        {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}, {-1, -1, -1, -1}};
     int cf(int kind) const { return cfg[prec][kind]; }
 
     size_t N() const { return (size_t)n * (size_t)ell; }
@@ -256,9 +258,23 @@ static aao_status dot_host(aao_ctx ctx, const double *a, const double *b, double
 // algorithmic bytes: one ell x n FP64 vector, and the half spectrum at the current
 // storage precision
 static double vec_bytes(aao_ctx ctx) { return 8.0 * (double)ctx->N(); }
-static double spec_bytes(aao_ctx ctx)
+// Element types of the preconditioner apply per precision mode: the forward transform
+// and the spectrum it writes (input side), the solves' output spectrum and the inverse
+// transform (output side), the solve arithmetic.
+static bool in_single(int prec) { return prec != AAO_PREC_FP64; }
+static bool out_single(int prec) { return prec == AAO_PREC_MIXED || prec == AAO_PREC_FP32; }
+static bool arith_single(int prec) { return prec == AAO_PREC_FP32; }
+static double spec_bytes(aao_ctx ctx, bool single)
 {
-    return (ctx->prec != AAO_PREC_FP64 ? 8.0 : 16.0) * (double)(ctx->ell / 2 + 1) * (double)ctx->n;
+    return (single ? 8.0 : 16.0) * (double)(ctx->ell / 2 + 1) * (double)ctx->n;
+}
+static double spec_in_bytes(aao_ctx ctx) { return spec_bytes(ctx, in_single(ctx->prec)); }
+static double spec_out_bytes(aao_ctx ctx) { return spec_bytes(ctx, out_single(ctx->prec)); }
+// the spectrum the forward transform writes: a separate single-precision buffer when
+// only the input side is single precision, else the solves work in place
+static void *in_spec(aao_ctx ctx)
+{
+    return in_single(ctx->prec) && !out_single(ctx->prec) ? ctx->spec_in : ctx->spec;
 }
 
 // --------------------------------------------------------------- operators
@@ -305,7 +321,7 @@ static aao_status refresh_tables(aao_ctx ctx, int cfg, bool sync)
     cfg = solve_effective_config(cfg, n);
     int cw = 0, nt = 0, stg = 0;
     solve_config_shape(cfg, &cw, &nt, &stg);
-    const int single = ctx->prec == AAO_PREC_FP32 ? 1 : 0;
+    const int single = arith_single(ctx->prec) ? 1 : 0;
     if (ctx->ptab_kappa == ctx->kappa && ctx->ptab_cw == cw && ctx->ptab_single == single)
         return AAO_OK;
     AAO_TRY(refresh_symbols(ctx));
@@ -327,35 +343,37 @@ static aao_status launch_small(aao_ctx ctx, int mode, int nv, int nblk);
 static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale,
                             const double *zprev, double *z, int transpose, bool first_norm = false)
 {
-    const bool single = ctx->prec != AAO_PREC_FP64;
-    const bool single_arith = ctx->prec == AAO_PREC_FP32;
+    const bool sin = in_single(ctx->prec), sout = out_single(ctx->prec);
+    const bool sar = arith_single(ctx->prec);
     const int n = (int)ctx->n, ell = (int)ctx->ell;
+    void *ispec = in_spec(ctx);
     AAO_TRY(refresh_symbols(ctx));
     AAO_TRY(refresh_tables(ctx, ctx->cf(AAO_CFG_SHIFTED_SOLVE), true));
+    const double solve_bytes = spec_in_bytes(ctx) + spec_out_bytes(ctx);
     if (ctx->bluestein && !zprev) {
         const BatchLaunch L = bl_launch(ctx);
-        AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) + spec_bytes(ctx),
-                     batch_fft_fwd(L, r, in_scale, 0, ctx->spec, single, ctx->st));
-        AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, 2 * spec_bytes(ctx),
-                   launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
+        AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) + spec_in_bytes(ctx),
+                     batch_fft_fwd(L, r, in_scale, 0, ispec, sin, ctx->st));
+        AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, solve_bytes,
+                   launch_shifted_solve(ispec, ctx->spec, ctx->lds, sin, sout, sar, n, ell, ctx->sym,
                                         ctx->ptab, transpose, ctx->fail, ctx->st,
                                         ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
-        AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_bytes(ctx),
-                     batch_fft_inv(L, ctx->spec, z, single, ctx->st));
+        AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_out_bytes(ctx),
+                     batch_fft_inv(L, ctx->spec, z, sout, ctx->st));
         return AAO_OK;
     }
-    AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) * (zprev ? 2 : 1) + spec_bytes(ctx),
+    AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) * (zprev ? 2 : 1) + spec_in_bytes(ctx),
                launch_fft_fwd(r, first_norm ? nullptr : in_scale, zprev, ctx->sigk, ctx->kappa,
-                              n, ell, ctx->spec, ctx->lds, single, ctx->tw, ctx->st,
+                              n, ell, ispec, ctx->lds, sin, ctx->tw, ctx->st,
                               ctx->cf(AAO_CFG_FFT_FWD), first_norm ? ctx->part : nullptr));
     if (first_norm)
-        AAO_TRY(launch_small(ctx, 4, 1, fft_fwd_blocks(ell, n, single, ctx->cf(AAO_CFG_FFT_FWD))));
-    AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, 2 * spec_bytes(ctx),
-               launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
+        AAO_TRY(launch_small(ctx, 4, 1, fft_fwd_blocks(ell, n, sin, ctx->cf(AAO_CFG_FFT_FWD))));
+    AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, solve_bytes,
+               launch_shifted_solve(ispec, ctx->spec, ctx->lds, sin, sout, sar, n, ell, ctx->sym,
                                     ctx->ptab, transpose, ctx->fail, ctx->st,
                                     ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
-    AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_bytes(ctx),
-               launch_fft_inv(ctx->spec, ctx->lds, single, z, n, ell, ctx->tw, ctx->st,
+    AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_out_bytes(ctx),
+               launch_fft_inv(ctx->spec, ctx->lds, sout, z, n, ell, ctx->tw, ctx->st,
                               ctx->cf(AAO_CFG_FFT_INV), first_norm ? in_scale : nullptr));
     return AAO_OK;
 }
@@ -405,7 +423,7 @@ void tune_append_file(int kind, int prec, int64_t n, int64_t ell, int code, doub
 std::vector<int> tune_candidates(aao_ctx ctx, int kind)
 {
     std::vector<int> out;
-    const bool single = ctx->prec != AAO_PREC_FP64;
+    const bool single = kind == AAO_CFG_FFT_INV ? out_single(ctx->prec) : in_single(ctx->prec);
     if (kind == AAO_CFG_SHIFTED_SOLVE) {
         for (int c = 0; c < solve_num_configs(); ++c)
             if (solve_config_ok(c, (int)ctx->n)) out.push_back(c);
@@ -436,19 +454,19 @@ static aao_status launch_kind(aao_ctx ctx, int kind, int code, double *buf)
                               ctx->kappa, ctx->tauk, 0, ctx->st, code));
         return AAO_OK;
     }
-    const bool single = ctx->prec != AAO_PREC_FP64;
-    const bool single_arith = ctx->prec == AAO_PREC_FP32;
+    const bool sin = in_single(ctx->prec), sout = out_single(ctx->prec);
+    const bool sar = arith_single(ctx->prec);
     const int n = (int)ctx->n, ell = (int)ctx->ell;
     if (kind == AAO_CFG_FFT_FWD)
-        AAO_HIP(launch_fft_fwd(buf, nullptr, nullptr, ctx->sigk, ctx->kappa, n, ell, ctx->spec,
-                               ctx->lds, single, ctx->tw, ctx->st, code));
+        AAO_HIP(launch_fft_fwd(buf, nullptr, nullptr, ctx->sigk, ctx->kappa, n, ell, in_spec(ctx),
+                               ctx->lds, sin, ctx->tw, ctx->st, code));
     else if (kind == AAO_CFG_SHIFTED_SOLVE) {
         AAO_TRY(refresh_tables(ctx, code, false));
-        AAO_HIP(launch_shifted_solve(ctx->spec, ctx->lds, single, single_arith, n, ell, ctx->sym,
-                                     ctx->ptab, 0, nullptr, ctx->st, code));
+        AAO_HIP(launch_shifted_solve(in_spec(ctx), ctx->spec, ctx->lds, sin, sout, sar, n, ell,
+                                     ctx->sym, ctx->ptab, 0, nullptr, ctx->st, code));
     }
     else
-        AAO_HIP(launch_fft_inv(ctx->spec, ctx->lds, single, buf, n, ell, ctx->tw, ctx->st, code));
+        AAO_HIP(launch_fft_inv(ctx->spec, ctx->lds, sout, buf, n, ell, ctx->tw, ctx->st, code));
     return AAO_OK;
 }
 
@@ -976,6 +994,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->tauk);
     (void)hipFree(ctx->sigk);
     (void)hipFree(ctx->spec);
+    (void)hipFree(ctx->spec_in);
     (void)hipFree(ctx->fail);
     (void)hipFree(ctx->sym);
     (void)hipFree(ctx->ptab);
@@ -1042,8 +1061,13 @@ aao_status aao_set_steps(aao_ctx ctx, const double *tau_k)
 aao_status aao_set_precision(aao_ctx ctx, int prec)
 {
     if (!ctx) return AAO_ERR_ARG;
-    if (prec != AAO_PREC_FP64 && prec != AAO_PREC_MIXED && prec != AAO_PREC_FP32)
+    if (prec != AAO_PREC_FP64 && prec != AAO_PREC_MIXED && prec != AAO_PREC_FP32 &&
+        prec != AAO_PREC_MIXED_IN)
         return arg_err(ctx, "unknown precision");
+    if (prec == AAO_PREC_MIXED_IN && !ctx->spec_in) {
+        const size_t H = (size_t)ctx->ell / 2 + 1;
+        AAO_TRY(dev_alloc(ctx, &ctx->spec_in, H * ctx->lds * 2 * sizeof(float)));
+    }
     ctx->prec = prec;
     return AAO_OK;
 }
@@ -1308,7 +1332,9 @@ aao_status aao_tune(aao_ctx ctx, int reps)
     aao_status s = AAO_OK;
     const size_t H = (size_t)ctx->ell / 2 + 1;
     if (launch_fill(buf, 0.0, 2 * ctx->N(), ctx->st) != hipSuccess ||
-        launch_fill((double *)ctx->spec, 0.0, H * ctx->lds * 2, ctx->st) != hipSuccess)
+        launch_fill((double *)ctx->spec, 0.0, H * ctx->lds * 2, ctx->st) != hipSuccess ||
+        (ctx->spec_in &&
+         launch_fill((double *)ctx->spec_in, 0.0, H * ctx->lds, ctx->st) != hipSuccess))
         s = AAO_ERR_HIP;
     if (s == AAO_OK) s = tune_impl(ctx, reps, buf);
     (void)hipStreamSynchronize(ctx->st);

@@ -76,16 +76,18 @@ hipError_t launch_fft_inv(const void *spec, int lds, bool single, double *z, int
 // is not a supported power of two).
 int fft_configs(int ell, int n, bool single, int *out, int cap);
 bool fft_config_ok(int cfg, int ell, int n, bool single);
-// In-place shifted solves (alpha_j M + beta_j kappa K) Y_j = X_j for every
-// half-spectrum row j; `single_arith` selects single-precision arithmetic.  sym:
-// the per-row table of launch_symbols; ptab: the partition tables of
-// launch_solve_tables for the same configuration and arithmetic.
-// cfg selects the launch shape (chunk, threads, LDS staging) among
-// solve_num_configs(); a value that is out of range or does not cover n selects
-// solve_default_config(n).
-hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
-                                int n, int ell, const double *sym, const void *ptab,
-                                int transpose, int *fail_flag, hipStream_t st, int cfg = -1);
+// Shifted solves (alpha_j M + beta_j kappa K) Y_j = X_j for every half-spectrum row
+// j: X from `in` (float2 rows if single_in, else double2), Y to `out` (float2 if
+// single_out); in == out solves in place (same element type).  `single_arith`
+// selects single-precision arithmetic (single in and out only).  sym: the per-row
+// table of launch_symbols; ptab: the partition tables of launch_solve_tables for the
+// same configuration and arithmetic.  cfg selects the launch shape (chunk, threads,
+// LDS staging) among solve_num_configs(); a value that is out of range or does not
+// cover n selects solve_default_config(n).
+hipError_t launch_shifted_solve(const void *in, void *out, int lds, bool single_in,
+                                bool single_out, bool single_arith, int n, int ell,
+                                const double *sym, const void *ptab, int transpose,
+                                int *fail_flag, hipStream_t st, int cfg = -1);
 // Per-row symbol table, (ell/2 + 1) x 2 orientations x (d, e) complex = 8 doubles a row.
 hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, hipStream_t st);
 // Partition tables (interior elimination factors and response end values) of every

@@ -58,7 +58,8 @@ extern "C" aao_status aao_apply_Pinv_noalloc(int64_t n, int64_t ell, double tau,
     if (n < 1 || ell < 2 || !(tau > 0.0) || !std::isfinite(tau) || !(kappa > 0.0) ||
         !std::isfinite(kappa) || !r || !z)
         return AAO_ERR_ARG;
-    if (prec != AAO_PREC_FP64 && prec != AAO_PREC_MIXED && prec != AAO_PREC_FP32)
+    if (prec != AAO_PREC_FP64 && prec != AAO_PREC_MIXED && prec != AAO_PREC_FP32 &&
+        prec != AAO_PREC_MIXED_IN)
         return AAO_ERR_ARG;
     Scheme sc{};
     if (!make_scheme(scheme, tau, &sc)) return AAO_ERR_ARG;
@@ -67,16 +68,19 @@ extern "C" aao_status aao_apply_Pinv_noalloc(int64_t n, int64_t ell, double tau,
     if (cfg < 0) return AAO_ERR_UNSUPPORTED;
     int cw = 0, nt = 0, stg = 0;
     solve_config_shape(cfg, &cw, &nt, &stg);
-    const bool single = prec != AAO_PREC_FP64;
+    const bool sin = prec != AAO_PREC_FP64;
+    const bool sout = prec == AAO_PREC_MIXED || prec == AAO_PREC_FP32;
     const bool single_arith = prec == AAO_PREC_FP32;
     const size_t H = (size_t)ell / 2 + 1;
     const int lds = (int)((n + 15) / 16 * 16);
-    // layout: twiddles | symbol table | partition tables | half spectrum
+    // layout: twiddles | symbol table | partition tables | half spectrum | the
+    // single-precision input spectrum when only the input side is single precision
     const size_t o_tw = 0;
     const size_t o_sym = o_tw + up256(16 * (size_t)ell);
     const size_t o_tab = o_sym + up256(64 * H);
     const size_t o_spec = o_tab + up256(2 * H * (size_t)(3 * cw + 8) * (single_arith ? 8 : 16));
-    const size_t end = o_spec + up256(H * (size_t)lds * (single ? 8 : 16));
+    const size_t o_in = o_spec + up256(H * (size_t)lds * (sout ? 8 : 16));
+    const size_t end = o_in + (sin && !sout ? up256(H * (size_t)lds * 8) : 0);
     if (end > kScratchBytes) return AAO_ERR_UNSUPPORTED;
     const size_t N = (size_t)n * (size_t)ell;
     {
@@ -94,6 +98,7 @@ extern "C" aao_status aao_apply_Pinv_noalloc(int64_t n, int64_t ell, double tau,
     double *sym = reinterpret_cast<double *>(base + o_sym);
     void *tab = base + o_tab;
     void *spec = base + o_spec;
+    void *ispec = sin && !sout ? base + o_in : spec;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int in = (int)n, il = (int)ell;
     // every table is rewritten by this call; the spectrum is fully written by the
@@ -101,11 +106,11 @@ extern "C" aao_status aao_apply_Pinv_noalloc(int64_t n, int64_t ell, double tau,
     if (launch_twiddles(tw, il, il, st) != hipSuccess ||
         launch_symbols(sym, in, il, sc, kappa, st) != hipSuccess ||
         launch_solve_tables(sym, in, il, cfg, single_arith, tab, st) != hipSuccess ||
-        launch_fft_fwd(r, nullptr, nullptr, nullptr, kappa, in, il, spec, lds, single, tw, st, -1,
+        launch_fft_fwd(r, nullptr, nullptr, nullptr, kappa, in, il, ispec, lds, sin, tw, st, -1,
                        nullptr) != hipSuccess ||
-        launch_shifted_solve(spec, lds, single, single_arith, in, il, sym, tab, transpose ? 1 : 0,
-                             nullptr, st, cfg) != hipSuccess ||
-        launch_fft_inv(spec, lds, single, z, in, il, tw, st, -1, nullptr) != hipSuccess) {
+        launch_shifted_solve(ispec, spec, lds, sin, sout, single_arith, in, il, sym, tab,
+                             transpose ? 1 : 0, nullptr, st, cfg) != hipSuccess ||
+        launch_fft_inv(spec, lds, sout, z, in, il, tw, st, -1, nullptr) != hipSuccess) {
         (void)hipGetLastError();
         return AAO_ERR_HIP;
     }

@@ -64,8 +64,11 @@ hipError_t batch_fft_fwd(const BatchLaunch &L, const double *r, const double *sc
                          void *spec, bool single, hipStream_t st);
 hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool single,
                          hipStream_t st);
-hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool single_arith,
-                       int scheme, int transpose, int *fail, hipStream_t st);
+// right-hand sides from `in`, solutions to `out` (in place when in == out); element
+// types float2 / double2 by single_in / single_out, arithmetic by single_arith
+hipError_t batch_solve(const BatchLaunch &L, const void *in, void *out, bool single_in,
+                       bool single_out, bool single_arith, int scheme, int transpose, int *fail,
+                       hipStream_t st);
 // nd = 1..4: the tiles also leave the partials of Vd[q] . y (q < nd) at
 // part[tile * ldp + q] (reduced per problem over L.mranges); nd = -1: the partial
 // of y . y at part[tile * ldp]

@@ -334,25 +334,29 @@ k_batch_fft_inv(const BProb *__restrict__ probs, const int2 *__restrict__ tiles,
 }
 
 // ------------------------------------------------------------ shifted solves
-template <typename A, typename S>
+// Right-hand sides read from `in` (element type SI), solutions written to `out` (SO);
+// in == out with SI == SO solves in place (a workgroup reads its row before writing).
+template <typename A, typename SI, typename SO>
 __global__ void __launch_bounds__(512)
 k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, int nrows,
-              const unsigned char *__restrict__ active, cx<S> *__restrict__ spec, int scheme,
-              int transpose, int *__restrict__ fail)
+              const unsigned char *__restrict__ active, const cx<SI> *in, cx<SO> *out,
+              int scheme, int transpose, int *__restrict__ fail)
 {
     constexpr int CW = 8;
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
     cx<A> *tab = reinterpret_cast<cx<A> *>(smraw);
     cx<A> *red = tab + psolve_tab_entries(CW);
-    cx<S> *stage = reinterpret_cast<cx<S> *>(red);
+    cx<SI> *stage = reinterpret_cast<cx<SI> *>(red);
+    cx<SO> *ostage = reinterpret_cast<cx<SO> *>(red);
     const int g = blockIdx.x;
     if (g >= nrows) return;
     const int2 e = rows[g];
     if (active && !active[e.x]) return;
     const BProb pb = probs[e.x];
     const int j = e.y, n = pb.n, ell = pb.ell, t = threadIdx.x;
-    cx<S> *row = spec + pb.soff + (size_t)j * pb.lds;
+    const cx<SI> *row = in + pb.soff + (size_t)j * pb.lds;
+    cx<SO> *orow = out + pb.soff + (size_t)j * pb.lds;
     // heat: alpha = 1 - w^j, beta = tau;  BD2: alpha = (1 - w^j)^2, beta = tau^2
     double sn, cs;
     sincospi((transpose ? 2.0 : -2.0) * (double)j / (double)ell, &sn, &cs);
@@ -366,17 +370,19 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
     const double h = 1.0 / (n + 1.0), kap = pb.kappa;
     const cx<A> d = {A(ar * (4.0 * h / 6.0) + br * kap * (2.0 / h)), A(ai * (4.0 * h / 6.0) + bi * kap * (2.0 / h))};
     const cx<A> ee = {A(ar * (h / 6.0) - br * kap / h), A(ai * (h / 6.0) - bi * kap / h)};
-    constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
+    constexpr int PAD = sizeof(cx<SI>) == 16 ? 2 : 4;
+    constexpr int OPAD = sizeof(cx<SO>) == 16 ? 2 : 4;
     const int NTP = NT + PAD;
+    const int ONTP = NT + OPAD;
     const int P = (n + CW - 1) / CW;
     const int len = (t < P) ? min(CW, n - t * CW) : 0;
     {
         // CW elements per thread (n <= CW NT), loaded together: unconditional at a
         // clamped index, parts kept apart (a whole-struct array would live in scratch)
-        S lx[CW], ly[CW];
+        SI lx[CW], ly[CW];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-            const cx<S> v = row[min(t + k * NT, n - 1)];
+            const cx<SI> v = row[min(t + k * NT, n - 1)];
             lx[k] = v.x;
             ly[k] = v.y;
         }
@@ -392,16 +398,16 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
     for (int i = 0; i < CW; ++i) {
         y[i] = {A(0), A(0)};
         if (i < len) {
-            const cx<S> v = stage[i * NTP + t];
+            const cx<SI> v = stage[i * NTP + t];
             y[i] = {A(v.x), A(v.y)};
         }
     }
     const bool bad = partition_solve<A, CW>(y, n, d, ee, tab, red);
 #pragma unroll
     for (int i = 0; i < CW; ++i)
-        if (i < len) stage[i * NTP + t] = {S(y[i].x), S(y[i].y)};
+        if (i < len) ostage[i * ONTP + t] = {SO(y[i].x), SO(y[i].y)};
     __syncthreads();
-    for (int q = t; q < n; q += NT) row[q] = stage[(q % CW) * NTP + q / CW];
+    for (int q = t; q < n; q += NT) orow[q] = ostage[(q % CW) * ONTP + q / CW];
     if (bad && fail) atomicOr(fail, 1);
 }
 
@@ -932,9 +938,10 @@ hipError_t batch_prepare()
     AAO_ATTR(k_batch_fft_fwd<double>, bl_smem(sizeof(double)))
     AAO_ATTR(k_batch_fft_inv<float>, bl_smem(sizeof(float)))
     AAO_ATTR(k_batch_fft_inv<double>, bl_smem(sizeof(double)))
-    AAO_ATTR((k_batch_solve<double, double>), solve_smem(16, 16))
-    AAO_ATTR((k_batch_solve<double, float>), solve_smem(8, 16))
-    AAO_ATTR((k_batch_solve<float, float>), solve_smem(8, 8))
+    AAO_ATTR((k_batch_solve<double, double, double>), solve_smem(16, 16))
+    AAO_ATTR((k_batch_solve<double, float, float>), solve_smem(8, 16))
+    AAO_ATTR((k_batch_solve<float, float, float>), solve_smem(8, 8))
+    AAO_ATTR((k_batch_solve<double, float, double>), solve_smem(16, 16))
 #undef AAO_ATTR
     return hipSuccess;
 }
@@ -987,27 +994,35 @@ hipError_t batch_fft_inv(const BatchLaunch &L, const void *spec, double *z, bool
     return hipGetLastError();
 }
 
-hipError_t batch_solve(const BatchLaunch &L, void *spec, bool single, bool single_arith,
-                       int scheme, int transpose, int *fail, hipStream_t st)
+hipError_t batch_solve(const BatchLaunch &L, const void *in, void *out, bool single_in,
+                       bool single_out, bool single_arith, int scheme, int transpose, int *fail,
+                       hipStream_t st)
 {
+    if ((in == out && single_in != single_out) || (single_arith && !(single_in && single_out)) ||
+        (!single_in && single_out))
+        return hipErrorInvalidValue;
     // one launch per class of n: NT = 64 << c threads cover n <= 8 NT unknowns
     for (int c = 0; c < kSolveClasses; ++c) {
         const int first = L.row_start[c], count = L.row_start[c + 1] - first;
         if (count <= 0) continue;
         const int NT = 64 << c;
         const int2 *rows = L.rows + first;
-        if (!single) {
-            k_batch_solve<double, double><<<count, NT, solve_smem(16, 16, NT), st>>>(
-                L.probs, rows, count, L.active, reinterpret_cast<cx<double> *>(spec), scheme,
-                transpose, fail);
+        if (!single_in) {
+            k_batch_solve<double, double, double><<<count, NT, solve_smem(16, 16, NT), st>>>(
+                L.probs, rows, count, L.active, reinterpret_cast<const cx<double> *>(in),
+                reinterpret_cast<cx<double> *>(out), scheme, transpose, fail);
+        } else if (!single_out) {
+            k_batch_solve<double, float, double><<<count, NT, solve_smem(16, 16, NT), st>>>(
+                L.probs, rows, count, L.active, reinterpret_cast<const cx<float> *>(in),
+                reinterpret_cast<cx<double> *>(out), scheme, transpose, fail);
         } else if (!single_arith) {
-            k_batch_solve<double, float><<<count, NT, solve_smem(8, 16, NT), st>>>(
-                L.probs, rows, count, L.active, reinterpret_cast<cx<float> *>(spec), scheme,
-                transpose, fail);
+            k_batch_solve<double, float, float><<<count, NT, solve_smem(8, 16, NT), st>>>(
+                L.probs, rows, count, L.active, reinterpret_cast<const cx<float> *>(in),
+                reinterpret_cast<cx<float> *>(out), scheme, transpose, fail);
         } else {
-            k_batch_solve<float, float><<<count, NT, solve_smem(8, 8, NT), st>>>(
-                L.probs, rows, count, L.active, reinterpret_cast<cx<float> *>(spec), scheme,
-                transpose, fail);
+            k_batch_solve<float, float, float><<<count, NT, solve_smem(8, 8, NT), st>>>(
+                L.probs, rows, count, L.active, reinterpret_cast<const cx<float> *>(in),
+                reinterpret_cast<cx<float> *>(out), scheme, transpose, fail);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

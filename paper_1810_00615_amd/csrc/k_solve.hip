@@ -29,27 +29,34 @@ namespace aao {
 // i*(NT/2+PAD) + t, PAD = 2 for 16-byte and 4 for 8-byte elements, which spreads
 // both the chunk-wise and the coalesced accesses over all banks.  Otherwise every
 // thread reads and writes its own chunk directly.
-template <typename A, typename S, int CW, int NTB, bool STAGE>
+// The right-hand sides are read from `in` (element type SI) and the solutions written
+// to `out` (element type SO); in == out (with SI == SO) solves in place: a workgroup
+// reads its whole row before it writes any of it.
+template <typename A, typename SI, typename SO, int CW, int NTB, bool STAGE>
 __global__ void __launch_bounds__(NTB)
-k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restrict__ sym,
+k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__restrict__ sym,
                 const cx<A> *__restrict__ ptab, int transpose, int *__restrict__ fail)
 {
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
     cx<A> *tab = reinterpret_cast<cx<A> *>(smraw);
     cx<A> *red = tab + psolve_tab_entries(CW);
-    cx<S> *stage = reinterpret_cast<cx<S> *>(red);
+    cx<SI> *stage = reinterpret_cast<cx<SI> *>(red);
+    cx<SO> *ostage = reinterpret_cast<cx<SO> *>(red);
 
     const int j = blockIdx.x;
     const int t = threadIdx.x;
-    cx<S> *row = spec + (size_t)j * lds;
+    const cx<SI> *row = in + (size_t)j * lds;
+    cx<SO> *orow = out + (size_t)j * lds;
 
     const int P = (n + CW - 1) / CW;
     const int a0 = t * CW;
     const int len = (t < P) ? min(CW, n - a0) : 0;
-    constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
+    constexpr int PAD = sizeof(cx<SI>) == 16 ? 2 : 4;
+    constexpr int OPAD = sizeof(cx<SO>) == 16 ? 2 : 4;
     const int NH = NT / 2;                       // threads per staged half
     const int NTP = NH + PAD;
+    const int ONTP = NH + OPAD;
     const int H = NH * CW;                       // unknowns per staged half
     const int mine = t / NH;                     // the half holding this thread's chunk
     const int tl = t - mine * NH;
@@ -63,10 +70,10 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
         for (int half = 0; half < 2; ++half) {
             const int q0 = half * H;
             const int q1 = min(n, q0 + H);
-            S lx[KH], ly[KH];   // separate parts: a whole-struct array would live in scratch
+            SI lx[KH], ly[KH];   // separate parts: a whole-struct array would live in scratch
 #pragma unroll
             for (int k = 0; k < KH; ++k) {
-                const cx<S> v = row[min(q0 + t + k * NT, n - 1)];
+                const cx<SI> v = row[min(q0 + t + k * NT, n - 1)];
                 lx[k] = v.x;
                 ly[k] = v.y;
             }
@@ -84,7 +91,7 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
 #pragma unroll
                 for (int i = 0; i < CW; ++i)
                     if (i < len) {
-                        const cx<S> v = stage[i * NTP + tl];
+                        const cx<SI> v = stage[i * NTP + tl];
                         y[i] = {A(v.x), A(v.y)};
                     }
             }
@@ -93,7 +100,7 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
     } else {
 #pragma unroll
         for (int i = 0; i < CW; ++i) {
-            const cx<S> v = row[min(a0 + i, n - 1)];   // unconditional: all in flight
+            const cx<SI> v = row[min(a0 + i, n - 1)];   // unconditional: all in flight
             if (i < len) y[i] = {A(v.x), A(v.y)};
         }
     }
@@ -113,18 +120,18 @@ k_shifted_solve(cx<S> *__restrict__ spec, int lds, int n, const double *__restri
             if (mine == half) {
 #pragma unroll
                 for (int i = 0; i < CW; ++i)
-                    if (i < len) stage[i * NTP + tl] = {S(y[i].x), S(y[i].y)};
+                    if (i < len) ostage[i * ONTP + tl] = {SO(y[i].x), SO(y[i].y)};
             }
             __syncthreads();
             for (int q = q0 + t; q < q1; q += NT) {
                 const int ql = q - q0;
-                row[q] = stage[(ql % CW) * NTP + ql / CW];
+                orow[q] = ostage[(ql % CW) * ONTP + ql / CW];
             }
         }
     } else {
 #pragma unroll
         for (int i = 0; i < CW; ++i)
-            if (i < len) row[a0 + i] = {S(y[i].x), S(y[i].y)};
+            if (i < len) orow[a0 + i] = {SO(y[i].x), SO(y[i].y)};
     }
     if (bad && fail) atomicOr(fail, 1);
 }
@@ -182,39 +189,48 @@ int solve_default_config(int n)
     return -1;
 }
 
-template <typename A, typename S, int CW, int NT, bool STAGE>
-static hipError_t solve_go(void *spec, int lds, int n, int ell, const double *sym,
+template <typename S>
+static constexpr size_t stage_bytes(int cw, int nt)
+{
+    return sizeof(cx<S>) * (size_t)cw * (nt / 2 + (sizeof(cx<S>) == 16 ? 2 : 4));
+}
+
+template <typename A, typename SI, typename SO, int CW, int NT, bool STAGE>
+static hipError_t solve_go(const void *in, void *out, int lds, int n, int ell, const double *sym,
                            const void *ptab, int transpose, int *fail, hipStream_t st)
 {
     size_t smem = sizeof(cx<A>) * psolve_lds_entries(CW, NT);
     if (STAGE) {
-        constexpr int PAD = sizeof(cx<S>) == 16 ? 2 : 4;
-        const size_t stg =
-            sizeof(cx<A>) * psolve_tab_entries(CW) + sizeof(cx<S>) * CW * (NT / 2 + PAD);
+        const size_t so = stage_bytes<SI>(CW, NT) > stage_bytes<SO>(CW, NT)
+                              ? stage_bytes<SI>(CW, NT)
+                              : stage_bytes<SO>(CW, NT);
+        const size_t stg = sizeof(cx<A>) * psolve_tab_entries(CW) + so;
         if (stg > smem) smem = stg;
     }
-    auto kern = k_shifted_solve<A, S, CW, NT, STAGE>;
+    auto kern = k_shifted_solve<A, SI, SO, CW, NT, STAGE>;
     if (smem > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    kern<<<ell / 2 + 1, NT, smem, st>>>(reinterpret_cast<cx<S> *>(spec), lds, n, sym,
+    kern<<<ell / 2 + 1, NT, smem, st>>>(reinterpret_cast<const cx<SI> *>(in),
+                                        reinterpret_cast<cx<SO> *>(out), lds, n, sym,
                                         reinterpret_cast<const cx<A> *>(ptab), transpose, fail);
     return hipGetLastError();
 }
 
-template <typename A, typename S>
-static hipError_t solve_disp(int cfg, void *spec, int lds, int n, int ell, const double *sym,
-                             const void *ptab, int transpose, int *fail, hipStream_t st)
+template <typename A, typename SI, typename SO>
+static hipError_t solve_disp(int cfg, const void *in, void *out, int lds, int n, int ell,
+                             const double *sym, const void *ptab, int transpose, int *fail,
+                             hipStream_t st)
 {
     const bool stage = cfg >= kNumSolveCfg;
 #define AAO_SCFG(I, CW, NT)                                                                    \
     case I:                                                                                    \
-        return stage ? solve_go<A, S, CW, NT, true>(spec, lds, n, ell, sym, ptab, transpose,     \
-                                                    fail, st)                                  \
-                     : solve_go<A, S, CW, NT, false>(spec, lds, n, ell, sym, ptab, transpose,    \
-                                                     fail, st);
+        return stage ? solve_go<A, SI, SO, CW, NT, true>(in, out, lds, n, ell, sym, ptab,        \
+                                                         transpose, fail, st)                  \
+                     : solve_go<A, SI, SO, CW, NT, false>(in, out, lds, n, ell, sym, ptab,       \
+                                                          transpose, fail, st);
     switch (cfg % kNumSolveCfg) {
         AAO_SCFG(0, 1, 256)
         AAO_SCFG(1, 2, 256)
@@ -453,19 +469,29 @@ hipError_t launch_solve_tables(const double *sym, int n, int ell, int cfg, bool 
                         : ptab_disp<double>(cw, sym, n, ell, out, st);
 }
 
-hipError_t launch_shifted_solve(void *spec, int lds, bool single_store, bool single_arith,
-                                int n, int ell, const double *sym, const void *ptab,
-                                int transpose, int *fail_flag, hipStream_t st, int cfg)
+hipError_t launch_shifted_solve(const void *in, void *out, int lds, bool single_in,
+                                bool single_out, bool single_arith, int n, int ell,
+                                const double *sym, const void *ptab, int transpose,
+                                int *fail_flag, hipStream_t st, int cfg)
 {
     cfg = solve_effective_config(cfg, n);
     if (cfg < 0 || !ptab) return hipErrorInvalidValue;
-    if (!single_store)
-        return solve_disp<double, double>(cfg, spec, lds, n, ell, sym, ptab, transpose,
-                                          fail_flag, st);
-    if (!single_arith)
-        return solve_disp<double, float>(cfg, spec, lds, n, ell, sym, ptab, transpose,
-                                         fail_flag, st);
-    return solve_disp<float, float>(cfg, spec, lds, n, ell, sym, ptab, transpose, fail_flag, st);
+    if (in == out && single_in != single_out) return hipErrorInvalidValue;
+    if (single_arith) {
+        if (!single_in || !single_out) return hipErrorInvalidValue;
+        return solve_disp<float, float, float>(cfg, in, out, lds, n, ell, sym, ptab, transpose,
+                                               fail_flag, st);
+    }
+    if (!single_in && !single_out)
+        return solve_disp<double, double, double>(cfg, in, out, lds, n, ell, sym, ptab,
+                                                  transpose, fail_flag, st);
+    if (single_in && single_out)
+        return solve_disp<double, float, float>(cfg, in, out, lds, n, ell, sym, ptab, transpose,
+                                                fail_flag, st);
+    if (single_in)
+        return solve_disp<double, float, double>(cfg, in, out, lds, n, ell, sym, ptab,
+                                                 transpose, fail_flag, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace aao

@@ -97,22 +97,27 @@ def test_heat_full_gmres_vs_oracle(heat2, orc):
     assert e < 1e-8
 
 
-def test_heat_full_gmres_mixed(heat2, orc):
+@pytest.mark.parametrize("prec", ["mixed", "mixed_in"])
+def test_heat_full_gmres_mixed(heat2, orc, prec):
     """Single-precision preconditioner inside FP64 flexible GMRES reaches the same 1e-8 true
-    residual (checked by the oracle's FP64 matvec)."""
+    residual (checked by the oracle's FP64 matvec); with single precision on the input
+    side only it takes the FP64 solve's two iterations."""
     w, P, u0r, br = heat2
     import torch
     b = torch.from_numpy(br).to(P.device)
-    P.set_precision("mixed")
+    P.set_precision(prec)
     try:
         U, info = P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit)
     finally:
         P.set_precision("fp64")
     Ug = U.cpu().numpy()
+    print(f"heat full {prec}: iters {info['iters']} true res {info['rel_resid_true']:.2e}")
     assert info["converged"]
     assert true_resid(orc, HEAT, w, Ug, br) <= w.tol
     Ur = orc.solve_seq(HEAT, w.n, w.ell, w.tau, w.kappa, br)
     assert normrel(Ug, Ur) < 1e-8
+    if prec == "mixed_in":
+        assert info["iters"] == 2
 
 
 @pytest.mark.parametrize("delta,q", [(0.5, 0), (0.5, 1), (0.9, 2)])

@@ -156,6 +156,29 @@ def test_pinv_reduced_precision(aao, orc, torch_dev, scheme, prec, tol, n, ell):
     assert normrel(z, ref) < tol
 
 
+@pytest.mark.parametrize("scheme", [HEAT, BD2])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("n,ell", [(63, 64), (255, 256), (4095, 16), (1023, 1024)])
+def test_pinv_mixed_in_backward_error(aao, orc, torch_dev, scheme, transpose, n, ell):
+    """Single precision on the input side only (forward transform and its spectrum):
+    the result is the exact C^{-1} of an input perturbed at the single-precision level,
+    i.e. the backward error ||C z - r|| / ||r|| (FP64 oracle product with C) is a small
+    multiple of the single-precision unit, while the full single-precision form
+    (output spectrum and inverse transform too) has a larger one."""
+    tau = 1.0 / ell
+    r = rand_vec((ell, n), [n, ell, 9])
+    out = {}
+    for prec in ("mixed_in", "mixed"):
+        P = aao.Problem(n, ell, tau, sched(scheme), precision=prec, device=torch_dev[1])
+        z = P.Pinv(to_dev(torch_dev, r), transpose=transpose).cpu().numpy()
+        Cz = orc.apply_C(scheme, n, ell, tau, 1.0, z, transpose=transpose)
+        out[prec] = normrel(Cz, r)
+    print(f"backward error scheme={scheme} n={n} ell={ell} tr={transpose}: "
+          f"mixed_in {out['mixed_in']:.2e}, mixed {out['mixed']:.2e}")
+    assert out["mixed_in"] < 2e-6
+    assert out["mixed_in"] <= out["mixed"]
+
+
 @pytest.mark.parametrize("q", [0, 1, 2])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_neumann_orders(aao, orc, torch_dev, q, transpose):
@@ -202,7 +225,7 @@ def test_gmres_heat_small(aao, orc, torch_dev):
     assert normrel(U.cpu().numpy(), x_o) < 1e-10
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_in"])
 def test_gmres_bd2_small(aao, orc, torch_dev, prec):
     n, ell = 127, 256
     tau = 1.0 / ell
@@ -220,6 +243,29 @@ def test_gmres_bd2_small(aao, orc, torch_dev, prec):
     r_true = orc.build_rhs(BD2, n, ell, tau, 1.0, u0r, v0r) - orc.apply_A(BD2, n, ell, tau, 1.0, U.cpu().numpy())
     assert np.linalg.norm(r_true) / np.linalg.norm(orc.build_rhs(BD2, n, ell, tau, 1.0, u0r, v0r)) < 1e-8
     assert normrel(U.cpu().numpy(), Ur) < 1e-4
+
+
+def test_gmres_mixed_in_same_iterations(aao, orc, torch_dev):
+    """Heat n=1023, ell=1024, 50-mode data, FGMRES(30) to 1e-8: the input-side
+    single-precision form takes the FP64 form's iteration count (the full
+    single-precision form takes one more) and meets the true residual (oracle
+    FP64 matvec)."""
+    from paper_1810_00615_amd.inputs import sine_amps
+    n, ell = 1023, 1024
+    tau = 1.0 / ell
+    m, a = sine_amps([2, 0], 50)
+    its = {}
+    for prec in ("fp64", "mixed_in", "mixed"):
+        P = aao.Problem(n, ell, tau, "heat", precision=prec, device=torch_dev[1])
+        b = P.rhs(P.project_sine(m, a))
+        U, info = P.solve(b, restart=30, tol=1e-8, maxit=100)
+        bn = b.cpu().numpy()
+        res = np.linalg.norm(bn - orc.apply_A(HEAT, n, ell, tau, 1.0, U.cpu().numpy())) / np.linalg.norm(bn)
+        assert info["converged"] and res <= 1e-8, (prec, res)
+        its[prec] = info["iters"]
+    print("iterations:", its)
+    assert its["mixed_in"] == its["fp64"]
+    assert its["mixed"] >= its["mixed_in"]
 
 
 @pytest.mark.parametrize("scheme,restart", [(HEAT, 50), (BD2, 8), (BD2, 60)])

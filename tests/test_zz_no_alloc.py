@@ -1,8 +1,8 @@
 """The allocation-free preconditioner apply (aao_apply_Pinv_noalloc) against the
-context-based aao_apply_Pinv, both called through the C ABI: two calls in a row on
-the shared static scratch, the second with a smaller input (and another scheme,
-precision and orientation), each checked against the context path and against the
-oracle; sizes beyond the static array are rejected before any launch."""
+context-based aao_apply_Pinv, both called through the C ABI: calls in a row on the
+shared static scratch, each with a smaller input than the one before (and another
+scheme, precision and orientation), each checked against the context path and
+against the oracle; sizes beyond the static array are rejected before any launch."""
 import ctypes
 
 import numpy as np
@@ -11,7 +11,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 HEAT, BD2 = 0, 1
-FP64, MIXED = 0, 1
+FP64, MIXED, MIXED_IN = 0, 1, 3
 UNSUPPORTED = -6
 
 
@@ -60,6 +60,7 @@ def test_noalloc_matches_context_apply_twice(L, orc):
     cases = [  # (n, ell, kappa, scheme, precision, transpose, tolerance vs context, vs oracle)
         (1023, 1024, 1.3, HEAT, FP64, 0, 1e-14, 1e-10),
         (63, 64, 0.8, BD2, MIXED, 1, 1e-14, 2e-5),
+        (31, 32, 1.1, HEAT, MIXED_IN, 0, 1e-14, 1e-5),
     ]
     for k, (n, ell, kappa, scheme, prec, tr, tol_ctx, tol_orc) in enumerate(cases):
         tau = 1.0 / ell
