@@ -7,13 +7,14 @@ with the GPU library (``paper_1810_00615_amd``) and never imports it.
 What the oracle computes, and the passage of Goddard & Wathen (arXiv
 1810.00615) each function follows:
 
-* ``apply_A`` / ``solve_seq`` / ``adjoint_seq`` -- the monolithic block
-  lower-triangular Toeplitz system of Sec. 2 (eq. monolithicheat for heat, the
-  system C_BD2 for the wave equation, eq. nonuniformmonolithicheat with variable
-  steps).  ``solve_seq`` is forward block substitution, i.e. the sequential
-  implicit time stepping of eq. timestepproblem1: the exact solution U.
+* ``apply_A`` / ``solve_seq`` / ``adjoint_seq`` -- the monolithic systems of
+  Sec. 2: eq. monolithicheat for heat, the systems C_BD2 and C_BD4 (two start-up
+  rows) and the two-sided central-difference system C_CD for the wave equation,
+  eq. nonuniformmonolithicheat with variable steps.  ``solve_seq`` is forward block
+  substitution, i.e. the sequential time stepping the monolithic system packages
+  (block tridiagonal elimination for C_CD): the exact solution U.
 * ``apply_C`` -- the block circulant preconditioner (eq. standardheatprecon,
-  eq. wavepreconditioner).
+  eq. wavepreconditioner, R_BD4, R_CD).
 * ``dft`` -- the direct O(ell^2) transform along time (the (U (x) I_n) factor of
   eq. precon2para in the per-column form of eq. alternativecal).
 * ``pinv_direct`` / ``pinv`` -- C^{-1} r by the Fourier diagonalisation of
@@ -39,6 +40,8 @@ import numpy as np
 
 HEAT = 0
 BD2 = 1
+BD4 = 2
+CD = 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "aao_oracle.c")
@@ -67,7 +70,8 @@ def _load():
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
-        for name in ("or_scheme_coeffs", "or_load_sine", "or_project_sine", "or_build_rhs",
+        for name in ("or_scheme_coeffs", "or_toeplitz", "or_block", "or_load_sine",
+                     "or_project_sine", "or_build_rhs",
                      "or_solve_seq", "or_adjoint_seq", "or_apply_A", "or_apply_C", "or_apply_E",
                      "or_shifted_solve_all", "or_pinv_direct", "or_grad", "or_mk_solve"):
             getattr(lib, name).restype = ctypes.c_int
@@ -115,13 +119,29 @@ def mk_solve(n, cm, ck, r):
     return x
 
 
-def scheme_coeffs(scheme, tau):
+def toeplitz(scheme, tau):
+    """(mlo, a, b): the Toeplitz blocks a_m M + b_m kappa K of the scheme for offsets
+    m = mlo .. mlo + len(a) - 1 (block (k, k - m) of the monolithic matrix)."""
     a = np.zeros(4)
     b = np.zeros(4)
-    s = _load().or_scheme_coeffs(scheme, ctypes.c_double(tau), _p(a), _p(b))
-    if s < 0:
+    mlo = ctypes.c_int(0)
+    mhi = ctypes.c_int(0)
+    if _load().or_toeplitz(scheme, ctypes.c_double(tau), ctypes.byref(mlo), ctypes.byref(mhi),
+                           _p(a), _p(b)) != 0:
         raise ValueError("unknown scheme")
-    return a[: s + 1].copy(), b[: s + 1].copy()
+    k = mhi.value - mlo.value + 1
+    return mlo.value, a[:k].copy(), b[:k].copy()
+
+
+def block(scheme, ell, tau, kappa, k, m, tau_k=None):
+    """(cm, ck) of the block in row k, column k - m (cm M + ck K), or None."""
+    cm = ctypes.c_double(0.0)
+    ck = ctypes.c_double(0.0)
+    tk = None if tau_k is None else _c(tau_k)
+    ok = _load().or_block(scheme, ctypes.c_double(tau), ctypes.c_double(kappa),
+                          _p(tk) if tk is not None else None, ell, k, m, ctypes.byref(cm),
+                          ctypes.byref(ck))
+    return (cm.value, ck.value) if ok else None
 
 
 def load_sine(n, modes, amps):

@@ -18,11 +18,19 @@
  *     Sec. 2, eq. applyEuler); the diffusivity kappa multiplies K.
  *   - a vector of the monolithic system is ell x n, row k = time level k+1,
  *     row-major (the ordering [u_1; ...; u_ell] of eq. monolithicheat).
- *   - block m of the lower-triangular Toeplitz matrix is A_m = a_m M + b_m kappa K.
+ *   - the block in row k, column k - m of the monolithic matrix is
+ *     a_m M + b_m kappa K (or_block); Toeplitz schemes use the same pair on every row:
  *       heat, implicit Euler (eq. timestepproblem1, read as M + tau K):
  *             A_0 = M + tau kappa K, A_1 = -M
  *       wave, BD2 (eq. BD2 and the system C_BD2):
  *             A_0 = M + tau^2 kappa K, A_1 = -2M, A_2 = M
+ *       wave, BD4 (eq. BD4 and the system C_BD4): A_0 = 2M + tau^2 kappa K,
+ *             A_1 = -5M, A_2 = 4M, A_3 = -M from the third row on; the first two rows
+ *             are the start-up rows B u_1 and C u_1 + B u_2, B = M + tau^2 kappa K,
+ *             C = -2M (not Toeplitz)
+ *       wave, central differences (eq. CenDiffDisc and the system C_CD): two-sided,
+ *             M u_{k-1} + (tau^2 kappa K - 2M) u_k + M u_{k+1}, i.e. offsets
+ *             m = -1, 0, 1 (the last row has no u_{ell+1})
  *   - the DFT along time is X_j = sum_k x_k w^{jk}, w = exp(-2 pi i/ell).
  */
 #include <complex.h>
@@ -32,27 +40,89 @@
 
 #define OR_HEAT 0
 #define OR_BD2 1
+#define OR_BD4 2
+#define OR_CD 3
 
 /* ---------------------------------------------------------------- scheme */
 
-/* Block coefficients (a_m, b_m), m = 0..s, of the monolithic matrix.
- * Heat: eq. monolithicheat (A_0 = M + tau K after the implicit Euler step,
- * A_1 = -M).  Wave BD2: the system C_BD2 (A_0 = M + tau^2 K, A_1 = -2M,
- * A_2 = M).  Returns s, or -1 for an unknown scheme. */
-int or_scheme_coeffs(int scheme, double tau, double *a, double *b)
+/* Toeplitz coefficients (a_m, b_m) of the scheme for offsets m = mlo..mhi (entry
+ * m - mlo): the blocks a_m M + b_m kappa K of every row away from the start-up rows,
+ * and so the blocks of the circulant preconditioner.
+ *   heat: eq. monolithicheat (A_0 = M + tau K after the implicit Euler step, A_1 = -M)
+ *   BD2:  the system C_BD2 (A_0 = M + tau^2 K, A_1 = -2M, A_2 = M)
+ *   BD4:  the system C_BD4 (A_0 = 2M + tau^2 K, A_1 = -5M, A_2 = 4M, A_3 = -M)
+ *   CD:   the system C_CD (M below, tau^2 K - 2M on, M above the diagonal)
+ * Returns 0, or -1 for an unknown scheme. */
+int or_toeplitz(int scheme, double tau, int *mlo, int *mhi, double *a, double *b)
 {
-    if (scheme == OR_HEAT) {
+    const double t2 = tau * tau;
+    switch (scheme) {
+    case OR_HEAT:
+        *mlo = 0; *mhi = 1;
         a[0] = 1.0;  b[0] = tau;
         a[1] = -1.0; b[1] = 0.0;
-        return 1;
-    }
-    if (scheme == OR_BD2) {
-        a[0] = 1.0;  b[0] = tau * tau;
+        return 0;
+    case OR_BD2:
+        *mlo = 0; *mhi = 2;
+        a[0] = 1.0;  b[0] = t2;
         a[1] = -2.0; b[1] = 0.0;
         a[2] = 1.0;  b[2] = 0.0;
-        return 2;
+        return 0;
+    case OR_BD4:
+        *mlo = 0; *mhi = 3;
+        a[0] = 2.0;  b[0] = t2;
+        a[1] = -5.0; b[1] = 0.0;
+        a[2] = 4.0;  b[2] = 0.0;
+        a[3] = -1.0; b[3] = 0.0;
+        return 0;
+    case OR_CD:
+        *mlo = -1; *mhi = 1;
+        a[0] = 1.0;  b[0] = 0.0;     /* m = -1: M u_{k+1} */
+        a[1] = -2.0; b[1] = t2;      /* m =  0 */
+        a[2] = 1.0;  b[2] = 0.0;     /* m =  1: M u_{k-1} */
+        return 0;
+    default:
+        return -1;
     }
-    return -1;
+}
+
+/* Lower-triangular Toeplitz schemes (heat, BD2, BD4): coefficients of offsets
+ * 0..s; returns s, or -1 (unknown scheme, or a two-sided scheme). */
+int or_scheme_coeffs(int scheme, double tau, double *a, double *b)
+{
+    int mlo, mhi;
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0 || mlo != 0) return -1;
+    return mhi;
+}
+
+/* The block in row k (0-based), column k - m of the monolithic matrix of size
+ * ell: *cm M + *ck K.  Returns 1 if that block exists, else 0 (outside the matrix
+ * or zero).  BD4 rows 0 and 1 are the start-up rows of the system C_BD4; with
+ * variable steps tau_k (heat, eq. nonuniformmonolithicheat) the diagonal block of
+ * row k is M + tau_k kappa K. */
+int or_block(int scheme, double tau, double kappa, const double *tau_k, int ell, int k, int m,
+             double *cm, double *ck)
+{
+    double a[4], b[4];
+    int mlo, mhi;
+    if (k < 0 || k >= ell || k - m < 0 || k - m >= ell) return 0;
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0 || m < mlo || m > mhi) return 0;
+    *cm = a[m - mlo];
+    *ck = b[m - mlo] * kappa;
+    if (scheme == OR_HEAT && m == 0 && tau_k) *ck = tau_k[k] * kappa;
+    if (scheme == OR_BD4 && k < 2) {
+        /* start-up rows: B u_1 = .., C u_1 + B u_2 = .. (BD2 steps) */
+        if (m == 0) {
+            *cm = 1.0;
+            *ck = tau * tau * kappa;
+        } else if (m == 1) {
+            *cm = -2.0;
+            *ck = 0.0;
+        } else {
+            return 0;
+        }
+    }
+    return 1;
 }
 
 /* ------------------------------------------------------- space operators */
@@ -144,11 +214,16 @@ int or_project_sine(int n, int J, const int *modes, const double *amps, double *
 }
 
 /* Right-hand side b of the monolithic system (ell x n, all rows but the first
- * one or two are zero).
+ * one to three are zero).
  *   heat (eq. monolithicheat): b_1 = M u_0.
  *   BD2  (system C_BD2): b_1 = A_0 (u_0 + tau v_0), b_2 = -M u_0; the first row
  *        is the start-up step u_1 = u_0 + tau v_0, which is the printed row
- *        A_0 u_1 = (M + tau^2 K) u_0 when the initial velocity v_0 is zero. */
+ *        A_0 u_1 = (M + tau^2 K) u_0 when the initial velocity v_0 is zero.
+ *   BD4  (system C_BD4): b_1 = B (u_0 + tau v_0), b_2 = -M u_0, b_3 = M u_0 (the
+ *        same start-up step; the u_0 terms of the second and third rows moved to
+ *        the right).
+ *   CD   (system C_CD): b_1 = -M u_0; the scheme takes no initial velocity (v_0 must
+ *        be NULL). */
 int or_build_rhs(int scheme, int n, int ell, double tau, double kappa,
                  const double *u0, const double *v0, double *b)
 {
@@ -157,51 +232,45 @@ int or_build_rhs(int scheme, int n, int ell, double tau, double kappa,
         or_mass_apply(n, u0, b);
         return 0;
     }
-    if (scheme == OR_BD2) {
-        if (ell < 2) return -1;
+    if (scheme == OR_BD2 || scheme == OR_BD4) {
+        if (ell < (scheme == OR_BD2 ? 2 : 3)) return -1;
         double *w = (double *)malloc(sizeof(double) * (size_t)n);
         for (int i = 0; i < n; ++i) w[i] = u0[i] + (v0 ? tau * v0[i] : 0.0);
-        mk_apply(n, 1.0, tau * tau * kappa, w, b);
+        mk_apply(n, 1.0, tau * tau * kappa, w, b);   /* BD2's A_0 = BD4's B */
         mk_apply(n, -1.0, 0.0, u0, b + n);
+        if (scheme == OR_BD4) mk_apply(n, 1.0, 0.0, u0, b + 2 * (size_t)n);
         free(w);
+        return 0;
+    }
+    if (scheme == OR_CD) {
+        if (v0) return -1;
+        mk_apply(n, -1.0, 0.0, u0, b);
         return 0;
     }
     return -1;
 }
 
-/* The diagonal block of time level k (0-based row).  With variable steps
- * (heat only, eq. nonuniformmonolithicheat) A_0^k = M + tau_k kappa K. */
-static void diag_block(int scheme, double tau, double kappa, const double *tau_k, int k,
-                       double *cm, double *ck)
-{
-    double a[4], b[4];
-    or_scheme_coeffs(scheme, tau, a, b);
-    *cm = a[0];
-    *ck = b[0] * kappa;
-    if (tau_k && scheme == OR_HEAT) *ck = tau_k[k] * kappa;
-}
-
 /* ------------------------------------------------------ monolithic matvec */
 
-/* y = A x (transpose = 0) or y = A^T x (transpose = 1), where A is the block
- * lower-triangular Toeplitz matrix of eq. monolithicheat / C_BD2, or the
- * variable-step matrix B of eq. nonuniformmonolithicheat when tau_k != NULL.
- * Row k: (A x)_k = sum_{m=0}^{min(s,k)} A_m x_{k-m}; every block is symmetric,
- * so (A^T x)_k = sum_{m=0}^{min(s, ell-1-k)} A_m^{(k+m)} x_{k+m}. */
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1), where A is the monolithic
+ * matrix of eq. monolithicheat / C_BD2 / C_BD4 / C_CD, or the variable-step matrix
+ * B of eq. nonuniformmonolithicheat when tau_k != NULL.
+ * Row k: (A x)_k = sum_m A_{k,k-m} x_{k-m}; every block is symmetric, so
+ * (A^T x)_k = sum_m A_{k+m,k} x_{k+m}. */
 int or_apply_A(int scheme, int n, int ell, double tau, double kappa, const double *tau_k,
                const double *x, double *y, int transpose)
 {
     double a[4], b[4];
-    int s = or_scheme_coeffs(scheme, tau, a, b);
-    if (s < 0) return -1;
+    int mlo, mhi;
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0) return -1;
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     memset(y, 0, sizeof(double) * (size_t)n * (size_t)ell);
     for (int k = 0; k < ell; ++k) {
-        for (int m = 0; m <= s; ++m) {
-            int src = transpose ? k + m : k - m;
-            if (src < 0 || src >= ell) continue;
-            double cm = a[m], ck = b[m] * kappa;
-            if (m == 0) diag_block(scheme, tau, kappa, tau_k, k, &cm, &ck);
+        for (int m = mlo; m <= mhi; ++m) {
+            double cm, ck;
+            const int src = transpose ? k + m : k - m;
+            const int row = transpose ? k + m : k;       /* the row holding the block */
+            if (!or_block(scheme, tau, kappa, tau_k, ell, row, m, &cm, &ck)) continue;
             mk_apply(n, cm, ck, x + (size_t)src * n, t);
             for (int i = 0; i < n; ++i) y[(size_t)k * n + i] += t[i];
         }
@@ -210,21 +279,23 @@ int or_apply_A(int scheme, int n, int ell, double tau, double kappa, const doubl
     return 0;
 }
 
-/* y = C x: the block circulant of eq. standardheatprecon / wavepreconditioner,
- * i.e. the same blocks wrapped around, (C x)_k = sum_m A_m x_{(k-m) mod ell}.
- * transpose = 1 gives C^T, (C^T x)_k = sum_m A_m x_{(k+m) mod ell}. */
+/* y = C x: the block circulant of eq. standardheatprecon / wavepreconditioner /
+ * R_BD4 / R_CD, i.e. the Toeplitz blocks wrapped around,
+ * (C x)_k = sum_m A_m x_{(k-m) mod ell}.  transpose = 1 gives C^T,
+ * (C^T x)_k = sum_m A_m x_{(k+m) mod ell}. */
 int or_apply_C(int scheme, int n, int ell, double tau, double kappa,
                const double *x, double *y, int transpose)
 {
     double a[4], b[4];
-    int s = or_scheme_coeffs(scheme, tau, a, b);
-    if (s < 0) return -1;
+    int mlo, mhi;
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0) return -1;
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     memset(y, 0, sizeof(double) * (size_t)n * (size_t)ell);
     for (int k = 0; k < ell; ++k) {
-        for (int m = 0; m <= s; ++m) {
-            int src = transpose ? (k + m) % ell : ((k - m) % ell + ell) % ell;
-            mk_apply(n, a[m], b[m] * kappa, x + (size_t)src * n, t);
+        for (int m = mlo; m <= mhi; ++m) {
+            int src = transpose ? k + m : k - m;
+            src = ((src % ell) + ell) % ell;
+            mk_apply(n, a[m - mlo], b[m - mlo] * kappa, x + (size_t)src * n, t);
             for (int i = 0; i < n; ++i) y[(size_t)k * n + i] += t[i];
         }
     }
@@ -244,26 +315,134 @@ int or_apply_E(int n, int ell, double tau, double kappa, const double *tau_k,
 
 /* --------------------------------------------------------- exact solves */
 
-/* Forward block substitution: the exact solution of A U = b, i.e. the
- * sequential time stepping of eq. timestepproblem1 / BD2 that the monolithic
- * system packages:  u_k = A_0^{-1} (b_k - sum_{m=1}^{min(s,k)} A_m u_{k-m}). */
+/* Dense n x n LU with partial pivoting (row-major a, in place; piv of n entries).
+ * Returns 0, or -4 on a zero pivot. */
+static int dense_lu(int n, double *a, int *piv)
+{
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(a[(size_t)r * n + c]) > fabs(a[(size_t)p * n + c])) p = r;
+        piv[c] = p;
+        if (a[(size_t)p * n + c] == 0.0) return -4;
+        if (p != c)
+            for (int k = 0; k < n; ++k) {
+                double t = a[(size_t)c * n + k];
+                a[(size_t)c * n + k] = a[(size_t)p * n + k];
+                a[(size_t)p * n + k] = t;
+            }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = a[(size_t)r * n + c] / a[(size_t)c * n + c];
+            a[(size_t)r * n + c] = f;
+            for (int k = c + 1; k < n; ++k) a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
+        }
+    }
+    return 0;
+}
+
+/* x = A^{-1} x with the factors of dense_lu: the row interchanges in order, then
+ * the unit lower and the upper triangular solves */
+static void dense_lu_solve(int n, const double *a, const int *piv, double *x)
+{
+    for (int c = 0; c < n; ++c) {
+        const int p = piv[c];
+        if (p != c) { double t = x[c]; x[c] = x[p]; x[p] = t; }
+    }
+    for (int c = 0; c < n; ++c)
+        for (int r = c + 1; r < n; ++r) x[r] -= a[(size_t)r * n + c] * x[c];
+    for (int c = n - 1; c >= 0; --c) {
+        for (int k = c + 1; k < n; ++k) x[c] -= a[(size_t)c * n + k] * x[k];
+        x[c] /= a[(size_t)c * n + c];
+    }
+}
+
+/* the dense matrix cm M + ck K (row-major n x n) */
+static void mk_dense(int n, double cm, double ck, double *a)
+{
+    const double h = 1.0 / (n + 1);
+    memset(a, 0, sizeof(double) * (size_t)n * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        a[(size_t)i * n + i] = cm * (4.0 * h / 6.0) + ck * (2.0 / h);
+        if (i > 0) a[(size_t)i * n + i - 1] = cm * (h / 6.0) - ck / h;
+        if (i < n - 1) a[(size_t)i * n + i + 1] = cm * (h / 6.0) - ck / h;
+    }
+}
+
+/* Central differences (system C_CD): block tridiagonal with diagonal
+ * D = tau^2 kappa K - 2M and M above and below; the exact solution of C_CD U = b by
+ * block Gaussian elimination in time (no pivoting between blocks, partial pivoting
+ * inside the dense n x n pivot blocks):
+ *   S_0 = D, S_k = D - M S_{k-1}^{-1} M;  y_0 = b_0, y_k = b_k - M S_{k-1}^{-1} y_{k-1};
+ *   u_{ell-1} = S_{ell-1}^{-1} y_{ell-1},  u_k = S_k^{-1} (y_k - M u_{k+1}).
+ * The matrix is symmetric, so this is also the solve with its transpose.
+ * Memory ell n^2 doubles: for small n only. */
+static int cd_solve(int n, int ell, double tau, double kappa, const double *bvec, double *U)
+{
+    const size_t nn = (size_t)n * (size_t)n;
+    double *S = (double *)malloc(sizeof(double) * nn * (size_t)ell);
+    int *piv = (int *)malloc(sizeof(int) * (size_t)n * (size_t)ell);
+    double *Mm = (double *)malloc(sizeof(double) * nn);
+    double *col = (double *)malloc(sizeof(double) * (size_t)n);
+    double *t = (double *)malloc(sizeof(double) * (size_t)n);
+    int st = 0;
+    mk_dense(n, 1.0, 0.0, Mm);
+    memcpy(U, bvec, sizeof(double) * (size_t)n * (size_t)ell);     /* y in U */
+    for (int k = 0; k < ell && st == 0; ++k) {
+        double *Sk = S + nn * (size_t)k;
+        mk_dense(n, -2.0, tau * tau * kappa, Sk);
+        if (k > 0) {
+            const double *Sp = S + nn * (size_t)(k - 1);
+            const int *pp = piv + (size_t)n * (k - 1);
+            /* S_k -= M S_{k-1}^{-1} M, column by column; y_k -= M S_{k-1}^{-1} y_{k-1} */
+            for (int c = 0; c < n; ++c) {
+                for (int r = 0; r < n; ++r) col[r] = Mm[(size_t)r * n + c];
+                dense_lu_solve(n, Sp, pp, col);
+                mk_apply(n, 1.0, 0.0, col, t);
+                for (int r = 0; r < n; ++r) Sk[(size_t)r * n + c] -= t[r];
+            }
+            memcpy(col, U + (size_t)(k - 1) * n, sizeof(double) * (size_t)n);
+            dense_lu_solve(n, Sp, pp, col);
+            mk_apply(n, 1.0, 0.0, col, t);
+            for (int r = 0; r < n; ++r) U[(size_t)k * n + r] -= t[r];
+        }
+        st = dense_lu(n, Sk, piv + (size_t)n * k);
+    }
+    for (int k = ell - 1; k >= 0 && st == 0; --k) {
+        double *uk = U + (size_t)k * n;
+        if (k < ell - 1) {
+            mk_apply(n, 1.0, 0.0, U + (size_t)(k + 1) * n, t);
+            for (int r = 0; r < n; ++r) uk[r] -= t[r];
+        }
+        dense_lu_solve(n, S + nn * (size_t)k, piv + (size_t)n * k, uk);
+    }
+    free(S); free(piv); free(Mm); free(col); free(t);
+    return st;
+}
+
+/* Forward block substitution: the exact solution of A U = b for the lower-triangular
+ * schemes, i.e. the sequential time stepping of eq. timestepproblem1 / BD2 / BD4 that
+ * the monolithic system packages:
+ *   u_k = A_{k,k}^{-1} (b_k - sum_{m>=1} A_{k,k-m} u_{k-m});
+ * for central differences the block tridiagonal elimination of cd_solve. */
 int or_solve_seq(int scheme, int n, int ell, double tau, double kappa, const double *tau_k,
                  const double *bvec, double *U)
 {
     double a[4], b[4];
-    int s = or_scheme_coeffs(scheme, tau, a, b);
-    if (s < 0) return -1;
+    int mlo, mhi;
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0) return -1;
+    if (scheme == OR_CD) return cd_solve(n, ell, tau, kappa, bvec, U);
     double *rhs = (double *)malloc(sizeof(double) * (size_t)n);
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     int st = 0;
     for (int k = 0; k < ell && st == 0; ++k) {
         memcpy(rhs, bvec + (size_t)k * n, sizeof(double) * (size_t)n);
-        for (int m = 1; m <= s && m <= k; ++m) {
-            mk_apply(n, a[m], b[m] * kappa, U + (size_t)(k - m) * n, t);
+        double cm, ck;
+        for (int m = 1; m <= mhi; ++m) {
+            if (!or_block(scheme, tau, kappa, tau_k, ell, k, m, &cm, &ck)) continue;
+            mk_apply(n, cm, ck, U + (size_t)(k - m) * n, t);
             for (int i = 0; i < n; ++i) rhs[i] -= t[i];
         }
-        double cm, ck;
-        diag_block(scheme, tau, kappa, tau_k, k, &cm, &ck);
+        or_block(scheme, tau, kappa, tau_k, ell, k, 0, &cm, &ck);
         st = mk_solve(n, cm, ck, rhs, U + (size_t)k * n);
     }
     free(rhs);
@@ -272,24 +451,27 @@ int or_solve_seq(int scheme, int n, int ell, double tau, double kappa, const dou
 }
 
 /* Backward block substitution: the exact solution of A^T L = g,
- * l_k = (A_0^k)^{-1} (g_k - sum_{m=1}^{min(s, ell-1-k)} A_m l_{k+m}). */
+ * l_k = A_{k,k}^{-1} (g_k - sum_{m>=1} A_{k+m,k} l_{k+m}) (every block symmetric);
+ * central differences: A is symmetric, A^T L = g is A L = g. */
 int or_adjoint_seq(int scheme, int n, int ell, double tau, double kappa, const double *tau_k,
                    const double *g, double *L)
 {
     double a[4], b[4];
-    int s = or_scheme_coeffs(scheme, tau, a, b);
-    if (s < 0) return -1;
+    int mlo, mhi;
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0) return -1;
+    if (scheme == OR_CD) return cd_solve(n, ell, tau, kappa, g, L);
     double *rhs = (double *)malloc(sizeof(double) * (size_t)n);
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     int st = 0;
     for (int k = ell - 1; k >= 0 && st == 0; --k) {
         memcpy(rhs, g + (size_t)k * n, sizeof(double) * (size_t)n);
-        for (int m = 1; m <= s && k + m < ell; ++m) {
-            mk_apply(n, a[m], b[m] * kappa, L + (size_t)(k + m) * n, t);
+        double cm, ck;
+        for (int m = 1; m <= mhi; ++m) {
+            if (!or_block(scheme, tau, kappa, tau_k, ell, k + m, m, &cm, &ck)) continue;
+            mk_apply(n, cm, ck, L + (size_t)(k + m) * n, t);
             for (int i = 0; i < n; ++i) rhs[i] -= t[i];
         }
-        double cm, ck;
-        diag_block(scheme, tau, kappa, tau_k, k, &cm, &ck);
+        or_block(scheme, tau, kappa, tau_k, ell, k, 0, &cm, &ck);
         st = mk_solve(n, cm, ck, rhs, L + (size_t)k * n);
     }
     free(rhs);
@@ -342,15 +524,16 @@ static void symbol(int scheme, int ell, double tau, int j, int transpose,
                    double complex *alpha, double complex *beta)
 {
     double a[4], b[4];
-    int s = or_scheme_coeffs(scheme, tau, a, b);
+    int mlo, mhi;
+    or_toeplitz(scheme, tau, &mlo, &mhi, a, b);
     double complex al = 0.0, be = 0.0;
-    for (int m = 0; m <= s; ++m) {
-        int p = (int)(((long long)j * m) % ell);
+    for (int m = mlo; m <= mhi; ++m) {
+        int p = (int)((((long long)j * m) % ell + ell) % ell);
         double ang = -2.0 * M_PI * p / ell;
         if (transpose) ang = -ang;
         double complex wp = cos(ang) + I * sin(ang);
-        al += a[m] * wp;
-        be += b[m] * wp;
+        al += a[m - mlo] * wp;
+        be += b[m - mlo] * wp;
     }
     *alpha = al;
     *beta = be;
@@ -450,39 +633,47 @@ int or_pinv_direct(int scheme, int n, int ell, double tau, double kappa, int tra
 /* Reductions of the adjoint gradient for L(U) with A(kappa) U = b(u_0, v_0, kappa):
  *   dL/du_0 = (db/du_0)^T l,  dL/dv_0 = (db/dv_0)^T l,
  *   dL/dkappa = l^T db/dkappa - l^T (dA/dkappa) U,
- * with (dA/dkappa U)_k = sum_m b_m^{(k)} K u_{k-m}.
+ * with (dA/dkappa U)_k = sum_m (K coefficient of block (k, k-m)) K u_{k-m}.
  * heat: b_1 = M u_0 -> g_u0 = M l_1, no kappa term in b.
  * BD2:  b_1 = A_0 (u_0 + tau v_0), b_2 = -M u_0 ->
  *       g_u0 = A_0 l_1 - M l_2, g_v0 = tau A_0 l_1,
- *       db_1/dkappa = tau^2 K (u_0 + tau v_0). */
+ *       db_1/dkappa = tau^2 K (u_0 + tau v_0).
+ * BD4:  b_1 = B (u_0 + tau v_0), b_2 = -M u_0, b_3 = M u_0 (B = BD2's A_0) ->
+ *       g_u0 = B l_1 - M l_2 + M l_3, g_v0 = tau B l_1, db_1/dkappa as BD2.
+ * CD:   b_1 = -M u_0 -> g_u0 = -M l_1, g_v0 = 0, no kappa term in b. */
 int or_grad(int scheme, int n, int ell, double tau, double kappa, const double *tau_k,
             const double *u0, const double *v0, const double *U, const double *L,
             double *g_u0, double *g_v0, double *g_kappa)
 {
     double a[4], b[4];
-    int s = or_scheme_coeffs(scheme, tau, a, b);
-    if (s < 0) return -1;
+    int mlo, mhi;
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0) return -1;
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     double gk = 0.0;
     for (int k = 0; k < ell; ++k) {
-        for (int m = 0; m <= s && m <= k; ++m) {
-            double bm = b[m];
-            if (m == 0 && tau_k && scheme == OR_HEAT) bm = tau_k[k];
-            if (bm == 0.0) continue;
+        for (int m = mlo; m <= mhi; ++m) {
+            double cm, bm;   /* with kappa = 1 the K coefficient is dA/dkappa's */
+            if (!or_block(scheme, tau, 1.0, tau_k, ell, k, m, &cm, &bm) || bm == 0.0) continue;
             or_stiff_apply(n, U + (size_t)(k - m) * n, t);
             double dot = 0.0;
             for (int i = 0; i < n; ++i) dot += L[(size_t)k * n + i] * t[i];
             gk -= bm * dot;
         }
     }
+    if (g_v0) memset(g_v0, 0, sizeof(double) * (size_t)n);
     if (scheme == OR_HEAT) {
         or_mass_apply(n, L, g_u0);
-        if (g_v0) memset(g_v0, 0, sizeof(double) * (size_t)n);
+    } else if (scheme == OR_CD) {
+        mk_apply(n, -1.0, 0.0, L, g_u0);
     } else {
         double *w = (double *)malloc(sizeof(double) * (size_t)n);
         mk_apply(n, 1.0, tau * tau * kappa, L, g_u0);
         or_mass_apply(n, L + n, t);
         for (int i = 0; i < n; ++i) g_u0[i] -= t[i];
+        if (scheme == OR_BD4) {
+            or_mass_apply(n, L + 2 * (size_t)n, t);
+            for (int i = 0; i < n; ++i) g_u0[i] += t[i];
+        }
         if (g_v0) {
             mk_apply(n, 1.0, tau * tau * kappa, L, g_v0);
             for (int i = 0; i < n; ++i) g_v0[i] *= tau;

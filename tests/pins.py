@@ -113,6 +113,41 @@ def bd2_closed_form(u0, v0, ell, tau, kappa):
     return U
 
 
+def bd4_mode_recursion(u0, v0, ell, tau, kappa):
+    """Per sine mode (blocks act as mu, lambda mu on mode m) the BD4 system C_BD4 is the
+    scalar recursion c_1 = c_0 + tau d_0 (start-up row), (1 + tau^2 kappa lambda) c_2 -
+    2 c_1 + c_0 = 0 (BD2 row), (2 + tau^2 kappa lambda) c_k - 5 c_{k-1} + 4 c_{k-2} -
+    c_{k-3} = 0 for k >= 3."""
+    n = u0.size
+    c0 = sine_coeffs(u0)
+    d0 = sine_coeffs(v0) if v0 is not None else np.zeros(n)
+    lm = lam(n, np.arange(1, n + 1))
+    t2 = tau * tau * kappa * lm
+    c = [c0, c0 + tau * d0]
+    c.append((2 * c[1] - c[0]) / (1 + t2))
+    for k in range(3, ell + 1):
+        c.append((5 * c[k - 1] - 4 * c[k - 2] + c[k - 3]) / (2 + t2))
+    return np.array([sine_synth(ck) for ck in c[1:ell + 1]])
+
+
+def cd_mode_solve(u0, ell, tau, kappa):
+    """Per sine mode the central-difference system C_CD is the ell x ell tridiagonal
+    Toeplitz system c_{k-1} + (tau^2 kappa lambda - 2) c_k + c_{k+1} = 0, k = 1..ell,
+    with c_0 the mode of u_0 moved to the right and no c_{ell+1} (the common factor mu
+    cancels)."""
+    n = u0.size
+    c0 = sine_coeffs(u0)
+    lm = lam(n, np.arange(1, n + 1))
+    C = np.empty((ell, n))
+    for m in range(n):
+        T = (np.diag(np.full(ell, tau * tau * kappa * lm[m] - 2.0)) + np.eye(ell, k=1)
+             + np.eye(ell, k=-1))
+        rhs = np.zeros(ell)
+        rhs[0] = -c0[m]
+        C[:, m] = np.linalg.solve(T, rhs)
+    return np.array([sine_synth(ck) for ck in C])
+
+
 def kron_A(blocks, ell, circulant=False):
     """sum_m Shift^m (x) A_m with Shift the ell x ell down-shift (cyclic if circulant)."""
     n = blocks[0].shape[0]
@@ -138,8 +173,12 @@ def eig_C(scheme, n, ell, tau, kappa, transpose=False):
     w = np.exp((1j if transpose else -1j) * 2 * np.pi * j / ell)
     if scheme == 0:
         al, be = 1 - w, np.full(ell, tau)
-    else:
+    elif scheme == 1:
         al, be = (1 - w) ** 2, np.full(ell, tau * tau)
+    elif scheme == 2:                       # BD4: 2 - 5 w + 4 w^2 - w^3 = (1 - w)^2 (2 - w)
+        al, be = (1 - w) ** 2 * (2 - w), np.full(ell, tau * tau)
+    else:                                   # CD: w^{-1} - 2 + w = -4 sin^2(pi j / ell)
+        al, be = -4.0 * np.sin(np.pi * j / ell) ** 2 + 0j, np.full(ell, tau * tau)
     return al[:, None] * mu_[None, :] + be[:, None] * kappa * (lam_ * mu_)[None, :]
 
 

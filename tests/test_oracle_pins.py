@@ -381,3 +381,156 @@ def test_variable_step_gradient_fd(orc):
     fd_u = (loss(u0 + hh * d, kappa)[0] - loss(u0 - hh * d, kappa)[0]) / (2 * hh)
     assert abs(gu @ d - fd_u) < 1e-7 * max(1.0, abs(fd_u))
     assert np.all(gv == 0.0)
+
+
+# ------------------------------------------------- BD4 and central differences
+
+BD4, CD = 2, 3
+
+
+def dense_scheme(scheme, n, ell, tau, kappa, circulant=False):
+    """The printed monolithic matrices (and their circulants) assembled from M, K by
+    quadrature: C_BD4 with its two start-up rows B, (C, B) and the Toeplitz rows
+    A_2 A_1 A_0 (A_3 from the fourth row), R_BD4; C_CD with M beside the diagonal
+    block tau^2 K - 2M, R_CD."""
+    M, K = pins.quad_MK(n)
+    N = n * ell
+    A = np.zeros((N, N))
+
+    def put(k, c, B):
+        if circulant:
+            c %= ell
+        elif not 0 <= c < ell:
+            return
+        A[k * n:(k + 1) * n, c * n:(c + 1) * n] += B
+    if scheme == BD4:
+        A0, A1, A2, A3 = 2 * M + tau * tau * kappa * K, -5 * M, 4 * M, -M
+        for k in range(ell):
+            if k < 2 and not circulant:
+                put(k, k, M + tau * tau * kappa * K)
+                if k == 1:
+                    put(k, 0, -2 * M)
+                continue
+            for m, B in enumerate((A0, A1, A2, A3)):
+                put(k, k - m, B)
+    else:
+        for k in range(ell):
+            put(k, k - 1, M)
+            put(k, k, tau * tau * kappa * K - 2 * M)
+            put(k, k + 1, M)
+    return A
+
+
+@pytest.mark.parametrize("scheme", [BD4, CD])
+def test_bd4_cd_match_dense_assembly(orc, scheme):
+    """apply_A / A^T / C / C^T, the exact solves and the transposed solves of the BD4
+    and central-difference systems against the printed block matrices."""
+    n, ell, tau, kappa = 5, 9, 0.11, 0.8
+    A = dense_scheme(scheme, n, ell, tau, kappa)
+    C = dense_scheme(scheme, n, ell, tau, kappa, circulant=True)
+    rng = np.random.default_rng(40 + scheme)
+    x = rng.standard_normal(n * ell)
+    assert rel(orc.apply_A(scheme, n, ell, tau, kappa, x), A @ x) < 1e-13
+    assert rel(orc.apply_A(scheme, n, ell, tau, kappa, x, transpose=True), A.T @ x) < 1e-13
+    assert rel(orc.apply_C(scheme, n, ell, tau, kappa, x), C @ x) < 1e-13
+    assert rel(orc.apply_C(scheme, n, ell, tau, kappa, x, transpose=True), C.T @ x) < 1e-13
+    assert rel(orc.solve_seq(scheme, n, ell, tau, kappa, x), np.linalg.solve(A, x)) < 1e-11
+    assert rel(orc.adjoint_seq(scheme, n, ell, tau, kappa, x), np.linalg.solve(A.T, x)) < 1e-11
+
+
+def test_bd4_sequential_solve_mode_recursion(orc):
+    """C_BD4 with initial velocity against the per-mode scalar BD4 recursion."""
+    n, ell = 23, 50
+    tau = 1.0 / ell
+    rng = np.random.default_rng(41)
+    u0 = pins.sine_synth(np.r_[rng.standard_normal(6), np.zeros(n - 6)])
+    v0 = pins.sine_synth(np.r_[rng.standard_normal(5), np.zeros(n - 5)])
+    b = orc.build_rhs(BD4, n, ell, tau, 1.3, u0, v0)
+    U = orc.solve_seq(BD4, n, ell, tau, 1.3, b)
+    assert rel(U, pins.bd4_mode_recursion(u0, v0, ell, tau, 1.3)) < 1e-11
+
+
+def test_cd_solve_mode_form(orc):
+    """C_CD against its per-mode ell x ell tridiagonal systems in time."""
+    n, ell = 15, 40
+    tau = 1.0 / ell
+    rng = np.random.default_rng(42)
+    u0 = pins.sine_synth(np.r_[rng.standard_normal(5), np.zeros(n - 5)])
+    b = orc.build_rhs(CD, n, ell, tau, 0.9, u0)
+    U = orc.solve_seq(CD, n, ell, tau, 0.9, b)
+    assert rel(U, pins.cd_mode_solve(u0, ell, tau, 0.9)) < 1e-10
+    with pytest.raises(RuntimeError):                  # no initial velocity for C_CD
+        orc.build_rhs(CD, n, ell, tau, 0.9, u0, u0)
+
+
+@pytest.mark.parametrize("scheme", [BD4, CD])
+def test_bd4_cd_symbol_and_pinv(orc, scheme):
+    """Circulant symbols in closed form (BD4: alpha_j = (1 - w^j)^2 (2 - w^j); CD:
+    alpha_j = -4 sin^2(pi j / ell), real), the shifted solves against dense solves, and
+    C^{-1} against the dense circulant."""
+    n, ell, tau, kappa = 6, 10, 0.1, 1.4
+    M, K = pins.quad_MK(n)
+    rng = np.random.default_rng(43)
+    X = rng.standard_normal((ell, n)) + 1j * rng.standard_normal((ell, n))
+    for tr in (False, True):
+        Y = orc.shifted_solve_all(scheme, n, ell, tau, kappa, X, transpose=tr)
+        for j in range(ell):
+            w = np.exp((1 if tr else -1) * 2j * np.pi * j / ell)
+            al = (1 - w) ** 2 * (2 - w) if scheme == BD4 else -4 * np.sin(np.pi * j / ell) ** 2
+            a2, b2 = orc.symbol(scheme, ell, tau, j, tr)
+            assert abs(a2 - al) < 1e-13 and abs(b2 - tau * tau) < 1e-15
+            assert rel(Y[j], np.linalg.solve(al * M + tau * tau * kappa * K, X[j])) < 1e-11
+    C = dense_scheme(scheme, n, ell, tau, kappa, circulant=True)
+    r = rng.standard_normal(n * ell)
+    for tr in (False, True):
+        z, ratio = orc.pinv_direct(scheme, n, ell, tau, kappa, r, transpose=tr)
+        assert rel(z, np.linalg.solve(C.T if tr else C, r)) < 1e-10 and ratio < 1e-12
+        assert rel(orc.pinv(scheme, n, ell, tau, kappa, r, transpose=tr), z) < 1e-11
+
+
+@pytest.mark.parametrize("scheme,bound", [(BD4, 3), (CD, 2)])
+def test_bd4_cd_preconditioned_rank(orc, scheme, bound):
+    """A - C is confined to the first rows (BD4: three rows, the start-up rows and the
+    wrapped blocks) or to the two corner blocks (CD), so C^{-1} A has at most 3n / 2n
+    eigenvalues other than 1 (exactly that many here)."""
+    n, ell, kappa = 4, 10, 1.0
+    tau = 1.0 / ell
+    N = n * ell
+    I = np.eye(N)
+    CinvA = np.column_stack([orc.pinv_direct(scheme, n, ell, tau, kappa,
+                                             orc.apply_A(scheme, n, ell, tau, kappa, I[:, c]))[0].ravel()
+                             for c in range(N)])
+    ev = np.linalg.eigvals(CinvA)
+    assert np.sum(np.abs(ev - 1.0) > 1e-7) == bound * n
+
+
+@pytest.mark.parametrize("scheme", [BD4, CD])
+def test_bd4_cd_adjoint_gradient_fd(orc, scheme):
+    """Gradients of L = 1/2 ||U - U_t||^2 for C_BD4 (g_u0 = B l_1 - M l_2 + M l_3,
+    g_v0 = tau B l_1, g_kappa with the start-up row's tau^2 K (u_0 + tau v_0)) and C_CD
+    (g_u0 = -M l_1) against central finite differences on exact solves."""
+    n, ell = 9, 14
+    tau = 1.0 / ell
+    kappa = 1.2
+    rng = np.random.default_rng(44 + scheme)
+    u0 = rng.standard_normal(n)
+    v0 = rng.standard_normal(n) if scheme == BD4 else None
+    U_t = rng.standard_normal((ell, n)) * 0.1
+
+    def loss(u, v, k):
+        U = orc.solve_seq(scheme, n, ell, tau, k, orc.build_rhs(scheme, n, ell, tau, k, u, v))
+        return 0.5 * np.sum((U - U_t) ** 2), U
+    _, U = loss(u0, v0, kappa)
+    lam_ = orc.adjoint_seq(scheme, n, ell, tau, kappa, U - U_t)
+    gu, gv, gk = orc.grad(scheme, n, ell, tau, kappa, u0, U, lam_, v0=v0)
+    hh = 1e-6
+    fd_k = (loss(u0, v0, kappa + hh)[0] - loss(u0, v0, kappa - hh)[0]) / (2 * hh)
+    assert abs(gk - fd_k) < 1e-7 * max(1.0, abs(fd_k))
+    d = rng.standard_normal(n)
+    fd_u = (loss(u0 + hh * d, v0, kappa)[0] - loss(u0 - hh * d, v0, kappa)[0]) / (2 * hh)
+    assert abs(gu @ d - fd_u) < 1e-7 * max(1.0, abs(fd_u))
+    if scheme == BD4:
+        fd_v = (loss(u0, v0 + hh * d, kappa)[0] - loss(u0, v0 - hh * d, kappa)[0]) / (2 * hh)
+        assert abs(gv @ d - fd_v) < 1e-7 * max(1.0, abs(fd_v))
+    else:
+        assert np.all(gv == 0.0)
