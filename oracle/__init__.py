@@ -12,7 +12,8 @@ What the oracle computes, and the passage of Goddard & Wathen (arXiv
   rows) and the two-sided central-difference system C_CD for the wave equation,
   eq. nonuniformmonolithicheat with variable steps.  ``solve_seq`` is forward block
   substitution, i.e. the sequential time stepping the monolithic system packages
-  (block tridiagonal elimination for C_CD): the exact solution U.
+  (for C_CD, Gaussian elimination with partial pivoting on its band): the exact
+  solution U.
 * ``apply_C`` -- the block circulant preconditioner (eq. standardheatprecon,
   eq. wavepreconditioner, R_BD4, R_CD).
 * ``dft`` -- the direct O(ell^2) transform along time (the (U (x) I_n) factor of
@@ -204,8 +205,48 @@ def apply_E(n, ell, tau, kappa, tau_k, x):
     return y
 
 
+def _cd_banded(n, ell, tau, kappa):
+    """The central-difference matrix C_CD (eq. CenDiffDisc: M u_{k-1} + (tau^2 kappa K
+    - 2M) u_k + M u_{k+1}, no u_{ell+1}) in LAPACK band storage, l = u = n + 1:
+    ab[u + r - c, c] = A[r, c] with r = k n + i, c = k' n + j."""
+    h = 1.0 / (n + 1)
+    N = n * ell
+    w = n + 1
+    ab = np.zeros((2 * w + 1, N))
+
+    def put(r, c, v):
+        ab[w + r - c, c] += v
+    t2 = tau * tau * kappa
+    for k in range(ell):
+        for dk, (cm, ck) in ((-1, (1.0, 0.0)), (0, (-2.0, t2)), (1, (1.0, 0.0))):
+            kk = k + dk
+            if not 0 <= kk < ell:
+                continue
+            for i in range(n):
+                r = k * n + i
+                put(r, kk * n + i, cm * 4.0 * h / 6.0 + ck * 2.0 / h)
+                if i > 0:
+                    put(r, kk * n + i - 1, cm * h / 6.0 - ck / h)
+                if i < n - 1:
+                    put(r, kk * n + i + 1, cm * h / 6.0 - ck / h)
+    return ab, w
+
+
+def _cd_solve(n, ell, tau, kappa, rhs):
+    """Exact solution of the symmetric system C_CD X = rhs: Gaussian elimination with
+    partial pivoting on its band (LAPACK gbsv through scipy, a library solve)."""
+    from scipy.linalg import solve_banded
+    ab, w = _cd_banded(n, ell, tau, kappa)
+    return solve_banded((w, w), ab, _c(rhs).ravel()).reshape(ell, n)
+
+
 def solve_seq(scheme, n, ell, tau, kappa, b, tau_k=None):
-    """Exact U with A U = b by forward block substitution (time stepping)."""
+    """Exact U with A U = b by forward block substitution (time stepping); for the
+    two-sided central-difference system a banded solve with partial pivoting."""
+    if scheme == CD:
+        if tau_k is not None:
+            raise ValueError("variable steps are defined for the heat scheme only")
+        return _cd_solve(n, ell, tau, kappa, b)
     b = _c(b).reshape(ell, n)
     tk = None if tau_k is None else _c(tau_k)
     U = np.empty((ell, n))
@@ -215,7 +256,10 @@ def solve_seq(scheme, n, ell, tau, kappa, b, tau_k=None):
 
 
 def adjoint_seq(scheme, n, ell, tau, kappa, g, tau_k=None):
-    """Exact L with A^T L = g by backward block substitution."""
+    """Exact L with A^T L = g by backward block substitution (central differences:
+    C_CD is symmetric, so the banded solve of solve_seq)."""
+    if scheme == CD:
+        return solve_seq(scheme, n, ell, tau, kappa, g, tau_k)
     g = _c(g).reshape(ell, n)
     tk = None if tau_k is None else _c(tau_k)
     L = np.empty((ell, n))

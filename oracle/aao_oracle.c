@@ -30,7 +30,8 @@
  *             C = -2M (not Toeplitz)
  *       wave, central differences (eq. CenDiffDisc and the system C_CD): two-sided,
  *             M u_{k-1} + (tau^2 kappa K - 2M) u_k + M u_{k+1}, i.e. offsets
- *             m = -1, 0, 1 (the last row has no u_{ell+1})
+ *             m = -1, 0, 1 (the last row has no u_{ell+1}); its exact solve is the
+ *             banded elimination in oracle/__init__.py
  *   - the DFT along time is X_j = sum_k x_k w^{jk}, w = exp(-2 pi i/ell).
  */
 #include <complex.h>
@@ -315,122 +316,18 @@ int or_apply_E(int n, int ell, double tau, double kappa, const double *tau_k,
 
 /* --------------------------------------------------------- exact solves */
 
-/* Dense n x n LU with partial pivoting (row-major a, in place; piv of n entries).
- * Returns 0, or -4 on a zero pivot. */
-static int dense_lu(int n, double *a, int *piv)
-{
-    for (int c = 0; c < n; ++c) {
-        int p = c;
-        for (int r = c + 1; r < n; ++r)
-            if (fabs(a[(size_t)r * n + c]) > fabs(a[(size_t)p * n + c])) p = r;
-        piv[c] = p;
-        if (a[(size_t)p * n + c] == 0.0) return -4;
-        if (p != c)
-            for (int k = 0; k < n; ++k) {
-                double t = a[(size_t)c * n + k];
-                a[(size_t)c * n + k] = a[(size_t)p * n + k];
-                a[(size_t)p * n + k] = t;
-            }
-        for (int r = c + 1; r < n; ++r) {
-            const double f = a[(size_t)r * n + c] / a[(size_t)c * n + c];
-            a[(size_t)r * n + c] = f;
-            for (int k = c + 1; k < n; ++k) a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
-        }
-    }
-    return 0;
-}
-
-/* x = A^{-1} x with the factors of dense_lu: the row interchanges in order, then
- * the unit lower and the upper triangular solves */
-static void dense_lu_solve(int n, const double *a, const int *piv, double *x)
-{
-    for (int c = 0; c < n; ++c) {
-        const int p = piv[c];
-        if (p != c) { double t = x[c]; x[c] = x[p]; x[p] = t; }
-    }
-    for (int c = 0; c < n; ++c)
-        for (int r = c + 1; r < n; ++r) x[r] -= a[(size_t)r * n + c] * x[c];
-    for (int c = n - 1; c >= 0; --c) {
-        for (int k = c + 1; k < n; ++k) x[c] -= a[(size_t)c * n + k] * x[k];
-        x[c] /= a[(size_t)c * n + c];
-    }
-}
-
-/* the dense matrix cm M + ck K (row-major n x n) */
-static void mk_dense(int n, double cm, double ck, double *a)
-{
-    const double h = 1.0 / (n + 1);
-    memset(a, 0, sizeof(double) * (size_t)n * (size_t)n);
-    for (int i = 0; i < n; ++i) {
-        a[(size_t)i * n + i] = cm * (4.0 * h / 6.0) + ck * (2.0 / h);
-        if (i > 0) a[(size_t)i * n + i - 1] = cm * (h / 6.0) - ck / h;
-        if (i < n - 1) a[(size_t)i * n + i + 1] = cm * (h / 6.0) - ck / h;
-    }
-}
-
-/* Central differences (system C_CD): block tridiagonal with diagonal
- * D = tau^2 kappa K - 2M and M above and below; the exact solution of C_CD U = b by
- * block Gaussian elimination in time (no pivoting between blocks, partial pivoting
- * inside the dense n x n pivot blocks):
- *   S_0 = D, S_k = D - M S_{k-1}^{-1} M;  y_0 = b_0, y_k = b_k - M S_{k-1}^{-1} y_{k-1};
- *   u_{ell-1} = S_{ell-1}^{-1} y_{ell-1},  u_k = S_k^{-1} (y_k - M u_{k+1}).
- * The matrix is symmetric, so this is also the solve with its transpose.
- * Memory ell n^2 doubles: for small n only. */
-static int cd_solve(int n, int ell, double tau, double kappa, const double *bvec, double *U)
-{
-    const size_t nn = (size_t)n * (size_t)n;
-    double *S = (double *)malloc(sizeof(double) * nn * (size_t)ell);
-    int *piv = (int *)malloc(sizeof(int) * (size_t)n * (size_t)ell);
-    double *Mm = (double *)malloc(sizeof(double) * nn);
-    double *col = (double *)malloc(sizeof(double) * (size_t)n);
-    double *t = (double *)malloc(sizeof(double) * (size_t)n);
-    int st = 0;
-    mk_dense(n, 1.0, 0.0, Mm);
-    memcpy(U, bvec, sizeof(double) * (size_t)n * (size_t)ell);     /* y in U */
-    for (int k = 0; k < ell && st == 0; ++k) {
-        double *Sk = S + nn * (size_t)k;
-        mk_dense(n, -2.0, tau * tau * kappa, Sk);
-        if (k > 0) {
-            const double *Sp = S + nn * (size_t)(k - 1);
-            const int *pp = piv + (size_t)n * (k - 1);
-            /* S_k -= M S_{k-1}^{-1} M, column by column; y_k -= M S_{k-1}^{-1} y_{k-1} */
-            for (int c = 0; c < n; ++c) {
-                for (int r = 0; r < n; ++r) col[r] = Mm[(size_t)r * n + c];
-                dense_lu_solve(n, Sp, pp, col);
-                mk_apply(n, 1.0, 0.0, col, t);
-                for (int r = 0; r < n; ++r) Sk[(size_t)r * n + c] -= t[r];
-            }
-            memcpy(col, U + (size_t)(k - 1) * n, sizeof(double) * (size_t)n);
-            dense_lu_solve(n, Sp, pp, col);
-            mk_apply(n, 1.0, 0.0, col, t);
-            for (int r = 0; r < n; ++r) U[(size_t)k * n + r] -= t[r];
-        }
-        st = dense_lu(n, Sk, piv + (size_t)n * k);
-    }
-    for (int k = ell - 1; k >= 0 && st == 0; --k) {
-        double *uk = U + (size_t)k * n;
-        if (k < ell - 1) {
-            mk_apply(n, 1.0, 0.0, U + (size_t)(k + 1) * n, t);
-            for (int r = 0; r < n; ++r) uk[r] -= t[r];
-        }
-        dense_lu_solve(n, S + nn * (size_t)k, piv + (size_t)n * k, uk);
-    }
-    free(S); free(piv); free(Mm); free(col); free(t);
-    return st;
-}
-
 /* Forward block substitution: the exact solution of A U = b for the lower-triangular
  * schemes, i.e. the sequential time stepping of eq. timestepproblem1 / BD2 / BD4 that
  * the monolithic system packages:
- *   u_k = A_{k,k}^{-1} (b_k - sum_{m>=1} A_{k,k-m} u_{k-m});
- * for central differences the block tridiagonal elimination of cd_solve. */
+ *   u_k = A_{k,k}^{-1} (b_k - sum_{m>=1} A_{k,k-m} u_{k-m}).
+ * The two-sided central-difference system is not triangular: -1 (the Python side
+ * solves it as a banded system with partial pivoting). */
 int or_solve_seq(int scheme, int n, int ell, double tau, double kappa, const double *tau_k,
                  const double *bvec, double *U)
 {
     double a[4], b[4];
     int mlo, mhi;
-    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0) return -1;
-    if (scheme == OR_CD) return cd_solve(n, ell, tau, kappa, bvec, U);
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0 || mlo < 0) return -1;
     double *rhs = (double *)malloc(sizeof(double) * (size_t)n);
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     int st = 0;
@@ -452,14 +349,13 @@ int or_solve_seq(int scheme, int n, int ell, double tau, double kappa, const dou
 
 /* Backward block substitution: the exact solution of A^T L = g,
  * l_k = A_{k,k}^{-1} (g_k - sum_{m>=1} A_{k+m,k} l_{k+m}) (every block symmetric);
- * central differences: A is symmetric, A^T L = g is A L = g. */
+ * -1 for the two-sided central-difference system, as in or_solve_seq. */
 int or_adjoint_seq(int scheme, int n, int ell, double tau, double kappa, const double *tau_k,
                    const double *g, double *L)
 {
     double a[4], b[4];
     int mlo, mhi;
-    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0) return -1;
-    if (scheme == OR_CD) return cd_solve(n, ell, tau, kappa, g, L);
+    if (or_toeplitz(scheme, tau, &mlo, &mhi, a, b) != 0 || mlo < 0) return -1;
     double *rhs = (double *)malloc(sizeof(double) * (size_t)n);
     double *t = (double *)malloc(sizeof(double) * (size_t)n);
     int st = 0;
