@@ -16,6 +16,15 @@
  *                A_0 = M + tau kappa K, A_1 = -M            (s = 1)
  *   AAO_WAVE_BD2 two-step backward difference, system C_BD2:
  *                A_0 = M + tau^2 kappa K, A_1 = -2M, A_2 = M (s = 2)
+ *   AAO_WAVE_BD4 four-step backward difference, eq. BD4 and system C_BD4:
+ *                A_0 = 2M + tau^2 kappa K, A_1 = -5M, A_2 = 4M, A_3 = -M from the
+ *                third row on; start-up rows B u_1 and C u_1 + B u_2 (B = M +
+ *                tau^2 kappa K, C = -2M); the circulant R_BD4 wraps A_0..A_3
+ *   AAO_WAVE_CD  central differences, eq. CenDiffDisc and system C_CD: two-sided,
+ *                M u_{k-1} + (tau^2 kappa K - 2M) u_k + M u_{k+1} (no u_{ell+1});
+ *                the circulant R_CD has the real, indefinite symbol
+ *                tau^2 kappa K - 4 sin^2(pi j / ell) M, whose blocks can be nearly
+ *                singular (the shifted solves do not pivot)
  * (The paper prints the heat block as K + tau M; implicit Euler on
  * M u' = -K u gives M + tau K, which is what is built.)
  *
@@ -59,7 +68,7 @@ typedef enum {
     AAO_ERR_UNSUPPORTED = -6
 } aao_status;
 
-enum { AAO_HEAT_IE = 0, AAO_WAVE_BD2 = 1 };
+enum { AAO_HEAT_IE = 0, AAO_WAVE_BD2 = 1, AAO_WAVE_BD4 = 2, AAO_WAVE_CD = 3 };
 
 /* Precision of the preconditioner apply inside GMRES (aao_set_precision).  In every
  * mode the outer flexible GMRES (matvec, residual, Arnoldi, update) stays double.
@@ -87,7 +96,8 @@ typedef struct {
 
 /* Create a context for n >= 1 interior nodes, ell >= 1 steps of size tau > 0
  * (tau is the step of the Toeplitz matrix and of the circulant; the mean step
- * when variable steps are set), scheme AAO_HEAT_IE or AAO_WAVE_BD2.  kappa = 1.
+ * when variable steps are set), scheme AAO_HEAT_IE, AAO_WAVE_BD2, AAO_WAVE_BD4 or
+ * AAO_WAVE_CD.  kappa = 1.
  * Allocates the device tables on the current HIP device.  Sec. 2. */
 aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *out);
 
@@ -124,7 +134,10 @@ aao_status aao_project_sine(aao_ctx ctx, int J, const int *modes, const double *
  * initial velocity v0 (device, n, or NULL for v0 = 0):
  *   heat: b_1 = M u0 (eq. monolithicheat), other rows 0;
  *   BD2:  b_1 = A_0 (u0 + tau v0), b_2 = -M u0, other rows 0 (system C_BD2,
- *         with the start-up row u_1 = u0 + tau v0). */
+ *         with the start-up row u_1 = u0 + tau v0);
+ *   BD4:  b_1 = B (u0 + tau v0), b_2 = -M u0, b_3 = M u0 (system C_BD4);
+ *   CD:   b_1 = -M u0 (system C_CD; the scheme has no initial velocity: v0 must be
+ *         NULL, AAO_ERR_ARG otherwise). */
 aao_status aao_build_rhs(aao_ctx ctx, const double *u0, const double *v0, double *b);
 
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1); with variable steps, B
@@ -217,11 +230,14 @@ aao_status aao_adjoint_solve(aao_ctx ctx, const double *g, double *lam, int rest
  * blocks are linear in kappa), given the forward solution U and the adjoint lam
  * (A^T lam = dL/dU), all device:
  *   g_u0    (device, n)   = (db/du0)^T lam   heat: M lam_1;
- *                                            BD2: A_0 lam_1 - M lam_2
- *   g_v0    (device, n or NULL) = (db/dv0)^T lam  (BD2: tau A_0 lam_1; heat: 0)
+ *                                            BD2: A_0 lam_1 - M lam_2;
+ *                                            BD4: B lam_1 - M lam_2 + M lam_3;
+ *                                            CD: -M lam_1
+ *   g_v0    (device, n or NULL) = (db/dv0)^T lam  (BD2: tau A_0 lam_1; BD4:
+ *           tau B lam_1; heat, CD: 0)
  *   g_kappa (host scalar, may be NULL) = lam^T db/dkappa - lam^T (dA/dkappa) U,
  *           (dA/dkappa U)_k = sum_m b_m^{(k)} K u_{k-m}.
- * u0 and v0 are needed only for the BD2 kappa term (NULL allowed otherwise). */
+ * u0 and v0 are needed only for the BD2 / BD4 kappa term (NULL allowed otherwise). */
 aao_status aao_grad(aao_ctx ctx, const double *u0, const double *v0, const double *U,
                     const double *lam, double *g_u0, double *g_v0, double *g_kappa);
 

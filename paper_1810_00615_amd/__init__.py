@@ -7,7 +7,7 @@ complex shifted tridiagonal solves written in HIP.  The C ABI is
 include/aao.h; this package is its Python binding (torch supplies memory and
 streams).
 """
-from .api import BD2, HEAT, AAOError, Batch, Problem  # noqa: F401
+from .api import BD2, BD4, CD, HEAT, AAOError, Batch, Problem  # noqa: F401
 from .autograd import AllAtOnceSolve, all_at_once_solve  # noqa: F401
 
-__all__ = ["Problem", "Batch", "AAOError", "HEAT", "BD2", "AllAtOnceSolve", "all_at_once_solve"]
+__all__ = ["Problem", "Batch", "AAOError", "HEAT", "BD2", "BD4", "CD", "AllAtOnceSolve", "all_at_once_solve"]

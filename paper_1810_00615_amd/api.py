@@ -16,8 +16,9 @@ import torch
 from ._lib import (CONFIG_KINDS, GMRES_CGS2_CLASSIC, GMRES_EARLY_CHECK, GMRES_TRANSPOSE,
                    GMRES_ZERO_GUESS, KERNELS, AAOError, Info, check, lib)
 
-HEAT, BD2 = 0, 1
-SCHEMES = {"heat": HEAT, "heat_ie": HEAT, "bd2": BD2, "wave_bd2": BD2}
+HEAT, BD2, BD4, CD = 0, 1, 2, 3
+SCHEMES = {"heat": HEAT, "heat_ie": HEAT, "bd2": BD2, "wave_bd2": BD2, "bd4": BD4,
+           "wave_bd4": BD4, "cd": CD, "wave_cd": CD}
 PRECISIONS = {"fp64": 0, "mixed": 1, "fp32": 2, "mixed_in": 3}
 
 
@@ -49,9 +50,10 @@ class Problem:
 
     Parameters follow the paper's statement of the problem: n interior nodes,
     ell time steps of size tau (default 1/ell, i.e. T = 1), the scheme
-    ("heat" = implicit Euler, "bd2" = two-step backward difference for the wave
-    equation), the coefficient kappa of K, optional variable steps (heat) and
-    the precision of the preconditioner apply ("fp64", "mixed", "fp32")."""
+    ("heat" = implicit Euler; for the wave equation "bd2" / "bd4" = two- / four-step
+    backward differences, "cd" = central differences), the coefficient kappa of K,
+    optional variable steps (heat) and the precision of the preconditioner apply
+    ("fp64", "mixed", "fp32", "mixed_in")."""
 
     def __init__(self, n: int, ell: int, tau: Optional[float] = None, scheme="heat",
                  kappa: float = 1.0, precision: str = "fp64", steps=None, neumann_order: int = 0,

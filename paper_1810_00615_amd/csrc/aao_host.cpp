@@ -196,20 +196,43 @@ static aao_status dev_alloc(aao_ctx ctx, void **p, size_t bytes)
 }
 
 namespace aao {
-// Block coefficients (a_m, b_m) of A_m = a_m M + b_m kappa K for a scheme constant
-// (Sec. 2: eq. monolithicheat read as A_0 = M + tau K, A_1 = -M; system C_BD2).
+// Block coefficients of a scheme constant (Sec. 2): the Toeplitz blocks
+// A_m = a_m M + b_m kappa K, the start-up rows and the block above the diagonal.
+//   heat: eq. monolithicheat read as A_0 = M + tau K, A_1 = -M;
+//   BD2:  system C_BD2, A_0 = M + tau^2 K, A_1 = -2M, A_2 = M;
+//   BD4:  system C_BD4, A_0 = 2M + tau^2 K, A_1 = -5M, A_2 = 4M, A_3 = -M, start-up
+//         rows B = M + tau^2 K (first row) and C = -2M, B (second row);
+//   CD:   system C_CD, M u_{k-1} + (tau^2 K - 2M) u_k + M u_{k+1}.
 bool make_scheme(int scheme, double tau, Scheme *out)
 {
     Scheme s{};
+    s.id = scheme;
+    const double t2 = tau * tau;
     if (scheme == AAO_HEAT_IE) {
         s.s = 1;
         s.a[0] = 1.0;  s.b[0] = tau;
         s.a[1] = -1.0; s.b[1] = 0.0;
     } else if (scheme == AAO_WAVE_BD2) {
         s.s = 2;
-        s.a[0] = 1.0;  s.b[0] = tau * tau;
+        s.a[0] = 1.0;  s.b[0] = t2;
         s.a[1] = -2.0; s.b[1] = 0.0;
         s.a[2] = 1.0;  s.b[2] = 0.0;
+    } else if (scheme == AAO_WAVE_BD4) {
+        s.s = 3;
+        s.a[0] = 2.0;  s.b[0] = t2;
+        s.a[1] = -5.0; s.b[1] = 0.0;
+        s.a[2] = 4.0;  s.b[2] = 0.0;
+        s.a[3] = -1.0; s.b[3] = 0.0;
+        s.nst = 2;
+        s.sa[0][0] = 1.0;  s.sb[0][0] = t2;           // B
+        s.sa[1][0] = 1.0;  s.sb[1][0] = t2;           // B
+        s.sa[1][1] = -2.0;                             // C
+    } else if (scheme == AAO_WAVE_CD) {
+        s.s = 1;
+        s.a[0] = -2.0; s.b[0] = t2;
+        s.a[1] = 1.0;  s.b[1] = 0.0;
+        s.up = 1;
+        s.au = 1.0;    s.bu = 0.0;
     } else {
         return false;
     }
@@ -428,7 +451,8 @@ std::vector<int> tune_candidates(aao_ctx ctx, int kind)
         for (int c = 0; c < solve_num_configs(); ++c)
             if (solve_config_ok(c, (int)ctx->n)) out.push_back(c);
     } else if (kind == AAO_CFG_MATVEC) {
-        for (int c = 0; c < matvec_num_configs(); ++c) out.push_back(c);
+        if (!scheme_generic(ctx->sc))   // the generic matvec has one launch shape
+            for (int c = 0; c < matvec_num_configs(); ++c) out.push_back(c);
     } else if (!ctx->bluestein) {
         int buf[32];
         const int k = fft_configs((int)ctx->ell, (int)ctx->n, single, buf, 32);
@@ -592,7 +616,9 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     for (int j = 0; j < m; ++j) Zl.p[j] = ctx->Z + N * j;
     double *V0 = ctx->V;
     const int mcfg = ctx->cf(AAO_CFG_MATVEC);
-    const bool fused = matvec_blocks(n, ell, mcfg) <= ldp;
+    // the Toeplitz matvec also forms the first Gram-Schmidt dots and residual norms;
+    // the start-up-row and two-sided schemes take a plain matvec and separate passes
+    const bool fused = matvec_blocks(n, ell, mcfg) <= ldp && !scheme_generic(ctx->sc);
     auto residual = [&](bool store) -> aao_status {
         // V_0 = b - A x, vs_0 = 1/||V_0|| (the norm formed by the same launch); with
         // store false only the norm (the check after a cycle, before a restart is
@@ -891,7 +917,9 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
     if (!out) return AAO_ERR_ARG;
     *out = nullptr;
     if (n < 1 || ell < 1 || !(tau > 0.0) || !std::isfinite(tau)) return AAO_ERR_ARG;
-    if (scheme != AAO_HEAT_IE && scheme != AAO_WAVE_BD2) return AAO_ERR_ARG;
+    if (scheme != AAO_HEAT_IE && scheme != AAO_WAVE_BD2 && scheme != AAO_WAVE_BD4 &&
+        scheme != AAO_WAVE_CD)
+        return AAO_ERR_ARG;
     if (n > 16384 || ell > 65535 || (double)n * (double)ell > 4.0e9) return AAO_ERR_UNSUPPORTED;
     aao_ctx ctx = nullptr;
     try {
@@ -1111,6 +1139,8 @@ aao_status aao_build_rhs(aao_ctx ctx, const double *u0, const double *v0, double
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
     if (!u0 || !b) return arg_err(ctx, "null vector");
+    if (v0 && ctx->scheme == AAO_WAVE_CD)
+        return arg_err(ctx, "the central-difference system takes no initial velocity");
     AAO_HIP(launch_build_rhs(b, u0, v0, (int)ctx->n, (int)ctx->ell, ctx->sc, ctx->kappa, ctx->tau,
                              ctx->st));
     return AAO_OK;
@@ -1184,16 +1214,28 @@ aao_status aao_grad(aao_ctx ctx, const double *u0, const double *v0, const doubl
     if (!U || !lam || !g_u0) return arg_err(ctx, "null vector");
     const int n = (int)ctx->n;
     const double tau = ctx->tau, kap = ctx->kappa;
-    const bool bd2 = ctx->scheme == AAO_WAVE_BD2;
-    if (bd2 && g_kappa && !u0) return arg_err(ctx, "u0 needed for the BD2 kappa gradient");
+    // BD2 and BD4 share the start-up row b_1 = (M + tau^2 kappa K)(u0 + tau v0)
+    const bool wave = ctx->scheme == AAO_WAVE_BD2 || ctx->scheme == AAO_WAVE_BD4;
+    const bool bd2 = wave;
+    if (wave && g_kappa && !u0) return arg_err(ctx, "u0 needed for the wave kappa gradient");
     hipStream_t st = ctx->st;
     const double *lam1 = lam, *lam2 = ctx->ell > 1 ? lam + n : nullptr;
-    if (!bd2) {
+    const double *lam3 = ctx->ell > 2 ? lam + 2 * (size_t)n : nullptr;
+    if (ctx->scheme == AAO_HEAT_IE) {
         AAO_HIP(launch_mk(lam1, 1.0, 0.0, nullptr, 0.0, 0.0, g_u0, n, st));
-        if (g_v0) AAO_HIP(launch_fill(g_v0, 0.0, (size_t)n, st));
+    } else if (ctx->scheme == AAO_WAVE_CD) {
+        AAO_HIP(launch_mk(lam1, -1.0, 0.0, nullptr, 0.0, 0.0, g_u0, n, st));   // b_1 = -M u0
     } else {
-        AAO_HIP(launch_mk(lam1, 1.0, tau * tau * kap, lam2, lam2 ? -1.0 : 0.0, 0.0, g_u0, n, st));
-        if (g_v0) AAO_HIP(launch_mk(lam1, tau, tau * tau * tau * kap, nullptr, 0.0, 0.0, g_v0, n, st));
+        // BD2: A_0 lam_1 - M lam_2; BD4: B lam_1 - M lam_2 + M lam_3
+        const bool bd4 = ctx->scheme == AAO_WAVE_BD4;
+        AAO_HIP(launch_mk(lam1, 1.0, tau * tau * kap, lam2, lam2 ? -1.0 : 0.0, 0.0, g_u0, n, st,
+                          bd4 ? lam3 : nullptr, 1.0, 0.0));
+    }
+    if (g_v0) {
+        if (wave)
+            AAO_HIP(launch_mk(lam1, tau, tau * tau * tau * kap, nullptr, 0.0, 0.0, g_v0, n, st));
+        else
+            AAO_HIP(launch_fill(g_v0, 0.0, (size_t)n, st));
     }
     if (g_kappa) {
         const int nb = dot_blocks(ctx->N());

@@ -36,12 +36,40 @@ template <typename T> __host__ __device__ inline cx<T> recip(cx<T> a) {
 }
 
 // ------------------------------------------------------------- scheme data
-// Blocks A_m = a_m M + b_m kappa K, m = 0..s (s <= 3).
+// The block in row k, column k - m of the monolithic matrix is a_m M + b_m kappa K
+// for the Toeplitz rows, m = 0..s (s <= 3); with up = 1 also one block above the
+// diagonal (m = -1): au M + bu kappa K; the first nst rows (nst <= 2) are start-up
+// rows with their own lower blocks sa[k][m] M + sb[k][m] kappa K (zero pairs absent).
+// The circulant preconditioner wraps the Toeplitz blocks (m = -up..s).
 struct Scheme {
+    int id;            // AAO_HEAT_IE, AAO_WAVE_BD2, ...
     int s;
     double a[4];
     double b[4];
+    int up;
+    double au, bu;
+    int nst;
+    double sa[2][4], sb[2][4];
 };
+// schemes whose matvec is not the plain lower-triangular Toeplitz one
+__host__ __device__ inline bool scheme_generic(const Scheme &sc) { return sc.up || sc.nst > 0; }
+// coefficients (cm, cb) of the block in row `row`, offset m (cm M + cb kappa K); false
+// if that block is zero (row and column bounds are the caller's)
+__host__ __device__ inline bool scheme_block(const Scheme &sc, int row, int m, double &cm,
+                                             double &cb)
+{
+    if (m < 0) {
+        if (m < -1 || !sc.up) return false;
+        cm = sc.au;
+        cb = sc.bu;
+    } else {
+        if (m > sc.s) return false;
+        const bool st = row < sc.nst;
+        cm = st ? sc.sa[row][m] : sc.a[m];
+        cb = st ? sc.sb[row][m] : sc.b[m];
+    }
+    return cm != 0.0 || cb != 0.0;
+}
 
 // Coefficients of a scheme constant of aao.h (AAO_HEAT_IE, ...) for step tau; false
 // for an unknown scheme.
@@ -208,9 +236,11 @@ hipError_t launch_fill(double *x, double v, size_t N, hipStream_t st);
 hipError_t launch_grad_kappa_parts(const double *U, const double *lam, int n, int ell,
                                    Scheme sc, const double *tau_k, double *part, int nblk,
                                    hipStream_t st);
-// y = (cm M + ck K) x for one n-vector, plus optional y += (cm2 M + ck2 K) x2
+// y = (cm M + ck K) x for one n-vector, plus optional y += (cm2 M + ck2 K) x2 and
+// y += (cm3 M + ck3 K) x3
 hipError_t launch_mk(const double *x, double cm, double ck, const double *x2, double cm2,
-                     double ck2, double *y, int n, hipStream_t st);
+                     double ck2, double *y, int n, hipStream_t st, const double *x3 = nullptr,
+                     double cm3 = 0.0, double ck3 = 0.0);
 hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double *part,
                              hipStream_t st);
 

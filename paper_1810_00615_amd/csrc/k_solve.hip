@@ -384,6 +384,8 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
 // d_j, e_j of every half-spectrum row, for the symbol (tr = 0) and its conjugate
 // (tr = 1): sym[(2 j + tr) * 4 + {0, 1, 2, 3}] = Re d, Im d, Re e, Im e with
 //   alpha_j = sum_m a_m w^{jm},  beta_j = sum_m b_m w^{jm},  w = exp(-+2 pi i/ell),
+//   m over the Toeplitz offsets -up..s (BD4: (1 - w^j)^2 (2 - w^j); central
+//   differences: w^{-j} - 2 + w^j = -4 sin^2(pi j / ell), real),
 //   d_j = alpha_j 4h/6 + beta_j kappa 2/h,  e_j = alpha_j h/6 - beta_j kappa/h.
 __global__ void k_symbols(double *__restrict__ sym, int n, int ell, Scheme sc, double kappa)
 {
@@ -392,14 +394,16 @@ __global__ void k_symbols(double *__restrict__ sym, int n, int ell, Scheme sc, d
     const double h = 1.0 / (n + 1.0);
     for (int tr = 0; tr < 2; ++tr) {
         double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-        for (int m = 0; m <= sc.s; ++m) {
-            const long long p = ((long long)j * m) % ell;
+        for (int m = -sc.up; m <= sc.s; ++m) {
+            // the Toeplitz blocks (start-up rows are not part of the circulant)
+            const double am = m < 0 ? sc.au : sc.a[m], bm = m < 0 ? sc.bu : sc.b[m];
+            const long long p = (((long long)j * m) % ell + ell) % ell;
             double sn, cs;
             sincospi((tr ? 2.0 : -2.0) * (double)p / (double)ell, &sn, &cs);
-            ar += sc.a[m] * cs;
-            ai += sc.a[m] * sn;
-            br += sc.b[m] * cs;
-            bi += sc.b[m] * sn;
+            ar += am * cs;
+            ai += am * sn;
+            br += bm * cs;
+            bi += bm * sn;
         }
         double *o = sym + ((size_t)j * 2 + tr) * 4;
         o[0] = ar * (4.0 * h / 6.0) + br * kappa * (2.0 / h);

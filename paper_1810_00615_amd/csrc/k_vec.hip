@@ -7,6 +7,7 @@
 // (fixed in-block tree) into a value-major array part[i * ldp + block], and the
 // partials are summed in a fixed order (k_reduce_parts, k_reduce_small).  No
 // floating-point atomics.
+#include "../../include/aao.h"
 #include "aao_internal.h"
 #include "lanes.h"
 
@@ -628,10 +629,45 @@ int matvec_blocks(int n, int ell, int cfg)
     return ((n + 255) / 256) * ((ell + R - 1) / R);
 }
 
+// Matvec of the schemes with start-up rows (BD4) or a block above the diagonal
+// (central differences): y_k = sum_m A_{k,k-m} x_{k-m}, or (transpose) y_k =
+// sum_m A_{k+m,k} x_{k+m} (every block symmetric); y = bsub - A x if bsub.  One
+// thread per output entry; the input rows of neighbouring threads and time levels
+// overlap, which the caches serve.
+__global__ void __launch_bounds__(256)
+k_matvec_gen(const double *__restrict__ x, double *__restrict__ y,
+             const double *__restrict__ bsub, int n, int ell, Scheme sc, double kappa,
+             int transpose)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= n) return;
+    const double h = 1.0 / (n + 1.0);
+    double acc = 0.0;
+    for (int m = -sc.up; m <= sc.s; ++m) {
+        const int src = transpose ? k + m : k - m;
+        const int row = transpose ? k + m : k;
+        if (src < 0 || src >= ell) continue;
+        double cm, cb;
+        if (!scheme_block(sc, row, m, cm, cb)) continue;
+        const double *xr = x + (size_t)src * n;
+        const double xl = i > 0 ? xr[i - 1] : 0.0, xc = xr[i], xrr = i < n - 1 ? xr[i + 1] : 0.0;
+        acc += cm * (h / 6.0) * (xl + 4.0 * xc + xrr) + cb * kappa * (1.0 / h) * (2.0 * xc - xl - xrr);
+    }
+    y[(size_t)k * n + i] = bsub ? bsub[(size_t)k * n + i] - acc : acc;
+}
+
 hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
                          Scheme sc, double kappa, const double *tau_k, int transpose,
                          hipStream_t st, int cfg, const VecList *V, int nv, double *part, int ldp)
 {
+    if (scheme_generic(sc)) {
+        // no fused dot products, no variable steps for these schemes
+        if (nv > 0 || tau_k || !y) return hipErrorInvalidValue;
+        dim3 grid((n + 255) / 256, ell);
+        k_matvec_gen<<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, transpose);
+        return hipGetLastError();
+    }
     if (cfg < 0 || cfg >= matvec_num_configs()) cfg = matvec_default_config();
     if (nv > 0 && (!V || !part || nv >= kMaxVecs || matvec_blocks(n, ell, cfg) > ldp))
         return hipErrorInvalidValue;
@@ -651,27 +687,30 @@ hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, 
     }
 }
 
-// y = (cm M + ck K) x (+ (cm2 M + ck2 K) x2), one n-vector
+// y = (cm M + ck K) x (+ (cm2 M + ck2 K) x2 + (cm3 M + ck3 K) x3), one n-vector
 __global__ void k_mk(const double *__restrict__ x, double cm, double ck,
                      const double *__restrict__ x2, double cm2, double ck2,
+                     const double *__restrict__ x3, double cm3, double ck3,
                      double *__restrict__ y, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double h = 1.0 / (n + 1.0);
-    const double xl = i > 0 ? x[i - 1] : 0.0, xr = i < n - 1 ? x[i + 1] : 0.0;
-    double v = cm * (h / 6.0) * (xl + 4.0 * x[i] + xr) + ck * (1.0 / h) * (2.0 * x[i] - xl - xr);
-    if (x2) {
-        const double zl = i > 0 ? x2[i - 1] : 0.0, zr = i < n - 1 ? x2[i + 1] : 0.0;
-        v += cm2 * (h / 6.0) * (zl + 4.0 * x2[i] + zr) + ck2 * (1.0 / h) * (2.0 * x2[i] - zl - zr);
-    }
+    auto term = [&](const double *z, double a, double c) {
+        const double zl = i > 0 ? z[i - 1] : 0.0, zr = i < n - 1 ? z[i + 1] : 0.0;
+        return a * (h / 6.0) * (zl + 4.0 * z[i] + zr) + c * (1.0 / h) * (2.0 * z[i] - zl - zr);
+    };
+    double v = term(x, cm, ck);
+    if (x2) v += term(x2, cm2, ck2);
+    if (x3) v += term(x3, cm3, ck3);
     y[i] = v;
 }
 
 hipError_t launch_mk(const double *x, double cm, double ck, const double *x2, double cm2,
-                     double ck2, double *y, int n, hipStream_t st)
+                     double ck2, double *y, int n, hipStream_t st, const double *x3, double cm3,
+                     double ck3)
 {
-    k_mk<<<(n + 255) / 256, 256, 0, st>>>(x, cm, ck, x2, cm2, ck2, y, n);
+    k_mk<<<(n + 255) / 256, 256, 0, st>>>(x, cm, ck, x2, cm2, ck2, x3, cm3, ck3, y, n);
     return hipGetLastError();
 }
 
@@ -706,27 +745,40 @@ hipError_t launch_project_sine(double *u0, int n, int J, const int *modes, const
     return hipGetLastError();
 }
 
-// heat: b_1 = M u0; BD2: b_1 = A_0 (u0 + tau v0), b_2 = -M u0; other rows 0.
+// Right-hand sides (the u0 / v0 terms of the first rows moved to the right):
+//   heat: b_1 = M u0;
+//   BD2:  b_1 = A_0 (u0 + tau v0), b_2 = -M u0;
+//   BD4:  b_1 = B (u0 + tau v0), b_2 = -M u0, b_3 = M u0 (B = M + tau^2 kappa K);
+//   CD:   b_1 = -M u0;
+// other rows 0.  wave: BD2 / BD4 (start-up row with tau^2 kappa K: kb = tau^2 kappa).
 __global__ void k_build_rhs(double *__restrict__ b, const double *__restrict__ u0,
-                            const double *__restrict__ v0, int n, int ell, int bd2,
-                            double a0b, double tau)
+                            const double *__restrict__ v0, int n, int ell, int id, double kb,
+                            double tau)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = blockIdx.y;
     if (i >= n) return;
     const double h = 1.0 / (n + 1.0);
+    const bool wave = id == AAO_WAVE_BD2 || id == AAO_WAVE_BD4;
+    const double ul = i > 0 ? u0[i - 1] : 0.0, ur = i < n - 1 ? u0[i + 1] : 0.0;
+    const double mu = (h / 6.0) * (ul + 4.0 * u0[i] + ur);
     double v = 0.0;
     if (k == 0) {
-        auto w = [&](int p) {
-            if (p < 0 || p >= n) return 0.0;
-            return u0[p] + (v0 ? tau * v0[p] : 0.0);
-        };
-        const double wl = w(i - 1), wc = w(i), wr = w(i + 1);
-        v = (h / 6.0) * (wl + 4.0 * wc + wr);
-        if (bd2) v += a0b * (1.0 / h) * (2.0 * wc - wl - wr);
-    } else if (k == 1 && bd2) {
-        const double ul = i > 0 ? u0[i - 1] : 0.0, ur = i < n - 1 ? u0[i + 1] : 0.0;
-        v = -(h / 6.0) * (ul + 4.0 * u0[i] + ur);
+        if (id == AAO_WAVE_CD) {
+            v = -mu;
+        } else {
+            auto w = [&](int p) {
+                if (p < 0 || p >= n) return 0.0;
+                return u0[p] + (v0 ? tau * v0[p] : 0.0);
+            };
+            const double wl = w(i - 1), wc = w(i), wr = w(i + 1);
+            v = (h / 6.0) * (wl + 4.0 * wc + wr);
+            if (wave) v += kb * (1.0 / h) * (2.0 * wc - wl - wr);
+        }
+    } else if (k == 1 && wave) {
+        v = -mu;
+    } else if (k == 2 && id == AAO_WAVE_BD4) {
+        v = mu;
     }
     b[(size_t)k * n + i] = v;
 }
@@ -734,15 +786,17 @@ __global__ void k_build_rhs(double *__restrict__ b, const double *__restrict__ u
 hipError_t launch_build_rhs(double *b, const double *u0, const double *v0, int n, int ell,
                             Scheme sc, double kappa, double tau, hipStream_t st)
 {
-    const int bd2 = sc.s == 2;
+    const bool wave = sc.id == AAO_WAVE_BD2 || sc.id == AAO_WAVE_BD4;
     dim3 grid((n + 255) / 256, ell);
-    k_build_rhs<<<grid, 256, 0, st>>>(b, u0, bd2 ? v0 : nullptr, n, ell, bd2, sc.b[0] * kappa,
-                                      tau);
+    k_build_rhs<<<grid, 256, 0, st>>>(b, u0, wave ? v0 : nullptr, n, ell, sc.id,
+                                      tau * tau * kappa, tau);
     return hipGetLastError();
 }
 
 // ----------------------------------------------------- gradient (kappa)
-// partials of sum_k sum_m c_m^{(k)} lam_k . (K u_{k-m}),  c_m = b_m (tau_k for m = 0)
+// partials of sum_k sum_m c_m^{(k)} lam_k . (K u_{k-m}),  c_m^{(k)} the K coefficient
+// (without kappa) of block (k, k - m): b_m, tau_k for m = 0 with variable steps, the
+// start-up rows' own, bu above the diagonal
 __global__ void __launch_bounds__(kRedThreads)
 k_grad_kappa(const double *__restrict__ U, const double *__restrict__ lam, int n, int ell,
              Scheme sc, const double *__restrict__ tau_k, double *__restrict__ part)
@@ -756,10 +810,11 @@ k_grad_kappa(const double *__restrict__ U, const double *__restrict__ lam, int n
         const int k = (int)(e / n);
         const int i = (int)(e - (size_t)k * n);
         double ku = 0.0;
-        for (int m = 0; m <= sc.s; ++m) {
-            double cm = sc.b[m];
+        for (int m = -sc.up; m <= sc.s; ++m) {
+            double am = 0.0, cm = 0.0;
+            if (!scheme_block(sc, k, m, am, cm)) continue;
             if (m == 0 && tau_k) cm = tau_k[k];
-            if (cm == 0.0 || k - m < 0) continue;
+            if (cm == 0.0 || k - m < 0 || k - m >= ell) continue;
             const double *ur = U + (size_t)(k - m) * n;
             const double ul = i > 0 ? ur[i - 1] : 0.0, urr = i < n - 1 ? ur[i + 1] : 0.0;
             ku += cm * hinv * (2.0 * ur[i] - ul - urr);
