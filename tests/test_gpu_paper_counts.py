@@ -65,7 +65,7 @@ def test_gpu_table2_neumann_counts(orc, delta):
         A = lambda v: P.A(to(v)).cpu().numpy().ravel()
         Pi = lambda v: P.Pinv(to(v), order=q).cpu().numpy().ravel()
         c, _ = table2_count(orc, n, ell, delta, q, [7, q], apply_op=A, apply_prec=Pi)
-        b = P.rhs(torch.as_tensor(paper_initial_data("x(1-x)", n), device="cuda"))
+        b = P.rhs(torch.as_tensor(paper_initial_data("bump", n), device="cuda"))
         x, info = P.solve(b, restart=30, tol=1e-5, maxit=100)
         br = b.cpu().numpy().ravel()
         xo, io = orc.fgmres(lambda v: orc.apply_A(0, n, ell, tau, 1.0, v, tau_k=tk).ravel(),

@@ -62,22 +62,22 @@ def table2_rows():
 
 
 def table2_count(orc, n, ell, delta, q, seed, apply_op=None, apply_prec=None):
-    """Table 2 as read here: Table 1's initial data x(1-x) on the jittered grid, the
-    left-preconditioned system Q_i^{-1} B U = Q_i^{-1} b (i = q + 1 terms of
-    eq. preconapprox1), GMRES from 0 stopping when the preconditioned residual
-    |Q_i^{-1}(b - B U)| <= 1e-5 (absolute), counting the initial residual as one more
-    iteration (the convention under which Table 1's count is 2)."""
+    """Table 2 as read here: the left-preconditioned system Q_i^{-1} B U = Q_i^{-1} b
+    (i = q + 1 terms of eq. preconapprox1) on the jittered grid, GMRES from 0 to the
+    relative tolerance 1e-5 counted in preconditioner applies (the convention the
+    Table 1, 3 and 4 pins use), with the paper's non-smooth initial data u_0^{ns}
+    (Table 2 does not name its data; with Table 1's smooth x(1-x) every count comes out
+    one to three below the printed one)."""
     from paper_1810_00615_amd.inputs import paper_initial_data, perturbed_steps
     tau = 1.0 / ell
     tk = perturbed_steps(ell, delta, seed)
-    b = orc.build_rhs(0, n, ell, tau, 1.0, paper_initial_data("x(1-x)", n)).ravel()
+    b = orc.build_rhs(0, n, ell, tau, 1.0, paper_initial_data("bump", n)).ravel()
     A = apply_op or (lambda v: orc.apply_A(0, n, ell, tau, 1.0, v, tau_k=tk).ravel())
     P = apply_prec or (lambda v: orc.neumann(0, n, ell, tau, 1.0, tk, v, q).ravel())
-    pb = P(b)
-    x, info = orc.fgmres(lambda v: P(A(v)), lambda v: v, pb, restart=100,
-                         tol=1e-5 / np.linalg.norm(pb), maxit=100)
+    x, info = orc.fgmres(lambda v: P(A(v)), lambda v: v, P(b), restart=100, tol=1e-5,
+                         maxit=100)
     assert info["converged"]
-    return info["iters"] + 1, tk
+    return info["iters"], tk
 
 
 @pytest.mark.parametrize("row", [r for r in table2_rows() if r[0] in ("a", "f")
