@@ -87,6 +87,7 @@ struct aao_ctx_s {
     // lengths that are not powers of two: Bluestein transforms (the batched
     // kernels with a batch of one)
     bool bluestein = false;
+    double *ntmp = nullptr;      // r - E z of a Neumann term (Bluestein lengths)
     BProb *bl_prob = nullptr;
     int2 *bl_tiles = nullptr;
     int bl_ntiles = 0;
@@ -373,8 +374,16 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     AAO_TRY(refresh_symbols(ctx));
     AAO_TRY(refresh_tables(ctx, ctx->cf(AAO_CFG_SHIFTED_SOLVE), true));
     const double solve_bytes = spec_in_bytes(ctx) + spec_out_bytes(ctx);
-    if (ctx->bluestein && !zprev) {
+    if (ctx->bluestein) {
         const BatchLaunch L = bl_launch(ctx);
+        if (zprev) {
+            // a Neumann term: the Bluestein tiles transform r - E z_prev, formed first
+            if (!ctx->ntmp) AAO_TRY(dev_alloc(ctx, (void **)&ctx->ntmp, sizeof(double) * ctx->N()));
+            AAO_HIP(launch_neumann_rhs(r, in_scale, zprev, ctx->sigk, ctx->kappa, n, ell,
+                                       ctx->ntmp, ctx->st));
+            r = ctx->ntmp;
+            in_scale = nullptr;
+        }
         AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) + spec_in_bytes(ctx),
                      batch_fft_fwd(L, r, in_scale, 0, ispec, sin, ctx->st));
         AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, solve_bytes,
@@ -1033,6 +1042,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->dmodes);
     (void)hipFree(ctx->damps);
     (void)hipFree(ctx->segpart);
+    (void)hipFree(ctx->ntmp);
     (void)hipFree(ctx->bl_prob);
     (void)hipFree(ctx->bl_tiles);
     (void)hipFree(ctx->bl_chirp);

@@ -230,6 +230,10 @@ hipError_t launch_scale(const double *w, const double *scale, double *out, size_
 // out = a * w (host scalar a)
 hipError_t launch_scale_h(const double *w, double a, double *out, size_t N, hipStream_t st);
 hipError_t launch_fill(double *x, double v, size_t N, hipStream_t st);
+// out = s r - blockdiag(sigma_k kappa K) z, s = *scale (nullptr: 1); ell x n vectors
+hipError_t launch_neumann_rhs(const double *r, const double *scale, const double *z,
+                              const double *sigk, double kappa, int n, int ell, double *out,
+                              hipStream_t st);
 
 // Gradient reduction helpers
 // partial sums of sum_k sum_m c_m^{(k)} lam_k . K u_{k-m} (negated later)

@@ -629,6 +629,30 @@ int matvec_blocks(int n, int ell, int cfg)
     return ((n + 255) / 256) * ((ell + R - 1) / R);
 }
 
+// out = s r - E z, E = blockdiag(sigma_k kappa K) (the residual a Neumann term of
+// eq. preconapprox1 transforms), s = *scale or 1; kap_h = kappa / h.
+__global__ void k_neumann_rhs(const double *__restrict__ r, const double *__restrict__ scale,
+                              const double *__restrict__ z, const double *__restrict__ sigk,
+                              double kap_h, int n, int ell, double *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y;
+    if (i >= n) return;
+    const size_t o = (size_t)k * n + i;
+    const double zl = i > 0 ? z[o - 1] : 0.0, zr = i < n - 1 ? z[o + 1] : 0.0;
+    const double s = scale ? *scale : 1.0;
+    out[o] = s * r[o] - sigk[k] * kap_h * (2.0 * z[o] - zl - zr);
+}
+
+hipError_t launch_neumann_rhs(const double *r, const double *scale, const double *z,
+                              const double *sigk, double kappa, int n, int ell, double *out,
+                              hipStream_t st)
+{
+    dim3 grid((n + 255) / 256, ell);
+    k_neumann_rhs<<<grid, 256, 0, st>>>(r, scale, z, sigk, kappa * (n + 1.0), n, ell, out);
+    return hipGetLastError();
+}
+
 // Matvec of the schemes with start-up rows (BD4) or a block above the diagonal
 // (central differences): y_k = sum_m A_{k,k-m} x_{k-m}, or (transpose) y_k =
 // sum_m A_{k+m,k} x_{k+m} (every block symmetric); y = bsub - A x if bsub.  One

@@ -193,6 +193,23 @@ def test_neumann_orders(aao, orc, torch_dev, q, transpose):
     assert normrel(z, ref) < 1e-10
 
 
+@pytest.mark.parametrize("ell", [5, 97, 1100])
+@pytest.mark.parametrize("q", [1, 2])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_neumann_orders_other_lengths(aao, orc, torch_dev, ell, q, transpose):
+    """Neumann terms at lengths that are not powers of two: Bluestein transforms of
+    r - E z (ell = 97, 1100) and the direct transform (ell = 5)."""
+    n = 63
+    tau = 1.0 / ell
+    from paper_1810_00615_amd.inputs import perturbed_steps
+    tk = perturbed_steps(ell, 0.7, [3, ell])
+    r = rand_vec((ell, n), [13, ell])
+    P = aao.Problem(n, ell, tau, "heat", kappa=1.2, steps=tk, device=torch_dev[1])
+    z = P.Pinv(to_dev(torch_dev, r), order=q, transpose=transpose).cpu().numpy()
+    ref = orc.neumann(HEAT, n, ell, tau, 1.2, tk, r, q, transpose=transpose)
+    assert normrel(z, ref) < 1e-10
+
+
 def test_neumann_uniform_steps_equal_order0(aao, torch_dev):
     n, ell = 31, 32
     r = rand_vec((ell, n), 12)
