@@ -92,6 +92,8 @@ def cpu_baseline(w, seconds_cap=60.0):
 
     import oracle
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if nthreads == 1:
+        seconds_cap = 25.0
     u0 = oracle.project_sine(w.n, w.modes, w.amps)
     b = oracle.build_rhs(oracle.HEAT, w.n, w.ell, w.tau, w.kappa, u0)
     times = []
@@ -116,6 +118,71 @@ def cpu_baseline(w, seconds_cap=60.0):
         "seconds": t_gmres,
         "sequential_timestepping_s": t_seq,
     }
+
+
+def cpu_baseline_single_core(timeout=240):
+    """cpu_baseline with one OpenMP thread, in a child process (the thread count of the
+    oracle's OpenMP runtime is fixed when its library loads)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+    code = ("import json, bench; from paper_1810_00615_amd.inputs import heat_large; "
+            "print(json.dumps(bench.cpu_baseline(heat_large())))")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                           text=True, timeout=timeout)
+        return json.loads(r.stdout.strip().splitlines()[-1])
+    except Exception as e:      # reported, not fatal
+        return {"error": repr(e)}
+
+
+def bench_beyond_cache(args):
+    """Heat n = 4095, ell = 16384 (67 M unknowns, 537 MB per FP64 vector, twice the
+    256 MB last-level cache): the preconditioner apply and its kernels, the matvec, and
+    the FP64 FGMRES(30) solve to 1e-8, so that the bandwidth figures are HBM figures."""
+    import torch
+
+    from paper_1810_00615_amd import Problem
+    from paper_1810_00615_amd.inputs import heat_large
+    w = heat_large(4095, 16384)
+    P = Problem(w.n, w.ell, w.tau, "heat", kappa=w.kappa)
+    b = P.rhs(P.project_sine(w.modes, w.amps))
+    N, S = w.n * w.ell, (w.ell // 2 + 1) * w.n
+    out = {"workload": w.name, "unknowns": N, "vector_MB": 8 * N / 1e6}
+    z = P.empty()
+    for prec in ("fp64", "mixed_in"):
+        P.set_precision(prec)
+        if not args.no_tune:
+            P.tune(reps=3)
+        for _ in range(2):
+            P.Pinv(b, out=z)
+        P.set_timing(True)
+        t, _ = _time(lambda: P.Pinv(b, out=z), 10)
+        kt = P.timing()
+        P.set_timing(False)
+        w_in = 16 if prec == "fp64" else 8
+        alg = 16 * N + 2 * (w_in + 16) * S
+        out[f"pinv_{prec}"] = {
+            "us": t * 1e6, "alg_bytes": alg, "GBps": alg / t / 1e9,
+            "frac_hbm": alg / t / 1e9 / HBM_PEAK_GBPS,
+            "kernel_avg_us": {k: kt[k][0] / max(kt[k][1], 1) * 1e3
+                              for k in ("fft_fwd", "shifted_solve", "fft_inv")},
+            "kernel_GBps": {k: kt[k][2] / max(kt[k][0], 1e-12) / 1e6
+                            for k in ("fft_fwd", "shifted_solve", "fft_inv")}}
+    P.set_precision("fp64")
+    P.set_timing(["matvec"])
+    t, _ = _time(lambda: P.A(b, out=z), 10)
+    km = P.timing()["matvec"]
+    P.set_timing(False)
+    out["matvec"] = {"us": km[0] / km[1] * 1e3, "GBps": km[2] / (km[0] * 1e-3) / 1e9,
+                     "frac_hbm": km[2] / (km[0] * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    x = P.empty()
+    P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit, out=x)
+    t, (_, info) = _time(lambda: P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit,
+                                         out=x), 2)
+    out["fp64_solve"] = {"solve_ms": t * 1e3, "iters": info["iters"],
+                         "true_rel_resid": info["rel_resid_true"]}
+    P.close()
+    return out
 
 
 def _time(fn, reps):
@@ -277,6 +344,8 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched 64-problem solves, FP64 and mixed (for profiler "
                          "runs): no headline, no sequential comparison")
+    ap.add_argument("--tune-cache", default=None,
+                    help="file of tuned launch shapes read and appended by the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain device copy of one ell x n FP64 vector "
                          "(reference kernel for the HBM byte counters)")
@@ -288,6 +357,9 @@ def main():
 
     import torch
 
+    if args.tune_cache:
+        from paper_1810_00615_amd.api import set_tune_cache
+        set_tune_cache(args.tune_cache)
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(args)}), flush=True)
         return
@@ -399,6 +471,11 @@ def main():
     out["pinv_fp64"] = time_pinv("fp64")
     out["pinv_mixed"] = time_pinv("mixed")
     out["pinv_mixed_in"] = time_pinv("mixed_in")
+    # the preconditioner apply against the HBM roofline (algorithmic bytes / apply time)
+    pf = out["pinv_fp64"]
+    out["pinv_roofline"] = {"bound": "hbm", "achieved": pf["GBps"], "peak": HBM_PEAK_GBPS,
+                            "unit": "GB/s", "frac": pf["frac_hbm"],
+                            "bytes_per_apply": pf["alg_bytes"], "us": pf["us"]}
 
     # --------------------------------------------------------------- mixed
     # "mixed": single-precision transforms and spectra on both sides of the solves;
@@ -419,7 +496,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extra:
         for key, fn in (("wave_bd2", bench_wave), ("batch", bench_batch),
-                        ("adjoint", bench_adjoint)):
+                        ("adjoint", bench_adjoint), ("beyond_cache", bench_beyond_cache)):
             try:
                 out[key] = fn(args)
             except Exception as e:          # the headline line is printed regardless
@@ -428,6 +505,7 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"]["single_core"] = cpu_baseline_single_core()
     print(json.dumps(out))
 
 

@@ -319,8 +319,9 @@ aao_status aao_config_shape(aao_ctx ctx, int kind, int code, int shape[3]);
 /* ------------------------------------------------------------------ batch
  * Many independent problems of uneven size advanced together: every phase of an
  * Arnoldi step is one launch over a work table spanning all problems, converged
- * problems are masked out on the device, and the launch sequence of each
- * Arnoldi step is captured once into a hipGraph and replayed.  Batch vectors
+ * problems are masked out on the device, and the launch sequence of a group of
+ * Arnoldi steps (AAO_BCFG_GRAPH_SPAN, up to a whole restart cycle) is captured once
+ * into a hipGraph and replayed.  Batch vectors
  * concatenate the ell_p x n_p arrays of the problems at the offsets returned by
  * aao_batch_offsets (aligned to 64 elements); per-node vectors (u0)
  * concatenate the n_p-vectors without gaps.  The transform along time uses
@@ -343,6 +344,25 @@ aao_status aao_batch_destroy(aao_batch b);
 aao_status aao_batch_offsets(aao_batch b, int64_t *offsets, int64_t *total);
 /* hipGraph replay of the Arnoldi steps on (1, default) or off (0, eager launches) */
 aao_status aao_batch_set_graph(aao_batch b, int enable);
+/* Launch shapes of a batch and their tuner.
+ *   AAO_BCFG_SLAB        elements per slab of the Gram-Schmidt, update and solution
+ *                        passes (a power of two in [256, 65536]; default 4096)
+ *   AAO_BCFG_MATVEC_ROWS time levels per matvec tile (2, 4 or 8; default 4)
+ *   AAO_BCFG_GRAPH_SPAN  Arnoldi steps per captured graph (1..63), or 0 for the rest of
+ *                        the restart cycle: one graph launch per cycle, the host reads
+ *                        the number of active problems once per graph.  Steps after
+ *                        every problem converged run fully masked, so the results do
+ *                        not depend on the span (default 1)
+ * aao_batch_tune times the candidates of each shape on the batch's own sizes (reps
+ * launches of the slab passes and of the matvec on scratch data; with a right-hand
+ * side bvec (device batch vector, may be NULL: span not tuned), reps zero-guess
+ * FGMRES(restart) solves of it for each span) and keeps the fastest; results are
+ * cached per process and in the aao_set_tune_cache file. */
+enum { AAO_BCFG_SLAB = 0, AAO_BCFG_MATVEC_ROWS = 1, AAO_BCFG_GRAPH_SPAN = 2, AAO_NUM_BCFG = 3 };
+aao_status aao_batch_get_config(aao_batch b, int kind, int *value);
+aao_status aao_batch_set_config(aao_batch b, int kind, int value);
+aao_status aao_batch_tune(aao_batch b, const double *bvec, int restart, double tol, int maxit,
+                          int reps);
 /* u0 (device, sum n_p) = L2 projections of sum_q amps[p*J + q] sin(modes[q] pi x) */
 aao_status aao_batch_project_sine(aao_batch b, int J, const int *modes, const double *amps,
                                   double *u0);

@@ -69,6 +69,10 @@ SIGNATURES = {
     "aao_batch_destroy": [ctypes.c_void_p],
     "aao_batch_offsets": [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)],
     "aao_batch_set_graph": [ctypes.c_void_p, ctypes.c_int],
+    "aao_batch_get_config": [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)],
+    "aao_batch_set_config": [ctypes.c_void_p, ctypes.c_int, ctypes.c_int],
+    "aao_batch_tune": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double,
+                       ctypes.c_int, ctypes.c_int],
     "aao_batch_project_sine": [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                ctypes.c_void_p],
     "aao_batch_build_rhs": [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
@@ -121,5 +125,6 @@ def check(status, where, ctx=None):
 
 GMRES_ZERO_GUESS, GMRES_TRANSPOSE, GMRES_CGS2_CLASSIC, GMRES_EARLY_CHECK = 1, 2, 4, 8
 CONFIG_KINDS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec"]
+BATCH_CONFIG_KINDS = ["slab", "matvec_rows", "graph_span"]
 KERNELS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec", "cgs_dot", "cgs_update_dot",
            "cgs_update_norm", "axpy", "arnoldi_update"]

@@ -13,7 +13,7 @@ from typing import Optional
 import numpy as np
 import torch
 
-from ._lib import (CONFIG_KINDS, GMRES_CGS2_CLASSIC, GMRES_EARLY_CHECK, GMRES_TRANSPOSE,
+from ._lib import (BATCH_CONFIG_KINDS, CONFIG_KINDS, GMRES_CGS2_CLASSIC, GMRES_EARLY_CHECK, GMRES_TRANSPOSE,
                    GMRES_ZERO_GUESS, KERNELS, AAOError, Info, check, lib)
 
 HEAT, BD2, BD4, CD = 0, 1, 2, 3
@@ -362,6 +362,28 @@ class Batch:
 
     def set_graph(self, enable: bool):
         self._c(self._L.aao_batch_set_graph(self._b, int(enable)), "aao_batch_set_graph")
+
+    def configs(self):
+        """{shape: value} of the batch's launch shapes (aao_batch_get_config)."""
+        out = {}
+        for kind, name in enumerate(BATCH_CONFIG_KINDS):
+            v = ctypes.c_int(0)
+            self._c(self._L.aao_batch_get_config(self._b, kind, ctypes.byref(v)),
+                    "aao_batch_get_config")
+            out[name] = v.value
+        return out
+
+    def set_config(self, shape: str, value: int):
+        self._c(self._L.aao_batch_set_config(self._b, BATCH_CONFIG_KINDS.index(shape), int(value)),
+                "aao_batch_set_config")
+
+    def tune(self, b=None, restart=30, tol=1e-8, maxit=300, reps=3):
+        """Time the candidate launch shapes on this batch (with a right-hand side b also
+        the graph span, by timing solves of it) and keep the fastest; returns configs()."""
+        self._sync_in()
+        self._c(self._L.aao_batch_tune(self._b, _ptr(b), int(restart), float(tol), int(maxit),
+                                       int(reps)), "aao_batch_tune")
+        return self.configs()
 
     def project_sine(self, modes, amps):
         """u0 for every problem (concatenated n_p-vectors); amps: (count, J)."""

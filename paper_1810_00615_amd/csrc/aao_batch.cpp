@@ -35,6 +35,10 @@ struct aao_batch_s {
     hipStream_t st = nullptr;
     bool own_stream = false;
     bool use_graph = true;
+    // launch shapes (aao_batch_set_config / aao_batch_tune): elements per slab of the
+    // Gram-Schmidt, update and solution passes; time levels per matvec tile; Arnoldi
+    // steps captured per graph (0 = the rest of the restart cycle)
+    int slab = kBatchSlabDefault, mrows = kMatvecRowsDefault, span = kGraphSpanDefault;
     // CGS2 with deferred re-orthogonalisation (two passes per Arnoldi step) unless the
     // solve asks for the three-pass form (AAO_GMRES_CGS2_CLASSIC)
     bool delayed = true;
@@ -65,9 +69,9 @@ struct aao_batch_s {
     int *iv = nullptr;              // iters | ksteps | nact
     unsigned char *flags = nullptr; // active | done | bad
     BState bs{};
-    std::vector<hipGraphExec_t> graphs;
+    std::vector<hipGraphExec_t> graphs;   // by first step: steps [j, j + span) of a cycle
     // the captured steps depend on these: a solve with other values recaptures
-    int graph_m = 0, graph_maxit = -1, graph_transpose = -1, graph_delayed = -1;
+    int graph_m = 0, graph_maxit = -1, graph_transpose = -1, graph_delayed = -1, graph_span = -1;
     double graph_tol = -1.0;
     double **dB = nullptr;           // one-entry pointer array for norms of the rhs
 
@@ -83,6 +87,7 @@ struct aao_batch_s {
         for (int c = 0; c < 5; ++c) L.row_start[c] = row_start[c];
         L.mtiles = mtiles;
         L.nmtiles = nmtiles;
+        L.mrows = mrows;
         L.slabs = slabs;
         L.nslabs = nslabs;
         L.pslabs = pslabs;
@@ -161,6 +166,48 @@ static aao_status ensure_ws(aao_batch b, int m)
     BT(upload(b, &b->dV, hv));
     BT(upload(b, &b->dZ, hz));
     b->m_alloc = m;
+    return AAO_OK;
+}
+
+// Work tables that depend on the launch shapes: matvec tiles (256 columns x mrows time
+// levels) with each problem's tile range, element slabs of `slab` elements with each
+// problem's slab range, and the block partials both leave (ldp values each).
+static aao_status build_work_tables(aao_batch b)
+{
+    std::vector<int4> mt, sl;
+    std::vector<int2> mr, ps;
+    for (int p = 0; p < b->count; ++p) {
+        const BProb &q = b->hp[p];
+        const int mfirst = (int)mt.size();
+        for (int by = 0; by < (q.ell + b->mrows - 1) / b->mrows; ++by)
+            for (int bx = 0; bx < (q.n + 255) / 256; ++bx) mt.push_back({p, bx, by, 0});
+        mr.push_back({mfirst, (int)mt.size()});
+        const size_t Np = (size_t)q.n * q.ell;
+        const int first = (int)sl.size();
+        for (size_t e0 = 0; e0 < Np; e0 += (size_t)b->slab)
+            sl.push_back({p, (int)e0, (int)std::min<size_t>((size_t)b->slab, Np - e0), 0});
+        ps.push_back({first, (int)sl.size()});
+    }
+    (void)hipFree(b->mtiles);
+    (void)hipFree(b->slabs);
+    (void)hipFree(b->pslabs);
+    (void)hipFree(b->mranges);
+    (void)hipFree(b->part);
+    b->mtiles = b->slabs = nullptr;
+    b->pslabs = b->mranges = nullptr;
+    b->part = nullptr;
+    b->nmtiles = (int)mt.size();
+    b->nslabs = (int)sl.size();
+    BT(upload(b, &b->mtiles, mt));
+    BT(upload(b, &b->slabs, sl));
+    BT(upload(b, &b->pslabs, ps));
+    BT(upload(b, &b->mranges, mr));
+    BT(balloc(b, (void **)&b->part, sizeof(double) * b->ldp * std::max(b->nslabs, b->nmtiles)));
+    // captured graphs hold the old tables
+    for (auto g : b->graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+    b->graphs.clear();
+    b->graph_m = 0;
     return AAO_OK;
 }
 
@@ -285,7 +332,7 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
 
     if (b->graph_m != m || b->graph_tol != tol || b->graph_maxit != maxit ||
         b->graph_transpose != transpose || b->graph_delayed != (int)b->delayed ||
-        (int)b->graphs.size() != m) {
+        b->graph_span != b->span || (int)b->graphs.size() != m) {
         for (auto g : b->graphs)
             if (g) (void)hipGraphExecDestroy(g);
         b->graphs.assign(m, nullptr);
@@ -294,6 +341,7 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
         b->graph_maxit = maxit;
         b->graph_transpose = transpose;
         b->graph_delayed = (int)b->delayed;
+        b->graph_span = b->span;
     }
     int nact = 0;
     int cycles = 0;
@@ -326,27 +374,39 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
             }
             break;
         }
+        // Arnoldi steps in groups of `span` (the rest of the cycle when span = 0), each
+        // group one captured graph; the host reads the number of active problems once per
+        // group.  Steps after every problem has converged run fully masked (each kernel
+        // finds no active work and returns), so a group's result does not depend on where
+        // the groups end.
         int steps_run = 0;
-        for (int j = 0; j < m; ++j) {
-            ++steps_run;
+        for (int j = 0; j < m;) {
             if (from_b && j == 0) {
-                // the captured step 0 reads V_0 from the workspace: launch eagerly
+                // the captured steps read V_0 from the workspace: step 0 of a cycle that
+                // starts from b is launched eagerly
                 BT(b_step(b, 0, m, tol, transpose, bvec));
-            } else if (b->use_graph && b->st) {
-                if (!b->graphs[j]) {
-                    hipGraph_t g = nullptr;
-                    BH(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
-                    aao_status cs = b_step(b, j, m, tol, transpose);
-                    hipError_t ce = hipStreamEndCapture(b->st, &g);
-                    if (cs < 0) return cs;
-                    BH(ce);
-                    BH(hipGraphInstantiate(&b->graphs[j], g, nullptr, nullptr, 0));
-                    (void)hipGraphDestroy(g);
-                }
-                BH(hipGraphLaunch(b->graphs[j], b->st));
+                j = 1;
             } else {
-                BT(b_step(b, j, m, tol, transpose));
+                const int j1 = b->span <= 0 ? m : std::min(m, j + b->span);
+                if (b->use_graph && b->st) {
+                    if (!b->graphs[j]) {
+                        hipGraph_t g = nullptr;
+                        BH(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+                        aao_status cs = AAO_OK;
+                        for (int q = j; q < j1 && cs == AAO_OK; ++q) cs = b_step(b, q, m, tol, transpose);
+                        hipError_t ce = hipStreamEndCapture(b->st, &g);
+                        if (cs < 0) return cs;
+                        BH(ce);
+                        BH(hipGraphInstantiate(&b->graphs[j], g, nullptr, nullptr, 0));
+                        (void)hipGraphDestroy(g);
+                    }
+                    BH(hipGraphLaunch(b->graphs[j], b->st));
+                } else {
+                    for (int q = j; q < j1; ++q) BT(b_step(b, q, m, tol, transpose));
+                }
+                j = j1;
             }
+            steps_run = j;
             BH(hipMemcpyAsync(&nact, b->iv + 2 * P, sizeof(int), hipMemcpyDeviceToHost, b->st));
             BH(hipStreamSynchronize(b->st));
             if (nact == 0) break;
@@ -389,6 +449,76 @@ static aao_status b_gmres(aao_batch b, const double *bvec, double *x, int m, dou
     return all ? AAO_OK : AAO_NOT_CONVERGED;
 }
 
+// candidates of each batch launch-shape kind
+static std::vector<int> bcfg_candidates(int kind)
+{
+    if (kind == AAO_BCFG_SLAB) return {1024, 2048, 4096, 8192, 16384};
+    if (kind == AAO_BCFG_MATVEC_ROWS) return {2, 4, 8};
+    return {1, 2, 4, 0};
+}
+
+static bool bcfg_ok(int kind, int value)
+{
+    if (kind == AAO_BCFG_SLAB) return value >= 256 && value <= 65536 && (value & (value - 1)) == 0;
+    if (kind == AAO_BCFG_MATVEC_ROWS) return value == 2 || value == 4 || value == 8;
+    if (kind == AAO_BCFG_GRAPH_SPAN) return value >= 0 && value <= kBMaxRestart;
+    return false;
+}
+
+static aao_status bcfg_apply(aao_batch b, int kind, int value)
+{
+    if (kind == AAO_BCFG_GRAPH_SPAN) {
+        b->span = value;   // the graph set is rebuilt by the next solve
+        return AAO_OK;
+    }
+    if (kind == AAO_BCFG_SLAB) {
+        if (b->slab == value) return AAO_OK;
+        b->slab = value;
+    } else {
+        if (b->mrows == value) return AAO_OK;
+        b->mrows = value;
+    }
+    BH(hipStreamSynchronize(b->st));
+    return build_work_tables(b);
+}
+
+// a key of the member sizes for the tuning cache
+static int64_t batch_hash(const aao_batch b)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix((uint64_t)b->scheme);
+    for (const BProb &q : b->hp) {
+        mix((uint64_t)q.n);
+        mix((uint64_t)q.ell);
+    }
+    return (int64_t)(h >> 1);
+}
+
+// time `reps` calls of fn on the batch stream (ms per call)
+template <typename F>
+static aao_status btime(aao_batch b, int reps, F fn, double *ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BH(hipEventCreate(&e0));
+    BH(hipEventCreate(&e1));
+    aao_status s = fn();   // warm-up
+    if (s == AAO_OK && hipEventRecord(e0, b->st) != hipSuccess) s = AAO_ERR_HIP;
+    for (int r = 0; r < reps && s == AAO_OK; ++r) s = fn();
+    float t = 0.0f;
+    if (s == AAO_OK && (hipEventRecord(e1, b->st) != hipSuccess ||
+                        hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+        s = AAO_ERR_HIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / reps;
+    return s;
+}
+
 // ------------------------------------------------------------------- ABI
 
 extern "C" {
@@ -419,9 +549,8 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
     b->prec = prec;
     aao_status s = AAO_OK;
     do {
-        std::vector<int2> ft, rw, ps, mr;
+        std::vector<int2> ft, rw;
         std::vector<int2> rwc[kSolveClasses];   // spectrum rows by class of n
-        std::vector<int4> mt, sl;
         size_t off = 0, soff = 0, coff = 0, boff = 0;
         int max_ell = 0, max_M = 0;
         for (int p = 0; p < count; ++p) {
@@ -450,14 +579,6 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             const int ntile = (q.n + 2 * Wp - 1) / (2 * Wp);
             for (int t = 0; t < ntile; ++t) ft.push_back({p, t});
             for (int j = 0; j <= q.ell / 2; ++j) rwc[solve_class(q.n)].push_back({p, j});
-            const int mfirst = (int)mt.size();
-            for (int by = 0; by < (q.ell + kMatvecRows - 1) / kMatvecRows; ++by)
-                for (int bx = 0; bx < (q.n + 255) / 256; ++bx) mt.push_back({p, bx, by, 0});
-            mr.push_back({mfirst, (int)mt.size()});
-            const int first = (int)sl.size();
-            for (size_t e0 = 0; e0 < Np; e0 += kBatchSlab)
-                sl.push_back({p, (int)e0, (int)std::min<size_t>(kBatchSlab, Np - e0), 0});
-            ps.push_back({first, (int)sl.size()});
         }
         b->Ntot = off;
         b->Stot = soff;
@@ -468,15 +589,10 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             b->row_start[c + 1] = (int)rw.size();
         }
         b->nrows = (int)rw.size();
-        b->nmtiles = (int)mt.size();
-        b->nslabs = (int)sl.size();
         if ((s = upload(b, &b->probs, b->hp)) != AAO_OK) break;
         if ((s = upload(b, &b->ftiles, ft)) != AAO_OK) break;
         if ((s = upload(b, &b->rows, rw)) != AAO_OK) break;
-        if ((s = upload(b, &b->mtiles, mt)) != AAO_OK) break;
-        if ((s = upload(b, &b->slabs, sl)) != AAO_OK) break;
-        if ((s = upload(b, &b->pslabs, ps)) != AAO_OK) break;
-        if ((s = upload(b, &b->mranges, mr)) != AAO_OK) break;
+        if ((s = build_work_tables(b)) != AAO_OK) break;
         if ((s = balloc(b, (void **)&b->chirp, sizeof(double) * 2 * coff)) != AAO_OK) break;
         if ((s = balloc(b, (void **)&b->bhat, sizeof(double) * 2 * boff)) != AAO_OK) break;
         if ((s = balloc(b, (void **)&b->tw, sizeof(double) * 2 * 4096)) != AAO_OK) break;
@@ -485,10 +601,6 @@ aao_status aao_batch_create(int count, const int64_t *n, const int64_t *ell, con
             (s = balloc(b, &b->spec_in, sizeof(float) * 2 * soff)) != AAO_OK)
             break;
         if ((s = balloc(b, (void **)&b->fail, sizeof(int))) != AAO_OK) break;
-        // block partials of the Gram-Schmidt slabs and of the matvec tiles
-        if ((s = balloc(b, (void **)&b->part,
-                        sizeof(double) * b->ldp * std::max(b->nslabs, b->nmtiles))) != AAO_OK)
-            break;
         // small per-problem arrays: 10 arrays of kBSmall doubles + 3 scalars per problem
         const size_t smn = (size_t)count * kBSmall;
         if ((s = balloc(b, (void **)&b->sm, sizeof(double) * (10 * smn + 3 * (size_t)count))) != AAO_OK) break;
@@ -581,6 +693,102 @@ aao_status aao_batch_set_graph(aao_batch b, int enable)
 {
     if (!b) return AAO_ERR_ARG;
     b->use_graph = enable != 0;
+    return AAO_OK;
+}
+
+aao_status aao_batch_get_config(aao_batch b, int kind, int *value)
+{
+    if (!b || !value || kind < 0 || kind >= AAO_NUM_BCFG) return AAO_ERR_ARG;
+    *value = kind == AAO_BCFG_SLAB ? b->slab : kind == AAO_BCFG_MATVEC_ROWS ? b->mrows : b->span;
+    return AAO_OK;
+}
+
+aao_status aao_batch_set_config(aao_batch b, int kind, int value)
+{
+    if (!b || kind < 0 || kind >= AAO_NUM_BCFG) return AAO_ERR_ARG;
+    if (b->broken) return AAO_ERR_HIP;
+    if (!bcfg_ok(kind, value)) {
+        b->err = "launch shape out of range";
+        return AAO_ERR_ARG;
+    }
+    return bcfg_apply(b, kind, value);
+}
+
+aao_status aao_batch_tune(aao_batch b, const double *bvec, int restart, double tol, int maxit,
+                          int reps)
+{
+    if (!b) return AAO_ERR_ARG;
+    if (b->broken) return AAO_ERR_HIP;
+    if (reps < 1 || reps > 100 || (bvec && (restart < 1 || restart > kBMaxRestart))) {
+        b->err = "bad tuning arguments";
+        return AAO_ERR_ARG;
+    }
+    int device = 0;
+    BH(hipGetDevice(&device));
+    const int64_t key = batch_hash(b);
+    // scratch: a 4-vector basis, search directions and w (the workspace), x for the solves
+    try {
+        BT(ensure_ws(b, std::max(4, bvec ? restart : 4)));
+        const size_t N = b->Ntot;
+        BH(launch_fill(b->V, 0.0, N * (b->m_alloc + 1), b->st));
+        BH(launch_fill(b->W, 0.0, N, b->st));
+        for (int kind = 0; kind < AAO_NUM_BCFG; ++kind) {
+            if (kind == AAO_BCFG_GRAPH_SPAN && !bvec) continue;
+            int code = 0;
+            if (tune_cache_get(device, 100 + kind, b->prec, b->count, key, &code) &&
+                bcfg_ok(kind, code)) {
+                BT(bcfg_apply(b, kind, code));
+                continue;
+            }
+            int best = -1;
+            double best_ms = 0.0;
+            double *xs = nullptr;
+            if (kind == AAO_BCFG_GRAPH_SPAN) BT(balloc(b, (void **)&xs, sizeof(double) * N));
+            for (int v : bcfg_candidates(kind)) {
+                aao_status st = bcfg_apply(b, kind, v);
+                double ms = 0.0;
+                const BatchLaunch L = b->launch(false);
+                if (st == AAO_OK && kind == AAO_BCFG_SLAB) {
+                    // the slab passes: an update with four basis vectors and their dots
+                    st = btime(b, reps, [&]() -> aao_status {
+                        BH(batch_cgs(1, L, b->dV, 4, b->W, b->bs.coef, b->bs.sst, nullptr,
+                                     b->part, b->ldp, false, b->st));
+                        BH(batch_reduce(L, b->part, b->ldp, 4, b->bs.dsum, b->bs.sst, false,
+                                        b->st));
+                        return AAO_OK;
+                    }, &ms);
+                } else if (st == AAO_OK && kind == AAO_BCFG_MATVEC_ROWS) {
+                    // a plain matvec and one that forms two Gram-Schmidt dots
+                    st = btime(b, reps, [&]() -> aao_status {
+                        BH(batch_matvec(L, b->V, b->W, nullptr, b->scheme, 0, false, b->st));
+                        BH(batch_matvec(L, b->V + N, b->W, nullptr, b->scheme, 0, false, b->st,
+                                        b->dV, 2, b->part, b->ldp));
+                        return AAO_OK;
+                    }, &ms);
+                } else if (st == AAO_OK) {
+                    st = btime(b, reps, [&]() -> aao_status {
+                        const aao_status r = b_gmres(b, bvec, xs, restart, tol, maxit, nullptr,
+                                                     0, true);
+                        return r < 0 ? r : AAO_OK;
+                    }, &ms);
+                }
+                if (st != AAO_OK) {
+                    (void)hipFree(xs);
+                    return st;
+                }
+                if (best < 0 || ms < best_ms) {
+                    best = v;
+                    best_ms = ms;
+                }
+            }
+            (void)hipFree(xs);
+            BT(bcfg_apply(b, kind, best));
+            tune_cache_put(device, 100 + kind, b->prec, b->count, key, best, 1e3 * best_ms);
+        }
+    } catch (...) {
+        return AAO_ERR_ALLOC;
+    }
+    BH(hipStreamSynchronize(b->st));
     return AAO_OK;
 }
 

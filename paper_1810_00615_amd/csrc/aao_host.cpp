@@ -480,6 +480,25 @@ bool config_valid(aao_ctx ctx, int kind, int code)
 
 }  // namespace
 
+namespace aao {
+bool tune_cache_get(int device, int kind, int prec, int64_t n, int64_t ell, int *code)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_read_file(device);
+    auto it = g_tune.find(TuneKey(device, kind, prec, n, ell));
+    if (it == g_tune.end()) return false;
+    *code = it->second;
+    return true;
+}
+
+void tune_cache_put(int device, int kind, int prec, int64_t n, int64_t ell, int code, double us)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[TuneKey(device, kind, prec, n, ell)] = code;
+    tune_append_file(kind, prec, n, ell, code, us);
+}
+}  // namespace aao
+
 static aao_status launch_kind(aao_ctx ctx, int kind, int code, double *buf)
 {
     if (kind == AAO_CFG_MATVEC) {

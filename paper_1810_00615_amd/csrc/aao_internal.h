@@ -71,6 +71,12 @@ __host__ __device__ inline bool scheme_block(const Scheme &sc, int row, int m, d
     return cm != 0.0 || cb != 0.0;
 }
 
+// Tuned launch shapes, cached per process and in the aao_set_tune_cache file, keyed by
+// (device, kind, precision, n, ell); a batch stores its shapes under kinds >= 100 with
+// n = the member count and ell = a hash of the member sizes.
+bool tune_cache_get(int device, int kind, int prec, int64_t n, int64_t ell, int *code);
+void tune_cache_put(int device, int kind, int prec, int64_t n, int64_t ell, int code, double us);
+
 // Coefficients of a scheme constant of aao.h (AAO_HEAT_IE, ...) for step tau; false
 // for an unknown scheme.
 bool make_scheme(int scheme, double tau, Scheme *out);

@@ -37,6 +37,7 @@ struct BatchLaunch {
     const int2 *rows;    int nrows;     // spectrum rows (problem, frequency), by class of n
     int row_start[5];                   // rows of class c: [row_start[c], row_start[c + 1])
     const int4 *mtiles;  int nmtiles;   // matvec tiles (problem, column block, row block, -)
+    int mrows;                          // time levels per matvec tile (2, 4 or 8)
     const int4 *slabs;   int nslabs;    // element slabs (problem, first, count, -)
     const int2 *pslabs;                 // slab range [x, y) of every problem
     const int2 *mranges;                // matvec tile range [x, y) of every problem
@@ -44,8 +45,11 @@ struct BatchLaunch {
     const double *chirp, *bhat, *tw;    // Bluestein tables, 4096-point twiddles
 };
 
-constexpr int kBatchSlab = 4096;        // elements per Gram-Schmidt / update slab
-constexpr int kMatvecRows = 4;          // time levels per batched matvec tile
+// launch shapes of a batch (aao_batch_tune / aao_batch_set_config): elements per
+// Gram-Schmidt / update slab, time levels per matvec tile, Arnoldi steps per graph
+constexpr int kBatchSlabDefault = 4096;
+constexpr int kMatvecRowsDefault = 4;
+constexpr int kGraphSpanDefault = 1;
 constexpr int kBSmall = 72;             // doubles per problem in the small per-problem arrays
 // shifted solves: class c = 0..3 of a problem holds n <= 8 * (64 << c) (workgroups of
 // 64 << c threads, 8 unknowns per thread)

@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <cstdlib>
 
+#include <type_traits>
+
 #include "batch.h"
 #include "fft_core.h"
 #include "lanes.h"
@@ -412,7 +414,7 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
 }
 
 // ------------------------------------------------------------------ matvec
-// y = A x (or bsub - A x) per problem, tiles of 256 columns x kMatvecRows time levels.  A
+// y = A x (or bsub - A x) per problem, tiles of 256 columns x RB time levels.  A
 // thread loads its own column of each input row once; the i -+ 1 neighbours come
 // from the adjacent lanes (DPP wave shift), and lanes 0 and 63 load the one
 // neighbour outside their wave.  Threads past n stay for the lane moves (with 0).
@@ -420,14 +422,13 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
 // DOTS > 0: the tile also leaves the partials of V_q . y, q < DOTS (the first
 // Gram-Schmidt pass of an early Arnoldi step), at part[tile * ldp + q]; DOTS = -1:
 // the partial of y . y (the norm of a residual), from registers.
-template <int DOTS>
+template <int DOTS, int RB>
 __global__ void __launch_bounds__(256)
 k_batch_matvec(const BProb *__restrict__ probs, const int4 *__restrict__ tiles, int ntiles,
                const unsigned char *__restrict__ active, const double *__restrict__ x,
                double *__restrict__ y, const double *__restrict__ bsub, int scheme, int transpose,
                const double *const *__restrict__ Vd, double *__restrict__ part, int ldp)
 {
-    constexpr int RB = kMatvecRows;
     constexpr int ND = DOTS < 0 ? 1 : DOTS;        // partials per tile
     __shared__ double red[(ND > 0 ? ND : 1) * 4];
     const int g = blockIdx.x;
@@ -1035,27 +1036,42 @@ hipError_t batch_matvec(const BatchLaunch &L, const double *x, double *y, const 
                         const double *const *Vd, int nd, double *part, int ldp)
 {
     const unsigned char *act = masked ? L.active : nullptr;
-    if (nd == 1)
-        k_batch_matvec<1><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
-                                                     scheme, transpose, Vd, part, ldp);
-    else if (nd == 2)
-        k_batch_matvec<2><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
-                                                     scheme, transpose, Vd, part, ldp);
-    else if (nd == 3)
-        k_batch_matvec<3><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
-                                                     scheme, transpose, Vd, part, ldp);
-    else if (nd == 4)
-        k_batch_matvec<4><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
-                                                     scheme, transpose, Vd, part, ldp);
-    else if (nd == -1)
-        k_batch_matvec<-1><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y,
-                                                      bsub, scheme, transpose, nullptr, part, ldp);
-    else if (nd == 0)
-        k_batch_matvec<0><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x, y, bsub,
-                                                     scheme, transpose, nullptr, nullptr, 0);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    auto go = [&](auto rb) -> hipError_t {
+        constexpr int RB = decltype(rb)::value;
+        if (nd == 1)
+            k_batch_matvec<1, RB><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x,
+                                                             y, bsub, scheme, transpose, Vd, part,
+                                                             ldp);
+        else if (nd == 2)
+            k_batch_matvec<2, RB><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x,
+                                                             y, bsub, scheme, transpose, Vd, part,
+                                                             ldp);
+        else if (nd == 3)
+            k_batch_matvec<3, RB><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x,
+                                                             y, bsub, scheme, transpose, Vd, part,
+                                                             ldp);
+        else if (nd == 4)
+            k_batch_matvec<4, RB><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x,
+                                                             y, bsub, scheme, transpose, Vd, part,
+                                                             ldp);
+        else if (nd == -1)
+            k_batch_matvec<-1, RB><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x,
+                                                              y, bsub, scheme, transpose, nullptr,
+                                                              part, ldp);
+        else if (nd == 0)
+            k_batch_matvec<0, RB><<<L.nmtiles, 256, 0, st>>>(L.probs, L.mtiles, L.nmtiles, act, x,
+                                                             y, bsub, scheme, transpose, nullptr,
+                                                             nullptr, 0);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    };
+    switch (L.mrows) {
+    case 2: return go(std::integral_constant<int, 2>{});
+    case 4: return go(std::integral_constant<int, 4>{});
+    case 8: return go(std::integral_constant<int, 8>{});
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <int MODE>

@@ -304,3 +304,82 @@ def test_batch_workload_64(dev, orc):
         assert infos[i]["converged"] and res <= 1e-8, (i, w.n, w.ell, res)
     print(f"batch 64: max true residual {worst:.2e}, iterations "
           f"{sorted(set(i['iters'] for i in infos))}")
+
+
+def test_batch_graph_spans_match_eager(dev, orc):
+    """Arnoldi steps captured per step, per three steps and per whole restart cycle (one
+    graph launch per cycle), and launched eagerly: bitwise the same solutions and the
+    same iteration counts (steps after convergence run fully masked), with restarts."""
+    J = 20
+    modes = np.arange(1, J + 1)
+    amps = np.random.default_rng(17).normal(0, 0.1, (len(SMALL), J))
+    res = {}
+    B, ns, ells, kappas = make(dev, "fp64")
+    b = B.rhs(B.project_sine(modes, amps))
+    for name, graph, span in (("eager", False, 1), ("span1", True, 1), ("span3", True, 3),
+                              ("cycle", True, 0)):
+        B.set_graph(graph)
+        B.set_config("graph_span", span)
+        x, infos, st = B.solve(b, restart=5, tol=1e-9, maxit=300)
+        assert st == 0, name
+        # members only: with the zero guess the alignment padding is never written
+        res[name] = ([v.cpu().numpy() for v in B.views(x)], [i["iters"] for i in infos])
+    print("iterations:", res["eager"][1])
+    for name in ("span1", "span3", "cycle"):
+        assert res[name][1] == res["eager"][1], name
+        for a, e in zip(res[name][0], res["eager"][0]):
+            assert np.array_equal(a, e), name
+
+
+@pytest.mark.parametrize("slab,rows", [(1024, 2), (16384, 8), (256, 4)])
+def test_batch_shapes_parity(dev, orc, slab, rows):
+    """Other slab sizes and matvec tile heights: the matvec (both orientations) against the
+    oracle and a solve to the 1e-8 true residual."""
+    B, ns, ells, kappas = make(dev, "fp64")
+    B.set_config("slab", slab)
+    B.set_config("matvec_rows", rows)
+    assert B.configs()["slab"] == slab and B.configs()["matvec_rows"] == rows
+    xs = [np.random.default_rng([i, 5]).standard_normal((l, n)) for i, (n, l) in enumerate(zip(ns, ells))]
+    for tr in (False, True):
+        y = B.A(B.pack(xs), transpose=tr)
+        for i, (yv, xv) in enumerate(zip(B.views(y), xs)):
+            ref = orc.apply_A(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i], xv, transpose=tr)
+            assert np.max(np.abs(yv.cpu().numpy() - ref)) <= 1e-13 * np.max(np.abs(ref))
+    b = B.pack(xs)
+    x, infos, st = B.solve(b, restart=30, tol=1e-8, maxit=300)
+    assert st == 0
+    for i, (xv, bv) in enumerate(zip(B.views(x), xs)):
+        r = bv - orc.apply_A(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i], xv.cpu().numpy())
+        assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(bv)
+
+
+def test_batch_tune_picks_admissible_shapes(dev, orc, tmp_path):
+    """The batch tuner times the slab sizes, matvec tile heights and (given a right-hand
+    side) graph spans on the batch's own sizes, keeps admissible ones, writes them to the
+    tuning file, and a second batch of the same sizes takes them from the cache."""
+    from paper_1810_00615_amd.api import set_tune_cache
+    cache = tmp_path / "btune.txt"
+    set_tune_cache(str(cache))
+    try:
+        J = 20
+        modes = np.arange(1, J + 1)
+        amps = np.random.default_rng(18).normal(0, 0.1, (len(SMALL), J))
+        B, ns, ells, kappas = make(dev, "mixed_in")
+        b = B.rhs(B.project_sine(modes, amps))
+        cfg = B.tune(b, restart=30, tol=1e-8, maxit=300, reps=2)
+        print("tuned batch shapes:", cfg)
+        assert cfg["slab"] in (1024, 2048, 4096, 8192, 16384)
+        assert cfg["matvec_rows"] in (2, 4, 8)
+        assert cfg["graph_span"] in (1, 2, 4, 0)
+        assert len(cache.read_text().splitlines()) == 3
+        B2, *_ = make(dev, "mixed_in")
+        assert B2.tune(b, reps=2) == cfg
+        assert len(cache.read_text().splitlines()) == 3
+        x, infos, st = B2.solve(b, restart=30, tol=1e-8, maxit=300)
+        assert st == 0
+        for i, (xv, bv) in enumerate(zip(B2.views(x), B2.views(b))):
+            bb = bv.cpu().numpy()
+            r = bb - orc.apply_A(HEAT, ns[i], ells[i], 1.0 / ells[i], kappas[i], xv.cpu().numpy())
+            assert np.linalg.norm(r) <= 1e-8 * np.linalg.norm(bb)
+    finally:
+        set_tune_cache(None)
