@@ -46,6 +46,7 @@ CD = 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "aao_oracle.c")
+_SRC2 = os.path.join(_HERE, "aao_oracle2d.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -60,7 +61,7 @@ def build(force: bool = True) -> str:
         tmp = _LIB + ".tmp"
         subprocess.check_call(
             ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-fPIC", "-shared",
-             _SRC, "-o", tmp, "-lm"])
+             _SRC, _SRC2, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -68,15 +69,18 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                   os.path.getmtime(_SRC2)):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         for name in ("or_scheme_coeffs", "or_toeplitz", "or_block", "or_load_sine",
                      "or_project_sine", "or_build_rhs",
                      "or_solve_seq", "or_adjoint_seq", "or_apply_A", "or_apply_C", "or_apply_E",
-                     "or_shifted_solve_all", "or_pinv_direct", "or_grad", "or_mk_solve"):
+                     "or_shifted_solve_all", "or_pinv_direct", "or_grad", "or_mk_solve",
+                     "or2_mk_solve", "or2_apply_A", "or2_apply_C", "or2_solve_seq",
+                     "or2_build_rhs", "or2_pinv_direct"):
             getattr(lib, name).restype = ctypes.c_int
-        for name in ("or_dft", "or_mass_apply", "or_stiff_apply", "or_symbol"):
+        for name in ("or_dft", "or_mass_apply", "or_stiff_apply", "or_symbol", "or2_mk_apply"):
             getattr(lib, name).restype = None
         _lib = lib
     return _lib
@@ -428,3 +432,69 @@ def grad(scheme, n, ell, tau, kappa, u0, U, L, v0=None, tau_k=None):
                          _p(v0c) if v0c is not None else None, _p(U), _p(L), _p(gu), _p(gv),
                          ctypes.byref(gk)), "grad")
     return gu, gv, gk.value
+
+
+# ------------------------------------------------------- two space dimensions
+# Q1 elements on the uniform nx x ny interior grid of the unit square: M2 = My (x) Mx,
+# K2 = Ky (x) Mx + My (x) Kx; a time level is an (ny, nx) array, x fastest
+# (aao_oracle2d.c).
+
+def mk2(nx, ny, cm, ck, x):
+    """(cm M2 + ck K2) x for one time level."""
+    x = _c(x).reshape(ny, nx)
+    y = np.empty((ny, nx))
+    _load().or2_mk_apply(nx, ny, ctypes.c_double(cm), ctypes.c_double(ck), _p(x), _p(y))
+    return y
+
+
+def mk2_solve(nx, ny, cm, ck, r):
+    r = _c(r).reshape(ny, nx)
+    u = np.empty((ny, nx))
+    _chk(_load().or2_mk_solve(nx, ny, ctypes.c_double(cm), ctypes.c_double(ck), _p(r), _p(u)),
+         "mk2_solve")
+    return u
+
+
+def apply_A2(scheme, nx, ny, ell, tau, kappa, x, transpose=False):
+    x = _c(x).reshape(ell, ny * nx)
+    y = np.empty((ell, ny * nx))
+    _chk(_load().or2_apply_A(scheme, nx, ny, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                             _p(x), _p(y), int(transpose)), "apply_A2")
+    return y
+
+
+def apply_C2(scheme, nx, ny, ell, tau, kappa, x, transpose=False):
+    x = _c(x).reshape(ell, ny * nx)
+    y = np.empty((ell, ny * nx))
+    _chk(_load().or2_apply_C(scheme, nx, ny, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                             _p(x), _p(y), int(transpose)), "apply_C2")
+    return y
+
+
+def solve_seq2(scheme, nx, ny, ell, tau, kappa, b, transpose=False):
+    """Exact U of the 2D monolithic system (A^T U = b with transpose) by block
+    substitution in time."""
+    b = _c(b).reshape(ell, ny * nx)
+    U = np.empty((ell, ny * nx))
+    _chk(_load().or2_solve_seq(scheme, nx, ny, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                               _p(b), _p(U), int(transpose)), "solve_seq2")
+    return U
+
+
+def build_rhs2(scheme, nx, ny, ell, tau, kappa, u0, v0=None):
+    u0 = _c(u0).ravel()
+    v0p = _p(_c(v0).ravel()) if v0 is not None else None
+    b = np.empty((ell, ny * nx))
+    _chk(_load().or2_build_rhs(scheme, nx, ny, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                               _p(u0), v0p, _p(b)), "build_rhs2")
+    return b
+
+
+def pinv2_direct(scheme, nx, ny, ell, tau, kappa, r, transpose=False):
+    """C^{-1} r in 2D with the direct DFT and banded 2D solves; (z, max|Im|/max|Re|)."""
+    r = _c(r).reshape(ell, ny * nx)
+    z = np.empty((ell, ny * nx))
+    ratio = ctypes.c_double(0.0)
+    _chk(_load().or2_pinv_direct(scheme, nx, ny, ell, ctypes.c_double(tau), ctypes.c_double(kappa),
+                                 int(transpose), _p(r), _p(z), ctypes.byref(ratio)), "pinv2_direct")
+    return z, ratio.value
