@@ -101,6 +101,27 @@ typedef struct {
  * Allocates the device tables on the current HIP device.  Sec. 2. */
 aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *out);
 
+/* Create a context on the unit square [0,1]^2: bilinear (Q1) elements on a uniform
+ * grid of nx x ny interior nodes (hx = 1/(nx+1), hy = 1/(ny+1)), zero Dirichlet data,
+ *     M2 = My (x) Mx,   K2 = Ky (x) Mx + My (x) Kx
+ * (Mx, Kx, My, Ky the 1D matrices above along each axis), and the time structure of
+ * `scheme` unchanged: blocks a_m M2 + b_m kappa K2.  The paper works in one space
+ * dimension; Sec. 3 and Sec. 5 note that beyond it the blocks of the middle factor of
+ * eq. precon2para stop being tridiagonal.  Here they are reduced to tridiagonal ones
+ * by the orthonormal sine transform along y, which diagonalises My and Ky: per
+ * frequency j and sine mode q the x-tridiagonal (alpha_j my_q + beta_j kappa ky_q) Mx
+ * + beta_j kappa my_q Kx, solved like the 1D blocks.
+ * A time level is ny x nx doubles, x fastest (node (ix, iy) at iy nx + ix); a
+ * monolithic vector is ell levels (ell nx ny doubles), per-node vectors nx ny
+ * doubles.  Requires ny + 1 a power of two (ny <= 2047), 1 <= nx <= 16384,
+ * 1 <= ell <= 65535; AAO_ERR_UNSUPPORTED otherwise.
+ * Supported on such a context: aao_set_stream, aao_set_kappa, aao_set_precision,
+ * aao_build_rhs (AAO_HEAT_IE and AAO_WAVE_BD2), aao_apply_A, aao_apply_Pinv (order
+ * 0), aao_gmres, aao_gmres_ex, aao_adjoint_solve, aao_set_timing*, aao_get_timing*.
+ * Every other entry point returns AAO_ERR_UNSUPPORTED. */
+aao_status aao_create_2d(int64_t nx, int64_t ny, int64_t ell, double tau, int scheme,
+                         aao_ctx *out);
+
 /* Free every device buffer of the context.  NULL is accepted. */
 aao_status aao_destroy(aao_ctx ctx);
 
@@ -273,7 +294,8 @@ enum {
     AAO_K_CGS_UPDATE_NORM = 6,  /* Gram-Schmidt: update + norm                    */
     AAO_K_AXPY = 7,             /* solution update x += Z y                       */
     AAO_K_ARNOLDI_UPDATE = 8,   /* Arnoldi update, delayed re-orthogonalisation   */
-    AAO_NUM_KERNELS = 9
+    AAO_K_SINE_Y = 9,           /* sine transform along y (unit-square contexts)  */
+    AAO_NUM_KERNELS = 10
 };
 aao_status aao_set_timing(aao_ctx ctx, int enable);
 aao_status aao_get_timing(aao_ctx ctx, int kernel, double *total_ms, int64_t *count);

@@ -27,6 +27,8 @@ class Info(ctypes.Structure):
 SIGNATURES = {
     "aao_create": [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                    ctypes.POINTER(ctypes.c_void_p)],
+    "aao_create_2d": [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_double,
+                      ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
     "aao_destroy": [ctypes.c_void_p],
     "aao_set_stream": [ctypes.c_void_p, ctypes.c_void_p],
     "aao_set_kappa": [ctypes.c_void_p, ctypes.c_double],
@@ -127,4 +129,4 @@ GMRES_ZERO_GUESS, GMRES_TRANSPOSE, GMRES_CGS2_CLASSIC, GMRES_EARLY_CHECK = 1, 2,
 CONFIG_KINDS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec"]
 BATCH_CONFIG_KINDS = ["slab", "matvec_rows", "graph_span"]
 KERNELS = ["fft_fwd", "shifted_solve", "fft_inv", "matvec", "cgs_dot", "cgs_update_dot",
-           "cgs_update_norm", "axpy", "arnoldi_update"]
+           "cgs_update_norm", "axpy", "arnoldi_update", "sine_y"]

@@ -68,9 +68,8 @@ class Problem:
         self._L = lib()
         self._ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            st = self._L.aao_create(self.n, self.ell, self.tau, self.scheme,
-                                    ctypes.byref(self._ctx))
-        check(st, "aao_create")
+            where, st = self._create()
+        check(st, where)
         self.kappa = None
         self.set_kappa(kappa)
         self.precision = None
@@ -80,6 +79,10 @@ class Problem:
         self.steps = None
         if steps is not None:
             self.set_steps(steps)
+
+    def _create(self):
+        return "aao_create", self._L.aao_create(self.n, self.ell, self.tau, self.scheme,
+                                                ctypes.byref(self._ctx))
 
     # -------------------------------------------------------------- setup
     def _c(self, st, where):
@@ -289,7 +292,33 @@ class Problem:
         return gu, gv, gk.value
 
 
-__all__ = ["Problem", "AAOError", "HEAT", "BD2", "set_tune_cache"]
+class Problem2D(Problem):
+    """The all-at-once system on the unit square (aao_create_2d): bilinear elements on
+    a uniform nx x ny interior grid, M2 = My (x) Mx, K2 = Ky (x) Mx + My (x) Kx, and the
+    time structure of `scheme`.  Vectors of the monolithic system are (ell, ny, nx)
+    tensors (x fastest); u0 and v0 are (ny, nx).  ny + 1 must be a power of two.
+    Variable steps, Neumann terms, gradients and launch-shape tuning are not
+    available here."""
+
+    def __init__(self, nx: int, ny: int, ell: int, tau: Optional[float] = None,
+                 scheme="heat", kappa: float = 1.0, precision: str = "fp64", device="cuda"):
+        self.nx = int(nx)
+        self.ny = int(ny)
+        super().__init__(self.nx * self.ny, ell, tau, scheme, kappa=kappa,
+                         precision=precision, device=device)
+
+    def _create(self):
+        return "aao_create_2d", self._L.aao_create_2d(self.nx, self.ny, self.ell, self.tau,
+                                                      self.scheme, ctypes.byref(self._ctx))
+
+    def empty(self):
+        return torch.empty((self.ell, self.ny, self.nx), dtype=torch.float64, device=self.device)
+
+    def zeros(self):
+        return torch.zeros((self.ell, self.ny, self.nx), dtype=torch.float64, device=self.device)
+
+
+__all__ = ["Problem", "Problem2D", "AAOError", "HEAT", "BD2", "set_tune_cache"]
 
 
 class Batch:

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaao.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["k_fft.hip", "k_solve.hip", "k_vec.hip", "k_batch.hip", "aao_host.cpp",
+SOURCES = ["k_fft.hip", "k_solve.hip", "k_vec.hip", "k_batch.hip", "k_space2d.hip", "aao_host.cpp",
            "aao_batch.cpp", "aao_noalloc.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -43,7 +43,9 @@ struct Status {
 }  // namespace
 
 struct aao_ctx_s {
-    int64_t n = 0, ell = 0;
+    int64_t n = 0, ell = 0;      // n: unknowns per time level (nx ny on the unit square)
+    int nx = 0, ny = 0;          // unit square (aao_create_2d); ny = 0 in one dimension
+    double *dsty = nullptr;      // sine transform of the preconditioner input (unit square)
     double tau = 0.0;
     int scheme = 0;
     double kappa = 1.0;
@@ -178,6 +180,12 @@ static aao_status arg_err(aao_ctx ctx, const char *msg)
     return AAO_ERR_ARG;
 }
 
+static aao_status unsupported_2d(aao_ctx ctx)
+{
+    ctx->err = "not available on a unit-square context";
+    return AAO_ERR_UNSUPPORTED;
+}
+
 static bool overlap(const void *a, const void *b, size_t bytes)
 {
     const char *pa = (const char *)a, *pb = (const char *)b;
@@ -306,6 +314,12 @@ static void *in_spec(aao_ctx ctx)
 static aao_status apply_A_impl(aao_ctx ctx, const double *x, double *y, const double *bsub,
                                int transpose)
 {
+    if (ctx->ny > 0) {
+        AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (bsub ? 3 : 2),
+                     launch_matvec2d(x, y, bsub, ctx->nx, ctx->ny, (int)ctx->ell, ctx->sc,
+                                     ctx->kappa, transpose, ctx->st));
+        return AAO_OK;
+    }
     AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (bsub ? 3 : 2),
                  launch_matvec(x, y, bsub, (int)ctx->n, (int)ctx->ell, ctx->sc,
                                            ctx->kappa, ctx->tauk, transpose, ctx->st,
@@ -326,12 +340,20 @@ static BatchLaunch bl_launch(aao_ctx ctx)
     return L;
 }
 
+// Rows of the shifted solves: n unknowns, one row per frequency in one dimension; on
+// the unit square nx unknowns and ny rows (sine modes in y) per frequency, row q of
+// frequency j at spectrum offset j lds + q nx.
+static int solve_n(aao_ctx ctx) { return ctx->ny > 0 ? ctx->nx : (int)ctx->n; }
+static int solve_rpf(aao_ctx ctx) { return ctx->ny > 0 ? ctx->ny : 1; }
+static int solve_sub(aao_ctx ctx) { return ctx->ny > 0 ? ctx->nx : 0; }
+
 // rebuild the per-row symbol table after a change of kappa; the stream is
 // synchronised so that later work on any stream sees the table
 static aao_status refresh_symbols(aao_ctx ctx)
 {
     if (ctx->sym_kappa == ctx->kappa) return AAO_OK;
-    AAO_HIP(launch_symbols(ctx->sym, (int)ctx->n, (int)ctx->ell, ctx->sc, ctx->kappa, ctx->st));
+    AAO_HIP(launch_symbols(ctx->sym, solve_n(ctx), (int)ctx->ell, ctx->sc, ctx->kappa, ctx->st,
+                           ctx->ny));
     AAO_HIP(hipStreamSynchronize(ctx->st));
     ctx->sym_kappa = ctx->kappa;
     return AAO_OK;
@@ -341,7 +363,7 @@ static aao_status refresh_symbols(aao_ctx ctx)
 // change of kappa, chunk width or arithmetic (synchronised like the symbols)
 static aao_status refresh_tables(aao_ctx ctx, int cfg, bool sync)
 {
-    const int n = (int)ctx->n;
+    const int n = solve_n(ctx);
     cfg = solve_effective_config(cfg, n);
     int cw = 0, nt = 0, stg = 0;
     solve_config_shape(cfg, &cw, &nt, &stg);
@@ -349,7 +371,8 @@ static aao_status refresh_tables(aao_ctx ctx, int cfg, bool sync)
     if (ctx->ptab_kappa == ctx->kappa && ctx->ptab_cw == cw && ctx->ptab_single == single)
         return AAO_OK;
     AAO_TRY(refresh_symbols(ctx));
-    AAO_HIP(launch_solve_tables(ctx->sym, n, (int)ctx->ell, cfg, single != 0, ctx->ptab, ctx->st));
+    AAO_HIP(launch_solve_tables(ctx->sym, n, (int)ctx->ell, cfg, single != 0, ctx->ptab, ctx->st,
+                                solve_rpf(ctx)));
     if (sync) AAO_HIP(hipStreamSynchronize(ctx->st));
     ctx->ptab_kappa = ctx->kappa;
     ctx->ptab_cw = cw;
@@ -370,10 +393,20 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     const bool sin = in_single(ctx->prec), sout = out_single(ctx->prec);
     const bool sar = arith_single(ctx->prec);
     const int n = (int)ctx->n, ell = (int)ctx->ell;
+    const int sn = solve_n(ctx), rpf = solve_rpf(ctx), sub = solve_sub(ctx);
     void *ispec = in_spec(ctx);
     AAO_TRY(refresh_symbols(ctx));
     AAO_TRY(refresh_tables(ctx, ctx->cf(AAO_CFG_SHIFTED_SOLVE), true));
     const double solve_bytes = spec_in_bytes(ctx) + spec_out_bytes(ctx);
+    const bool sq = ctx->ny > 0;
+    if (sq) {
+        // unit square: C^{-1} = S_y F^{-1} [solves] F S_y (S_y the sine transform in y,
+        // which commutes with the time transform F)
+        if (zprev) return AAO_ERR_UNSUPPORTED;
+        AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
+                     launch_dst_y(r, ctx->dsty, ctx->nx, ctx->ny, ell, ctx->st));
+        r = ctx->dsty;
+    }
     if (ctx->bluestein) {
         const BatchLaunch L = bl_launch(ctx);
         if (zprev) {
@@ -387,11 +420,14 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
         AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) + spec_in_bytes(ctx),
                      batch_fft_fwd(L, r, in_scale, 0, ispec, sin, ctx->st));
         AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, solve_bytes,
-                   launch_shifted_solve(ispec, ctx->spec, ctx->lds, sin, sout, sar, n, ell, ctx->sym,
+                   launch_shifted_solve(ispec, ctx->spec, ctx->lds, sin, sout, sar, sn, ell, ctx->sym,
                                         ctx->ptab, transpose, ctx->fail, ctx->st,
-                                        ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
+                                        ctx->cf(AAO_CFG_SHIFTED_SOLVE), rpf, sub));
         AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_out_bytes(ctx),
                      batch_fft_inv(L, ctx->spec, z, sout, ctx->st));
+        if (sq)
+            AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
+                         launch_dst_y(z, z, ctx->nx, ctx->ny, ell, ctx->st));
         return AAO_OK;
     }
     AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) * (zprev ? 2 : 1) + spec_in_bytes(ctx),
@@ -401,12 +437,15 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     if (first_norm)
         AAO_TRY(launch_small(ctx, 4, 1, fft_fwd_blocks(ell, n, sin, ctx->cf(AAO_CFG_FFT_FWD))));
     AAO_LAUNCH_B(AAO_K_SHIFTED_SOLVE, solve_bytes,
-               launch_shifted_solve(ispec, ctx->spec, ctx->lds, sin, sout, sar, n, ell, ctx->sym,
+               launch_shifted_solve(ispec, ctx->spec, ctx->lds, sin, sout, sar, sn, ell, ctx->sym,
                                     ctx->ptab, transpose, ctx->fail, ctx->st,
-                                    ctx->cf(AAO_CFG_SHIFTED_SOLVE)));
+                                    ctx->cf(AAO_CFG_SHIFTED_SOLVE), rpf, sub));
     AAO_LAUNCH_B(AAO_K_FFT_INV, vec_bytes(ctx) + spec_out_bytes(ctx),
                launch_fft_inv(ctx->spec, ctx->lds, sout, z, n, ell, ctx->tw, ctx->st,
                               ctx->cf(AAO_CFG_FFT_INV), first_norm ? in_scale : nullptr));
+    if (sq)
+        AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
+                     launch_dst_y(z, z, ctx->nx, ctx->ny, ell, ctx->st));
     return AAO_OK;
 }
 
@@ -646,7 +685,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     const int mcfg = ctx->cf(AAO_CFG_MATVEC);
     // the Toeplitz matvec also forms the first Gram-Schmidt dots and residual norms;
     // the start-up-row and two-sided schemes take a plain matvec and separate passes
-    const bool fused = matvec_blocks(n, ell, mcfg) <= ldp && !scheme_generic(ctx->sc);
+    const bool fused = matvec_blocks(n, ell, mcfg) <= ldp && !scheme_generic(ctx->sc) &&
+                       ctx->ny == 0;
     auto residual = [&](bool store) -> aao_status {
         // V_0 = b - A x, vs_0 = 1/||V_0|| (the norm formed by the same launch); with
         // store false only the norm (the check after a cycle, before a restart is
@@ -672,7 +712,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     // (pinv_once, first_norm) and read with the first Hessenberg column; otherwise
     // one synchronisation here.
     aao_info inf{};
-    const bool defer_b = zero_guess && !ctx->bluestein && fft_supported_fast(ell) && maxit > 0;
+    const bool defer_b = zero_guess && !ctx->bluestein && fft_supported_fast(ell) && maxit > 0 &&
+                         fft_fwd_blocks(ell, n, in_single(ctx->prec), ctx->cf(AAO_CFG_FFT_FWD)) <= ldp;
     double bnorm = 0.0, beta = 0.0;
     if (zero_guess) Vl.p[0] = b;
     auto check_b = [&]() -> aao_status {
@@ -936,19 +977,12 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     return inf.converged ? AAO_OK : AAO_NOT_CONVERGED;
 }
 
-// ------------------------------------------------------------------- ABI
-
-extern "C" {
-
-aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *out)
+// A context with n unknowns a level; on the unit square (ny > 0) n = nx ny and the
+// shifted solves have ny rows of nx unknowns per frequency.  Arguments are checked by
+// the callers.
+static aao_status create_impl(int64_t n, int64_t ell, double tau, int scheme, int nx, int ny,
+                              aao_ctx *out)
 {
-    if (!out) return AAO_ERR_ARG;
-    *out = nullptr;
-    if (n < 1 || ell < 1 || !(tau > 0.0) || !std::isfinite(tau)) return AAO_ERR_ARG;
-    if (scheme != AAO_HEAT_IE && scheme != AAO_WAVE_BD2 && scheme != AAO_WAVE_BD4 &&
-        scheme != AAO_WAVE_CD)
-        return AAO_ERR_ARG;
-    if (n > 16384 || ell > 65535 || (double)n * (double)ell > 4.0e9) return AAO_ERR_UNSUPPORTED;
     aao_ctx ctx = nullptr;
     try {
         ctx = new aao_ctx_s();
@@ -956,6 +990,8 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
         return AAO_ERR_ALLOC;
     }
     ctx->n = n;
+    ctx->nx = nx;
+    ctx->ny = ny;
     ctx->ell = ell;
     ctx->tau = tau;
     ctx->scheme = scheme;
@@ -971,8 +1007,11 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
         if ((s = dev_alloc(ctx, (void **)&ctx->tw, sizeof(double) * 2 * ell)) != AAO_OK) break;
         if ((s = dev_alloc(ctx, &ctx->spec, H * ctx->lds * 2 * sizeof(double))) != AAO_OK) break;
         if ((s = dev_alloc(ctx, (void **)&ctx->fail, sizeof(int))) != AAO_OK) break;
-        if ((s = dev_alloc(ctx, (void **)&ctx->sym, sizeof(double) * 8 * H)) != AAO_OK) break;
-        if ((s = dev_alloc(ctx, &ctx->ptab, solve_table_bytes((int)ell))) != AAO_OK) break;
+        const int rpf = solve_rpf(ctx);
+        if ((s = dev_alloc(ctx, (void **)&ctx->sym, sizeof(double) * 8 * H * rpf)) != AAO_OK) break;
+        if ((s = dev_alloc(ctx, &ctx->ptab, solve_table_bytes((int)ell, rpf))) != AAO_OK) break;
+        if (ny > 0 && (s = dev_alloc(ctx, (void **)&ctx->dsty, sizeof(double) * ctx->N())) != AAO_OK)
+            break;
         ctx->nblk = dot_blocks(ctx->N());
         ctx->ldp = kPartStride;
         if ((s = dev_alloc(ctx, (void **)&ctx->part,
@@ -1036,6 +1075,40 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
     return AAO_OK;
 }
 
+static bool scheme_known(int scheme)
+{
+    return scheme == AAO_HEAT_IE || scheme == AAO_WAVE_BD2 || scheme == AAO_WAVE_BD4 ||
+           scheme == AAO_WAVE_CD;
+}
+
+// ------------------------------------------------------------------- ABI
+
+extern "C" {
+
+aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *out)
+{
+    if (!out) return AAO_ERR_ARG;
+    *out = nullptr;
+    if (n < 1 || ell < 1 || !(tau > 0.0) || !std::isfinite(tau) || !scheme_known(scheme))
+        return AAO_ERR_ARG;
+    if (n > 16384 || ell > 65535 || (double)n * (double)ell > 4.0e9) return AAO_ERR_UNSUPPORTED;
+    return create_impl(n, ell, tau, scheme, 0, 0, out);
+}
+
+aao_status aao_create_2d(int64_t nx, int64_t ny, int64_t ell, double tau, int scheme,
+                         aao_ctx *out)
+{
+    if (!out) return AAO_ERR_ARG;
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || ell < 1 || !(tau > 0.0) || !std::isfinite(tau) ||
+        !scheme_known(scheme))
+        return AAO_ERR_ARG;
+    if (nx > 16384 || ny > 2047 || !dst_y_supported((int)ny) || ell > 65535 ||
+        (double)nx * (double)ny * (double)ell > 2.0e9 || (double)(ell / 2 + 1) * ny > 2.0e9)
+        return AAO_ERR_UNSUPPORTED;
+    return create_impl(nx * ny, ell, tau, scheme, (int)nx, (int)ny, out);
+}
+
 aao_status aao_destroy(aao_ctx ctx)
 {
     if (!ctx) return AAO_OK;
@@ -1062,6 +1135,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->damps);
     (void)hipFree(ctx->segpart);
     (void)hipFree(ctx->ntmp);
+    (void)hipFree(ctx->dsty);
     (void)hipFree(ctx->bl_prob);
     (void)hipFree(ctx->bl_tiles);
     (void)hipFree(ctx->bl_chirp);
@@ -1090,6 +1164,7 @@ aao_status aao_set_steps(aao_ctx ctx, const double *tau_k)
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
+    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (!tau_k) {
         (void)hipFree(ctx->tauk);
         (void)hipFree(ctx->sigk);
@@ -1132,6 +1207,7 @@ aao_status aao_set_precision(aao_ctx ctx, int prec)
 aao_status aao_set_neumann_order(aao_ctx ctx, int q)
 {
     if (!ctx) return AAO_ERR_ARG;
+    if (ctx->ny > 0 && q != 0) return unsupported_2d(ctx);
     if (q < 0 || q > 64) return arg_err(ctx, "neumann order must be in [0, 64]");
     ctx->neumann = q;
     return AAO_OK;
@@ -1141,6 +1217,7 @@ aao_status aao_project_sine(aao_ctx ctx, int J, const int *modes, const double *
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
+    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (J < 0 || (J > 0 && (!modes || !amps)) || !u0) return arg_err(ctx, "bad sine series");
     for (int m = 0; m < J; ++m)
         if (modes[m] < 1) return arg_err(ctx, "modes must be >= 1");
@@ -1170,6 +1247,16 @@ aao_status aao_build_rhs(aao_ctx ctx, const double *u0, const double *v0, double
     if (!u0 || !b) return arg_err(ctx, "null vector");
     if (v0 && ctx->scheme == AAO_WAVE_CD)
         return arg_err(ctx, "the central-difference system takes no initial velocity");
+    if (ctx->ny > 0) {
+        if (ctx->scheme != AAO_HEAT_IE && ctx->scheme != AAO_WAVE_BD2) return unsupported_2d(ctx);
+        if (ctx->scheme == AAO_WAVE_BD2 && ctx->ell < 2)
+            return arg_err(ctx, "the BD2 right-hand side needs ell >= 2");
+        if (v0 && ctx->scheme == AAO_HEAT_IE)
+            return arg_err(ctx, "the heat system takes no initial velocity");
+        AAO_HIP(launch_build_rhs2d(b, u0, v0, ctx->nx, ctx->ny, (int)ctx->ell, ctx->sc, ctx->kappa,
+                                   ctx->tau, ctx->st));
+        return AAO_OK;
+    }
     AAO_HIP(launch_build_rhs(b, u0, v0, (int)ctx->n, (int)ctx->ell, ctx->sc, ctx->kappa, ctx->tau,
                              ctx->st));
     return AAO_OK;
@@ -1191,6 +1278,7 @@ aao_status aao_apply_Pinv(aao_ctx ctx, const double *r, double *z, int neumann_o
     if (ctx->broken) return AAO_ERR_HIP;
     if (!r || !z) return arg_err(ctx, "null vector");
     if (neumann_order < 0 || neumann_order > 64) return arg_err(ctx, "bad neumann order");
+    if (ctx->ny > 0 && neumann_order != 0) return unsupported_2d(ctx);
     if (overlap(r, z, ctx->N() * sizeof(double))) return arg_err(ctx, "r and z overlap");
     return pinv_impl(ctx, r, nullptr, z, neumann_order, transpose ? 1 : 0);
 }
@@ -1240,6 +1328,7 @@ aao_status aao_grad(aao_ctx ctx, const double *u0, const double *v0, const doubl
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
+    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (!U || !lam || !g_u0) return arg_err(ctx, "null vector");
     const int n = (int)ctx->n;
     const double tau = ctx->tau, kap = ctx->kappa;
@@ -1299,6 +1388,7 @@ aao_status aao_grad_checkpointed(aao_ctx ctx, const double *u0, const double *Uc
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
+    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (ctx->scheme != AAO_HEAT_IE) {
         ctx->err = "checkpointed gradients are implemented for the heat scheme";
         return AAO_ERR_UNSUPPORTED;
@@ -1395,6 +1485,7 @@ aao_status aao_tune(aao_ctx ctx, int reps)
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
+    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (reps < 1 || reps > 1000) return arg_err(ctx, "reps must be in [1, 1000]");
     // scratch: two real ell x n arrays (zeros) for the transforms and the matvec; the
     // half spectrum is workspace and is rewritten by every apply
@@ -1428,6 +1519,7 @@ aao_status aao_set_tune_cache(const char *path)
 aao_status aao_get_config(aao_ctx ctx, int kind, int *code)
 {
     if (!ctx || !code) return AAO_ERR_ARG;
+    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
     *code = ctx->cfg[ctx->prec][kind];
     return AAO_OK;
@@ -1436,6 +1528,7 @@ aao_status aao_get_config(aao_ctx ctx, int kind, int *code)
 aao_status aao_set_config(aao_ctx ctx, int kind, int code)
 {
     if (!ctx) return AAO_ERR_ARG;
+    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
     if (!config_valid(ctx, kind, code)) return arg_err(ctx, "launch shape does not fit n, ell");
     ctx->cfg[ctx->prec][kind] = code;
@@ -1445,6 +1538,7 @@ aao_status aao_set_config(aao_ctx ctx, int kind, int code)
 aao_status aao_config_shape(aao_ctx ctx, int kind, int code, int shape[3])
 {
     if (!ctx || !shape) return AAO_ERR_ARG;
+    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
     if (code < 0) return arg_err(ctx, "default shapes have no code");
     if (kind == AAO_CFG_SHIFTED_SOLVE) {

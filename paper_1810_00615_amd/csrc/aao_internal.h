@@ -118,18 +118,23 @@ bool fft_config_ok(int cfg, int ell, int n, bool single);
 // same configuration and arithmetic.  cfg selects the launch shape (chunk, threads,
 // LDS staging) among solve_num_configs(); a value that is out of range or does not
 // cover n selects solve_default_config(n).
+// rpf > 1 (unit square, rpf = ny): every frequency has rpf rows of n unknowns, row q of
+// frequency j at offset j lds + q sub of the spectrum.
 hipError_t launch_shifted_solve(const void *in, void *out, int lds, bool single_in,
                                 bool single_out, bool single_arith, int n, int ell,
                                 const double *sym, const void *ptab, int transpose,
-                                int *fail_flag, hipStream_t st, int cfg = -1);
-// Per-row symbol table, (ell/2 + 1) x 2 orientations x (d, e) complex = 8 doubles a row.
-hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, hipStream_t st);
+                                int *fail_flag, hipStream_t st, int cfg = -1, int rpf = 1,
+                                int sub = 0);
+// Per-row symbol table, (ell/2 + 1) rpf rows x 2 orientations x (d, e) complex = 8
+// doubles a row; ny > 0 selects the Q1 blocks of the unit square (rpf = ny, n = nx).
+hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, hipStream_t st,
+                          int ny = 0);
 // Partition tables (interior elimination factors and response end values) of every
 // row and orientation for the chunk width of configuration cfg, in the solve's
-// arithmetic; out holds solve_table_bytes(ell).
+// arithmetic; out holds solve_table_bytes(ell, rpf).
 hipError_t launch_solve_tables(const double *sym, int n, int ell, int cfg, bool single_arith,
-                               void *out, hipStream_t st);
-size_t solve_table_bytes(int ell);
+                               void *out, hipStream_t st, int rpf = 1);
+size_t solve_table_bytes(int ell, int rpf = 1);
 int solve_effective_config(int cfg, int n);
 int solve_num_configs();
 bool solve_config_ok(int cfg, int n);
@@ -253,6 +258,20 @@ hipError_t launch_mk(const double *x, double cm, double ck, const double *x2, do
                      double cm3 = 0.0, double ck3 = 0.0);
 hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double *part,
                              hipStream_t st);
+
+// ------------------------------------------------- unit square (Q1 elements)
+// Vectors of one time level are ny x nx, x fastest; ell levels follow each other.
+// Orthonormal sine transform along y of every level (its own inverse); in == out
+// allowed.  Needs ny + 1 a power of two, ny <= 2047.
+bool dst_y_supported(int ny);
+hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, hipStream_t st);
+// y = A x (A^T x with transpose), y = bsub - A x if bsub, for the Q1 blocks
+// a_m M2 + b_m kappa K2 (M2 = My (x) Mx, K2 = Ky (x) Mx + My (x) Kx).
+hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
+                           int ell, Scheme sc, double kappa, int transpose, hipStream_t st);
+// Right-hand side of the heat and BD2 systems on the unit square.
+hipError_t launch_build_rhs2d(double *b, const double *u0, const double *v0, int nx, int ny,
+                              int ell, Scheme sc, double kappa, double tau, hipStream_t st);
 
 
 }  // namespace aao

@@ -32,10 +32,14 @@ namespace aao {
 // The right-hand sides are read from `in` (element type SI) and the solutions written
 // to `out` (element type SO); in == out (with SI == SO) solves in place: a workgroup
 // reads its whole row before it writes any of it.
+// Rows: rpf rows per frequency (1 in one space dimension; ny on the unit square, where
+// row (j, q) is the x-line of sine mode q in y of frequency j) at spectrum offset
+// (j / rpf) lds + (j % rpf) sub.
 template <typename A, typename SI, typename SO, int CW, int NTB, bool STAGE>
 __global__ void __launch_bounds__(NTB)
 k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__restrict__ sym,
-                const cx<A> *__restrict__ ptab, int transpose, int *__restrict__ fail)
+                const cx<A> *__restrict__ ptab, int transpose, int *__restrict__ fail, int rpf,
+                int sub)
 {
     extern __shared__ unsigned char smraw[];
     const int NT = blockDim.x;
@@ -46,8 +50,10 @@ k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__r
 
     const int j = blockIdx.x;
     const int t = threadIdx.x;
-    const cx<SI> *row = in + (size_t)j * lds;
-    cx<SO> *orow = out + (size_t)j * lds;
+    const int jf = j / rpf;
+    const size_t roff = (size_t)jf * lds + (size_t)(j - jf * rpf) * sub;
+    const cx<SI> *row = in + roff;
+    cx<SO> *orow = out + roff;
 
     const int P = (n + CW - 1) / CW;
     const int a0 = t * CW;
@@ -197,7 +203,8 @@ static constexpr size_t stage_bytes(int cw, int nt)
 
 template <typename A, typename SI, typename SO, int CW, int NT, bool STAGE>
 static hipError_t solve_go(const void *in, void *out, int lds, int n, int ell, const double *sym,
-                           const void *ptab, int transpose, int *fail, hipStream_t st)
+                           const void *ptab, int transpose, int *fail, hipStream_t st, int rpf,
+                           int sub)
 {
     size_t smem = sizeof(cx<A>) * psolve_lds_entries(CW, NT);
     if (STAGE) {
@@ -213,24 +220,25 @@ static hipError_t solve_go(const void *in, void *out, int lds, int n, int ell, c
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    kern<<<ell / 2 + 1, NT, smem, st>>>(reinterpret_cast<const cx<SI> *>(in),
-                                        reinterpret_cast<cx<SO> *>(out), lds, n, sym,
-                                        reinterpret_cast<const cx<A> *>(ptab), transpose, fail);
+    kern<<<(ell / 2 + 1) * rpf, NT, smem, st>>>(reinterpret_cast<const cx<SI> *>(in),
+                                                reinterpret_cast<cx<SO> *>(out), lds, n, sym,
+                                                reinterpret_cast<const cx<A> *>(ptab), transpose,
+                                                fail, rpf, sub);
     return hipGetLastError();
 }
 
 template <typename A, typename SI, typename SO>
 static hipError_t solve_disp(int cfg, const void *in, void *out, int lds, int n, int ell,
                              const double *sym, const void *ptab, int transpose, int *fail,
-                             hipStream_t st)
+                             hipStream_t st, int rpf, int sub)
 {
     const bool stage = cfg >= kNumSolveCfg;
 #define AAO_SCFG(I, CW, NT)                                                                    \
     case I:                                                                                    \
         return stage ? solve_go<A, SI, SO, CW, NT, true>(in, out, lds, n, ell, sym, ptab,        \
-                                                         transpose, fail, st)                  \
+                                                         transpose, fail, st, rpf, sub)        \
                      : solve_go<A, SI, SO, CW, NT, false>(in, out, lds, n, ell, sym, ptab,       \
-                                                          transpose, fail, st);
+                                                          transpose, fail, st, rpf, sub);
     switch (cfg % kNumSolveCfg) {
         AAO_SCFG(0, 1, 256)
         AAO_SCFG(1, 2, 256)
@@ -387,11 +395,27 @@ hipError_t launch_heat_segments(const double *u0, const double *Uck, int stride,
 //   m over the Toeplitz offsets -up..s (BD4: (1 - w^j)^2 (2 - w^j); central
 //   differences: w^{-j} - 2 + w^j = -4 sin^2(pi j / ell), real),
 //   d_j = alpha_j 4h/6 + beta_j kappa 2/h,  e_j = alpha_j h/6 - beta_j kappa/h.
-__global__ void k_symbols(double *__restrict__ sym, int n, int ell, Scheme sc, double kappa)
+// On the unit square (ny > 0; Q1 blocks alpha My (x) Mx + beta kappa (Ky (x) Mx +
+// My (x) Kx)) the sine transform in y leaves, for mode q = 1..ny of row (j, q - 1),
+// the x-tridiagonal A Mx + B Kx with A = alpha my_q + beta kappa ky_q, B = beta kappa my_q,
+//   my_q = hy/6 (4 + 2 cos(pi q/(ny+1))),  ky_q = 4 sin^2(pi q/(2(ny+1))) / hy,
+// so d = A 4h/6 + B 2/h, e = A h/6 - B/h with h = 1/(n+1) the x spacing.
+__global__ void k_symbols(double *__restrict__ sym, int n, int ell, Scheme sc, double kappa,
+                          int ny)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j > ell / 2) return;
+    const int rpf = ny > 0 ? ny : 1;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (ell / 2 + 1) * rpf) return;
+    const int j = r / rpf;
     const double h = 1.0 / (n + 1.0);
+    double my = 1.0, ky = 0.0;
+    if (ny > 0) {
+        const int q = r - j * rpf + 1;
+        const double hy = 1.0 / (ny + 1.0);
+        const double sh = sinpi((double)q / (2.0 * (ny + 1.0)));
+        my = hy / 6.0 * (4.0 + 2.0 * cospi((double)q / (ny + 1.0)));
+        ky = 4.0 * sh * sh / hy;
+    }
     for (int tr = 0; tr < 2; ++tr) {
         double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
         for (int m = -sc.up; m <= sc.s; ++m) {
@@ -405,18 +429,22 @@ __global__ void k_symbols(double *__restrict__ sym, int n, int ell, Scheme sc, d
             br += bm * cs;
             bi += bm * sn;
         }
-        double *o = sym + ((size_t)j * 2 + tr) * 4;
-        o[0] = ar * (4.0 * h / 6.0) + br * kappa * (2.0 / h);
-        o[1] = ai * (4.0 * h / 6.0) + bi * kappa * (2.0 / h);
-        o[2] = ar * (h / 6.0) - br * kappa / h;
-        o[3] = ai * (h / 6.0) - bi * kappa / h;
+        // A = alpha my + beta kappa ky, B = beta kappa my
+        const double Ar = ar * my + br * kappa * ky, Ai = ai * my + bi * kappa * ky;
+        const double Br = br * kappa * my, Bi = bi * kappa * my;
+        double *o = sym + ((size_t)r * 2 + tr) * 4;
+        o[0] = Ar * (4.0 * h / 6.0) + Br * (2.0 / h);
+        o[1] = Ai * (4.0 * h / 6.0) + Bi * (2.0 / h);
+        o[2] = Ar * (h / 6.0) - Br / h;
+        o[3] = Ai * (h / 6.0) - Bi / h;
     }
 }
 
-hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, hipStream_t st)
+hipError_t launch_symbols(double *sym, int n, int ell, Scheme sc, double kappa, hipStream_t st,
+                          int ny)
 {
-    const int rows = ell / 2 + 1;
-    k_symbols<<<(rows + 255) / 256, 256, 0, st>>>(sym, n, ell, sc, kappa);
+    const int rows = (ell / 2 + 1) * (ny > 0 ? ny : 1);
+    k_symbols<<<(rows + 255) / 256, 256, 0, st>>>(sym, n, ell, sc, kappa, ny);
     return hipGetLastError();
 }
 
@@ -434,9 +462,9 @@ __global__ void k_ptab(const double *__restrict__ sym, int rows, int n, cx<A> *_
     build_tab<A, CW>(d, e, n - (P - 1) * CW - 1, out + (size_t)id * psolve_tab_entries(CW));
 }
 
-size_t solve_table_bytes(int ell)
+size_t solve_table_bytes(int ell, int rpf)
 {
-    return sizeof(cx<double>) * 2 * (size_t)(ell / 2 + 1) * psolve_tab_entries(32);
+    return sizeof(cx<double>) * 2 * (size_t)(ell / 2 + 1) * (size_t)rpf * psolve_tab_entries(32);
 }
 
 int solve_effective_config(int cfg, int n)
@@ -445,9 +473,10 @@ int solve_effective_config(int cfg, int n)
 }
 
 template <typename A>
-static hipError_t ptab_disp(int cw, const double *sym, int n, int ell, void *out, hipStream_t st)
+static hipError_t ptab_disp(int cw, const double *sym, int n, int ell, void *out, hipStream_t st,
+                            int rpf)
 {
-    const int rows = ell / 2 + 1;
+    const int rows = (ell / 2 + 1) * rpf;
     const int grid = (2 * rows + 255) / 256;
     cx<A> *o = reinterpret_cast<cx<A> *>(out);
     switch (cw) {
@@ -463,38 +492,38 @@ static hipError_t ptab_disp(int cw, const double *sym, int n, int ell, void *out
 }
 
 hipError_t launch_solve_tables(const double *sym, int n, int ell, int cfg, bool single_arith,
-                               void *out, hipStream_t st)
+                               void *out, hipStream_t st, int rpf)
 {
     cfg = solve_effective_config(cfg, n);
-    if (cfg < 0) return hipErrorInvalidValue;
+    if (cfg < 0 || rpf < 1) return hipErrorInvalidValue;
     int cw, nt, stage;
     solve_config_shape(cfg, &cw, &nt, &stage);
-    return single_arith ? ptab_disp<float>(cw, sym, n, ell, out, st)
-                        : ptab_disp<double>(cw, sym, n, ell, out, st);
+    return single_arith ? ptab_disp<float>(cw, sym, n, ell, out, st, rpf)
+                        : ptab_disp<double>(cw, sym, n, ell, out, st, rpf);
 }
 
 hipError_t launch_shifted_solve(const void *in, void *out, int lds, bool single_in,
                                 bool single_out, bool single_arith, int n, int ell,
                                 const double *sym, const void *ptab, int transpose,
-                                int *fail_flag, hipStream_t st, int cfg)
+                                int *fail_flag, hipStream_t st, int cfg, int rpf, int sub)
 {
     cfg = solve_effective_config(cfg, n);
-    if (cfg < 0 || !ptab) return hipErrorInvalidValue;
+    if (cfg < 0 || !ptab || rpf < 1) return hipErrorInvalidValue;
     if (in == out && single_in != single_out) return hipErrorInvalidValue;
     if (single_arith) {
         if (!single_in || !single_out) return hipErrorInvalidValue;
         return solve_disp<float, float, float>(cfg, in, out, lds, n, ell, sym, ptab, transpose,
-                                               fail_flag, st);
+                                               fail_flag, st, rpf, sub);
     }
     if (!single_in && !single_out)
         return solve_disp<double, double, double>(cfg, in, out, lds, n, ell, sym, ptab,
-                                                  transpose, fail_flag, st);
+                                                  transpose, fail_flag, st, rpf, sub);
     if (single_in && single_out)
         return solve_disp<double, float, float>(cfg, in, out, lds, n, ell, sym, ptab, transpose,
-                                                fail_flag, st);
+                                                fail_flag, st, rpf, sub);
     if (single_in)
         return solve_disp<double, float, double>(cfg, in, out, lds, n, ell, sym, ptab,
-                                                 transpose, fail_flag, st);
+                                                 transpose, fail_flag, st, rpf, sub);
     return hipErrorInvalidValue;
 }
 

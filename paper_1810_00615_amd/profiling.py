@@ -34,6 +34,7 @@ FAMILIES = [
     ("reduce", r"k_reduce_small|k_reduce_parts|k_batch_reduce|k_batch_small"),
     ("axpy", r"k_multi_axpy|k_batch_axpy"),
     ("arnoldi_update", r"k_arnoldi_update"),
+    ("sine_y", r"k_dst_y"),
     ("dot", r"k_dot1"),
     ("copy", r"copyBuffer|elementwise_kernel.*copy|direct_copy"),
 ]

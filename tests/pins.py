@@ -160,15 +160,9 @@ def kron_A(blocks, ell, circulant=False):
     return A
 
 
-def eig_C(scheme, n, ell, tau, kappa, transpose=False):
-    """Eigenvalues of the block circulant on the (frequency j, sine mode m) basis:
-    hatA_j = alpha_j M + beta_j kappa K acts on sine mode m as
-    alpha_j mu_m + beta_j kappa lambda_m mu_m (M, K share the sine eigenvectors)."""
-    h = 1.0 / (n + 1)
-    m = np.arange(1, n + 1)
-    c = np.cos(m * np.pi * h)
-    mu_ = (h / 3.0) * (2.0 + c)
-    lam_ = 6.0 * (1.0 - c) / (h * h * (2.0 + c))
+def alpha_beta(scheme, ell, tau, transpose=False):
+    """Symbols alpha_j = sum_m a_m w^{jm}, beta_j = sum_m b_m w^{jm} of the circulant
+    (blocks a_m M + b_m kappa K), w = exp(-+2 pi i / ell), in closed form."""
     j = np.arange(ell)
     w = np.exp((1j if transpose else -1j) * 2 * np.pi * j / ell)
     if scheme == 0:
@@ -179,6 +173,19 @@ def eig_C(scheme, n, ell, tau, kappa, transpose=False):
         al, be = (1 - w) ** 2 * (2 - w), np.full(ell, tau * tau)
     else:                                   # CD: w^{-1} - 2 + w = -4 sin^2(pi j / ell)
         al, be = -4.0 * np.sin(np.pi * j / ell) ** 2 + 0j, np.full(ell, tau * tau)
+    return al, be
+
+
+def eig_C(scheme, n, ell, tau, kappa, transpose=False):
+    """Eigenvalues of the block circulant on the (frequency j, sine mode m) basis:
+    hatA_j = alpha_j M + beta_j kappa K acts on sine mode m as
+    alpha_j mu_m + beta_j kappa lambda_m mu_m (M, K share the sine eigenvectors)."""
+    h = 1.0 / (n + 1)
+    m = np.arange(1, n + 1)
+    c = np.cos(m * np.pi * h)
+    mu_ = (h / 3.0) * (2.0 + c)
+    lam_ = 6.0 * (1.0 - c) / (h * h * (2.0 + c))
+    al, be = alpha_beta(scheme, ell, tau, transpose)
     return al[:, None] * mu_[None, :] + be[:, None] * kappa * (lam_ * mu_)[None, :]
 
 
@@ -197,4 +204,37 @@ def pinv_spectral(scheme, n, ell, tau, kappa, r, transpose=False):
     Xs = dst(X, type=1, axis=1)
     Ys = Xs / eig_C(scheme, n, ell, tau, kappa, transpose)
     Y = idst(Ys, type=1, axis=1)
+    return np.fft.ifft(Y, axis=0).real
+
+
+def eig_C2(scheme, nx, ny, ell, tau, kappa, transpose=False):
+    """Eigenvalues of the 2D block circulant (Q1 blocks alpha_j M2 + beta_j kappa K2)
+    on the (frequency j, sine mode q in y, sine mode p in x) basis, shape (ell, ny, nx):
+    M2 and K2 = Ky (x) Mx + My (x) Kx share the sine-product eigenvectors, with the 1D
+    eigenvalues mu (mass) and lambda mu (stiffness) along each axis."""
+    def mk(n):
+        h = 1.0 / (n + 1)
+        c = np.cos(np.arange(1, n + 1) * np.pi * h)
+        mu_ = (h / 3.0) * (2.0 + c)
+        return mu_, 2.0 * (1.0 - c) / h
+    mux, kx = mk(nx)
+    muy, ky = mk(ny)
+    m2 = muy[:, None] * mux[None, :]
+    k2 = ky[:, None] * mux[None, :] + muy[:, None] * kx[None, :]
+    al, be = alpha_beta(scheme, ell, tau, transpose)
+    return al[:, None, None] * m2[None] + be[:, None, None] * kappa * k2[None]
+
+
+def cond_C2(scheme, nx, ny, ell, tau, kappa):
+    e = np.abs(eig_C2(scheme, nx, ny, ell, tau, kappa))
+    return e.max() / e.min()
+
+
+def pinv_spectral2(scheme, nx, ny, ell, tau, kappa, r, transpose=False):
+    """2D C^{-1} r by the full eigen-decomposition: FFT in time, DST-I along y and x,
+    division by the eigenvalues, inverse transforms."""
+    from scipy.fft import dstn, idstn
+    X = np.fft.fft(np.asarray(r, dtype=np.float64).reshape(ell, ny, nx), axis=0)
+    Xs = dstn(X, type=1, axes=(1, 2))
+    Y = idstn(Xs / eig_C2(scheme, nx, ny, ell, tau, kappa, transpose), type=1, axes=(1, 2))
     return np.fft.ifft(Y, axis=0).real

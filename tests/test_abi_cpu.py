@@ -48,6 +48,19 @@ def test_create_rejects_bad_arguments(L, args):
     assert not c.value
 
 
+@pytest.mark.parametrize("args,code", [((0, 3, 4, 0.1, 0), -1), ((4, 0, 4, 0.1, 0), -1),
+                                       ((4, 3, 0, 0.1, 0), -1), ((4, 3, 4, 0.0, 0), -1),
+                                       ((4, 3, 4, 0.1, 7), -1), ((4, 4, 4, 0.1, 0), -6),
+                                       ((4, 6, 4, 0.1, 0), -6), ((4, 4095, 4, 0.1, 0), -6),
+                                       ((20000, 3, 4, 0.1, 0), -6)])
+def test_create_2d_rejects_bad_arguments(L, args, code):
+    """Argument errors, and grids whose y size is not one below a power of two (the sine
+    transform's requirement) or too large, are refused before any device call."""
+    c = ctypes.c_void_p()
+    assert L.aao_create_2d(*args, ctypes.byref(c)) == code
+    assert not c.value
+
+
 def test_create_rejects_null_out(L):
     assert L.aao_create(4, 4, 0.1, 0, None) == -1
 

@@ -1,0 +1,220 @@
+"""The unit-square path on the GPU (aao_create_2d) against the two-dimensional oracle:
+right-hand sides, the block-Toeplitz matvec with the Q1 stencils in both orientations
+(every scheme), the circulant preconditioner apply through the sine transform in y
+(every scheme, both orientations, power-of-two, Bluestein and direct-transform lengths,
+every precision mode), GMRES to the exact block-substitution solution, and at a large
+grid the closed-form solution of 2D implicit Euler.
+
+Tolerances: right-hand side and matvec 1e-14 relative to the largest entry; C^{-1}
+(FP64) max(1e-12, 8 eps kappa_2(C)) in the 2-norm against the oracle and against the
+eigen-decomposition; single-precision modes max(1e-5, 8 eps_32 kappa_2(C)); solutions
+within 4 kappa_2(A) tol of the exact one."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HEAT, BD2, BD4, CD = 0, 1, 2, 3
+NAME = {HEAT: "heat", BD2: "bd2", BD4: "bd4", CD: "cd"}
+EPS = 2.0 ** -52
+EPS32 = 2.0 ** -23
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch.device("cuda:0")
+
+
+def maxrel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def normrel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def td(dev, x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev)
+
+
+@pytest.mark.parametrize("scheme", [HEAT, BD2])
+@pytest.mark.parametrize("nx,ny,ell", [(1, 1, 2), (5, 3, 4), (64, 7, 3), (130, 31, 6)])
+def test_rhs_2d(dev, orc, scheme, nx, ny, ell):
+    from paper_1810_00615_amd import Problem2D
+    tau, kappa = 1.0 / ell, 1.3
+    rng = np.random.default_rng([nx, ny, ell, scheme])
+    u0, v0 = rng.standard_normal((ny, nx)), rng.standard_normal((ny, nx))
+    P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
+    vv = v0 if scheme == BD2 else None
+    b = P.rhs(td(dev, u0), None if vv is None else td(dev, vv)).cpu().numpy()
+    assert b.shape == (ell, ny, nx)
+    ref = orc.build_rhs2(scheme, nx, ny, ell, tau, kappa, u0, vv)
+    assert maxrel(b, ref) < 1e-14
+
+
+def test_rhs_2d_rejections(dev):
+    from paper_1810_00615_amd import AAOError, Problem2D
+    u0 = td(dev, np.ones((3, 4)))
+    with pytest.raises(AAOError):
+        Problem2D(4, 3, 5, scheme="bd4", device=dev).rhs(u0)
+    with pytest.raises(AAOError):
+        Problem2D(4, 3, 5, scheme="heat", device=dev).rhs(u0, u0)
+    P = Problem2D(4, 3, 5, device=dev)
+    with pytest.raises(AAOError):
+        P.set_steps(np.full(5, 0.2))
+    with pytest.raises(AAOError):
+        P.Pinv(P.zeros(), order=1)
+
+
+@pytest.mark.parametrize("scheme", [HEAT, BD2, BD4, CD])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("nx,ny,ell", [(1, 1, 1), (3, 1, 4), (5, 3, 5), (70, 7, 33),
+                                       (129, 15, 40)])
+def test_apply_A_2d(dev, orc, scheme, transpose, nx, ny, ell):
+    from paper_1810_00615_amd import Problem2D
+    tau, kappa = 1.0 / ell, 0.9
+    x = np.random.default_rng([nx, ny, ell, 2]).standard_normal((ell, ny, nx))
+    P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
+    y = P.A(td(dev, x), transpose=transpose).cpu().numpy()
+    ref = orc.apply_A2(scheme, nx, ny, ell, tau, kappa, x, transpose=transpose)
+    assert maxrel(y, ref) < 1e-14
+
+
+# (nx, ny, ell): power-of-two lengths, Bluestein lengths (17..2048 otherwise) and the
+# direct transform of short odd lengths; ny from 1 (sine transform of length 1) up
+PINV_SHAPES = [(1, 1, 1), (3, 1, 2), (5, 3, 4), (2, 7, 3), (17, 7, 8), (64, 15, 64),
+               (33, 7, 17), (40, 31, 16), (9, 63, 32), (20, 3, 100)]
+
+
+@pytest.mark.parametrize("scheme", [HEAT, BD2, BD4, CD])
+@pytest.mark.parametrize("transpose", [False, True])
+@pytest.mark.parametrize("nx,ny,ell", PINV_SHAPES)
+def test_pinv_2d(dev, orc, scheme, transpose, nx, ny, ell):
+    import pins
+    from paper_1810_00615_amd import Problem2D
+    tau, kappa = 1.0 / ell, 1.0
+    r = np.random.default_rng([nx, ny, ell, 3]).standard_normal((ell, ny, nx))
+    P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
+    z = P.Pinv(td(dev, r), transpose=transpose).cpu().numpy()
+    cond = pins.cond_C2(scheme, nx, ny, ell, tau, kappa)
+    tol = max(1e-12, 8 * EPS * cond)
+    zo, _ = orc.pinv2_direct(scheme, nx, ny, ell, tau, kappa, r, transpose=transpose)
+    zs = pins.pinv_spectral2(scheme, nx, ny, ell, tau, kappa, r, transpose)
+    e_o, e_s = normrel(z, zo), normrel(z, zs)
+    print(f"{NAME[scheme]} 2d pinv {nx}x{ny} ell={ell} tr={transpose}: vs oracle {e_o:.2e}, "
+          f"vs spectral {e_s:.2e}, tol {tol:.2e}")
+    assert e_o < tol and e_s < tol
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_in", "fp32"])
+@pytest.mark.parametrize("scheme", [HEAT, BD2])
+def test_pinv_2d_single_precision(dev, scheme, precision):
+    import pins
+    from paper_1810_00615_amd import Problem2D
+    nx, ny, ell = 50, 31, 64
+    tau = 1.0 / ell
+    r = np.random.default_rng([4, scheme]).standard_normal((ell, ny, nx))
+    P = Problem2D(nx, ny, ell, tau, NAME[scheme], precision=precision, device=dev)
+    z = P.Pinv(td(dev, r)).cpu().numpy()
+    cond = pins.cond_C2(scheme, nx, ny, ell, tau, 1.0)
+    e = normrel(z, pins.pinv_spectral2(scheme, nx, ny, ell, tau, 1.0, r))
+    print(f"{NAME[scheme]} 2d pinv {precision}: {e:.2e} (cond {cond:.2e})")
+    assert e < max(1e-5, 8 * EPS32 * cond)
+
+
+def _cond_A_bound(scheme, nx, ny, ell, tau, kappa):
+    """kappa_2(A) of the small test systems, from the dense matrix."""
+    import oracle
+    N = nx * ny * ell
+    I = np.eye(N)
+    A = np.column_stack([oracle.apply_A2(scheme, nx, ny, ell, tau, kappa, I[:, c]).ravel()
+                         for c in range(N)])
+    return np.linalg.cond(A)
+
+
+@pytest.mark.parametrize("scheme", [HEAT, BD2, BD4])
+def test_gmres_2d_to_exact(dev, orc, scheme):
+    from paper_1810_00615_amd import Problem2D
+    nx, ny, ell = 9, 7, 12
+    tau, kappa = 1.0 / ell, 0.8
+    rng = np.random.default_rng(80 + scheme)
+    b = rng.standard_normal((ell, ny, nx))
+    P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
+    tol = 1e-11
+    U, info = P.solve(td(dev, b), restart=60, tol=tol, maxit=600)
+    assert info["converged"], info
+    Ur = orc.solve_seq2(scheme, nx, ny, ell, tau, kappa, b)
+    cA = _cond_A_bound(scheme, nx, ny, ell, tau, kappa)
+    e = normrel(U.cpu().numpy(), Ur)
+    print(f"{NAME[scheme]} 2d gmres: {info['iters']} iterations, error {e:.2e}, cond(A) {cA:.2e}")
+    assert e < 4 * cA * tol
+    lam, info_t = P.adjoint(td(dev, b), restart=60, tol=tol, maxit=600)
+    assert info_t["converged"], info_t
+    lr = orc.solve_seq2(scheme, nx, ny, ell, tau, kappa, b, transpose=True)
+    assert normrel(lam.cpu().numpy(), lr) < 4 * cA * tol
+
+
+@pytest.mark.parametrize("scheme", [HEAT, BD2])
+def test_gmres_2d_rhs_medium(dev, orc, scheme):
+    """A solve from initial data through the library's right-hand side, on a grid with
+    several x-chunks of the solves and a ragged last sine-transform tile, against the
+    oracle's block substitution."""
+    from paper_1810_00615_amd import Problem2D
+    nx, ny, ell = 37, 31, 32
+    tau, kappa = 1.0 / ell, 1.0
+    rng = np.random.default_rng(90 + scheme)
+    u0 = rng.standard_normal((ny, nx))
+    v0 = rng.standard_normal((ny, nx)) if scheme == BD2 else None
+    P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
+    b = P.rhs(td(dev, u0), None if v0 is None else td(dev, v0))
+    U, info = P.solve(b, restart=40, tol=1e-12, maxit=400)
+    assert info["converged"], info
+    Ur = orc.solve_seq2(scheme, nx, ny, ell, tau, kappa,
+                        orc.build_rhs2(scheme, nx, ny, ell, tau, kappa, u0, v0))
+    e = normrel(U.cpu().numpy(), Ur)
+    print(f"{NAME[scheme]} 2d rhs solve {nx}x{ny} ell={ell}: {info['iters']} iterations, {e:.2e}")
+    assert e < 1e-8
+
+
+def test_heat_2d_large_closed_form(dev):
+    """Implicit Euler on a 511 x 511 grid, 64 steps (16.7M unknowns): initial data a sum
+    of sine products, whose exact discrete solution decays mode by mode,
+    u_k = sum_pq c_pq (1 + tau kappa lambda_pq)^{-k} s_p (x) s_q with lambda_pq the
+    generalised eigenvalue of (K2, M2) -- checked at every time level."""
+    import torch
+    from paper_1810_00615_amd import Problem2D
+    nx = ny = 511
+    ell, kappa = 64, 0.05
+    tau = 1.0 / ell
+    modes = [(1, 1, 1.0), (2, 3, 0.5), (7, 5, -0.25), (40, 33, 0.125)]
+
+    def sines(n, m):
+        return np.sin(np.pi * m * np.arange(1, n + 1) / (n + 1))
+
+    def lam1(n, m):
+        h = 1.0 / (n + 1)
+        c = np.cos(np.pi * m * h)
+        return 6.0 * (1.0 - c) / (h * h * (2.0 + c))
+    u0 = sum(a * np.outer(sines(ny, q), sines(nx, p)) for p, q, a in modes)
+    P = Problem2D(nx, ny, ell, tau, "heat", kappa=kappa, device=dev)
+    b = P.rhs(td(dev, u0))
+    U, info = P.solve(b, restart=30, tol=1e-10, maxit=100)
+    assert info["converged"], info
+    Ug = U.cpu().numpy()
+    Ur = np.stack([sum(a * (1.0 + tau * kappa * (lam1(nx, p) + lam1(ny, q))) ** (-(k + 1)) *
+                       np.outer(sines(ny, q), sines(nx, p)) for p, q, a in modes)
+                   for k in range(ell)])
+    worst = max(normrel(Ug[k], Ur[k]) for k in range(ell))
+    e = normrel(Ug, Ur)
+    print(f"heat 2d 511x511x64: {info['iters']} iterations, error {e:.2e}, "
+          f"worst level {worst:.2e}")
+    # the slowest mode keeps a third of its amplitude over the 64 steps, so the
+    # per-level error stays within a small multiple of the global one
+    assert e < 1e-8 and worst < 1e-7
+    del U, b
+    torch.cuda.empty_cache()

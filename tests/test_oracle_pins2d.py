@@ -129,3 +129,18 @@ def test_2d_heat_preconditioned_structure(orc):
         e[0] = M2[:, c]
         ref = orc.pinv2_direct(HEAT, nx, ny, ell, tau, 1.0, e)[0].ravel()
         assert rel(D[:, N - nn + c], ref) < 1e-12
+
+
+@pytest.mark.parametrize("scheme", [0, 1, 2, 3])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_2d_pinv_matches_eigendecomposition(orc, scheme, transpose):
+    """The oracle's 2D C^{-1} (direct DFT in time, banded 2D solves) against the full
+    eigen-decomposition of the block circulant (FFT in time, sine transforms along y
+    and x, division by alpha_j mu_pq + beta_j kappa lambda_pq), every scheme."""
+    nx, ny, ell = 6, 4, 7
+    tau, kappa = 1.0 / ell, 0.7
+    r = np.random.default_rng([70, scheme]).standard_normal((ell, nx * ny))
+    z, _ = orc.pinv2_direct(scheme, nx, ny, ell, tau, kappa, r, transpose=transpose)
+    ref = pins.pinv_spectral2(scheme, nx, ny, ell, tau, kappa, r, transpose)
+    tol = max(1e-13, 8 * 2.0 ** -52 * pins.cond_C2(scheme, nx, ny, ell, tau, kappa))
+    assert rel(z, ref) < tol
