@@ -185,6 +185,61 @@ def bench_beyond_cache(args):
     return out
 
 
+def bench_square(args):
+    """Heat on the unit square, Q1 elements, 511 x 511 interior nodes, 64 steps (16.7 M
+    unknowns, the unknown count of the headline): the preconditioner apply with its
+    kernels (sine transform along y, time transforms, shifted solves), the matvec, and
+    FGMRES(30) to 1e-8 in FP64 and with the single-precision input side."""
+    import torch
+
+    from paper_1810_00615_amd import Problem2D
+    from paper_1810_00615_amd.inputs import square_heat
+    w = square_heat()
+    P = Problem2D(w.nx, w.ny, w.ell, w.tau, "heat", kappa=w.kappa)
+    b = P.rhs(torch.from_numpy(w.u0).cuda())
+    N = w.nx * w.ny * w.ell
+    S = (w.ell // 2 + 1) * w.nx * w.ny
+    out = {"workload": w.name, "unknowns": N, "vector_MB": 8 * N / 1e6}
+    z = P.empty()
+    x = P.empty()
+    kinds = ("sine_y", "fft_fwd", "shifted_solve", "fft_inv")
+    for prec in ("fp64", "mixed_in"):
+        P.set_precision(prec)
+        if not args.no_tune:
+            out[f"shapes_{prec}"] = {k: v for k, v in P.tune(reps=5).items()}
+        for _ in range(2):
+            P.Pinv(b, out=z)
+        P.set_timing(True)
+        t, _ = _time(lambda: P.Pinv(b, out=z), 10)
+        kt = P.timing()
+        P.set_timing(False)
+        w_in = 16 if prec == "fp64" else 8
+        # two sine passes (read + write N doubles each), the transforms and the solves
+        alg = 32 * N + 16 * N + 2 * (w_in + 16) * S
+        P.solve(b, restart=w.restart, tol=w.tol, maxit=w.maxit, out=x)
+        ts, (_, info) = _time(lambda: P.solve(b, restart=w.restart, tol=w.tol,
+                                               maxit=w.maxit, out=x), 3)
+        out[f"pinv_{prec}"] = {
+            "us": t * 1e6, "alg_bytes": alg, "GBps": alg / t / 1e9,
+            "frac_hbm": alg / t / 1e9 / HBM_PEAK_GBPS,
+            "kernel_avg_us": {k: kt[k][0] / max(kt[k][1], 1) * 1e3 for k in kinds},
+            "kernel_GBps": {k: kt[k][2] / max(kt[k][0], 1e-12) / 1e6 for k in kinds}}
+        out[f"{prec}_solve"] = {"solve_ms": ts * 1e3, "iters": info["iters"],
+                                "true_rel_resid": info["rel_resid_true"],
+                                "converged": bool(info["converged"])}
+    P.set_precision("fp64")
+    P.set_timing(["matvec"])
+    _time(lambda: P.A(b, out=z), 10)
+    km = P.timing()["matvec"]
+    P.set_timing(False)
+    out["matvec"] = {"us": km[0] / km[1] * 1e3, "GBps": km[2] / (km[0] * 1e-3) / 1e9,
+                     "frac_hbm": km[2] / (km[0] * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    out["mixed_in_speedup_vs_fp64"] = (out["fp64_solve"]["solve_ms"] /
+                                       out["mixed_in_solve"]["solve_ms"])
+    P.close()
+    return out
+
+
 def _time(fn, reps):
     import torch
     torch.cuda.synchronize()
@@ -341,6 +396,8 @@ def main():
                          "apply timing, mixed solve, extra workloads or CPU baseline")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the built-in launch shapes instead of autotuning them")
+    ap.add_argument("--square-only", action="store_true",
+                    help="only the unit-square leg (heat 511 x 511, 64 steps; for profiler runs)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched 64-problem solves, FP64 and mixed (for profiler "
                          "runs): no headline, no sequential comparison")
@@ -362,6 +419,9 @@ def main():
         set_tune_cache(args.tune_cache)
     if args.batch_only:
         print(json.dumps({"batch": bench_batch(args)}), flush=True)
+        return
+    if args.square_only:
+        print(json.dumps({"square": bench_square(args)}), flush=True)
         return
 
     from paper_1810_00615_amd import Problem
@@ -496,7 +556,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extra:
         for key, fn in (("wave_bd2", bench_wave), ("batch", bench_batch),
-                        ("adjoint", bench_adjoint), ("beyond_cache", bench_beyond_cache)):
+                        ("adjoint", bench_adjoint), ("beyond_cache", bench_beyond_cache),
+                        ("square", bench_square)):
             try:
                 out[key] = fn(args)
             except Exception as e:          # the headline line is printed regardless

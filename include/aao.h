@@ -117,8 +117,11 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
  * 1 <= ell <= 65535; AAO_ERR_UNSUPPORTED otherwise.
  * Supported on such a context: aao_set_stream, aao_set_kappa, aao_set_precision,
  * aao_build_rhs (AAO_HEAT_IE and AAO_WAVE_BD2), aao_apply_A, aao_apply_Pinv (order
- * 0), aao_gmres, aao_gmres_ex, aao_adjoint_solve, aao_set_timing*, aao_get_timing*.
- * Every other entry point returns AAO_ERR_UNSUPPORTED. */
+ * 0), aao_gmres, aao_gmres_ex, aao_adjoint_solve, aao_set_timing*, aao_get_timing*,
+ * aao_tune, aao_get_config, aao_set_config, aao_config_shape (the shifted solves'
+ * shapes apply to rows of nx unknowns).  aao_set_steps, aao_set_neumann_order (q >
+ * 0), aao_project_sine, aao_grad and aao_grad_checkpointed return
+ * AAO_ERR_UNSUPPORTED. */
 aao_status aao_create_2d(int64_t nx, int64_t ny, int64_t ell, double tau, int scheme,
                          aao_ctx *out);
 
@@ -320,7 +323,8 @@ aao_status aao_get_timing_ex(aao_ctx ctx, int kernel, double *total_ms, int64_t 
  * keeps the fastest for the current precision mode; it synchronises the stream.
  * Results are cached per process by (device, kernel, precision, n, ell); once
  * aao_set_tune_cache has named a file, results are also read from and appended to it,
- * one line "kernel precision n ell code microseconds".
+ * one line "kernel precision n ell code microseconds" (on a unit-square context n is
+ * recorded as -(ny 2^20 + nx), and the matvec has a single shape).
  * aao_set_config rejects a code that does not fit (n, ell) with AAO_ERR_ARG.
  * aao_config_shape decodes a code: FFT -> {points per thread, W, 0}; solve -> {CW,
  * NT, staged}; matvec -> {R, DPP, 0}. */

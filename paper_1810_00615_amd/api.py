@@ -297,8 +297,8 @@ class Problem2D(Problem):
     a uniform nx x ny interior grid, M2 = My (x) Mx, K2 = Ky (x) Mx + My (x) Kx, and the
     time structure of `scheme`.  Vectors of the monolithic system are (ell, ny, nx)
     tensors (x fastest); u0 and v0 are (ny, nx).  ny + 1 must be a power of two.
-    Variable steps, Neumann terms, gradients and launch-shape tuning are not
-    available here."""
+    Variable steps, Neumann terms and the gradient reductions are not available
+    here (the adjoint solve is)."""
 
     def __init__(self, nx: int, ny: int, ell: int, tau: Optional[float] = None,
                  scheme="heat", kappa: float = 1.0, precision: str = "fp64", device="cuda"):

@@ -46,6 +46,7 @@ struct aao_ctx_s {
     int64_t n = 0, ell = 0;      // n: unknowns per time level (nx ny on the unit square)
     int nx = 0, ny = 0;          // unit square (aao_create_2d); ny = 0 in one dimension
     double *dsty = nullptr;      // sine transform of the preconditioner input (unit square)
+    double *twy = nullptr;       // twiddles of the sine transform's length 2 (ny + 1)
     double tau = 0.0;
     int scheme = 0;
     double kappa = 1.0;
@@ -404,7 +405,7 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
         // which commutes with the time transform F)
         if (zprev) return AAO_ERR_UNSUPPORTED;
         AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
-                     launch_dst_y(r, ctx->dsty, ctx->nx, ctx->ny, ell, ctx->st));
+                     launch_dst_y(r, ctx->dsty, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
         r = ctx->dsty;
     }
     if (ctx->bluestein) {
@@ -427,7 +428,7 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
                      batch_fft_inv(L, ctx->spec, z, sout, ctx->st));
         if (sq)
             AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
-                         launch_dst_y(z, z, ctx->nx, ctx->ny, ell, ctx->st));
+                         launch_dst_y(z, z, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
         return AAO_OK;
     }
     AAO_LAUNCH_B(AAO_K_FFT_FWD, vec_bytes(ctx) * (zprev ? 2 : 1) + spec_in_bytes(ctx),
@@ -445,7 +446,7 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
                               ctx->cf(AAO_CFG_FFT_INV), first_norm ? in_scale : nullptr));
     if (sq)
         AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
-                     launch_dst_y(z, z, ctx->nx, ctx->ny, ell, ctx->st));
+                     launch_dst_y(z, z, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
     return AAO_OK;
 }
 
@@ -490,6 +491,12 @@ void tune_append_file(int kind, int prec, int64_t n, int64_t ell, int code, doub
     std::fclose(f);
 }
 
+// size key of the tuning cache: n, or -(ny 2^20 + nx) on the unit square
+int64_t tune_n(aao_ctx ctx)
+{
+    return ctx->ny > 0 ? -(((int64_t)ctx->ny << 20) + ctx->nx) : ctx->n;
+}
+
 // admissible codes of one kernel for the context's sizes and precision mode
 std::vector<int> tune_candidates(aao_ctx ctx, int kind)
 {
@@ -497,9 +504,10 @@ std::vector<int> tune_candidates(aao_ctx ctx, int kind)
     const bool single = kind == AAO_CFG_FFT_INV ? out_single(ctx->prec) : in_single(ctx->prec);
     if (kind == AAO_CFG_SHIFTED_SOLVE) {
         for (int c = 0; c < solve_num_configs(); ++c)
-            if (solve_config_ok(c, (int)ctx->n)) out.push_back(c);
+            if (solve_config_ok(c, solve_n(ctx))) out.push_back(c);
     } else if (kind == AAO_CFG_MATVEC) {
-        if (!scheme_generic(ctx->sc))   // the generic matvec has one launch shape
+        // the generic and the unit-square matvecs have one launch shape
+        if (!scheme_generic(ctx->sc) && ctx->ny == 0)
             for (int c = 0; c < matvec_num_configs(); ++c) out.push_back(c);
     } else if (!ctx->bluestein) {
         int buf[32];
@@ -553,8 +561,9 @@ static aao_status launch_kind(aao_ctx ctx, int kind, int code, double *buf)
                                ctx->lds, sin, ctx->tw, ctx->st, code));
     else if (kind == AAO_CFG_SHIFTED_SOLVE) {
         AAO_TRY(refresh_tables(ctx, code, false));
-        AAO_HIP(launch_shifted_solve(in_spec(ctx), ctx->spec, ctx->lds, sin, sout, sar, n, ell,
-                                     ctx->sym, ctx->ptab, 0, nullptr, ctx->st, code));
+        AAO_HIP(launch_shifted_solve(in_spec(ctx), ctx->spec, ctx->lds, sin, sout, sar,
+                                     solve_n(ctx), ell, ctx->sym, ctx->ptab, 0, nullptr, ctx->st,
+                                     code, solve_rpf(ctx), solve_sub(ctx)));
     }
     else
         AAO_HIP(launch_fft_inv(ctx->spec, ctx->lds, sout, buf, n, ell, ctx->tw, ctx->st, code));
@@ -572,7 +581,7 @@ static aao_status tune_impl(aao_ctx ctx, int reps, double *buf)
     }
     aao_status s = AAO_OK;
     for (int kind = 0; kind < AAO_NUM_CFG && s == AAO_OK; ++kind) {
-        const TuneKey key(ctx->device, kind, ctx->prec, ctx->n, ctx->ell);
+        const TuneKey key(ctx->device, kind, ctx->prec, tune_n(ctx), ctx->ell);
         {
             std::lock_guard<std::mutex> g(g_tune_mu);
             tune_read_file(ctx->device);
@@ -606,7 +615,7 @@ static aao_status tune_impl(aao_ctx ctx, int reps, double *buf)
         ctx->cfg[ctx->prec][kind] = best;
         std::lock_guard<std::mutex> g(g_tune_mu);
         g_tune[key] = best;
-        tune_append_file(kind, ctx->prec, ctx->n, ctx->ell, best, 1e3 * best_ms / reps);
+        tune_append_file(kind, ctx->prec, tune_n(ctx), ctx->ell, best, 1e3 * best_ms / reps);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1010,8 +1019,15 @@ static aao_status create_impl(int64_t n, int64_t ell, double tau, int scheme, in
         const int rpf = solve_rpf(ctx);
         if ((s = dev_alloc(ctx, (void **)&ctx->sym, sizeof(double) * 8 * H * rpf)) != AAO_OK) break;
         if ((s = dev_alloc(ctx, &ctx->ptab, solve_table_bytes((int)ell, rpf))) != AAO_OK) break;
-        if (ny > 0 && (s = dev_alloc(ctx, (void **)&ctx->dsty, sizeof(double) * ctx->N())) != AAO_OK)
-            break;
+        if (ny > 0) {
+            if ((s = dev_alloc(ctx, (void **)&ctx->dsty, sizeof(double) * ctx->N())) != AAO_OK) break;
+            if ((s = dev_alloc(ctx, (void **)&ctx->twy, sizeof(double) * 4 * (ny + 1))) != AAO_OK)
+                break;
+            if (launch_twiddles(ctx->twy, 2 * (ny + 1), 2 * (ny + 1), nullptr) != hipSuccess) {
+                s = AAO_ERR_HIP;
+                break;
+            }
+        }
         ctx->nblk = dot_blocks(ctx->N());
         ctx->ldp = kPartStride;
         if ((s = dev_alloc(ctx, (void **)&ctx->part,
@@ -1136,6 +1152,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->segpart);
     (void)hipFree(ctx->ntmp);
     (void)hipFree(ctx->dsty);
+    (void)hipFree(ctx->twy);
     (void)hipFree(ctx->bl_prob);
     (void)hipFree(ctx->bl_tiles);
     (void)hipFree(ctx->bl_chirp);
@@ -1485,7 +1502,6 @@ aao_status aao_tune(aao_ctx ctx, int reps)
 {
     if (!ctx) return AAO_ERR_ARG;
     if (ctx->broken) return AAO_ERR_HIP;
-    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (reps < 1 || reps > 1000) return arg_err(ctx, "reps must be in [1, 1000]");
     // scratch: two real ell x n arrays (zeros) for the transforms and the matvec; the
     // half spectrum is workspace and is rewritten by every apply
@@ -1519,7 +1535,6 @@ aao_status aao_set_tune_cache(const char *path)
 aao_status aao_get_config(aao_ctx ctx, int kind, int *code)
 {
     if (!ctx || !code) return AAO_ERR_ARG;
-    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
     *code = ctx->cfg[ctx->prec][kind];
     return AAO_OK;
@@ -1528,7 +1543,6 @@ aao_status aao_get_config(aao_ctx ctx, int kind, int *code)
 aao_status aao_set_config(aao_ctx ctx, int kind, int code)
 {
     if (!ctx) return AAO_ERR_ARG;
-    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
     if (!config_valid(ctx, kind, code)) return arg_err(ctx, "launch shape does not fit n, ell");
     ctx->cfg[ctx->prec][kind] = code;
@@ -1538,7 +1552,6 @@ aao_status aao_set_config(aao_ctx ctx, int kind, int code)
 aao_status aao_config_shape(aao_ctx ctx, int kind, int code, int shape[3])
 {
     if (!ctx || !shape) return AAO_ERR_ARG;
-    if (ctx->ny > 0) return unsupported_2d(ctx);
     if (kind < 0 || kind >= AAO_NUM_CFG) return arg_err(ctx, "bad config kind");
     if (code < 0) return arg_err(ctx, "default shapes have no code");
     if (kind == AAO_CFG_SHIFTED_SOLVE) {

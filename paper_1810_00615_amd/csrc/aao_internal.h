@@ -262,9 +262,11 @@ hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double 
 // ------------------------------------------------- unit square (Q1 elements)
 // Vectors of one time level are ny x nx, x fastest; ell levels follow each other.
 // Orthonormal sine transform along y of every level (its own inverse); in == out
-// allowed.  Needs ny + 1 a power of two, ny <= 2047.
+// allowed.  Needs ny + 1 a power of two, ny <= 2047; tw the twiddle table of length
+// 2 (ny + 1) (launch_twiddles).
 bool dst_y_supported(int ny);
-hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, hipStream_t st);
+hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, const double *tw,
+                        hipStream_t st);
 // y = A x (A^T x with transpose), y = bsub - A x if bsub, for the Q1 blocks
 // a_m M2 + b_m kappa K2 (M2 = My (x) Mx, K2 = Ky (x) Mx + My (x) Kx).
 hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,

@@ -147,7 +147,8 @@ k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__r
 // a time.  A row of n unknowns needs n <= CW * NT.
 static const int kSolveCfg[][2] = {{1, 256}, {2, 256}, {4, 256}, {8, 256}, {8, 512},
                                    {8, 1024}, {16, 128}, {16, 256}, {16, 512}, {16, 1024},
-                                   {32, 128}, {32, 256}};
+                                   {32, 128}, {32, 256}, {4, 64}, {8, 64}, {16, 64},
+                                   {4, 128}, {8, 128}};
 constexpr int kNumSolveCfg = sizeof(kSolveCfg) / sizeof(kSolveCfg[0]);
 
 int solve_num_configs() { return 2 * kNumSolveCfg; }
@@ -252,6 +253,11 @@ static hipError_t solve_disp(int cfg, const void *in, void *out, int lds, int n,
         AAO_SCFG(9, 16, 1024)
         AAO_SCFG(10, 32, 128)
         AAO_SCFG(11, 32, 256)
+        AAO_SCFG(12, 4, 64)
+        AAO_SCFG(13, 8, 64)
+        AAO_SCFG(14, 16, 64)
+        AAO_SCFG(15, 4, 128)
+        AAO_SCFG(16, 8, 128)
     default: return hipErrorInvalidValue;
     }
 #undef AAO_SCFG

@@ -13,223 +13,186 @@
 // This file: the sine transform along y, the block-Toeplitz matvec with the Q1
 // stencils, and the right-hand side.  All FP64 and memory-bound.
 #include "../../include/aao.h"
-#include "aao_internal.h"
+#include "fft_core.h"
 
 namespace aao {
 
 // ------------------------------------------------------------ sine transform
 // out[k][p][i] = sqrt(2/(ny+1)) sum_q in[k][q][i] sin(pi p q/(ny+1)), p, q = 1..ny.
 // Two neighbouring columns (a, b) of a level form one complex sequence v = a + i b.
-// Its odd extension z of length Ly = 2(ny+1) (z_0 = z_{ny+1} = 0, z_q = v_q,
-// z_{Ly-q} = -v_q) has the DFT Z_p = -2i (A_p + i B_p), A and B the unnormalised sine
+// Its odd extension z of length L = 2(ny+1) (z_0 = z_{ny+1} = 0, z_q = v_q,
+// z_{L-q} = -v_q) has the DFT Z_p = -2i (A_p + i B_p), A and B the unnormalised sine
 // transforms of a and b, so A_p = -Im Z_p / 2 and B_p = Re Z_p / 2.
-// One workgroup holds S sequences (2S columns of one level) and a twiddle table in
-// LDS and transforms them with radix-4 Stockham passes (a last radix-2 pass when
-// log2 Ly is odd), in place: each pass reads all its inputs into registers, waits,
-// then writes.
-constexpr int kDstThreads = 256;
-constexpr int kDstElems = 4096;                          // complex sequence entries per workgroup
-constexpr int kDstVals = kDstElems / kDstThreads;        // per thread and pass
-
+// The transform along y has the shape of the time-axis transforms (a strided axis,
+// contiguous columns), so it runs on the same register-resident radix-16 Stockham
+// machinery: a workgroup owns W complex columns (2W real columns, one row segment of
+// 16 W bytes per row) of one level, thread (t, c) holds P points of column c, and the
+// stages exchange through LDS one real plane at a time.  Mirrored positions of the
+// extension are loaded twice (the second load hits the cache).
 bool dst_y_supported(int ny) { return ny >= 1 && ny <= 2047 && ((ny + 1) & ny) == 0; }
 
-static int dst_seqs(int nx, int ny)
-{
-    const int Ly = 2 * (ny + 1);
-    int S = kDstElems / Ly;
-    if (S > 32) S = 32;
-    const int need = (nx + 1) / 2;
-    if (S > need) S = need;
-    return S < 1 ? 1 : S;
-}
+template <int L>
+constexpr int dst_points() { return L < 16 ? L : 16; }
+// workgroup size bound: dst_cols keeps lengths up to 1024 within 512 threads
+template <int L>
+constexpr int dst_max_threads() { return L >= 2048 ? 1024 : 512; }
 
-template <int R>
-__device__ __forceinline__ void dft_small(cx<double> (&v)[R])
+template <int L>
+__global__ void __launch_bounds__(dst_max_threads<L>())
+k_dst_y(const double *in, double *out, int nx, int ny, int ell, int W,
+        const cx<double> *__restrict__ tw)
 {
-    if (R == 2) {
-        const cx<double> a = v[0], b = v[1];
-        v[0] = a + b;
-        v[1] = a - b;
-    } else {
-        // forward radix 4: factors (-i)^{rs}
-        const cx<double> t0 = v[0] + v[2], t1 = v[0] - v[2];
-        const cx<double> t2 = v[1] + v[3], t3 = v[1] - v[3];
-        v[0] = t0 + t2;
-        v[2] = t0 - t2;
-        v[1] = t1 - mul_i(t3);
-        v[3] = t1 + mul_i(t3);
-    }
-}
-
-// One Stockham pass of radix R over S sequences of length Ly held in buf, for
-// sub-transform length Ns: butterfly j (< Ly/R) of sequence s reads entries
-// j + r Ly/R, multiplies entry r by w^{r (j mod Ns) Ly/(Ns R)} (w = exp(-2 pi i/Ly)),
-// transforms them and writes entry r to (j / Ns) Ns R + (j mod Ns) + r Ns.
-template <int R>
-__device__ __forceinline__ void dst_pass(cx<double> *buf, const cx<double> *tw, int S, int Ly,
-                                         int lgLy, int Ns, int lgNs)
-{
-    constexpr int IT = kDstVals / R;   // butterflies per thread
-    const int lgnb = lgLy - (R == 4 ? 2 : 1);
-    const int nb = 1 << lgnb;
-    const int items = S << lgnb;
-    const int tws = Ly >> (lgNs + (R == 4 ? 2 : 1));
-    cx<double> v[IT][R];
-    int dst[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        const int b = threadIdx.x + it * kDstThreads;
-        dst[it] = -1;
-        if (b < items) {
-            const int s = b >> lgnb;
-            const int j = b & (nb - 1);
-            const int jm = j & (Ns - 1);
-            const cx<double> *src = buf + (size_t)s * Ly + j;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const cx<double> x = src[r * nb];
-                v[it][r] = r == 0 ? x : x * tw[r * jm * tws];
-            }
-            dft_small<R>(v[it]);
-            dst[it] = s * Ly + ((j >> lgNs) << lgNs) * R + jm;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-        if (dst[it] >= 0) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) buf[dst[it] + r * Ns] = v[it][r];
-        }
-    }
-    __syncthreads();
-}
-
-// grid (ceil(nx / 2S), ell); in == out allowed (a workgroup reads its whole tile
-// before it writes, and tiles are disjoint)
-__global__ void __launch_bounds__(kDstThreads)
-k_dst_y(const double *in, double *out, int nx, int ny, int S)
-{
+    constexpr int P = dst_points<L>();
     extern __shared__ unsigned char dsm_raw[];
-    const int Ly = 2 * (ny + 1);
-    const int lgLy = 31 - __builtin_clz(Ly);
-    cx<double> *buf = reinterpret_cast<cx<double> *>(dsm_raw);
-    cx<double> *tw = buf + (size_t)S * Ly;
-    const int t = threadIdx.x;
-    const int TX = 2 * S;
-    const int x0 = blockIdx.x * TX;
-    const size_t lvl = (size_t)blockIdx.y * ny * nx;
-
-    // the tile (ny rows of TX columns), all loads in flight before any LDS store
-    const int tot = ny * TX;
-    double val[kDstVals];
+    double *sm = reinterpret_cast<double *>(dsm_raw);
+    const int c = threadIdx.x % W;
+    const int t = threadIdx.x / W;
+    const int tiles_x = (nx + 2 * W - 1) / (2 * W);
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    const int lvl = g / tiles_x;
+    if (lvl >= ell) return;                       // padding workgroup: no barrier reached
+    const int x0 = (g - lvl * tiles_x) * 2 * W + 2 * c;
+    const bool ha = x0 < nx, hb = x0 + 1 < nx;
+    const size_t base = (size_t)lvl * ny * nx;
+    cx<double> v[P];
 #pragma unroll
-    for (int k = 0; k < kDstVals; ++k) {
-        const int e = t + k * kDstThreads;
-        const int q = e / TX, c = e - q * TX;
-        const bool ok = e < tot && x0 + c < nx;
-        val[k] = ok ? in[lvl + (size_t)q * nx + x0 + c] : 0.0;
+    for (int idx = 0; idx < P; ++idx) {
+        const int pos = first_pos<L, P>(t, idx);
+        const bool lo = pos <= ny;                 // z_pos = v_pos, else -v_{L-pos}
+        const int q = lo ? pos : L - pos;          // 1..ny for data, 0 / ny+1 for zeros
+        const bool data = q >= 1 && q <= ny;
+        const size_t o = base + (size_t)(data ? q - 1 : 0) * nx + x0;
+        const double a = (data && ha) ? in[o] : 0.0;
+        const double b = (data && hb) ? in[o + 1] : 0.0;
+        v[idx] = lo ? cx<double>{a, b} : cx<double>{-a, -b};
     }
-    for (int p = t; p < Ly; p += kDstThreads) {
-        double sn, cs;
-        sincospi(-2.0 * (double)p / (double)Ly, &sn, &cs);
-        tw[p] = {cs, sn};
-    }
-    for (int s = t; s < S; s += kDstThreads) {
-        buf[(size_t)s * Ly] = {0.0, 0.0};
-        buf[(size_t)s * Ly + ny + 1] = {0.0, 0.0};
-    }
-    double *bd = reinterpret_cast<double *>(buf);
-#pragma unroll
-    for (int k = 0; k < kDstVals; ++k) {
-        const int e = t + k * kDstThreads;
-        if (e < tot) {
-            const int q = e / TX, c = e - q * TX;
-            const size_t base = 2 * (size_t)(c >> 1) * Ly + (c & 1);
-            bd[base + 2 * (q + 1)] = val[k];
-            bd[base + 2 * (Ly - q - 1)] = -val[k];
-        }
-    }
-    __syncthreads();
-
-    int Ns = 1, lgNs = 0;
-    while (lgNs + 2 <= lgLy) {
-        dst_pass<4>(buf, tw, S, Ly, lgLy, Ns, lgNs);
-        Ns <<= 2;
-        lgNs += 2;
-    }
-    if (lgNs < lgLy) dst_pass<2>(buf, tw, S, Ly, lgLy, Ns, lgNs);
-
+    run_stages<double, L, P, 0, false>(v, sm, t, c, W, tw, 1);
+    __syncthreads();                               // in == out: every load has completed
     const double f = 0.5 * sqrt(2.0 / (ny + 1.0));
 #pragma unroll
-    for (int k = 0; k < kDstVals; ++k) {
-        const int e = t + k * kDstThreads;
-        const int q = e / TX, c = e - q * TX;
-        if (e < tot && x0 + c < nx) {
-            const cx<double> z = buf[(size_t)(c >> 1) * Ly + q + 1];
-            out[lvl + (size_t)q * nx + x0 + c] = (c & 1) ? f * z.x : -f * z.y;
+    for (int idx = 0; idx < P; ++idx) {
+        const int p = final_pos<L, P>(t, idx);
+        if (p >= 1 && p <= ny) {
+            const size_t o = base + (size_t)(p - 1) * nx + x0;
+            if (ha) out[o] = -f * v[idx].y;
+            if (hb) out[o + 1] = f * v[idx].x;
         }
     }
 }
 
-hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, hipStream_t st)
+// complex columns per workgroup: a 128-byte row segment where the thread and LDS
+// budgets allow (at most 512 threads up to length 1024, else 1024; 80 KB of LDS so
+// that two workgroups share a compute unit, else 160 KB), no wider than the grid needs
+static int dst_cols(int L, int nx)
 {
-    if (!dst_y_supported(ny) || nx < 1 || ell < 1 || ell > 65535) return hipErrorInvalidValue;
-    const int S = dst_seqs(nx, ny);
-    const int Ly = 2 * (ny + 1);
-    const size_t smem = sizeof(cx<double>) * ((size_t)S * Ly + Ly);
+    const int P = L < 16 ? L : 16;
+    const int need = (nx + 1) / 2;
+    const int maxt = L >= 2048 ? 1024 : 512;
+    int best = 1;
+    for (int W = 1; W <= 64; W *= 2) {
+        const size_t lds = (size_t)lds_rows(L) * W * sizeof(double);
+        if (W * (L / P) > maxt || lds > 160 * 1024) break;
+        if (W > 8 && lds > 80 * 1024) break;
+        best = W;
+        if (W >= need) break;
+    }
+    return best;
+}
+
+template <int L>
+static hipError_t dst_go(const double *in, double *out, int nx, int ny, int ell,
+                         const double *tw, hipStream_t st)
+{
+    const int W = dst_cols(L, nx);
+    const int threads = W * (L / dst_points<L>());
+    const size_t smem = (size_t)lds_rows(L) * W * sizeof(double);
+    auto kern = k_dst_y<L>;
     if (smem > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_dst_y,
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    dim3 grid((nx + 2 * S - 1) / (2 * S), ell);
-    k_dst_y<<<grid, kDstThreads, smem, st>>>(in, out, nx, ny, S);
+    const long long tiles = (long long)((nx + 2 * W - 1) / (2 * W)) * ell;
+    if (tiles > (1LL << 30)) return hipErrorInvalidValue;
+    kern<<<xcd_grid((int)tiles), threads, smem, st>>>(in, out, nx, ny, ell, W,
+                                                     reinterpret_cast<const cx<double> *>(tw));
     return hipGetLastError();
 }
 
+hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, const double *tw,
+                        hipStream_t st)
+{
+    if (!dst_y_supported(ny) || nx < 1 || ell < 1 || !tw) return hipErrorInvalidValue;
+    switch (2 * (ny + 1)) {
+    case 4: return dst_go<4>(in, out, nx, ny, ell, tw, st);
+    case 8: return dst_go<8>(in, out, nx, ny, ell, tw, st);
+    case 16: return dst_go<16>(in, out, nx, ny, ell, tw, st);
+    case 32: return dst_go<32>(in, out, nx, ny, ell, tw, st);
+    case 64: return dst_go<64>(in, out, nx, ny, ell, tw, st);
+    case 128: return dst_go<128>(in, out, nx, ny, ell, tw, st);
+    case 256: return dst_go<256>(in, out, nx, ny, ell, tw, st);
+    case 512: return dst_go<512>(in, out, nx, ny, ell, tw, st);
+    case 1024: return dst_go<1024>(in, out, nx, ny, ell, tw, st);
+    case 2048: return dst_go<2048>(in, out, nx, ny, ell, tw, st);
+    case 4096: return dst_go<4096>(in, out, nx, ny, ell, tw, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // ------------------------------------------------------------ Q1 stencils
-// P = M2 x and Q = K2 x at node (iy, ix) of one level:
+// M2 x and K2 x at one node of a level, with
 //   M2 = My (x) Mx:  hx hy / 36 * [1 4 1] (x) [1 4 1],
-//   K2 = Ky (x) Mx + My (x) Kx:  hx/(6 hy) [-1 2 -1]_y [1 4 1]_x + hy/(6 hx) [1 4 1]_y [-1 2 -1]_x.
-// The nine loads are issued at clamped addresses and masked.
-__device__ __forceinline__ void q1_mk(const double *__restrict__ xl, int nx, int ny, int ix,
-                                      int iy, double hx, double hy, double &P, double &Q)
+//   K2 = Ky (x) Mx + My (x) Kx:  hx/(6 hy) [-1 2 -1]_y [1 4 1]_x + hy/(6 hx) [1 4 1]_y [-1 2 -1]_x;
+// the loads are issued at clamped addresses and masked.
+
+// ------------------------------------------------------------------ matvec
+// y_k = sum_m (a_m M2 + b_m kappa K2) x_{k-m} (start-up rows and the block above the
+// diagonal through scheme_block), or the transpose y_k = sum_m A_{k+m,k} x_{k+m}
+// (every block symmetric).  A thread owns MR consecutive nodes of one x-column and
+// walks a segment of kMv2Seg time levels (upwards, or downwards for the transpose),
+// keeping M2 x and K2 x of the W levels its rows touch in registers: window slot c
+// holds level k - dir (c - up).  The MR + 2 rows of a level are loaded together (MR
+// independent outputs per step keep enough loads in flight), and the vertical stencil
+// shares them.
+constexpr int kMv2Seg = 8;
+constexpr int kMv2Rows = 4;
+
+// M2 x and K2 x at nodes (iy0 + o, ix), o < MR, of one level (Q1 stencils above)
+template <int MR>
+__device__ __forceinline__ void q1_mk_rows(const double *__restrict__ xl, int nx, int ny, int ix,
+                                           int iy0, double hx, double hy, double (&P)[MR],
+                                           double (&Q)[MR])
 {
     const int il = ix > 0 ? ix - 1 : 0, ir = ix < nx - 1 ? ix + 1 : ix;
     const double ml = ix > 0 ? 1.0 : 0.0, mr = ix < nx - 1 ? 1.0 : 0.0;
-    double mrow[3], krow[3];
+    double mrow[MR + 2], krow[MR + 2];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const int yy = iy + d - 1;
+    for (int d = 0; d < MR + 2; ++d) {
+        const int yy = iy0 + d - 1;
         const bool ok = yy >= 0 && yy < ny;
-        const double *row = xl + (size_t)(ok ? yy : iy) * nx;
+        const double *row = xl + (size_t)(ok ? yy : 0) * nx;
         const double a = ml * row[il], b = row[ix], c = mr * row[ir];
         const double w = ok ? 1.0 : 0.0;
         mrow[d] = w * (a + 4.0 * b + c);
         krow[d] = w * (2.0 * b - a - c);
     }
-    P = (hx * hy / 36.0) * (mrow[0] + 4.0 * mrow[1] + mrow[2]);
-    Q = (hx / (6.0 * hy)) * (2.0 * mrow[1] - mrow[0] - mrow[2]) +
-        (hy / (6.0 * hx)) * (krow[0] + 4.0 * krow[1] + krow[2]);
+    const double cm = hx * hy / 36.0, ck1 = hx / (6.0 * hy), ck2 = hy / (6.0 * hx);
+#pragma unroll
+    for (int o = 0; o < MR; ++o) {
+        P[o] = cm * (mrow[o] + 4.0 * mrow[o + 1] + mrow[o + 2]);
+        Q[o] = ck1 * (2.0 * mrow[o + 1] - mrow[o] - mrow[o + 2]) +
+               ck2 * (krow[o] + 4.0 * krow[o + 1] + krow[o + 2]);
+    }
 }
 
-// ------------------------------------------------------------------ matvec
-// y_k = sum_m (a_m M2 + b_m kappa K2) x_{k-m} (start-up rows and the block above the
-// diagonal through scheme_block), or the transpose y_k = sum_m A_{k+m,k} x_{k+m}
-// (every block symmetric).  A thread owns one node and walks a segment of TS time
-// levels (upwards, or downwards for the transpose), keeping M2 x and K2 x of the W
-// levels its rows touch in registers: window slot c holds level k - dir (c - up).
-constexpr int kMv2Seg = 32;
-
-template <int W>
+template <int W, int MR>
 __global__ void __launch_bounds__(256)
 k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
            int nx, int ny, int ell, Scheme sc, double kappa, int transpose)
 {
     const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int iy = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (ix >= nx || iy >= ny) return;
+    const int iy0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * MR;
+    if (ix >= nx || iy0 >= ny) return;
     const int up = sc.up;
     const int dir = transpose ? -1 : 1;
     const int kb = blockIdx.z * kMv2Seg;
@@ -238,37 +201,51 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
     const int cnt = ke - kb;
     const size_t lv = (size_t)nx * ny;
     const double hx = 1.0 / (nx + 1.0), hy = 1.0 / (ny + 1.0);
-    double P[W], Q[W];
+    double P[W][MR], Q[W][MR];
 #pragma unroll
     for (int c = 0; c < W; ++c) {
         const int L = k0 - dir * (c - up);
-        P[c] = Q[c] = 0.0;
-        if (L >= 0 && L < ell) q1_mk(x + (size_t)L * lv, nx, ny, ix, iy, hx, hy, P[c], Q[c]);
+#pragma unroll
+        for (int o = 0; o < MR; ++o) P[c][o] = Q[c][o] = 0.0;
+        if (L >= 0 && L < ell) q1_mk_rows<MR>(x + (size_t)L * lv, nx, ny, ix, iy0, hx, hy, P[c], Q[c]);
     }
-    const size_t node = (size_t)iy * nx + ix;
     for (int t = 0; t < cnt; ++t) {
         const int k = k0 + dir * t;
-        double acc = 0.0;
+        double acc[MR];
+#pragma unroll
+        for (int o = 0; o < MR; ++o) acc[o] = 0.0;
 #pragma unroll
         for (int c = 0; c < W; ++c) {
             const int m = c - up;
             const int src = transpose ? k + m : k - m;
             const int row = transpose ? src : k;
             double cm, cb;
-            if (src >= 0 && src < ell && scheme_block(sc, row, m, cm, cb))
-                acc += cm * P[c] + cb * kappa * Q[c];
+            if (src >= 0 && src < ell && scheme_block(sc, row, m, cm, cb)) {
+                const double ck = cb * kappa;
+#pragma unroll
+                for (int o = 0; o < MR; ++o) acc[o] += cm * P[c][o] + ck * Q[c][o];
+            }
         }
-        const size_t o = (size_t)k * lv + node;
-        y[o] = bsub ? bsub[o] - acc : acc;
+#pragma unroll
+        for (int o = 0; o < MR; ++o) {
+            if (iy0 + o < ny) {
+                const size_t off = (size_t)k * lv + (size_t)(iy0 + o) * nx + ix;
+                y[off] = bsub ? bsub[off] - acc[o] : acc[o];
+            }
+        }
         if (t + 1 < cnt) {
 #pragma unroll
-            for (int c = W - 1; c > 0; --c) {
-                P[c] = P[c - 1];
-                Q[c] = Q[c - 1];
-            }
+            for (int c = W - 1; c > 0; --c)
+#pragma unroll
+                for (int o = 0; o < MR; ++o) {
+                    P[c][o] = P[c - 1][o];
+                    Q[c][o] = Q[c - 1][o];
+                }
             const int L = k + dir + dir * up;
-            P[0] = Q[0] = 0.0;
-            if (L >= 0 && L < ell) q1_mk(x + (size_t)L * lv, nx, ny, ix, iy, hx, hy, P[0], Q[0]);
+#pragma unroll
+            for (int o = 0; o < MR; ++o) P[0][o] = Q[0][o] = 0.0;
+            if (L >= 0 && L < ell)
+                q1_mk_rows<MR>(x + (size_t)L * lv, nx, ny, ix, iy0, hx, hy, P[0], Q[0]);
         }
     }
 }
@@ -276,11 +253,12 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
 hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
                            int ell, Scheme sc, double kappa, int transpose, hipStream_t st)
 {
-    dim3 grid((nx + 63) / 64, (ny + 3) / 4, (ell + kMv2Seg - 1) / kMv2Seg);
+    constexpr int MR = kMv2Rows;
+    dim3 grid((nx + 63) / 64, (ny + 4 * MR - 1) / (4 * MR), (ell + kMv2Seg - 1) / kMv2Seg);
     switch (sc.s + sc.up + 1) {
-    case 2: k_matvec2d<2><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
-    case 3: k_matvec2d<3><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
-    case 4: k_matvec2d<4><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+    case 2: k_matvec2d<2, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+    case 3: k_matvec2d<3, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+    case 4: k_matvec2d<4, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -298,16 +276,16 @@ k_rhs2d(double *__restrict__ b, const double *__restrict__ u0, const double *__r
     if (ix >= nx || iy >= ny) return;
     const double hx = 1.0 / (nx + 1.0), hy = 1.0 / (ny + 1.0);
     const size_t lv = (size_t)nx * ny, node = (size_t)iy * nx + ix;
-    double Pu, Qu;
-    q1_mk(u0, nx, ny, ix, iy, hx, hy, Pu, Qu);
+    double Pu[1], Qu[1];
+    q1_mk_rows<1>(u0, nx, ny, ix, iy, hx, hy, Pu, Qu);
     int k = 1;
     if (scheme == AAO_HEAT_IE) {
-        b[node] = Pu;
+        b[node] = Pu[0];
     } else {
-        double Pv = 0.0, Qv = 0.0;
-        if (v0) q1_mk(v0, nx, ny, ix, iy, hx, hy, Pv, Qv);
-        b[node] = (Pu + tau * Pv) + tau * tau * kappa * (Qu + tau * Qv);
-        b[lv + node] = -Pu;
+        double Pv[1] = {0.0}, Qv[1] = {0.0};
+        if (v0) q1_mk_rows<1>(v0, nx, ny, ix, iy, hx, hy, Pv, Qv);
+        b[node] = (Pu[0] + tau * Pv[0]) + tau * tau * kappa * (Qu[0] + tau * Qv[0]);
+        b[lv + node] = -Pu[0];
         k = 2;
     }
     for (; k < ell; ++k) b[(size_t)k * lv + node] = 0.0;

@@ -134,3 +134,36 @@ def heat_adjoint(n=2047, ell=2048):
                  amps + da, restart=30, tol=1e-10)
     w.extra = dict(target_amps=amps, target_kappa=1.0)
     return w
+
+
+@dataclass
+class SquareWorkload:
+    name: str
+    scheme: int
+    nx: int
+    ny: int
+    ell: int
+    tau: float
+    kappa: float
+    u0: np.ndarray                        # (ny, nx) nodal values, x fastest
+    restart: int = 30
+    tol: float = 1e-8
+    maxit: int = 300
+
+
+def square_heat(nx=511, ny=511, ell=64):
+    """Heat on the unit square, nx x ny interior nodes (511 x 511, 16.7 M unknowns with
+    64 steps: the unknown count of the 1D n = 4095, ell = 4096 case), tau = 1/ell,
+    kappa = 1; u_0 the nodal values of sin(pi x) sin(pi y) plus an 8 x 8 series of sine
+    products with N(0, 0.1^2) amplitudes; GMRES(30) at 1e-8."""
+    rng = np.random.default_rng([6, 0])
+    a = rng.normal(0.0, 0.1, size=(8, 8))
+    a[0, 0] += 1.0
+    x = np.arange(1, nx + 1) / (nx + 1)
+    y = np.arange(1, ny + 1) / (ny + 1)
+    m = np.arange(1, 9)
+    sx = np.sin(np.pi * np.outer(m, x))       # (8, nx)
+    sy = np.sin(np.pi * np.outer(m, y))       # (8, ny)
+    u0 = sy.T @ a @ sx                        # a[q, p] sin(q pi y) sin(p pi x)
+    return SquareWorkload(f"square_heat_{nx}x{ny}_l{ell}", HEAT, nx, ny, ell, 1.0 / ell, 1.0,
+                          np.ascontiguousarray(u0))
