@@ -372,10 +372,9 @@ k_batch_solve(const BProb *__restrict__ probs, const int2 *__restrict__ rows, in
     const double h = 1.0 / (n + 1.0), kap = pb.kappa;
     const cx<A> d = {A(ar * (4.0 * h / 6.0) + br * kap * (2.0 / h)), A(ai * (4.0 * h / 6.0) + bi * kap * (2.0 / h))};
     const cx<A> ee = {A(ar * (h / 6.0) - br * kap / h), A(ai * (h / 6.0) - bi * kap / h)};
-    constexpr int PAD = sizeof(cx<SI>) == 16 ? 2 : 4;
-    constexpr int OPAD = sizeof(cx<SO>) == 16 ? 2 : 4;
-    const int NTP = NT + PAD;
-    const int ONTP = NT + OPAD;
+    // odd row pitch: the chunk-wise and the coalesced accesses both spread over all banks
+    const int NTP = NT + 1;
+    const int ONTP = NT + 1;
     const int P = (n + CW - 1) / CW;
     const int len = (t < P) ? min(CW, n - t * CW) : 0;
     {

@@ -26,7 +26,7 @@ namespace aao {
 // global accesses are coalesced, half a row at a time (the chunks of the first
 // NT/2 threads, then the rest), so that the staging area is no larger than the
 // reduced-system area it aliases.  Element i of chunk t of a half sits in slot
-// i*(NT/2+PAD) + t, PAD = 2 for 16-byte and 4 for 8-byte elements, which spreads
+// i*(NT/2+PAD) + t, PAD = 1 (an odd row pitch), which spreads
 // both the chunk-wise and the coalesced accesses over all banks.  Otherwise every
 // thread reads and writes its own chunk directly.
 // The right-hand sides are read from `in` (element type SI) and the solutions written
@@ -58,8 +58,8 @@ k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__r
     const int P = (n + CW - 1) / CW;
     const int a0 = t * CW;
     const int len = (t < P) ? min(CW, n - a0) : 0;
-    constexpr int PAD = sizeof(cx<SI>) == 16 ? 2 : 4;
-    constexpr int OPAD = sizeof(cx<SO>) == 16 ? 2 : 4;
+    constexpr int PAD = 1;
+    constexpr int OPAD = 1;
     const int NH = NT / 2;                       // threads per staged half
     const int NTP = NH + PAD;
     const int ONTP = NH + OPAD;
@@ -71,19 +71,21 @@ k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__r
     for (int i = 0; i < CW; ++i) y[i] = {A(0), A(0)};
     if (STAGE) {
         // H / NT = CW / 2 elements per thread and half, loaded together (unconditional
-        // at a clamped index; a guarded load per element would be waited for in turn)
+        // at a clamped index; a guarded load per element would be waited for in turn).
+        // The second half's loads are issued as soon as the first half sits in LDS (into
+        // the same registers), so they are in flight while the first half is read.
         constexpr int KH = CW >= 2 ? CW / 2 : 1;
-        for (int half = 0; half < 2; ++half) {
-            const int q0 = half * H;
-            const int q1 = min(n, q0 + H);
-            SI lx[KH], ly[KH];   // separate parts: a whole-struct array would live in scratch
+        SI lx[KH], ly[KH];   // separate parts: a whole-struct array would live in scratch
+        auto load_half = [&](int q0) {
 #pragma unroll
             for (int k = 0; k < KH; ++k) {
                 const cx<SI> v = row[min(q0 + t + k * NT, n - 1)];
                 lx[k] = v.x;
                 ly[k] = v.y;
             }
-            if (half == 1) __syncthreads();      // the first half has been read
+        };
+        auto stage_half = [&](int q0) {
+            const int q1 = min(n, q0 + H);
 #pragma unroll
             for (int k = 0; k < KH; ++k) {
                 const int q = q0 + t + k * NT;
@@ -92,16 +94,24 @@ k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__r
                     stage[(ql % CW) * NTP + ql / CW] = {lx[k], ly[k]};
                 }
             }
-            __syncthreads();
-            if (mine == half) {
+        };
+        auto read_half = [&]() {
 #pragma unroll
-                for (int i = 0; i < CW; ++i)
-                    if (i < len) {
-                        const cx<SI> v = stage[i * NTP + tl];
-                        y[i] = {A(v.x), A(v.y)};
-                    }
-            }
-        }
+            for (int i = 0; i < CW; ++i)
+                if (i < len) {
+                    const cx<SI> v = stage[i * NTP + tl];
+                    y[i] = {A(v.x), A(v.y)};
+                }
+        };
+        load_half(0);
+        stage_half(0);
+        load_half(H);
+        __syncthreads();
+        if (mine == 0) read_half();
+        __syncthreads();                         // the first half has been read
+        stage_half(H);
+        __syncthreads();
+        if (mine == 1) read_half();
         // partition_solve's first barrier precedes its first write to the area
     } else {
 #pragma unroll
@@ -199,7 +209,7 @@ int solve_default_config(int n)
 template <typename S>
 static constexpr size_t stage_bytes(int cw, int nt)
 {
-    return sizeof(cx<S>) * (size_t)cw * (nt / 2 + (sizeof(cx<S>) == 16 ? 2 : 4));
+    return sizeof(cx<S>) * (size_t)cw * (nt / 2 + 1);
 }
 
 template <typename A, typename SI, typename SO, int CW, int NT, bool STAGE>
