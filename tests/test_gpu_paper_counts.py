@@ -1,7 +1,8 @@
 """The paper-table regression suite on the GPU path: every printed GMRES iteration
 count of Tables 1, 3(a), 4 and 5 (tolerance 1e-5; fixture tests/golden/
 paper_iteration_counts.txt) is reproduced by the library's right-preconditioned
-FGMRES from x0 = 0.
+FGMRES from x0 = 0, and by the library's operators in the paper's left-preconditioned
+form.
 
 The paper uses left preconditioning and does not state its norm or counting
 convention, so each count is compared within the slack of the oracle's own
@@ -40,6 +41,34 @@ def test_gpu_iteration_counts(orc, row):
           f"oracle (right) {io['iters']}, true residual {res:.1e}")
     assert info["status"] == 0 and res <= 1e-5
     assert abs(info["iters"] - io["iters"]) <= 1
+    assert abs(info["iters"] - printed) <= SLACK.get((scheme_name, data, n, ell), 1)
+    P.close()
+
+
+@pytest.mark.parametrize("row", rows(), ids=lambda r: f"{r[0]}-{r[1]}-{r[2]}x{r[3]}")
+def test_gpu_operators_left_counts(orc, row):
+    """The paper's own form on the GPU operators: the library's matvec and C^{-1} inside
+    left-preconditioned GMRES (C^{-1} A U = C^{-1} b from 0, relative 1e-5, counted in
+    preconditioner applies after the initial one) give the oracle's left-preconditioned
+    count and stay within the printed count's slack."""
+    import torch
+    from test_oracle_paper_tables import initial
+    from paper_1810_00615_amd import Problem
+    scheme_name, data, n, ell, printed = row
+    scheme = 0 if scheme_name == "heat" else 1
+    tau = 1.0 / ell
+    P = Problem(n, ell, scheme="heat" if scheme == 0 else "bd2", kappa=1.0)
+    to = lambda v: torch.as_tensor(np.ascontiguousarray(v).reshape(ell, n), device="cuda")
+    op = lambda v: P.Pinv(P.A(to(v))).cpu().numpy().ravel()
+    b = orc.build_rhs(scheme, n, ell, tau, 1.0, initial(data, n)).ravel()
+    bp = P.Pinv(to(b)).cpu().numpy().ravel()
+    x, info = orc.fgmres(op, lambda v: v, bp, restart=100, tol=1e-5, maxit=100)
+    opo = lambda v: orc.pinv(scheme, n, ell, tau, 1.0, orc.apply_A(scheme, n, ell, tau, 1.0, v)).ravel()
+    bpo = orc.pinv(scheme, n, ell, tau, 1.0, b).ravel()
+    xo, io = orc.fgmres(opo, lambda v: v, bpo, restart=100, tol=1e-5, maxit=100)
+    print(f"{scheme_name} {data} n={n} ell={ell}: printed {printed}, GPU operators (left) "
+          f"{info['iters']}, oracle (left) {io['iters']}")
+    assert info["converged"] and info["iters"] == io["iters"]
     assert abs(info["iters"] - printed) <= SLACK.get((scheme_name, data, n, ell), 1)
     P.close()
 
