@@ -218,3 +218,64 @@ def test_heat_2d_large_closed_form(dev):
     assert e < 1e-8 and worst < 1e-7
     del U, b
     torch.cuda.empty_cache()
+
+
+def test_bd2_2d_large_closed_form(dev):
+    """BD2 on a 255 x 255 grid, 128 steps (8.3M unknowns) from sine-product u0 and v0:
+    per mode (p, q) the system is the scalar BD2 recursion with lambda_pq = lambda^x_p +
+    lambda^y_q, c_k = rho^k (c_0 cos k phi + B sin k phi) (rho = (1 + tau^2 kappa
+    lambda)^(-1/2), phi = atan(tau sqrt(kappa lambda)), c_1 = c_0 + tau d_0) -- checked
+    at every time level."""
+    from paper_1810_00615_amd import Problem2D
+    nx = ny = 255
+    ell, kappa = 128, 1.0
+    tau = 1.0 / ell
+
+    def sines(n, m):
+        return np.sin(np.pi * m * np.arange(1, n + 1) / (n + 1))
+
+    def lam1(n, m):
+        h = 1.0 / (n + 1)
+        c = np.cos(np.pi * m * h)
+        return 6.0 * (1.0 - c) / (h * h * (2.0 + c))
+    umodes = [(1, 1, 1.0), (2, 3, 0.5), (5, 4, -0.25)]
+    vmodes = [(1, 1, 0.3), (3, 2, -0.2)]
+    u0 = sum(a * np.outer(sines(ny, q), sines(nx, p)) for p, q, a in umodes)
+    v0 = sum(a * np.outer(sines(ny, q), sines(nx, p)) for p, q, a in vmodes)
+    P = Problem2D(nx, ny, ell, tau, "bd2", kappa=kappa, device=dev)
+    b = P.rhs(td(dev, u0), td(dev, v0))
+    U, info = P.solve(b, restart=30, tol=1e-11, maxit=200)
+    assert info["converged"], info
+    Ug = U.cpu().numpy()
+    Ur = np.zeros((ell, ny, nx))
+    for (p, q) in {(p, q) for p, q, _ in umodes} | {(p, q) for p, q, _ in vmodes}:
+        c0 = sum(a for pp, qq, a in umodes if (pp, qq) == (p, q))
+        d0 = sum(a for pp, qq, a in vmodes if (pp, qq) == (p, q))
+        lm = lam1(nx, p) + lam1(ny, q)
+        rho = 1.0 / np.sqrt(1.0 + tau * tau * kappa * lm)
+        phi = np.arctan(tau * np.sqrt(kappa * lm))
+        B = ((c0 + tau * d0) / rho - c0 * np.cos(phi)) / np.sin(phi)
+        shape = np.outer(sines(ny, q), sines(nx, p))
+        for k in range(1, ell + 1):
+            Ur[k - 1] += rho ** k * (c0 * np.cos(k * phi) + B * np.sin(k * phi)) * shape
+    e = normrel(Ug, Ur)
+    worst = max(normrel(Ug[k], Ur[k]) for k in range(ell))
+    print(f"bd2 2d 255x255x128: {info['iters']} iterations, error {e:.2e}, worst level {worst:.2e}")
+    assert e < 1e-8 and worst < 1e-7
+
+
+@pytest.mark.parametrize("ny", [1, 2047])
+def test_pinv_2d_sine_length_extremes(dev, ny):
+    """The sine transform at its shortest (ny = 1) and longest (ny = 2047, odd extension of
+    length 4096) lengths, with a ragged column tile, against the eigen-decomposition."""
+    import pins
+    from paper_1810_00615_amd import Problem2D
+    nx, ell = 5, 8
+    tau = 1.0 / ell
+    r = np.random.default_rng([5, ny]).standard_normal((ell, ny, nx))
+    P = Problem2D(nx, ny, ell, tau, "heat", device=dev)
+    z = P.Pinv(td(dev, r)).cpu().numpy()
+    e = normrel(z, pins.pinv_spectral2(0, nx, ny, ell, tau, 1.0, r))
+    tol = max(1e-12, 8 * EPS * pins.cond_C2(0, nx, ny, ell, tau, 1.0))
+    print(f"heat 2d pinv {nx}x{ny} ell={ell}: {e:.2e} (tol {tol:.2e})")
+    assert e < tol
