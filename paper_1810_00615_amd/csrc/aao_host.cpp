@@ -694,8 +694,18 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     const int mcfg = ctx->cf(AAO_CFG_MATVEC);
     // the Toeplitz matvec also forms the first Gram-Schmidt dots and residual norms;
     // the start-up-row and two-sided schemes take a plain matvec and separate passes
-    const bool fused = matvec_blocks(n, ell, mcfg) <= ldp && !scheme_generic(ctx->sc) &&
-                       ctx->ny == 0;
+    // (on the unit square the Q1 matvec forms them for every scheme)
+    const bool sq = ctx->ny > 0;
+    const int mvb = sq ? matvec2d_blocks(ctx->nx, ctx->ny, ell, true) : matvec_blocks(n, ell, mcfg);
+    const bool fused = mvb <= ldp && (sq || !scheme_generic(ctx->sc));
+    // a matvec that also forms the partials of L_q . y (q < cnt; see launch_matvec)
+    auto mv_dots = [&](const double *xin, double *out, const double *bs, const VecList *L,
+                       int cnt) -> hipError_t {
+        return sq ? launch_matvec2d(xin, out, bs, ctx->nx, ctx->ny, ell, ctx->sc, ctx->kappa,
+                                    transpose, st, L, cnt, ctx->part, ldp)
+                  : launch_matvec(xin, out, bs, n, ell, ctx->sc, ctx->kappa, ctx->tauk,
+                                  transpose, st, mcfg, L, cnt, ctx->part, ldp);
+    };
     auto residual = [&](bool store) -> aao_status {
         // V_0 = b - A x, vs_0 = 1/||V_0|| (the norm formed by the same launch); with
         // store false only the norm (the check after a cycle, before a restart is
@@ -706,10 +716,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             VecList self{};
             self.p[0] = out;
             AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (store ? 3 : 2),
-                         launch_matvec(x, out, b, n, ell, ctx->sc, ctx->kappa,
-                                       ctx->tauk, transpose, st, mcfg, &self, 1, ctx->part,
-                                       ldp));
-            return small(3, 0, matvec_blocks(n, ell, mcfg));
+                         mv_dots(x, out, b, &self, 1));
+            return small(3, 0, mvb);
         }
         AAO_TRY(apply_A_impl(ctx, x, V0, b, transpose));
         AAO_HIP(launch_dot1_parts(V0, V0, N, ctx->part, st));
@@ -807,9 +815,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                                 (early_always || est_prev * (est_prev / est_prev2) <= tol);
             if (fused) {
                 AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (expect ? 1 + nv : 2 + nv),
-                             launch_matvec(Zj, expect ? nullptr : ctx->W, nullptr, n, ell,
-                                           ctx->sc, ctx->kappa, ctx->tauk, transpose, st, mcfg,
-                                           &Vl, nv, ctx->part, ldp));
+                             mv_dots(Zj, expect ? nullptr : ctx->W, nullptr, &Vl, nv));
             } else {
                 AAO_TRY(apply_A_impl(ctx, Zj, ctx->W, nullptr, transpose));
                 AAO_LAUNCH_B(AAO_K_CGS_DOT, vec_bytes(ctx) * (nv + 1),
@@ -820,7 +826,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 // CGS2 with the re-orthogonalisation of v_j deferred to this step: one
                 // pass writes the final v_j and the once-projected w1 (the next pending
                 // vector) and forms the dots that re-orthogonalise w1 in the next step
-                AAO_TRY(small(5, nv, fused ? matvec_blocks(n, ell, mcfg) : nb));
+                AAO_TRY(small(5, nv, fused ? mvb : nb));
                 // When the estimates so far predict convergence at this step, look
                 // first: with |w1|^2 = |w|^2 - |h|^2 the column is known without the
                 // update pass, and if its estimate meets tol the update (whose vectors
@@ -846,9 +852,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                 }
                 if (!provisional) {
                     if (expect)   // w was not stored by the first pass
-                        AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * 2,
-                                     launch_matvec(Zj, ctx->W, nullptr, n, ell, ctx->sc,
-                                                   ctx->kappa, ctx->tauk, transpose, st, mcfg));
+                        AAO_TRY(apply_A_impl(ctx, Zj, ctx->W, nullptr, transpose));
                     AAO_LAUNCH_B(AAO_K_ARNOLDI_UPDATE, vec_bytes(ctx) * (nv + (j > 0 ? 3 : 2)),
                                  launch_arnoldi_update(Vl, nv, ctx->W, ctx->scv(), ctx->scw(),
                                                        j > 0 ? ctx->V + N * j : nullptr, Vn, N,
@@ -865,7 +869,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
                     }
                 }
             } else {
-                AAO_TRY(small(0, nv, fused ? matvec_blocks(n, ell, mcfg) : nb));
+                AAO_TRY(small(0, nv, fused ? mvb : nb));
                 // CGS2: re-project, form the new (unnormalised) basis vector and its norm
                 AAO_LAUNCH_B(AAO_K_CGS_UPDATE_DOT, vec_bytes(ctx) * (nv + 1),
                              launch_update_dot(Vl, nv, ctx->W, ctx->sc_(), N, ctx->part, ldp,
@@ -942,7 +946,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             y[i] = s / H[(size_t)i * m + i];
             yc.v[i] = y[i];
         }
-        if (x_zero && fused && matvec_comb_ok(mcfg, k)) {
+        if (x_zero && fused && (sq ? k >= 1 && k <= 4 : matvec_comb_ok(mcfg, k))) {
             // x = Z y formed inside the residual-check launch (x is not read, so no
             // block reads rows another one writes): one pass over Z, b and x
             MatvecComb cb{};
@@ -952,9 +956,12 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             }
             cb.xout = x;
             AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (k + 2),
-                         launch_matvec_comb(cb, k, b, n, ell, ctx->sc, ctx->kappa, ctx->tauk,
-                                            transpose, st, mcfg, ctx->part, ldp));
-            AAO_TRY(small(3, 0, matvec_blocks(n, ell, mcfg)));
+                         sq ? launch_matvec2d_comb(cb, k, b, ctx->nx, ctx->ny, ell, ctx->sc,
+                                                   ctx->kappa, transpose, st, ctx->part, ldp)
+                            : launch_matvec_comb(cb, k, b, n, ell, ctx->sc, ctx->kappa,
+                                                 ctx->tauk, transpose, st, mcfg, ctx->part,
+                                                 ldp));
+            AAO_TRY(small(3, 0, mvb));
         } else {
             AAO_LAUNCH_B(AAO_K_AXPY, vec_bytes(ctx) * (k + (x_zero ? 1 : 2)),
                          launch_multi_axpy(Zl, k, yc, x, N, !x_zero, st));

@@ -268,9 +268,20 @@ bool dst_y_supported(int ny);
 hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, const double *tw,
                         hipStream_t st);
 // y = A x (A^T x with transpose), y = bsub - A x if bsub, for the Q1 blocks
-// a_m M2 + b_m kappa K2 (M2 = My (x) Mx, K2 = Ky (x) Mx + My (x) Kx).
+// a_m M2 + b_m kappa K2 (M2 = My (x) Mx, K2 = Ky (x) Mx + My (x) Kx).  With nv > 0 the
+// launch also leaves the block partials of V_q . y (q < nv) and of y . y (value nv);
+// nv == 1 with V->p[0] == y only those of y . y (value 0); y may then be null.
+// matvec2d_blocks(..., true) partials per value.
 hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
-                           int ell, Scheme sc, double kappa, int transpose, hipStream_t st);
+                           int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
+                           const VecList *V = nullptr, int nv = 0, double *part = nullptr,
+                           int ldp = 0);
+// The residual check of a solution update (as launch_matvec_comb): x = sum_{q<nz}
+// c_q z_q formed on the fly and written to cb.xout, partials of |bsub - A x|^2.
+hipError_t launch_matvec2d_comb(const MatvecComb &cb, int nz, const double *bsub, int nx, int ny,
+                                int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
+                                double *part, int ldp);
+int matvec2d_blocks(int nx, int ny, int ell, bool dots);
 // Right-hand side of the heat and BD2 systems on the unit square.
 hipError_t launch_build_rhs2d(double *b, const double *u0, const double *v0, int nx, int ny,
                               int ell, Scheme sc, double kappa, double tau, hipStream_t st);

@@ -148,33 +148,71 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
 // ------------------------------------------------------------------ matvec
 // y_k = sum_m (a_m M2 + b_m kappa K2) x_{k-m} (start-up rows and the block above the
 // diagonal through scheme_block), or the transpose y_k = sum_m A_{k+m,k} x_{k+m}
-// (every block symmetric).  A thread owns MR consecutive nodes of one x-column and
-// walks a segment of kMv2Seg time levels (upwards, or downwards for the transpose),
-// keeping M2 x and K2 x of the W levels its rows touch in registers: window slot c
-// holds level k - dir (c - up).  The MR + 2 rows of a level are loaded together (MR
-// independent outputs per step keep enough loads in flight), and the vertical stencil
-// shares them.
+// (every block symmetric); y = bsub - A x if bsub.  A thread owns MR consecutive
+// nodes of one x-column and walks a segment of kMv2Seg time levels (upwards, or
+// downwards for the transpose), keeping M2 x and K2 x of the W levels its rows touch
+// in registers: window slot c holds level k - dir (c - up).  The MR + 2 rows of a
+// level are loaded together (MR independent outputs per step keep enough loads in
+// flight), and the vertical stencil shares them.
+//
+// The GMRES forms of the launch (as in one dimension): DOTS = 1 also leaves the block
+// partials of V_q . y (q < nv) and of y . y (value nv), the first Gram-Schmidt pass;
+// DOTS = 2 the partial of y . y only (a residual norm); with NZ > 0 the input is
+// x = sum_{q<NZ} c_q z_q, formed on the fly and stored to cb.xout for the nodes and
+// levels the thread owns.  Partials are value-major, part[q ldp + block].
 constexpr int kMv2Seg = 8;
-constexpr int kMv2Rows = 4;
+constexpr int kMv2Rows = 4;     // plain launch
+constexpr int kMv2RowsDot = 2;  // launches with dot products (the outputs stay in registers)
 
-// M2 x and K2 x at nodes (iy0 + o, ix), o < MR, of one level (Q1 stencils above)
-template <int MR>
-__device__ __forceinline__ void q1_mk_rows(const double *__restrict__ xl, int nx, int ny, int ix,
-                                           int iy0, double hx, double hy, double (&P)[MR],
-                                           double (&Q)[MR])
+int matvec2d_blocks(int nx, int ny, int ell, bool dots)
+{
+    const int mr = dots ? kMv2RowsDot : kMv2Rows;
+    return ((nx + 63) / 64) * ((ny + 4 * mr - 1) / (4 * mr)) * ((ell + kMv2Seg - 1) / kMv2Seg);
+}
+
+// the (MR + 2) x 3 neighbourhood of nodes (iy0 + o, ix), o < MR, of level L of x
+// (NZ = 0) or of sum_q c_q z_q; loads at clamped addresses, masked
+template <int MR, int NZ>
+__device__ __forceinline__ void q1_load(const double *__restrict__ x, const MatvecComb &cb,
+                                        size_t lofs, int nx, int ny, int ix, int iy0,
+                                        double (&v)[MR + 2][3])
 {
     const int il = ix > 0 ? ix - 1 : 0, ir = ix < nx - 1 ? ix + 1 : ix;
     const double ml = ix > 0 ? 1.0 : 0.0, mr = ix < nx - 1 ? 1.0 : 0.0;
-    double mrow[MR + 2], krow[MR + 2];
 #pragma unroll
     for (int d = 0; d < MR + 2; ++d) {
         const int yy = iy0 + d - 1;
-        const bool ok = yy >= 0 && yy < ny;
-        const double *row = xl + (size_t)(ok ? yy : 0) * nx;
-        const double a = ml * row[il], b = row[ix], c = mr * row[ir];
-        const double w = ok ? 1.0 : 0.0;
-        mrow[d] = w * (a + 4.0 * b + c);
-        krow[d] = w * (2.0 * b - a - c);
+        const double w = (yy >= 0 && yy < ny) ? 1.0 : 0.0;
+        const size_t ro = lofs + (size_t)((yy >= 0 && yy < ny) ? yy : 0) * nx;
+        if (NZ == 0) {
+            v[d][0] = w * ml * x[ro + il];
+            v[d][1] = w * x[ro + ix];
+            v[d][2] = w * mr * x[ro + ir];
+        } else {
+            double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+            for (int q = 0; q < NZ; ++q) {
+                a += cb.c[q] * cb.z[q][ro + il];
+                b += cb.c[q] * cb.z[q][ro + ix];
+                c += cb.c[q] * cb.z[q][ro + ir];
+            }
+            v[d][0] = w * ml * a;
+            v[d][1] = w * b;
+            v[d][2] = w * mr * c;
+        }
+    }
+}
+
+// M2 x and K2 x at the MR nodes from their neighbourhood (Q1 stencils above)
+template <int MR>
+__device__ __forceinline__ void q1_apply(const double (&v)[MR + 2][3], double hx, double hy,
+                                         double (&P)[MR], double (&Q)[MR])
+{
+    double mrow[MR + 2], krow[MR + 2];
+#pragma unroll
+    for (int d = 0; d < MR + 2; ++d) {
+        mrow[d] = v[d][0] + 4.0 * v[d][1] + v[d][2];
+        krow[d] = 2.0 * v[d][1] - v[d][0] - v[d][2];
     }
     const double cm = hx * hy / 36.0, ck1 = hx / (6.0 * hy), ck2 = hy / (6.0 * hx);
 #pragma unroll
@@ -185,14 +223,40 @@ __device__ __forceinline__ void q1_mk_rows(const double *__restrict__ xl, int nx
     }
 }
 
-template <int W, int MR>
+// M2 x and K2 x at nodes (iy0 + o, ix), o < MR, of one level of x
+template <int MR>
+__device__ __forceinline__ void q1_mk_rows(const double *__restrict__ xl, int nx, int ny, int ix,
+                                           int iy0, double hx, double hy, double (&P)[MR],
+                                           double (&Q)[MR])
+{
+    double v[MR + 2][3];
+    q1_load<MR, 0>(xl, MatvecComb{}, 0, nx, ny, ix, iy0, v);
+    q1_apply<MR>(v, hx, hy, P, Q);
+}
+
+// sum over the workgroup of one value per thread, fixed order (4 waves); every thread
+// gets the sum
+__device__ __forceinline__ double block_sum4(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double s = ((red[0] + red[1]) + red[2]) + red[3];
+    __syncthreads();
+    return s;
+}
+
+template <int W, int MR, int DOTS, int NZ>
 __global__ void __launch_bounds__(256)
 k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
-           int nx, int ny, int ell, Scheme sc, double kappa, int transpose)
+           int nx, int ny, int ell, Scheme sc, double kappa, int transpose, VecList V, int nv,
+           double *__restrict__ part, int ldp, MatvecComb cb)
 {
     const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
     const int iy0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * MR;
-    if (ix >= nx || iy0 >= ny) return;
+    const bool live = ix < nx && iy0 < ny;
+    if (DOTS == 0 && !live) return;       // (the dot forms keep every thread for the sums)
     const int up = sc.up;
     const int dir = transpose ? -1 : 1;
     const int kb = blockIdx.z * kMv2Seg;
@@ -202,14 +266,33 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
     const size_t lv = (size_t)nx * ny;
     const double hx = 1.0 / (nx + 1.0), hy = 1.0 / (ny + 1.0);
     double P[W][MR], Q[W][MR];
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-        const int L = k0 - dir * (c - up);
+    double C[NZ > 0 ? W : 1][MR];          // centre values of x (stored to cb.xout)
+    auto fill = [&](int c, int L) {
 #pragma unroll
         for (int o = 0; o < MR; ++o) P[c][o] = Q[c][o] = 0.0;
-        if (L >= 0 && L < ell) q1_mk_rows<MR>(x + (size_t)L * lv, nx, ny, ix, iy0, hx, hy, P[c], Q[c]);
-    }
-    for (int t = 0; t < cnt; ++t) {
+        if (NZ > 0) {
+#pragma unroll
+            for (int o = 0; o < MR; ++o) C[NZ > 0 ? c : 0][o] = 0.0;
+        }
+        if (live && L >= 0 && L < ell) {
+            double v[MR + 2][3];
+            q1_load<MR, NZ>(x, cb, (size_t)L * lv, nx, ny, ix, iy0, v);
+            q1_apply<MR>(v, hx, hy, P[c], Q[c]);
+            if (NZ > 0) {
+#pragma unroll
+                for (int o = 0; o < MR; ++o) C[NZ > 0 ? c : 0][o] = v[o + 1][1];
+            }
+        }
+    };
+#pragma unroll
+    for (int c = 0; c < W; ++c) fill(c, k0 - dir * (c - up));
+    double yv[DOTS > 0 ? kMv2Seg : 1][MR];   // the outputs (zero past the segment's end)
+#pragma unroll
+    for (int t = 0; t < (DOTS > 0 ? kMv2Seg : 1); ++t)
+#pragma unroll
+        for (int o = 0; o < MR; ++o) yv[t][o] = 0.0;
+    for (int t = 0; t < kMv2Seg; ++t) {
+        if (t >= cnt) break;
         const int k = k0 + dir * t;
         double acc[MR];
 #pragma unroll
@@ -219,19 +302,25 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
             const int m = c - up;
             const int src = transpose ? k + m : k - m;
             const int row = transpose ? src : k;
-            double cm, cb;
-            if (src >= 0 && src < ell && scheme_block(sc, row, m, cm, cb)) {
-                const double ck = cb * kappa;
+            double cm, cb2;
+            if (src >= 0 && src < ell && scheme_block(sc, row, m, cm, cb2)) {
+                const double ck = cb2 * kappa;
 #pragma unroll
                 for (int o = 0; o < MR; ++o) acc[o] += cm * P[c][o] + ck * Q[c][o];
             }
         }
 #pragma unroll
         for (int o = 0; o < MR; ++o) {
-            if (iy0 + o < ny) {
-                const size_t off = (size_t)k * lv + (size_t)(iy0 + o) * nx + ix;
-                y[off] = bsub ? bsub[off] - acc[o] : acc[o];
+            const bool own = live && iy0 + o < ny;
+            const size_t off = (size_t)k * lv + (size_t)(own ? iy0 + o : 0) * nx + ix;
+            const double out = bsub ? (own ? bsub[off] : 0.0) - acc[o] : acc[o];
+            if (DOTS > 0) {
+#pragma unroll
+                for (int tt = 0; tt < kMv2Seg; ++tt)
+                    if (tt == t) yv[DOTS > 0 ? tt : 0][o] = own ? out : 0.0;
             }
+            if (own && y) y[off] = out;
+            if (NZ > 0 && own) cb.xout[off] = C[NZ > 0 ? up : 0][o];
         }
         if (t + 1 < cnt) {
 #pragma unroll
@@ -240,28 +329,93 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
                 for (int o = 0; o < MR; ++o) {
                     P[c][o] = P[c - 1][o];
                     Q[c][o] = Q[c - 1][o];
+                    if (NZ > 0) C[NZ > 0 ? c : 0][o] = C[NZ > 0 ? c - 1 : 0][o];
                 }
-            const int L = k + dir + dir * up;
-#pragma unroll
-            for (int o = 0; o < MR; ++o) P[0][o] = Q[0][o] = 0.0;
-            if (L >= 0 && L < ell)
-                q1_mk_rows<MR>(x + (size_t)L * lv, nx, ny, ix, iy0, hx, hy, P[0], Q[0]);
+            fill(0, k + dir + dir * up);
         }
     }
+    if (DOTS == 0) return;
+    __shared__ double red[4];
+    const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    double yy = 0.0;
+#pragma unroll
+    for (int t = 0; t < kMv2Seg; ++t)
+#pragma unroll
+        for (int o = 0; o < MR; ++o) yy += yv[DOTS > 0 ? t : 0][o] * yv[DOTS > 0 ? t : 0][o];
+    if (DOTS == 2) {
+        const double s = block_sum4(yy, red);
+        if (threadIdx.x == 0) part[blk] = s;
+        return;
+    }
+    // V_q . y over this block's tile, one basis vector at a time
+    for (int q = 0; q < nv; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < kMv2Seg; ++t) {
+            const int k = k0 + dir * t;
+#pragma unroll
+            for (int o = 0; o < MR; ++o) {
+                const bool own = live && t < cnt && iy0 + o < ny;
+                const size_t off = (size_t)(own ? k : 0) * lv + (size_t)(own ? iy0 + o : 0) * nx + ix;
+                a += own ? V.p[q][off] * yv[DOTS > 0 ? t : 0][o] : 0.0;
+            }
+        }
+        const double s = block_sum4(a, red);
+        if (threadIdx.x == 0) part[(size_t)q * ldp + blk] = s;
+    }
+    const double s = block_sum4(yy, red);
+    if (threadIdx.x == 0) part[(size_t)nv * ldp + blk] = s;
 }
 
-hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
-                           int ell, Scheme sc, double kappa, int transpose, hipStream_t st)
+template <int DOTS, int NZ>
+static hipError_t matvec2d_go(const double *x, double *y, const double *bsub, int nx, int ny,
+                              int ell, Scheme sc, double kappa, int transpose, const VecList &V,
+                              int nv, double *part, int ldp, const MatvecComb &cb, hipStream_t st)
 {
-    constexpr int MR = kMv2Rows;
+    constexpr int MR = DOTS > 0 ? kMv2RowsDot : kMv2Rows;
     dim3 grid((nx + 63) / 64, (ny + 4 * MR - 1) / (4 * MR), (ell + kMv2Seg - 1) / kMv2Seg);
     switch (sc.s + sc.up + 1) {
-    case 2: k_matvec2d<2, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
-    case 3: k_matvec2d<3, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
-    case 4: k_matvec2d<4, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+    case 2: k_matvec2d<2, MR, DOTS, NZ><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp, cb); break;
+    case 3: k_matvec2d<3, MR, DOTS, NZ><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp, cb); break;
+    case 4: k_matvec2d<4, MR, DOTS, NZ><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp, cb); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
+                           int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
+                           const VecList *V, int nv, double *part, int ldp)
+{
+    static const VecList none{};
+    if (nv > 0) {
+        if (!V || !part || nv >= kMaxVecs || matvec2d_blocks(nx, ny, ell, true) > ldp)
+            return hipErrorInvalidValue;
+        // a one-entry list equal to the output selects the self-norm only
+        if (nv == 1 && V->p[0] == y)
+            return matvec2d_go<2, 0>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part,
+                                     ldp, MatvecComb{}, st);
+        return matvec2d_go<1, 0>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, *V, nv, part, ldp,
+                                 MatvecComb{}, st);
+    }
+    if (!y) return hipErrorInvalidValue;
+    return matvec2d_go<0, 0>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, nullptr, 0,
+                             MatvecComb{}, st);
+}
+
+hipError_t launch_matvec2d_comb(const MatvecComb &cb, int nz, const double *bsub, int nx, int ny,
+                                int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
+                                double *part, int ldp)
+{
+    static const VecList none{};
+    if (!part || !cb.xout || matvec2d_blocks(nx, ny, ell, true) > ldp) return hipErrorInvalidValue;
+    switch (nz) {
+    case 1: return matvec2d_go<2, 1>(nullptr, nullptr, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part, ldp, cb, st);
+    case 2: return matvec2d_go<2, 2>(nullptr, nullptr, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part, ldp, cb, st);
+    case 3: return matvec2d_go<2, 3>(nullptr, nullptr, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part, ldp, cb, st);
+    case 4: return matvec2d_go<2, 4>(nullptr, nullptr, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part, ldp, cb, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------- right-hand side
