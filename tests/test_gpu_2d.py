@@ -279,3 +279,31 @@ def test_pinv_2d_sine_length_extremes(dev, ny):
     tol = max(1e-12, 8 * EPS * pins.cond_C2(0, nx, ny, ell, tau, 1.0))
     print(f"heat 2d pinv {nx}x{ny} ell={ell}: {e:.2e} (tol {tol:.2e})")
     assert e < tol
+
+
+@pytest.mark.parametrize("variant", ["x0", "early_check", "classic", "short_restart"])
+def test_gmres_2d_variants(dev, orc, variant):
+    """The GMRES forms on the unit square (the matvec's fused dots, the residual check
+    that forms x = Z y, the early column check, a given initial guess, the three-pass
+    CGS2, restarts) all reach the exact block-substitution solution."""
+    from paper_1810_00615_amd import Problem2D
+    nx, ny, ell = 21, 15, 24
+    tau, kappa = 1.0 / ell, 0.7
+    rng = np.random.default_rng([81, len(variant)])
+    b = rng.standard_normal((ell, ny, nx))
+    P = Problem2D(nx, ny, ell, tau, "bd2", kappa=kappa, device=dev)
+    kw = dict(restart=40, tol=1e-11, maxit=400)
+    if variant == "x0":
+        kw["x0"] = td(dev, 0.1 * rng.standard_normal((ell, ny, nx)))
+    elif variant == "early_check":
+        kw["early_check"] = True
+    elif variant == "classic":
+        kw["cgs2"] = "classic"
+    else:
+        kw["restart"] = 3
+    U, info = P.solve(td(dev, b), **kw)
+    assert info["converged"], info
+    Ur = orc.solve_seq2(1, nx, ny, ell, tau, kappa, b)
+    e = normrel(U.cpu().numpy(), Ur)
+    print(f"bd2 2d gmres {variant}: {info['iters']} iterations, error {e:.2e}")
+    assert e < 1e-7
