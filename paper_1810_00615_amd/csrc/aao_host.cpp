@@ -45,7 +45,6 @@ struct Status {
 struct aao_ctx_s {
     int64_t n = 0, ell = 0;      // n: unknowns per time level (nx ny on the unit square)
     int nx = 0, ny = 0;          // unit square (aao_create_2d); ny = 0 in one dimension
-    double *dsty = nullptr;      // sine transform of the preconditioner input (unit square)
     double *twy = nullptr;       // twiddles of the sine transform's length 2 (ny + 1)
     double tau = 0.0;
     int scheme = 0;
@@ -400,7 +399,7 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     // nothing reads before the inverse transform overwrites it, so the apply touches no
     // more memory than the FP64 one (the 64 MB of cache it would otherwise displace
     // slow the transforms down by a fifth)
-    if (ispec == ctx->spec_in && !zprev && !ctx->bluestein &&
+    if (ispec == ctx->spec_in && !zprev && !ctx->bluestein && ctx->ny == 0 &&
         (double)(ctx->ell / 2 + 1) * ctx->lds <= (double)ctx->N())
         ispec = z;
     AAO_TRY(refresh_symbols(ctx));
@@ -410,10 +409,12 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     if (sq) {
         // unit square: C^{-1} = S_y F^{-1} [solves] F S_y (S_y the sine transform in y,
         // which commutes with the time transform F)
+        // (S_y r goes to z, which the time transform reads before the inverse transform
+        // overwrites it: no extra vector in the working set)
         if (zprev) return AAO_ERR_UNSUPPORTED;
         AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
-                     launch_dst_y(r, ctx->dsty, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
-        r = ctx->dsty;
+                     launch_dst_y(r, z, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
+        r = z;
     }
     if (ctx->bluestein) {
         const BatchLaunch L = bl_launch(ctx);
@@ -1034,7 +1035,6 @@ static aao_status create_impl(int64_t n, int64_t ell, double tau, int scheme, in
         if ((s = dev_alloc(ctx, (void **)&ctx->sym, sizeof(double) * 8 * H * rpf)) != AAO_OK) break;
         if ((s = dev_alloc(ctx, &ctx->ptab, solve_table_bytes((int)ell, rpf))) != AAO_OK) break;
         if (ny > 0) {
-            if ((s = dev_alloc(ctx, (void **)&ctx->dsty, sizeof(double) * ctx->N())) != AAO_OK) break;
             if ((s = dev_alloc(ctx, (void **)&ctx->twy, sizeof(double) * 4 * (ny + 1))) != AAO_OK)
                 break;
             if (launch_twiddles(ctx->twy, 2 * (ny + 1), 2 * (ny + 1), nullptr) != hipSuccess) {
@@ -1165,7 +1165,6 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->damps);
     (void)hipFree(ctx->segpart);
     (void)hipFree(ctx->ntmp);
-    (void)hipFree(ctx->dsty);
     (void)hipFree(ctx->twy);
     (void)hipFree(ctx->bl_prob);
     (void)hipFree(ctx->bl_tiles);
