@@ -954,7 +954,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             y[i] = s / H[(size_t)i * m + i];
             yc.v[i] = y[i];
         }
-        if (x_zero && fused && (sq ? k >= 1 && k <= 4 : matvec_comb_ok(mcfg, k))) {
+        if (x_zero && fused && !sq && matvec_comb_ok(mcfg, k)) {
             // x = Z y formed inside the residual-check launch (x is not read, so no
             // block reads rows another one writes): one pass over Z, b and x
             MatvecComb cb{};
@@ -964,11 +964,8 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             }
             cb.xout = x;
             AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (k + 2),
-                         sq ? launch_matvec2d_comb(cb, k, b, ctx->nx, ctx->ny, ell, ctx->sc,
-                                                   ctx->kappa, transpose, st, ctx->part, ldp)
-                            : launch_matvec_comb(cb, k, b, n, ell, ctx->sc, ctx->kappa,
-                                                 ctx->tauk, transpose, st, mcfg, ctx->part,
-                                                 ldp));
+                         launch_matvec_comb(cb, k, b, n, ell, ctx->sc, ctx->kappa, ctx->tauk,
+                                            transpose, st, mcfg, ctx->part, ldp));
             AAO_TRY(small(3, 0, mvb));
         } else {
             AAO_LAUNCH_B(AAO_K_AXPY, vec_bytes(ctx) * (k + (x_zero ? 1 : 2)),

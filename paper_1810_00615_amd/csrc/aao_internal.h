@@ -276,11 +276,6 @@ hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int n
                            int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
                            const VecList *V = nullptr, int nv = 0, double *part = nullptr,
                            int ldp = 0);
-// The residual check of a solution update (as launch_matvec_comb): x = sum_{q<nz}
-// c_q z_q formed on the fly and written to cb.xout, partials of |bsub - A x|^2.
-hipError_t launch_matvec2d_comb(const MatvecComb &cb, int nz, const double *bsub, int nx, int ny,
-                                int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
-                                double *part, int ldp);
 int matvec2d_blocks(int nx, int ny, int ell, bool dots);
 // Right-hand side of the heat and BD2 systems on the unit square.
 hipError_t launch_build_rhs2d(double *b, const double *u0, const double *v0, int nx, int ny,

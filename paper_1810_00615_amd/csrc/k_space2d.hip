@@ -157,9 +157,10 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
 //
 // The GMRES forms of the launch (as in one dimension): DOTS = 1 also leaves the block
 // partials of V_q . y (q < nv) and of y . y (value nv), the first Gram-Schmidt pass;
-// DOTS = 2 the partial of y . y only (a residual norm); with NZ > 0 the input is
-// x = sum_{q<NZ} c_q z_q, formed on the fly and stored to cb.xout for the nodes and
-// levels the thread owns.  Partials are value-major, part[q ldp + block].
+// DOTS = 2 the partial of y . y only (a residual norm).  Partials are value-major,
+// part[q ldp + block].  (Forming x = Z y inside the residual check, as the 1D matvec
+// does, made this kernel slower than a separate axpy: the combination is recomputed
+// at every neighbour of the 9-point stencil.)
 constexpr int kMv2Seg = 8;
 constexpr int kMv2Rows = 4;     // plain launch
 constexpr int kMv2RowsDot = 2;  // launches with dot products (the outputs stay in registers)
@@ -170,12 +171,11 @@ int matvec2d_blocks(int nx, int ny, int ell, bool dots)
     return ((nx + 63) / 64) * ((ny + 4 * mr - 1) / (4 * mr)) * ((ell + kMv2Seg - 1) / kMv2Seg);
 }
 
-// the (MR + 2) x 3 neighbourhood of nodes (iy0 + o, ix), o < MR, of level L of x
-// (NZ = 0) or of sum_q c_q z_q; loads at clamped addresses, masked
-template <int MR, int NZ>
-__device__ __forceinline__ void q1_load(const double *__restrict__ x, const MatvecComb &cb,
-                                        size_t lofs, int nx, int ny, int ix, int iy0,
-                                        double (&v)[MR + 2][3])
+// the (MR + 2) x 3 neighbourhood of nodes (iy0 + o, ix), o < MR, of the level of x
+// at offset lofs; loads at clamped addresses, masked
+template <int MR>
+__device__ __forceinline__ void q1_load(const double *__restrict__ x, size_t lofs, int nx, int ny,
+                                        int ix, int iy0, double (&v)[MR + 2][3])
 {
     const int il = ix > 0 ? ix - 1 : 0, ir = ix < nx - 1 ? ix + 1 : ix;
     const double ml = ix > 0 ? 1.0 : 0.0, mr = ix < nx - 1 ? 1.0 : 0.0;
@@ -184,22 +184,9 @@ __device__ __forceinline__ void q1_load(const double *__restrict__ x, const Matv
         const int yy = iy0 + d - 1;
         const double w = (yy >= 0 && yy < ny) ? 1.0 : 0.0;
         const size_t ro = lofs + (size_t)((yy >= 0 && yy < ny) ? yy : 0) * nx;
-        if (NZ == 0) {
-            v[d][0] = w * ml * x[ro + il];
-            v[d][1] = w * x[ro + ix];
-            v[d][2] = w * mr * x[ro + ir];
-        } else {
-            double a = 0.0, b = 0.0, c = 0.0;
-#pragma unroll
-            for (int q = 0; q < NZ; ++q) {
-                a += cb.c[q] * cb.z[q][ro + il];
-                b += cb.c[q] * cb.z[q][ro + ix];
-                c += cb.c[q] * cb.z[q][ro + ir];
-            }
-            v[d][0] = w * ml * a;
-            v[d][1] = w * b;
-            v[d][2] = w * mr * c;
-        }
+        v[d][0] = w * ml * x[ro + il];
+        v[d][1] = w * x[ro + ix];
+        v[d][2] = w * mr * x[ro + ir];
     }
 }
 
@@ -230,7 +217,7 @@ __device__ __forceinline__ void q1_mk_rows(const double *__restrict__ xl, int nx
                                            double (&Q)[MR])
 {
     double v[MR + 2][3];
-    q1_load<MR, 0>(xl, MatvecComb{}, 0, nx, ny, ix, iy0, v);
+    q1_load<MR>(xl, 0, nx, ny, ix, iy0, v);
     q1_apply<MR>(v, hx, hy, P, Q);
 }
 
@@ -247,11 +234,11 @@ __device__ __forceinline__ double block_sum4(double v, double *red)
     return s;
 }
 
-template <int W, int MR, int DOTS, int NZ>
+template <int W, int MR, int DOTS>
 __global__ void __launch_bounds__(256)
 k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
            int nx, int ny, int ell, Scheme sc, double kappa, int transpose, VecList V, int nv,
-           double *__restrict__ part, int ldp, MatvecComb cb)
+           double *__restrict__ part, int ldp)
 {
     const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
     const int iy0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * MR;
@@ -266,22 +253,13 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
     const size_t lv = (size_t)nx * ny;
     const double hx = 1.0 / (nx + 1.0), hy = 1.0 / (ny + 1.0);
     double P[W][MR], Q[W][MR];
-    double C[NZ > 0 ? W : 1][MR];          // centre values of x (stored to cb.xout)
     auto fill = [&](int c, int L) {
 #pragma unroll
         for (int o = 0; o < MR; ++o) P[c][o] = Q[c][o] = 0.0;
-        if (NZ > 0) {
-#pragma unroll
-            for (int o = 0; o < MR; ++o) C[NZ > 0 ? c : 0][o] = 0.0;
-        }
         if (live && L >= 0 && L < ell) {
             double v[MR + 2][3];
-            q1_load<MR, NZ>(x, cb, (size_t)L * lv, nx, ny, ix, iy0, v);
+            q1_load<MR>(x, (size_t)L * lv, nx, ny, ix, iy0, v);
             q1_apply<MR>(v, hx, hy, P[c], Q[c]);
-            if (NZ > 0) {
-#pragma unroll
-                for (int o = 0; o < MR; ++o) C[NZ > 0 ? c : 0][o] = v[o + 1][1];
-            }
         }
     };
 #pragma unroll
@@ -320,7 +298,6 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
                     if (tt == t) yv[DOTS > 0 ? tt : 0][o] = own ? out : 0.0;
             }
             if (own && y) y[off] = out;
-            if (NZ > 0 && own) cb.xout[off] = C[NZ > 0 ? up : 0][o];
         }
         if (t + 1 < cnt) {
 #pragma unroll
@@ -329,7 +306,6 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
                 for (int o = 0; o < MR; ++o) {
                     P[c][o] = P[c - 1][o];
                     Q[c][o] = Q[c - 1][o];
-                    if (NZ > 0) C[NZ > 0 ? c : 0][o] = C[NZ > 0 ? c - 1 : 0][o];
                 }
             fill(0, k + dir + dir * up);
         }
@@ -367,17 +343,17 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
     if (threadIdx.x == 0) part[(size_t)nv * ldp + blk] = s;
 }
 
-template <int DOTS, int NZ>
+template <int DOTS>
 static hipError_t matvec2d_go(const double *x, double *y, const double *bsub, int nx, int ny,
                               int ell, Scheme sc, double kappa, int transpose, const VecList &V,
-                              int nv, double *part, int ldp, const MatvecComb &cb, hipStream_t st)
+                              int nv, double *part, int ldp, hipStream_t st)
 {
     constexpr int MR = DOTS > 0 ? kMv2RowsDot : kMv2Rows;
     dim3 grid((nx + 63) / 64, (ny + 4 * MR - 1) / (4 * MR), (ell + kMv2Seg - 1) / kMv2Seg);
     switch (sc.s + sc.up + 1) {
-    case 2: k_matvec2d<2, MR, DOTS, NZ><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp, cb); break;
-    case 3: k_matvec2d<3, MR, DOTS, NZ><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp, cb); break;
-    case 4: k_matvec2d<4, MR, DOTS, NZ><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp, cb); break;
+    case 2: k_matvec2d<2, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
+    case 3: k_matvec2d<3, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
+    case 4: k_matvec2d<4, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -393,29 +369,13 @@ hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int n
             return hipErrorInvalidValue;
         // a one-entry list equal to the output selects the self-norm only
         if (nv == 1 && V->p[0] == y)
-            return matvec2d_go<2, 0>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part,
-                                     ldp, MatvecComb{}, st);
-        return matvec2d_go<1, 0>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, *V, nv, part, ldp,
-                                 MatvecComb{}, st);
+            return matvec2d_go<2>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part,
+                                  ldp, st);
+        return matvec2d_go<1>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, *V, nv, part, ldp,
+                              st);
     }
     if (!y) return hipErrorInvalidValue;
-    return matvec2d_go<0, 0>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, nullptr, 0,
-                             MatvecComb{}, st);
-}
-
-hipError_t launch_matvec2d_comb(const MatvecComb &cb, int nz, const double *bsub, int nx, int ny,
-                                int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
-                                double *part, int ldp)
-{
-    static const VecList none{};
-    if (!part || !cb.xout || matvec2d_blocks(nx, ny, ell, true) > ldp) return hipErrorInvalidValue;
-    switch (nz) {
-    case 1: return matvec2d_go<2, 1>(nullptr, nullptr, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part, ldp, cb, st);
-    case 2: return matvec2d_go<2, 2>(nullptr, nullptr, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part, ldp, cb, st);
-    case 3: return matvec2d_go<2, 3>(nullptr, nullptr, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part, ldp, cb, st);
-    case 4: return matvec2d_go<2, 4>(nullptr, nullptr, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part, ldp, cb, st);
-    default: return hipErrorInvalidValue;
-    }
+    return matvec2d_go<0>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, nullptr, 0, st);
 }
 
 // ---------------------------------------------------------- right-hand side
