@@ -220,7 +220,8 @@ int or2_solve_seq(int scheme, int nx, int ny, int ell, double tau, double kappa,
 }
 
 /* Right-hand side of the 2D system: the rows of the 1D oracle's or_build_rhs with M2, K2
- *   heat b_1 = M2 u0;  BD2 b_1 = (M2 + tau^2 kappa K2)(u0 + tau v0), b_2 = -M2 u0. */
+ *   heat b_1 = M2 u0;  BD2 b_1 = (M2 + tau^2 kappa K2)(u0 + tau v0), b_2 = -M2 u0;
+ *   BD4 as BD2 plus b_3 = M2 u0;  CD b_1 = -M2 u0 (no v0).  -1 for a short ell. */
 int or2_build_rhs(int scheme, int nx, int ny, int ell, double tau, double kappa,
                   const double *u0, const double *v0, double *bvec)
 {
@@ -230,13 +231,24 @@ int or2_build_rhs(int scheme, int nx, int ny, int ell, double tau, double kappa,
         or2_mk_apply(nx, ny, 1.0, 0.0, u0, bvec);
         return 0;
     }
-    if (scheme == 1) {
-        if (ell < 2) return -1;
+    if (scheme == 1 || scheme == 2) {
+        /* BD2 (system C_BD2) and BD4 (eq. BD4, system C_BD4): the first row's block
+         * (M2 + tau^2 kappa K2, BD4's start-up block B) acts on u_1 = u0 + tau v0;
+         * the u0 terms of the following rows move to the right */
+        if (ell < (scheme == 1 ? 2 : 3)) return -1;
         double *w = (double *)malloc(sizeof(double) * n);
         for (size_t e = 0; e < n; ++e) w[e] = u0[e] + (v0 ? tau * v0[e] : 0.0);
         or2_mk_apply(nx, ny, 1.0, tau * tau * kappa, w, bvec);
         or2_mk_apply(nx, ny, -1.0, 0.0, u0, bvec + n);
+        if (scheme == 2) or2_mk_apply(nx, ny, 1.0, 0.0, u0, bvec + 2 * n);
         free(w);
+        return 0;
+    }
+    if (scheme == 3) {
+        /* central differences (eq. CenDiffDisc): M2 u_0 of the first row moves to the
+         * right; no initial velocity enters */
+        if (v0) return -1;
+        or2_mk_apply(nx, ny, -1.0, 0.0, u0, bvec);
         return 0;
     }
     return -1;

@@ -144,3 +144,62 @@ def test_2d_pinv_matches_eigendecomposition(orc, scheme, transpose):
     ref = pins.pinv_spectral2(scheme, nx, ny, ell, tau, kappa, r, transpose)
     tol = max(1e-13, 8 * 2.0 ** -52 * pins.cond_C2(scheme, nx, ny, ell, tau, kappa))
     assert rel(z, ref) < tol
+
+
+@pytest.mark.parametrize("scheme", [2, 3])
+def test_2d_bd4_cd_rhs_by_sine_modes(orc, scheme):
+    """BD4 (system C_BD4) and central differences (eq. CenDiffDisc) on the unit square:
+    every block is a combination of M2 and K2, which act on the sine product s_q (x) s_p
+    as mu_pq and lambda_pq mu_pq (lambda_pq = lambda^x_p + lambda^y_q).  Per mode, BD4 is
+    the scalar recursion c_1 = c_0 + tau d_0, (1 + t) c_2 = 2 c_1 - c_0, (2 + t) c_k =
+    5 c_{k-1} - 4 c_{k-2} + c_{k-3} (t = tau^2 kappa lambda_pq), and CD the ell x ell
+    tridiagonal system c_{k-1} + (t - 2) c_k + c_{k+1} = 0 with c_0 moved to the right.
+    The oracle's right-hand side solved by block substitution must give these modes."""
+    nx, ny, ell, kappa = 7, 5, 9, 1.3
+    tau = 1.0 / ell
+    rng = np.random.default_rng(63)
+    Sx = np.sin(np.pi * np.outer(np.arange(1, nx + 1), np.arange(1, nx + 1)) / (nx + 1))
+    Sy = np.sin(np.pi * np.outer(np.arange(1, ny + 1), np.arange(1, ny + 1)) / (ny + 1))
+    C0 = rng.standard_normal((ny, nx))
+    D0 = rng.standard_normal((ny, nx))
+    u0 = (Sy.T @ C0 @ Sx).ravel()
+    v0 = (Sy.T @ D0 @ Sx).ravel() if scheme == 2 else None
+    b = orc.build_rhs2(scheme, nx, ny, ell, tau, kappa, u0, v0)
+    if scheme == 2:
+        U = orc.solve_seq2(scheme, nx, ny, ell, tau, kappa, b)
+    else:
+        # CD couples u_{k+1} into row k, so no block substitution: solve with the
+        # matrix that the oracle's matvec applies, column by column
+        N = nx * ny * ell
+        A = np.stack([orc.apply_A2(scheme, nx, ny, ell, tau, kappa, e).ravel()
+                      for e in np.eye(N)], axis=1)
+        U = np.linalg.solve(A, b.ravel()).reshape(ell, nx * ny)
+    lam = pins.lam(ny, np.arange(1, ny + 1))[:, None] + pins.lam(nx, np.arange(1, nx + 1))[None, :]
+    t = tau * tau * kappa * lam
+    if scheme == 2:
+        c = [C0, C0 + tau * D0]
+        c.append((2 * c[1] - c[0]) / (1 + t))
+        for k in range(3, ell + 1):
+            c.append((5 * c[k - 1] - 4 * c[k - 2] + c[k - 3]) / (2 + t))
+        modes = c[1:]
+    else:
+        modes = np.empty((ell, ny, nx))
+        for q in range(ny):
+            for p in range(nx):
+                T = (np.diag(np.full(ell, t[q, p] - 2.0)) + np.eye(ell, k=1)
+                     + np.eye(ell, k=-1))
+                rhs = np.zeros(ell)
+                rhs[0] = -C0[q, p]
+                modes[:, q, p] = np.linalg.solve(T, rhs)
+    for k in range(ell):
+        assert rel(U[k], (Sy.T @ modes[k] @ Sx).ravel()) < 1e-11
+
+
+def test_2d_rhs_rejections(orc):
+    u0 = np.ones(12)
+    with pytest.raises(RuntimeError):
+        orc.build_rhs2(2, 4, 3, 2, 0.5, 1.0, u0)          # BD4 needs ell >= 3
+    with pytest.raises(RuntimeError):
+        orc.build_rhs2(1, 4, 3, 1, 0.5, 1.0, u0)          # BD2 needs ell >= 2
+    with pytest.raises(RuntimeError):
+        orc.build_rhs2(3, 4, 3, 4, 0.25, 1.0, u0, u0)     # CD takes no velocity
