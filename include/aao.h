@@ -116,7 +116,7 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
  * doubles.  Requires ny + 1 a power of two (ny <= 2047), 1 <= nx <= 16384,
  * 1 <= ell <= 65535; AAO_ERR_UNSUPPORTED otherwise.
  * Supported on such a context: aao_set_stream, aao_set_kappa, aao_set_precision,
- * aao_build_rhs (AAO_HEAT_IE and AAO_WAVE_BD2), aao_apply_A, aao_apply_Pinv (order
+ * aao_build_rhs (M2 in place of M, K2 of K), aao_apply_A, aao_apply_Pinv (order
  * 0), aao_gmres, aao_gmres_ex, aao_adjoint_solve, aao_set_timing*, aao_get_timing*,
  * aao_tune, aao_get_config, aao_set_config, aao_config_shape (the shifted solves'
  * shapes apply to rows of nx unknowns).  aao_set_steps, aao_set_neumann_order (q >

@@ -1275,9 +1275,10 @@ aao_status aao_build_rhs(aao_ctx ctx, const double *u0, const double *v0, double
     if (v0 && ctx->scheme == AAO_WAVE_CD)
         return arg_err(ctx, "the central-difference system takes no initial velocity");
     if (ctx->ny > 0) {
-        if (ctx->scheme != AAO_HEAT_IE && ctx->scheme != AAO_WAVE_BD2) return unsupported_2d(ctx);
         if (ctx->scheme == AAO_WAVE_BD2 && ctx->ell < 2)
             return arg_err(ctx, "the BD2 right-hand side needs ell >= 2");
+        if (ctx->scheme == AAO_WAVE_BD4 && ctx->ell < 3)
+            return arg_err(ctx, "the BD4 right-hand side needs ell >= 3");
         if (v0 && ctx->scheme == AAO_HEAT_IE)
             return arg_err(ctx, "the heat system takes no initial velocity");
         AAO_HIP(launch_build_rhs2d(b, u0, v0, ctx->nx, ctx->ny, (int)ctx->ell, ctx->sc, ctx->kappa,

@@ -379,8 +379,9 @@ hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int n
 }
 
 // ---------------------------------------------------------- right-hand side
-// Heat: b_0 = M2 u0.  BD2: b_0 = (M2 + tau^2 kappa K2)(u0 + tau v0), b_1 = -M2 u0
-// (v0 = 0 if absent).  Every later row is zero.
+// The first rows of the monolithic right-hand side, every later row zero:
+//   heat b_0 = M2 u0;  BD2 b_0 = (M2 + tau^2 kappa K2)(u0 + tau v0), b_1 = -M2 u0;
+//   BD4 as BD2 plus b_2 = M2 u0;  CD b_0 = -M2 u0  (v0 = 0 if absent).
 __global__ void __launch_bounds__(256)
 k_rhs2d(double *__restrict__ b, const double *__restrict__ u0, const double *__restrict__ v0,
         int nx, int ny, int ell, int scheme, double tau, double kappa)
@@ -395,12 +396,15 @@ k_rhs2d(double *__restrict__ b, const double *__restrict__ u0, const double *__r
     int k = 1;
     if (scheme == AAO_HEAT_IE) {
         b[node] = Pu[0];
+    } else if (scheme == AAO_WAVE_CD) {
+        b[node] = -Pu[0];
     } else {
         double Pv[1] = {0.0}, Qv[1] = {0.0};
         if (v0) q1_mk_rows<1>(v0, nx, ny, ix, iy, hx, hy, Pv, Qv);
         b[node] = (Pu[0] + tau * Pv[0]) + tau * tau * kappa * (Qu[0] + tau * Qv[0]);
         b[lv + node] = -Pu[0];
         k = 2;
+        if (scheme == AAO_WAVE_BD4) b[2 * lv + node] = Pu[0], k = 3;
     }
     for (; k < ell; ++k) b[(size_t)k * lv + node] = 0.0;
 }
@@ -408,7 +412,9 @@ k_rhs2d(double *__restrict__ b, const double *__restrict__ u0, const double *__r
 hipError_t launch_build_rhs2d(double *b, const double *u0, const double *v0, int nx, int ny,
                               int ell, Scheme sc, double kappa, double tau, hipStream_t st)
 {
-    if (sc.id != AAO_HEAT_IE && (sc.id != AAO_WAVE_BD2 || ell < 2)) return hipErrorInvalidValue;
+    const int rows = sc.id == AAO_WAVE_BD4 ? 3 : sc.id == AAO_WAVE_BD2 ? 2 : 1;
+    if (sc.id < AAO_HEAT_IE || sc.id > AAO_WAVE_CD || ell < rows) return hipErrorInvalidValue;
+    if (sc.id == AAO_WAVE_CD && v0) return hipErrorInvalidValue;
     dim3 grid((nx + 63) / 64, (ny + 3) / 4);
     k_rhs2d<<<grid, 256, 0, st>>>(b, u0, v0, nx, ny, ell, sc.id, tau, kappa);
     return hipGetLastError();

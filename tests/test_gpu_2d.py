@@ -42,15 +42,19 @@ def td(dev, x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(dev)
 
 
-@pytest.mark.parametrize("scheme", [HEAT, BD2])
+@pytest.mark.parametrize("scheme", [HEAT, BD2, BD4, CD])
 @pytest.mark.parametrize("nx,ny,ell", [(1, 1, 2), (5, 3, 4), (64, 7, 3), (130, 31, 6)])
 def test_rhs_2d(dev, orc, scheme, nx, ny, ell):
-    from paper_1810_00615_amd import Problem2D
+    from paper_1810_00615_amd import AAOError, Problem2D
     tau, kappa = 1.0 / ell, 1.3
     rng = np.random.default_rng([nx, ny, ell, scheme])
     u0, v0 = rng.standard_normal((ny, nx)), rng.standard_normal((ny, nx))
     P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
-    vv = v0 if scheme == BD2 else None
+    vv = v0 if scheme in (BD2, BD4) else None
+    if scheme == BD4 and ell < 3:
+        with pytest.raises(AAOError):
+            P.rhs(td(dev, u0))
+        return
     b = P.rhs(td(dev, u0), None if vv is None else td(dev, vv)).cpu().numpy()
     assert b.shape == (ell, ny, nx)
     ref = orc.build_rhs2(scheme, nx, ny, ell, tau, kappa, u0, vv)
@@ -61,7 +65,11 @@ def test_rhs_2d_rejections(dev):
     from paper_1810_00615_amd import AAOError, Problem2D
     u0 = td(dev, np.ones((3, 4)))
     with pytest.raises(AAOError):
-        Problem2D(4, 3, 5, scheme="bd4", device=dev).rhs(u0)
+        Problem2D(4, 3, 1, scheme="bd2", device=dev).rhs(u0)
+    with pytest.raises(AAOError):
+        Problem2D(4, 3, 2, scheme="bd4", device=dev).rhs(u0)
+    with pytest.raises(AAOError):
+        Problem2D(4, 3, 5, scheme="cd", device=dev).rhs(u0, u0)
     with pytest.raises(AAOError):
         Problem2D(4, 3, 5, scheme="heat", device=dev).rhs(u0, u0)
     P = Problem2D(4, 3, 5, device=dev)
@@ -159,7 +167,7 @@ def test_gmres_2d_to_exact(dev, orc, scheme):
     assert normrel(lam.cpu().numpy(), lr) < 4 * cA * tol
 
 
-@pytest.mark.parametrize("scheme", [HEAT, BD2])
+@pytest.mark.parametrize("scheme", [HEAT, BD2, BD4])
 def test_gmres_2d_rhs_medium(dev, orc, scheme):
     """A solve from initial data through the library's right-hand side, on a grid with
     several x-chunks of the solves and a ragged last sine-transform tile, against the
@@ -169,10 +177,11 @@ def test_gmres_2d_rhs_medium(dev, orc, scheme):
     tau, kappa = 1.0 / ell, 1.0
     rng = np.random.default_rng(90 + scheme)
     u0 = rng.standard_normal((ny, nx))
-    v0 = rng.standard_normal((ny, nx)) if scheme == BD2 else None
+    v0 = rng.standard_normal((ny, nx)) if scheme in (BD2, BD4) else None
     P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
     b = P.rhs(td(dev, u0), None if v0 is None else td(dev, v0))
-    U, info = P.solve(b, restart=40, tol=1e-12, maxit=400)
+    # random data excites every mode; BD4's high modes converge slowly under C^{-1}
+    U, info = P.solve(b, restart=40, tol=1e-12, maxit=400 if scheme != BD4 else 2000)
     assert info["converged"], info
     Ur = orc.solve_seq2(scheme, nx, ny, ell, tau, kappa,
                         orc.build_rhs2(scheme, nx, ny, ell, tau, kappa, u0, v0))
@@ -261,6 +270,58 @@ def test_bd2_2d_large_closed_form(dev):
     e = normrel(Ug, Ur)
     worst = max(normrel(Ug[k], Ur[k]) for k in range(ell))
     print(f"bd2 2d 255x255x128: {info['iters']} iterations, error {e:.2e}, worst level {worst:.2e}")
+    assert e < 1e-8 and worst < 1e-7
+
+
+@pytest.mark.parametrize("scheme", [BD4, CD])
+def test_wave_2d_modes(dev, scheme):
+    """BD4 and central differences on a 127 x 63 grid, 64 steps, from sine-product initial
+    data through the library's right-hand side: per mode (p, q) the monolithic system is
+    scalar in time with t = tau^2 kappa lambda_pq, lambda_pq = lambda^x_p + lambda^y_q --
+    BD4 the recursion c_1 = c_0 + tau d_0, (1 + t) c_2 = 2 c_1 - c_0, (2 + t) c_k =
+    5 c_{k-1} - 4 c_{k-2} + c_{k-3}; CD the ell x ell tridiagonal system c_{k-1} +
+    (t - 2) c_k + c_{k+1} = 0 with c_0 moved to the right -- checked at every level."""
+    from paper_1810_00615_amd import Problem2D
+    nx, ny, ell, kappa = 127, 63, 64, 1.0
+    tau = 1.0 / ell
+
+    def sines(n, m):
+        return np.sin(np.pi * m * np.arange(1, n + 1) / (n + 1))
+
+    def lam1(n, m):
+        h = 1.0 / (n + 1)
+        c = np.cos(np.pi * m * h)
+        return 6.0 * (1.0 - c) / (h * h * (2.0 + c))
+    umodes = {(1, 1): 1.0, (2, 3): 0.5, (6, 2): -0.25}
+    vmodes = {(1, 1): 0.3, (3, 2): -0.2} if scheme == BD4 else {}
+    u0 = sum(a * np.outer(sines(ny, q), sines(nx, p)) for (p, q), a in umodes.items())
+    v0 = sum(a * np.outer(sines(ny, q), sines(nx, p)) for (p, q), a in vmodes.items()) \
+        if vmodes else None
+    P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
+    b = P.rhs(td(dev, u0), None if v0 is None else td(dev, v0))
+    U, info = P.solve(b, restart=30, tol=1e-11, maxit=300)
+    assert info["converged"], info
+    Ug = U.cpu().numpy()
+    Ur = np.zeros((ell, ny, nx))
+    for (p, q) in set(umodes) | set(vmodes):
+        c0, d0 = umodes.get((p, q), 0.0), vmodes.get((p, q), 0.0)
+        t = tau * tau * kappa * (lam1(nx, p) + lam1(ny, q))
+        if scheme == BD4:
+            c = [c0, c0 + tau * d0]
+            c.append((2 * c[1] - c[0]) / (1 + t))
+            for k in range(3, ell + 1):
+                c.append((5 * c[k - 1] - 4 * c[k - 2] + c[k - 3]) / (2 + t))
+            ck = np.array(c[1:])
+        else:
+            T = np.diag(np.full(ell, t - 2.0)) + np.eye(ell, k=1) + np.eye(ell, k=-1)
+            rhs = np.zeros(ell)
+            rhs[0] = -c0
+            ck = np.linalg.solve(T, rhs)
+        Ur += ck[:, None, None] * np.outer(sines(ny, q), sines(nx, p))[None]
+    e = normrel(Ug, Ur)
+    worst = max(normrel(Ug[k], Ur[k]) for k in range(ell))
+    print(f"{NAME[scheme]} 2d {nx}x{ny}x{ell}: {info['iters']} iterations, error {e:.2e}, "
+          f"worst level {worst:.2e}")
     assert e < 1e-8 and worst < 1e-7
 
 
