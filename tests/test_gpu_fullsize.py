@@ -39,6 +39,7 @@ def heat2(dev, orc):
     from paper_1810_00615_amd.inputs import heat_large
     w = heat_large()
     P = Problem(w.n, w.ell, w.tau, "heat", kappa=w.kappa, device=dev)
+    print("heat full tuned shapes:", P.tune(reps=3))   # as the benchmark runs it
     u0r = orc.project_sine(w.n, w.modes, w.amps)
     br = orc.build_rhs(HEAT, w.n, w.ell, w.tau, w.kappa, u0r)
     return w, P, u0r, br
