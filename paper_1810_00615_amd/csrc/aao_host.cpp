@@ -819,8 +819,10 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
             // update pass, and w is not stored unless that check fails.  (A looser
             // margin fires at every step of a slowly converging tail, each false
             // expectation costing a second matvec and a host round trip.)
+            // (the unit-square matvec reads w back for dots past its first ones)
             const bool expect = delayed && fused && j > 0 &&
-                                (early_always || est_prev * (est_prev / est_prev2) <= tol);
+                                (early_always || est_prev * (est_prev / est_prev2) <= tol) &&
+                                !(sq && nv > matvec2d_dot_walk());
             if (fused) {
                 AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (expect ? 1 + nv : 2 + nv),
                              mv_dots(Zj, expect ? nullptr : ctx->W, nullptr, &Vl, nv));

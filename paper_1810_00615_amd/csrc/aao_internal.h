@@ -271,13 +271,15 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
 // a_m M2 + b_m kappa K2 (M2 = My (x) Mx, K2 = Ky (x) Mx + My (x) Kx).  With nv > 0 the
 // launch also leaves the block partials of V_q . y (q < nv) and of y . y (value nv);
 // nv == 1 with V->p[0] == y only those of y . y (value 0); y may then be null.
-// matvec2d_blocks(..., true) partials per value.
+// matvec2d_blocks(..., true) partials per value.  With nv > matvec2d_dot_walk() the
+// dots past the first ones read y back, so y must not be null.
 hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
                            int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
                            const VecList *V = nullptr, int nv = 0, double *part = nullptr,
                            int ldp = 0);
 int matvec2d_blocks(int nx, int ny, int ell, bool dots);
-// Right-hand side of the heat and BD2 systems on the unit square.
+int matvec2d_dot_walk();
+// Right-hand side of every scheme on the unit square (the first rows, zeros after).
 hipError_t launch_build_rhs2d(double *b, const double *u0, const double *v0, int nx, int ny,
                               int ell, Scheme sc, double kappa, double tau, hipStream_t st);
 

@@ -158,12 +158,20 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
 // The GMRES forms of the launch (as in one dimension): DOTS = 1 also leaves the block
 // partials of V_q . y (q < nv) and of y . y (value nv), the first Gram-Schmidt pass;
 // DOTS = 2 the partial of y . y only (a residual norm).  Partials are value-major,
-// part[q ldp + block].  (Forming x = Z y inside the residual check, as the 1D matvec
-// does, made this kernel slower than a separate axpy: the combination is recomputed
-// at every neighbour of the 9-point stencil.)
+// part[q ldp + block].  The rows of bsub and of the first kMv2DotG basis vectors that
+// the next level needs are loaded with that level's x rows, so their latency overlaps
+// the stencil's, and their dot products accumulate while the segment is walked; basis
+// vectors past kMv2DotG are dotted after the walk with y read back, so those launches
+// need y.  (Forming x = Z y
+// inside the residual check, as the 1D matvec does, made this kernel slower than a
+// separate axpy: the combination is recomputed at every neighbour of the 9-point
+// stencil.)
 constexpr int kMv2Seg = 8;
 constexpr int kMv2Rows = 4;     // plain launch
-constexpr int kMv2RowsDot = 2;  // launches with dot products (the outputs stay in registers)
+constexpr int kMv2RowsDot = 4;  // launches with dot products
+constexpr int kMv2DotG = 2;     // basis vectors dotted during the walk
+
+int matvec2d_dot_walk() { return kMv2DotG; }
 
 int matvec2d_blocks(int nx, int ny, int ell, bool dots)
 {
@@ -236,10 +244,11 @@ __device__ __forceinline__ double block_sum4(double v, double *red)
 
 template <int W, int MR, int DOTS>
 __global__ void __launch_bounds__(256)
-k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
+k_matvec2d(const double *__restrict__ x, double *y, const double *__restrict__ bsub,
            int nx, int ny, int ell, Scheme sc, double kappa, int transpose, VecList V, int nv,
            double *__restrict__ part, int ldp)
 {
+    constexpr int G = DOTS == 1 ? kMv2DotG : 1;
     const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
     const int iy0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * MR;
     const bool live = ix < nx && iy0 < ny;
@@ -252,6 +261,14 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
     const int cnt = ke - kb;
     const size_t lv = (size_t)nx * ny;
     const double hx = 1.0 / (nx + 1.0), hy = 1.0 / (ny + 1.0);
+    const int ng = DOTS == 1 ? min(nv, G) : 0;
+    bool own[MR];
+    size_t nofs[MR];                      // node offsets within a level
+#pragma unroll
+    for (int o = 0; o < MR; ++o) {
+        own[o] = live && iy0 + o < ny;
+        nofs[o] = (size_t)(own[o] ? iy0 + o : 0) * nx + (own[o] ? ix : 0);
+    }
     double P[W][MR], Q[W][MR];
     auto fill = [&](int c, int L) {
 #pragma unroll
@@ -262,13 +279,23 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
             q1_apply<MR>(v, hx, hy, P[c], Q[c]);
         }
     };
+    // rows of bsub and of the first G basis vectors at level k (zero where not owned)
+    double bc[MR], vc[G][MR];
+    auto fetch = [&](int k) {
+#pragma unroll
+        for (int o = 0; o < MR; ++o) {
+            const size_t off = (size_t)k * lv + nofs[o];
+            bc[o] = (bsub && own[o]) ? bsub[off] : 0.0;
+#pragma unroll
+            for (int g = 0; g < G; ++g) vc[g][o] = (g < ng && own[o]) ? V.p[g][off] : 0.0;
+        }
+    };
 #pragma unroll
     for (int c = 0; c < W; ++c) fill(c, k0 - dir * (c - up));
-    double yv[DOTS > 0 ? kMv2Seg : 1][MR];   // the outputs (zero past the segment's end)
+    if (cnt > 0) fetch(k0);
+    double yy = 0.0, ad[G];
 #pragma unroll
-    for (int t = 0; t < (DOTS > 0 ? kMv2Seg : 1); ++t)
-#pragma unroll
-        for (int o = 0; o < MR; ++o) yv[t][o] = 0.0;
+    for (int g = 0; g < G; ++g) ad[g] = 0.0;
     for (int t = 0; t < kMv2Seg; ++t) {
         if (t >= cnt) break;
         const int k = k0 + dir * t;
@@ -289,15 +316,12 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
         }
 #pragma unroll
         for (int o = 0; o < MR; ++o) {
-            const bool own = live && iy0 + o < ny;
-            const size_t off = (size_t)k * lv + (size_t)(own ? iy0 + o : 0) * nx + ix;
-            const double out = bsub ? (own ? bsub[off] : 0.0) - acc[o] : acc[o];
-            if (DOTS > 0) {
+            const double out = own[o] ? (bsub ? bc[o] - acc[o] : acc[o]) : 0.0;
+            if (DOTS > 0) yy += out * out;
 #pragma unroll
-                for (int tt = 0; tt < kMv2Seg; ++tt)
-                    if (tt == t) yv[DOTS > 0 ? tt : 0][o] = own ? out : 0.0;
-            }
-            if (own && y) y[off] = out;
+            for (int g = 0; g < G; ++g)
+                if (DOTS == 1) ad[g] += vc[g][o] * out;
+            if (own[o] && y) y[(size_t)k * lv + nofs[o]] = out;
         }
         if (t + 1 < cnt) {
 #pragma unroll
@@ -308,33 +332,32 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
                     Q[c][o] = Q[c - 1][o];
                 }
             fill(0, k + dir + dir * up);
+            fetch(k + dir);
         }
     }
     if (DOTS == 0) return;
     __shared__ double red[4];
     const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    double yy = 0.0;
-#pragma unroll
-    for (int t = 0; t < kMv2Seg; ++t)
-#pragma unroll
-        for (int o = 0; o < MR; ++o) yy += yv[DOTS > 0 ? t : 0][o] * yv[DOTS > 0 ? t : 0][o];
     if (DOTS == 2) {
         const double s = block_sum4(yy, red);
         if (threadIdx.x == 0) part[blk] = s;
         return;
     }
-    // V_q . y over this block's tile, one basis vector at a time
-    for (int q = 0; q < nv; ++q) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+        if (g < ng) {
+            const double s = block_sum4(ad[g], red);
+            if (threadIdx.x == 0) part[(size_t)g * ldp + blk] = s;
+        }
+    // basis vectors past the first G: y read back (this thread wrote these entries;
+    // the launcher requires y for nv > G)
+    for (int q = G; q < nv; ++q) {
         double a = 0.0;
+        for (int t = 0; t < cnt; ++t) {
+            const size_t lo = (size_t)(k0 + dir * t) * lv;
 #pragma unroll
-        for (int t = 0; t < kMv2Seg; ++t) {
-            const int k = k0 + dir * t;
-#pragma unroll
-            for (int o = 0; o < MR; ++o) {
-                const bool own = live && t < cnt && iy0 + o < ny;
-                const size_t off = (size_t)(own ? k : 0) * lv + (size_t)(own ? iy0 + o : 0) * nx + ix;
-                a += own ? V.p[q][off] * yv[DOTS > 0 ? t : 0][o] : 0.0;
-            }
+            for (int o = 0; o < MR; ++o)
+                if (own[o]) a += V.p[q][lo + nofs[o]] * y[lo + nofs[o]];
         }
         const double s = block_sum4(a, red);
         if (threadIdx.x == 0) part[(size_t)q * ldp + blk] = s;
@@ -367,6 +390,7 @@ hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int n
     if (nv > 0) {
         if (!V || !part || nv >= kMaxVecs || matvec2d_blocks(nx, ny, ell, true) > ldp)
             return hipErrorInvalidValue;
+        if (nv > kMv2DotG && !y) return hipErrorInvalidValue;   // dots past the walk read y
         // a one-entry list equal to the output selects the self-norm only
         if (nv == 1 && V->p[0] == y)
             return matvec2d_go<2>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part,
