@@ -27,8 +27,10 @@ namespace aao {
 // contiguous columns), so it runs on the same register-resident radix-16 Stockham
 // machinery: a workgroup owns W complex columns (2W real columns, one row segment of
 // 16 W bytes per row) of one level, thread (t, c) holds P points of column c, and the
-// stages exchange through LDS one real plane at a time.  Mirrored positions of the
-// extension are loaded twice (the second load hits the cache).
+// stages exchange through LDS one real plane at a time.  The rows enter through LDS
+// in whole row segments, so each is read from memory once (the mirrored positions of
+// the extension read LDS).  (Staging the output rows as well raised the register
+// count past the two workgroups per compute unit that the LDS allows.)
 bool dst_y_supported(int ny) { return ny >= 1 && ny <= 2047 && ((ny + 1) & ny) == 0; }
 
 template <int L>
@@ -45,15 +47,38 @@ k_dst_y(const double *in, double *out, int nx, int ny, int ell, int W,
     constexpr int P = dst_points<L>();
     extern __shared__ unsigned char dsm_raw[];
     double *sm = reinterpret_cast<double *>(dsm_raw);
+    const int NT = blockDim.x;
     const int c = threadIdx.x % W;
     const int t = threadIdx.x / W;
     const int tiles_x = (nx + 2 * W - 1) / (2 * W);
     const int g = xcd_tile(blockIdx.x, gridDim.x);
     const int lvl = g / tiles_x;
     if (lvl >= ell) return;                       // padding workgroup: no barrier reached
-    const int x0 = (g - lvl * tiles_x) * 2 * W + 2 * c;
-    const bool ha = x0 < nx, hb = x0 + 1 < nx;
+    const int xb = (g - lvl * tiles_x) * 2 * W;   // first real column of the tile
+    const int W2 = 2 * W, lw2 = __ffs(W2) - 1;    // W is a power of two
     const size_t base = (size_t)lvl * ny * nx;
+    // The tile's ny rows of 2W doubles pass through LDS (row q at sm[q * 2W]): each
+    // row is read from memory once, in 2W-double segments, and the mirrored positions
+    // of the extension read LDS instead.  ny * 2W < P * NT, so P passes cover it;
+    // they go in groups of eight loads (all in flight, then written).
+    constexpr int GL = P < 8 ? P : 8;
+#pragma unroll
+    for (int u0 = 0; u0 < P; u0 += GL) {
+        double val[GL];
+#pragma unroll
+        for (int u = 0; u < GL; ++u) {
+            const int e = threadIdx.x + (u0 + u) * NT;
+            const int q = min(e >> lw2, ny - 1), x = min(xb + (e & (W2 - 1)), nx - 1);
+            val[u] = in[base + (size_t)q * nx + x];   // clamped: issued unconditionally
+        }
+#pragma unroll
+        for (int u = 0; u < GL; ++u) {
+            const int e = threadIdx.x + (u0 + u) * NT;
+            if (e < ny * W2) sm[e] = xb + (e & (W2 - 1)) < nx ? val[u] : 0.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
     cx<double> v[P];
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
@@ -61,14 +86,15 @@ k_dst_y(const double *in, double *out, int nx, int ny, int ell, int W,
         const bool lo = pos <= ny;                 // z_pos = v_pos, else -v_{L-pos}
         const int q = lo ? pos : L - pos;          // 1..ny for data, 0 / ny+1 for zeros
         const bool data = q >= 1 && q <= ny;
-        const size_t o = base + (size_t)(data ? q - 1 : 0) * nx + x0;
-        const double a = (data && ha) ? in[o] : 0.0;
-        const double b = (data && hb) ? in[o + 1] : 0.0;
+        const double2 ab = *reinterpret_cast<const double2 *>(sm + ((data ? q - 1 : 0) << lw2) + 2 * c);
+        const double a = data ? ab.x : 0.0, b = data ? ab.y : 0.0;
         v[idx] = lo ? cx<double>{a, b} : cx<double>{-a, -b};
     }
+    __syncthreads();                               // staging read before the first exchange
     run_stages<double, L, P, 0, false>(v, sm, t, c, W, tw, 1);
-    __syncthreads();                               // in == out: every load has completed
     const double f = 0.5 * sqrt(2.0 / (ny + 1.0));
+    const int x0 = xb + 2 * c;
+    const bool ha = x0 < nx, hb = x0 + 1 < nx;
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
         const int p = final_pos<L, P>(t, idx);
