@@ -268,17 +268,86 @@ __device__ __forceinline__ double block_sum4(double v, double *red)
     return s;
 }
 
+// The plain launch (no dot products): the window walk alone.  (Sharing the dot forms
+// body, with its per-level fetches, made this launch a third slower.)
+template <int W, int MR>
+__global__ void __launch_bounds__(256)
+k_matvec2d_plain(const double *__restrict__ x, double *__restrict__ y,
+                 const double *__restrict__ bsub, int nx, int ny, int ell, Scheme sc,
+                 double kappa, int transpose)
+{
+    const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int iy0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * MR;
+    if (ix >= nx || iy0 >= ny) return;
+    const int up = sc.up;
+    const int dir = transpose ? -1 : 1;
+    const int kb = blockIdx.z * kMv2Seg;
+    const int ke = min(ell, kb + kMv2Seg);
+    const int k0 = transpose ? ke - 1 : kb;
+    const int cnt = ke - kb;
+    const size_t lv = (size_t)nx * ny;
+    const double hx = 1.0 / (nx + 1.0), hy = 1.0 / (ny + 1.0);
+    double P[W][MR], Q[W][MR];
+    auto fill = [&](int c, int L) {
+#pragma unroll
+        for (int o = 0; o < MR; ++o) P[c][o] = Q[c][o] = 0.0;
+        if (L >= 0 && L < ell) {
+            double v[MR + 2][3];
+            q1_load<MR>(x, (size_t)L * lv, nx, ny, ix, iy0, v);
+            q1_apply<MR>(v, hx, hy, P[c], Q[c]);
+        }
+    };
+#pragma unroll
+    for (int c = 0; c < W; ++c) fill(c, k0 - dir * (c - up));
+    for (int t = 0; t < kMv2Seg; ++t) {
+        if (t >= cnt) break;
+        const int k = k0 + dir * t;
+        double acc[MR];
+#pragma unroll
+        for (int o = 0; o < MR; ++o) acc[o] = 0.0;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            const int m = c - up;
+            const int src = transpose ? k + m : k - m;
+            const int row = transpose ? src : k;
+            double cm, cb2;
+            if (src >= 0 && src < ell && scheme_block(sc, row, m, cm, cb2)) {
+                const double ck = cb2 * kappa;
+#pragma unroll
+                for (int o = 0; o < MR; ++o) acc[o] += cm * P[c][o] + ck * Q[c][o];
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < MR; ++o) {
+            const bool own = iy0 + o < ny;
+            const size_t off = (size_t)k * lv + (size_t)(own ? iy0 + o : 0) * nx + ix;
+            const double out = bsub ? (own ? bsub[off] : 0.0) - acc[o] : acc[o];
+            if (own) y[off] = out;
+        }
+        if (t + 1 < cnt) {
+#pragma unroll
+            for (int c = W - 1; c > 0; --c)
+#pragma unroll
+                for (int o = 0; o < MR; ++o) {
+                    P[c][o] = P[c - 1][o];
+                    Q[c][o] = Q[c - 1][o];
+                }
+            fill(0, k + dir + dir * up);
+        }
+    }
+}
+
+// The GMRES forms (DOTS = 1 or 2).
 template <int W, int MR, int DOTS>
 __global__ void __launch_bounds__(256)
-k_matvec2d(const double *__restrict__ x, double *y, const double *__restrict__ bsub,
+k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
            int nx, int ny, int ell, Scheme sc, double kappa, int transpose, VecList V, int nv,
            double *__restrict__ part, int ldp)
 {
     constexpr int G = DOTS == 1 ? kMv2DotG : 1;
     const int ix = blockIdx.x * 64 + (threadIdx.x & 63);
     const int iy0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * MR;
-    const bool live = ix < nx && iy0 < ny;
-    if (DOTS == 0 && !live) return;       // (the dot forms keep every thread for the sums)
+    const bool live = ix < nx && iy0 < ny;   // every thread stays for the sums
     const int up = sc.up;
     const int dir = transpose ? -1 : 1;
     const int kb = blockIdx.z * kMv2Seg;
@@ -342,12 +411,13 @@ k_matvec2d(const double *__restrict__ x, double *y, const double *__restrict__ b
         }
 #pragma unroll
         for (int o = 0; o < MR; ++o) {
+            const size_t off = (size_t)k * lv + nofs[o];
             const double out = own[o] ? (bsub ? bc[o] - acc[o] : acc[o]) : 0.0;
-            if (DOTS > 0) yy += out * out;
+            yy += out * out;
 #pragma unroll
             for (int g = 0; g < G; ++g)
                 if (DOTS == 1) ad[g] += vc[g][o] * out;
-            if (own[o] && y) y[(size_t)k * lv + nofs[o]] = out;
+            if (own[o] && y) y[off] = out;
         }
         if (t + 1 < cnt) {
 #pragma unroll
@@ -361,7 +431,6 @@ k_matvec2d(const double *__restrict__ x, double *y, const double *__restrict__ b
             fetch(k + dir);
         }
     }
-    if (DOTS == 0) return;
     __shared__ double red[4];
     const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     if (DOTS == 2) {
@@ -399,11 +468,20 @@ static hipError_t matvec2d_go(const double *x, double *y, const double *bsub, in
 {
     constexpr int MR = DOTS > 0 ? kMv2RowsDot : kMv2Rows;
     dim3 grid((nx + 63) / 64, (ny + 4 * MR - 1) / (4 * MR), (ell + kMv2Seg - 1) / kMv2Seg);
-    switch (sc.s + sc.up + 1) {
-    case 2: k_matvec2d<2, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
-    case 3: k_matvec2d<3, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
-    case 4: k_matvec2d<4, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
-    default: return hipErrorInvalidValue;
+    if constexpr (DOTS == 0) {
+        switch (sc.s + sc.up + 1) {
+        case 2: k_matvec2d_plain<2, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+        case 3: k_matvec2d_plain<3, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+        case 4: k_matvec2d_plain<4, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (sc.s + sc.up + 1) {
+        case 2: k_matvec2d<2, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
+        case 3: k_matvec2d<3, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
+        case 4: k_matvec2d<4, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
