@@ -58,6 +58,16 @@ k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__r
     const int P = (n + CW - 1) / CW;
     const int a0 = t * CW;
     const int len = (t < P) ? min(CW, n - a0) : 0;
+
+    // The row's symbol and partition table are loaded before its data, so that their
+    // latency is not added after the data arrive; the table goes to LDS while the
+    // data loads are in flight.
+    const double *sj = sym + ((size_t)j * 2 + (transpose ? 1 : 0)) * 4;
+    const cx<A> d = {A(sj[0]), A(sj[1])};
+    const cx<A> e = {A(sj[2]), A(sj[3])};
+    const cx<A> *rtab = ptab + ((size_t)j * 2 + (transpose ? 1 : 0)) * psolve_tab_entries(CW);
+    const bool tab_lane = t < psolve_tab_entries(CW);
+    const cx<A> tv = tab_lane ? rtab[t] : cx<A>{A(0), A(0)};
     constexpr int PAD = 1;
     constexpr int OPAD = 1;
     const int NH = NT / 2;                       // threads per staged half
@@ -104,6 +114,7 @@ k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__r
                 }
         };
         load_half(0);
+        if (tab_lane) tab[t] = tv;               // (the table does not alias the staging)
         stage_half(0);
         load_half(H);
         __syncthreads();
@@ -119,15 +130,11 @@ k_shifted_solve(const cx<SI> *in, cx<SO> *out, int lds, int n, const double *__r
             const cx<SI> v = row[min(a0 + i, n - 1)];   // unconditional: all in flight
             if (i < len) y[i] = {A(v.x), A(v.y)};
         }
+        if (tab_lane) tab[t] = tv;
     }
 
-    // symbol of frequency j (tabulated per row and orientation)
-    const double *sj = sym + ((size_t)j * 2 + (transpose ? 1 : 0)) * 4;
-    const cx<A> d = {A(sj[0]), A(sj[1])};
-    const cx<A> e = {A(sj[2]), A(sj[3])};
-
-    const cx<A> *rtab = ptab + ((size_t)j * 2 + (transpose ? 1 : 0)) * psolve_tab_entries(CW);
-    const bool bad = partition_solve<A, CW, kTabGlobal>(y, n, d, e, tab, red, rtab);
+    // the table was written to LDS above; partition_solve's first barrier orders it
+    const bool bad = partition_solve<A, CW, kTabReady>(y, n, d, e, tab, red);
     if (STAGE) {
         for (int half = 0; half < 2; ++half) {
             const int q0 = half * H;

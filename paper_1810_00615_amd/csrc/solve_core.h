@@ -132,30 +132,24 @@ __device__ __forceinline__ void build_tab(cx<A> d, cx<A> e, int mlast, P tab)
 // eliminated unknowns are recovered level by level.  No pivoting, as in the
 // Thomas algorithm the method prescribes per block.
 //
-// Where partition_solve finds the table: built by thread 0, copied from a table
-// precomputed per row in global memory, or already written to LDS by the caller.
-enum TabSource { kTabBuild = 0, kTabGlobal = 1, kTabReady = 2 };
+// Where partition_solve finds the table: built by thread 0, or already written to LDS
+// by the caller (the shifted solves copy a table precomputed per row).
+enum TabSource { kTabBuild = 0, kTabReady = 2 };
 
-// tab: psolve_tab_entries(CW) entries of LDS (NT >= that count with kTabGlobal); red:
+// tab: psolve_tab_entries(CW) entries of LDS; red:
 // 6*NT entries (may alias a staging area the caller has finished reading: the first
 // barrier below precedes every write to it, and the last barrier follows every read).
 // With kTabReady the caller's writes to tab must precede the call's first barrier.
 // Every thread of the block must call it.  Returns true if a value is not finite.
 template <typename A, int CW, int TABSRC = kTabBuild>
-__device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *tab, cx<A> *red,
-                                const cx<A> *__restrict__ gtab = nullptr)
+__device__ bool partition_solve(cx<A> (&y)[CW], int n, cx<A> d, cx<A> e, cx<A> *tab, cx<A> *red)
 {
     const int NT = blockDim.x;
     const int t = threadIdx.x;
     const cx<A> zero = {A(0), A(0)};
     const int P = (n + CW - 1) / CW;                     // number of chunks / separators
     const int mlast = n - (P - 1) * CW - 1;              // interior length of the last chunk
-    if (TABSRC == kTabGlobal) {
-        // copy the precomputed table into LDS (read there as broadcasts)
-        if (t < psolve_tab_entries(CW)) tab[t] = gtab[t];
-    } else if (TABSRC == kTabBuild && t == 0) {
-        build_tab<A, CW>(d, e, mlast, tab);
-    }
+    if (TABSRC == kTabBuild && t == 0) build_tab<A, CW>(d, e, mlast, tab);
     const cx<A> *s_ip = tab, *s_cp = tab + CW, *s_gu = tab + 2 * CW, *s_end = tab + 3 * CW;
     // level-0 reduced system (a | c | d, NT each), then the neighbour terms and the
     // compacted deeper levels in the second half
