@@ -34,7 +34,10 @@ namespace {
 constexpr int kMaxRestart = 63;
 constexpr int kPartStride = 16384;   // partials per value (dot and fused-matvec blocks)
 constexpr int kSmallStride = 80;   // doubles per small-scalar array
-constexpr int kSmallArrays = 10;
+constexpr int kSmallArrays = 11;
+// k_reduce_small reads its partials with one workgroup; from this many values on, one
+// workgroup per value sums them first (a single workgroup's bandwidth bounds it there)
+constexpr int kPreSumValues = 6;
 
 struct Status {
     aao_status st;
@@ -125,6 +128,7 @@ struct aao_ctx_s {
     double *sa() { return small + 7 * kSmallStride; }    // re-orthogonalisation coefficients
     double *scv() { return small + 8 * kSmallStride; }   // update-pass coefficients (v_j)
     double *scw() { return small + 9 * kSmallStride; }   // update-pass coefficients (w1)
+    double *spsum() { return small + 10 * kSmallStride; }   // pre-summed partials
 };
 
 #define AAO_HIP(call)                                                                   \
@@ -653,6 +657,12 @@ static aao_status launch_small(aao_ctx ctx, int mode, int nv, int nblk)
     const SmallArgs sa{mode,       nv,        ctx->sh1(), ctx->sh2(), ctx->sc_(),
                        ctx->svs(), ctx->hdev, ctx->fail,  ctx->sa(),  ctx->scv(),
                        ctx->scw(), ctx->seq};
+    const int cnt = mode <= 1 ? nv : (mode >= 5 ? nv + 1 : 1);   // values k_reduce_small sums
+    if (cnt >= kPreSumValues && nblk > 1) {
+        AAO_HIP(launch_reduce_parts(ctx->part, nblk, ctx->ldp, cnt, ctx->spsum(), ctx->st));
+        AAO_HIP(launch_reduce_small(ctx->spsum(), 1, 1, sa, ctx->st));
+        return AAO_OK;
+    }
     AAO_HIP(launch_reduce_small(ctx->part, nblk, ctx->ldp, sa, ctx->st));
     return AAO_OK;
 }

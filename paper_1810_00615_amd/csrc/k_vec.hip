@@ -231,8 +231,19 @@ k_reduce_parts(const double *__restrict__ part, int nblk, int ldp, double *__res
 {
     __shared__ double red[256];
     const int i = blockIdx.x;
+    const double *p = part + (size_t)i * ldp;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(size_t)i * ldp + b];
+    // sixteen loads in flight per thread, then added in a fixed order
+    for (int base = 0; base < nblk; base += 16 * (int)blockDim.x) {
+        double v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int b = base + k * (int)blockDim.x + (int)threadIdx.x;
+            v[k] = b < nblk ? p[b] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += v[k];
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = blockDim.x / 2; off > 0; off >>= 1) {
