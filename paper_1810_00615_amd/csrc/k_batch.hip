@@ -627,19 +627,26 @@ __global__ void k_batch_reduce(const int2 *__restrict__ pslabs, int count,
                                const double *__restrict__ part, int ldp, int cnt,
                                double *__restrict__ sums, int sst)
 {
-    // one wave per problem: lane l sums blocks l, l + 64, ... of each slot, then a
-    // fixed shuffle tree (the order is the same on every run)
-    const int p = blockIdx.x;
-    if (p >= count || (active && !active[p])) return;
+    // one wave per (problem, value): lane l sums blocks l, l + 64, ... in order (eight
+    // loads in flight), then a fixed shuffle tree (the order is the same on every run)
+    const int p = blockIdx.x, i = blockIdx.y;
+    if (p >= count || i >= cnt || (active && !active[p])) return;
     const int2 rg = pslabs[p];                     // block range [x, y)
     const int lane = threadIdx.x;
-    for (int i = 0; i < cnt; ++i) {
-        double s = 0.0;
-        for (int b = rg.x + lane; b < rg.y; b += 64) s += part[(size_t)b * ldp + i];
+    double s = 0.0;
+    for (int b0 = rg.x; b0 < rg.y; b0 += 8 * 64) {
+        double v[8];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) sums[(size_t)p * sst + i] = s;
+        for (int k = 0; k < 8; ++k) {
+            const int b = b0 + k * 64 + lane;
+            v[k] = b < rg.y ? part[(size_t)b * ldp + i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) sums[(size_t)p * sst + i] = s;
 }
 
 // Per-problem Arnoldi bookkeeping and Givens update, one thread per problem.
@@ -1109,8 +1116,10 @@ hipError_t batch_cgs_delayed(const BatchLaunch &L, const double *const *V, int n
 hipError_t batch_reduce(const BatchLaunch &L, const double *part, int ldp, int cnt, double *sums,
                         int sst, bool masked, hipStream_t st, const int2 *ranges)
 {
-    k_batch_reduce<<<L.count, 64, 0, st>>>(ranges ? ranges : L.pslabs, L.count,
-                                           masked ? L.active : nullptr, part, ldp, cnt, sums, sst);
+    if (cnt < 1) return hipSuccess;
+    k_batch_reduce<<<dim3(L.count, cnt), 64, 0, st>>>(ranges ? ranges : L.pslabs, L.count,
+                                                      masked ? L.active : nullptr, part, ldp, cnt,
+                                                      sums, sst);
     return hipGetLastError();
 }
 
