@@ -296,6 +296,66 @@ def bench_wave(args):
     return out
 
 
+def bench_wave_schemes(args):
+    """BD4 (eq. BD4, system C_BD4) and central differences (eq. CenDiffDisc), n = 2047,
+    ell = 2048 (4.2 M unknowns): the preconditioner apply and its kernels, the matvec
+    (start-up rows, the block above the diagonal), and FGMRES(30) from the smooth
+    u_0 = sin 2 pi x to the paper's tolerance 1e-5 (Sec. 4) -- BD4 at this size,
+    central differences at n = 511, ell = 512 (beyond it its count grows, the poor
+    behaviour Sec. 4 reports for the scheme)."""
+    import numpy as np
+    import torch
+
+    from paper_1810_00615_amd import Problem
+    out = {}
+    kinds = ("fft_fwd", "shifted_solve", "fft_inv")
+    for sch in ("bd4", "cd"):
+        n, ell = 2047, 2048
+        P = Problem(n, ell, 1.0 / ell, sch, kappa=1.0)
+        if not args.no_tune:
+            P.tune(reps=3)
+        u0 = P.project_sine(np.array([2], dtype=np.int32), np.array([1.0]))
+        b = P.rhs(u0)
+        N, S = n * ell, (ell // 2 + 1) * n
+        z = P.empty()
+        for _ in range(2):
+            P.Pinv(b, out=z)
+        P.set_timing(True)
+        t, _ = _time(lambda: P.Pinv(b, out=z), 10)
+        kt = P.timing()
+        P.set_timing(False)
+        alg = 16 * N + 64 * S
+        rec = {"workload": f"wave_{sch}_n{n}_l{ell}", "unknowns": N,
+               "pinv_fp64": {"us": t * 1e6, "alg_bytes": alg, "GBps": alg / t / 1e9,
+                             "frac_hbm": alg / t / 1e9 / HBM_PEAK_GBPS,
+                             "kernel_avg_us": {k: kt[k][0] / max(kt[k][1], 1) * 1e3
+                                               for k in kinds}}}
+        P.set_timing(["matvec"])
+        _time(lambda: P.A(b, out=z), 10)
+        km = P.timing()["matvec"]
+        P.set_timing(False)
+        rec["matvec"] = {"us": km[0] / km[1] * 1e3, "GBps": km[2] / (km[0] * 1e-3) / 1e9,
+                         "frac_hbm": km[2] / (km[0] * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+        if sch == "cd":
+            P.close()
+            n, ell = 511, 512
+            P = Problem(n, ell, 1.0 / ell, sch, kappa=1.0)
+            if not args.no_tune:
+                P.tune(reps=3)
+            b = P.rhs(P.project_sine(np.array([2], dtype=np.int32), np.array([1.0])))
+        x = P.empty()
+        solve = lambda: P.solve(b, restart=30, tol=1e-5, maxit=300, out=x)[1]
+        solve()
+        t, info = _time(solve, 3)
+        rec["solve"] = {"n": n, "ell": ell, "tol": 1e-5, "solve_ms": t * 1e3,
+                        "iters": info["iters"], "true_rel_resid": info["rel_resid_true"],
+                        "converged": bool(info["converged"])}
+        out[sch] = rec
+        P.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_batch(args):
     """64 heat problems of uneven n, ell, kappa: batched mixed-precision FGMRES(30) to
     1e-8 (hipGraph replay), against the same 64 problems solved one after the other
@@ -555,7 +615,8 @@ def main():
     del P, x, b, u0
     torch.cuda.empty_cache()
     if not args.no_extra:
-        for key, fn in (("wave_bd2", bench_wave), ("batch", bench_batch),
+        for key, fn in (("wave_bd2", bench_wave), ("wave_bd4_cd", bench_wave_schemes),
+                        ("batch", bench_batch),
                         ("adjoint", bench_adjoint), ("beyond_cache", bench_beyond_cache),
                         ("square", bench_square)):
             try:

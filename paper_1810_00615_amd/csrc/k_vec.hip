@@ -666,30 +666,60 @@ hipError_t launch_neumann_rhs(const double *r, const double *scale, const double
 
 // Matvec of the schemes with start-up rows (BD4) or a block above the diagonal
 // (central differences): y_k = sum_m A_{k,k-m} x_{k-m}, or (transpose) y_k =
-// sum_m A_{k+m,k} x_{k+m} (every block symmetric); y = bsub - A x if bsub.  One
-// thread per output entry; the input rows of neighbouring threads and time levels
-// overlap, which the caches serve.
+// sum_m A_{k+m,k} x_{k+m} (every block symmetric); y = bsub - A x if bsub.  A thread
+// owns one spatial node and kMvWalkSeg consecutive output levels (downwards in time
+// for the transpose); the kMvWalkSeg + W - 1 input levels they touch (W = s + up + 1)
+// are loaded first, all at once (clamped, masked), and reduced to M x and K x at the
+// node, so each input level is read once per segment.  Slot j holds level
+// k0 - dir (s - j); output t takes offset m = c - up from slot t + W - 1 - c.  The
+// blocks come from scheme_block (start-up rows, the block above the diagonal).
+constexpr int kMvWalkSeg = 8;
+
+template <int W>
 __global__ void __launch_bounds__(256)
-k_matvec_gen(const double *__restrict__ x, double *__restrict__ y,
-             const double *__restrict__ bsub, int n, int ell, Scheme sc, double kappa,
-             int transpose)
+k_matvec_walk(const double *__restrict__ x, double *__restrict__ y,
+              const double *__restrict__ bsub, int n, int ell, Scheme sc, double kappa,
+              int transpose)
 {
+    constexpr int NL = kMvWalkSeg + W - 1;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
     if (i >= n) return;
+    const int up = sc.up;
+    const int dir = transpose ? -1 : 1;
+    const int kb = blockIdx.y * kMvWalkSeg;
+    const int ke = min(ell, kb + kMvWalkSeg);
+    const int k0 = transpose ? ke - 1 : kb;
+    const int cnt = ke - kb;
     const double h = 1.0 / (n + 1.0);
-    double acc = 0.0;
-    for (int m = -sc.up; m <= sc.s; ++m) {
-        const int src = transpose ? k + m : k - m;
-        const int row = transpose ? k + m : k;
-        if (src < 0 || src >= ell) continue;
-        double cm, cb;
-        if (!scheme_block(sc, row, m, cm, cb)) continue;
-        const double *xr = x + (size_t)src * n;
-        const double xl = i > 0 ? xr[i - 1] : 0.0, xc = xr[i], xrr = i < n - 1 ? xr[i + 1] : 0.0;
-        acc += cm * (h / 6.0) * (xl + 4.0 * xc + xrr) + cb * kappa * (1.0 / h) * (2.0 * xc - xl - xrr);
+    const int il = i > 0 ? i - 1 : 0, ir = i < n - 1 ? i + 1 : i;
+    const double ml = i > 0 ? 1.0 : 0.0, mr = i < n - 1 ? 1.0 : 0.0;
+    double P[NL], Q[NL];               // (M x)_i and (K x)_i of the touched levels
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        const int L = k0 - dir * (sc.s - j);
+        const double w = (L >= 0 && L < ell) ? 1.0 : 0.0;
+        const double *row = x + (size_t)(L >= 0 && L < ell ? L : 0) * n;
+        const double l = w * ml * row[il], cc = w * row[i], r = w * mr * row[ir];
+        P[j] = (h / 6.0) * (l + 4.0 * cc + r);
+        Q[j] = (1.0 / h) * (2.0 * cc - l - r);
     }
-    y[(size_t)k * n + i] = bsub ? bsub[(size_t)k * n + i] - acc : acc;
+#pragma unroll
+    for (int t = 0; t < kMvWalkSeg; ++t) {
+        if (t >= cnt) continue;
+        const int k = k0 + dir * t;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            const int m = c - up;
+            const int src = transpose ? k + m : k - m;
+            const int row = transpose ? src : k;
+            double cm, cb;
+            if (src >= 0 && src < ell && scheme_block(sc, row, m, cm, cb))
+                acc += cm * P[t + W - 1 - c] + cb * kappa * Q[t + W - 1 - c];
+        }
+        const size_t o = (size_t)k * n + i;
+        y[o] = bsub ? bsub[o] - acc : acc;
+    }
 }
 
 hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, int ell,
@@ -699,8 +729,13 @@ hipError_t launch_matvec(const double *x, double *y, const double *bsub, int n, 
     if (scheme_generic(sc)) {
         // no fused dot products, no variable steps for these schemes
         if (nv > 0 || tau_k || !y) return hipErrorInvalidValue;
-        dim3 grid((n + 255) / 256, ell);
-        k_matvec_gen<<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, transpose);
+        dim3 grid((n + 255) / 256, (ell + kMvWalkSeg - 1) / kMvWalkSeg);
+        switch (sc.s + sc.up + 1) {
+        case 2: k_matvec_walk<2><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, transpose); break;
+        case 3: k_matvec_walk<3><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, transpose); break;
+        case 4: k_matvec_walk<4><<<grid, 256, 0, st>>>(x, y, bsub, n, ell, sc, kappa, transpose); break;
+        default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     if (cfg < 0 || cfg >= matvec_num_configs()) cfg = matvec_default_config();

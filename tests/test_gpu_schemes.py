@@ -59,7 +59,8 @@ def test_rhs(dev, orc, scheme, n, ell):
 
 @pytest.mark.parametrize("scheme", [BD4, CD])
 @pytest.mark.parametrize("transpose", [False, True])
-@pytest.mark.parametrize("n,ell", [(1, 1), (1, 4), (5, 3), (64, 17), (130, 33), (257, 100)])
+@pytest.mark.parametrize("n,ell", [(1, 1), (1, 4), (5, 3), (64, 17), (130, 33), (257, 100),
+                                   (513, 24)])
 def test_apply_A(dev, orc, scheme, transpose, n, ell):
     from paper_1810_00615_amd import Problem
     tau, kappa = 1.0 / ell, 0.9
