@@ -863,35 +863,38 @@ __global__ void k_batch_chirp(const BProb *__restrict__ probs, int count,
 
 // Filter spectra by a direct DFT of length M (setup only):
 //   forward filter  b_m = conj(c_m), |m| < ell (wrapped), inverse filter c_m.
-__global__ void k_batch_bhat(const BProb *__restrict__ probs, int count,
-                             const cx<double> *__restrict__ chirp, cx<double> *__restrict__ bhat)
+// Filter spectra of a problem: the forward filter b_m = conj(c_m) (m < ell) and
+// conj(c_{M-m}) (m > M - ell), zero between (M >= 2 ell - 1), is even in m, so its
+// length-M DFT is B_q = conj(c_0) + 2 sum_{m=1}^{ell-1} conj(c_m) cos(2 pi q m / M); the
+// inverse filter's (c in place of conj c) is conj(B_q).  The cosines come from a
+// table of the M-th roots in LDS (exact index q m mod M), one workgroup row of q.
+__global__ void __launch_bounds__(256)
+k_batch_bhat(const BProb *__restrict__ probs, int count, const cx<double> *__restrict__ chirp,
+             cx<double> *__restrict__ bhat)
 {
+    __shared__ double cosq[4096];
     const int p = blockIdx.y;
     if (p >= count) return;
     const BProb pb = probs[p];
     const int M = pb.M, ell = pb.ell;
+    if ((int)blockIdx.x * (int)blockDim.x >= M) return;   // (uniform over the workgroup)
+    for (int k = threadIdx.x; k < M; k += blockDim.x) cosq[k] = cospi(2.0 * k / (double)M);
+    __syncthreads();
     const cx<double> *ch = chirp + pb.coff;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < M; q += gridDim.x * blockDim.x) {
-        double fr = 0.0, fi = 0.0, ir = 0.0, ii = 0.0;
-        for (int m = 0; m < M; ++m) {
-            int src = -1;
-            if (m < ell) src = m;
-            else if (m > M - ell) src = M - m;
-            if (src < 0) continue;
-            const cx<double> cm = ch[src];
-            const long long ph = ((long long)q * m) % M;
-            double s, c;
-            sincospi(-2.0 * (double)ph / (double)M, &s, &c);
-            // forward filter conj(c): (cm.x - i cm.y) (c + i s)
-            fr += cm.x * c + cm.y * s;
-            fi += cm.x * s - cm.y * c;
-            // inverse filter c: (cm.x + i cm.y) (c + i s)
-            ir += cm.x * c - cm.y * s;
-            ii += cm.x * s + cm.y * c;
-        }
-        bhat[pb.boff + q] = {fr, fi};
-        bhat[pb.boff + M + q] = {ir, ii};
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M) return;
+    double fr = 0.0, fi = 0.0;
+    for (int m = 1; m < ell; ++m) {
+        const double cs = cosq[(int)(((long long)q * m) & (M - 1))];
+        const cx<double> cm = ch[m];
+        fr += cm.x * cs;
+        fi -= cm.y * cs;
     }
+    const cx<double> c0 = ch[0];
+    fr = c0.x + 2.0 * fr;
+    fi = -c0.y + 2.0 * fi;
+    bhat[pb.boff + q] = {fr, fi};
+    bhat[pb.boff + M + q] = {fr, -fi};
 }
 
 // ------------------------------------------------------------- launchers
