@@ -18,33 +18,54 @@
 namespace aao {
 
 // ------------------------------------------------------------ sine transform
-// out[k][p][i] = sqrt(2/(ny+1)) sum_q in[k][q][i] sin(pi p q/(ny+1)), p, q = 1..ny.
-// Two neighbouring columns (a, b) of a level form one complex sequence v = a + i b.
-// Its odd extension z of length L = 2(ny+1) (z_0 = z_{ny+1} = 0, z_q = v_q,
-// z_{L-q} = -v_q) has the DFT Z_p = -2i (A_p + i B_p), A and B the unnormalised sine
-// transforms of a and b, so A_p = -Im Z_p / 2 and B_p = Re Z_p / 2.
+// out[k][p][i] = sqrt(2/N) sum_q in[k][q][i] sin(pi p q / N), p, q = 1..ny, N = ny + 1.
+// A length-N transform per column (half the length of the odd extension), by the
+// sine-weighted fold of the sequence with its mirror:
+//   y_0 = 0,  y_q = sin(pi q/N) (f_q + f_{N-q}) + (f_q - f_{N-q}) / 2,  q = 1..N-1,
+// whose DFT Y_k = sum_q y_q exp(2 pi i q k/N) gives, for real f,
+//   S_{2k} = Im Y_k,   S_{2k+1} - S_{2k-1} = Re Y_k  (S_{-1} = -S_1),
+// since the symmetric part of y carries only cosines and the antisymmetric part only
+// sines, and 2 sin(pi q/N) cos(2 pi q k/N) = sin(pi q (2k+1)/N) - sin(pi q (2k-1)/N).
+// The odd coefficients are therefore a running sum over k.  Two neighbouring real
+// columns (a, b) of a level go through one complex transform as f = a + i b; with
+// Z the forward DFT of y (exp(-2 pi i q k/N)), Y_k = Z_{N-k}, and the two real
+// spectra separate by the conjugate symmetry Y^a_k = (Y_k + conj Y_{N-k}) / 2,
+// Y^b_k = (Y_k - conj Y_{N-k}) / (2 i):
+//   2 S^a_{2k} = Im Z_{N-k} - Im Z_k,   2 S^b_{2k} = Re Z_k - Re Z_{N-k},
+//   2 S^a_{2k+1} = sum_{j<=k} d^a_j,  d^a_j = Re Z_j + Re Z_{N-j} (j >= 1), d^a_0 = Re Z_0,
+// and likewise d^b with the imaginary parts.
 // The transform along y has the shape of the time-axis transforms (a strided axis,
-// contiguous columns), so it runs on the same register-resident radix-16 Stockham
-// machinery: a workgroup owns W complex columns (2W real columns, one row segment of
-// 16 W bytes per row) of one level, thread (t, c) holds P points of column c, and the
-// stages exchange through LDS one real plane at a time.  The rows enter through LDS
-// in whole row segments, so each is read from memory once (the mirrored positions of
-// the extension read LDS).  (Staging the output rows as well raised the register
-// count past the two workgroups per compute unit that the LDS allows.)
+// contiguous columns), so it runs on the same register-resident Stockham machinery
+// (radix 8): a workgroup owns W complex columns (2W real columns, one row segment of
+// 16 W bytes per row) of one level, thread (t, c) holds P points of column c.  The
+// rows enter through LDS in whole row segments, so each is read from memory once and
+// the mirrored reads of the fold come from LDS.  After the transform the spectrum
+// goes to LDS once more; thread (t, c) then owns k = tK .. tK + K - 1 (K = P/2): the
+// even outputs and its part of the running sum, completed by a shuffle scan over the
+// threads of its column in the wave and the totals of the waves before it.
 bool dst_y_supported(int ny) { return ny >= 1 && ny <= 2047 && ((ny + 1) & ny) == 0; }
 
-template <int L>
-constexpr int dst_points() { return L < 16 ? L : 16; }
-// workgroup size bound: dst_cols keeps lengths up to 1024 within 512 threads
-template <int L>
-constexpr int dst_max_threads() { return L >= 2048 ? 1024 : 512; }
+template <int N>
+constexpr int dst_points() { return N < 8 ? N : 8; }
 
-template <int L>
-__global__ void __launch_bounds__(dst_max_threads<L>())
-k_dst_y(const double *in, double *out, int nx, int ny, int ell, int W,
-        const cx<double> *__restrict__ tw)
+// LDS bytes of a workgroup of W complex columns: the staged rows ((N - 1) 2W doubles),
+// one exchange plane (lds_rows(N) W doubles) and the spectrum (rows k + k/8 < N + N/8,
+// W complex each) plus the per-wave running-sum totals share one buffer.
+static size_t dst_lds(int N, int W)
 {
-    constexpr int P = dst_points<L>();
+    const int P = N < 8 ? N : 8;
+    const int waves = (W * (N / P) + 63) / 64;
+    const size_t stage = (size_t)(N - 1) * 2 * W * 8;
+    const size_t plane = (size_t)(N + N / 16 + 1) * W * 8;
+    const size_t spec = ((size_t)(N + N / 8 + 1) + waves) * W * 16;
+    return stage > plane ? (stage > spec ? stage : spec) : (plane > spec ? plane : spec);
+}
+
+template <int N>
+__global__ void __launch_bounds__(1024)
+k_dst_y(const double *in, double *out, int nx, int ell, int W, const cx<double> *__restrict__ tw)
+{
+    constexpr int P = dst_points<N>(), TN = N / P, K = P / 2 > 0 ? P / 2 : 1, ny = N - 1;
     extern __shared__ unsigned char dsm_raw[];
     double *sm = reinterpret_cast<double *>(dsm_raw);
     const int NT = blockDim.x;
@@ -57,13 +78,13 @@ k_dst_y(const double *in, double *out, int nx, int ny, int ell, int W,
     const int xb = (g - lvl * tiles_x) * 2 * W;   // first real column of the tile
     const int W2 = 2 * W, lw2 = __ffs(W2) - 1;    // W is a power of two
     const size_t base = (size_t)lvl * ny * nx;
-    // The tile's ny rows of 2W doubles pass through LDS (row q at sm[q * 2W]): each
-    // row is read from memory once, in 2W-double segments, and the mirrored positions
-    // of the extension read LDS instead.  ny * 2W < P * NT, so P passes cover it;
-    // they go in groups of eight loads (all in flight, then written).
-    constexpr int GL = P < 8 ? P : 8;
+    // The tile's ny rows of 2W doubles pass through LDS (row q at sm[q * 2W]):
+    // ny * 2W < 2P * NT, so 2P passes cover it, in groups of eight loads (all in
+    // flight, then written).
+    constexpr int NL = 2 * P;
+    constexpr int GL = NL < 8 ? NL : 8;
 #pragma unroll
-    for (int u0 = 0; u0 < P; u0 += GL) {
+    for (int u0 = 0; u0 < NL; u0 += GL) {
         double val[GL];
 #pragma unroll
         for (int u = 0; u < GL; ++u) {
@@ -79,45 +100,94 @@ k_dst_y(const double *in, double *out, int nx, int ny, int ell, int W,
         __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
+    // the fold: rows q - 1 and N - q - 1 of the column pair, sin(pi q/N) = -Im tw[q]
+    // (tw holds exp(-2 pi i k / 2N))
+    const double2 *rows = reinterpret_cast<const double2 *>(sm);
     cx<double> v[P];
 #pragma unroll
     for (int idx = 0; idx < P; ++idx) {
-        const int pos = first_pos<L, P>(t, idx);
-        const bool lo = pos <= ny;                 // z_pos = v_pos, else -v_{L-pos}
-        const int q = lo ? pos : L - pos;          // 1..ny for data, 0 / ny+1 for zeros
-        const bool data = q >= 1 && q <= ny;
-        const double2 ab = *reinterpret_cast<const double2 *>(sm + ((data ? q - 1 : 0) << lw2) + 2 * c);
-        const double a = data ? ab.x : 0.0, b = data ? ab.y : 0.0;
-        v[idx] = lo ? cx<double>{a, b} : cx<double>{-a, -b};
+        const int q = first_pos<N, P>(t, idx);
+        const bool data = q >= 1;
+        const double2 fq = rows[(data ? q - 1 : 0) * W + c];
+        const double2 fm = rows[(data ? N - q - 1 : 0) * W + c];
+        const double s = data ? -tw[q].y : 0.0, h = data ? 0.5 : 0.0;
+        v[idx] = {s * (fq.x + fm.x) + h * (fq.x - fm.x), s * (fq.y + fm.y) + h * (fq.y - fm.y)};
     }
     __syncthreads();                               // staging read before the first exchange
-    run_stages<double, L, P, 0, false>(v, sm, t, c, W, tw, 1);
-    const double f = 0.5 * sqrt(2.0 / (ny + 1.0));
+    run_stages<double, N, P, 0, false>(v, sm, t, c, W, tw, 2);
+    // spectrum to LDS (every exchange read has passed its barrier)
+    double2 *zs = reinterpret_cast<double2 *>(sm);
+#pragma unroll
+    for (int idx = 0; idx < P; ++idx) {
+        const int k = final_pos<N, P>(t, idx);
+        zs[(k + (k >> 3)) * W + c] = make_double2(v[idx].x, v[idx].y);
+    }
+    __syncthreads();
+    double ea[K], eb[K], pa[K], pb[K];
+    double ra = 0.0, rb = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int k = t * K + i, km = (N - k) & (N - 1);
+        const double2 z = zs[(k + (k >> 3)) * W + c];
+        const double2 zm = zs[(km + (km >> 3)) * W + c];
+        ea[i] = zm.y - z.y;
+        eb[i] = z.x - zm.x;
+        const double w = k == 0 ? 0.5 : 1.0;       // d_0 = Re / Im Z_0
+        ra += w * (z.x + zm.x);
+        rb += w * (z.y + zm.y);
+        pa[i] = ra;
+        pb[i] = rb;
+    }
+    // inclusive scan of the thread sums over t: the threads of column c sit W lanes apart
+    const int lane = threadIdx.x & 63;
+    double sa = ra, sb = rb;
+    for (int d = W; d < 64; d <<= 1) {
+        const double oa = __shfl_up(sa, d, 64), ob = __shfl_up(sb, d, 64);
+        if (lane >= d) {
+            sa += oa;
+            sb += ob;
+        }
+    }
+    double xa = sa - ra, xb2 = sb - rb;             // exclusive within the wave
+    if (NT > 64) {                                  // uniform over the workgroup
+        double2 *wt = zs + (N + N / 8 + 1) * W;
+        const int wv = threadIdx.x >> 6;
+        if (lane >= 64 - W) wt[wv * W + c] = make_double2(sa, sb);
+        __syncthreads();
+        for (int w2 = 0; w2 < wv; ++w2) {
+            const double2 o = wt[w2 * W + c];
+            xa += o.x;
+            xb2 += o.y;
+        }
+    }
+    const double f = 0.5 * sqrt(2.0 / N);
     const int x0 = xb + 2 * c;
     const bool ha = x0 < nx, hb = x0 + 1 < nx;
 #pragma unroll
-    for (int idx = 0; idx < P; ++idx) {
-        const int p = final_pos<L, P>(t, idx);
-        if (p >= 1 && p <= ny) {
-            const size_t o = base + (size_t)(p - 1) * nx + x0;
-            if (ha) out[o] = -f * v[idx].y;
-            if (hb) out[o + 1] = f * v[idx].x;
+    for (int i = 0; i < K; ++i) {
+        const int k = t * K + i;
+        if (k >= 1) {                               // p = 2k
+            const size_t o = base + (size_t)(2 * k - 1) * nx + x0;
+            if (ha) out[o] = f * ea[i];
+            if (hb) out[o + 1] = f * eb[i];
         }
+        const size_t o = base + (size_t)(2 * k) * nx + x0;   // p = 2k + 1
+        if (ha) out[o] = f * (xa + pa[i]);
+        if (hb) out[o + 1] = f * (xb2 + pb[i]);
     }
 }
 
 // complex columns per workgroup: a 128-byte row segment where the thread and LDS
-// budgets allow (at most 512 threads up to length 1024, else 1024; 80 KB of LDS so
-// that two workgroups share a compute unit, else 160 KB), no wider than the grid needs
-static int dst_cols(int L, int nx)
+// budgets allow (at most 1024 threads; 80 KB of LDS so that two workgroups share a
+// compute unit, else 160 KB), no wider than the grid needs
+static int dst_cols(int N, int nx)
 {
-    const int P = L < 16 ? L : 16;
+    const int P = N < 8 ? N : 8;
     const int need = (nx + 1) / 2;
-    const int maxt = L >= 2048 ? 1024 : 512;
     int best = 1;
     for (int W = 1; W <= 64; W *= 2) {
-        const size_t lds = (size_t)lds_rows(L) * W * sizeof(double);
-        if (W * (L / P) > maxt || lds > 160 * 1024) break;
+        const size_t lds = dst_lds(N, W);
+        if (W * (N / P) > 1024 || lds > 160 * 1024) break;
         if (W > 8 && lds > 80 * 1024) break;
         best = W;
         if (W >= need) break;
@@ -125,14 +195,14 @@ static int dst_cols(int L, int nx)
     return best;
 }
 
-template <int L>
-static hipError_t dst_go(const double *in, double *out, int nx, int ny, int ell,
-                         const double *tw, hipStream_t st)
+template <int N>
+static hipError_t dst_go(const double *in, double *out, int nx, int ell, const double *tw,
+                         hipStream_t st)
 {
-    const int W = dst_cols(L, nx);
-    const int threads = W * (L / dst_points<L>());
-    const size_t smem = (size_t)lds_rows(L) * W * sizeof(double);
-    auto kern = k_dst_y<L>;
+    const int W = dst_cols(N, nx);
+    const int threads = W * (N / dst_points<N>());
+    const size_t smem = dst_lds(N, W);
+    auto kern = k_dst_y<N>;
     if (smem > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -140,7 +210,7 @@ static hipError_t dst_go(const double *in, double *out, int nx, int ny, int ell,
     }
     const long long tiles = (long long)((nx + 2 * W - 1) / (2 * W)) * ell;
     if (tiles > (1LL << 30)) return hipErrorInvalidValue;
-    kern<<<xcd_grid((int)tiles), threads, smem, st>>>(in, out, nx, ny, ell, W,
+    kern<<<xcd_grid((int)tiles), threads, smem, st>>>(in, out, nx, ell, W,
                                                      reinterpret_cast<const cx<double> *>(tw));
     return hipGetLastError();
 }
@@ -149,18 +219,18 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
                         hipStream_t st)
 {
     if (!dst_y_supported(ny) || nx < 1 || ell < 1 || !tw) return hipErrorInvalidValue;
-    switch (2 * (ny + 1)) {
-    case 4: return dst_go<4>(in, out, nx, ny, ell, tw, st);
-    case 8: return dst_go<8>(in, out, nx, ny, ell, tw, st);
-    case 16: return dst_go<16>(in, out, nx, ny, ell, tw, st);
-    case 32: return dst_go<32>(in, out, nx, ny, ell, tw, st);
-    case 64: return dst_go<64>(in, out, nx, ny, ell, tw, st);
-    case 128: return dst_go<128>(in, out, nx, ny, ell, tw, st);
-    case 256: return dst_go<256>(in, out, nx, ny, ell, tw, st);
-    case 512: return dst_go<512>(in, out, nx, ny, ell, tw, st);
-    case 1024: return dst_go<1024>(in, out, nx, ny, ell, tw, st);
-    case 2048: return dst_go<2048>(in, out, nx, ny, ell, tw, st);
-    case 4096: return dst_go<4096>(in, out, nx, ny, ell, tw, st);
+    switch (ny + 1) {
+    case 2: return dst_go<2>(in, out, nx, ell, tw, st);
+    case 4: return dst_go<4>(in, out, nx, ell, tw, st);
+    case 8: return dst_go<8>(in, out, nx, ell, tw, st);
+    case 16: return dst_go<16>(in, out, nx, ell, tw, st);
+    case 32: return dst_go<32>(in, out, nx, ell, tw, st);
+    case 64: return dst_go<64>(in, out, nx, ell, tw, st);
+    case 128: return dst_go<128>(in, out, nx, ell, tw, st);
+    case 256: return dst_go<256>(in, out, nx, ell, tw, st);
+    case 512: return dst_go<512>(in, out, nx, ell, tw, st);
+    case 1024: return dst_go<1024>(in, out, nx, ell, tw, st);
+    case 2048: return dst_go<2048>(in, out, nx, ell, tw, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -325,10 +325,12 @@ def test_wave_2d_modes(dev, scheme):
     assert e < 1e-8 and worst < 1e-7
 
 
-@pytest.mark.parametrize("ny", [1, 2047])
+@pytest.mark.parametrize("ny", [1, 255, 511, 1023, 2047])
 def test_pinv_2d_sine_length_extremes(dev, ny):
-    """The sine transform at its shortest (ny = 1) and longest (ny = 2047, odd extension of
-    length 4096) lengths, with a ragged column tile, against the eigen-decomposition."""
+    """The sine transform at its shortest (ny = 1, a length-2 transform) and longest
+    (ny = 2047, length 2048) lengths and the long lengths between, whose running sum of
+    odd coefficients spans several waves, with a ragged column tile, against the
+    eigen-decomposition."""
     import pins
     from paper_1810_00615_amd import Problem2D
     nx, ell = 5, 8
