@@ -121,7 +121,12 @@ aao_status aao_create(int64_t n, int64_t ell, double tau, int scheme, aao_ctx *o
  * aao_tune, aao_get_config, aao_set_config, aao_config_shape (the shifted solves'
  * shapes apply to rows of nx unknowns).  aao_set_steps, aao_set_neumann_order (q >
  * 0), aao_project_sine, aao_grad and aao_grad_checkpointed return
- * AAO_ERR_UNSUPPORTED. */
+ * AAO_ERR_UNSUPPORTED.
+ * aao_gmres, aao_gmres_ex and aao_adjoint_solve iterate in sine coordinates along y
+ * (the sine transform is orthonormal and its own inverse, so the steps and residual
+ * norms are those of the nodal system): the right-hand side is transformed into one
+ * more vector of the context (allocated on the first solve), the iterate in place on
+ * entry and exit; x holds nodal values when the call returns, also after a failure. */
 aao_status aao_create_2d(int64_t nx, int64_t ny, int64_t ell, double tau, int scheme,
                          aao_ctx *out);
 

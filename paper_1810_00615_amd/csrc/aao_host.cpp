@@ -49,6 +49,8 @@ struct aao_ctx_s {
     int64_t n = 0, ell = 0;      // n: unknowns per time level (nx ny on the unit square)
     int nx = 0, ny = 0;          // unit square (aao_create_2d); ny = 0 in one dimension
     double *twy = nullptr;       // twiddles of the sine transform's length 2 (ny + 1)
+    bool hat = false;            // unit square: operators in sine coordinates along y
+    double *bhat = nullptr;      // GMRES right-hand side in those coordinates
     double tau = 0.0;
     int scheme = 0;
     double kappa = 1.0;
@@ -321,7 +323,8 @@ static aao_status apply_A_impl(aao_ctx ctx, const double *x, double *y, const do
     if (ctx->ny > 0) {
         AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (bsub ? 3 : 2),
                      launch_matvec2d(x, y, bsub, ctx->nx, ctx->ny, (int)ctx->ell, ctx->sc,
-                                     ctx->kappa, transpose, ctx->st));
+                                     ctx->kappa, transpose, ctx->st, nullptr, 0, nullptr, 0,
+                                     ctx->hat));
         return AAO_OK;
     }
     AAO_LAUNCH_B(AAO_K_MATVEC, vec_bytes(ctx) * (bsub ? 3 : 2),
@@ -403,19 +406,20 @@ static aao_status pinv_once(aao_ctx ctx, const double *r, const double *in_scale
     // nothing reads before the inverse transform overwrites it, so the apply touches no
     // more memory than the FP64 one (the 64 MB of cache it would otherwise displace
     // slow the transforms down by a fifth)
-    if (ispec == ctx->spec_in && !zprev && !ctx->bluestein && ctx->ny == 0 &&
+    if (ispec == ctx->spec_in && !zprev && !ctx->bluestein && (ctx->ny == 0 || ctx->hat) &&
         (double)(ctx->ell / 2 + 1) * ctx->lds <= (double)ctx->N())
         ispec = z;
     AAO_TRY(refresh_symbols(ctx));
     AAO_TRY(refresh_tables(ctx, ctx->cf(AAO_CFG_SHIFTED_SOLVE), true));
     const double solve_bytes = spec_in_bytes(ctx) + spec_out_bytes(ctx);
-    const bool sq = ctx->ny > 0;
+    // unit square: C^{-1} = S_y F^{-1} [solves] F S_y (S_y the sine transform in y,
+    // which commutes with the time transform F); in sine coordinates (GMRES) the
+    // middle factor alone
+    if (ctx->ny > 0 && zprev) return AAO_ERR_UNSUPPORTED;
+    const bool sq = ctx->ny > 0 && !ctx->hat;
     if (sq) {
-        // unit square: C^{-1} = S_y F^{-1} [solves] F S_y (S_y the sine transform in y,
-        // which commutes with the time transform F)
         // (S_y r goes to z, which the time transform reads before the inverse transform
         // overwrites it: no extra vector in the working set)
-        if (zprev) return AAO_ERR_UNSUPPORTED;
         AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
                      launch_dst_y(r, z, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
         r = z;
@@ -687,9 +691,48 @@ static aao_status wait_small(aao_ctx ctx)
 
 // ------------------------------------------------------------------ GMRES
 
+static aao_status gmres_core(aao_ctx ctx, const double *b, double *x, int m, double tol,
+                             int maxit, aao_info *info, int transpose, bool zero_guess,
+                             bool classic, bool early_always);
+
+// On the unit square GMRES runs in sine coordinates along y: S_y is orthonormal and
+// its own inverse, so FGMRES on (S_y A S_y) (S_y x) = S_y b takes the same steps with
+// the same residual norms, while its operators lose both sine transforms of every
+// preconditioner apply (C^{-1} becomes F^{-1} [solves] F) and the 9-point stencils
+// become 3-point ones per sine mode.  b is transformed once into a vector of the
+// context, x on entry (unless it is a zero guess) and on exit.
 static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, double tol,
                              int maxit, aao_info *info, int transpose, bool zero_guess,
                              bool classic = false, bool early_always = false)
+{
+    if (ctx->ny == 0 || ctx->hat)
+        return gmres_core(ctx, b, x, m, tol, maxit, info, transpose, zero_guess, classic,
+                          early_always);
+    if (m < 1 || m > kMaxRestart) return arg_err(ctx, "restart must be in [1, 63]");
+    if (!(tol >= 0.0) || maxit < 0) return arg_err(ctx, "bad tol / maxit");
+    if (!b || !x) return arg_err(ctx, "null vector");
+    const size_t N = ctx->N();
+    if (overlap(b, x, N * sizeof(double))) return arg_err(ctx, "b and x overlap");
+    if (!ctx->bhat) AAO_TRY(dev_alloc(ctx, (void **)&ctx->bhat, sizeof(double) * N));
+    const int ell = (int)ctx->ell;
+    AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
+                 launch_dst_y(b, ctx->bhat, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
+    if (!zero_guess)
+        AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
+                     launch_dst_y(x, x, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
+    ctx->hat = true;
+    const aao_status s = gmres_core(ctx, ctx->bhat, x, m, tol, maxit, info, transpose, zero_guess,
+                                    classic, early_always);
+    ctx->hat = false;
+    // back to nodal values, also after a failed solve (x then holds the last iterate)
+    AAO_LAUNCH_B(AAO_K_SINE_Y, 2 * vec_bytes(ctx),
+                 launch_dst_y(x, x, ctx->nx, ctx->ny, ell, ctx->twy, ctx->st));
+    return s;
+}
+
+static aao_status gmres_core(aao_ctx ctx, const double *b, double *x, int m, double tol,
+                             int maxit, aao_info *info, int transpose, bool zero_guess,
+                             bool classic, bool early_always)
 {
     if (m < 1 || m > kMaxRestart) return arg_err(ctx, "restart must be in [1, 63]");
     if (!(tol >= 0.0) || maxit < 0) return arg_err(ctx, "bad tol / maxit");
@@ -720,7 +763,7 @@ static aao_status gmres_impl(aao_ctx ctx, const double *b, double *x, int m, dou
     auto mv_dots = [&](const double *xin, double *out, const double *bs, const VecList *L,
                        int cnt) -> hipError_t {
         return sq ? launch_matvec2d(xin, out, bs, ctx->nx, ctx->ny, ell, ctx->sc, ctx->kappa,
-                                    transpose, st, L, cnt, ctx->part, ldp)
+                                    transpose, st, L, cnt, ctx->part, ldp, ctx->hat)
                   : launch_matvec(xin, out, bs, n, ell, ctx->sc, ctx->kappa, ctx->tauk,
                                   transpose, st, mcfg, L, cnt, ctx->part, ldp);
     };
@@ -1175,6 +1218,7 @@ aao_status aao_destroy(aao_ctx ctx)
     (void)hipFree(ctx->segpart);
     (void)hipFree(ctx->ntmp);
     (void)hipFree(ctx->twy);
+    (void)hipFree(ctx->bhat);
     (void)hipFree(ctx->bl_prob);
     (void)hipFree(ctx->bl_tiles);
     (void)hipFree(ctx->bl_chirp);

@@ -272,11 +272,12 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
 // launch also leaves the block partials of V_q . y (q < nv) and of y . y (value nv);
 // nv == 1 with V->p[0] == y only those of y . y (value 0); y may then be null.
 // matvec2d_blocks(..., true) partials per value.  With nv > matvec2d_dot_walk() the
-// dots past the first ones read y back, so y must not be null.
+// dots past the first ones read y back, so y must not be null.  With hat the vectors
+// are in sine coordinates along y (S_y A S_y: x-stencils per sine mode).
 hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
                            int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
                            const VecList *V = nullptr, int nv = 0, double *part = nullptr,
-                           int ldp = 0);
+                           int ldp = 0, bool hat = false);
 int matvec2d_blocks(int nx, int ny, int ell, bool dots);
 int matvec2d_dot_walk();
 // Right-hand side of every scheme on the unit square (the first rows, zeros after).

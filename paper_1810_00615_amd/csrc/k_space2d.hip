@@ -240,6 +240,11 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
 //   M2 = My (x) Mx:  hx hy / 36 * [1 4 1] (x) [1 4 1],
 //   K2 = Ky (x) Mx + My (x) Kx:  hx/(6 hy) [-1 2 -1]_y [1 4 1]_x + hy/(6 hx) [1 4 1]_y [-1 2 -1]_x;
 // the loads are issued at clamped addresses and masked.
+// In sine coordinates along y (row q of a level holding the coefficient of the q-th
+// sine mode) the same operators are S_y M2 S_y = diag(my_q) (x) Mx and
+// S_y K2 S_y = diag(ky_q) (x) Mx + diag(my_q) (x) Kx, with
+// my_q = hy/6 e_q, ky_q = (6 - e_q)/hy, e_q = 4 + 2 cos(pi q/(ny + 1)):
+// a three-point stencil within the row (HAT below).
 
 // ------------------------------------------------------------------ matvec
 // y_k = sum_m (a_m M2 + b_m kappa K2) x_{k-m} (start-up rows and the block above the
@@ -277,7 +282,7 @@ int matvec2d_blocks(int nx, int ny, int ell, bool dots)
 
 // the (MR + 2) x 3 neighbourhood of nodes (iy0 + o, ix), o < MR, of the level of x
 // at offset lofs; loads at clamped addresses, masked
-template <int MR>
+template <int MR, bool HAT = false>
 __device__ __forceinline__ void q1_load(const double *__restrict__ x, size_t lofs, int nx, int ny,
                                         int ix, int iy0, double (&v)[MR + 2][3])
 {
@@ -285,6 +290,10 @@ __device__ __forceinline__ void q1_load(const double *__restrict__ x, size_t lof
     const double ml = ix > 0 ? 1.0 : 0.0, mr = ix < nx - 1 ? 1.0 : 0.0;
 #pragma unroll
     for (int d = 0; d < MR + 2; ++d) {
+        if (HAT && (d == 0 || d == MR + 1)) {     // no coupling between sine modes
+            v[d][0] = v[d][1] = v[d][2] = 0.0;
+            continue;
+        }
         const int yy = iy0 + d - 1;
         const double w = (yy >= 0 && yy < ny) ? 1.0 : 0.0;
         const size_t ro = lofs + (size_t)((yy >= 0 && yy < ny) ? yy : 0) * nx;
@@ -314,6 +323,30 @@ __device__ __forceinline__ void q1_apply(const double (&v)[MR + 2][3], double hx
     }
 }
 
+// the same in sine coordinates along y: e[o] = 4 + 2 cos(pi (iy0 + o + 1)/(ny + 1))
+template <int MR>
+__device__ __forceinline__ void q1_apply_hat(const double (&v)[MR + 2][3], double hx, double hy,
+                                             const double (&e)[MR], double (&P)[MR],
+                                             double (&Q)[MR])
+{
+    const double cm = hx * hy / 36.0, ck1 = hx / (6.0 * hy), ck2 = hy / (6.0 * hx);
+#pragma unroll
+    for (int o = 0; o < MR; ++o) {
+        const double mrow = v[o + 1][0] + 4.0 * v[o + 1][1] + v[o + 1][2];
+        const double krow = 2.0 * v[o + 1][1] - v[o + 1][0] - v[o + 1][2];
+        P[o] = cm * e[o] * mrow;
+        Q[o] = ck1 * (6.0 - e[o]) * mrow + ck2 * e[o] * krow;
+    }
+}
+
+// the sine-mode factors e[o] of rows iy0 .. iy0 + MR - 1
+template <int MR>
+__device__ __forceinline__ void hat_modes(int iy0, int ny, double (&e)[MR])
+{
+#pragma unroll
+    for (int o = 0; o < MR; ++o) e[o] = 4.0 + 2.0 * cospi((iy0 + o + 1.0) / (ny + 1.0));
+}
+
 // M2 x and K2 x at nodes (iy0 + o, ix), o < MR, of one level of x
 template <int MR>
 __device__ __forceinline__ void q1_mk_rows(const double *__restrict__ xl, int nx, int ny, int ix,
@@ -340,7 +373,7 @@ __device__ __forceinline__ double block_sum4(double v, double *red)
 
 // The plain launch (no dot products): the window walk alone.  (Sharing the dot forms
 // body, with its per-level fetches, made this launch a third slower.)
-template <int W, int MR>
+template <int W, int MR, bool HAT>
 __global__ void __launch_bounds__(256)
 k_matvec2d_plain(const double *__restrict__ x, double *__restrict__ y,
                  const double *__restrict__ bsub, int nx, int ny, int ell, Scheme sc,
@@ -357,14 +390,17 @@ k_matvec2d_plain(const double *__restrict__ x, double *__restrict__ y,
     const int cnt = ke - kb;
     const size_t lv = (size_t)nx * ny;
     const double hx = 1.0 / (nx + 1.0), hy = 1.0 / (ny + 1.0);
+    double e[MR];
+    if (HAT) hat_modes<MR>(iy0, ny, e);
     double P[W][MR], Q[W][MR];
     auto fill = [&](int c, int L) {
 #pragma unroll
         for (int o = 0; o < MR; ++o) P[c][o] = Q[c][o] = 0.0;
         if (L >= 0 && L < ell) {
             double v[MR + 2][3];
-            q1_load<MR>(x, (size_t)L * lv, nx, ny, ix, iy0, v);
-            q1_apply<MR>(v, hx, hy, P[c], Q[c]);
+            q1_load<MR, HAT>(x, (size_t)L * lv, nx, ny, ix, iy0, v);
+            if (HAT) q1_apply_hat<MR>(v, hx, hy, e, P[c], Q[c]);
+            else q1_apply<MR>(v, hx, hy, P[c], Q[c]);
         }
     };
 #pragma unroll
@@ -408,7 +444,7 @@ k_matvec2d_plain(const double *__restrict__ x, double *__restrict__ y,
 }
 
 // The GMRES forms (DOTS = 1 or 2).
-template <int W, int MR, int DOTS>
+template <int W, int MR, int DOTS, bool HAT>
 __global__ void __launch_bounds__(256)
 k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ bsub,
            int nx, int ny, int ell, Scheme sc, double kappa, int transpose, VecList V, int nv,
@@ -434,14 +470,17 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
         own[o] = live && iy0 + o < ny;
         nofs[o] = (size_t)(own[o] ? iy0 + o : 0) * nx + (own[o] ? ix : 0);
     }
+    double e[MR];
+    if (HAT) hat_modes<MR>(iy0, ny, e);
     double P[W][MR], Q[W][MR];
     auto fill = [&](int c, int L) {
 #pragma unroll
         for (int o = 0; o < MR; ++o) P[c][o] = Q[c][o] = 0.0;
         if (live && L >= 0 && L < ell) {
             double v[MR + 2][3];
-            q1_load<MR>(x, (size_t)L * lv, nx, ny, ix, iy0, v);
-            q1_apply<MR>(v, hx, hy, P[c], Q[c]);
+            q1_load<MR, HAT>(x, (size_t)L * lv, nx, ny, ix, iy0, v);
+            if (HAT) q1_apply_hat<MR>(v, hx, hy, e, P[c], Q[c]);
+            else q1_apply<MR>(v, hx, hy, P[c], Q[c]);
         }
     };
     // rows of bsub and of the first G basis vectors at level k (zero where not owned)
@@ -531,7 +570,7 @@ k_matvec2d(const double *__restrict__ x, double *__restrict__ y, const double *_
     if (threadIdx.x == 0) part[(size_t)nv * ldp + blk] = s;
 }
 
-template <int DOTS>
+template <int DOTS, bool HAT>
 static hipError_t matvec2d_go(const double *x, double *y, const double *bsub, int nx, int ny,
                               int ell, Scheme sc, double kappa, int transpose, const VecList &V,
                               int nv, double *part, int ldp, hipStream_t st)
@@ -540,25 +579,36 @@ static hipError_t matvec2d_go(const double *x, double *y, const double *bsub, in
     dim3 grid((nx + 63) / 64, (ny + 4 * MR - 1) / (4 * MR), (ell + kMv2Seg - 1) / kMv2Seg);
     if constexpr (DOTS == 0) {
         switch (sc.s + sc.up + 1) {
-        case 2: k_matvec2d_plain<2, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
-        case 3: k_matvec2d_plain<3, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
-        case 4: k_matvec2d_plain<4, MR><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+        case 2: k_matvec2d_plain<2, MR, HAT><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+        case 3: k_matvec2d_plain<3, MR, HAT><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
+        case 4: k_matvec2d_plain<4, MR, HAT><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose); break;
         default: return hipErrorInvalidValue;
         }
     } else {
         switch (sc.s + sc.up + 1) {
-        case 2: k_matvec2d<2, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
-        case 3: k_matvec2d<3, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
-        case 4: k_matvec2d<4, MR, DOTS><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
+        case 2: k_matvec2d<2, MR, DOTS, HAT><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
+        case 3: k_matvec2d<3, MR, DOTS, HAT><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
+        case 4: k_matvec2d<4, MR, DOTS, HAT><<<grid, 256, 0, st>>>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv, part, ldp); break;
         default: return hipErrorInvalidValue;
         }
     }
     return hipGetLastError();
 }
 
+template <int DOTS>
+static hipError_t matvec2d_pick(bool hat, const double *x, double *y, const double *bsub, int nx,
+                                int ny, int ell, Scheme sc, double kappa, int transpose,
+                                const VecList &V, int nv, double *part, int ldp, hipStream_t st)
+{
+    return hat ? matvec2d_go<DOTS, true>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv,
+                                         part, ldp, st)
+               : matvec2d_go<DOTS, false>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv,
+                                          part, ldp, st);
+}
+
 hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
                            int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
-                           const VecList *V, int nv, double *part, int ldp)
+                           const VecList *V, int nv, double *part, int ldp, bool hat)
 {
     static const VecList none{};
     if (nv > 0) {
@@ -567,13 +617,14 @@ hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int n
         if (nv > kMv2DotG && !y) return hipErrorInvalidValue;   // dots past the walk read y
         // a one-entry list equal to the output selects the self-norm only
         if (nv == 1 && V->p[0] == y)
-            return matvec2d_go<2>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, part,
-                                  ldp, st);
-        return matvec2d_go<1>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, *V, nv, part, ldp,
-                              st);
+            return matvec2d_pick<2>(hat, x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0,
+                                    part, ldp, st);
+        return matvec2d_pick<1>(hat, x, y, bsub, nx, ny, ell, sc, kappa, transpose, *V, nv, part,
+                                ldp, st);
     }
     if (!y) return hipErrorInvalidValue;
-    return matvec2d_go<0>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, nullptr, 0, st);
+    return matvec2d_pick<0>(hat, x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, nullptr,
+                            0, st);
 }
 
 // ---------------------------------------------------------- right-hand side
