@@ -273,7 +273,8 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
 // nv == 1 with V->p[0] == y only those of y . y (value 0); y may then be null.
 // matvec2d_blocks(..., true) partials per value.  With nv > matvec2d_dot_walk() the
 // dots past the first ones read y back, so y must not be null.  With hat the vectors
-// are in sine coordinates along y (S_y A S_y: x-stencils per sine mode).
+// are in sine coordinates along y (S_y A S_y: x-stencils per sine mode); the forms with
+// dot products (GMRES) exist in those coordinates only.
 hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
                            int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
                            const VecList *V = nullptr, int nv = 0, double *part = nullptr,

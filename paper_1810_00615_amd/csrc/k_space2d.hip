@@ -256,20 +256,21 @@ hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, 
 // level are loaded together (MR independent outputs per step keep enough loads in
 // flight), and the vertical stencil shares them.
 //
-// The GMRES forms of the launch (as in one dimension): DOTS = 1 also leaves the block
+// The GMRES forms of the launch (as in one dimension; GMRES on the unit square runs in
+// sine coordinates, so these exist for the HAT stencils only): DOTS = 1 also leaves the block
 // partials of V_q . y (q < nv) and of y . y (value nv), the first Gram-Schmidt pass;
 // DOTS = 2 the partial of y . y only (a residual norm).  Partials are value-major,
 // part[q ldp + block].  The rows of bsub and of the first kMv2DotG basis vectors that
 // the next level needs are loaded with that level's x rows, so their latency overlaps
 // the stencil's, and their dot products accumulate while the segment is walked; basis
 // vectors past kMv2DotG are dotted after the walk with y read back, so those launches
-// need y.  (Forming x = Z y
-// inside the residual check, as the 1D matvec does, made this kernel slower than a
-// separate axpy: the combination is recomputed at every neighbour of the 9-point
-// stencil.)
+// need y.  Without the halo rows of the 9-point stencil two rows per thread beat four
+// (92 against 97 us per launch at 511 x 511 x 64).  (Forming x = Z y inside the
+// residual check, as the 1D matvec does, made the nodal kernel slower than a separate
+// axpy: the combination is recomputed at every neighbour of the 9-point stencil.)
 constexpr int kMv2Seg = 8;
 constexpr int kMv2Rows = 4;     // plain launch
-constexpr int kMv2RowsDot = 4;  // launches with dot products
+constexpr int kMv2RowsDot = 2;  // launches with dot products
 constexpr int kMv2DotG = 2;     // basis vectors dotted during the walk
 
 int matvec2d_dot_walk() { return kMv2DotG; }
@@ -595,16 +596,6 @@ static hipError_t matvec2d_go(const double *x, double *y, const double *bsub, in
     return hipGetLastError();
 }
 
-template <int DOTS>
-static hipError_t matvec2d_pick(bool hat, const double *x, double *y, const double *bsub, int nx,
-                                int ny, int ell, Scheme sc, double kappa, int transpose,
-                                const VecList &V, int nv, double *part, int ldp, hipStream_t st)
-{
-    return hat ? matvec2d_go<DOTS, true>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv,
-                                         part, ldp, st)
-               : matvec2d_go<DOTS, false>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, V, nv,
-                                          part, ldp, st);
-}
 
 hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int nx, int ny,
                            int ell, Scheme sc, double kappa, int transpose, hipStream_t st,
@@ -615,16 +606,19 @@ hipError_t launch_matvec2d(const double *x, double *y, const double *bsub, int n
         if (!V || !part || nv >= kMaxVecs || matvec2d_blocks(nx, ny, ell, true) > ldp)
             return hipErrorInvalidValue;
         if (nv > kMv2DotG && !y) return hipErrorInvalidValue;   // dots past the walk read y
+        if (!hat) return hipErrorInvalidValue;   // GMRES runs in sine coordinates only
         // a one-entry list equal to the output selects the self-norm only
         if (nv == 1 && V->p[0] == y)
-            return matvec2d_pick<2>(hat, x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0,
-                                    part, ldp, st);
-        return matvec2d_pick<1>(hat, x, y, bsub, nx, ny, ell, sc, kappa, transpose, *V, nv, part,
-                                ldp, st);
+            return matvec2d_go<2, true>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0,
+                                        part, ldp, st);
+        return matvec2d_go<1, true>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, *V, nv, part,
+                                    ldp, st);
     }
     if (!y) return hipErrorInvalidValue;
-    return matvec2d_pick<0>(hat, x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0, nullptr,
-                            0, st);
+    return hat ? matvec2d_go<0, true>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0,
+                                      nullptr, 0, st)
+               : matvec2d_go<0, false>(x, y, bsub, nx, ny, ell, sc, kappa, transpose, none, 0,
+                                       nullptr, 0, st);
 }
 
 // ---------------------------------------------------------- right-hand side

@@ -370,3 +370,28 @@ def test_gmres_2d_variants(dev, orc, variant):
     e = normrel(U.cpu().numpy(), Ur)
     print(f"bd2 2d gmres {variant}: {info['iters']} iterations, error {e:.2e}")
     assert e < 1e-7
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_in", "fp32"])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_gmres_2d_precisions(dev, orc, precision, transpose):
+    """GMRES on the unit square (in sine coordinates along y) with each single-precision
+    preconditioner mode, forward and adjoint, from a given initial guess: the FP64
+    outer iteration reaches the exact block-substitution solution."""
+    from paper_1810_00615_amd import Problem2D
+    nx, ny, ell = 21, 15, 24
+    tau, kappa = 1.0 / ell, 0.9
+    rng = np.random.default_rng([82, len(precision), int(transpose)])
+    b = rng.standard_normal((ell, ny, nx))
+    x0 = td(dev, 0.1 * rng.standard_normal((ell, ny, nx)))
+    P = Problem2D(nx, ny, ell, tau, "heat", kappa=kappa, device=dev)
+    P.set_precision(precision)
+    if transpose:
+        U, info = P.adjoint(td(dev, b), restart=40, tol=1e-11, maxit=400)
+    else:
+        U, info = P.solve(td(dev, b), restart=40, tol=1e-11, maxit=400, x0=x0)
+    assert info["converged"], info
+    Ur = orc.solve_seq2(0, nx, ny, ell, tau, kappa, b, transpose=transpose)
+    e = normrel(U.cpu().numpy(), Ur)
+    print(f"heat 2d gmres {precision} tr={transpose}: {info['iters']} iterations, error {e:.2e}")
+    assert e < 1e-8
