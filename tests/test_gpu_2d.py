@@ -395,3 +395,25 @@ def test_gmres_2d_precisions(dev, orc, precision, transpose):
     e = normrel(U.cpu().numpy(), Ur)
     print(f"heat 2d gmres {precision} tr={transpose}: {info['iters']} iterations, error {e:.2e}")
     assert e < 1e-8
+
+
+def test_gmres_2d_stopped_early_returns_nodal_iterate(dev):
+    """A solve stopped by maxit (GMRES in sine coordinates, from a given initial guess)
+    hands back the nodal iterate: the residual it reports is that of the nodal matvec
+    applied to the returned x."""
+    import torch
+    from paper_1810_00615_amd import Problem2D
+    nx, ny, ell = 33, 31, 40
+    tau, kappa = 1.0 / ell, 1.3
+    rng = np.random.default_rng(83)
+    b = td(dev, rng.standard_normal((ell, ny, nx)))
+    x0 = td(dev, 0.1 * rng.standard_normal((ell, ny, nx)))
+    P = Problem2D(nx, ny, ell, tau, "bd2", kappa=kappa, device=dev)
+    U, info = P.solve(b, restart=30, tol=1e-14, maxit=3, x0=x0)
+    assert info["status"] == 1 and not info["converged"], info
+    r = b - P.A(U)
+    rel = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    print(f"bd2 2d stopped after {info['iters']}: reported {info['rel_resid_true']:.6e}, "
+          f"nodal {rel:.6e}")
+    assert rel < 0.999
+    assert abs(rel - info["rel_resid_true"]) <= 1e-6 * rel
