@@ -263,7 +263,7 @@ hipError_t launch_dot1_parts(const double *a, const double *b, size_t N, double 
 // Vectors of one time level are ny x nx, x fastest; ell levels follow each other.
 // Orthonormal sine transform along y of every level (its own inverse); in == out
 // allowed.  Needs ny + 1 a power of two, ny <= 2047; tw the twiddle table of length
-// 2 (ny + 1) (launch_twiddles).
+// 2 (ny + 1) (launch_twiddles): the length-(ny + 1) transform takes every other entry.
 bool dst_y_supported(int ny);
 hipError_t launch_dst_y(const double *in, double *out, int nx, int ny, int ell, const double *tw,
                         hipStream_t st);
