@@ -417,3 +417,28 @@ def test_gmres_2d_stopped_early_returns_nodal_iterate(dev):
           f"nodal {rel:.6e}")
     assert rel < 0.999
     assert abs(rel - info["rel_resid_true"]) <= 1e-6 * rel
+
+
+@pytest.mark.parametrize("scheme", [HEAT, BD2])
+@pytest.mark.parametrize("nx,ny,ell", [(1, 1, 1), (1, 3, 2), (5, 1, 3), (65, 3, 9), (2, 255, 2)])
+def test_gmres_2d_small_and_ragged(dev, orc, scheme, nx, ny, ell):
+    """GMRES in sine coordinates at the smallest shapes (one node, one sine mode, one
+    time level) and at ragged tiles of the sine pass and the matvec (nx = 65, a long
+    column with nx = 2), forward and adjoint, against block substitution."""
+    from paper_1810_00615_amd import Problem2D
+    tau, kappa = 1.0 / max(ell, 2), 1.1
+    rng = np.random.default_rng([84, scheme, nx, ny, ell])
+    b = rng.standard_normal((ell, ny, nx))
+    P = Problem2D(nx, ny, ell, tau, NAME[scheme], kappa=kappa, device=dev)
+    cA = _cond_A_bound(scheme, nx, ny, ell, tau, kappa)
+    for transpose in (False, True):
+        if transpose:
+            U, info = P.adjoint(td(dev, b), restart=40, tol=1e-12, maxit=400)
+        else:
+            U, info = P.solve(td(dev, b), restart=40, tol=1e-12, maxit=400)
+        assert info["converged"], (transpose, info)
+        Ur = orc.solve_seq2(scheme, nx, ny, ell, tau, kappa, b, transpose=transpose)
+        e = normrel(U.cpu().numpy(), Ur)
+        print(f"{NAME[scheme]} 2d {nx}x{ny}x{ell} tr={transpose}: {info['iters']} iterations, "
+              f"error {e:.2e}")
+        assert e < max(1e-10, 4 * cA * 1e-12)
