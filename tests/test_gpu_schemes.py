@@ -59,8 +59,8 @@ def test_rhs(dev, orc, scheme, n, ell):
 
 @pytest.mark.parametrize("scheme", [BD4, CD])
 @pytest.mark.parametrize("transpose", [False, True])
-@pytest.mark.parametrize("n,ell", [(1, 1), (1, 4), (5, 3), (64, 17), (130, 33), (257, 100),
-                                   (513, 24)])
+@pytest.mark.parametrize("n,ell", [(1, 1), (1, 4), (5, 3), (64, 17), (65, 9), (130, 33),
+                                   (257, 100), (320, 9), (513, 24), (4097, 5)])
 def test_apply_A(dev, orc, scheme, transpose, n, ell):
     from paper_1810_00615_amd import Problem
     tau, kappa = 1.0 / ell, 0.9
