@@ -461,6 +461,9 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched 64-problem solves, FP64 and mixed (for profiler "
                          "runs): no headline, no sequential comparison")
+    ap.add_argument("--beyond-cache-only", action="store_true",
+                    help="only the beyond-cache leg (heat n = 4095, ell = 16384, 537 MB "
+                         "vectors; for profiler runs)")
     ap.add_argument("--tune-cache", default=None,
                     help="file of tuned launch shapes read and appended by the autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -482,6 +485,16 @@ def main():
         return
     if args.square_only:
         print(json.dumps({"square": bench_square(args)}), flush=True)
+        return
+    if args.beyond_cache_only:
+        if args.calibrate_copy:
+            # one plain device copy of one vector of this leg (4095 x 16384 doubles)
+            src = torch.zeros(4095 * 16384, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        print(json.dumps({"beyond_cache": bench_beyond_cache(args)}), flush=True)
         return
 
     from paper_1810_00615_amd import Problem
