@@ -461,6 +461,9 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched 64-problem solves, FP64 and mixed (for profiler "
                          "runs): no headline, no sequential comparison")
+    ap.add_argument("--wave-only", action="store_true",
+                    help="only the wave BD2 leg (n = 2047, ell = 8192, FP64 and the "
+                         "single-precision modes; for profiler runs)")
     ap.add_argument("--beyond-cache-only", action="store_true",
                     help="only the beyond-cache leg (heat n = 4095, ell = 16384, 537 MB "
                          "vectors; for profiler runs)")
@@ -485,6 +488,9 @@ def main():
         return
     if args.square_only:
         print(json.dumps({"square": bench_square(args)}), flush=True)
+        return
+    if args.wave_only:
+        print(json.dumps({"wave_bd2": bench_wave(args)}), flush=True)
         return
     if args.beyond_cache_only:
         if args.calibrate_copy:

@@ -930,44 +930,65 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
 {
     __shared__ double wsum[16][kMaxVecs];
     __shared__ double sums[kMaxVecs + 1];   // final sums (LDS: indexed at run time)
+    // the step's scalars, read once by parallel loads: the serial update below reads
+    // them from LDS instead of one dependent global load after another
+    __shared__ double lvs[kMaxVecs + 1], la[kMaxVecs + 1], lh1[kMaxVecs + 1],
+        lh2[kMaxVecs + 1], lc[kMaxVecs + 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int cnt = (a.mode <= 1) ? a.nv : (a.mode >= 5 ? a.nv + 1 : 1);
-    // thread t sums the partials t, t + 1024, ... of every value, the loads of two
-    // values (32 per thread) in flight at a time; then each wave and finally thread 0
-    // add in a fixed order
-    for (int i0 = 0; i0 < cnt; i0 += 2) {
-        double s[2] = {0.0, 0.0};
-        for (int base = 0; base < nblk; base += 16 * 1024) {
-            double v[2][16];
+    const int nv = a.nv;
+    if ((int)threadIdx.x <= nv) {
+        const int i = threadIdx.x;
+        lvs[i] = a.vs[i];
+        if (a.mode >= 5) la[i] = a.a[i];
+        if (a.mode == 1) lc[i] = a.c[i];
+        if (a.mode == 2) {
+            lh1[i] = a.h1[i];
+            lh2[i] = a.h2[i];
+        }
+    }
+    if (nblk == 1) {
+        // one partial per value (pre-summed): value i is thread i's load
+        if ((int)threadIdx.x < cnt) sums[threadIdx.x] = part[(size_t)threadIdx.x * ldp];
+        __syncthreads();
+    } else {
+        // thread t sums the partials t, t + 1024, ... of every value, the loads of two
+        // values (32 per thread) in flight at a time; then each wave and finally one
+        // thread per value add in a fixed order
+        for (int i0 = 0; i0 < cnt; i0 += 2) {
+            double s[2] = {0.0, 0.0};
+            for (int base = 0; base < nblk; base += 16 * 1024) {
+                double v[2][16];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const double *p = part + (size_t)min(i0 + q, cnt - 1) * ldp;
+                for (int q = 0; q < 2; ++q) {
+                    const double *p = part + (size_t)min(i0 + q, cnt - 1) * ldp;
 #pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    const int b = base + k * 1024 + (int)threadIdx.x;
-                    v[q][k] = (i0 + q < cnt && b < nblk) ? p[b] : 0.0;
+                    for (int k = 0; k < 16; ++k) {
+                        const int b = base + k * 1024 + (int)threadIdx.x;
+                        v[q][k] = (i0 + q < cnt && b < nblk) ? p[b] : 0.0;
+                    }
                 }
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) s[q] += v[q][k];
             }
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+            for (int q = 0; q < 2; ++q) {
 #pragma unroll
-                for (int k = 0; k < 16; ++k) s[q] += v[q][k];
+                for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_down(s[q], off, 64);
+                if (lane == 0 && i0 + q < cnt) wsum[wv][i0 + q] = s[q];
+            }
         }
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_down(s[q], off, 64);
-            if (lane == 0 && i0 + q < cnt) wsum[wv][i0 + q] = s[q];
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            double s = 0.0;
+            for (int w = 0; w < 16; ++w) s += wsum[w][threadIdx.x];
+            sums[threadIdx.x] = s;
         }
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int i = 0; i < cnt; ++i) {
-        double s = 0.0;
-        for (int w = 0; w < 16; ++w) s += wsum[w][i];
-        sums[i] = s;
-    }
-    const int nv = a.nv;
     if (a.mode == 5) {
         // delayed re-orthogonalisation, after w = A z_j (sums: S_i . w, i <= j):
         // p_j = sum_{i<j} a_i v_i + alpha v_j with |p_j| = 1, so
@@ -977,20 +998,20 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
         const int j = nv - 1;
         double aa = 0.0, ab = 0.0;
         for (int i = 0; i < j; ++i) {
-            const double bi = a.vs[i] * sums[i];
-            aa += a.a[i] * a.a[i];
-            ab += a.a[i] * bi;
+            const double bi = lvs[i] * sums[i];
+            aa += la[i] * la[i];
+            ab += la[i] * bi;
         }
         const double alpha = j > 0 ? sqrt(fmax(1.0 - aa, 1e-300)) : 1.0;
-        const double hj = (a.vs[j] * sums[j] - ab) / alpha;
+        const double hj = (lvs[j] * sums[j] - ab) / alpha;
         for (int i = 0; i < j; ++i) {
-            const double bi = a.vs[i] * sums[i];
-            a.cv[i] = -a.a[i] * a.vs[i] / alpha;
-            a.cw[i] = (bi - a.a[i] * hj / alpha) * a.vs[i];
+            const double bi = lvs[i] * sums[i];
+            a.cv[i] = -la[i] * lvs[i] / alpha;
+            a.cw[i] = (bi - la[i] * hj / alpha) * lvs[i];
             a.host[i] = bi;
         }
-        a.cv[j] = a.vs[j] / alpha;
-        a.cw[j] = hj / alpha * a.vs[j];
+        a.cv[j] = lvs[j] / alpha;
+        a.cw[j] = hj / alpha * lvs[j];
         a.host[j] = hj;
         a.host[kHostWW] = sums[nv];   // w . w
         if (j > 0) a.vs[j] = 1.0;   // S_j is rewritten as the unit vector v_j
@@ -1002,26 +1023,29 @@ k_reduce_small(const double *__restrict__ part, int nblk, int ldp, SmallArgs a)
         const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
         a.vs[nv] = inv;
         for (int i = 0; i <= j; ++i) {
-            a.a[i] = (i < j ? a.vs[i] : 1.0) * sums[i] * inv;
-            a.host[kHostA + i] = a.a[i];
+            const double ai = (i < j ? lvs[i] : 1.0) * sums[i] * inv;
+            a.a[i] = ai;
+            a.host[kHostA + i] = ai;
         }
         a.host[nv] = beta;
     } else if (a.mode == 0) {
         for (int i = 0; i < nv; ++i) {
-            a.h1[i] = a.vs[i] * sums[i];
-            a.c[i] = a.vs[i] * a.h1[i];
+            const double h = lvs[i] * sums[i];
+            a.h1[i] = h;
+            a.c[i] = lvs[i] * h;
         }
     } else if (a.mode == 1) {
         for (int i = 0; i < nv; ++i) {
-            a.h2[i] = a.vs[i] * sums[i];
-            a.c[i] += a.vs[i] * a.h2[i];
+            const double h = lvs[i] * sums[i];
+            a.h2[i] = h;
+            a.c[i] = lc[i] + lvs[i] * h;
         }
     } else if (a.mode == 2 || a.mode == 3) {
         const double nrm = sqrt(fmax(sums[0], 0.0));
         const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
         if (a.mode == 2) {
             a.vs[nv] = inv;
-            for (int i = 0; i < nv; ++i) a.host[i] = a.h1[i] + a.h2[i];
+            for (int i = 0; i < nv; ++i) a.host[i] = lh1[i] + lh2[i];
             a.host[nv] = nrm;
         } else {
             a.vs[0] = inv;
